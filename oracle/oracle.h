@@ -1,0 +1,72 @@
+/*
+ * CPU FP64 oracle for the geodesic-interaction hot path.
+ *
+ * TEST INFRASTRUCTURE ONLY. Nothing in the product path may include, link,
+ * load or call this code: only the tests, the smoke check and the benchmark's
+ * CPU-baseline leg do. It shares no code with the HIP library.
+ *
+ * What it computes, and the passages it follows (arXiv 2404.19751):
+ *  - mesh half-edge structure, corner-angle sums, pseudo-source vertices
+ *    (Sec. 2.2: triangulated surface; Sec. 3.2: spherical vertices have angle
+ *    sum < 2 pi);
+ *  - exact polyhedral geodesic distance and initial unit tangent for every
+ *    particle pair closer than a cutoff (Sec. 2.2, the MMP idea of
+ *    considering all local unfoldings; Sec. 3.1, distances l_ij and tangents
+ *    at the source; submeshing by the Euclidean lower bound). This is the plain
+ *    definition written out: a shortest path is a chain of straight segments
+ *    in planar unfoldings, bending only at saddle or boundary vertices; every
+ *    such chain shorter than the cutoff is enumerated by brute force, with no
+ *    trimming, and the shortest kept (Dijkstra over the bend vertices);
+ *  - the per-particle straight walk across faces with parallel transport of
+ *    the velocity (Sec. 3.2, the shift algorithm and its steps (a)-(d));
+ *  - Philox4x32-10 (Salmon et al., SC'11) for Brownian noise (Sec. 2.1).
+ */
+#ifndef GSIM_ORACLE_H
+#define GSIM_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct orc_mesh orc_mesh;
+typedef struct orc_pairs orc_pairs;
+
+/* 0 = ok; 1 = bad argument; 2 = non-manifold edge; 3 = inconsistent
+ * orientation; 4 = non-manifold vertex; 5 = degenerate face. */
+int orc_mesh_build(int nv, const double *V, int nf, const int *T, orc_mesh **out);
+void orc_mesh_free(orc_mesh *m);
+/* twin[3nf], theta[nv] (corner-angle sum), pseudo[nv], boundary[nv] */
+void orc_mesh_export(const orc_mesh *m, int *twin, double *theta, unsigned char *pseudo, unsigned char *boundary);
+
+/* Geodesic neighbour pairs (i -> j, j != i, d_ij < cutoff) for the sources
+ * listed in `src` (all particles if src == NULL). cutoff <= 0 or infinite
+ * means "all pairs" (only sensible on small meshes). nthreads <= 0: OpenMP
+ * default. Returns NULL on bad input. */
+orc_pairs *orc_geodesic_pairs(const orc_mesh *m, int n, const int *face, const double *bary, double cutoff,
+                              int nsrc, const int *src, int nthreads);
+int64_t orc_pairs_count(const orc_pairs *p);
+int64_t orc_pairs_tie_count(const orc_pairs *p);
+/* off[nsrc+1], nbr[P], dist[P], tan[P][3], flags[P], tie_off[P+1], tie_tan[T][3] */
+void orc_pairs_export(const orc_pairs *p, int64_t *off, int32_t *nbr, double *dist, double *tan, uint8_t *flags,
+                      int64_t *tie_off, double *tie_tan);
+/* counters: [0] windows processed, [1] windows pruned by the bound,
+ * [2] roots expanded, [3] pseudo-source distance improvements, [4] sources
+ * rejected (position on a vertex) */
+void orc_pairs_counters(const orc_pairs *p, int64_t *c5);
+void orc_pairs_free(orc_pairs *p);
+
+/* Per-particle walk (shift). disp[n][3] (normal part removed inside), vel may
+ * be NULL. face/bary/vel updated in place. stats[5]: crossings, vertex hits,
+ * boundary hits, iteration-cap hits, near-vertex passes. flags[n] (may be
+ * NULL): bit0 vertex hit, bit1 near-vertex pass, bit2 cap hit, bit3 boundary. */
+int orc_walk(const orc_mesh *m, int n, int *face, double *bary, const double *disp, double *vel, int64_t *stats,
+             uint8_t *flags);
+
+/* Philox4x32-10: out[4] for counter ctr[4] and key key[2]. */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,358 @@
+"""Pins for the oracle's mesh structure and geodesics against closed forms,
+invariants and the paper's worked metric example. None of these re-type the
+oracle's formulas: each expected value comes from an independent geometric
+construction (a planar development, a great circle, symmetry)."""
+import math
+
+import numpy as np
+import pytest
+from scipy.integrate import quad
+
+from paper_2404_19751_amd import workloads as W
+from tests.util import locate, pair_dict, place, interior_points
+
+
+# ---------------------------------------------------------------- mesh ----
+@pytest.mark.parametrize("mk,chi", [(lambda: W.icosphere(2), 2), (lambda: W.torus(1.0, 0.3, 12, 7), 0),
+                                    (lambda: W.cube(2), 2), (lambda: W.bumpy_sphere(2), 2)])
+def test_gauss_bonnet_closed(orc, mk, chi):
+    """Discrete Gauss-Bonnet: sum of angle defects = 2 pi chi."""
+    m = mk()
+    om = orc.OracleMesh(m.V, m.T)
+    assert abs(np.sum(2 * np.pi - om.theta) - 2 * np.pi * chi) < 1e-9
+    assert om.boundary.sum() == 0
+
+
+def test_gauss_bonnet_open(orc):
+    m = W.l_shape(3)
+    om = orc.OracleMesh(m.V, m.T)
+    inner = om.boundary == 0
+    tot = np.sum(2 * np.pi - om.theta[inner]) + np.sum(np.pi - om.theta[~inner])
+    assert abs(tot - 2 * np.pi) < 1e-9
+    corner = int(np.argmin(np.linalg.norm(m.V - [1.0, 1.0, 0.0], axis=1)))
+    assert om.boundary[corner] and abs(om.theta[corner] - 1.5 * np.pi) < 1e-12
+
+
+def test_pseudo_sources(orc):
+    ico = orc.OracleMesh(*(lambda m: (m.V, m.T))(W.icosphere(3)))
+    assert ico.pseudo.sum() == 0  # convex: every vertex spherical
+    tor = W.torus(1.0, 0.3, 20, 10)
+    ot = orc.OracleMesh(tor.V, tor.T)
+    assert 0.3 < ot.pseudo.mean() < 0.7  # the inner half of a torus is saddle-shaped
+    sad = W.cone_fan(2.5 * np.pi, 8)
+    oc = orc.OracleMesh(sad.V, sad.T)
+    assert oc.pseudo[0] and abs(oc.theta[0] - 2.5 * np.pi) < 1e-12
+
+
+def test_mesh_rejects(orc):
+    m = W.icosphere(1)
+    T = m.T.copy()
+    T[0] = T[0][[0, 2, 1]]  # flip one face
+    with pytest.raises(ValueError, match="orientation"):
+        orc.OracleMesh(m.V, T)
+    T = np.concatenate([m.T, m.T[:1]], 0)  # an edge shared by three faces
+    with pytest.raises(ValueError):
+        orc.OracleMesh(m.V, T)
+
+
+# ------------------------------------------------------------ CF1 / CF2 ----
+def test_flat_grid_is_euclidean(orc):
+    g = W.flat_grid(6, 5, 1.2, 1.0)
+    om = orc.OracleMesh(g.V, g.T)
+    f, b = W.random_particles(g.nf, 40, 11)
+    pr = orc.geodesic_pairs(om, f, b, 0.45)
+    x = om.xyz(f, b)
+    n_exp = 0
+    for i in range(40):
+        got = pair_dict(pr, i)
+        for j in range(40):
+            d = np.linalg.norm(x[j] - x[i])
+            if j == i or d >= 0.45:
+                assert j not in got
+                continue
+            n_exp += 1
+            p = got[j]
+            assert abs(pr.dist[p] - d) <= 1e-13
+            assert np.linalg.norm(pr.tan[p] - (x[j] - x[i]) / d) <= 1e-12
+    assert n_exp == pr.off[-1] > 50
+
+
+def test_same_face_pairs_attain_euclidean(orc):
+    m = W.icosphere(2)
+    om = orc.OracleMesh(m.V, m.T)
+    f = np.array([5, 5, 5], np.int32)
+    b = np.array([[0.6, 0.2, 0.2], [0.2, 0.6, 0.2], [0.1, 0.15, 0.75]])
+    pr = orc.geodesic_pairs(om, f, b, 10.0)
+    x = om.xyz(f, b)
+    for i in range(3):
+        for j, p in pair_dict(pr, i).items():
+            assert abs(pr.dist[p] - np.linalg.norm(x[j] - x[i])) < 1e-15
+
+
+# ------------------------------------------------------------------ CF3 ----
+def _developed_sheet(m):
+    x = m.meta["x"]
+    chord = np.hypot(np.diff(x), np.diff(np.sin(x)))
+    S = np.concatenate([[0.0], np.cumsum(chord)])
+
+    def s_of(px):
+        i = min(np.searchsorted(x, px, side="right") - 1, len(x) - 2)
+        return S[i] + (px - x[i]) / (x[i + 1] - x[i]) * chord[i]
+    return s_of
+
+
+def test_corrugated_sheet_develops_to_plane(orc):
+    """z = sin x with a y-aligned grid: every quad is a planar rectangle, so
+    geodesic distance = Euclidean distance in the developed (s, y) plane."""
+    m = W.corrugated_sheet(24, 6)
+    om = orc.OracleMesh(m.V, m.T)
+    assert np.allclose(om.theta[om.boundary == 0], 2 * np.pi, atol=1e-12)
+    s_of = _developed_sheet(m)
+    f, b = interior_points(m, 30, 5)
+    x = om.xyz(f, b)
+    sy = np.array([[s_of(p[0]), p[1]] for p in x])
+    pr = orc.geodesic_pairs(om, f, b, 1.5)
+    cnt = 0
+    for i in range(30):
+        got = pair_dict(pr, i)
+        for j in range(30):
+            d = np.linalg.norm(sy[j] - sy[i])
+            if j != i and d < 1.5 - 1e-9:
+                cnt += 1
+                assert abs(pr.dist[got[j]] - d) < 1e-12
+    assert cnt > 40
+
+
+def test_corrugated_sheet_metric_of_the_paper(orc):
+    """The paper's worked example: R(x,y) = (x, y, sin x) has g_xx = 1 + cos^2 x
+    (Sec. 2.2, metric tensor example). Along a line y = const the mesh distance
+    must converge to the integral of sqrt(g_xx), with O(h^2) error."""
+    xa, xb = math.pi / 4, 5 * math.pi / 4  # grid nodes at every resolution used
+    exact = quad(lambda t: math.sqrt(1.0 + math.cos(t) ** 2), xa, xb)[0]
+    errs = []
+    for nx in (16, 32, 64):
+        m = W.corrugated_sheet(nx, 2, sy=1.0)
+        om = orc.OracleMesh(m.V, m.T)
+        # both points on grid edges x = const (sources on an edge)
+        f, b = place(m, [(xa, 0.3, math.sin(xa)), (xb, 0.3, math.sin(xb))])
+        pr = orc.geodesic_pairs(om, f, b, 20.0)
+        errs.append(abs(pr.dist[pair_dict(pr, 0)[1]] - exact))
+    assert errs[1] < errs[0] / 3.0 and errs[2] < errs[1] / 3.0 and errs[2] < 2e-3
+
+
+# ------------------------------------------------------------------ CF4 ----
+def test_prism_wraparound_and_ties(orc):
+    n, R, H = 6, 1.0, 1.0
+    m = W.prism(n, R, H, nz=3)
+    om = orc.OracleMesh(m.V, m.T)
+    side = 2 * R * math.sin(math.pi / n)
+    C = n * side
+
+    def pt(s, z):
+        k = int(s // side) % n
+        t = (s - (s // side) * side) / side
+        a = np.array([R * math.cos(2 * math.pi * k / n), R * math.sin(2 * math.pi * k / n)])
+        c = np.array([R * math.cos(2 * math.pi * (k + 1) / n), R * math.sin(2 * math.pi * (k + 1) / n)])
+        q = (1 - t) * a + t * c
+        return (q[0], q[1], z)
+
+    coords = [(0.3, 0.2), (2.9, 0.7), (5.6, 0.5), (1.7, 0.9), (0.3 + C / 2, 0.2)]
+    f, b = place(m, [pt(s, z) for s, z in coords])
+    pr = orc.geodesic_pairs(om, f, b, math.inf)
+    for i in range(len(coords)):
+        got = pair_dict(pr, i)
+        for j in range(len(coords)):
+            if j == i:
+                continue
+            ds, dz = coords[j][0] - coords[i][0], coords[j][1] - coords[i][1]
+            d = min(math.hypot(ds + k * C, dz) for k in (-1, 0, 1))
+            assert abs(pr.dist[got[j]] - d) < 1e-12
+    p = pair_dict(pr, 0)[4]  # exactly half way round: two tied routes
+    assert pr.flags[p] & 1 and pr.tie_off[p + 1] - pr.tie_off[p] == 2
+
+
+# ------------------------------------------------------------------ CF5 ----
+def _cone_point(m, theta, n, r, phi):
+    a = theta / n
+    k = int(phi // a) % n
+    al = phi - k * a
+    apex, r1, r2 = m.V[0], m.V[1 + k], m.V[1 + (k + 1) % n]
+    e1 = (r1 - apex) / np.linalg.norm(r1 - apex)
+    w = r2 - apex
+    w = w - np.dot(w, e1) * e1
+    e2 = w / np.linalg.norm(w)
+    return apex + r * (math.cos(al) * e1 + math.sin(al) * e2)
+
+
+@pytest.mark.parametrize("theta,n", [(1.5 * np.pi, 6), (2.5 * np.pi, 8), (3.2 * np.pi, 10)])
+def test_cone_fan(orc, theta, n):
+    """Intrinsic cone with total angle theta: law of cosines in the opened-up
+    cone when the angular gap is below pi, else the path bends at the apex
+    (a saddle when theta > 2 pi) and d = r1 + r2."""
+    m = W.cone_fan(theta, n)
+    om = orc.OracleMesh(m.V, m.T)
+    rmax = 0.9 * math.cos(theta / (2 * n))
+    rng = np.random.default_rng(3)
+    pol = [(rmax * (0.15 + 0.8 * rng.random()), theta * rng.random()) for _ in range(14)]
+    f, b = place(m, [_cone_point(m, theta, n, r, p) for r, p in pol])
+    pr = orc.geodesic_pairs(om, f, b, math.inf)
+    x = om.xyz(f, b)
+    for i, (ri, pi_) in enumerate(pol):
+        got = pair_dict(pr, i)
+        for j, (rj, pj) in enumerate(pol):
+            if j == i:
+                continue
+            dp = abs(pi_ - pj)
+            dp = min(dp, theta - dp)
+            if dp < math.pi:
+                d = math.sqrt(ri * ri + rj * rj - 2 * ri * rj * math.cos(dp))
+            else:
+                d = ri + rj
+            p = got[j]
+            assert abs(pr.dist[p] - d) < 1e-12, (i, j, pr.dist[p], d)
+            if dp > math.pi + 1e-6:
+                to_apex = (m.V[0] - x[i]) / np.linalg.norm(m.V[0] - x[i])
+                assert np.linalg.norm(pr.tan[p] - to_apex) < 1e-9
+
+
+# ------------------------------------------------------------------ CF6 ----
+def test_l_shape_reflex_corner(orc):
+    m = W.l_shape(4)
+    om = orc.OracleMesh(m.V, m.T)
+    pts = [(1.8, 0.6, 0), (0.6, 1.8, 0), (1.7, 0.3, 0), (0.3, 1.55, 0), (0.4, 0.4, 0)]
+    f, b = place(m, pts)
+    pr = orc.geodesic_pairs(om, f, b, math.inf)
+    c = np.array([1.0, 1.0, 0.0])
+    P = np.array(pts, float)
+    for i in range(5):
+        got = pair_dict(pr, i)
+        for j in range(5):
+            if j == i:
+                continue
+            s, t = P[i], P[j]
+            # does segment st leave the region (enter x > 1, y > 1)?
+            u = np.linspace(0, 1, 2001)[:, None]
+            seg = s + u * (t - s)
+            leaves = np.any((seg[:, 0] > 1 + 1e-9) & (seg[:, 1] > 1 + 1e-9))
+            d = (np.linalg.norm(s - c) + np.linalg.norm(c - t)) if leaves else np.linalg.norm(t - s)
+            assert abs(pr.dist[got[j]] - d) < 1e-12
+            if leaves:
+                assert np.linalg.norm(pr.tan[got[j]] - (c - s) / np.linalg.norm(c - s)) < 1e-9
+
+
+# ------------------------------------------------------------- CF7 / CF8 ----
+def test_tetrahedron(orc):
+    m = W.tetrahedron(1.0)
+    V = m.V
+    pts = [(V[0] + V[1]) / 2, (V[2] + V[3]) / 2, V[[0, 1, 2]].mean(0), V[[1, 2, 3]].mean(0)]
+    f, b = place(m, pts)
+    om = orc.OracleMesh(m.V, m.T)
+    pr = orc.geodesic_pairs(om, f, b, math.inf)
+    p = pair_dict(pr, 0)[1]
+    assert abs(pr.dist[p] - 1.0) < 1e-12
+    assert np.linalg.norm(pts[0] - pts[1]) == pytest.approx(1 / math.sqrt(2))
+    assert pr.flags[p] & 1 and pr.tie_off[p + 1] - pr.tie_off[p] == 4  # four tied routes
+    p = pair_dict(pr, 2)[3]
+    assert abs(pr.dist[p] - 1 / math.sqrt(3)) < 1e-12 and not pr.flags[p] & 1
+
+
+def test_cube(orc):
+    m = W.cube(1)
+    om = orc.OracleMesh(m.V, m.T)
+    pts = [(0.5, 0.5, 1), (0.5, 0.5, 0), (1, 0.5, 0.5), (0.2, 0.3, 1), (1, 0.6, 0.1)]
+    f, b = place(m, pts)
+    pr = orc.geodesic_pairs(om, f, b, math.inf)
+    g0 = pair_dict(pr, 0)
+    assert abs(pr.dist[g0[1]] - 2.0) < 1e-12 and pr.tie_off[g0[1] + 1] - pr.tie_off[g0[1]] == 4
+    assert abs(pr.dist[g0[2]] - 1.0) < 1e-12 and not pr.flags[g0[2]] & 1
+    p = pair_dict(pr, 3)[4]
+    assert abs(pr.dist[p] - math.sqrt(2.98)) < 1e-12
+    # tangent at (0.2,0.3,1) towards the unfolded image (1.9, 0.6) of the target
+    t = np.array([1.7, 0.3, 0.0]) / math.hypot(1.7, 0.3)
+    assert np.linalg.norm(pr.tan[p] - t) < 1e-12
+
+
+def test_cube_finer_triangulation_same_distances(orc):
+    m = W.cube(3)
+    om = orc.OracleMesh(m.V, m.T)
+    f, b = place(m, [(0.2, 0.3, 1), (1, 0.6, 0.1), (0.5, 0.5, 0)])
+    pr = orc.geodesic_pairs(om, f, b, math.inf)
+    assert abs(pr.dist[pair_dict(pr, 0)[1]] - math.sqrt(2.98)) < 1e-12
+
+
+# ------------------------------------------------------------------ CF9 ----
+def test_sphere_convergence(orc):
+    """Exact polyhedral distances converge to the great-circle distance at
+    O(h^2) (Sec. 2.2: exact methods, error O(h^2); Sec. 4: the sphere can be
+    compared with the analytical result)."""
+    dirs = np.array([[0.3, 0.5, 0.8], [-0.4, 0.7, 0.2], [0.9, -0.1, 0.3], [0.1, 0.2, -0.95]])
+    dirs /= np.linalg.norm(dirs, axis=1, keepdims=True)
+    errs = []
+    for lv in (1, 2, 3, 4):
+        m = W.icosphere(lv)
+        om = orc.OracleMesh(m.V, m.T)
+        # radially project the directions onto the mesh
+        pts = []
+        for d in dirs:
+            for fi in range(m.nf):
+                A, B, Cc = m.V[m.T[fi]]
+                n = np.cross(B - A, Cc - A)
+                t = np.dot(A, n) / np.dot(d, n)
+                if t <= 0:
+                    continue
+                try:
+                    fb = locate(type("M", (), dict(V=m.V, T=m.T[fi:fi + 1], nf=1))(), t * d, tol=1e-9)
+                    pts.append((fi, fb[1]))
+                    break
+                except ValueError:
+                    continue
+        f = np.array([p[0] for p in pts], np.int32)
+        b = np.array([p[1] for p in pts])
+        pr = orc.geodesic_pairs(om, f, b, 1.5)
+        e = 0.0
+        for i in range(len(dirs)):
+            for j, p in pair_dict(pr, i).items():
+                e = max(e, abs(pr.dist[p] - math.acos(np.clip(dirs[i] @ dirs[j], -1, 1))))
+        errs.append(e)
+    assert all(errs[k + 1] < errs[k] / 2.5 for k in range(3)), errs
+
+
+# ----------------------------------------------------------------- CF14 ----
+@pytest.mark.parametrize("mk,n,cut", [(lambda: W.bumpy_sphere(3, 0.15), 40, 0.7),
+                                      (lambda: W.torus(1.0, 0.3, 24, 10), 40, 0.8)])
+def test_global_invariants(orc, mk, n, cut):
+    """d_ij = d_ji (independent runs), triangle inequality, Euclidean lower
+    bound (Sec. 3.1, submeshing paragraph), unit tangents in the source face."""
+    m = mk()
+    om = orc.OracleMesh(m.V, m.T)
+    assert om.pseudo.sum() > 0
+    f, b = W.random_particles(m.nf, n, 9)
+    pr = orc.geodesic_pairs(om, f, b, cut)
+    x = om.xyz(f, b)
+    D = np.full((n, n), np.inf)
+    for i in range(n):
+        for j, p in pair_dict(pr, i).items():
+            D[i, j] = pr.dist[p]
+            assert pr.dist[p] >= np.linalg.norm(x[j] - x[i]) - 1e-15
+            t = pr.tan[p]
+            assert abs(np.linalg.norm(t) - 1) < 1e-12 and abs(t @ om.normal[f[i]]) < 1e-12
+    fin = np.isfinite(D)
+    assert np.array_equal(fin, fin.T)
+    assert np.max(np.abs(D[fin] - D.T[fin]) / D[fin]) < 1e-11
+    for k in range(n):
+        via = D[:, [k]] + D[[k], :]
+        ok = np.isfinite(via) & fin
+        assert np.all(D[ok] <= via[ok] + 1e-12)
+
+
+def test_oracle_sample_matches_full(orc):
+    m = W.icosphere(3)
+    om = orc.OracleMesh(m.V, m.T)
+    f, b = W.random_particles(m.nf, 64, 0)
+    full = orc.geodesic_pairs(om, f, b, 0.5)
+    src = np.array([3, 17, 40], np.int32)
+    part = orc.geodesic_pairs(om, f, b, 0.5, sources=src)
+    for k, i in enumerate(src):
+        a = slice(full.off[i], full.off[i + 1])
+        c = slice(part.off[k], part.off[k + 1])
+        assert np.array_equal(full.nbr[a], part.nbr[c]) and np.array_equal(full.dist[a], part.dist[c])
