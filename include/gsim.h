@@ -1,0 +1,181 @@
+/*
+ * gsim: geodesic-interaction hot path for particles on triangulated
+ * surfaces, for AMD MI355X (gfx950).
+ *
+ * Reference method: Webb & Sussman, "curvedSpaceSim: A framework for
+ * simulating particles interacting along geodesics" (arXiv 2404.19751).
+ * The operations exported here are the paper's two primitives for mesh
+ * spaces: "displacement" (geodesic distances l_ij and the tangent directions
+ * at the source, Sec. 2.1 last paragraph and Sec. 3.1) and "shift" (moving a
+ * particle straight across faces, rotating the displacement and the velocity
+ * about every crossed edge, Sec. 3.2), plus the force sum of Sec. 3.1 and the
+ * overdamped / Brownian updates of Sec. 2.1.
+ *
+ * Conventions shared by every call
+ *  - A particle position is a face index plus a barycentric triple of
+ *    doubles (Sec. 3, mesh-space models), bary[k] weighting the face's k-th
+ *    vertex tri[f][k]. Triples must be >= 0 and sum to 1 (to rounding).
+ *  - Vectors (forces, displacements, velocities, tangents) are 3D and lie in
+ *    the plane of the particle's current face (Sec. 3.2, first paragraph).
+ *  - Faces are listed counter-clockwise seen from outside (outward normals).
+ *  - Host pointers are borrowed for the duration of the call only and never
+ *    retained; device state is owned by the context. Calls named *_dev take
+ *    device pointers (e.g. a torch tensor's data_ptr) and are ordered on the
+ *    context's stream.
+ *  - Every call returns a gsim_status; nothing throws or aborts across the
+ *    ABI. gsim_last_error() describes the last failure on a context.
+ *  - A context is not thread-safe; its precision is fixed at creation.
+ */
+#ifndef GSIM_H
+#define GSIM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct gsim_ctx gsim_ctx;
+
+typedef enum {
+    GSIM_OK = 0,
+    GSIM_E_ARG = -1,      /* bad argument (null pointer, size, unknown id, out-of-range face) */
+    GSIM_E_MESH = -2,     /* mesh not a 2-manifold, inconsistently oriented, or a face angle < 1e-6 rad */
+    GSIM_E_OOM = -3,      /* device allocation failed */
+    GSIM_E_CAPACITY = -4, /* caller buffer too small: the required count is reported */
+    GSIM_E_DEVICE = -5,   /* HIP runtime error */
+    GSIM_E_STATE = -6,    /* e.g. no particles set on the mesh */
+    GSIM_E_LIMIT = -7     /* a per-source work limit was exceeded (see gsim_last_error) */
+} gsim_status;
+
+typedef enum { GSIM_FP64 = 0, GSIM_FP32_MIXED = 1 } gsim_precision;
+
+typedef struct {
+    int32_t nv, nf;
+    int32_t n_boundary_edges;
+    int32_t n_pseudo_sources; /* saddle (angle sum >= 2 pi - 1e-9) or boundary vertices */
+    double mean_edge, min_edge, max_edge;
+    double bbox_min[3], bbox_max[3];
+} gsim_mesh_info;
+
+/* Neighbour pairs (i -> j, j != i, d_ij < cutoff) as CSR rows sorted by j.
+ * The caller owns every buffer. On input `capacity` is the number of pair
+ * entries nbr/dist/tan/flags can hold; on return `count` is the number of
+ * pairs (also on GSIM_E_CAPACITY, so a second call can size the buffers). */
+typedef struct {
+    int64_t capacity;
+    int64_t count;
+    int64_t *off;   /* [n+1] */
+    int32_t *nbr;   /* [capacity] neighbour index j */
+    double *dist;   /* [capacity] geodesic distance d_ij */
+    double *tan;    /* [capacity][3] unit tangent at i towards j, in the plane of i's face */
+    uint8_t *flags; /* [capacity] GSIM_PAIR_* bits */
+} gsim_pairs;
+
+enum {
+    GSIM_PAIR_TIE = 1,     /* a second, different initial direction is within the tie gap (cut locus) */
+    GSIM_PAIR_ZERO = 2,    /* d == 0: tangent undefined, contributes no force */
+    GSIM_PAIR_GUARD = 4    /* distance re-checked in FP64 near the cutoff (FP32-mixed mode) */
+};
+
+typedef enum { GSIM_POT_HARMONIC = 0, GSIM_POT_COULOMB = 1, GSIM_POT_GAUSSIAN = 2 } gsim_potential_kind;
+
+/* harmonic: U = (k/2)(1 - d/sigma)^2 for d < sigma;  coulomb: U = k/d;
+ * gaussian: U = k exp(-d^2 / 2 sigma^2) (Sec. 2.1). cutoff <= 0 or
+ * non-finite means all pairs. */
+typedef struct {
+    int32_t kind;
+    double k, sigma, cutoff;
+} gsim_potential;
+
+typedef enum { GSIM_INT_OVERDAMPED = 0, GSIM_INT_BROWNIAN = 1 } gsim_integrator_kind;
+
+/* overdamped: D = mobility dt F.
+ * brownian:   friction D = dt F + sqrt(2 kT friction dt) (eta1 ex + eta2 ey),
+ *             eta from Philox4x32-10 with counter (particle, step lo, step hi, 0)
+ *             and key (seed lo, seed hi), Box-Muller on two 53-bit uniforms. */
+typedef struct {
+    int32_t kind;
+    double dt, mobility, kT, friction;
+    uint64_t seed;
+} gsim_integrator;
+
+typedef struct {
+    int64_t crossings, vertex_hits, boundary_hits, cap_hits, near_vertex;
+} gsim_walk_stats;
+
+/* ---- context ------------------------------------------------------------ */
+/* device: HIP device ordinal. hip_stream: a hipStream_t to run on, or NULL for
+ * a stream the context creates (default priority). */
+gsim_status gsim_create(int device, gsim_precision prec, void *hip_stream, gsim_ctx **out);
+void gsim_destroy(gsim_ctx *ctx);
+const char *gsim_last_error(const gsim_ctx *ctx); /* valid until the next call on ctx */
+gsim_status gsim_synchronize(gsim_ctx *ctx);
+
+/* ---- mesh ----------------------------------------------------------------
+ * Builds the half-edge structure, corner-angle sums, pseudo-source flags and
+ * per-half-edge unfolding constants on the host and copies them to device
+ * memory once. xyz[nv][3], tri[nf][3]. Returns GSIM_E_MESH for non-manifold
+ * or inconsistently oriented input or a face with an angle below 1e-6 rad. */
+gsim_status gsim_mesh_upload(gsim_ctx *ctx, int32_t nv, const double *xyz, int32_t nf, const int32_t *tri,
+                             int32_t *mesh_id);
+gsim_status gsim_mesh_info_get(gsim_ctx *ctx, int32_t mesh_id, gsim_mesh_info *out);
+
+/* ---- particle state -------------------------------------------------------
+ * face[n], bary[n][3], vel[n][3] (NULL = zero velocities). */
+gsim_status gsim_particles_set(gsim_ctx *ctx, int32_t mesh_id, int32_t n, const int32_t *face, const double *bary,
+                               const double *vel);
+/* any output pointer may be NULL; xyz[n][3] receives the 3D positions */
+gsim_status gsim_particles_get(gsim_ctx *ctx, int32_t mesh_id, int32_t *face, double *bary, double *vel,
+                               double *xyz);
+gsim_status gsim_particles_set_dev(gsim_ctx *ctx, int32_t mesh_id, int32_t n, const int32_t *face_dev,
+                                   const double *bary_dev, const double *vel_dev);
+gsim_status gsim_particles_get_dev(gsim_ctx *ctx, int32_t mesh_id, int32_t *face_dev, double *bary_dev,
+                                   double *vel_dev);
+
+/* ---- hot path -------------------------------------------------------------
+ * geodesic_pairs: exact polyhedral geodesic distance and initial unit tangent
+ * for every pair closer than `cutoff` (Sec. 3.1: sequence-tree distances and
+ * tangents relative to the source; submeshing by the Euclidean lower bound).
+ * Euclidean prefilter, window propagation and target query run on the GPU;
+ * the CSR is then copied to the caller's host buffers. */
+gsim_status gsim_geodesic_pairs(gsim_ctx *ctx, int32_t mesh_id, double cutoff, gsim_pairs *out);
+
+/* compute_forces: F_i = sum_j U'(d_ij) t_ij (Sec. 3.1 force sum; with t_ij
+ * pointing from i towards j a repulsive potential pushes i away from j) and
+ * E = (1/2) sum_i sum_j U(d_ij). force[n][3] host buffer; energy may be NULL.
+ * Recomputes the pairs for the potential's cutoff. */
+gsim_status gsim_compute_forces(gsim_ctx *ctx, int32_t mesh_id, const gsim_potential *pot, double *force,
+                                double *energy);
+
+/* displace_on_surface: the shift (Sec. 3.2). disp[n][3] host buffer; its
+ * component normal to the particle's face is removed first. With
+ * transport_velocity != 0 the stored velocities are parallel-transported
+ * along the walk. stats may be NULL. */
+gsim_status gsim_displace_on_surface(gsim_ctx *ctx, int32_t mesh_id, const double *disp, int transport_velocity,
+                                     gsim_walk_stats *stats);
+
+/* step: nsteps full time steps on device (prefilter, window propagation,
+ * query, forces, integrator, walk); state stays in device memory. The noise
+ * counter of step k is the number of steps taken on this mesh since its
+ * particles were last set (so a run can be resumed bit-identically). */
+gsim_status gsim_step(gsim_ctx *ctx, int32_t mesh_id, const gsim_potential *pot, const gsim_integrator *integ,
+                      int32_t nsteps);
+
+/* ---- instrumentation ------------------------------------------------------
+ * Per-kernel timing with HIP events recorded on the context's stream, only
+ * while enabled. name: "prefilter", "geodesic", "compact", "forces",
+ * "integrate", "walk". avg_ms is the mean launch duration. */
+gsim_status gsim_timing_enable(gsim_ctx *ctx, int on);
+gsim_status gsim_timing_get(gsim_ctx *ctx, const char *name, double *avg_ms, int64_t *launches);
+/* Work counters. Of the last geodesic pass: [0] windows processed,
+ * [1] windows pruned at the cutoff, [2] bend-vertex (pseudo-source) launches,
+ * [3] stale windows dropped, [4] candidate pairs, [5] neighbour pairs,
+ * [6] sources over a work limit. Summed over the passes since timing was
+ * last enabled: [7] neighbour pairs, [8] windows, [9] passes. c10[10]. */
+gsim_status gsim_counters_get(gsim_ctx *ctx, int64_t *c10);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

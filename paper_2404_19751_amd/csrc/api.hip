@@ -1,0 +1,675 @@
+// C-ABI of the gsim library: context, mesh upload, particle state and the
+// hot-path entry points. Device memory belongs to the context; host buffers
+// are borrowed for the duration of a call. No exception crosses the ABI.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/gsim.h"
+#include "gsim_internal.h"
+
+using namespace gsim;
+
+namespace {
+
+struct Buf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+struct MeshState {
+    HostMesh host;
+    DevMesh dm;
+    std::vector<Buf> owned;
+    // particles
+    int n = 0;
+    int32_t *face = nullptr;
+    double *bary = nullptr, *vel = nullptr, *xyz = nullptr;
+    // prefilter
+    Buf cell_of, cell_start, cell_fill, order, cand_cnt, cand_off, cand, tmp64;
+    // candidate-layout results
+    Buf cdist, ctan, cflags;
+    // pairs
+    Buf nbr_cnt, off, nbr, dist, tan, flags;
+    int64_t n_cand = 0, n_pairs = 0;
+    double pairs_cutoff = -1.0;
+    bool pairs_valid = false;
+    // forces / integrator
+    Buf F, Ei, E, disp, wflags;
+    uint64_t step = 0;  // steps taken since the state was set: the noise counter
+};
+
+struct TimingRec {
+    double total_ms = 0.0;
+    int64_t n = 0;
+};
+
+}  // namespace
+
+struct gsim_ctx {
+    int device = 0;
+    gsim_precision prec = GSIM_FP64;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    std::string err;
+    std::vector<MeshState *> meshes;
+    Buf stack, work, ctr, wstats, scan_scratch, sum_scratch;
+    int32_t nslots = 0;
+    GeoParams gp{};
+    Counters last{};
+    unsigned long long cum_pairs = 0, cum_windows = 0, cum_passes = 0;
+    bool timing = false;
+    std::map<std::string, TimingRec> times;
+    std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> pending;
+    std::vector<hipEvent_t> free_events;
+    int max_slots = 2048;
+};
+
+namespace {
+
+gsim_status fail(gsim_ctx *c, gsim_status s, const std::string &msg) {
+    if (c) c->err = msg;
+    return s;
+}
+
+#define HIPCHK(c, x)                                                                              \
+    do {                                                                                          \
+        hipError_t e_ = (x);                                                                      \
+        if (e_ != hipSuccess)                                                                     \
+            return fail(c, e_ == hipErrorOutOfMemory ? GSIM_E_OOM : GSIM_E_DEVICE,                \
+                        std::string(#x " failed: ") + hipGetErrorString(e_));                      \
+    } while (0)
+
+hipError_t ensure(Buf &b, size_t bytes) {
+    if (b.bytes >= bytes && b.p) return hipSuccess;
+    if (b.p) {
+        hipError_t e = hipFree(b.p);
+        if (e != hipSuccess) return e;
+        b.p = nullptr;
+        b.bytes = 0;
+    }
+    size_t want = std::max<size_t>(bytes + bytes / 4, 256);
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e == hipSuccess) b.bytes = want;
+    return e;
+}
+void release(Buf &b) {
+    if (b.p) (void)hipFree(b.p);
+    b.p = nullptr;
+    b.bytes = 0;
+}
+template <class T>
+T *P(Buf &b) {
+    return static_cast<T *>(b.p);
+}
+
+hipEvent_t take_event(gsim_ctx *c) {
+    if (!c->free_events.empty()) {
+        hipEvent_t e = c->free_events.back();
+        c->free_events.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+void resolve_timing(gsim_ctx *c) {
+    for (auto &p : c->pending) {
+        float ms = 0.f;
+        if (hipEventSynchronize(p.second.second) == hipSuccess &&
+            hipEventElapsedTime(&ms, p.second.first, p.second.second) == hipSuccess) {
+            TimingRec &r = c->times[p.first];
+            r.total_ms += ms;
+            r.n += 1;
+        }
+        c->free_events.push_back(p.second.first);
+        c->free_events.push_back(p.second.second);
+    }
+    c->pending.clear();
+}
+
+struct Stage {
+    gsim_ctx *c;
+    const char *name;
+    hipEvent_t a = nullptr, b = nullptr;
+    Stage(gsim_ctx *c_, const char *n) : c(c_), name(n) {
+        if (c->timing) {
+            a = take_event(c);
+            b = take_event(c);
+            if (a) (void)hipEventRecord(a, c->stream);
+        }
+    }
+    ~Stage() {
+        if (c->timing && a && b) {
+            (void)hipEventRecord(b, c->stream);
+            c->pending.push_back({name, {a, b}});
+            if (c->pending.size() > 4096) resolve_timing(c);
+        }
+    }
+};
+
+MeshState *get_mesh(gsim_ctx *c, int32_t id) {
+    if (!c || id < 0 || id >= (int32_t)c->meshes.size()) return nullptr;
+    return c->meshes[id];
+}
+
+bool finite_cutoff(double c) { return c > 0.0 && std::isfinite(c); }
+
+// ---------------------------------------------------------------- pairs
+gsim_status run_pairs(gsim_ctx *c, MeshState *ms, double cutoff) {
+    hipStream_t s = c->stream;
+    const int n = ms->n;
+    if (n <= 0) return fail(c, GSIM_E_STATE, "no particles on this mesh");
+    if (!finite_cutoff(cutoff)) return fail(c, GSIM_E_ARG, "cutoff must be positive and finite");
+    DevMesh &m = ms->dm;
+    {
+        Stage st(c, "prefilter");
+        HIPCHK(c, launch_xyz(m, n, ms->face, ms->bary, ms->xyz, s));
+        // cell grid: cells no smaller than the cutoff, at most 128 per axis
+        PrefilterBufs pb{};
+        double ext = 0.0;
+        for (int d = 0; d < 3; ++d) ext = std::max(ext, m.bbmax[d] - m.bbmin[d]);
+        double cell = std::max(cutoff, ext / 128.0);
+        int64_t ncell = 1;
+        for (int d = 0; d < 3; ++d) {
+            pb.dims[d] = std::max(1, (int)std::ceil((m.bbmax[d] - m.bbmin[d]) / cell));
+            ncell *= pb.dims[d];
+        }
+        pb.cell = cell;
+        HIPCHK(c, ensure(ms->cell_of, sizeof(int32_t) * n));
+        HIPCHK(c, ensure(ms->cell_start, sizeof(int32_t) * (ncell + 1)));
+        HIPCHK(c, ensure(ms->cell_fill, sizeof(int32_t) * ncell));
+        HIPCHK(c, ensure(ms->order, sizeof(int32_t) * n));
+        HIPCHK(c, ensure(ms->cand_cnt, sizeof(int32_t) * (n + 1)));
+        HIPCHK(c, ensure(ms->cand_off, sizeof(int64_t) * (n + 1)));
+        HIPCHK(c, ensure(ms->tmp64, sizeof(int64_t) * (std::max<int64_t>(ncell, n) + 1)));
+        size_t nb = (std::max<int64_t>(ncell, n) + 1023) / 1024 + 2;
+        HIPCHK(c, ensure(c->scan_scratch, sizeof(int64_t) * nb));
+        pb.xyz = ms->xyz;
+        pb.cell_of = P<int32_t>(ms->cell_of);
+        pb.cell_start = P<int32_t>(ms->cell_start);
+        pb.cell_fill = P<int32_t>(ms->cell_fill);
+        pb.order = P<int32_t>(ms->order);
+        pb.cand_cnt = P<int32_t>(ms->cand_cnt);
+        pb.cand_off = P<int64_t>(ms->cand_off);
+        HIPCHK(c, launch_prefilter_bin(m, n, pb, s));
+        HIPCHK(c, launch_scan_i32_to_i64(pb.cell_fill, P<int64_t>(ms->tmp64), (int)ncell, P<int64_t>(c->scan_scratch), s));
+        HIPCHK(c, launch_i64_to_i32(P<int64_t>(ms->tmp64), pb.cell_start, (int)ncell, s));
+        HIPCHK(c, launch_zero_i32(pb.cell_fill, ncell, s));
+        HIPCHK(c, launch_bin_scatter(n, pb, s));
+        HIPCHK(c, launch_prefilter_count(n, cutoff, pb, s));
+        HIPCHK(c, launch_scan_i32_to_i64(pb.cand_cnt, pb.cand_off, n, P<int64_t>(c->scan_scratch), s));
+        int64_t total = 0;
+        HIPCHK(c, hipMemcpyAsync(&total, pb.cand_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        ms->n_cand = total;
+        HIPCHK(c, ensure(ms->cand, sizeof(int32_t) * (total + 1)));
+        pb.cand = P<int32_t>(ms->cand);
+        pb.cand_cap = total;
+        HIPCHK(c, launch_prefilter_fill(n, cutoff, pb, s));
+        HIPCHK(c, ensure(ms->cdist, sizeof(double) * (total + 1)));
+        HIPCHK(c, ensure(ms->ctan, sizeof(double) * 3 * (total + 1)));
+        HIPCHK(c, ensure(ms->cflags, total + 1));
+        ms->owned.clear();
+    }
+    {
+        PrefilterBufs pb{};
+        pb.cand_off = P<int64_t>(ms->cand_off);
+        pb.cand = P<int32_t>(ms->cand);
+        pb.order = P<int32_t>(ms->order);
+        GeoParams gp = c->gp;
+        gp.cutoff = cutoff;
+        if (!(gp.launch_delta > 0.0)) gp.launch_delta = 0.5 * m.mean_edge;
+        int32_t nslots = std::min<int32_t>(n, c->max_slots);
+        HIPCHK(c, ensure(c->stack, (size_t)nslots * gp.stack_cap * window_record_bytes()));
+        HIPCHK(c, launch_zero_i32(P<int32_t>(c->work), 8, s));
+        HIPCHK(c, launch_zero_u64(P<unsigned long long>(c->ctr), 8, s));
+        GeoOut out{P<double>(ms->cdist), P<double>(ms->ctan), P<uint8_t>(ms->cflags)};
+        Stage st(c, "geodesic");
+        HIPCHK(c, launch_geodesic(m, n, ms->face, ms->bary, ms->xyz, pb, gp, out, P<char>(c->stack), nslots,
+                                  P<int32_t>(c->work), P<Counters>(c->ctr), c->prec == GSIM_FP32_MIXED, s));
+    }
+    {
+        Stage st(c, "compact");
+        HIPCHK(c, ensure(ms->nbr_cnt, sizeof(int32_t) * (n + 1)));
+        HIPCHK(c, ensure(ms->off, sizeof(int64_t) * (n + 1)));
+        HIPCHK(c, launch_count_nbrs(n, P<int64_t>(ms->cand_off), P<double>(ms->cdist), cutoff, P<int32_t>(ms->nbr_cnt), s));
+        HIPCHK(c, launch_scan_i32_to_i64(P<int32_t>(ms->nbr_cnt), P<int64_t>(ms->off), n, P<int64_t>(c->scan_scratch), s));
+        int64_t total = 0;
+        HIPCHK(c, hipMemcpyAsync(&total, P<int64_t>(ms->off) + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(&c->last, c->ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        ms->n_pairs = total;
+        HIPCHK(c, ensure(ms->nbr, sizeof(int32_t) * (total + 1)));
+        HIPCHK(c, ensure(ms->dist, sizeof(double) * (total + 1)));
+        HIPCHK(c, ensure(ms->tan, sizeof(double) * 3 * (total + 1)));
+        HIPCHK(c, ensure(ms->flags, total + 1));
+        HIPCHK(c, launch_compact(n, P<int64_t>(ms->cand_off), P<int32_t>(ms->cand), P<double>(ms->cdist),
+                                 P<double>(ms->ctan), P<uint8_t>(ms->cflags), cutoff, P<int64_t>(ms->off),
+                                 P<int32_t>(ms->nbr), P<double>(ms->dist), P<double>(ms->tan), P<uint8_t>(ms->flags), s));
+    }
+    c->last.cand_pairs = (unsigned long long)ms->n_cand;
+    c->last.nbr_pairs = (unsigned long long)ms->n_pairs;
+    c->cum_pairs += c->last.nbr_pairs;
+    c->cum_windows += c->last.windows;
+    c->cum_passes += 1;
+    ms->pairs_cutoff = cutoff;
+    ms->pairs_valid = true;
+    if (c->last.limited) {
+        ms->pairs_valid = false;
+        return fail(c, GSIM_E_LIMIT,
+                    std::to_string(c->last.limited) +
+                        " source(s) exceeded a per-source limit (candidates > 128, bend vertices > 256, window "
+                        "stack or window count)");
+    }
+    return GSIM_OK;
+}
+
+template <class T>
+hipError_t upload(T *&dst, const T *src, size_t count, hipStream_t s) {
+    hipError_t e = hipMalloc(&dst, sizeof(T) * std::max<size_t>(count, 1));
+    if (e != hipSuccess) return e;
+    if (count) e = hipMemcpyAsync(dst, src, sizeof(T) * count, hipMemcpyHostToDevice, s);
+    return e;
+}
+
+int pot_kind_ok(const gsim_potential *p) { return p && p->kind >= 0 && p->kind <= 2; }
+
+gsim_status run_forces(gsim_ctx *c, MeshState *ms, const gsim_potential *pot) {
+    const int n = ms->n;
+    HIPCHK(c, ensure(ms->F, sizeof(double) * 3 * n));
+    HIPCHK(c, ensure(ms->Ei, sizeof(double) * n));
+    HIPCHK(c, ensure(ms->E, sizeof(double) * 4));
+    HIPCHK(c, ensure(c->sum_scratch, sizeof(double) * ((n + 255) / 256 + 2)));
+    Stage st(c, "forces");
+    HIPCHK(c, launch_forces(n, P<int64_t>(ms->off), P<double>(ms->dist), P<double>(ms->tan), pot->kind, pot->k,
+                            pot->sigma, P<double>(ms->F), P<double>(ms->Ei), c->stream));
+    HIPCHK(c, launch_sum(P<double>(ms->Ei), n, P<double>(ms->E), P<double>(c->sum_scratch), c->stream));
+    return GSIM_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+gsim_status gsim_create(int device, gsim_precision prec, void *hip_stream, gsim_ctx **out) {
+    if (!out) return GSIM_E_ARG;
+    *out = nullptr;
+    if (prec != GSIM_FP64 && prec != GSIM_FP32_MIXED) return GSIM_E_ARG;
+    gsim_ctx *c = new (std::nothrow) gsim_ctx();
+    if (!c) return GSIM_E_OOM;
+    c->device = device;
+    c->prec = prec;
+    if (hipSetDevice(device) != hipSuccess) {
+        delete c;
+        return GSIM_E_DEVICE;
+    }
+    if (hip_stream) {
+        c->stream = (hipStream_t)hip_stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return GSIM_E_DEVICE;
+        }
+        c->own_stream = true;
+    }
+    c->gp.cutoff = 0.0;
+    c->gp.launch_delta = 0.0;  // 0 = half the mean edge length
+    c->gp.cone_tol = prec == GSIM_FP64 ? 1e-12 : 1e-6;
+    c->gp.tie_rel = prec == GSIM_FP64 ? 1e-9 : 1e-4;
+    c->gp.stack_cap = 4096;
+    c->gp.max_windows = 4000000;
+    if (ensure(c->work, sizeof(int32_t) * 8) != hipSuccess || ensure(c->ctr, sizeof(Counters)) != hipSuccess ||
+        ensure(c->wstats, sizeof(unsigned long long) * 8) != hipSuccess) {
+        gsim_destroy(c);
+        return GSIM_E_OOM;
+    }
+    *out = c;
+    return GSIM_OK;
+}
+
+void gsim_destroy(gsim_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    resolve_timing(c);
+    for (auto e : c->free_events) (void)hipEventDestroy(e);
+    for (MeshState *ms : c->meshes) {
+        if (!ms) continue;
+        for (Buf *b : {&ms->cell_of, &ms->cell_start, &ms->cell_fill, &ms->order, &ms->cand_cnt, &ms->cand_off,
+                       &ms->cand, &ms->tmp64, &ms->cdist, &ms->ctan, &ms->cflags, &ms->nbr_cnt, &ms->off, &ms->nbr,
+                       &ms->dist, &ms->tan, &ms->flags, &ms->F, &ms->Ei, &ms->E, &ms->disp, &ms->wflags})
+            release(*b);
+        for (void *p : {(void *)ms->face, (void *)ms->bary, (void *)ms->vel, (void *)ms->xyz})
+            if (p) (void)hipFree(p);
+        for (void *p : {(void *)ms->dm.V, (void *)ms->dm.T, (void *)ms->dm.he, (void *)ms->dm.hef,
+                        (void *)ms->dm.vflag, (void *)ms->dm.theta, (void *)ms->dm.fan_off, (void *)ms->dm.fan,
+                        (void *)ms->dm.corner, (void *)ms->dm.fnrm})
+            if (p) (void)hipFree(p);
+        delete ms;
+    }
+    for (Buf *b : {&c->stack, &c->work, &c->ctr, &c->wstats, &c->scan_scratch, &c->sum_scratch}) release(*b);
+    if (c->own_stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+const char *gsim_last_error(const gsim_ctx *c) { return c ? c->err.c_str() : "null context"; }
+
+gsim_status gsim_synchronize(gsim_ctx *c) {
+    if (!c) return GSIM_E_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return GSIM_OK;
+}
+
+gsim_status gsim_mesh_upload(gsim_ctx *c, int32_t nv, const double *xyz, int32_t nf, const int32_t *tri,
+                             int32_t *mesh_id) {
+    if (!c || !mesh_id || !xyz || !tri || nv < 3 || nf < 1) return fail(c, GSIM_E_ARG, "bad mesh arguments");
+    try {
+        MeshState *ms = new MeshState();
+        std::string why = build_host_mesh(nv, xyz, nf, tri, ms->host);
+        if (!why.empty()) {
+            delete ms;
+            return fail(c, GSIM_E_MESH, "mesh rejected: " + why);
+        }
+        HostMesh &H = ms->host;
+        DevMesh &d = ms->dm;
+        d.nv = nv;
+        d.nf = nf;
+        hipStream_t s = c->stream;
+        (void)hipSetDevice(c->device);
+        HIPCHK(c, upload(d.V, H.V.data(), H.V.size(), s));
+        HIPCHK(c, upload(d.T, H.T.data(), H.T.size(), s));
+        HIPCHK(c, upload(d.he, H.he.data(), H.he.size(), s));
+        HIPCHK(c, upload(d.hef, H.hef.data(), H.hef.size(), s));
+        HIPCHK(c, upload(d.vflag, H.vflag.data(), H.vflag.size(), s));
+        HIPCHK(c, upload(d.theta, H.theta.data(), H.theta.size(), s));
+        HIPCHK(c, upload(d.fan_off, H.fan_off.data(), H.fan_off.size(), s));
+        HIPCHK(c, upload(d.fan, H.fan.data(), H.fan.size(), s));
+        HIPCHK(c, upload(d.corner, H.corner.data(), H.corner.size(), s));
+        HIPCHK(c, upload(d.fnrm, H.fnrm.data(), H.fnrm.size(), s));
+        for (int k = 0; k < 3; ++k) {
+            d.bbmin[k] = H.bbmin[k];
+            d.bbmax[k] = H.bbmax[k];
+        }
+        d.mean_edge = H.mean_edge;
+        d.min_edge = H.min_edge;
+        d.max_edge = H.max_edge;
+        d.n_boundary_edges = H.n_boundary_edges;
+        d.n_pseudo = H.n_pseudo;
+        HIPCHK(c, hipStreamSynchronize(s));
+        c->meshes.push_back(ms);
+        *mesh_id = (int32_t)c->meshes.size() - 1;
+        return GSIM_OK;
+    } catch (const std::bad_alloc &) {
+        return fail(c, GSIM_E_OOM, "host allocation failed");
+    } catch (...) {
+        return fail(c, GSIM_E_ARG, "unexpected host error during mesh upload");
+    }
+}
+
+gsim_status gsim_mesh_info_get(gsim_ctx *c, int32_t id, gsim_mesh_info *out) {
+    MeshState *ms = get_mesh(c, id);
+    if (!ms || !out) return fail(c, GSIM_E_ARG, "unknown mesh id");
+    const DevMesh &d = ms->dm;
+    out->nv = d.nv;
+    out->nf = d.nf;
+    out->n_boundary_edges = d.n_boundary_edges;
+    out->n_pseudo_sources = d.n_pseudo;
+    out->mean_edge = d.mean_edge;
+    out->min_edge = d.min_edge;
+    out->max_edge = d.max_edge;
+    for (int k = 0; k < 3; ++k) {
+        out->bbox_min[k] = d.bbmin[k];
+        out->bbox_max[k] = d.bbmax[k];
+    }
+    return GSIM_OK;
+}
+
+static gsim_status alloc_particles(gsim_ctx *c, MeshState *ms, int32_t n) {
+    if (ms->n == n && ms->face) return GSIM_OK;
+    for (void *p : {(void *)ms->face, (void *)ms->bary, (void *)ms->vel, (void *)ms->xyz})
+        if (p) (void)hipFree(p);
+    ms->face = nullptr;
+    ms->bary = ms->vel = ms->xyz = nullptr;
+    ms->n = 0;
+    HIPCHK(c, hipMalloc(&ms->face, sizeof(int32_t) * std::max(n, 1)));
+    HIPCHK(c, hipMalloc(&ms->bary, sizeof(double) * 3 * std::max(n, 1)));
+    HIPCHK(c, hipMalloc(&ms->vel, sizeof(double) * 3 * std::max(n, 1)));
+    HIPCHK(c, hipMalloc(&ms->xyz, sizeof(double) * 3 * std::max(n, 1)));
+    ms->n = n;
+    return GSIM_OK;
+}
+
+static gsim_status check_state(gsim_ctx *c, const MeshState *ms, int32_t n, const int32_t *face, const double *bary) {
+    for (int32_t i = 0; i < n; ++i) {
+        if (face[i] < 0 || face[i] >= ms->dm.nf) return fail(c, GSIM_E_ARG, "face index out of range");
+        const double *b = bary + 3 * (size_t)i;
+        int zeros = 0;
+        for (int k = 0; k < 3; ++k) {
+            if (!(b[k] >= 0.0) || !(b[k] <= 1.0)) return fail(c, GSIM_E_ARG, "barycentric coordinate outside [0,1]");
+            zeros += b[k] == 0.0;
+        }
+        if (std::fabs(b[0] + b[1] + b[2] - 1.0) > 1e-9) return fail(c, GSIM_E_ARG, "barycentric triple must sum to 1");
+        if (zeros >= 2) return fail(c, GSIM_E_ARG, "particle placed exactly on a vertex");
+    }
+    return GSIM_OK;
+}
+
+gsim_status gsim_particles_set(gsim_ctx *c, int32_t id, int32_t n, const int32_t *face, const double *bary,
+                               const double *vel) {
+    MeshState *ms = get_mesh(c, id);
+    if (!ms || n < 1 || !face || !bary) return fail(c, GSIM_E_ARG, "bad particle arguments");
+    gsim_status st = check_state(c, ms, n, face, bary);
+    if (st != GSIM_OK) return st;
+    if ((st = alloc_particles(c, ms, n)) != GSIM_OK) return st;
+    hipStream_t s = c->stream;
+    HIPCHK(c, hipMemcpyAsync(ms->face, face, sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(ms->bary, bary, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s));
+    if (vel) HIPCHK(c, hipMemcpyAsync(ms->vel, vel, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s));
+    else HIPCHK(c, hipMemsetAsync(ms->vel, 0, sizeof(double) * 3 * n, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    ms->pairs_valid = false;
+    ms->step = 0;
+    return GSIM_OK;
+}
+
+gsim_status gsim_particles_set_dev(gsim_ctx *c, int32_t id, int32_t n, const int32_t *face, const double *bary,
+                                   const double *vel) {
+    MeshState *ms = get_mesh(c, id);
+    if (!ms || n < 1 || !face || !bary) return fail(c, GSIM_E_ARG, "bad particle arguments");
+    gsim_status st = alloc_particles(c, ms, n);
+    if (st != GSIM_OK) return st;
+    hipStream_t s = c->stream;
+    HIPCHK(c, hipMemcpyAsync(ms->face, face, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(ms->bary, bary, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
+    if (vel) HIPCHK(c, hipMemcpyAsync(ms->vel, vel, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
+    else HIPCHK(c, hipMemsetAsync(ms->vel, 0, sizeof(double) * 3 * n, s));
+    ms->pairs_valid = false;
+    ms->step = 0;
+    return GSIM_OK;
+}
+
+gsim_status gsim_particles_get(gsim_ctx *c, int32_t id, int32_t *face, double *bary, double *vel, double *xyz) {
+    MeshState *ms = get_mesh(c, id);
+    if (!ms) return fail(c, GSIM_E_ARG, "unknown mesh id");
+    if (ms->n <= 0) return fail(c, GSIM_E_STATE, "no particles on this mesh");
+    hipStream_t s = c->stream;
+    const int n = ms->n;
+    if (face) HIPCHK(c, hipMemcpyAsync(face, ms->face, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    if (bary) HIPCHK(c, hipMemcpyAsync(bary, ms->bary, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s));
+    if (vel) HIPCHK(c, hipMemcpyAsync(vel, ms->vel, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s));
+    if (xyz) {
+        HIPCHK(c, launch_xyz(ms->dm, n, ms->face, ms->bary, ms->xyz, s));
+        HIPCHK(c, hipMemcpyAsync(xyz, ms->xyz, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s));
+    }
+    HIPCHK(c, hipStreamSynchronize(s));
+    return GSIM_OK;
+}
+
+gsim_status gsim_particles_get_dev(gsim_ctx *c, int32_t id, int32_t *face, double *bary, double *vel) {
+    MeshState *ms = get_mesh(c, id);
+    if (!ms) return fail(c, GSIM_E_ARG, "unknown mesh id");
+    if (ms->n <= 0) return fail(c, GSIM_E_STATE, "no particles on this mesh");
+    hipStream_t s = c->stream;
+    const int n = ms->n;
+    if (face) HIPCHK(c, hipMemcpyAsync(face, ms->face, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+    if (bary) HIPCHK(c, hipMemcpyAsync(bary, ms->bary, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
+    if (vel) HIPCHK(c, hipMemcpyAsync(vel, ms->vel, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
+    return GSIM_OK;
+}
+
+gsim_status gsim_geodesic_pairs(gsim_ctx *c, int32_t id, double cutoff, gsim_pairs *out) {
+    MeshState *ms = get_mesh(c, id);
+    if (!ms || !out) return fail(c, GSIM_E_ARG, "bad arguments");
+    try {
+        gsim_status st = run_pairs(c, ms, cutoff);
+        if (st != GSIM_OK) return st;
+        out->count = ms->n_pairs;
+        if (out->capacity < ms->n_pairs || !out->off || (ms->n_pairs && (!out->nbr || !out->dist || !out->tan)))
+            return fail(c, GSIM_E_CAPACITY, "pair buffers too small: " + std::to_string(ms->n_pairs) + " needed");
+        hipStream_t s = c->stream;
+        const int64_t P_ = ms->n_pairs;
+        HIPCHK(c, hipMemcpyAsync(out->off, ms->off.p, sizeof(int64_t) * (ms->n + 1), hipMemcpyDeviceToHost, s));
+        if (P_) {
+            HIPCHK(c, hipMemcpyAsync(out->nbr, ms->nbr.p, sizeof(int32_t) * P_, hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipMemcpyAsync(out->dist, ms->dist.p, sizeof(double) * P_, hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipMemcpyAsync(out->tan, ms->tan.p, sizeof(double) * 3 * P_, hipMemcpyDeviceToHost, s));
+            if (out->flags) HIPCHK(c, hipMemcpyAsync(out->flags, ms->flags.p, P_, hipMemcpyDeviceToHost, s));
+        }
+        HIPCHK(c, hipStreamSynchronize(s));
+        return GSIM_OK;
+    } catch (...) {
+        return fail(c, GSIM_E_ARG, "unexpected host error");
+    }
+}
+
+gsim_status gsim_compute_forces(gsim_ctx *c, int32_t id, const gsim_potential *pot, double *force, double *energy) {
+    MeshState *ms = get_mesh(c, id);
+    if (!ms || !pot_kind_ok(pot) || !force) return fail(c, GSIM_E_ARG, "bad arguments");
+    try {
+        gsim_status st = run_pairs(c, ms, pot->cutoff);
+        if (st != GSIM_OK) return st;
+        if ((st = run_forces(c, ms, pot)) != GSIM_OK) return st;
+        hipStream_t s = c->stream;
+        HIPCHK(c, hipMemcpyAsync(force, ms->F.p, sizeof(double) * 3 * ms->n, hipMemcpyDeviceToHost, s));
+        if (energy) HIPCHK(c, hipMemcpyAsync(energy, ms->E.p, sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        return GSIM_OK;
+    } catch (...) {
+        return fail(c, GSIM_E_ARG, "unexpected host error");
+    }
+}
+
+gsim_status gsim_displace_on_surface(gsim_ctx *c, int32_t id, const double *disp, int transport_velocity,
+                                     gsim_walk_stats *stats) {
+    MeshState *ms = get_mesh(c, id);
+    if (!ms || !disp) return fail(c, GSIM_E_ARG, "bad arguments");
+    if (ms->n <= 0) return fail(c, GSIM_E_STATE, "no particles on this mesh");
+    const int n = ms->n;
+    hipStream_t s = c->stream;
+    HIPCHK(c, ensure(ms->disp, sizeof(double) * 3 * n));
+    HIPCHK(c, ensure(ms->wflags, n));
+    HIPCHK(c, hipMemcpyAsync(ms->disp.p, disp, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s));
+    HIPCHK(c, launch_zero_u64(P<unsigned long long>(c->wstats), 8, s));
+    {
+        Stage st(c, "walk");
+        HIPCHK(c, launch_walk(ms->dm, n, ms->face, ms->bary, P<double>(ms->disp), transport_velocity ? ms->vel : nullptr,
+                              P<unsigned long long>(c->wstats), P<uint8_t>(ms->wflags), s));
+    }
+    unsigned long long h[8];
+    HIPCHK(c, hipMemcpyAsync(h, c->wstats.p, sizeof(h), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (stats) {
+        stats->crossings = (int64_t)h[0];
+        stats->vertex_hits = (int64_t)h[1];
+        stats->boundary_hits = (int64_t)h[2];
+        stats->cap_hits = (int64_t)h[3];
+        stats->near_vertex = (int64_t)h[4];
+    }
+    ms->pairs_valid = false;
+    return GSIM_OK;
+}
+
+gsim_status gsim_step(gsim_ctx *c, int32_t id, const gsim_potential *pot, const gsim_integrator *integ,
+                      int32_t nsteps) {
+    MeshState *ms = get_mesh(c, id);
+    if (!ms || !pot_kind_ok(pot) || !integ || nsteps < 0) return fail(c, GSIM_E_ARG, "bad arguments");
+    if (integ->kind != GSIM_INT_OVERDAMPED && integ->kind != GSIM_INT_BROWNIAN)
+        return fail(c, GSIM_E_ARG, "unknown integrator");
+    if (ms->n <= 0) return fail(c, GSIM_E_STATE, "no particles on this mesh");
+    const int n = ms->n;
+    hipStream_t s = c->stream;
+    try {
+        HIPCHK(c, ensure(ms->disp, sizeof(double) * 3 * n));
+        HIPCHK(c, ensure(ms->wflags, n));
+        for (int32_t k = 0; k < nsteps; ++k) {
+            gsim_status st = run_pairs(c, ms, pot->cutoff);
+            if (st != GSIM_OK) return st;
+            if ((st = run_forces(c, ms, pot)) != GSIM_OK) return st;
+            {
+                Stage sg(c, "integrate");
+                HIPCHK(c, launch_integrate(ms->dm, n, ms->face, P<double>(ms->F), integ->kind, integ->dt,
+                                           integ->mobility, integ->kT, integ->friction, integ->seed, ms->step,
+                                           P<double>(ms->disp), s));
+            }
+            {
+                Stage sg(c, "walk");
+                HIPCHK(c, launch_walk(ms->dm, n, ms->face, ms->bary, P<double>(ms->disp), ms->vel, nullptr,
+                                      P<uint8_t>(ms->wflags), s));
+            }
+            ms->step++;
+            ms->pairs_valid = false;
+        }
+        return GSIM_OK;
+    } catch (...) {
+        return fail(c, GSIM_E_ARG, "unexpected host error");
+    }
+}
+
+gsim_status gsim_timing_enable(gsim_ctx *c, int on) {
+    if (!c) return GSIM_E_ARG;
+    resolve_timing(c);
+    c->timing = on != 0;
+    if (on) {
+        c->times.clear();
+        c->cum_pairs = c->cum_windows = c->cum_passes = 0;
+    }
+    return GSIM_OK;
+}
+
+gsim_status gsim_timing_get(gsim_ctx *c, const char *name, double *avg_ms, int64_t *launches) {
+    if (!c || !name) return GSIM_E_ARG;
+    resolve_timing(c);
+    auto it = c->times.find(name);
+    if (it == c->times.end()) {
+        if (avg_ms) *avg_ms = 0.0;
+        if (launches) *launches = 0;
+        return GSIM_OK;
+    }
+    if (avg_ms) *avg_ms = it->second.n ? it->second.total_ms / double(it->second.n) : 0.0;
+    if (launches) *launches = it->second.n;
+    return GSIM_OK;
+}
+
+gsim_status gsim_counters_get(gsim_ctx *c, int64_t *c10) {
+    if (!c || !c10) return GSIM_E_ARG;
+    c10[7] = (int64_t)c->cum_pairs;
+    c10[8] = (int64_t)c->cum_windows;
+    c10[9] = (int64_t)c->cum_passes;
+    c10[0] = (int64_t)c->last.windows;
+    c10[1] = (int64_t)c->last.pruned;
+    c10[2] = (int64_t)c->last.launches;
+    c10[3] = (int64_t)c->last.stale;
+    c10[4] = (int64_t)c->last.cand_pairs;
+    c10[5] = (int64_t)c->last.nbr_pairs;
+    c10[6] = (int64_t)c->last.limited;
+    return GSIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,145 @@
+// Internal declarations shared by the host API and the kernel translation
+// units of the gsim library. Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+namespace gsim {
+
+// Per-half-edge unfolding record. Half-edge h = 3f + k runs from vertex
+// T[f][k] (A) to T[f][(k+1)%3] (B); face f lies on its left. The "edge frame"
+// of h has its origin at A, x along A->B, y towards the opposite vertex C.
+struct alignas(16) HeRec {
+    double L;    // |AB|
+    double cx;   // C in the edge frame (cy > 0)
+    double cy;
+    double Lp;   // |CA| = length of prev(h)
+    double Ln;   // |BC| = length of next(h)
+    int32_t tn;  // twin(next(h)) : the half-edge entered across BC, -1 on the boundary
+    int32_t tp;  // twin(prev(h)) : the half-edge entered across CA
+    int32_t opp; // vertex C
+    int32_t flags;  // bit0: C is a pseudo-source vertex
+    int32_t twin;   // twin(h)
+    int32_t pad;
+};
+static_assert(sizeof(HeRec) == 64, "HeRec must be one 64-byte record");
+
+// FP32 copy of the geometric part (FP32-mixed mode).
+struct alignas(16) HeRecF {
+    float L, cx, cy, Lp;
+    float Ln;
+    int32_t tn, tp;
+    int32_t opp_flags;  // (opp << 1) | pseudo
+};
+static_assert(sizeof(HeRecF) == 32, "HeRecF must be 32 bytes");
+
+enum : uint8_t { VF_PSEUDO = 1, VF_BOUNDARY = 2 };
+enum : uint8_t { GSIM_PAIR_TIE_BIT = 1, GSIM_PAIR_ZERO_BIT = 2, GSIM_PAIR_GUARD_BIT = 4 };
+
+struct DevMesh {
+    int32_t nv = 0, nf = 0;
+    double *V = nullptr;        // [nv][3]
+    int32_t *T = nullptr;       // [nf][3]
+    HeRec *he = nullptr;        // [3nf]
+    HeRecF *hef = nullptr;      // [3nf]
+    uint8_t *vflag = nullptr;   // [nv]
+    double *theta = nullptr;    // [nv] corner-angle sum
+    int32_t *fan_off = nullptr; // [nv+1]
+    int32_t *fan = nullptr;     // [3nf] outgoing half-edges, CCW, boundary fans start clockwise-most
+    double *corner = nullptr;   // [3nf] corner angle of face h/3 at the tail of h
+    double *fnrm = nullptr;     // [nf][3] unit outward normal
+    double bbmin[3], bbmax[3];
+    double mean_edge = 0, min_edge = 0, max_edge = 0;
+    int32_t n_boundary_edges = 0, n_pseudo = 0;
+};
+
+// Host-side mesh analysis (mesh_build.cpp).
+struct HostMesh {
+    int nv = 0, nf = 0;
+    std::vector<double> V;
+    std::vector<int32_t> T;
+    std::vector<int32_t> twin;
+    std::vector<HeRec> he;
+    std::vector<HeRecF> hef;
+    std::vector<uint8_t> vflag;
+    std::vector<double> theta, corner, fnrm;
+    std::vector<int32_t> fan_off, fan;
+    double bbmin[3], bbmax[3];
+    double mean_edge = 0, min_edge = 0, max_edge = 0;
+    int32_t n_boundary_edges = 0, n_pseudo = 0;
+};
+// Returns empty string on success, else the reason the mesh is rejected.
+std::string build_host_mesh(int nv, const double *xyz, int nf, const int32_t *tri, HostMesh &out);
+
+// ---------------------------------------------------------------- kernels
+struct PrefilterBufs {
+    double *xyz;          // [n][3]
+    int32_t *cell_of;     // [n]
+    int32_t *cell_start;  // [ncell+1]
+    int32_t *cell_fill;   // [ncell]
+    int32_t *order;       // [n] particles sorted by cell
+    int32_t *cand_cnt;    // [n+1] (scan in place -> cand_off)
+    int64_t *cand_off;    // [n+1]
+    int32_t *cand;        // [cap]
+    int64_t cand_cap;
+    int32_t dims[3];
+    double cell;
+};
+
+struct GeoParams {
+    double cutoff;        // > 0, finite
+    double launch_delta;  // bend-vertex launch bucket width
+    double cone_tol;      // relative closed-cone slack
+    double tie_rel;       // tie gap (relative)
+    int32_t stack_cap;    // windows per stack slot
+    int32_t max_windows;  // per-source work limit
+};
+
+struct GeoOut {
+    double *dist;   // [cand_cap]  (cand layout)
+    double *tan;    // [cand_cap][3]
+    uint8_t *flags; // [cand_cap]
+};
+
+struct Counters {   // device-side, int64
+    unsigned long long windows, pruned, launches, stale, cand_pairs, nbr_pairs, limited, pad;
+};
+
+// launchers (return hipError_t of the launch)
+hipError_t launch_xyz(const DevMesh &m, int n, const int32_t *face, const double *bary, double *xyz,
+                      hipStream_t s);
+hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t s);
+hipError_t launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t s);
+hipError_t launch_prefilter_bin(const DevMesh &m, int n, PrefilterBufs &b, hipStream_t s);
+hipError_t launch_prefilter_count(int n, double cutoff, PrefilterBufs &b, hipStream_t s);
+hipError_t launch_prefilter_fill(int n, double cutoff, PrefilterBufs &b, hipStream_t s);
+hipError_t launch_scan_i32_to_i64(const int32_t *in, int64_t *out, int n, int64_t *scratch, hipStream_t s);
+hipError_t launch_scan_i32_inplace(int32_t *inout, int n, int32_t *scratch, hipStream_t s);
+
+hipError_t launch_geodesic(const DevMesh &m, int n, const int32_t *face, const double *bary, const double *xyz,
+                           const PrefilterBufs &pb, const GeoParams &gp, GeoOut out, char *stack_mem,
+                           int32_t nslots, int32_t *work_ctr, Counters *ctr, bool fp32, hipStream_t s);
+
+hipError_t launch_bin_scatter(int n, PrefilterBufs &b, hipStream_t s);
+hipError_t launch_i64_to_i32(const int64_t *in, int32_t *out, int n, hipStream_t s);
+size_t window_record_bytes();
+
+hipError_t launch_count_nbrs(int n, const int64_t *cand_off, const double *dist, double cutoff, int32_t *cnt,
+                             hipStream_t s);
+hipError_t launch_compact(int n, const int64_t *cand_off, const int32_t *cand, const double *dist,
+                          const double *tan, const uint8_t *flags, double cutoff, const int64_t *off,
+                          int32_t *nbr, double *odist, double *otan, uint8_t *oflags, hipStream_t s);
+
+hipError_t launch_forces(int n, const int64_t *off, const double *dist, const double *tan, int kind, double k,
+                         double sigma, double *F, double *Ei, hipStream_t s);
+hipError_t launch_sum(const double *x, int n, double *out, double *scratch, hipStream_t s);
+hipError_t launch_integrate(const DevMesh &m, int n, const int32_t *face, const double *F, int kind, double dt,
+                            double mobility, double kT, double friction, uint64_t seed, uint64_t step,
+                            double *disp, hipStream_t s);
+hipError_t launch_walk(const DevMesh &m, int n, int32_t *face, double *bary, const double *disp, double *vel,
+                       unsigned long long *stats, uint8_t *flags, hipStream_t s);
+
+}  // namespace gsim

@@ -1,0 +1,223 @@
+// The shift (arXiv 2404.19751, Sec. 3.2): move each particle by its
+// displacement along a straight path across faces. Exit edges are found in
+// barycentric coordinates (the rate of change of each coordinate along the
+// unit direction); at every crossed edge the particle moves into the face
+// across it and the direction and the velocity are rotated about the edge
+// axis into the new face's plane (parallel transport). A path through a
+// vertex leaves along the straightest direction (Polthier-Schmies: equal
+// angle on both sides, i.e. half the vertex's angle sum). At a boundary edge
+// the remaining displacement is reflected in the face plane; at a boundary
+// vertex it is reversed.
+//
+// One lane per particle, FP64 throughout; the face-crossing loop is
+// latency-bound on the face/vertex records, which stay in L2.
+#include <cmath>
+
+#include "gsim_internal.h"
+
+namespace gsim {
+namespace {
+
+constexpr int kWalkCap = 10000;
+constexpr double kVertexTol = 1e-12;  // x mean edge: exit parameters this close meet at a vertex
+constexpr double kNearTol = 1e-9;     // x mean edge: a pass this close to a vertex is flagged
+
+struct d3 {
+    double x, y, z;
+};
+__device__ inline d3 ld3(const double *p) { return {p[0], p[1], p[2]}; }
+__device__ inline d3 operator-(d3 a, d3 b) { return {a.x - b.x, a.y - b.y, a.z - b.z}; }
+__device__ inline d3 operator+(d3 a, d3 b) { return {a.x + b.x, a.y + b.y, a.z + b.z}; }
+__device__ inline d3 operator*(double s, d3 a) { return {s * a.x, s * a.y, s * a.z}; }
+__device__ inline double dot(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * b.z; }
+__device__ inline d3 cross(d3 a, d3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
+__device__ inline d3 unit(d3 a) { return (1.0 / sqrt(dot(a, a))) * a; }
+
+__global__ __launch_bounds__(128) void k_walk(DevMesh m, int n, int32_t *__restrict__ face, double *__restrict__ bary,
+                       const double *__restrict__ disp, double *__restrict__ vel, unsigned long long *__restrict__ stats,
+                       uint8_t *__restrict__ flags) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int f = face[i];
+    double b[3] = {bary[3 * i], bary[3 * i + 1], bary[3 * i + 2]};
+    d3 nf = ld3(m.fnrm + 3 * (int64_t)f);
+    d3 D = ld3(disp + 3 * (int64_t)i);
+    D = D - dot(D, nf) * nf;
+    d3 v = {0, 0, 0};
+    const bool hv = vel != nullptr;
+    if (hv) {
+        v = ld3(vel + 3 * (int64_t)i);
+        v = v - dot(v, nf) * nf;
+    }
+    double rem = sqrt(dot(D, D));
+    unsigned cross_n = 0, vhit = 0, bhit = 0, cap = 0, near = 0;
+    uint8_t fl = 0;
+    const double lbar = m.mean_edge;
+    if (rem > 0.0) {
+        d3 u = (1.0 / rem) * D;
+        int excl = -1;   // slot whose edge was just crossed/reflected: not an exit
+        int onlyk = -1;  // sitting on the vertex of this slot: only its opposite edge is an exit
+        for (int it = 0;; ++it) {
+            if (it >= kWalkCap) {
+                cap = 1;
+                fl |= 4;
+                break;
+            }
+            const int32_t *t = m.T + 3 * (int64_t)f;
+            d3 P[3] = {ld3(m.V + 3 * (int64_t)t[0]), ld3(m.V + 3 * (int64_t)t[1]), ld3(m.V + 3 * (int64_t)t[2])};
+            nf = ld3(m.fnrm + 3 * (int64_t)f);
+            double twoA = sqrt(dot(cross(P[1] - P[0], P[2] - P[0]), cross(P[1] - P[0], P[2] - P[0])));
+            double rate[3], s[3];
+            int k1 = -1, k2 = -1;
+            for (int k = 0; k < 3; ++k) {
+                // gradient of b_k: in-plane normal of the opposite edge, pointing to vertex k
+                d3 g = cross(nf, P[(k + 2) % 3] - P[(k + 1) % 3]);
+                rate[k] = dot(u, g) / twoA;
+                bool allowed = (onlyk < 0 || k == onlyk) && k != excl;
+                s[k] = (allowed && rate[k] < 0.0) ? fmax(-b[k] / rate[k], 0.0) : INFINITY;
+            }
+            for (int k = 0; k < 3; ++k)
+                if (k1 < 0 || s[k] < s[k1]) k1 = k;
+            for (int k = 0; k < 3; ++k)
+                if (k != k1 && (k2 < 0 || s[k] < s[k2])) k2 = k;
+            const double s1 = s[k1], s2 = s[k2];
+            if (!(rem > s1)) {
+                for (int k = 0; k < 3; ++k) b[k] += rem * rate[k];
+                break;
+            }
+            const double gap = s2 - s1;
+            if (gap <= kVertexTol * lbar) {
+                // through the vertex where b[k1] and b[k2] vanish together
+                const int ws = 3 - k1 - k2;
+                const int wv = t[ws];
+                rem -= s1;
+                ++vhit;
+                fl |= 1;
+                if (m.vflag[wv] & VF_BOUNDARY) {
+                    u = -1.0 * u;
+                    v = -1.0 * v;
+                    b[0] = b[1] = b[2] = 0.0;
+                    b[ws] = 1.0;
+                    onlyk = ws;
+                    excl = -1;
+                    continue;
+                }
+                // polar angle (around wv) of the direction back along the path
+                const int hin = 3 * f + ws;
+                const int a0 = m.fan_off[wv], a1 = m.fan_off[wv + 1];
+                double acc = 0.0;
+                for (int a = a0; a < a1 && m.fan[a] != hin; ++a) acc += m.corner[m.fan[a]];
+                const int hn = hin - hin % 3 + (hin % 3 + 1) % 3;
+                d3 e1 = unit(ld3(m.V + 3 * (int64_t)m.T[hn]) - ld3(m.V + 3 * (int64_t)wv));
+                d3 back = -1.0 * u;
+                double ang = atan2(dot(cross(e1, back), nf), dot(e1, back));
+                ang = fmin(fmax(ang, 0.0), m.corner[hin]);
+                const double Theta = m.theta[wv];
+                double phi = fmod(acc + ang + 0.5 * Theta, Theta);
+                // velocity as an angle from the direction of travel
+                double vmag = sqrt(dot(v, v)), psi = 0.0;
+                if (hv && vmag > 0.0) psi = atan2(dot(cross(u, v), nf), dot(u, v));
+                int hout = m.fan[a1 - 1];
+                double base = 0.0, run = 0.0;
+                for (int a = a0; a < a1; ++a) {
+                    double c = m.corner[m.fan[a]];
+                    if (phi < run + c) {
+                        hout = m.fan[a];
+                        base = run;
+                        break;
+                    }
+                    run += c;
+                    base = run - c;
+                }
+                double gam = fmin(fmax(phi - base, 0.0), m.corner[hout]);
+                const int g = hout / 3;
+                const int ho = hout - hout % 3 + (hout % 3 + 1) % 3;
+                d3 ng = ld3(m.fnrm + 3 * (int64_t)g);
+                d3 e0 = unit(ld3(m.V + 3 * (int64_t)m.T[ho]) - ld3(m.V + 3 * (int64_t)wv));
+                d3 e0p = cross(ng, e0);
+                double sg, cg;
+                sincos(gam, &sg, &cg);
+                u = cg * e0 + sg * e0p;
+                if (hv && vmag > 0.0) {
+                    double sp, cp;
+                    sincos(psi, &sp, &cp);
+                    v = vmag * (cp * u + sp * cross(ng, u));
+                }
+                f = g;
+                b[0] = b[1] = b[2] = 0.0;
+                b[hout % 3] = 1.0;
+                onlyk = hout % 3;
+                excl = -1;
+                continue;
+            }
+            if (gap <= kNearTol * lbar) {
+                ++near;
+                fl |= 2;
+            }
+            // cross the edge opposite slot k1
+            for (int k = 0; k < 3; ++k) b[k] += s1 * rate[k];
+            b[k1] = 0.0;
+            rem -= s1;
+            const int h = 3 * f + (k1 + 1) % 3;
+            d3 e = unit(P[(k1 + 2) % 3] - P[(k1 + 1) % 3]);
+            d3 mo = cross(e, nf);  // in-plane normal of the edge, pointing out of f
+            const int tw = m.he[h].twin;
+            if (tw < 0) {
+                ++bhit;
+                fl |= 8;
+                u = u - 2.0 * dot(u, mo) * mo;
+                v = v - 2.0 * dot(v, mo) * mo;
+                excl = k1;
+                onlyk = -1;
+                continue;
+            }
+            ++cross_n;
+            const int g = tw / 3, q = tw % 3;
+            double nb[3];
+            nb[q] = b[(k1 + 2) % 3];
+            nb[(q + 1) % 3] = b[(k1 + 1) % 3];
+            nb[(q + 2) % 3] = 0.0;
+            d3 mi = cross(e, ld3(m.fnrm + 3 * (int64_t)g));  // pointing into the new face
+            double ue = dot(u, e), um = dot(u, mo);
+            u = ue * e + um * mi;
+            if (hv) {
+                double ve = dot(v, e), vm = dot(v, mo);
+                v = ve * e + vm * mi;
+            }
+            f = g;
+            b[0] = nb[0];
+            b[1] = nb[1];
+            b[2] = nb[2];
+            excl = (q + 2) % 3;
+            onlyk = -1;
+        }
+    }
+    face[i] = f;
+    bary[3 * i] = b[0];
+    bary[3 * i + 1] = b[1];
+    bary[3 * i + 2] = b[2];
+    if (hv) {
+        vel[3 * i] = v.x;
+        vel[3 * i + 1] = v.y;
+        vel[3 * i + 2] = v.z;
+    }
+    if (flags) flags[i] = fl;
+    if (stats) {
+        if (cross_n) atomicAdd(&stats[0], (unsigned long long)cross_n);
+        if (vhit) atomicAdd(&stats[1], (unsigned long long)vhit);
+        if (bhit) atomicAdd(&stats[2], (unsigned long long)bhit);
+        if (cap) atomicAdd(&stats[3], (unsigned long long)cap);
+        if (near) atomicAdd(&stats[4], (unsigned long long)near);
+    }
+}
+
+}  // namespace
+
+hipError_t launch_walk(const DevMesh &m, int n, int32_t *face, double *bary, const double *disp, double *vel,
+                       unsigned long long *stats, uint8_t *flags, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_walk, dim3((n + 127) / 128), dim3(128), 0, s, m, n, face, bary, disp, vel, stats, flags);
+    return hipGetLastError();
+}
+
+}  // namespace gsim

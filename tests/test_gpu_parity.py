@@ -1,0 +1,242 @@
+"""GPU parity: the HIP path through the C-ABI against the CPU oracle, on the
+same seeded inputs. Neighbour sets and faces bit-exact; floating point within
+the stated tolerance (FP64 mode 1e-12 relative)."""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2404_19751_amd import workloads as W
+from tests.util import place
+
+pytestmark = pytest.mark.gpu
+
+RTOL64 = 1e-12
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2404_19751_amd import gsim
+    c = gsim.Context(0, "fp64")
+    yield c
+    c.close()
+
+
+def compare_pairs(g, o, lbar, rtol=RTOL64, tan_floor=1e-3, label=""):
+    """Bit-exact neighbour sets; distances and log-map vectors d*t within
+    rtol; tie-flagged pairs may take any tangent of the oracle's tie set."""
+    n = len(o.off) - 1
+    assert np.array_equal(g["off"], o.off), f"{label}: neighbour counts differ"
+    assert np.array_equal(g["nbr"], o.nbr), f"{label}: neighbour sets differ"
+    d_o, d_g = o.dist, g["dist"]
+    rel = np.abs(d_g - d_o) / np.maximum(d_o, 1e-300)
+    assert rel.max(initial=0.0) <= rtol, f"{label}: max rel dist err {rel.max()}"
+    scale = np.maximum(d_o, tan_floor * lbar)
+    bad = []
+    for p in range(len(d_o)):
+        if d_o[p] == 0.0:
+            continue
+        err = np.linalg.norm(d_o[p] * (g["tan"][p] - o.tan[p])) / scale[p]
+        if err <= rtol * 10:
+            continue
+        ties = o.ties(p)
+        best = min(np.linalg.norm(d_o[p] * (g["tan"][p] - t)) / scale[p] for t in ties) if len(ties) else err
+        tie = (o.flags[p] & 1) or (g["flags"][p] & 1)
+        if not (tie and best <= rtol * 10):
+            bad.append((p, err, best, int(o.flags[p]), int(g["flags"][p])))
+    assert not bad, f"{label}: tangent mismatches {bad[:5]} of {len(bad)}"
+    return rel.max(initial=0.0)
+
+
+def run_pairs(ctx, orc, m, face, bary, cutoff, label):
+    om = orc.OracleMesh(m.V, m.T)
+    mid = ctx.mesh_upload(m.V, m.T)
+    ctx.particles_set(mid, face, bary)
+    log(f"[gpu] {label}: geodesic_pairs nf={m.nf} n={len(face)} cutoff={cutoff}")
+    g = ctx.geodesic_pairs(mid, cutoff)
+    o = orc.geodesic_pairs(om, face, bary, cutoff)
+    err = compare_pairs(g, o, W.mean_edge_length(m), label=label)
+    log(f"[gpu] {label}: pairs={len(o.dist)} max_rel_err={err:.3e} counters={ctx.counters()}")
+    return g, o, om, mid
+
+
+def test_c1_pairs(ctx, orc):
+    w = W.workload("c1")
+    run_pairs(ctx, orc, w.mesh, w.face, w.bary, w.potential["cutoff"], "c1")
+
+
+def test_c2_pairs_fp64(ctx, orc):
+    w = W.workload("c2")
+    run_pairs(ctx, orc, w.mesh, w.face, w.bary, w.potential["cutoff"], "c2")
+
+
+@pytest.mark.parametrize("name,mk,n,cut", [
+    ("flat", lambda: W.flat_grid(10, 8, 1.0, 0.8), 60, 0.35),
+    ("corrugated", lambda: W.corrugated_sheet(24, 6), 50, 1.2),
+    ("cube", lambda: W.cube(3), 40, 1.6),
+    ("tetra", lambda: W.tetrahedron(1.0), 12, 0.9),
+    ("cone_saddle", lambda: W.cone_fan(2.5 * np.pi, 8), 30, 1.2),
+    ("lshape", lambda: W.l_shape(4), 40, 1.5),
+    ("torus", lambda: W.torus(1.0, 0.3, 30, 12), 80, 0.7),
+    ("bumpy_l3", lambda: W.bumpy_sphere(3, 0.15), 80, 0.6),
+])
+def test_small_meshes(ctx, orc, name, mk, n, cut):
+    m = mk()
+    f, b = W.random_particles(m.nf, n, 17)
+    run_pairs(ctx, orc, m, f, b, cut, name)
+
+
+def test_sources_on_edges(ctx, orc):
+    """Particles exactly on edges (one barycentric coordinate zero)."""
+    m = W.tetrahedron(1.0)
+    V = m.V
+    pts = [(V[0] + V[1]) / 2, (V[2] + V[3]) / 2, V[[0, 1, 2]].mean(0), V[[1, 2, 3]].mean(0), 0.3 * V[0] + 0.7 * V[2]]
+    f, b = place(m, pts)
+    g, o, _, _ = run_pairs(ctx, orc, m, f, b, 1.5, "tetra-edges")
+    p = np.nonzero((o.nbr == 1) & (np.arange(len(o.nbr)) < o.off[1]))[0][0]
+    assert abs(g["dist"][p] - 1.0) < 1e-12 and g["flags"][p] & 1
+
+
+def test_isolated_and_single_particle(ctx, orc):
+    m = W.icosphere(3)
+    mid = ctx.mesh_upload(m.V, m.T)
+    f, b = W.random_particles(m.nf, 5, 3)
+    ctx.particles_set(mid, f[:1], b[:1])
+    g = ctx.geodesic_pairs(mid, 0.3)
+    assert len(g["nbr"]) == 0 and np.array_equal(g["off"], [0, 0])
+    ctx.particles_set(mid, f, b)
+    g = ctx.geodesic_pairs(mid, 1e-3)
+    assert len(g["nbr"]) == 0
+
+
+def test_forces_parity(ctx, orc):
+    from paper_2404_19751_amd import gsim
+    w = W.workload("c2")
+    om = orc.OracleMesh(w.mesh.V, w.mesh.T)
+    mid = ctx.mesh_upload(w.mesh.V, w.mesh.T)
+    ctx.particles_set(mid, w.face, w.bary)
+    for kind in ("harmonic", "gaussian", "coulomb"):
+        log(f"[gpu] forces {kind}")
+        F, E = ctx.compute_forces(mid, gsim.potential(kind, 1.0, 0.15, 0.15))
+        o = orc.geodesic_pairs(om, w.face, w.bary, 0.15)
+        Fo, Eo = orc.forces(len(w.face), o, kind, 1.0, 0.15)
+        scale = np.zeros(len(w.face))
+        for i in range(len(w.face)):
+            for p in range(o.off[i], o.off[i + 1]):
+                scale[i] += abs(orc.potential(kind, o.dist[p], 1.0, 0.15)[1])
+        err = np.linalg.norm(F - Fo, axis=1)
+        assert np.all(err <= 1e-11 * np.maximum(scale, 1e-300) + 1e-300), (kind, err.max())
+        assert abs(E - Eo) <= 1e-11 * abs(Eo) + 1e-300
+
+
+def test_walk_parity(ctx, orc):
+    w = W.workload("c2")
+    om = orc.OracleMesh(w.mesh.V, w.mesh.T)
+    mid = ctx.mesh_upload(w.mesh.V, w.mesh.T)
+    rng = np.random.default_rng(8)
+    D = rng.normal(size=(len(w.face), 3)) * 0.1
+    vel = rng.normal(size=(len(w.face), 3))
+    ctx.particles_set(mid, w.face, w.bary, vel)
+    log("[gpu] walk c2")
+    st = ctx.displace_on_surface(mid, D, True)
+    fg, bg, vg, _ = ctx.particles_get(mid)
+    fo, bo, vo, sto, flo = orc.walk(om, w.face, w.bary, D, vel)
+    ok = flo == 0
+    assert ok.mean() > 0.99
+    assert np.array_equal(fg[ok], fo[ok])
+    assert np.abs(bg[ok] - bo[ok]).max() < 1e-12
+    assert np.abs(vg[ok] - vo[ok]).max() < 1e-12
+    assert st["crossings"] == sto["crossings"] and st["crossings"] > 1000
+
+
+def test_walk_boundary_and_vertex(ctx, orc):
+    m = W.l_shape(4)
+    om = orc.OracleMesh(m.V, m.T)
+    mid = ctx.mesh_upload(m.V, m.T)
+    f, b = W.random_particles(m.nf, 200, 4)
+    D = np.random.default_rng(2).normal(size=(200, 3)) * 0.8
+    ctx.particles_set(mid, f, b)
+    st = ctx.displace_on_surface(mid, D, False)
+    fg, bg, _, _ = ctx.particles_get(mid)
+    fo, bo, _, sto, flo = orc.walk(om, f, b, D)
+    ok = flo & 3 == 0
+    assert sto["boundary_hits"] > 10 and st["boundary_hits"] == sto["boundary_hits"]
+    assert np.array_equal(fg[ok], fo[ok]) and np.abs(bg[ok] - bo[ok]).max() < 1e-11
+    # straight through a cone apex: the straightest rule
+    theta, nn = 1.5 * np.pi, 6
+    cm = W.cone_fan(theta, nn)
+    ocm = orc.OracleMesh(cm.V, cm.T)
+    apex, r1, r2 = cm.V[0], cm.V[1], cm.V[2]
+    start = apex + 0.4 * (r1 - apex) + 0.1 * (r2 - apex)
+    fs, bs = place(cm, [start])
+    Dv = (apex - start) / np.linalg.norm(apex - start) * (np.linalg.norm(apex - start) + 0.25)
+    cmid = ctx.mesh_upload(cm.V, cm.T)
+    ctx.particles_set(cmid, fs, bs)
+    st = ctx.displace_on_surface(cmid, Dv[None, :], False)
+    fg, bg, _, _ = ctx.particles_get(cmid)
+    fo, bo, _, sto, _ = orc.walk(ocm, fs, bs, Dv[None, :])
+    assert st["vertex_hits"] == 1 and sto["vertex_hits"] == 1
+    assert fg[0] == fo[0] and np.abs(bg - bo).max() < 1e-12
+
+
+def test_c1_trajectory(ctx, orc):
+    """Ten full overdamped steps on the GPU against ten oracle steps."""
+    from paper_2404_19751_amd import gsim
+    w = W.workload("c1")
+    om = orc.OracleMesh(w.mesh.V, w.mesh.T)
+    mid = ctx.mesh_upload(w.mesh.V, w.mesh.T)
+    ctx.particles_set(mid, w.face, w.bary)
+    pot = gsim.potential("harmonic", 1.0, 0.5, 0.5)
+    ig = gsim.integrator("overdamped", 0.01, 1.0)
+    f, b = w.face.copy(), w.bary.copy()
+    for s in range(w.steps):
+        ctx.step(mid, pot, ig, 1)
+        f, b, _ = orc.step(om, f, b, w.potential, w.integrator, s)
+        fg, bg, _, _ = ctx.particles_get(mid)
+        assert np.array_equal(fg, f), f"step {s}"
+        assert np.abs(bg - b).max() < 1e-11, f"step {s}: {np.abs(bg - b).max()}"
+    log("[gpu] c1 trajectory ok")
+
+
+def test_brownian_step(ctx, orc):
+    from paper_2404_19751_amd import gsim
+    m = W.height_field(40, 2.0, 6, 2)
+    om = orc.OracleMesh(m.V, m.T)
+    lbar = W.mean_edge_length(m)
+    f, b = W.random_particles(m.nf, 300, 3)
+    mid = ctx.mesh_upload(m.V, m.T)
+    ctx.particles_set(mid, f, b)
+    sig = 3 * lbar
+    ctx.step(mid, gsim.potential("harmonic", 1.0, sig, sig), gsim.integrator("brownian", 0.005, 1.0, 0.1, 1.0, 3), 1)
+    fo, bo, info = orc.step(om, f, b, dict(kind="harmonic", k=1.0, sigma=sig, cutoff=sig),
+                            dict(kind="brownian", dt=0.005, kT=0.1, friction=1.0, seed=3), 0)
+    fg, bg, _, _ = ctx.particles_get(mid)
+    ok = info["walk_flags"] & 3 == 0
+    assert np.array_equal(fg[ok], fo[ok]) and np.abs(bg[ok] - bo[ok]).max() < 1e-10
+    assert info["walk"]["crossings"] > 50
+
+
+def test_mesh_rejected(ctx):
+    from paper_2404_19751_amd import gsim
+    m = W.icosphere(1)
+    T = m.T.copy()
+    T[0] = T[0][[0, 2, 1]]
+    with pytest.raises(gsim.GsimError) as e:
+        ctx.mesh_upload(m.V, T)
+    assert e.value.status == gsim.E_MESH
+
+
+def test_bad_particles_rejected(ctx):
+    from paper_2404_19751_amd import gsim
+    m = W.icosphere(2)
+    mid = ctx.mesh_upload(m.V, m.T)
+    with pytest.raises(gsim.GsimError):
+        ctx.particles_set(mid, np.array([m.nf + 3], np.int32), np.array([[0.2, 0.3, 0.5]]))
+    with pytest.raises(gsim.GsimError):
+        ctx.particles_set(mid, np.array([0], np.int32), np.array([[1.0, 0.0, 0.0]]))  # on a vertex
