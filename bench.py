@@ -60,7 +60,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32"])
+    ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -72,25 +73,30 @@ def main():
     from paper_2404_19751_amd import gsim, workloads as W
 
     w = W.workload("c2")
-    ctx = gsim.Context(0, args.precision)
-    mid = ctx.mesh_upload(w.mesh.V, w.mesh.T)
-    ctx.particles_set(mid, w.face, w.bary)
     pot = gsim.potential("harmonic", w.potential["k"], w.potential["sigma"], w.potential["cutoff"])
     ig = gsim.integrator("overdamped", w.integrator["dt"], w.integrator["mobility"])
 
-    for _ in range(args.warmup):
-        ctx.step(mid, pot, ig, 1)
-    ctx.synchronize()
-    ctx.timing(True)
-    ctx.synchronize()
-    t0 = time.perf_counter()
-    ctx.step(mid, pot, ig, args.steps)
-    ctx.synchronize()
-    dt = time.perf_counter() - t0
-    cnt = ctx.counters()
-    stages = {k: ctx.timing_get(k)[0] for k in ("prefilter", "geodesic", "compact", "forces", "integrate", "walk")}
-    ctx.timing(False)
+    def run(precision):
+        ctx = gsim.Context(0, precision)
+        mid = ctx.mesh_upload(w.mesh.V, w.mesh.T)
+        ctx.particles_set(mid, w.face, w.bary)
+        for _ in range(args.warmup):
+            ctx.step(mid, pot, ig, 1)
+        ctx.synchronize()
+        ctx.timing(True)
+        ctx.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(mid, pot, ig, args.steps)
+        ctx.synchronize()
+        dt = time.perf_counter() - t0
+        cnt = ctx.counters()
+        stages = {k: ctx.timing_get(k)[0] for k in
+                  ("prefilter", "geodesic", "geodesic_guard", "compact", "forces", "integrate", "walk")}
+        ctx.timing(False)
+        ctx.close()
+        return dt, cnt, stages
 
+    dt, cnt, stages = run(args.precision)
     pairs = cnt["cum_pairs"]
     n = len(w.face)
     geo_ms = stages["geodesic"]
@@ -123,10 +129,14 @@ def main():
                      "kernel": "k_geodesic", "per_unit": f"{FLOPS_PER_WINDOW:.0f} flop/window",
                      "units_per_launch": win_per_launch, "avg_launch_ms": geo_ms},
     }
+    if not args.no_compare:
+        other = "fp64" if args.precision == "fp32" else "fp32"
+        dt2, cnt2, st2 = run(other)
+        line[other] = {"pairs_per_s": cnt2["cum_pairs"] / dt2, "particle_steps_per_s": n * args.steps / dt2,
+                       "ms_per_step": 1e3 * dt2 / args.steps, "stage_ms": st2}
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w)
     print(json.dumps(line), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

@@ -162,6 +162,19 @@ gsim_status gsim_displace_on_surface(gsim_ctx *ctx, int32_t mesh_id, const doubl
 gsim_status gsim_step(gsim_ctx *ctx, int32_t mesh_id, const gsim_potential *pot, const gsim_integrator *integ,
                       int32_t nsteps);
 
+/* ---- tuning ----------------------------------------------------------------
+ * Knobs of the geodesic kernel (set by the autotuner or by hand; results stay
+ * exact, only the amount of work or the launch shape changes):
+ *   "launch_delta"  bend-vertex launch bucket width (0 = half the mean edge)
+ *   "stack_cap"     window-stack capacity per resident wavefront (64 .. 4M)
+ *   "max_slots"     resident wavefronts of the persistent grid (1 .. 65536)
+ *   "max_windows"   per-source work limit (GSIM_E_LIMIT beyond it)
+ *   "cone_tol"      closed-cone slack relative to the edge length
+ *   "tie_rel"       relative gap under which a pair is flagged as a tie
+ *   "tie_dir"       tangents closer than this angle (rad) count as one direction
+ *   "guard_rel"     FP32-mixed: relative band around the cutoff recomputed in FP64 */
+gsim_status gsim_tune_set(gsim_ctx *ctx, const char *name, double value);
+
 /* ---- instrumentation ------------------------------------------------------
  * Per-kernel timing with HIP events recorded on the context's stream, only
  * while enabled. name: "prefilter", "geodesic", "compact", "forces",

@@ -39,7 +39,7 @@ struct MeshState {
     double pairs_cutoff = -1.0;
     bool pairs_valid = false;
     // forces / integrator
-    Buf F, Ei, E, disp, wflags;
+    Buf F, Ei, E, disp, wflags, guard;
     uint64_t step = 0;  // steps taken since the state was set: the noise counter
 };
 
@@ -226,13 +226,28 @@ gsim_status run_pairs(gsim_ctx *c, MeshState *ms, double cutoff) {
         gp.cutoff = cutoff;
         if (!(gp.launch_delta > 0.0)) gp.launch_delta = 0.5 * m.mean_edge;
         int32_t nslots = std::min<int32_t>(n, c->max_slots);
-        HIPCHK(c, ensure(c->stack, (size_t)nslots * gp.stack_cap * window_record_bytes()));
-        HIPCHK(c, launch_zero_i32(P<int32_t>(c->work), 8, s));
+        const bool fp32 = c->prec == GSIM_FP32_MIXED;
+        if (fp32 && 3 * (int64_t)m.nf >= (int64_t(1) << 24))
+            return fail(c, GSIM_E_LIMIT, "FP32-mixed mode packs half-edge ids in 24 bits: mesh too large");
+        HIPCHK(c, ensure(c->stack, (size_t)nslots * gp.stack_cap * window_record_bytes(false)));
+        HIPCHK(c, ensure(ms->guard, (size_t)n + 4));
+        HIPCHK(c, launch_zero_i32(P<int32_t>(c->work), 16, s));
         HIPCHK(c, launch_zero_u64(P<unsigned long long>(c->ctr), 8, s));
+        if (fp32) HIPCHK(c, launch_zero_i32(P<int32_t>(ms->guard), (n + 3) / 4, s));
         GeoOut out{P<double>(ms->cdist), P<double>(ms->ctan), P<uint8_t>(ms->cflags)};
-        Stage st(c, "geodesic");
-        HIPCHK(c, launch_geodesic(m, n, ms->face, ms->bary, ms->xyz, pb, gp, out, P<char>(c->stack), nslots,
-                                  P<int32_t>(c->work), P<Counters>(c->ctr), c->prec == GSIM_FP32_MIXED, s));
+        {
+            Stage st(c, "geodesic");
+            HIPCHK(c, launch_geodesic(m, n, ms->face, ms->bary, ms->xyz, pb, gp, out, P<char>(c->stack), nslots,
+                                      P<int32_t>(c->work), P<Counters>(c->ctr), fp32, P<uint8_t>(ms->guard), false,
+                                      s));
+        }
+        if (fp32) {
+            // FP64 recompute of every source with a pair inside the guard band
+            Stage st(c, "geodesic_guard");
+            HIPCHK(c, launch_geodesic(m, n, ms->face, ms->bary, ms->xyz, pb, gp, out, P<char>(c->stack), nslots,
+                                      P<int32_t>(c->work) + 8, P<Counters>(c->ctr), false, P<uint8_t>(ms->guard),
+                                      true, s));
+        }
     }
     {
         Stage st(c, "compact");
@@ -321,11 +336,13 @@ gsim_status gsim_create(int device, gsim_precision prec, void *hip_stream, gsim_
     }
     c->gp.cutoff = 0.0;
     c->gp.launch_delta = 0.0;  // 0 = half the mean edge length
-    c->gp.cone_tol = prec == GSIM_FP64 ? 1e-12 : 1e-6;
+    c->gp.cone_tol = prec == GSIM_FP64 ? 1e-12 : 1e-5;
     c->gp.tie_rel = prec == GSIM_FP64 ? 1e-9 : 1e-4;
+    c->gp.guard_rel = 1e-4;
+    c->gp.tie_dir = prec == GSIM_FP64 ? 1e-6 : 5e-6;
     c->gp.stack_cap = 4096;
     c->gp.max_windows = 4000000;
-    if (ensure(c->work, sizeof(int32_t) * 8) != hipSuccess || ensure(c->ctr, sizeof(Counters)) != hipSuccess ||
+    if (ensure(c->work, sizeof(int32_t) * 16) != hipSuccess || ensure(c->ctr, sizeof(Counters)) != hipSuccess ||
         ensure(c->wstats, sizeof(unsigned long long) * 8) != hipSuccess) {
         gsim_destroy(c);
         return GSIM_E_OOM;
@@ -344,13 +361,14 @@ void gsim_destroy(gsim_ctx *c) {
         if (!ms) continue;
         for (Buf *b : {&ms->cell_of, &ms->cell_start, &ms->cell_fill, &ms->order, &ms->cand_cnt, &ms->cand_off,
                        &ms->cand, &ms->tmp64, &ms->cdist, &ms->ctan, &ms->cflags, &ms->nbr_cnt, &ms->off, &ms->nbr,
-                       &ms->dist, &ms->tan, &ms->flags, &ms->F, &ms->Ei, &ms->E, &ms->disp, &ms->wflags})
+                       &ms->dist, &ms->tan, &ms->flags, &ms->F, &ms->Ei, &ms->E, &ms->disp, &ms->wflags,
+                       &ms->guard})
             release(*b);
         for (void *p : {(void *)ms->face, (void *)ms->bary, (void *)ms->vel, (void *)ms->xyz})
             if (p) (void)hipFree(p);
         for (void *p : {(void *)ms->dm.V, (void *)ms->dm.T, (void *)ms->dm.he, (void *)ms->dm.hef,
                         (void *)ms->dm.vflag, (void *)ms->dm.theta, (void *)ms->dm.fan_off, (void *)ms->dm.fan,
-                        (void *)ms->dm.corner, (void *)ms->dm.fnrm})
+                        (void *)ms->dm.corner, (void *)ms->dm.fnrm, (void *)ms->dm.fpos})
             if (p) (void)hipFree(p);
         delete ms;
     }
@@ -393,6 +411,7 @@ gsim_status gsim_mesh_upload(gsim_ctx *c, int32_t nv, const double *xyz, int32_t
         HIPCHK(c, upload(d.fan, H.fan.data(), H.fan.size(), s));
         HIPCHK(c, upload(d.corner, H.corner.data(), H.corner.size(), s));
         HIPCHK(c, upload(d.fnrm, H.fnrm.data(), H.fnrm.size(), s));
+        HIPCHK(c, upload(d.fpos, H.fpos.data(), H.fpos.size(), s));
         for (int k = 0; k < 3; ++k) {
             d.bbmin[k] = H.bbmin[k];
             d.bbmax[k] = H.bbmax[k];
@@ -654,6 +673,21 @@ gsim_status gsim_timing_get(gsim_ctx *c, const char *name, double *avg_ms, int64
     }
     if (avg_ms) *avg_ms = it->second.n ? it->second.total_ms / double(it->second.n) : 0.0;
     if (launches) *launches = it->second.n;
+    return GSIM_OK;
+}
+
+gsim_status gsim_tune_set(gsim_ctx *c, const char *name, double value) {
+    if (!c || !name) return GSIM_E_ARG;
+    std::string k(name);
+    if (k == "launch_delta") c->gp.launch_delta = value;
+    else if (k == "cone_tol" && value >= 0.0) c->gp.cone_tol = value;
+    else if (k == "tie_rel" && value >= 0.0) c->gp.tie_rel = value;
+    else if (k == "tie_dir" && value >= 0.0) c->gp.tie_dir = value;
+    else if (k == "guard_rel" && value >= 0.0) c->gp.guard_rel = value;
+    else if (k == "stack_cap" && value >= 64 && value <= (1 << 22)) c->gp.stack_cap = (int32_t)value;
+    else if (k == "max_windows" && value >= 1) c->gp.max_windows = (int32_t)std::min(value, 2.0e9);
+    else if (k == "max_slots" && value >= 1 && value <= 65536) c->max_slots = (int)value;
+    else return fail(c, GSIM_E_ARG, "unknown tuning knob or value out of range: " + k);
     return GSIM_OK;
 }
 

@@ -51,6 +51,7 @@ struct DevMesh {
     int32_t *fan = nullptr;     // [3nf] outgoing half-edges, CCW, boundary fans start clockwise-most
     double *corner = nullptr;   // [3nf] corner angle of face h/3 at the tail of h
     double *fnrm = nullptr;     // [nf][3] unit outward normal
+    double *fpos = nullptr;     // [nf][3][3] the face's vertex positions in slot order
     double bbmin[3], bbmax[3];
     double mean_edge = 0, min_edge = 0, max_edge = 0;
     int32_t n_boundary_edges = 0, n_pseudo = 0;
@@ -65,7 +66,7 @@ struct HostMesh {
     std::vector<HeRec> he;
     std::vector<HeRecF> hef;
     std::vector<uint8_t> vflag;
-    std::vector<double> theta, corner, fnrm;
+    std::vector<double> theta, corner, fnrm, fpos;
     std::vector<int32_t> fan_off, fan;
     double bbmin[3], bbmax[3];
     double mean_edge = 0, min_edge = 0, max_edge = 0;
@@ -94,6 +95,8 @@ struct GeoParams {
     double launch_delta;  // bend-vertex launch bucket width
     double cone_tol;      // relative closed-cone slack
     double tie_rel;       // tie gap (relative)
+    double tie_dir;       // two candidate tangents closer than this (rad) are the same direction
+    double guard_rel;     // FP32 results this close (relative) to the cutoff are recomputed in FP64
     int32_t stack_cap;    // windows per stack slot
     int32_t max_windows;  // per-source work limit
 };
@@ -121,11 +124,12 @@ hipError_t launch_scan_i32_inplace(int32_t *inout, int n, int32_t *scratch, hipS
 
 hipError_t launch_geodesic(const DevMesh &m, int n, const int32_t *face, const double *bary, const double *xyz,
                            const PrefilterBufs &pb, const GeoParams &gp, GeoOut out, char *stack_mem,
-                           int32_t nslots, int32_t *work_ctr, Counters *ctr, bool fp32, hipStream_t s);
+                           int32_t nslots, int32_t *work_ctr, Counters *ctr, bool fp32, uint8_t *guard,
+                           bool guard_pass, hipStream_t s);
 
 hipError_t launch_bin_scatter(int n, PrefilterBufs &b, hipStream_t s);
 hipError_t launch_i64_to_i32(const int64_t *in, int32_t *out, int n, hipStream_t s);
-size_t window_record_bytes();
+size_t window_record_bytes(bool fp32);
 
 hipError_t launch_count_nbrs(int n, const int64_t *cand_off, const double *dist, double cutoff, int32_t *cnt,
                              hipStream_t s);

@@ -8,26 +8,38 @@
 // frame: rays from p through the interval enter face(h). Processing a window
 // unfolds face(h)'s third vertex C, queries the targets in face(h), offers C
 // as a bend vertex, and emits at most two child windows on the far edges.
-// Windows whose lower bound sg + dist(p, interval) reaches the cutoff are
-// dropped: this is the paper's submeshing by the Euclidean lower bound, done
-// implicitly (no patch copy).
+//
+// Pruning (both exact for every pair closer than the cutoff):
+//  - the paper's submeshing by the Euclidean lower bound (Sec. 3.1), done
+//    implicitly: a window is dropped once sg + dist(p, interval) reaches the
+//    cutoff;
+//  - target-directed: any path through a window to target j has length at
+//    least sg + dist(p, interval) + |X - x_j| for the 3D crossing point X on
+//    the window's edge slice, so a window is dropped when that bound reaches
+//    the cutoff for every candidate target. A bend vertex found only through
+//    dropped windows can only lead to pairs at or beyond the cutoff.
 //
 // Bend vertices (pseudo-sources) are re-rooted in distance buckets: whenever
 // no window is left, every bend vertex whose distance improved since its last
 // launch and lies within `launch_delta` of the smallest such distance is
 // launched (a full fan of windows, sg = its distance). Windows of a root
-// whose distance has improved since they were made are stale and dropped.
-// The result is exact for every pair closer than the cutoff: the optimal
-// chain's windows all have lower bound below the pair distance, and the last
-// launch of every bend vertex carries its final distance.
+// whose distance improved after they were made are stale and dropped. The
+// last launch of every bend vertex carries its final distance, and the
+// optimal chain's windows all have lower bounds below the pair distance, so
+// processing order changes only the amount of work.
 //
-// Mapping to CDNA4: one wavefront per source (persistent grid, sources taken
-// in spatial cell order from eight per-XCD work chunks so each XCD's L2 holds
+// Precision: FP64 throughout, or FP32 windows (half the register, stack and
+// record bytes) with the child-interval endpoint intersections computed in
+// FP64; a source with any pair within the guard band of the cutoff is then
+// recomputed by the FP64 kernel so neighbour sets stay exact.
+//
+// Mapping to CDNA4: one wavefront per source (persistent grid, sources in
+// spatial cell order from eight per-XCD work chunks so each XCD's L2 serves
 // one region of the mesh); each lane holds one live window in registers; a
 // lane with two children keeps one and pushes the other onto the source's
 // window stack with a ballot/popcount compaction; idle lanes pop. Target and
 // bend-vertex tables live in LDS; their updates are serialised across lanes
-// by a ballot loop (no atomics, deterministic per wave order).
+// by a ballot loop (no atomics, deterministic in wave order).
 #include <cmath>
 
 #include "gsim_internal.h"
@@ -38,14 +50,74 @@ namespace {
 constexpr int kWave = 64;
 constexpr int kMaxCand = 128;
 constexpr int kHash = 256;
-constexpr int kRootCap = 256;
+// bend-vertex table: 255 slots so that slot + 1 fits the 8 bits the FP32
+// stack record keeps for it
+constexpr int kRootCap = 255;
+constexpr int kRootMax = 255;
 constexpr int kChunks = 8;
 
-struct WinRec {
-    double px, py, b0, b1, sg, c, s;
+template <typename R>
+struct Win {
+    R px, py, b0, b1, sg, c, s;
+    int he, root;
+};
+
+// stack records: 64 bytes (FP64) / 32 bytes (FP32, he and root packed)
+struct Rec64 {
+    double v[7];
     int32_t he, root;
 };
-static_assert(sizeof(WinRec) == 64, "window record is 64 bytes");
+struct Rec32 {
+    float v[7];
+    uint32_t hr;  // (he << 8) | (root + 1)
+};
+static_assert(sizeof(Rec64) == 64 && sizeof(Rec32) == 32, "stack record sizes");
+template <typename R>
+struct RecOf;
+template <>
+struct RecOf<double> {
+    using T = Rec64;
+};
+template <>
+struct RecOf<float> {
+    using T = Rec32;
+};
+
+__device__ inline void store_rec(Rec64 &q, const Win<double> &w) {
+    q.v[0] = w.px; q.v[1] = w.py; q.v[2] = w.b0; q.v[3] = w.b1; q.v[4] = w.sg; q.v[5] = w.c; q.v[6] = w.s;
+    q.he = w.he;
+    q.root = w.root;
+}
+__device__ inline void load_rec(const Rec64 &q, Win<double> &w) {
+    w.px = q.v[0]; w.py = q.v[1]; w.b0 = q.v[2]; w.b1 = q.v[3]; w.sg = q.v[4]; w.c = q.v[5]; w.s = q.v[6];
+    w.he = q.he;
+    w.root = q.root;
+}
+__device__ inline void store_rec(Rec32 &q, const Win<float> &w) {
+    q.v[0] = w.px; q.v[1] = w.py; q.v[2] = w.b0; q.v[3] = w.b1; q.v[4] = w.sg; q.v[5] = w.c; q.v[6] = w.s;
+    q.hr = ((uint32_t)w.he << 8) | (uint32_t)(w.root + 1);  // root + 1 in [0, kRootCap] < 256
+}
+__device__ inline void load_rec(const Rec32 &q, Win<float> &w) {
+    w.px = q.v[0]; w.py = q.v[1]; w.b0 = q.v[2]; w.b1 = q.v[3]; w.sg = q.v[4]; w.c = q.v[5]; w.s = q.v[6];
+    w.he = (int)(q.hr >> 8);
+    w.root = (int)(q.hr & 255u) - 1;
+}
+
+// half-edge record in the working precision
+template <typename R>
+struct He {
+    R L, cx, cy, Lp, Ln;
+    int tn, tp, opp;
+    bool pseudo;
+};
+__device__ inline He<double> load_he(const DevMesh &m, int h, double) {
+    const HeRec r = m.he[h];
+    return {r.L, r.cx, r.cy, r.Lp, r.Ln, r.tn, r.tp, r.opp, (r.flags & 1) != 0};
+}
+__device__ inline He<float> load_he(const DevMesh &m, int h, float) {
+    const HeRecF r = m.hef[h];
+    return {r.L, r.cx, r.cy, r.Lp, r.Ln, r.tn, r.tp, r.opp_flags >> 1, (r.opp_flags & 1) != 0};
+}
 
 struct GeoArgs {
     DevMesh m;
@@ -58,9 +130,11 @@ struct GeoArgs {
     const int32_t *order;
     GeoParams gp;
     GeoOut out;
-    WinRec *stack;
+    void *stack;
     int32_t *work;
     Counters *ctr;
+    uint8_t *guard;   // per source: FP32 pass marks, FP64 pass consumes
+    int guard_pass;   // 1: FP64 recompute of marked sources only
 };
 
 struct Lds {
@@ -71,24 +145,25 @@ struct Lds {
     int32_t head[kHash];
     int32_t rkey[kRootCap];
     double rD[kRootCap], rL[kRootCap], rtx[kRootCap], rty[kRootCap];
+    int32_t rcount;
 };
 
 __device__ inline int lane_id() { return threadIdx.x; }
 __device__ inline uint64_t lanemask_lt() { return (1ull << threadIdx.x) - 1ull; }
 __device__ inline int hash_face(int f) { return (int)(((uint32_t)f * 2654435761u) >> 24) & (kHash - 1); }
-__device__ inline int hash_vert(int v) { return (int)(((uint32_t)v * 2246822519u) >> 20) & (kRootCap - 1); }
+__device__ inline int hash_vert(int v) { return (int)((((uint32_t)v * 2246822519u) >> 16) % kRootCap); }
 
 __device__ inline double wave_min(double v) {
     for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
     return v;
 }
 
-__device__ inline double seg_dist(double px, double py, double b0, double b1) {
-    double dx = px < b0 ? b0 - px : (px > b1 ? px - b1 : 0.0);
+template <typename R>
+__device__ inline R seg_dist(R px, R py, R b0, R b1) {
+    R dx = px < b0 ? b0 - px : (px > b1 ? px - b1 : R(0));
     return sqrt(dx * dx + py * py);
 }
 
-// first target slot in face f (or -1)
 __device__ inline int first_in_face(const Lds &L, int f) {
     int s = L.head[hash_face(f)];
     while (s >= 0 && L.tface[s] != f) s = L.tnext[s];
@@ -100,16 +175,34 @@ __device__ inline int next_in_face(const Lds &L, int s, int f) {
     return s;
 }
 
+// Does any candidate target lie within `rem` (3D) of the edge slice
+// P + x u, x in [x0, x1]? (rem <= 0: no.)
+__device__ inline bool reaches_target(const Lds &L, int nc, const double P[3], const double u[3], double x0,
+                                      double x1, double rem) {
+    if (!(rem > 0.0)) return false;
+    const double r2 = rem * rem;
+    for (int s = 0; s < nc; ++s) {
+        double q0 = L.tx3[s][0] - P[0], q1 = L.tx3[s][1] - P[1], q2 = L.tx3[s][2] - P[2];
+        double t = q0 * u[0] + q1 * u[1] + q2 * u[2];
+        t = fmin(fmax(t, x0), x1);
+        q0 -= t * u[0];
+        q1 -= t * u[1];
+        q2 -= t * u[2];
+        if (q0 * q0 + q1 * q1 + q2 * q2 < r2) return true;
+    }
+    return false;
+}
+
 // Serialised target update: best distance, its tangent, and the best
 // distance among candidates whose direction differs (tie gap).
-__device__ inline void target_update(Lds &L, bool ok, int slot, double d, double tx, double ty) {
+__device__ inline void target_update(Lds &L, bool ok, int slot, double d, double tx, double ty, double dir_tol) {
     uint64_t m = __ballot(ok);
     while (m) {
         int l = __ffsll((unsigned long long)m) - 1;
         if (lane_id() == l) {
             double c1 = L.d1[slot];
             double ax = L.t1x[slot], ay = L.t1y[slot];
-            bool differ = !(c1 < INFINITY) || fabs(ax * ty - ay * tx) > 1e-6 || ax * tx + ay * ty < 0.0;
+            bool differ = !(c1 < INFINITY) || fabs(ax * ty - ay * tx) > dir_tol || ax * tx + ay * ty < 0.0;
             if (d < c1) {
                 if (differ) L.d2[slot] = fmin(L.d2[slot], c1);
                 L.d1[slot] = d;
@@ -131,10 +224,10 @@ __device__ inline void root_update(Lds &L, bool ok, int v, double d, double tx, 
         if (lane_id() == l) {
             int e = hash_vert(v), probes = 0;
             while (L.rkey[e] >= 0 && L.rkey[e] != v && probes < kRootCap) {
-                e = (e + 1) & (kRootCap - 1);
+                e = e + 1 == kRootCap ? 0 : e + 1;
                 ++probes;
             }
-            if (probes >= kRootCap) {
+            if (probes >= kRootCap || (L.rkey[e] < 0 && L.rcount >= kRootMax - 1)) {
                 overflow = true;
             } else if (L.rkey[e] < 0) {
                 L.rkey[e] = v;
@@ -142,6 +235,7 @@ __device__ inline void root_update(Lds &L, bool ok, int v, double d, double tx, 
                 L.rL[e] = INFINITY;
                 L.rtx[e] = tx;
                 L.rty[e] = ty;
+                L.rcount++;
             } else if (d < L.rD[e]) {
                 L.rD[e] = d;
                 L.rtx[e] = tx;
@@ -152,109 +246,133 @@ __device__ inline void root_update(Lds &L, bool ok, int v, double d, double tx, 
     }
 }
 
-struct Win {
-    double px, py, b0, b1, sg, c, s;
-    int he, root;
-};
-
-__device__ inline void push_windows(WinRec *stk, int &sp, int cap, bool want, const Win &w, bool &overflow) {
+template <typename Rec, typename R>
+__device__ inline void push_windows(Rec *stk, int &sp, int cap, bool want, const Win<R> &w, bool &overflow) {
     uint64_t m = __ballot(want);
     int cnt = __popcll(m);
     if (!cnt) return;
     int r = __popcll(m & lanemask_lt());
     if (want) {
         int pos = sp + r;
-        if (pos < cap) {
-            WinRec q;
-            q.px = w.px; q.py = w.py; q.b0 = w.b0; q.b1 = w.b1; q.sg = w.sg; q.c = w.c; q.s = w.s;
-            q.he = w.he; q.root = w.root;
-            stk[pos] = q;
-        } else {
-            overflow = true;
-        }
+        if (pos < cap) store_rec(stk[pos], w);
+        else overflow = true;
     }
     sp = min(sp + cnt, cap);
 }
 
-// Child windows of a window (p, [b0,b1]) on half-edge record R, C's
-// intercept txc on the entry edge. Left child: across C->A (stored on R.tp,
-// frame origin A, x towards C). Right child: across B->C (stored on R.tn,
-// frame origin C, x towards B). `full` = the root lies on the entry edge
-// itself (both far edges fully visible).
-__device__ inline void children(const HeRec &R, const Win &w, double txc, bool full, double cutoff, Win &cl,
-                                bool &hl, Win &cr, bool &hr, int &pruned) {
-    const double px = w.px, py = w.py, b0 = w.b0, b1 = w.b1;
+// Child intervals. Left child: across C->A (stored on tp, frame origin A,
+// x towards C). Right child: across B->C (stored on tn, frame origin C, x
+// towards B). The endpoint intersections are evaluated in FP64 in both
+// precisions.
+template <typename R>
+__device__ inline void child_left(const He<R> &h, const Win<R> &w, double txc, bool full, double &x0, double &x1) {
+    if (full) {
+        x0 = 0.0;
+        x1 = (double)h.Lp;
+        return;
+    }
+    const double px = w.px, py = w.py, b0 = w.b0, b1 = w.b1, cx = h.cx, cy = h.cy, Lp = h.Lp;
+    x0 = b0 <= 0.0 ? 0.0 : Lp * (py * b0) / (py * cx + cy * (b0 - px));
+    x1 = b1 >= txc ? Lp : Lp * (py * b1) / (py * cx + cy * (b1 - px));
+    x0 = fmin(fmax(x0, 0.0), Lp);
+    x1 = fmin(fmax(x1, 0.0), Lp);
+}
+template <typename R>
+__device__ inline void child_right(const He<R> &h, const Win<R> &w, double txc, bool full, double &x0, double &x1) {
+    if (full) {
+        x0 = 0.0;
+        x1 = (double)h.Ln;
+        return;
+    }
+    const double px = w.px, py = w.py, b0 = w.b0, b1 = w.b1, cx = h.cx, cy = h.cy, L = h.L, Ln = h.Ln;
+    x0 = b0 <= txc ? 0.0 : Ln * ((px - cx) * (-py) - (py - cy) * (b0 - px)) / ((L - cx) * (-py) + cy * (b0 - px));
+    x1 = b1 >= L ? Ln : Ln * ((px - cx) * (-py) - (py - cy) * (b1 - px)) / ((L - cx) * (-py) + cy * (b1 - px));
+    x0 = fmin(fmax(x0, 0.0), Ln);
+    x1 = fmin(fmax(x1, 0.0), Ln);
+}
+
+// Both children of a window. F3: the face's vertices in 3D in the order
+// (A, B, C) = (tail, head, opposite) of the entry half-edge.
+template <typename R>
+__device__ inline void children(const He<R> &h, const Win<R> &w, double txc, bool full, double cutoff,
+                                const double F3[3][3], const Lds &L, int nc, double lb_slack, Win<R> &cl, bool &hl,
+                                Win<R> &cr, bool &hr, int &pruned) {
     hl = false;
     hr = false;
-    if (R.tp >= 0 && (full || b0 < txc)) {
-        double ex = R.cx / R.Lp, ey = R.cy / R.Lp;
+    if (h.tp >= 0 && (full || (double)w.b0 < txc)) {
         double x0, x1;
-        if (full) {
-            x0 = 0.0;
-            x1 = R.Lp;
-        } else {
-            x0 = b0 <= 0.0 ? 0.0 : R.Lp * (py * b0) / (py * R.cx + R.cy * (b0 - px));
-            x1 = b1 >= txc ? R.Lp : R.Lp * (py * b1) / (py * R.cx + R.cy * (b1 - px));
-            x0 = fmin(fmax(x0, 0.0), R.Lp);
-            x1 = fmin(fmax(x1, 0.0), R.Lp);
-        }
-        cl.px = ex * px + ey * py;
-        cl.py = ex * py - ey * px;
-        cl.b0 = x0;
-        cl.b1 = x1;
+        child_left(h, w, txc, full, x0, x1);
+        const R ex = h.cx / h.Lp, ey = h.cy / h.Lp;
+        cl.px = ex * w.px + ey * w.py;
+        cl.py = ex * w.py - ey * w.px;
+        cl.b0 = (R)x0;
+        cl.b1 = (R)x1;
         cl.sg = w.sg;
         cl.c = w.c * ex - w.s * ey;
         cl.s = w.s * ex + w.c * ey;
-        cl.he = R.tp;
+        cl.he = h.tp;
         cl.root = w.root;
-        if (x1 - x0 > 1e-12 * R.Lp) {
-            if (w.sg + seg_dist(cl.px, cl.py, x0, x1) < cutoff) hl = true;
+        if (x1 - x0 > 1e-12 * (double)h.Lp) {
+            double rem = cutoff - (double)w.sg - (double)seg_dist(cl.px, cl.py, cl.b0, cl.b1) + lb_slack;
+            double u[3] = {F3[2][0] - F3[0][0], F3[2][1] - F3[0][1], F3[2][2] - F3[0][2]};
+            double il = 1.0 / sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            u[0] *= il; u[1] *= il; u[2] *= il;
+            if (reaches_target(L, nc, F3[0], u, x0, x1, rem)) hl = true;
             else ++pruned;
         }
     }
-    if (R.tn >= 0 && (full || b1 > txc)) {
-        double ux = (R.L - R.cx) / R.Ln, uy = -R.cy / R.Ln;
+    if (h.tn >= 0 && (full || (double)w.b1 > txc)) {
         double x0, x1;
-        if (full) {
-            x0 = 0.0;
-            x1 = R.Ln;
-        } else {
-            double b = b0;
-            x0 = b0 <= txc ? 0.0
-                           : R.Ln * ((px - R.cx) * (-py) - (py - R.cy) * (b - px)) /
-                                 ((R.L - R.cx) * (-py) + R.cy * (b - px));
-            b = b1;
-            x1 = b1 >= R.L ? R.Ln
-                           : R.Ln * ((px - R.cx) * (-py) - (py - R.cy) * (b - px)) /
-                                 ((R.L - R.cx) * (-py) + R.cy * (b - px));
-            x0 = fmin(fmax(x0, 0.0), R.Ln);
-            x1 = fmin(fmax(x1, 0.0), R.Ln);
-        }
-        double qx = px - R.cx, qy = py - R.cy;
+        child_right(h, w, txc, full, x0, x1);
+        const R ux = (h.L - h.cx) / h.Ln, uy = -h.cy / h.Ln;
+        const R qx = w.px - h.cx, qy = w.py - h.cy;
         cr.px = ux * qx + uy * qy;
         cr.py = ux * qy - uy * qx;
-        cr.b0 = x0;
-        cr.b1 = x1;
+        cr.b0 = (R)x0;
+        cr.b1 = (R)x1;
         cr.sg = w.sg;
         cr.c = w.c * ux - w.s * uy;
         cr.s = w.s * ux + w.c * uy;
-        cr.he = R.tn;
+        cr.he = h.tn;
         cr.root = w.root;
-        if (x1 - x0 > 1e-12 * R.Ln) {
-            if (w.sg + seg_dist(cr.px, cr.py, x0, x1) < cutoff) hr = true;
+        if (x1 - x0 > 1e-12 * (double)h.Ln) {
+            double rem = cutoff - (double)w.sg - (double)seg_dist(cr.px, cr.py, cr.b0, cr.b1) + lb_slack;
+            double u[3] = {F3[1][0] - F3[2][0], F3[1][1] - F3[2][1], F3[1][2] - F3[2][2]};
+            double il = 1.0 / sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
+            u[0] *= il; u[1] *= il; u[2] *= il;
+            if (reaches_target(L, nc, F3[2], u, x0, x1, rem)) hr = true;
             else ++pruned;
         }
     }
 }
 
+__device__ inline void face_xyz(const DevMesh &m, int f, int k, double F3[3][3]) {
+    const double *p = m.fpos + 9 * (int64_t)f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int q = (k + i) % 3;
+        F3[i][0] = p[3 * q];
+        F3[i][1] = p[3 * q + 1];
+        F3[i][2] = p[3 * q + 2];
+    }
+}
+
+template <typename R>
 __global__ __launch_bounds__(kWave) void k_geodesic(GeoArgs a) {
+    using Rec = typename RecOf<R>::T;
     __shared__ Lds L;
     const int lane = lane_id();
     const double cutoff = a.gp.cutoff;
+    const bool fp32 = sizeof(R) == 4;
+    // FP32 results may be off by rounding: everything within the guard band
+    // above the cutoff is still propagated and recorded, so that pairs near
+    // the cutoff are seen and recomputed in FP64
+    const double lb_slack = fp32 ? fmax(1e-4, a.gp.guard_rel) * cutoff : 0.0;
+    const double cut_acc = cutoff + lb_slack;
+    const double tol = a.gp.cone_tol;
     const HeRec *__restrict__ he = a.m.he;
-    WinRec *stk = a.stack + (size_t)blockIdx.x * a.gp.stack_cap;
-    const int chunk0 = blockIdx.x % kChunks;
-    int chunk = chunk0, chunks_left = kChunks;
+    Rec *stk = reinterpret_cast<Rec *>(a.stack) + (size_t)blockIdx.x * a.gp.stack_cap;
+    int chunk = blockIdx.x % kChunks, chunks_left = kChunks;
 
     unsigned long long c_win = 0, c_pruned = 0, c_launch = 0, c_stale = 0, c_limited = 0;
 
@@ -275,6 +393,7 @@ __global__ __launch_bounds__(kWave) void k_geodesic(GeoArgs a) {
         }
         if (idx < 0) break;
         const int src = a.order[idx];
+        if (a.guard_pass && a.guard[src] == 0) continue;
         const int64_t c0 = a.cand_off[src];
         const int nc = (int)(a.cand_off[src + 1] - c0);
         if (nc == 0) continue;
@@ -290,6 +409,7 @@ __global__ __launch_bounds__(kWave) void k_geodesic(GeoArgs a) {
         // ---- LDS tables
         for (int e = lane; e < kHash; e += kWave) L.head[e] = -1;
         for (int e = lane; e < kRootCap; e += kWave) L.rkey[e] = -1;
+        if (lane == 0) L.rcount = 0;
         __syncthreads();
         for (int s = lane; s < nc; s += kWave) {
             int j = a.cand[c0 + s];
@@ -313,16 +433,14 @@ __global__ __launch_bounds__(kWave) void k_geodesic(GeoArgs a) {
         int pruned = 0;
         unsigned long long nwin = 0;
 
-        // ---- seed from the source (root -1, sg = 0)
+        // ---- seed from the source (root -1, sg = 0), in FP64
         const int fs = a.face[src];
         const double sb[3] = {a.bary[3 * (int64_t)src], a.bary[3 * (int64_t)src + 1], a.bary[3 * (int64_t)src + 2]};
         const HeRec R0 = he[3 * fs];
         const double P[3][2] = {{0.0, 0.0}, {R0.L, 0.0}, {R0.cx, R0.cy}};
         const double sx = sb[1] * P[1][0] + sb[2] * P[2][0], sy = sb[1] * P[1][1] + sb[2] * P[2][1];
         {
-            // direct targets in the source face
             int slot = lane < 1 ? first_in_face(L, fs) : -1;
-            // one lane walks the (short) chain; other lanes idle
             while (__ballot(slot >= 0)) {
                 bool ok = slot >= 0;
                 double d = 0, tx = 0, ty = 0;
@@ -336,50 +454,49 @@ __global__ __launch_bounds__(kWave) void k_geodesic(GeoArgs a) {
                         ty = dy / d;
                     }
                 }
-                target_update(L, ok, slot, d, tx, ty);
+                target_update(L, ok, slot, d, tx, ty, a.gp.tie_dir);
                 if (ok) slot = next_in_face(L, slot, fs);
             }
         }
         {
-            Win w;
+            Win<R> w, wa, wb;
             bool want = false, wantA = false, wantB = false;
-            Win wa, wb;
             bool rok = false;
             int rv = 0;
             double rd = 0, rtx = 0, rty = 0;
             if (lane < 3) {
                 const int k = lane, h = 3 * fs + k;
-                const HeRec R = he[h];
-                const double ex = (P[(k + 1) % 3][0] - P[k][0]) / R.L, ey = (P[(k + 1) % 3][1] - P[k][1]) / R.L;
-                // bend-vertex candidate: the tail of h
+                const HeRec Rh = he[h];
+                const double ex = (P[(k + 1) % 3][0] - P[k][0]) / Rh.L, ey = (P[(k + 1) % 3][1] - P[k][1]) / Rh.L;
                 int v = a.m.T[h];
                 if (a.m.vflag[v] & VF_PSEUDO) {
                     double dx = P[k][0] - sx, dy = P[k][1] - sy;
                     rd = sqrt(dx * dx + dy * dy);
-                    rok = rd < cutoff;
+                    rok = rd < cut_acc;
                     rv = v;
                     rtx = rd > 0 ? dx / rd : 0.0;
                     rty = rd > 0 ? dy / rd : 0.0;
                 }
-                const double hx = sb[(k + 1) % 3] * R.L + sb[(k + 2) % 3] * R.cx, hy = sb[(k + 2) % 3] * R.cy;
-                if (R.twin >= 0) {
-                    w.px = R.L - hx;
-                    w.py = -hy;
-                    w.b0 = 0.0;
-                    w.b1 = R.L;
-                    w.sg = 0.0;
-                    w.c = -ex;
-                    w.s = -ey;
-                    w.he = R.twin;
+                const double hx = sb[(k + 1) % 3] * Rh.L + sb[(k + 2) % 3] * Rh.cx, hy = sb[(k + 2) % 3] * Rh.cy;
+                if (Rh.twin >= 0) {
+                    w.px = (R)(Rh.L - hx);
+                    w.py = (R)(-hy);
+                    w.b0 = R(0);
+                    w.b1 = (R)Rh.L;
+                    w.sg = R(0);
+                    w.c = (R)(-ex);
+                    w.s = (R)(-ey);
+                    w.he = Rh.twin;
                     w.root = -1;
                     if (sb[(k + 2) % 3] > 0.0) {
-                        want = seg_dist(w.px, w.py, 0.0, R.L) < cutoff;
+                        want = seg_dist(Rh.L - hx, -hy, 0.0, Rh.L) < cut_acc;
                     } else {
                         // source on this edge: the face across contains it as well
-                        const HeRec Rt = he[R.twin];
-                        w.py = 0.0;
-                        double txc = 0.0;
-                        children(Rt, w, txc, true, cutoff, wa, wantA, wb, wantB, pruned);
+                        const He<R> Ht = load_he(a.m, Rh.twin, R(0));
+                        w.py = R(0);
+                        double F3[3][3];
+                        face_xyz(a.m, Rh.twin / 3, Rh.twin % 3, F3);
+                        children(Ht, w, 0.0, true, cutoff, F3, L, nc, lb_slack, wa, wantA, wb, wantB, pruned);
                     }
                 }
             }
@@ -388,13 +505,13 @@ __global__ __launch_bounds__(kWave) void k_geodesic(GeoArgs a) {
             for (int k = 0; k < 3; ++k) {
                 bool on = sb[(k + 2) % 3] <= 0.0 && he[3 * fs + k].twin >= 0;
                 if (!on) continue;  // wave-uniform
-                const HeRec R = he[3 * fs + k];
-                const int t = R.twin, g = t / 3, m = t % 3;
+                const HeRec Rh = he[3 * fs + k];
+                const int t = Rh.twin, g = t / 3, m = t % 3;
                 const HeRec Rt = he[t];
-                const double ex = (P[(k + 1) % 3][0] - P[k][0]) / R.L, ey = (P[(k + 1) % 3][1] - P[k][1]) / R.L;
+                const double ex = (P[(k + 1) % 3][0] - P[k][0]) / Rh.L, ey = (P[(k + 1) % 3][1] - P[k][1]) / Rh.L;
                 const double c = -ex, s = -ey;
-                const double hx = sb[(k + 1) % 3] * R.L + sb[(k + 2) % 3] * R.cx;
-                const double ptx = R.L - hx;
+                const double hx = sb[(k + 1) % 3] * Rh.L + sb[(k + 2) % 3] * Rh.cx;
+                const double ptx = Rh.L - hx;
                 int slot = lane < 1 ? first_in_face(L, g) : -1;
                 while (__ballot(slot >= 0)) {
                     bool ok = slot >= 0;
@@ -411,13 +528,13 @@ __global__ __launch_bounds__(kWave) void k_geodesic(GeoArgs a) {
                             ty = s * dx + c * dy;
                         }
                     }
-                    target_update(L, ok, slot, d, tx, ty);
+                    target_update(L, ok, slot, d, tx, ty, a.gp.tie_dir);
                     if (ok) slot = next_in_face(L, slot, g);
                 }
                 bool ok = lane == 0 && (Rt.flags & 1);
                 double dx = Rt.cx - ptx, dy = Rt.cy;
                 double d = sqrt(dx * dx + dy * dy);
-                root_update(L, ok && d < cutoff, Rt.opp, d, (c * dx - s * dy) / d, (s * dx + c * dy) / d, overflow);
+                root_update(L, ok && d < cut_acc, Rt.opp, d, (c * dx - s * dy) / d, (s * dx + c * dy) / d, overflow);
             }
             push_windows(stk, sp, a.gp.stack_cap, want, w, overflow);
             push_windows(stk, sp, a.gp.stack_cap, wantA, wa, overflow);
@@ -426,21 +543,18 @@ __global__ __launch_bounds__(kWave) void k_geodesic(GeoArgs a) {
 
         // ---- propagation
         bool have = false;
-        Win w;
+        Win<R> w;
         for (;;) {
             // stack writes by other lanes must be visible before popping
             __syncthreads();
             if (__ballot(overflow)) overflow = true;
             if (overflow) break;
-            // refill idle lanes from the stack
             uint64_t need = __ballot(!have);
             int take = min(__popcll(need), sp);
             if (!have) {
                 int r = __popcll(need & lanemask_lt());
                 if (r < take) {
-                    WinRec q = stk[sp - 1 - r];
-                    w.px = q.px; w.py = q.py; w.b0 = q.b0; w.b1 = q.b1; w.sg = q.sg; w.c = q.c; w.s = q.s;
-                    w.he = q.he; w.root = q.root;
+                    load_rec(stk[sp - 1 - r], w);
                     have = true;
                 }
             }
@@ -449,45 +563,65 @@ __global__ __launch_bounds__(kWave) void k_geodesic(GeoArgs a) {
                 // no window anywhere: launch the next bucket of bend vertices
                 double mn = INFINITY;
                 for (int e = lane; e < kRootCap; e += kWave)
-                    if (L.rkey[e] >= 0 && L.rD[e] < L.rL[e] && L.rD[e] < cutoff) mn = fmin(mn, L.rD[e]);
+                    if (L.rkey[e] >= 0 && L.rD[e] < L.rL[e] && L.rD[e] < cut_acc) mn = fmin(mn, L.rD[e]);
                 mn = wave_min(mn);
                 if (!(mn < INFINITY)) break;
                 const double thr = mn + a.gp.launch_delta;
                 for (int base = 0; base < kRootCap; base += kWave) {
                     const int e = base + lane;
-                    bool sel = L.rkey[e] >= 0 && L.rD[e] < L.rL[e] && L.rD[e] <= thr && L.rD[e] < cutoff;
-                    uint64_t m = __ballot(sel);
-                    while (m) {
-                        const int el = base + __ffsll((unsigned long long)m) - 1;
-                        m &= m - 1;
+                    bool sel = e < kRootCap && L.rkey[e] >= 0 && L.rD[e] < L.rL[e] && L.rD[e] <= thr &&
+                               L.rD[e] < cut_acc;
+                    uint64_t mk = __ballot(sel);
+                    while (mk) {
+                        const int el = base + __ffsll((unsigned long long)mk) - 1;
+                        mk &= mk - 1;
                         const int v = L.rkey[el];
                         const double D = L.rD[el];
                         const double vtx = L.rtx[el], vty = L.rty[el];
                         __syncthreads();
                         if (lane == 0) L.rL[el] = D;
-                        ++c_launch;
-                        const int f0 = a.m.fan_off[v], f1 = a.m.fan_off[v + 1];
                         const double vx = a.m.V[3 * (int64_t)v], vy = a.m.V[3 * (int64_t)v + 1],
                                      vz = a.m.V[3 * (int64_t)v + 2];
+                        // a bend vertex farther (in 3D) than the remaining budget from
+                        // every target cannot lead to a pair below the cutoff
+                        bool useful = false;
+                        {
+                            const double rem = cutoff - D + lb_slack;
+                            for (int s = lane; s < nc; s += kWave) {
+                                double q0 = L.tx3[s][0] - vx, q1 = L.tx3[s][1] - vy, q2 = L.tx3[s][2] - vz;
+                                useful |= q0 * q0 + q1 * q1 + q2 * q2 < rem * rem;
+                            }
+                        }
+                        if (__ballot(useful) == 0) continue;
+                        ++c_launch;
+                        const int f0 = a.m.fan_off[v], f1 = a.m.fan_off[v + 1];
                         for (int fb = f0; fb < f1; fb += kWave) {
                             const int q = fb + lane;
                             const bool act = q < f1;
-                            int h = act ? a.m.fan[q] : 0;
+                            const int h = act ? a.m.fan[q] : 0;
                             const int hn = h - h % 3 + (h % 3 + 1) % 3;
-                            HeRec Rh = he[h], Rn = he[hn];
-                            Win nw;
+                            const HeRec Rh = he[h], Rn = he[hn];
+                            Win<R> nw;
                             bool want2 = false;
                             if (act && Rn.twin >= 0) {
-                                nw.px = Rn.L - Rn.cx;
-                                nw.py = -Rn.cy;
-                                nw.b0 = 0.0;
-                                nw.b1 = Rn.L;
-                                nw.sg = D;
-                                nw.c = 1.0;
-                                nw.s = 0.0;
+                                // window across the edge opposite v: twin(next(h)) runs u2 -> u1
+                                const double px = Rn.L - Rn.cx, py = -Rn.cy;
+                                nw.px = (R)px;
+                                nw.py = (R)py;
+                                nw.b0 = R(0);
+                                nw.b1 = (R)Rn.L;
+                                nw.sg = (R)D;
+                                nw.c = R(1);
+                                nw.s = R(0);
                                 nw.he = Rn.twin;
                                 nw.root = el;
-                                want2 = D + seg_dist(nw.px, nw.py, 0.0, Rn.L) < cutoff;
+                                double F3[3][3];
+                                face_xyz(a.m, h / 3, h % 3, F3);  // (v, u1, u2)
+                                double u[3] = {F3[1][0] - F3[2][0], F3[1][1] - F3[2][1], F3[1][2] - F3[2][2]};
+                                const double il = 1.0 / Rn.L;
+                                u[0] *= il; u[1] *= il; u[2] *= il;
+                                want2 = reaches_target(L, nc, F3[2], u, 0.0, Rn.L,
+                                                       cutoff - D - seg_dist(px, py, 0.0, Rn.L) + lb_slack);
                             }
                             // direct targets in face(h)
                             const int g = h / 3;
@@ -500,15 +634,15 @@ __global__ __launch_bounds__(kWave) void k_geodesic(GeoArgs a) {
                                            dz = L.tx3[slot][2] - vz;
                                     d = D + sqrt(dx * dx + dy * dy + dz * dz);
                                 }
-                                target_update(L, ok, slot, d, vtx, vty);
+                                target_update(L, ok, slot, d, vtx, vty, a.gp.tie_dir);
                                 if (ok) slot = next_in_face(L, slot, g);
                             }
                             // adjacent bend vertices along the two edges at v
                             const int u1 = act ? a.m.T[hn] : 0;  // head of h
-                            bool ok1 = act && (a.m.vflag[u1] & VF_PSEUDO) && D + Rh.L < cutoff;
+                            bool ok1 = act && (a.m.vflag[u1] & VF_PSEUDO) && D + Rh.L < cut_acc;
                             root_update(L, ok1, u1, D + Rh.L, vtx, vty, overflow);
                             const int u2 = act ? Rh.opp : 0;
-                            bool ok2 = act && (a.m.vflag[u2] & VF_PSEUDO) && D + Rh.Lp < cutoff;
+                            bool ok2 = act && (a.m.vflag[u2] & VF_PSEUDO) && D + Rh.Lp < cut_acc;
                             root_update(L, ok2, u2, D + Rh.Lp, vtx, vty, overflow);
                             push_windows(stk, sp, a.gp.stack_cap, want2, nw, overflow);
                         }
@@ -523,52 +657,51 @@ __global__ __launch_bounds__(kWave) void k_geodesic(GeoArgs a) {
             }
 
             // ---- process the lane's window
-            Win cl, cr;
+            Win<R> cl, cr;
             bool hl = false, hr = false;
-            if (have) {
-                if (w.root >= 0 && w.sg > L.rD[w.root]) {
-                    have = false;
-                    ++c_stale;
-                }
+            // stale: the root's distance improved after this window was made
+            // (compared in the working precision the window was stored in)
+            if (have && w.root >= 0 && w.sg > (R)L.rD[w.root]) {
+                have = false;
+                ++c_stale;
             }
-            HeRec R;
+            He<R> H;
             double txc = 0.0;
-            int f = -1;
+            int f = -1, k = 0;
             if (have) {
-                R = he[w.he];
+                H = load_he(a.m, w.he, R(0));
                 f = w.he / 3;
-                txc = w.px + (R.cx - w.px) * (-w.py) / (R.cy - w.py);
+                k = w.he % 3;
+                txc = (double)w.px + ((double)H.cx - (double)w.px) * (-(double)w.py) / ((double)H.cy - (double)w.py);
             }
-            const double tol = a.gp.cone_tol;
             // targets in face f
             {
                 int slot = have ? first_in_face(L, f) : -1;
-                const int k = have ? w.he % 3 : 0;
                 while (__ballot(slot >= 0)) {
                     bool ok = false;
                     double d = 0, tx = 0, ty = 0;
                     if (slot >= 0) {
-                        double qx = L.tb[slot][(k + 1) % 3] * R.L + L.tb[slot][(k + 2) % 3] * R.cx;
-                        double qy = L.tb[slot][(k + 2) % 3] * R.cy;
-                        double xq = w.px + (qx - w.px) * (-w.py) / (qy - w.py);
-                        double sl = tol * R.L;
+                        const R qx = (R)L.tb[slot][(k + 1) % 3] * H.L + (R)L.tb[slot][(k + 2) % 3] * H.cx;
+                        const R qy = (R)L.tb[slot][(k + 2) % 3] * H.cy;
+                        const R xq = w.px + (qx - w.px) * (-w.py) / (qy - w.py);
+                        const R sl = (R)tol * H.L;
                         if (xq >= w.b0 - sl && xq <= w.b1 + sl) {
-                            double dx = qx - w.px, dy = qy - w.py;
-                            double l = sqrt(dx * dx + dy * dy);
-                            d = w.sg + l;
-                            ok = d < cutoff;
+                            R dx = qx - w.px, dy = qy - w.py;
+                            const R l = sqrt(dx * dx + dy * dy);
+                            d = (double)w.sg + (double)l;
+                            ok = d < cut_acc;
                             if (w.root < 0) {
                                 dx /= l;
                                 dy /= l;
-                                tx = w.c * dx - w.s * dy;
-                                ty = w.s * dx + w.c * dy;
+                                tx = (double)(w.c * dx - w.s * dy);
+                                ty = (double)(w.s * dx + w.c * dy);
                             } else {
                                 tx = L.rtx[w.root];
                                 ty = L.rty[w.root];
                             }
                         }
                     }
-                    target_update(L, ok, slot, d, tx, ty);
+                    target_update(L, ok, slot, d, tx, ty, a.gp.tie_dir);
                     if (slot >= 0) slot = next_in_face(L, slot, f);
                 }
             }
@@ -576,29 +709,33 @@ __global__ __launch_bounds__(kWave) void k_geodesic(GeoArgs a) {
             {
                 bool ok = false;
                 double d = 0, tx = 0, ty = 0;
-                if (have && (R.flags & 1)) {
-                    double sl = tol * R.L;
-                    if (txc >= w.b0 - sl && txc <= w.b1 + sl) {
-                        double dx = R.cx - w.px, dy = R.cy - w.py;
-                        double l = sqrt(dx * dx + dy * dy);
-                        d = w.sg + l;
-                        ok = d < cutoff;
+                if (have && H.pseudo) {
+                    const double sl = tol * (double)H.L;
+                    if (txc >= (double)w.b0 - sl && txc <= (double)w.b1 + sl) {
+                        R dx = H.cx - w.px, dy = H.cy - w.py;
+                        const R l = sqrt(dx * dx + dy * dy);
+                        d = (double)w.sg + (double)l;
+                        ok = d < cut_acc;
                         if (w.root < 0) {
                             dx /= l;
                             dy /= l;
-                            tx = w.c * dx - w.s * dy;
-                            ty = w.s * dx + w.c * dy;
+                            tx = (double)(w.c * dx - w.s * dy);
+                            ty = (double)(w.s * dx + w.c * dy);
                         } else {
                             tx = L.rtx[w.root];
                             ty = L.rty[w.root];
                         }
                     }
                 }
-                root_update(L, ok, have ? R.opp : 0, d, tx, ty, overflow);
+                root_update(L, ok, have ? H.opp : 0, d, tx, ty, overflow);
             }
-            if (have) children(R, w, txc, false, cutoff, cl, hl, cr, hr, pruned);
+            if (have) {
+                double F3[3][3];
+                face_xyz(a.m, f, k, F3);
+                children(H, w, txc, false, cutoff, F3, L, nc, lb_slack, cl, hl, cr, hr, pruned);
+            }
             // keep one child in the lane, push the other
-            bool push = hl && hr;
+            const bool push = hl && hr;
             push_windows(stk, sp, a.gp.stack_cap, push, cr, overflow);
             if (have) {
                 if (hl) w = cl;
@@ -619,42 +756,48 @@ __global__ __launch_bounds__(kWave) void k_geodesic(GeoArgs a) {
         double ey3[3] = {nn[1] * ex3[2] - nn[2] * ex3[1], nn[2] * ex3[0] - nn[0] * ex3[2],
                          nn[0] * ex3[1] - nn[1] * ex3[0]};
         __syncthreads();
+        const bool ovf = __ballot(overflow) != 0;
+        bool near_cut = false;
         for (int s = lane; s < nc; s += kWave) {
             const int64_t o = c0 + s;
             double d = L.d1[s];
             uint8_t fl = 0;
-            if (__ballot(overflow)) d = NAN;
+            if (ovf) d = NAN;
             if (L.d2[s] - d <= a.gp.tie_rel * d) fl |= GSIM_PAIR_TIE_BIT;
             if (d == 0.0) fl |= GSIM_PAIR_ZERO_BIT;
+            if (a.guard_pass) fl |= GSIM_PAIR_GUARD_BIT;
+            near_cut |= fabs(d - cutoff) <= a.gp.guard_rel * cutoff;
             a.out.dist[o] = d;
             a.out.flags[o] = fl;
             for (int q = 0; q < 3; ++q) a.out.tan[3 * o + q] = L.t1x[s] * ex3[q] + L.t1y[s] * ey3[q];
         }
+        const bool any_near = __ballot(near_cut) != 0;
+        if (fp32 && a.guard && lane == 0) a.guard[src] = any_near ? 1 : 0;
         c_win += nwin;
         c_pruned += (unsigned long long)pruned;
-        if (__ballot(overflow)) ++c_limited;
+        if (ovf) ++c_limited;
         __syncthreads();
     }
-    // counters: lane sums (pruned is per lane; others wave-uniform)
-    unsigned long long pr = c_pruned;
-    for (int o = 32; o > 0; o >>= 1) pr += __shfl_xor(pr, o);
+    unsigned long long pr = c_pruned, st = c_stale;
+    for (int o = 32; o > 0; o >>= 1) {
+        pr += __shfl_xor(pr, o);
+        st += __shfl_xor(st, o);
+    }
     if (lane == 0) {
         atomicAdd(&a.ctr->windows, c_win);
         atomicAdd(&a.ctr->pruned, pr);
         atomicAdd(&a.ctr->launches, c_launch);
+        atomicAdd(&a.ctr->stale, st);
         atomicAdd(&a.ctr->limited, c_limited);
     }
-    unsigned long long st = c_stale;
-    for (int o = 32; o > 0; o >>= 1) st += __shfl_xor(st, o);
-    if (lane == 0) atomicAdd(&a.ctr->stale, st);
 }
 
 }  // namespace
 
 hipError_t launch_geodesic(const DevMesh &m, int n, const int32_t *face, const double *bary, const double *xyz,
                            const PrefilterBufs &pb, const GeoParams &gp, GeoOut out, char *stack_mem,
-                           int32_t nslots, int32_t *work_ctr, Counters *ctr, bool fp32, hipStream_t s) {
-    (void)fp32;
+                           int32_t nslots, int32_t *work_ctr, Counters *ctr, bool fp32, uint8_t *guard,
+                           bool guard_pass, hipStream_t s) {
     GeoArgs a;
     a.m = m;
     a.n = n;
@@ -666,13 +809,16 @@ hipError_t launch_geodesic(const DevMesh &m, int n, const int32_t *face, const d
     a.order = pb.order;
     a.gp = gp;
     a.out = out;
-    a.stack = reinterpret_cast<WinRec *>(stack_mem);
+    a.stack = stack_mem;
     a.work = work_ctr;
     a.ctr = ctr;
-    hipLaunchKernelGGL(k_geodesic, dim3(nslots), dim3(kWave), 0, s, a);
+    a.guard = guard;
+    a.guard_pass = guard_pass ? 1 : 0;
+    if (fp32) hipLaunchKernelGGL(k_geodesic<float>, dim3(nslots), dim3(kWave), 0, s, a);
+    else hipLaunchKernelGGL(k_geodesic<double>, dim3(nslots), dim3(kWave), 0, s, a);
     return hipGetLastError();
 }
 
-size_t window_record_bytes() { return sizeof(WinRec); }
+size_t window_record_bytes(bool fp32) { return fp32 ? sizeof(Rec32) : sizeof(Rec64); }
 
 }  // namespace gsim

@@ -61,6 +61,10 @@ std::string build_host_mesh(int nv, const double *xyz, int nf, const int32_t *tr
     M.corner.assign(ne, 0.0);
     M.theta.assign(nv, 0.0);
     M.fnrm.assign(3 * size_t(nf), 0.0);
+    M.fpos.assign(9 * size_t(nf), 0.0);
+    for (int f = 0; f < nf; ++f)
+        for (int k = 0; k < 3; ++k)
+            for (int d = 0; d < 3; ++d) M.fpos[9 * size_t(f) + 3 * k + d] = M.V[3 * size_t(M.T[3 * f + k]) + d];
     double lsum = 0.0;
     int64_t lcnt = 0;
     M.min_edge = INFINITY;

@@ -25,7 +25,7 @@ PAIR_TIE, PAIR_ZERO, PAIR_GUARD = 1, 2, 4
 EXPORTS = ["gsim_create", "gsim_destroy", "gsim_last_error", "gsim_synchronize", "gsim_mesh_upload",
            "gsim_mesh_info_get", "gsim_particles_set", "gsim_particles_get", "gsim_particles_set_dev",
            "gsim_particles_get_dev", "gsim_geodesic_pairs", "gsim_compute_forces", "gsim_displace_on_surface",
-           "gsim_step", "gsim_timing_enable", "gsim_timing_get", "gsim_counters_get"]
+           "gsim_step", "gsim_timing_enable", "gsim_timing_get", "gsim_counters_get", "gsim_tune_set"]
 
 
 class GsimError(RuntimeError):
@@ -90,6 +90,7 @@ def load(path: str = LIB_PATH):
         "gsim_timing_enable": ([V, C.c_int], C.c_int),
         "gsim_timing_get": ([V, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
         "gsim_counters_get": ([V, V], C.c_int),
+        "gsim_tune_set": ([V, C.c_char_p, C.c_double], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -239,6 +240,10 @@ class Context:
         n = C.c_int64()
         self._chk(self.L.gsim_timing_get(self.h, name.encode(), C.byref(ms), C.byref(n)))
         return ms.value, n.value
+
+    def tune(self, **knobs):
+        for k, v in knobs.items():
+            self._chk(self.L.gsim_tune_set(self.h, k.encode(), float(v)))
 
     def counters(self) -> dict:
         c = np.zeros(10, np.int64)

@@ -1,0 +1,113 @@
+"""GPU parity in FP32-mixed mode: FP32 windows, FP64 endpoint intersections
+and an FP64 recompute of every source with a pair near the cutoff. Neighbour
+sets and faces bit-exact; distances, tangents and forces within 1e-5
+relative of the FP64 oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+from paper_2404_19751_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+RTOL32 = 1e-5
+
+
+def log(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def ctx32():
+    from paper_2404_19751_amd import gsim
+    c = gsim.Context(0, "fp32")
+    yield c
+    c.close()
+
+
+def compare32(g, o, lbar, label):
+    assert np.array_equal(g["off"], o.off), f"{label}: neighbour counts differ"
+    assert np.array_equal(g["nbr"], o.nbr), f"{label}: neighbour sets differ"
+    rel = np.abs(g["dist"] - o.dist) / o.dist
+    assert rel.max(initial=0) <= RTOL32, f"{label}: dist rel err {rel.max()}"
+    scale = np.maximum(o.dist, 1e-3 * lbar)
+    err = np.linalg.norm(o.dist[:, None] * (g["tan"] - o.tan), axis=1) / scale
+    # a pair flagged as a near-tie (gap below 1e-4 d) may take the other direction
+    amb = ((g["flags"] & 1) != 0) | ((o.flags & 1) != 0)
+    print(f"[gpu-fp32] {label}: {amb.sum()} of {len(amb)} pairs flagged as near-ties", flush=True)
+    assert err[~amb].max(initial=0) <= RTOL32, f"{label}: tangent err {err[~amb].max()}"
+    return rel.max(initial=0), err[~amb].max(initial=0)
+
+
+@pytest.mark.parametrize("name", ["c1", "c2"])
+def test_pairs_fp32(ctx32, orc, name):
+    w = W.workload(name)
+    om = orc.OracleMesh(w.mesh.V, w.mesh.T)
+    mid = ctx32.mesh_upload(w.mesh.V, w.mesh.T)
+    ctx32.particles_set(mid, w.face, w.bary)
+    log(f"[gpu-fp32] {name} pairs")
+    g = ctx32.geodesic_pairs(mid, w.potential["cutoff"])
+    o = orc.geodesic_pairs(om, w.face, w.bary, w.potential["cutoff"])
+    d_err, t_err = compare32(g, o, w.mean_edge, name)
+    log(f"[gpu-fp32] {name}: pairs={len(o.dist)} dist_err={d_err:.2e} tan_err={t_err:.2e} {ctx32.counters()}")
+
+
+@pytest.mark.parametrize("name,mk,n,cut", [
+    ("torus", lambda: W.torus(1.0, 0.3, 30, 12), 80, 0.7),
+    ("lshape", lambda: W.l_shape(4), 40, 1.5),
+    ("cone_saddle", lambda: W.cone_fan(2.5 * np.pi, 8), 30, 1.2),
+])
+def test_small_fp32(ctx32, orc, name, mk, n, cut):
+    m = mk()
+    f, b = W.random_particles(m.nf, n, 17)
+    om = orc.OracleMesh(m.V, m.T)
+    mid = ctx32.mesh_upload(m.V, m.T)
+    ctx32.particles_set(mid, f, b)
+    g = ctx32.geodesic_pairs(mid, cut)
+    o = orc.geodesic_pairs(om, f, b, cut)
+    compare32(g, o, W.mean_edge_length(m), name)
+
+
+def test_guard_band_keeps_neighbour_sets_exact(ctx32, orc):
+    """Cutoffs placed a hair above / below a true pair distance: the FP64
+    recompute must decide membership exactly as the FP64 oracle does."""
+    w = W.workload("c2")
+    om = orc.OracleMesh(w.mesh.V, w.mesh.T)
+    o = orc.geodesic_pairs(om, w.face, w.bary, 0.15)
+    mid = ctx32.mesh_upload(w.mesh.V, w.mesh.T)
+    ctx32.particles_set(mid, w.face, w.bary)
+    d = float(np.sort(o.dist)[len(o.dist) // 2])
+    for cut in (d * (1 + 3e-9), d * (1 - 3e-9)):
+        g = ctx32.geodesic_pairs(mid, cut)
+        oo = orc.geodesic_pairs(om, w.face, w.bary, cut)
+        assert np.array_equal(g["nbr"], oo.nbr) and np.array_equal(g["off"], oo.off)
+        assert (g["flags"] & 4).any()  # recomputed in FP64
+    log("[gpu-fp32] guard band ok")
+
+
+def test_forces_fp32(ctx32, orc):
+    from paper_2404_19751_amd import gsim
+    w = W.workload("c2")
+    om = orc.OracleMesh(w.mesh.V, w.mesh.T)
+    mid = ctx32.mesh_upload(w.mesh.V, w.mesh.T)
+    ctx32.particles_set(mid, w.face, w.bary)
+    F, E = ctx32.compute_forces(mid, gsim.potential("harmonic", 1.0, 0.15, 0.15))
+    o = orc.geodesic_pairs(om, w.face, w.bary, 0.15)
+    Fo, Eo = orc.forces(len(w.face), o, "harmonic", 1.0, 0.15)
+    scale = np.zeros(len(w.face))
+    for i in range(len(w.face)):
+        for p in range(o.off[i], o.off[i + 1]):
+            scale[i] += abs(orc.potential("harmonic", o.dist[p], 1.0, 0.15)[1])
+    err = np.linalg.norm(F - Fo, axis=1)
+    # particles with a near-tie pair (gap below 1e-4 d, flagged by the GPU) may
+    # take the other initial direction for that pair: their force is ambiguous
+    g = ctx32.geodesic_pairs(mid, 0.15)
+    amb = np.zeros(len(w.face), bool)
+    for i in range(len(w.face)):
+        amb[i] = bool((g["flags"][g["off"][i]:g["off"][i + 1]] & 1).any())
+    print(f"[gpu-fp32] forces: {amb.sum()} of {len(amb)} particles with a near-tie pair", flush=True)
+    assert (~amb).mean() > 0.8
+    bad = np.nonzero(~amb & (err > RTOL32 * scale))[0]
+    assert len(bad) == 0, [(int(i), err[i], scale[i]) for i in bad[:5]]
+    assert abs(E - Eo) <= RTOL32 * abs(Eo)
