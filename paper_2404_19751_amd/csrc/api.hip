@@ -57,7 +57,10 @@ struct gsim_ctx {
     bool own_stream = false;
     std::string err;
     std::vector<MeshState *> meshes;
-    Buf stack, work, ctr, wstats, scan_scratch, sum_scratch;
+    Buf stack, work, ctr, wstats, scan_scratch, sum_scratch, pf_over, prof;
+    bool profile_sources = false;
+    int prof_n = 0;
+    int64_t passes = 0;
     int32_t nslots = 0;
     GeoParams gp{};
     Counters last{};
@@ -161,136 +164,130 @@ MeshState *get_mesh(gsim_ctx *c, int32_t id) {
 bool finite_cutoff(double c) { return c > 0.0 && std::isfinite(c); }
 
 // ---------------------------------------------------------------- pairs
-gsim_status run_pairs(gsim_ctx *c, MeshState *ms, double cutoff) {
+// A call (geodesic_pairs, compute_forces, step) zeroes the device counters,
+// queues its work without any host synchronisation, and reads the counters
+// back once at the end.
+gsim_status begin_call(gsim_ctx *c) {
+    HIPCHK(c, launch_zero_u64(P<unsigned long long>(c->ctr), 8, c->stream));
+    HIPCHK(c, launch_zero_i32(P<int32_t>(c->pf_over), 1, c->stream));
+    c->passes = 0;
+    return GSIM_OK;
+}
+
+gsim_status end_call(gsim_ctx *c) {
+    int32_t over = 0;
+    HIPCHK(c, hipMemcpyAsync(&c->last, c->ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipMemcpyAsync(&over, c->pf_over.p, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->cum_pairs += c->last.nbr_pairs;
+    c->cum_windows += c->last.windows;
+    c->cum_passes += c->passes;
+    if (over || c->last.limited)
+        return fail(c, GSIM_E_LIMIT,
+                    std::to_string(over + (long long)c->last.limited) +
+                        " source(s) exceeded a per-source limit (more than " +
+                        std::to_string(max_candidates_per_source()) +
+                        " candidate targets within the cutoff, more than 254 bend vertices, window stack or window "
+                        "count); the results of this call are incomplete");
+    return GSIM_OK;
+}
+
+// Candidate rows and geodesics for every source, device-only.
+gsim_status pairs_device(gsim_ctx *c, MeshState *ms, double cutoff) {
     hipStream_t s = c->stream;
     const int n = ms->n;
     if (n <= 0) return fail(c, GSIM_E_STATE, "no particles on this mesh");
     if (!finite_cutoff(cutoff)) return fail(c, GSIM_E_ARG, "cutoff must be positive and finite");
     DevMesh &m = ms->dm;
+    const int cap = max_candidates_per_source();
+    const bool fp32 = c->prec == GSIM_FP32_MIXED;
+    if (fp32 && 3 * (int64_t)m.nf >= (int64_t(1) << 24))
+        return fail(c, GSIM_E_LIMIT, "FP32-mixed mode packs half-edge ids in 24 bits: mesh too large");
+    // cell grid: cells no smaller than the cutoff, at most 128 per axis
+    PrefilterBufs pb{};
+    double ext = 0.0;
+    for (int d = 0; d < 3; ++d) ext = std::max(ext, m.bbmax[d] - m.bbmin[d]);
+    const double cell = std::max(cutoff, ext / 128.0);
+    int64_t ncell = 1;
+    for (int d = 0; d < 3; ++d) {
+        pb.dims[d] = std::max(1, (int)std::ceil((m.bbmax[d] - m.bbmin[d]) / cell));
+        ncell *= pb.dims[d];
+    }
+    pb.cell = cell;
+    pb.cap_c = cap;
+    HIPCHK(c, ensure(ms->cell_of, sizeof(int32_t) * n));
+    HIPCHK(c, ensure(ms->cell_start, sizeof(int32_t) * (ncell + 1)));
+    HIPCHK(c, ensure(ms->cell_fill, sizeof(int32_t) * ncell));
+    HIPCHK(c, ensure(ms->order, sizeof(int32_t) * n));
+    HIPCHK(c, ensure(ms->cand_cnt, sizeof(int32_t) * (n + 1)));
+    HIPCHK(c, ensure(ms->cand, sizeof(int32_t) * (size_t)n * cap));
+    HIPCHK(c, ensure(ms->cdist, sizeof(double) * (size_t)n * cap));
+    HIPCHK(c, ensure(ms->ctan, sizeof(double) * 3 * (size_t)n * cap));
+    HIPCHK(c, ensure(ms->cflags, (size_t)n * cap));
+    HIPCHK(c, ensure(ms->tmp64, sizeof(int64_t) * (std::max<int64_t>(ncell, n) + 1)));
+    HIPCHK(c, ensure(c->scan_scratch, sizeof(int64_t) * ((std::max<int64_t>(ncell, n) + 1023) / 1024 + 2)));
+    GeoParams gp = c->gp;
+    gp.cutoff = cutoff;
+    if (!(gp.launch_delta > 0.0)) gp.launch_delta = 0.5 * m.mean_edge;
+    const int32_t nslots = std::min<int32_t>(n, c->max_slots);
+    HIPCHK(c, ensure(c->stack, (size_t)nslots * gp.stack_cap * 64));
+    if (c->profile_sources && c->prof_n != n) {
+        HIPCHK(c, ensure(c->prof, sizeof(long long) * 4 * (size_t)n));
+        HIPCHK(c, launch_zero_u64(P<unsigned long long>(c->prof), 4 * (int64_t)n, s));
+        c->prof_n = n;
+    }
+    pb.xyz = ms->xyz;
+    pb.cell_of = P<int32_t>(ms->cell_of);
+    pb.cell_start = P<int32_t>(ms->cell_start);
+    pb.cell_fill = P<int32_t>(ms->cell_fill);
+    pb.order = P<int32_t>(ms->order);
+    pb.cand_cnt = P<int32_t>(ms->cand_cnt);
+    pb.cand = P<int32_t>(ms->cand);
     {
         Stage st(c, "prefilter");
         HIPCHK(c, launch_xyz(m, n, ms->face, ms->bary, ms->xyz, s));
-        // cell grid: cells no smaller than the cutoff, at most 128 per axis
-        PrefilterBufs pb{};
-        double ext = 0.0;
-        for (int d = 0; d < 3; ++d) ext = std::max(ext, m.bbmax[d] - m.bbmin[d]);
-        double cell = std::max(cutoff, ext / 128.0);
-        int64_t ncell = 1;
-        for (int d = 0; d < 3; ++d) {
-            pb.dims[d] = std::max(1, (int)std::ceil((m.bbmax[d] - m.bbmin[d]) / cell));
-            ncell *= pb.dims[d];
-        }
-        pb.cell = cell;
-        HIPCHK(c, ensure(ms->cell_of, sizeof(int32_t) * n));
-        HIPCHK(c, ensure(ms->cell_start, sizeof(int32_t) * (ncell + 1)));
-        HIPCHK(c, ensure(ms->cell_fill, sizeof(int32_t) * ncell));
-        HIPCHK(c, ensure(ms->order, sizeof(int32_t) * n));
-        HIPCHK(c, ensure(ms->cand_cnt, sizeof(int32_t) * (n + 1)));
-        HIPCHK(c, ensure(ms->cand_off, sizeof(int64_t) * (n + 1)));
-        HIPCHK(c, ensure(ms->tmp64, sizeof(int64_t) * (std::max<int64_t>(ncell, n) + 1)));
-        size_t nb = (std::max<int64_t>(ncell, n) + 1023) / 1024 + 2;
-        HIPCHK(c, ensure(c->scan_scratch, sizeof(int64_t) * nb));
-        pb.xyz = ms->xyz;
-        pb.cell_of = P<int32_t>(ms->cell_of);
-        pb.cell_start = P<int32_t>(ms->cell_start);
-        pb.cell_fill = P<int32_t>(ms->cell_fill);
-        pb.order = P<int32_t>(ms->order);
-        pb.cand_cnt = P<int32_t>(ms->cand_cnt);
-        pb.cand_off = P<int64_t>(ms->cand_off);
         HIPCHK(c, launch_prefilter_bin(m, n, pb, s));
         HIPCHK(c, launch_scan_i32_to_i64(pb.cell_fill, P<int64_t>(ms->tmp64), (int)ncell, P<int64_t>(c->scan_scratch), s));
         HIPCHK(c, launch_i64_to_i32(P<int64_t>(ms->tmp64), pb.cell_start, (int)ncell, s));
         HIPCHK(c, launch_zero_i32(pb.cell_fill, ncell, s));
         HIPCHK(c, launch_bin_scatter(n, pb, s));
-        HIPCHK(c, launch_prefilter_count(n, cutoff, pb, s));
-        HIPCHK(c, launch_scan_i32_to_i64(pb.cand_cnt, pb.cand_off, n, P<int64_t>(c->scan_scratch), s));
-        int64_t total = 0;
-        HIPCHK(c, hipMemcpyAsync(&total, pb.cand_off + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        HIPCHK(c, hipStreamSynchronize(s));
-        ms->n_cand = total;
-        HIPCHK(c, ensure(ms->cand, sizeof(int32_t) * (total + 1)));
-        pb.cand = P<int32_t>(ms->cand);
-        pb.cand_cap = total;
-        HIPCHK(c, launch_prefilter_fill(n, cutoff, pb, s));
-        HIPCHK(c, ensure(ms->cdist, sizeof(double) * (total + 1)));
-        HIPCHK(c, ensure(ms->ctan, sizeof(double) * 3 * (total + 1)));
-        HIPCHK(c, ensure(ms->cflags, total + 1));
-        ms->owned.clear();
+        HIPCHK(c, launch_prefilter_rows(n, cutoff, pb, P<int32_t>(c->pf_over), s));
     }
+    HIPCHK(c, launch_zero_i32(P<int32_t>(c->work), 16, s));
+    GeoOut out{P<double>(ms->cdist), P<double>(ms->ctan), P<uint8_t>(ms->cflags)};
     {
-        PrefilterBufs pb{};
-        pb.cand_off = P<int64_t>(ms->cand_off);
-        pb.cand = P<int32_t>(ms->cand);
-        pb.order = P<int32_t>(ms->order);
-        GeoParams gp = c->gp;
-        gp.cutoff = cutoff;
-        if (!(gp.launch_delta > 0.0)) gp.launch_delta = 0.5 * m.mean_edge;
-        int32_t nslots = std::min<int32_t>(n, c->max_slots);
-        const bool fp32 = c->prec == GSIM_FP32_MIXED;
-        if (fp32 && 3 * (int64_t)m.nf >= (int64_t(1) << 24))
-            return fail(c, GSIM_E_LIMIT, "FP32-mixed mode packs half-edge ids in 24 bits: mesh too large");
-        HIPCHK(c, ensure(c->stack, (size_t)nslots * gp.stack_cap * window_record_bytes(false)));
-        HIPCHK(c, ensure(ms->guard, (size_t)n + 4));
-        HIPCHK(c, launch_zero_i32(P<int32_t>(c->work), 16, s));
-        HIPCHK(c, launch_zero_u64(P<unsigned long long>(c->ctr), 8, s));
-        if (fp32) HIPCHK(c, launch_zero_i32(P<int32_t>(ms->guard), (n + 3) / 4, s));
-        GeoOut out{P<double>(ms->cdist), P<double>(ms->ctan), P<uint8_t>(ms->cflags)};
-        {
-            Stage st(c, "geodesic");
-            HIPCHK(c, launch_geodesic(m, n, ms->face, ms->bary, ms->xyz, pb, gp, out, P<char>(c->stack), nslots,
-                                      P<int32_t>(c->work), P<Counters>(c->ctr), fp32, P<uint8_t>(ms->guard), false,
-                                      s));
-        }
-        if (fp32) {
-            // FP64 recompute of every source with a pair inside the guard band
-            Stage st(c, "geodesic_guard");
-            HIPCHK(c, launch_geodesic(m, n, ms->face, ms->bary, ms->xyz, pb, gp, out, P<char>(c->stack), nslots,
-                                      P<int32_t>(c->work) + 8, P<Counters>(c->ctr), false, P<uint8_t>(ms->guard),
-                                      true, s));
-        }
+        Stage st(c, "geodesic");
+        HIPCHK(c, launch_geodesic(m, n, ms->face, ms->bary, ms->xyz, pb.cand_cnt, pb.cand, cap, pb.order, gp, out,
+                                  P<char>(c->stack), nslots, P<int32_t>(c->work), P<Counters>(c->ctr), fp32,
+                                  c->profile_sources ? P<long long>(c->prof) : nullptr, s));
     }
-    {
-        Stage st(c, "compact");
-        HIPCHK(c, ensure(ms->nbr_cnt, sizeof(int32_t) * (n + 1)));
-        HIPCHK(c, ensure(ms->off, sizeof(int64_t) * (n + 1)));
-        HIPCHK(c, launch_count_nbrs(n, P<int64_t>(ms->cand_off), P<double>(ms->cdist), cutoff, P<int32_t>(ms->nbr_cnt), s));
-        HIPCHK(c, launch_scan_i32_to_i64(P<int32_t>(ms->nbr_cnt), P<int64_t>(ms->off), n, P<int64_t>(c->scan_scratch), s));
-        int64_t total = 0;
-        HIPCHK(c, hipMemcpyAsync(&total, P<int64_t>(ms->off) + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
-        HIPCHK(c, hipMemcpyAsync(&c->last, c->ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, s));
-        HIPCHK(c, hipStreamSynchronize(s));
-        ms->n_pairs = total;
-        HIPCHK(c, ensure(ms->nbr, sizeof(int32_t) * (total + 1)));
-        HIPCHK(c, ensure(ms->dist, sizeof(double) * (total + 1)));
-        HIPCHK(c, ensure(ms->tan, sizeof(double) * 3 * (total + 1)));
-        HIPCHK(c, ensure(ms->flags, total + 1));
-        HIPCHK(c, launch_compact(n, P<int64_t>(ms->cand_off), P<int32_t>(ms->cand), P<double>(ms->cdist),
-                                 P<double>(ms->ctan), P<uint8_t>(ms->cflags), cutoff, P<int64_t>(ms->off),
-                                 P<int32_t>(ms->nbr), P<double>(ms->dist), P<double>(ms->tan), P<uint8_t>(ms->flags), s));
-    }
-    c->last.cand_pairs = (unsigned long long)ms->n_cand;
-    c->last.nbr_pairs = (unsigned long long)ms->n_pairs;
-    c->cum_pairs += c->last.nbr_pairs;
-    c->cum_windows += c->last.windows;
-    c->cum_passes += 1;
     ms->pairs_cutoff = cutoff;
-    ms->pairs_valid = true;
-    if (c->last.limited) {
-        ms->pairs_valid = false;
-        return fail(c, GSIM_E_LIMIT,
-                    std::to_string(c->last.limited) +
-                        " source(s) exceeded a per-source limit (candidates > 128, bend vertices > 256, window "
-                        "stack or window count)");
-    }
+    c->passes++;
     return GSIM_OK;
 }
 
-template <class T>
-hipError_t upload(T *&dst, const T *src, size_t count, hipStream_t s) {
-    hipError_t e = hipMalloc(&dst, sizeof(T) * std::max<size_t>(count, 1));
-    if (e != hipSuccess) return e;
-    if (count) e = hipMemcpyAsync(dst, src, sizeof(T) * count, hipMemcpyHostToDevice, s);
-    return e;
+// Compact the candidate rows into the caller-facing CSR (host sync for the size).
+gsim_status compact_pairs(gsim_ctx *c, MeshState *ms, double cutoff) {
+    hipStream_t s = c->stream;
+    const int n = ms->n, cap = max_candidates_per_source();
+    Stage st(c, "compact");
+    HIPCHK(c, ensure(ms->nbr_cnt, sizeof(int32_t) * (n + 1)));
+    HIPCHK(c, ensure(ms->off, sizeof(int64_t) * (n + 1)));
+    HIPCHK(c, launch_count_rows(n, P<int32_t>(ms->cand_cnt), cap, P<double>(ms->cdist), cutoff, P<int32_t>(ms->nbr_cnt), s));
+    HIPCHK(c, launch_scan_i32_to_i64(P<int32_t>(ms->nbr_cnt), P<int64_t>(ms->off), n, P<int64_t>(c->scan_scratch), s));
+    int64_t total = 0;
+    HIPCHK(c, hipMemcpyAsync(&total, P<int64_t>(ms->off) + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    ms->n_pairs = total;
+    HIPCHK(c, ensure(ms->nbr, sizeof(int32_t) * (total + 1)));
+    HIPCHK(c, ensure(ms->dist, sizeof(double) * (total + 1)));
+    HIPCHK(c, ensure(ms->tan, sizeof(double) * 3 * (total + 1)));
+    HIPCHK(c, ensure(ms->flags, total + 1));
+    HIPCHK(c, launch_compact_rows(n, P<int32_t>(ms->cand_cnt), cap, P<int32_t>(ms->cand), P<double>(ms->cdist),
+                                  P<double>(ms->ctan), P<uint8_t>(ms->cflags), cutoff, P<int64_t>(ms->off),
+                                  P<int32_t>(ms->nbr), P<double>(ms->dist), P<double>(ms->tan), P<uint8_t>(ms->flags),
+                                  s));
+    return GSIM_OK;
 }
 
 int pot_kind_ok(const gsim_potential *p) { return p && p->kind >= 0 && p->kind <= 2; }
@@ -302,10 +299,19 @@ gsim_status run_forces(gsim_ctx *c, MeshState *ms, const gsim_potential *pot) {
     HIPCHK(c, ensure(ms->E, sizeof(double) * 4));
     HIPCHK(c, ensure(c->sum_scratch, sizeof(double) * ((n + 255) / 256 + 2)));
     Stage st(c, "forces");
-    HIPCHK(c, launch_forces(n, P<int64_t>(ms->off), P<double>(ms->dist), P<double>(ms->tan), pot->kind, pot->k,
-                            pot->sigma, P<double>(ms->F), P<double>(ms->Ei), c->stream));
+    HIPCHK(c, launch_forces_rows(n, P<int32_t>(ms->cand_cnt), max_candidates_per_source(), P<double>(ms->cdist),
+                                 P<double>(ms->ctan), pot->cutoff, pot->kind, pot->k, pot->sigma, P<double>(ms->F),
+                                 P<double>(ms->Ei), &P<Counters>(c->ctr)->nbr_pairs, c->stream));
     HIPCHK(c, launch_sum(P<double>(ms->Ei), n, P<double>(ms->E), P<double>(c->sum_scratch), c->stream));
     return GSIM_OK;
+}
+
+template <class T>
+hipError_t upload(T *&dst, const T *src, size_t count, hipStream_t s) {
+    hipError_t e = hipMalloc(&dst, sizeof(T) * std::max<size_t>(count, 1));
+    if (e != hipSuccess) return e;
+    if (count) e = hipMemcpyAsync(dst, src, sizeof(T) * count, hipMemcpyHostToDevice, s);
+    return e;
 }
 
 }  // namespace
@@ -335,15 +341,20 @@ gsim_status gsim_create(int device, gsim_precision prec, void *hip_stream, gsim_
         c->own_stream = true;
     }
     c->gp.cutoff = 0.0;
-    c->gp.launch_delta = 0.0;  // 0 = half the mean edge length
-    c->gp.cone_tol = prec == GSIM_FP64 ? 1e-12 : 1e-5;
-    c->gp.tie_rel = prec == GSIM_FP64 ? 1e-9 : 1e-4;
+    c->gp.launch_delta = 1e300;  // one bucket: every improved bend vertex once the stack drains
+    c->gp.cone_tol = 1e-12;
+    c->gp.tie_rel = 1e-9;
     c->gp.guard_rel = 1e-4;
-    c->gp.tie_dir = prec == GSIM_FP64 ? 1e-6 : 5e-6;
-    c->gp.stack_cap = 4096;
+    c->gp.tie_dir = 1e-6;
+    c->gp.cone_tol32 = 1e-5;
+    c->gp.tie_rel32 = 1e-4;
+    c->gp.tie_dir32 = 5e-6;
+    c->gp.eager = 0;
+    c->gp.stack_cap = 2048;
     c->gp.max_windows = 4000000;
     if (ensure(c->work, sizeof(int32_t) * 16) != hipSuccess || ensure(c->ctr, sizeof(Counters)) != hipSuccess ||
-        ensure(c->wstats, sizeof(unsigned long long) * 8) != hipSuccess) {
+        ensure(c->wstats, sizeof(unsigned long long) * 8) != hipSuccess ||
+        ensure(c->pf_over, sizeof(int32_t) * 4) != hipSuccess) {
         gsim_destroy(c);
         return GSIM_E_OOM;
     }
@@ -372,7 +383,9 @@ void gsim_destroy(gsim_ctx *c) {
             if (p) (void)hipFree(p);
         delete ms;
     }
-    for (Buf *b : {&c->stack, &c->work, &c->ctr, &c->wstats, &c->scan_scratch, &c->sum_scratch}) release(*b);
+    for (Buf *b : {&c->stack, &c->work, &c->ctr, &c->wstats, &c->scan_scratch, &c->sum_scratch, &c->pf_over,
+                   &c->prof})
+        release(*b);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -547,8 +560,13 @@ gsim_status gsim_geodesic_pairs(gsim_ctx *c, int32_t id, double cutoff, gsim_pai
     MeshState *ms = get_mesh(c, id);
     if (!ms || !out) return fail(c, GSIM_E_ARG, "bad arguments");
     try {
-        gsim_status st = run_pairs(c, ms, cutoff);
-        if (st != GSIM_OK) return st;
+        gsim_status st;
+        if ((st = begin_call(c)) != GSIM_OK) return st;
+        if ((st = pairs_device(c, ms, cutoff)) != GSIM_OK) return st;
+        if ((st = compact_pairs(c, ms, cutoff)) != GSIM_OK) return st;
+        if ((st = end_call(c)) != GSIM_OK) return st;
+        c->last.nbr_pairs = (unsigned long long)ms->n_pairs;
+        c->cum_pairs += c->last.nbr_pairs;
         out->count = ms->n_pairs;
         if (out->capacity < ms->n_pairs || !out->off || (ms->n_pairs && (!out->nbr || !out->dist || !out->tan)))
             return fail(c, GSIM_E_CAPACITY, "pair buffers too small: " + std::to_string(ms->n_pairs) + " needed");
@@ -572,9 +590,11 @@ gsim_status gsim_compute_forces(gsim_ctx *c, int32_t id, const gsim_potential *p
     MeshState *ms = get_mesh(c, id);
     if (!ms || !pot_kind_ok(pot) || !force) return fail(c, GSIM_E_ARG, "bad arguments");
     try {
-        gsim_status st = run_pairs(c, ms, pot->cutoff);
-        if (st != GSIM_OK) return st;
+        gsim_status st;
+        if ((st = begin_call(c)) != GSIM_OK) return st;
+        if ((st = pairs_device(c, ms, pot->cutoff)) != GSIM_OK) return st;
         if ((st = run_forces(c, ms, pot)) != GSIM_OK) return st;
+        if ((st = end_call(c)) != GSIM_OK) return st;
         hipStream_t s = c->stream;
         HIPCHK(c, hipMemcpyAsync(force, ms->F.p, sizeof(double) * 3 * ms->n, hipMemcpyDeviceToHost, s));
         if (energy) HIPCHK(c, hipMemcpyAsync(energy, ms->E.p, sizeof(double), hipMemcpyDeviceToHost, s));
@@ -627,9 +647,10 @@ gsim_status gsim_step(gsim_ctx *c, int32_t id, const gsim_potential *pot, const 
     try {
         HIPCHK(c, ensure(ms->disp, sizeof(double) * 3 * n));
         HIPCHK(c, ensure(ms->wflags, n));
+        gsim_status st;
+        if ((st = begin_call(c)) != GSIM_OK) return st;
         for (int32_t k = 0; k < nsteps; ++k) {
-            gsim_status st = run_pairs(c, ms, pot->cutoff);
-            if (st != GSIM_OK) return st;
+            if ((st = pairs_device(c, ms, pot->cutoff)) != GSIM_OK) return st;
             if ((st = run_forces(c, ms, pot)) != GSIM_OK) return st;
             {
                 Stage sg(c, "integrate");
@@ -645,7 +666,7 @@ gsim_status gsim_step(gsim_ctx *c, int32_t id, const gsim_potential *pot, const 
             ms->step++;
             ms->pairs_valid = false;
         }
-        return GSIM_OK;
+        return end_call(c);
     } catch (...) {
         return fail(c, GSIM_E_ARG, "unexpected host error");
     }
@@ -683,11 +704,27 @@ gsim_status gsim_tune_set(gsim_ctx *c, const char *name, double value) {
     else if (k == "cone_tol" && value >= 0.0) c->gp.cone_tol = value;
     else if (k == "tie_rel" && value >= 0.0) c->gp.tie_rel = value;
     else if (k == "tie_dir" && value >= 0.0) c->gp.tie_dir = value;
+    else if (k == "eager") c->gp.eager = value != 0.0;
+    else if (k == "cone_tol32" && value >= 0.0) c->gp.cone_tol32 = value;
+    else if (k == "tie_rel32" && value >= 0.0) c->gp.tie_rel32 = value;
+    else if (k == "tie_dir32" && value >= 0.0) c->gp.tie_dir32 = value;
     else if (k == "guard_rel" && value >= 0.0) c->gp.guard_rel = value;
     else if (k == "stack_cap" && value >= 64 && value <= (1 << 22)) c->gp.stack_cap = (int32_t)value;
     else if (k == "max_windows" && value >= 1) c->gp.max_windows = (int32_t)std::min(value, 2.0e9);
     else if (k == "max_slots" && value >= 1 && value <= 65536) c->max_slots = (int)value;
     else return fail(c, GSIM_E_ARG, "unknown tuning knob or value out of range: " + k);
+    return GSIM_OK;
+}
+
+gsim_status gsim_source_profile(gsim_ctx *c, int on, int64_t *out, int32_t n) {
+    if (!c) return GSIM_E_ARG;
+    if (out) {
+        if (!c->profile_sources || n != c->prof_n) return fail(c, GSIM_E_STATE, "source profiling not active");
+        HIPCHK(c, hipMemcpyAsync(out, c->prof.p, sizeof(long long) * 4 * (size_t)n, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    c->profile_sources = on != 0;
+    c->prof_n = 0;
     return GSIM_OK;
 }
 

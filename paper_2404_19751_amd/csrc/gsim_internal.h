@@ -82,10 +82,9 @@ struct PrefilterBufs {
     int32_t *cell_start;  // [ncell+1]
     int32_t *cell_fill;   // [ncell]
     int32_t *order;       // [n] particles sorted by cell
-    int32_t *cand_cnt;    // [n+1] (scan in place -> cand_off)
-    int64_t *cand_off;    // [n+1]
-    int32_t *cand;        // [cap]
-    int64_t cand_cap;
+    int32_t *cand_cnt;    // [n] candidates per source (may exceed cap_c: overflow)
+    int32_t *cand;        // [n][cap_c] candidate rows, sorted by j
+    int cap_c;
     int32_t dims[3];
     double cell;
 };
@@ -97,6 +96,8 @@ struct GeoParams {
     double tie_rel;       // tie gap (relative)
     double tie_dir;       // two candidate tangents closer than this (rad) are the same direction
     double guard_rel;     // FP32 results this close (relative) to the cutoff are recomputed in FP64
+    double cone_tol32, tie_rel32, tie_dir32;  // the FP32 pass's counterparts
+    int32_t eager;        // launch bend vertices as soon as they are found
     int32_t stack_cap;    // windows per stack slot
     int32_t max_windows;  // per-source work limit
 };
@@ -117,28 +118,26 @@ hipError_t launch_xyz(const DevMesh &m, int n, const int32_t *face, const double
 hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t s);
 hipError_t launch_prefilter_bin(const DevMesh &m, int n, PrefilterBufs &b, hipStream_t s);
-hipError_t launch_prefilter_count(int n, double cutoff, PrefilterBufs &b, hipStream_t s);
-hipError_t launch_prefilter_fill(int n, double cutoff, PrefilterBufs &b, hipStream_t s);
 hipError_t launch_scan_i32_to_i64(const int32_t *in, int64_t *out, int n, int64_t *scratch, hipStream_t s);
-hipError_t launch_scan_i32_inplace(int32_t *inout, int n, int32_t *scratch, hipStream_t s);
 
 hipError_t launch_geodesic(const DevMesh &m, int n, const int32_t *face, const double *bary, const double *xyz,
-                           const PrefilterBufs &pb, const GeoParams &gp, GeoOut out, char *stack_mem,
-                           int32_t nslots, int32_t *work_ctr, Counters *ctr, bool fp32, uint8_t *guard,
-                           bool guard_pass, hipStream_t s);
+                           const int32_t *cand_cnt, const int32_t *cand, int cap_c, const int32_t *order,
+                           const GeoParams &gp, GeoOut out, char *stack_mem, int32_t nslots, int32_t *work_ctr,
+                           Counters *ctr, bool fp32, long long *prof, hipStream_t s);
+int max_candidates_per_source();
 
 hipError_t launch_bin_scatter(int n, PrefilterBufs &b, hipStream_t s);
 hipError_t launch_i64_to_i32(const int64_t *in, int32_t *out, int n, hipStream_t s);
-size_t window_record_bytes(bool fp32);
 
-hipError_t launch_count_nbrs(int n, const int64_t *cand_off, const double *dist, double cutoff, int32_t *cnt,
+hipError_t launch_prefilter_rows(int n, double cutoff, PrefilterBufs &b, int32_t *overflow, hipStream_t s);
+hipError_t launch_count_rows(int n, const int32_t *cnt, int cap_c, const double *dist, double cutoff, int32_t *out,
                              hipStream_t s);
-hipError_t launch_compact(int n, const int64_t *cand_off, const int32_t *cand, const double *dist,
-                          const double *tan, const uint8_t *flags, double cutoff, const int64_t *off,
-                          int32_t *nbr, double *odist, double *otan, uint8_t *oflags, hipStream_t s);
-
-hipError_t launch_forces(int n, const int64_t *off, const double *dist, const double *tan, int kind, double k,
-                         double sigma, double *F, double *Ei, hipStream_t s);
+hipError_t launch_compact_rows(int n, const int32_t *cnt, int cap_c, const int32_t *cand, const double *dist,
+                               const double *tan, const uint8_t *flags, double cutoff, const int64_t *off,
+                               int32_t *nbr, double *odist, double *otan, uint8_t *oflags, hipStream_t s);
+hipError_t launch_forces_rows(int n, const int32_t *cnt, int cap_c, const double *dist, const double *tan,
+                              double cutoff, int kind, double k, double sigma, double *F, double *Ei,
+                              unsigned long long *npairs, hipStream_t s);
 hipError_t launch_sum(const double *x, int n, double *out, double *scratch, hipStream_t s);
 hipError_t launch_integrate(const DevMesh &m, int n, const int32_t *face, const double *F, int kind, double dt,
                             double mobility, double kT, double friction, uint64_t seed, uint64_t step,

@@ -9,37 +9,39 @@
 // unfolds face(h)'s third vertex C, queries the targets in face(h), offers C
 // as a bend vertex, and emits at most two child windows on the far edges.
 //
-// Pruning (both exact for every pair closer than the cutoff):
+// Pruning (all exact for every pair closer than the cutoff):
 //  - the paper's submeshing by the Euclidean lower bound (Sec. 3.1), done
 //    implicitly: a window is dropped once sg + dist(p, interval) reaches the
 //    cutoff;
 //  - target-directed: any path through a window to target j has length at
 //    least sg + dist(p, interval) + |X - x_j| for the 3D crossing point X on
-//    the window's edge slice, so a window is dropped when that bound reaches
-//    the cutoff for every candidate target. A bend vertex found only through
-//    dropped windows can only lead to pairs at or beyond the cutoff.
+//    the window's edge slice. A window is dropped when that bound reaches,
+//    for every candidate target, the cutoff or the target's best distance so
+//    far (widened by the tie gap so second-best directions are still seen).
+//    A bend vertex reached only through dropped windows can only lead to
+//    pairs that are beyond the cutoff or already matched.
 //
-// Bend vertices (pseudo-sources) are re-rooted in distance buckets: whenever
-// no window is left, every bend vertex whose distance improved since its last
-// launch and lies within `launch_delta` of the smallest such distance is
-// launched (a full fan of windows, sg = its distance). Windows of a root
+// Bend vertices (pseudo-sources) are launched as a full fan of windows with
+// sg = their distance, either as soon as they are found or improved (eager)
+// or when no window is left (bucketed by `launch_delta`). Windows of a root
 // whose distance improved after they were made are stale and dropped. The
-// last launch of every bend vertex carries its final distance, and the
-// optimal chain's windows all have lower bounds below the pair distance, so
+// last launch of every bend vertex carries its final distance, so the
 // processing order changes only the amount of work.
 //
 // Precision: FP64 throughout, or FP32 windows (half the register, stack and
 // record bytes) with the child-interval endpoint intersections computed in
 // FP64; a source with any pair within the guard band of the cutoff is then
-// recomputed by the FP64 kernel so neighbour sets stay exact.
+// recomputed at once in FP64 by the same wavefront, so neighbour sets stay
+// exact.
 //
-// Mapping to CDNA4: one wavefront per source (persistent grid, sources in
+// Mapping to CDNA4: one wavefront per source (persistent grid; sources in
 // spatial cell order from eight per-XCD work chunks so each XCD's L2 serves
 // one region of the mesh); each lane holds one live window in registers; a
-// lane with two children keeps one and pushes the other onto the source's
-// window stack with a ballot/popcount compaction; idle lanes pop. Target and
-// bend-vertex tables live in LDS; their updates are serialised across lanes
-// by a ballot loop (no atomics, deterministic in wave order).
+// lane with two children keeps one and pushes the other onto an LDS window
+// stack (ballot/popcount compaction; a per-wave global overflow area takes
+// what does not fit); idle lanes pop. Target and bend-vertex tables live in
+// LDS; their updates are serialised across lanes by a ballot loop (no
+// atomics, deterministic in wave order).
 #include <cmath>
 
 #include "gsim_internal.h"
@@ -53,8 +55,8 @@ constexpr int kHash = 256;
 // bend-vertex table: 255 slots so that slot + 1 fits the 8 bits the FP32
 // stack record keeps for it
 constexpr int kRootCap = 255;
-constexpr int kRootMax = 255;
 constexpr int kChunks = 8;
+constexpr int kStackBytes = 16384;
 
 template <typename R>
 struct Win {
@@ -69,7 +71,7 @@ struct Rec64 {
 };
 struct Rec32 {
     float v[7];
-    uint32_t hr;  // (he << 8) | (root + 1)
+    uint32_t hr;  // (he << 8) | (root + 1), root + 1 in [0, kRootCap]
 };
 static_assert(sizeof(Rec64) == 64 && sizeof(Rec32) == 32, "stack record sizes");
 template <typename R>
@@ -95,7 +97,7 @@ __device__ inline void load_rec(const Rec64 &q, Win<double> &w) {
 }
 __device__ inline void store_rec(Rec32 &q, const Win<float> &w) {
     q.v[0] = w.px; q.v[1] = w.py; q.v[2] = w.b0; q.v[3] = w.b1; q.v[4] = w.sg; q.v[5] = w.c; q.v[6] = w.s;
-    q.hr = ((uint32_t)w.he << 8) | (uint32_t)(w.root + 1);  // root + 1 in [0, kRootCap] < 256
+    q.hr = ((uint32_t)w.he << 8) | (uint32_t)(w.root + 1);
 }
 __device__ inline void load_rec(const Rec32 &q, Win<float> &w) {
     w.px = q.v[0]; w.py = q.v[1]; w.b0 = q.v[2]; w.b1 = q.v[3]; w.sg = q.v[4]; w.c = q.v[5]; w.s = q.v[6];
@@ -125,16 +127,16 @@ struct GeoArgs {
     const int32_t *face;
     const double *bary;
     const double *xyz;
-    const int64_t *cand_off;
-    const int32_t *cand;
+    const int32_t *cand_cnt;  // [n]
+    const int32_t *cand;      // [n][cap_c], each row sorted by j
+    int cap_c;
     const int32_t *order;
     GeoParams gp;
-    GeoOut out;
-    void *stack;
+    GeoOut out;               // [n][cap_c] rows
+    void *stack;              // per wave: stack_cap records of 64 bytes
     int32_t *work;
     Counters *ctr;
-    uint8_t *guard;   // per source: FP32 pass marks, FP64 pass consumes
-    int guard_pass;   // 1: FP64 recompute of marked sources only
+    long long *prof;  // optional [n][4]: cycles, loop iterations, windows, launches per source
 };
 
 struct Lds {
@@ -143,9 +145,12 @@ struct Lds {
     double tx3[kMaxCand][3];
     double d1[kMaxCand], d2[kMaxCand], t1x[kMaxCand], t1y[kMaxCand];
     int32_t head[kHash];
-    int32_t rkey[kRootCap];
+    int32_t rkey[kRootCap + 1];
     double rD[kRootCap], rL[kRootCap], rtx[kRootCap], rty[kRootCap];
-    int32_t rcount;
+    int32_t rcount, dirty;
+    int32_t sel[kRootCap + 1];   // launch list: root slots
+    int32_t pref[kRootCap + 2];  // prefix sums of their fan sizes
+    alignas(16) unsigned char stk[kStackBytes];
 };
 
 __device__ inline int lane_id() { return threadIdx.x; }
@@ -175,34 +180,42 @@ __device__ inline int next_in_face(const Lds &L, int s, int f) {
     return s;
 }
 
-// Does any candidate target lie within `rem` (3D) of the edge slice
-// P + x u, x in [x0, x1]? (rem <= 0: no.)
-__device__ inline bool reaches_target(const Lds &L, int nc, const double P[3], const double u[3], double x0,
-                                      double x1, double rem) {
-    if (!(rem > 0.0)) return false;
-    const double r2 = rem * rem;
-    for (int s = 0; s < nc; ++s) {
+// Per-source constants shared by the helpers.
+struct Ctx {
+    double cutoff, cut_acc, lb_slack, tol, tie_rel, tie_dir;
+    int nc;
+};
+
+// Could a path of length `base` to the edge slice P + x u (x in [x0, x1])
+// still improve some candidate target? (3D distance as the lower bound of
+// the rest of the path.)
+__device__ inline bool reaches_target(const Lds &L, const Ctx &C, const double P[3], const double u[3], double x0,
+                                      double x1, double base) {
+    for (int s = 0; s < C.nc; ++s) {
+        const double bound = fmin(C.cut_acc, L.d1[s] * (1.0 + C.tie_rel) + C.lb_slack);
+        const double rem = bound - base;
+        if (!(rem > 0.0)) continue;
         double q0 = L.tx3[s][0] - P[0], q1 = L.tx3[s][1] - P[1], q2 = L.tx3[s][2] - P[2];
         double t = q0 * u[0] + q1 * u[1] + q2 * u[2];
         t = fmin(fmax(t, x0), x1);
         q0 -= t * u[0];
         q1 -= t * u[1];
         q2 -= t * u[2];
-        if (q0 * q0 + q1 * q1 + q2 * q2 < r2) return true;
+        if (q0 * q0 + q1 * q1 + q2 * q2 < rem * rem) return true;
     }
     return false;
 }
 
 // Serialised target update: best distance, its tangent, and the best
 // distance among candidates whose direction differs (tie gap).
-__device__ inline void target_update(Lds &L, bool ok, int slot, double d, double tx, double ty, double dir_tol) {
+__device__ inline void target_update(Lds &L, const Ctx &C, bool ok, int slot, double d, double tx, double ty) {
     uint64_t m = __ballot(ok);
     while (m) {
         int l = __ffsll((unsigned long long)m) - 1;
         if (lane_id() == l) {
             double c1 = L.d1[slot];
             double ax = L.t1x[slot], ay = L.t1y[slot];
-            bool differ = !(c1 < INFINITY) || fabs(ax * ty - ay * tx) > dir_tol || ax * tx + ay * ty < 0.0;
+            bool differ = !(c1 < INFINITY) || fabs(ax * ty - ay * tx) > C.tie_dir || ax * tx + ay * ty < 0.0;
             if (d < c1) {
                 if (differ) L.d2[slot] = fmin(L.d2[slot], c1);
                 L.d1[slot] = d;
@@ -216,7 +229,7 @@ __device__ inline void target_update(Lds &L, bool ok, int slot, double d, double
     }
 }
 
-// Serialised bend-vertex update (insert or improve).
+// Serialised bend-vertex update (insert or improve); marks the table dirty.
 __device__ inline void root_update(Lds &L, bool ok, int v, double d, double tx, double ty, bool &overflow) {
     uint64_t m = __ballot(ok);
     while (m) {
@@ -227,7 +240,7 @@ __device__ inline void root_update(Lds &L, bool ok, int v, double d, double tx, 
                 e = e + 1 == kRootCap ? 0 : e + 1;
                 ++probes;
             }
-            if (probes >= kRootCap || (L.rkey[e] < 0 && L.rcount >= kRootMax - 1)) {
+            if (probes >= kRootCap || (L.rkey[e] < 0 && L.rcount >= kRootCap - 1)) {
                 overflow = true;
             } else if (L.rkey[e] < 0) {
                 L.rkey[e] = v;
@@ -236,29 +249,70 @@ __device__ inline void root_update(Lds &L, bool ok, int v, double d, double tx, 
                 L.rtx[e] = tx;
                 L.rty[e] = ty;
                 L.rcount++;
+                L.dirty = 1;
             } else if (d < L.rD[e]) {
                 L.rD[e] = d;
                 L.rtx[e] = tx;
                 L.rty[e] = ty;
+                L.dirty = 1;
             }
         }
         m &= m - 1;
     }
 }
 
-template <typename Rec, typename R>
-__device__ inline void push_windows(Rec *stk, int &sp, int cap, bool want, const Win<R> &w, bool &overflow) {
-    uint64_t m = __ballot(want);
-    int cnt = __popcll(m);
-    if (!cnt) return;
-    int r = __popcll(m & lanemask_lt());
-    if (want) {
-        int pos = sp + r;
-        if (pos < cap) store_rec(stk[pos], w);
-        else overflow = true;
+// Two-level window stack: LDS first, a per-wave global area for overflow.
+template <typename R>
+struct Stack {
+    using Rec = typename RecOf<R>::T;
+    static constexpr int kL = kStackBytes / (int)sizeof(Rec);
+    Rec *lds;
+    Rec *glb;
+    int gcap;
+    int lsp, gsp;
+
+    __device__ void push(bool want, const Win<R> &w, bool &overflow) {
+        uint64_t m = __ballot(want);
+        int cnt = __popcll(m);
+        if (!cnt) return;
+        int r = __popcll(m & lanemask_lt());
+        int space = kL - lsp;
+        if (want) {
+            if (r < space) {
+                store_rec(lds[lsp + r], w);
+            } else {
+                int pos = gsp + (r - space);
+                if (pos < gcap) store_rec(glb[pos], w);
+                else overflow = true;
+            }
+        }
+        int to_l = min(cnt, space);
+        lsp += to_l;
+        gsp = min(gsp + (cnt - to_l), gcap);
     }
-    sp = min(sp + cnt, cap);
-}
+    // refill lanes without a window; returns whether any lane holds one
+    __device__ bool refill(bool &have, Win<R> &w) {
+        uint64_t need = __ballot(!have);
+        int nneed = __popcll(need);
+        int r = __popcll(need & lanemask_lt());
+        int take_l = min(nneed, lsp);
+        if (!have && r < take_l) {
+            load_rec(lds[lsp - 1 - r], w);
+            have = true;
+        }
+        lsp -= take_l;
+        if (nneed > take_l && gsp > 0) {
+            __syncthreads();  // make earlier global pushes of other lanes visible
+            int take_g = min(nneed - take_l, gsp);
+            if (!have && r >= take_l && r < take_l + take_g) {
+                load_rec(glb[gsp - 1 - (r - take_l)], w);
+                have = true;
+            }
+            gsp -= take_g;
+        }
+        return __ballot(have) != 0;
+    }
+};
 
 // Child intervals. Left child: across C->A (stored on tp, frame origin A,
 // x towards C). Right child: across B->C (stored on tn, frame origin C, x
@@ -294,9 +348,9 @@ __device__ inline void child_right(const He<R> &h, const Win<R> &w, double txc, 
 // Both children of a window. F3: the face's vertices in 3D in the order
 // (A, B, C) = (tail, head, opposite) of the entry half-edge.
 template <typename R>
-__device__ inline void children(const He<R> &h, const Win<R> &w, double txc, bool full, double cutoff,
-                                const double F3[3][3], const Lds &L, int nc, double lb_slack, Win<R> &cl, bool &hl,
-                                Win<R> &cr, bool &hr, int &pruned) {
+__device__ inline void children(const He<R> &h, const Win<R> &w, double txc, bool full, const Ctx &C,
+                                const double F3[3][3], const Lds &L, Win<R> &cl, bool &hl, Win<R> &cr, bool &hr,
+                                int &pruned) {
     hl = false;
     hr = false;
     if (h.tp >= 0 && (full || (double)w.b0 < txc)) {
@@ -313,11 +367,11 @@ __device__ inline void children(const He<R> &h, const Win<R> &w, double txc, boo
         cl.he = h.tp;
         cl.root = w.root;
         if (x1 - x0 > 1e-12 * (double)h.Lp) {
-            double rem = cutoff - (double)w.sg - (double)seg_dist(cl.px, cl.py, cl.b0, cl.b1) + lb_slack;
+            double base = (double)w.sg + (double)seg_dist(cl.px, cl.py, cl.b0, cl.b1);
             double u[3] = {F3[2][0] - F3[0][0], F3[2][1] - F3[0][1], F3[2][2] - F3[0][2]};
             double il = 1.0 / sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
             u[0] *= il; u[1] *= il; u[2] *= il;
-            if (reaches_target(L, nc, F3[0], u, x0, x1, rem)) hl = true;
+            if (reaches_target(L, C, F3[0], u, x0, x1, base)) hl = true;
             else ++pruned;
         }
     }
@@ -336,11 +390,11 @@ __device__ inline void children(const He<R> &h, const Win<R> &w, double txc, boo
         cr.he = h.tn;
         cr.root = w.root;
         if (x1 - x0 > 1e-12 * (double)h.Ln) {
-            double rem = cutoff - (double)w.sg - (double)seg_dist(cr.px, cr.py, cr.b0, cr.b1) + lb_slack;
+            double base = (double)w.sg + (double)seg_dist(cr.px, cr.py, cr.b0, cr.b1);
             double u[3] = {F3[1][0] - F3[2][0], F3[1][1] - F3[2][1], F3[1][2] - F3[2][2]};
             double il = 1.0 / sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
             u[0] *= il; u[1] *= il; u[2] *= il;
-            if (reaches_target(L, nc, F3[2], u, x0, x1, rem)) hr = true;
+            if (reaches_target(L, C, F3[2], u, x0, x1, base)) hr = true;
             else ++pruned;
         }
     }
@@ -357,25 +411,467 @@ __device__ inline void face_xyz(const DevMesh &m, int f, int k, double F3[3][3])
     }
 }
 
+struct SrcStats {
+    unsigned long long windows, launches, stale;
+    int pruned;
+    bool overflow;
+};
+
+// Launch the dirty bend vertices (distance improved since their last
+// launch) within launch_delta of the smallest such distance. The selected
+// roots are compacted into a list and their fans flattened over the lanes,
+// so one launch round costs a few memory round trips, not one per root.
 template <typename R>
-__global__ __launch_bounds__(kWave) void k_geodesic(GeoArgs a) {
-    using Rec = typename RecOf<R>::T;
-    __shared__ Lds L;
+__device__ void launch_roots(const GeoArgs &a, Lds &L, const Ctx &C, Stack<R> &S, SrcStats &st) {
     const int lane = lane_id();
-    const double cutoff = a.gp.cutoff;
+    const HeRec *__restrict__ he = a.m.he;
+    double mn = INFINITY;
+    for (int e = lane; e < kRootCap; e += kWave)
+        if (L.rkey[e] >= 0 && L.rD[e] < L.rL[e] && L.rD[e] < C.cut_acc) mn = fmin(mn, L.rD[e]);
+    mn = wave_min(mn);
+    if (lane == 0) L.dirty = 0;
+    if (!(mn < INFINITY)) return;
+    const double thr = mn + a.gp.launch_delta;
+    // 1. compact the selected roots, mark them launched
+    int nsel = 0;
+    bool left = false;
+    for (int base = 0; base < kRootCap; base += kWave) {
+        const int e = base + lane;
+        const bool cand = e < kRootCap && L.rkey[e] >= 0 && L.rD[e] < L.rL[e] && L.rD[e] < C.cut_acc;
+        const bool sel = cand && L.rD[e] <= thr;
+        left |= cand && !sel;
+        const uint64_t mk = __ballot(sel);
+        if (sel) {
+            L.sel[nsel + __popcll(mk & lanemask_lt())] = e;
+            L.rL[e] = L.rD[e];
+        }
+        nsel += __popcll(mk);
+    }
+    if (__ballot(left) != 0 && lane == 0) L.dirty = 1;
+    // 2. per root: is any target within reach (3D bound), and its fan size
+    int carry = 0;
+    for (int base = 0; base < nsel; base += kWave) {
+        const int k = base + lane;
+        int deg = 0;
+        if (k < nsel) {
+            const int e = L.sel[k], v = L.rkey[e];
+            const double D = L.rD[e];
+            const double vx = a.m.V[3 * (int64_t)v], vy = a.m.V[3 * (int64_t)v + 1], vz = a.m.V[3 * (int64_t)v + 2];
+            bool useful = false;
+            for (int s = 0; s < C.nc && !useful; ++s) {
+                const double bound = fmin(C.cut_acc, L.d1[s] * (1.0 + C.tie_rel) + C.lb_slack) - D;
+                const double q0 = L.tx3[s][0] - vx, q1 = L.tx3[s][1] - vy, q2 = L.tx3[s][2] - vz;
+                useful = bound > 0.0 && q0 * q0 + q1 * q1 + q2 * q2 < bound * bound;
+            }
+            if (useful) deg = a.m.fan_off[v + 1] - a.m.fan_off[v];
+        }
+        // wave-inclusive scan of deg
+        int inc = deg;
+        for (int o = 1; o < kWave; o <<= 1) {
+            const int y = __shfl_up(inc, o);
+            if (lane >= o) inc += y;
+        }
+        if (k < nsel) L.pref[k + 1] = carry + inc;
+        st.launches += (unsigned long long)__popcll(__ballot(deg > 0));
+        carry += __shfl(inc, kWave - 1);
+    }
+    if (lane == 0) L.pref[0] = 0;
+    const int total = carry;
+    // 3. flattened fans: lane <- (root k, fan position)
+    for (int base = 0; base < total; base += kWave) {
+        const int idx = base + lane;
+        const bool act = idx < total;
+        int k = 0;
+        if (act) {
+            int lo = 0, hi = nsel - 1;  // largest k with pref[k] <= idx
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (L.pref[mid] <= idx) lo = mid;
+                else hi = mid - 1;
+            }
+            k = lo;
+        }
+        const int el = act ? L.sel[k] : 0;
+        const int v = act ? L.rkey[el] : 0;
+        const double D = act ? L.rD[el] : 0.0;
+        const double vtx = act ? L.rtx[el] : 0.0, vty = act ? L.rty[el] : 0.0;
+        const int h = act ? a.m.fan[a.m.fan_off[v] + (idx - L.pref[k])] : 0;
+        const int hn = h - h % 3 + (h % 3 + 1) % 3;
+        const HeRec Rh = he[h], Rn = he[hn];
+        Win<R> nw;
+        bool want = false;
+        if (act && Rn.twin >= 0) {
+            // window across the edge opposite v: twin(next(h)) runs u2 -> u1
+            const double px = Rn.L - Rn.cx, py = -Rn.cy;
+            nw.px = (R)px;
+            nw.py = (R)py;
+            nw.b0 = R(0);
+            nw.b1 = (R)Rn.L;
+            nw.sg = (R)D;
+            nw.c = R(1);
+            nw.s = R(0);
+            nw.he = Rn.twin;
+            nw.root = el;
+            double F3[3][3];
+            face_xyz(a.m, h / 3, h % 3, F3);  // (v, u1, u2)
+            double u[3] = {F3[1][0] - F3[2][0], F3[1][1] - F3[2][1], F3[1][2] - F3[2][2]};
+            const double il = 1.0 / Rn.L;
+            u[0] *= il; u[1] *= il; u[2] *= il;
+            want = reaches_target(L, C, F3[2], u, 0.0, Rn.L, D + seg_dist(px, py, 0.0, Rn.L));
+        }
+        // direct targets in face(h)
+        const int g = h / 3;
+        int slot = act ? first_in_face(L, g) : -1;
+        const double *pv = a.m.V + 3 * (int64_t)v;
+        while (__ballot(slot >= 0)) {
+            const bool ok = slot >= 0;
+            double d = 0;
+            if (ok) {
+                const double dx = L.tx3[slot][0] - pv[0], dy = L.tx3[slot][1] - pv[1], dz = L.tx3[slot][2] - pv[2];
+                d = D + sqrt(dx * dx + dy * dy + dz * dz);
+            }
+            target_update(L, C, ok, slot, d, vtx, vty);
+            if (ok) slot = next_in_face(L, slot, g);
+        }
+        // adjacent bend vertices along the two edges at v
+        const int u1 = act ? a.m.T[hn] : 0;  // head of h
+        const bool ok1 = act && (a.m.vflag[u1] & VF_PSEUDO) && D + Rh.L < C.cut_acc;
+        root_update(L, ok1, u1, D + Rh.L, vtx, vty, st.overflow);
+        const int u2 = act ? Rh.opp : 0;
+        const bool ok2 = act && (a.m.vflag[u2] & VF_PSEUDO) && D + Rh.Lp < C.cut_acc;
+        root_update(L, ok2, u2, D + Rh.Lp, vtx, vty, st.overflow);
+        S.push(want, nw, st.overflow);
+    }
+}
+
+// Geodesics from one source to its candidate targets; writes the row and
+// returns whether any pair lies inside the guard band of the cutoff.
+template <typename R>
+__device__ bool run_source(const GeoArgs &a, Lds &L, int src, int64_t c0, int nc, bool guard_mode, int slot_id,
+                           SrcStats &st) {
+    const int lane = lane_id();
+    const long long t_start = clock64();
+    const unsigned long long launches0 = st.launches;
+    long long iters = 0;
     const bool fp32 = sizeof(R) == 4;
+    Ctx C;
+    C.cutoff = a.gp.cutoff;
     // FP32 results may be off by rounding: everything within the guard band
     // above the cutoff is still propagated and recorded, so that pairs near
     // the cutoff are seen and recomputed in FP64
-    const double lb_slack = fp32 ? fmax(1e-4, a.gp.guard_rel) * cutoff : 0.0;
-    const double cut_acc = cutoff + lb_slack;
-    const double tol = a.gp.cone_tol;
+    C.lb_slack = fp32 ? fmax(1e-4, a.gp.guard_rel) * C.cutoff : 0.0;
+    C.cut_acc = C.cutoff + C.lb_slack;
+    C.tol = fp32 ? a.gp.cone_tol32 : a.gp.cone_tol;
+    C.tie_rel = fp32 ? a.gp.tie_rel32 : a.gp.tie_rel;
+    C.tie_dir = fp32 ? a.gp.tie_dir32 : a.gp.tie_dir;
+    C.nc = nc;
     const HeRec *__restrict__ he = a.m.he;
-    Rec *stk = reinterpret_cast<Rec *>(a.stack) + (size_t)blockIdx.x * a.gp.stack_cap;
+    Stack<R> S;
+    S.lds = reinterpret_cast<typename RecOf<R>::T *>(L.stk);
+    S.glb = reinterpret_cast<typename RecOf<R>::T *>(reinterpret_cast<Rec64 *>(a.stack) +
+                                                      (size_t)slot_id * a.gp.stack_cap);
+    S.gcap = fp32 ? 2 * a.gp.stack_cap : a.gp.stack_cap;
+    S.lsp = 0;
+    S.gsp = 0;
+
+    // ---- LDS tables
+    for (int e = lane; e < kHash; e += kWave) L.head[e] = -1;
+    for (int e = lane; e < kRootCap; e += kWave) L.rkey[e] = -1;
+    if (lane == 0) {
+        L.rcount = 0;
+        L.dirty = 0;
+    }
+    __syncthreads();
+    for (int s = lane; s < nc; s += kWave) {
+        int j = a.cand[c0 + s];
+        int f = a.face[j];
+        L.tj[s] = j;
+        L.tface[s] = f;
+        for (int d = 0; d < 3; ++d) {
+            L.tb[s][d] = a.bary[3 * (int64_t)j + d];
+            L.tx3[s][d] = a.xyz[3 * (int64_t)j + d];
+        }
+        L.d1[s] = INFINITY;
+        L.d2[s] = INFINITY;
+        L.t1x[s] = 0.0;
+        L.t1y[s] = 0.0;
+        L.tnext[s] = atomicExch(&L.head[hash_face(f)], s);
+    }
+    __syncthreads();
+
+    bool overflow = false;
+    int pruned = 0;
+
+    // ---- seed from the source (root -1, sg = 0), in FP64
+    const int fs = a.face[src];
+    const double sb[3] = {a.bary[3 * (int64_t)src], a.bary[3 * (int64_t)src + 1], a.bary[3 * (int64_t)src + 2]};
+    const HeRec R0 = he[3 * fs];
+    const double P[3][2] = {{0.0, 0.0}, {R0.L, 0.0}, {R0.cx, R0.cy}};
+    const double sx = sb[1] * P[1][0] + sb[2] * P[2][0], sy = sb[1] * P[1][1] + sb[2] * P[2][1];
+    {
+        int slot = lane < 1 ? first_in_face(L, fs) : -1;
+        while (__ballot(slot >= 0)) {
+            bool ok = slot >= 0;
+            double d = 0, tx = 0, ty = 0;
+            if (ok) {
+                double qx = L.tb[slot][1] * P[1][0] + L.tb[slot][2] * P[2][0];
+                double qy = L.tb[slot][1] * P[1][1] + L.tb[slot][2] * P[2][1];
+                double dx = qx - sx, dy = qy - sy;
+                d = sqrt(dx * dx + dy * dy);
+                if (d > 0.0) {
+                    tx = dx / d;
+                    ty = dy / d;
+                }
+            }
+            target_update(L, C, ok, slot, d, tx, ty);
+            if (ok) slot = next_in_face(L, slot, fs);
+        }
+    }
+    {
+        Win<R> w, wa, wb;
+        bool want = false, wantA = false, wantB = false;
+        bool rok = false;
+        int rv = 0;
+        double rd = 0, rtx = 0, rty = 0;
+        if (lane < 3) {
+            const int k = lane, h = 3 * fs + k;
+            const HeRec Rh = he[h];
+            const double ex = (P[(k + 1) % 3][0] - P[k][0]) / Rh.L, ey = (P[(k + 1) % 3][1] - P[k][1]) / Rh.L;
+            int v = a.m.T[h];
+            if (a.m.vflag[v] & VF_PSEUDO) {
+                double dx = P[k][0] - sx, dy = P[k][1] - sy;
+                rd = sqrt(dx * dx + dy * dy);
+                rok = rd < C.cut_acc;
+                rv = v;
+                rtx = rd > 0 ? dx / rd : 0.0;
+                rty = rd > 0 ? dy / rd : 0.0;
+            }
+            const double hx = sb[(k + 1) % 3] * Rh.L + sb[(k + 2) % 3] * Rh.cx, hy = sb[(k + 2) % 3] * Rh.cy;
+            if (Rh.twin >= 0) {
+                w.px = (R)(Rh.L - hx);
+                w.py = (R)(-hy);
+                w.b0 = R(0);
+                w.b1 = (R)Rh.L;
+                w.sg = R(0);
+                w.c = (R)(-ex);
+                w.s = (R)(-ey);
+                w.he = Rh.twin;
+                w.root = -1;
+                if (sb[(k + 2) % 3] > 0.0) {
+                    want = seg_dist(Rh.L - hx, -hy, 0.0, Rh.L) < C.cut_acc;
+                } else {
+                    // source on this edge: the face across contains it as well
+                    const He<R> Ht = load_he(a.m, Rh.twin, R(0));
+                    w.py = R(0);
+                    double F3[3][3];
+                    face_xyz(a.m, Rh.twin / 3, Rh.twin % 3, F3);
+                    children(Ht, w, 0.0, true, C, F3, L, wa, wantA, wb, wantB, pruned);
+                }
+            }
+        }
+        root_update(L, rok, rv, rd, rtx, rty, overflow);
+        // on-edge sources: targets and third vertex of the face across
+        for (int k = 0; k < 3; ++k) {
+            bool on = sb[(k + 2) % 3] <= 0.0 && he[3 * fs + k].twin >= 0;
+            if (!on) continue;  // wave-uniform
+            const HeRec Rh = he[3 * fs + k];
+            const int t = Rh.twin, g = t / 3, m = t % 3;
+            const HeRec Rt = he[t];
+            const double ex = (P[(k + 1) % 3][0] - P[k][0]) / Rh.L, ey = (P[(k + 1) % 3][1] - P[k][1]) / Rh.L;
+            const double c = -ex, s = -ey;
+            const double hx = sb[(k + 1) % 3] * Rh.L + sb[(k + 2) % 3] * Rh.cx;
+            const double ptx = Rh.L - hx;
+            int slot = lane < 1 ? first_in_face(L, g) : -1;
+            while (__ballot(slot >= 0)) {
+                bool ok = slot >= 0;
+                double d = 0, tx = 0, ty = 0;
+                if (ok) {
+                    double qx = L.tb[slot][(m + 1) % 3] * Rt.L + L.tb[slot][(m + 2) % 3] * Rt.cx;
+                    double qy = L.tb[slot][(m + 2) % 3] * Rt.cy;
+                    double dx = qx - ptx, dy = qy;
+                    d = sqrt(dx * dx + dy * dy);
+                    if (d > 0) {
+                        dx /= d;
+                        dy /= d;
+                        tx = c * dx - s * dy;
+                        ty = s * dx + c * dy;
+                    }
+                }
+                target_update(L, C, ok, slot, d, tx, ty);
+                if (ok) slot = next_in_face(L, slot, g);
+            }
+            bool ok = lane == 0 && (Rt.flags & 1);
+            double dx = Rt.cx - ptx, dy = Rt.cy;
+            double d = sqrt(dx * dx + dy * dy);
+            root_update(L, ok && d < C.cut_acc, Rt.opp, d, (c * dx - s * dy) / d, (s * dx + c * dy) / d, overflow);
+        }
+        S.push(want, w, overflow);
+        S.push(wantA, wa, overflow);
+        S.push(wantB, wb, overflow);
+    }
+
+    // ---- propagation
+    const bool eager = a.gp.eager != 0;
+    bool have = false;
+    Win<R> w;
+    unsigned long long nwin = 0;
+    for (;;) {
+        ++iters;
+        if (__ballot(overflow)) overflow = true;
+        if (overflow) break;
+        bool busy = S.refill(have, w);
+        // bend-vertex launches: eagerly whenever the table is dirty, else
+        // once nothing is left to propagate
+        if (L.dirty && (eager || !busy)) {
+            launch_roots(a, L, C, S, st);
+            if (!busy) busy = S.refill(have, w);
+        }
+        if (!busy) {
+            if (!L.dirty) break;
+            continue;
+        }
+        nwin += (unsigned long long)__popcll(__ballot(have));
+        if (nwin > (unsigned long long)a.gp.max_windows) {
+            overflow = true;
+            break;
+        }
+
+        // ---- process the lane's window
+        Win<R> cl, cr;
+        bool hl = false, hr = false;
+        // stale: the root's distance improved after this window was made
+        // (compared in the working precision the window was stored in)
+        if (have && w.root >= 0 && w.sg > (R)L.rD[w.root]) {
+            have = false;
+            ++st.stale;
+        }
+        He<R> H;
+        double txc = 0.0;
+        double F3[3][3];
+        int f = -1, k = 0;
+        if (have) {
+            // both records depend only on the entry half-edge: issue them together
+            f = w.he / 3;
+            k = w.he % 3;
+            H = load_he(a.m, w.he, R(0));
+            face_xyz(a.m, f, k, F3);
+            txc = (double)w.px + ((double)H.cx - (double)w.px) * (-(double)w.py) / ((double)H.cy - (double)w.py);
+        }
+        // targets in face f
+        {
+            int slot = have ? first_in_face(L, f) : -1;
+            while (__ballot(slot >= 0)) {
+                bool ok = false;
+                double d = 0, tx = 0, ty = 0;
+                if (slot >= 0) {
+                    const R qx = (R)L.tb[slot][(k + 1) % 3] * H.L + (R)L.tb[slot][(k + 2) % 3] * H.cx;
+                    const R qy = (R)L.tb[slot][(k + 2) % 3] * H.cy;
+                    const R xq = w.px + (qx - w.px) * (-w.py) / (qy - w.py);
+                    const R sl = (R)C.tol * H.L;
+                    if (xq >= w.b0 - sl && xq <= w.b1 + sl) {
+                        R dx = qx - w.px, dy = qy - w.py;
+                        const R l = sqrt(dx * dx + dy * dy);
+                        d = (double)w.sg + (double)l;
+                        ok = d < C.cut_acc;
+                        if (w.root < 0) {
+                            dx /= l;
+                            dy /= l;
+                            tx = (double)(w.c * dx - w.s * dy);
+                            ty = (double)(w.s * dx + w.c * dy);
+                        } else {
+                            tx = L.rtx[w.root];
+                            ty = L.rty[w.root];
+                        }
+                    }
+                }
+                target_update(L, C, ok, slot, d, tx, ty);
+                if (slot >= 0) slot = next_in_face(L, slot, f);
+            }
+        }
+        // third vertex as a bend vertex
+        {
+            bool ok = false;
+            double d = 0, tx = 0, ty = 0;
+            if (have && H.pseudo) {
+                const double sl = C.tol * (double)H.L;
+                if (txc >= (double)w.b0 - sl && txc <= (double)w.b1 + sl) {
+                    R dx = H.cx - w.px, dy = H.cy - w.py;
+                    const R l = sqrt(dx * dx + dy * dy);
+                    d = (double)w.sg + (double)l;
+                    ok = d < C.cut_acc;
+                    if (w.root < 0) {
+                        dx /= l;
+                        dy /= l;
+                        tx = (double)(w.c * dx - w.s * dy);
+                        ty = (double)(w.s * dx + w.c * dy);
+                    } else {
+                        tx = L.rtx[w.root];
+                        ty = L.rty[w.root];
+                    }
+                }
+            }
+            root_update(L, ok, have ? H.opp : 0, d, tx, ty, overflow);
+        }
+        if (have) children(H, w, txc, false, C, F3, L, cl, hl, cr, hr, pruned);
+        // keep one child in the lane, push the other
+        S.push(hl && hr, cr, overflow);
+        if (have) {
+            if (hl) w = cl;
+            else if (hr) w = cr;
+            else have = false;
+        }
+    }
+
+    // ---- results (row of the candidate layout)
+    const int32_t *T = a.m.T;
+    const double *p0 = a.m.V + 3 * (int64_t)T[3 * fs], *p1 = a.m.V + 3 * (int64_t)T[3 * fs + 1];
+    const double *nn = a.m.fnrm + 3 * (int64_t)fs;
+    double ex3[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+    double el = sqrt(ex3[0] * ex3[0] + ex3[1] * ex3[1] + ex3[2] * ex3[2]);
+    ex3[0] /= el;
+    ex3[1] /= el;
+    ex3[2] /= el;
+    double ey3[3] = {nn[1] * ex3[2] - nn[2] * ex3[1], nn[2] * ex3[0] - nn[0] * ex3[2], nn[0] * ex3[1] - nn[1] * ex3[0]};
+    const bool ovf = __ballot(overflow) != 0;
+    bool near_cut = false;
+    for (int s = lane; s < nc; s += kWave) {
+        const int64_t o = c0 + s;
+        double d = L.d1[s];
+        uint8_t fl = 0;
+        if (ovf) d = NAN;
+        if (L.d2[s] - d <= C.tie_rel * d) fl |= GSIM_PAIR_TIE_BIT;
+        if (d == 0.0) fl |= GSIM_PAIR_ZERO_BIT;
+        if (guard_mode) fl |= GSIM_PAIR_GUARD_BIT;
+        near_cut |= fabs(d - C.cutoff) <= a.gp.guard_rel * C.cutoff;
+        a.out.dist[o] = d;
+        a.out.flags[o] = fl;
+        for (int q = 0; q < 3; ++q) a.out.tan[3 * o + q] = L.t1x[s] * ex3[q] + L.t1y[s] * ey3[q];
+    }
+    const bool any_near = __ballot(near_cut) != 0;
+    if (a.prof && lane == 0) {
+        long long *q = a.prof + 4 * (int64_t)src;
+        q[0] += clock64() - t_start;
+        q[1] += iters;
+        q[2] += (long long)nwin;
+        q[3] += (long long)(st.launches - launches0);
+    }
+    st.windows += nwin;
+    st.pruned += pruned;
+    st.overflow |= ovf;
+    __syncthreads();
+    return any_near;
+}
+
+template <bool kMixed>
+__global__ __launch_bounds__(kWave) void k_geodesic(GeoArgs a) {
+    __shared__ Lds L;
+    const int lane = lane_id();
     int chunk = blockIdx.x % kChunks, chunks_left = kChunks;
-
-    unsigned long long c_win = 0, c_pruned = 0, c_launch = 0, c_stale = 0, c_limited = 0;
-
+    SrcStats st;
+    st.windows = st.launches = st.stale = 0;
+    st.pruned = 0;
+    st.overflow = false;
+    unsigned long long c_limited = 0;
     for (;;) {
         // ---- next source: XCD-local chunk first, then the others
         int idx = -1;
@@ -393,401 +889,33 @@ __global__ __launch_bounds__(kWave) void k_geodesic(GeoArgs a) {
         }
         if (idx < 0) break;
         const int src = a.order[idx];
-        if (a.guard_pass && a.guard[src] == 0) continue;
-        const int64_t c0 = a.cand_off[src];
-        const int nc = (int)(a.cand_off[src + 1] - c0);
-        if (nc == 0) continue;
+        const int64_t c0 = (int64_t)src * a.cap_c;
+        const int nc = a.cand_cnt[src];
+        if (nc <= 0) continue;
         if (nc > kMaxCand) {
-            for (int s = lane; s < nc; s += kWave) {
-                a.out.dist[c0 + s] = NAN;
-                a.out.flags[c0 + s] = 0;
-            }
             if (lane == 0) ++c_limited;
             continue;
         }
-
-        // ---- LDS tables
-        for (int e = lane; e < kHash; e += kWave) L.head[e] = -1;
-        for (int e = lane; e < kRootCap; e += kWave) L.rkey[e] = -1;
-        if (lane == 0) L.rcount = 0;
-        __syncthreads();
-        for (int s = lane; s < nc; s += kWave) {
-            int j = a.cand[c0 + s];
-            int f = a.face[j];
-            L.tj[s] = j;
-            L.tface[s] = f;
-            for (int d = 0; d < 3; ++d) {
-                L.tb[s][d] = a.bary[3 * (int64_t)j + d];
-                L.tx3[s][d] = a.xyz[3 * (int64_t)j + d];
-            }
-            L.d1[s] = INFINITY;
-            L.d2[s] = INFINITY;
-            L.t1x[s] = 0.0;
-            L.t1y[s] = 0.0;
-            L.tnext[s] = atomicExch(&L.head[hash_face(f)], s);
+        st.overflow = false;
+        if (kMixed) {
+            // FP32 pass; a pair inside the guard band sends the source through FP64
+            if (run_source<float>(a, L, src, c0, nc, false, blockIdx.x, st))
+                run_source<double>(a, L, src, c0, nc, true, blockIdx.x, st);
+        } else {
+            run_source<double>(a, L, src, c0, nc, false, blockIdx.x, st);
         }
-        __syncthreads();
-
-        bool overflow = false;
-        int sp = 0;
-        int pruned = 0;
-        unsigned long long nwin = 0;
-
-        // ---- seed from the source (root -1, sg = 0), in FP64
-        const int fs = a.face[src];
-        const double sb[3] = {a.bary[3 * (int64_t)src], a.bary[3 * (int64_t)src + 1], a.bary[3 * (int64_t)src + 2]};
-        const HeRec R0 = he[3 * fs];
-        const double P[3][2] = {{0.0, 0.0}, {R0.L, 0.0}, {R0.cx, R0.cy}};
-        const double sx = sb[1] * P[1][0] + sb[2] * P[2][0], sy = sb[1] * P[1][1] + sb[2] * P[2][1];
-        {
-            int slot = lane < 1 ? first_in_face(L, fs) : -1;
-            while (__ballot(slot >= 0)) {
-                bool ok = slot >= 0;
-                double d = 0, tx = 0, ty = 0;
-                if (ok) {
-                    double qx = L.tb[slot][1] * P[1][0] + L.tb[slot][2] * P[2][0];
-                    double qy = L.tb[slot][1] * P[1][1] + L.tb[slot][2] * P[2][1];
-                    double dx = qx - sx, dy = qy - sy;
-                    d = sqrt(dx * dx + dy * dy);
-                    if (d > 0.0) {
-                        tx = dx / d;
-                        ty = dy / d;
-                    }
-                }
-                target_update(L, ok, slot, d, tx, ty, a.gp.tie_dir);
-                if (ok) slot = next_in_face(L, slot, fs);
-            }
-        }
-        {
-            Win<R> w, wa, wb;
-            bool want = false, wantA = false, wantB = false;
-            bool rok = false;
-            int rv = 0;
-            double rd = 0, rtx = 0, rty = 0;
-            if (lane < 3) {
-                const int k = lane, h = 3 * fs + k;
-                const HeRec Rh = he[h];
-                const double ex = (P[(k + 1) % 3][0] - P[k][0]) / Rh.L, ey = (P[(k + 1) % 3][1] - P[k][1]) / Rh.L;
-                int v = a.m.T[h];
-                if (a.m.vflag[v] & VF_PSEUDO) {
-                    double dx = P[k][0] - sx, dy = P[k][1] - sy;
-                    rd = sqrt(dx * dx + dy * dy);
-                    rok = rd < cut_acc;
-                    rv = v;
-                    rtx = rd > 0 ? dx / rd : 0.0;
-                    rty = rd > 0 ? dy / rd : 0.0;
-                }
-                const double hx = sb[(k + 1) % 3] * Rh.L + sb[(k + 2) % 3] * Rh.cx, hy = sb[(k + 2) % 3] * Rh.cy;
-                if (Rh.twin >= 0) {
-                    w.px = (R)(Rh.L - hx);
-                    w.py = (R)(-hy);
-                    w.b0 = R(0);
-                    w.b1 = (R)Rh.L;
-                    w.sg = R(0);
-                    w.c = (R)(-ex);
-                    w.s = (R)(-ey);
-                    w.he = Rh.twin;
-                    w.root = -1;
-                    if (sb[(k + 2) % 3] > 0.0) {
-                        want = seg_dist(Rh.L - hx, -hy, 0.0, Rh.L) < cut_acc;
-                    } else {
-                        // source on this edge: the face across contains it as well
-                        const He<R> Ht = load_he(a.m, Rh.twin, R(0));
-                        w.py = R(0);
-                        double F3[3][3];
-                        face_xyz(a.m, Rh.twin / 3, Rh.twin % 3, F3);
-                        children(Ht, w, 0.0, true, cutoff, F3, L, nc, lb_slack, wa, wantA, wb, wantB, pruned);
-                    }
-                }
-            }
-            root_update(L, rok, rv, rd, rtx, rty, overflow);
-            // on-edge sources: targets and third vertex of the face across
-            for (int k = 0; k < 3; ++k) {
-                bool on = sb[(k + 2) % 3] <= 0.0 && he[3 * fs + k].twin >= 0;
-                if (!on) continue;  // wave-uniform
-                const HeRec Rh = he[3 * fs + k];
-                const int t = Rh.twin, g = t / 3, m = t % 3;
-                const HeRec Rt = he[t];
-                const double ex = (P[(k + 1) % 3][0] - P[k][0]) / Rh.L, ey = (P[(k + 1) % 3][1] - P[k][1]) / Rh.L;
-                const double c = -ex, s = -ey;
-                const double hx = sb[(k + 1) % 3] * Rh.L + sb[(k + 2) % 3] * Rh.cx;
-                const double ptx = Rh.L - hx;
-                int slot = lane < 1 ? first_in_face(L, g) : -1;
-                while (__ballot(slot >= 0)) {
-                    bool ok = slot >= 0;
-                    double d = 0, tx = 0, ty = 0;
-                    if (ok) {
-                        double qx = L.tb[slot][(m + 1) % 3] * Rt.L + L.tb[slot][(m + 2) % 3] * Rt.cx;
-                        double qy = L.tb[slot][(m + 2) % 3] * Rt.cy;
-                        double dx = qx - ptx, dy = qy;
-                        d = sqrt(dx * dx + dy * dy);
-                        if (d > 0) {
-                            dx /= d;
-                            dy /= d;
-                            tx = c * dx - s * dy;
-                            ty = s * dx + c * dy;
-                        }
-                    }
-                    target_update(L, ok, slot, d, tx, ty, a.gp.tie_dir);
-                    if (ok) slot = next_in_face(L, slot, g);
-                }
-                bool ok = lane == 0 && (Rt.flags & 1);
-                double dx = Rt.cx - ptx, dy = Rt.cy;
-                double d = sqrt(dx * dx + dy * dy);
-                root_update(L, ok && d < cut_acc, Rt.opp, d, (c * dx - s * dy) / d, (s * dx + c * dy) / d, overflow);
-            }
-            push_windows(stk, sp, a.gp.stack_cap, want, w, overflow);
-            push_windows(stk, sp, a.gp.stack_cap, wantA, wa, overflow);
-            push_windows(stk, sp, a.gp.stack_cap, wantB, wb, overflow);
-        }
-
-        // ---- propagation
-        bool have = false;
-        Win<R> w;
-        for (;;) {
-            // stack writes by other lanes must be visible before popping
-            __syncthreads();
-            if (__ballot(overflow)) overflow = true;
-            if (overflow) break;
-            uint64_t need = __ballot(!have);
-            int take = min(__popcll(need), sp);
-            if (!have) {
-                int r = __popcll(need & lanemask_lt());
-                if (r < take) {
-                    load_rec(stk[sp - 1 - r], w);
-                    have = true;
-                }
-            }
-            sp -= take;
-            if (__ballot(have) == 0) {
-                // no window anywhere: launch the next bucket of bend vertices
-                double mn = INFINITY;
-                for (int e = lane; e < kRootCap; e += kWave)
-                    if (L.rkey[e] >= 0 && L.rD[e] < L.rL[e] && L.rD[e] < cut_acc) mn = fmin(mn, L.rD[e]);
-                mn = wave_min(mn);
-                if (!(mn < INFINITY)) break;
-                const double thr = mn + a.gp.launch_delta;
-                for (int base = 0; base < kRootCap; base += kWave) {
-                    const int e = base + lane;
-                    bool sel = e < kRootCap && L.rkey[e] >= 0 && L.rD[e] < L.rL[e] && L.rD[e] <= thr &&
-                               L.rD[e] < cut_acc;
-                    uint64_t mk = __ballot(sel);
-                    while (mk) {
-                        const int el = base + __ffsll((unsigned long long)mk) - 1;
-                        mk &= mk - 1;
-                        const int v = L.rkey[el];
-                        const double D = L.rD[el];
-                        const double vtx = L.rtx[el], vty = L.rty[el];
-                        __syncthreads();
-                        if (lane == 0) L.rL[el] = D;
-                        const double vx = a.m.V[3 * (int64_t)v], vy = a.m.V[3 * (int64_t)v + 1],
-                                     vz = a.m.V[3 * (int64_t)v + 2];
-                        // a bend vertex farther (in 3D) than the remaining budget from
-                        // every target cannot lead to a pair below the cutoff
-                        bool useful = false;
-                        {
-                            const double rem = cutoff - D + lb_slack;
-                            for (int s = lane; s < nc; s += kWave) {
-                                double q0 = L.tx3[s][0] - vx, q1 = L.tx3[s][1] - vy, q2 = L.tx3[s][2] - vz;
-                                useful |= q0 * q0 + q1 * q1 + q2 * q2 < rem * rem;
-                            }
-                        }
-                        if (__ballot(useful) == 0) continue;
-                        ++c_launch;
-                        const int f0 = a.m.fan_off[v], f1 = a.m.fan_off[v + 1];
-                        for (int fb = f0; fb < f1; fb += kWave) {
-                            const int q = fb + lane;
-                            const bool act = q < f1;
-                            const int h = act ? a.m.fan[q] : 0;
-                            const int hn = h - h % 3 + (h % 3 + 1) % 3;
-                            const HeRec Rh = he[h], Rn = he[hn];
-                            Win<R> nw;
-                            bool want2 = false;
-                            if (act && Rn.twin >= 0) {
-                                // window across the edge opposite v: twin(next(h)) runs u2 -> u1
-                                const double px = Rn.L - Rn.cx, py = -Rn.cy;
-                                nw.px = (R)px;
-                                nw.py = (R)py;
-                                nw.b0 = R(0);
-                                nw.b1 = (R)Rn.L;
-                                nw.sg = (R)D;
-                                nw.c = R(1);
-                                nw.s = R(0);
-                                nw.he = Rn.twin;
-                                nw.root = el;
-                                double F3[3][3];
-                                face_xyz(a.m, h / 3, h % 3, F3);  // (v, u1, u2)
-                                double u[3] = {F3[1][0] - F3[2][0], F3[1][1] - F3[2][1], F3[1][2] - F3[2][2]};
-                                const double il = 1.0 / Rn.L;
-                                u[0] *= il; u[1] *= il; u[2] *= il;
-                                want2 = reaches_target(L, nc, F3[2], u, 0.0, Rn.L,
-                                                       cutoff - D - seg_dist(px, py, 0.0, Rn.L) + lb_slack);
-                            }
-                            // direct targets in face(h)
-                            const int g = h / 3;
-                            int slot = act ? first_in_face(L, g) : -1;
-                            while (__ballot(slot >= 0)) {
-                                bool ok = slot >= 0;
-                                double d = 0;
-                                if (ok) {
-                                    double dx = L.tx3[slot][0] - vx, dy = L.tx3[slot][1] - vy,
-                                           dz = L.tx3[slot][2] - vz;
-                                    d = D + sqrt(dx * dx + dy * dy + dz * dz);
-                                }
-                                target_update(L, ok, slot, d, vtx, vty, a.gp.tie_dir);
-                                if (ok) slot = next_in_face(L, slot, g);
-                            }
-                            // adjacent bend vertices along the two edges at v
-                            const int u1 = act ? a.m.T[hn] : 0;  // head of h
-                            bool ok1 = act && (a.m.vflag[u1] & VF_PSEUDO) && D + Rh.L < cut_acc;
-                            root_update(L, ok1, u1, D + Rh.L, vtx, vty, overflow);
-                            const int u2 = act ? Rh.opp : 0;
-                            bool ok2 = act && (a.m.vflag[u2] & VF_PSEUDO) && D + Rh.Lp < cut_acc;
-                            root_update(L, ok2, u2, D + Rh.Lp, vtx, vty, overflow);
-                            push_windows(stk, sp, a.gp.stack_cap, want2, nw, overflow);
-                        }
-                    }
-                }
-                continue;
-            }
-            nwin += (unsigned long long)__popcll(__ballot(have));
-            if (nwin > (unsigned long long)a.gp.max_windows) {
-                overflow = true;
-                break;
-            }
-
-            // ---- process the lane's window
-            Win<R> cl, cr;
-            bool hl = false, hr = false;
-            // stale: the root's distance improved after this window was made
-            // (compared in the working precision the window was stored in)
-            if (have && w.root >= 0 && w.sg > (R)L.rD[w.root]) {
-                have = false;
-                ++c_stale;
-            }
-            He<R> H;
-            double txc = 0.0;
-            int f = -1, k = 0;
-            if (have) {
-                H = load_he(a.m, w.he, R(0));
-                f = w.he / 3;
-                k = w.he % 3;
-                txc = (double)w.px + ((double)H.cx - (double)w.px) * (-(double)w.py) / ((double)H.cy - (double)w.py);
-            }
-            // targets in face f
-            {
-                int slot = have ? first_in_face(L, f) : -1;
-                while (__ballot(slot >= 0)) {
-                    bool ok = false;
-                    double d = 0, tx = 0, ty = 0;
-                    if (slot >= 0) {
-                        const R qx = (R)L.tb[slot][(k + 1) % 3] * H.L + (R)L.tb[slot][(k + 2) % 3] * H.cx;
-                        const R qy = (R)L.tb[slot][(k + 2) % 3] * H.cy;
-                        const R xq = w.px + (qx - w.px) * (-w.py) / (qy - w.py);
-                        const R sl = (R)tol * H.L;
-                        if (xq >= w.b0 - sl && xq <= w.b1 + sl) {
-                            R dx = qx - w.px, dy = qy - w.py;
-                            const R l = sqrt(dx * dx + dy * dy);
-                            d = (double)w.sg + (double)l;
-                            ok = d < cut_acc;
-                            if (w.root < 0) {
-                                dx /= l;
-                                dy /= l;
-                                tx = (double)(w.c * dx - w.s * dy);
-                                ty = (double)(w.s * dx + w.c * dy);
-                            } else {
-                                tx = L.rtx[w.root];
-                                ty = L.rty[w.root];
-                            }
-                        }
-                    }
-                    target_update(L, ok, slot, d, tx, ty, a.gp.tie_dir);
-                    if (slot >= 0) slot = next_in_face(L, slot, f);
-                }
-            }
-            // third vertex as a bend vertex
-            {
-                bool ok = false;
-                double d = 0, tx = 0, ty = 0;
-                if (have && H.pseudo) {
-                    const double sl = tol * (double)H.L;
-                    if (txc >= (double)w.b0 - sl && txc <= (double)w.b1 + sl) {
-                        R dx = H.cx - w.px, dy = H.cy - w.py;
-                        const R l = sqrt(dx * dx + dy * dy);
-                        d = (double)w.sg + (double)l;
-                        ok = d < cut_acc;
-                        if (w.root < 0) {
-                            dx /= l;
-                            dy /= l;
-                            tx = (double)(w.c * dx - w.s * dy);
-                            ty = (double)(w.s * dx + w.c * dy);
-                        } else {
-                            tx = L.rtx[w.root];
-                            ty = L.rty[w.root];
-                        }
-                    }
-                }
-                root_update(L, ok, have ? H.opp : 0, d, tx, ty, overflow);
-            }
-            if (have) {
-                double F3[3][3];
-                face_xyz(a.m, f, k, F3);
-                children(H, w, txc, false, cutoff, F3, L, nc, lb_slack, cl, hl, cr, hr, pruned);
-            }
-            // keep one child in the lane, push the other
-            const bool push = hl && hr;
-            push_windows(stk, sp, a.gp.stack_cap, push, cr, overflow);
-            if (have) {
-                if (hl) w = cl;
-                else if (hr) w = cr;
-                else have = false;
-            }
-        }
-
-        // ---- results
-        const int32_t *T = a.m.T;
-        const double *p0 = a.m.V + 3 * (int64_t)T[3 * fs], *p1 = a.m.V + 3 * (int64_t)T[3 * fs + 1];
-        const double *nn = a.m.fnrm + 3 * (int64_t)fs;
-        double ex3[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
-        double el = sqrt(ex3[0] * ex3[0] + ex3[1] * ex3[1] + ex3[2] * ex3[2]);
-        ex3[0] /= el;
-        ex3[1] /= el;
-        ex3[2] /= el;
-        double ey3[3] = {nn[1] * ex3[2] - nn[2] * ex3[1], nn[2] * ex3[0] - nn[0] * ex3[2],
-                         nn[0] * ex3[1] - nn[1] * ex3[0]};
-        __syncthreads();
-        const bool ovf = __ballot(overflow) != 0;
-        bool near_cut = false;
-        for (int s = lane; s < nc; s += kWave) {
-            const int64_t o = c0 + s;
-            double d = L.d1[s];
-            uint8_t fl = 0;
-            if (ovf) d = NAN;
-            if (L.d2[s] - d <= a.gp.tie_rel * d) fl |= GSIM_PAIR_TIE_BIT;
-            if (d == 0.0) fl |= GSIM_PAIR_ZERO_BIT;
-            if (a.guard_pass) fl |= GSIM_PAIR_GUARD_BIT;
-            near_cut |= fabs(d - cutoff) <= a.gp.guard_rel * cutoff;
-            a.out.dist[o] = d;
-            a.out.flags[o] = fl;
-            for (int q = 0; q < 3; ++q) a.out.tan[3 * o + q] = L.t1x[s] * ex3[q] + L.t1y[s] * ey3[q];
-        }
-        const bool any_near = __ballot(near_cut) != 0;
-        if (fp32 && a.guard && lane == 0) a.guard[src] = any_near ? 1 : 0;
-        c_win += nwin;
-        c_pruned += (unsigned long long)pruned;
-        if (ovf) ++c_limited;
-        __syncthreads();
+        if (st.overflow) ++c_limited;
     }
-    unsigned long long pr = c_pruned, st = c_stale;
+    unsigned long long pr = (unsigned long long)st.pruned, sl = st.stale;
     for (int o = 32; o > 0; o >>= 1) {
         pr += __shfl_xor(pr, o);
-        st += __shfl_xor(st, o);
+        sl += __shfl_xor(sl, o);
     }
     if (lane == 0) {
-        atomicAdd(&a.ctr->windows, c_win);
+        atomicAdd(&a.ctr->windows, st.windows);
         atomicAdd(&a.ctr->pruned, pr);
-        atomicAdd(&a.ctr->launches, c_launch);
-        atomicAdd(&a.ctr->stale, st);
+        atomicAdd(&a.ctr->launches, st.launches);
+        atomicAdd(&a.ctr->stale, sl);
         atomicAdd(&a.ctr->limited, c_limited);
     }
 }
@@ -795,30 +923,30 @@ __global__ __launch_bounds__(kWave) void k_geodesic(GeoArgs a) {
 }  // namespace
 
 hipError_t launch_geodesic(const DevMesh &m, int n, const int32_t *face, const double *bary, const double *xyz,
-                           const PrefilterBufs &pb, const GeoParams &gp, GeoOut out, char *stack_mem,
-                           int32_t nslots, int32_t *work_ctr, Counters *ctr, bool fp32, uint8_t *guard,
-                           bool guard_pass, hipStream_t s) {
+                           const int32_t *cand_cnt, const int32_t *cand, int cap_c, const int32_t *order,
+                           const GeoParams &gp, GeoOut out, char *stack_mem, int32_t nslots, int32_t *work_ctr,
+                           Counters *ctr, bool fp32, long long *prof, hipStream_t s) {
     GeoArgs a;
+    a.prof = prof;
     a.m = m;
     a.n = n;
     a.face = face;
     a.bary = bary;
     a.xyz = xyz;
-    a.cand_off = pb.cand_off;
-    a.cand = pb.cand;
-    a.order = pb.order;
+    a.cand_cnt = cand_cnt;
+    a.cand = cand;
+    a.cap_c = cap_c;
+    a.order = order;
     a.gp = gp;
     a.out = out;
     a.stack = stack_mem;
     a.work = work_ctr;
     a.ctr = ctr;
-    a.guard = guard;
-    a.guard_pass = guard_pass ? 1 : 0;
-    if (fp32) hipLaunchKernelGGL(k_geodesic<float>, dim3(nslots), dim3(kWave), 0, s, a);
-    else hipLaunchKernelGGL(k_geodesic<double>, dim3(nslots), dim3(kWave), 0, s, a);
+    if (fp32) hipLaunchKernelGGL(k_geodesic<true>, dim3(nslots), dim3(kWave), 0, s, a);
+    else hipLaunchKernelGGL(k_geodesic<false>, dim3(nslots), dim3(kWave), 0, s, a);
     return hipGetLastError();
 }
 
-size_t window_record_bytes(bool fp32) { return fp32 ? sizeof(Rec32) : sizeof(Rec64); }
+int max_candidates_per_source() { return kMaxCand; }
 
 }  // namespace gsim

@@ -124,15 +124,19 @@ __global__ void k_bin_scatter(int n, PrefilterBufs b) {
     b.order[pos] = j;
 }
 
-template <bool kFill>
-__global__ void k_candidates(int n, double cut2, PrefilterBufs b) {
+// Candidate targets of each source: every particle whose Euclidean
+// distance is below the cutoff (the paper's lower bound, Sec. 3.1), from the
+// 27 cells around the source, kept sorted by particle index in a row of
+// fixed capacity. cand_cnt holds the true count; a count above the capacity
+// is reported through `overflow`.
+__global__ void k_candidates_rows(int n, double cut2, PrefilterBufs b, int32_t *__restrict__ overflow) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const double xi = b.xyz[3 * i], yi = b.xyz[3 * i + 1], zi = b.xyz[3 * i + 2];
     int lin = b.cell_of[i];
     int cx = lin % b.dims[0], cy = (lin / b.dims[0]) % b.dims[1], cz = lin / (b.dims[0] * b.dims[1]);
     int cnt = 0;
-    int64_t base = kFill ? b.cand_off[i] : 0;
+    int32_t *row = b.cand + (int64_t)i * b.cap_c;
     for (int dz = -1; dz <= 1; ++dz) {
         int z = cz + dz;
         if (z < 0 || z >= b.dims[2]) continue;
@@ -148,14 +152,13 @@ __global__ void k_candidates(int n, double cut2, PrefilterBufs b) {
                     if (j == i) continue;
                     double ex = b.xyz[3 * j] - xi, ey = b.xyz[3 * j + 1] - yi, ez = b.xyz[3 * j + 2] - zi;
                     if (ex * ex + ey * ey + ez * ez < cut2) {
-                        if (kFill) {
-                            // insertion into the row, kept sorted by j
-                            int64_t p = base + cnt;
-                            while (p > base && b.cand[p - 1] > j) {
-                                b.cand[p] = b.cand[p - 1];
+                        if (cnt < b.cap_c) {
+                            int p = cnt;
+                            while (p > 0 && row[p - 1] > j) {
+                                row[p] = row[p - 1];
                                 --p;
                             }
-                            b.cand[p] = j;
+                            row[p] = j;
                         }
                         ++cnt;
                     }
@@ -163,28 +166,31 @@ __global__ void k_candidates(int n, double cut2, PrefilterBufs b) {
             }
         }
     }
-    if (!kFill) b.cand_cnt[i] = cnt;
+    b.cand_cnt[i] = cnt;
+    if (cnt > b.cap_c) atomicAdd(overflow, 1);
 }
 
 // ------------------------------------------------------------ compaction
-__global__ void k_count_nbrs(int n, const int64_t *__restrict__ coff, const double *__restrict__ dist,
-                             double cutoff, int32_t *__restrict__ cnt) {
+__global__ void k_count_rows(int n, const int32_t *__restrict__ cnt, int cap, const double *__restrict__ dist,
+                             double cutoff, int32_t *__restrict__ out) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    int c = 0;
-    for (int64_t p = coff[i]; p < coff[i + 1]; ++p) c += dist[p] < cutoff;
-    cnt[i] = c;
+    int c = 0, m = min(cnt[i], cap);
+    for (int s = 0; s < m; ++s) c += dist[(int64_t)i * cap + s] < cutoff;
+    out[i] = c;
 }
 
-__global__ void k_compact(int n, const int64_t *__restrict__ coff, const int32_t *__restrict__ cand,
-                          const double *__restrict__ dist, const double *__restrict__ tan,
-                          const uint8_t *__restrict__ flags, double cutoff, const int64_t *__restrict__ off,
-                          int32_t *__restrict__ nbr, double *__restrict__ od, double *__restrict__ ot,
-                          uint8_t *__restrict__ of) {
+__global__ void k_compact_rows(int n, const int32_t *__restrict__ cnt, int cap, const int32_t *__restrict__ cand,
+                               const double *__restrict__ dist, const double *__restrict__ tan,
+                               const uint8_t *__restrict__ flags, double cutoff, const int64_t *__restrict__ off,
+                               int32_t *__restrict__ nbr, double *__restrict__ od, double *__restrict__ ot,
+                               uint8_t *__restrict__ of) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int64_t q = off[i];
-    for (int64_t p = coff[i]; p < coff[i + 1]; ++p) {
+    int m = min(cnt[i], cap);
+    for (int s = 0; s < m; ++s) {
+        int64_t p = (int64_t)i * cap + s;
         if (!(dist[p] < cutoff)) continue;
         nbr[q] = cand[p];
         od[q] = dist[p];
@@ -197,15 +203,20 @@ __global__ void k_compact(int n, const int64_t *__restrict__ coff, const int32_t
 }
 
 // ------------------------------------------------------------ forces
-// F_i = sum_j U'(d_ij) t_ij and E_i = (1/2) sum_j U(d_ij), ascending j.
-__global__ void k_forces(int n, const int64_t *__restrict__ off, const double *__restrict__ dist,
-                         const double *__restrict__ tan, int kind, double k, double sigma, double *__restrict__ F,
-                         double *__restrict__ Ei) {
+// F_i = sum_j U'(d_ij) t_ij and E_i = (1/2) sum_j U(d_ij), ascending j, over
+// the pairs of the row closer than the cutoff.
+__global__ void k_forces_rows(int n, const int32_t *__restrict__ cnt, int cap, const double *__restrict__ dist,
+                              const double *__restrict__ tan, double cutoff, int kind, double k, double sigma,
+                              double *__restrict__ F, double *__restrict__ Ei, unsigned long long *__restrict__ npairs) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
-    for (int64_t p = off[i]; p < off[i + 1]; ++p) {
+    int m = min(cnt[i], cap), np = 0;
+    for (int s = 0; s < m; ++s) {
+        int64_t p = (int64_t)i * cap + s;
         double d = dist[p];
+        if (!(d < cutoff)) continue;
+        ++np;
         if (!(d > 0.0)) continue;
         double U, dU;
         if (kind == 0) {  // harmonic
@@ -233,6 +244,7 @@ __global__ void k_forces(int n, const int64_t *__restrict__ off, const double *_
     F[3 * i + 1] = fy;
     F[3 * i + 2] = fz;
     Ei[i] = e;
+    if (npairs && np) atomicAdd(npairs, (unsigned long long)np);
 }
 
 // deterministic two-level sum
@@ -352,14 +364,9 @@ hipError_t launch_prefilter_bin(const DevMesh &m, int n, PrefilterBufs &b, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_prefilter_count(int n, double cutoff, PrefilterBufs &b, hipStream_t s) {
+hipError_t launch_prefilter_rows(int n, double cutoff, PrefilterBufs &b, int32_t *overflow, hipStream_t s) {
     double c2 = cutoff * cutoff * (1.0 + 1e-12);
-    hipLaunchKernelGGL((k_candidates<false>), dim3(nblocks(n)), dim3(kBlock), 0, s, n, c2, b);
-    return hipGetLastError();
-}
-hipError_t launch_prefilter_fill(int n, double cutoff, PrefilterBufs &b, hipStream_t s) {
-    double c2 = cutoff * cutoff * (1.0 + 1e-12);
-    hipLaunchKernelGGL((k_candidates<true>), dim3(nblocks(n)), dim3(kBlock), 0, s, n, c2, b);
+    hipLaunchKernelGGL(k_candidates_rows, dim3(nblocks(n, 64)), dim3(64), 0, s, n, c2, b, overflow);
     return hipGetLastError();
 }
 hipError_t launch_bin_scatter(int n, PrefilterBufs &b, hipStream_t s) {
@@ -371,21 +378,23 @@ hipError_t launch_i64_to_i32(const int64_t *in, int32_t *out, int n, hipStream_t
     return hipGetLastError();
 }
 
-hipError_t launch_count_nbrs(int n, const int64_t *cand_off, const double *dist, double cutoff, int32_t *cnt,
+hipError_t launch_count_rows(int n, const int32_t *cnt, int cap_c, const double *dist, double cutoff, int32_t *out,
                              hipStream_t s) {
-    hipLaunchKernelGGL(k_count_nbrs, dim3(nblocks(n)), dim3(kBlock), 0, s, n, cand_off, dist, cutoff, cnt);
+    hipLaunchKernelGGL(k_count_rows, dim3(nblocks(n)), dim3(kBlock), 0, s, n, cnt, cap_c, dist, cutoff, out);
     return hipGetLastError();
 }
-hipError_t launch_compact(int n, const int64_t *cand_off, const int32_t *cand, const double *dist,
-                          const double *tan, const uint8_t *flags, double cutoff, const int64_t *off, int32_t *nbr,
-                          double *odist, double *otan, uint8_t *oflags, hipStream_t s) {
-    hipLaunchKernelGGL(k_compact, dim3(nblocks(n)), dim3(kBlock), 0, s, n, cand_off, cand, dist, tan, flags, cutoff,
-                       off, nbr, odist, otan, oflags);
+hipError_t launch_compact_rows(int n, const int32_t *cnt, int cap_c, const int32_t *cand, const double *dist,
+                               const double *tan, const uint8_t *flags, double cutoff, const int64_t *off,
+                               int32_t *nbr, double *odist, double *otan, uint8_t *oflags, hipStream_t s) {
+    hipLaunchKernelGGL(k_compact_rows, dim3(nblocks(n)), dim3(kBlock), 0, s, n, cnt, cap_c, cand, dist, tan, flags,
+                       cutoff, off, nbr, odist, otan, oflags);
     return hipGetLastError();
 }
-hipError_t launch_forces(int n, const int64_t *off, const double *dist, const double *tan, int kind, double k,
-                         double sigma, double *F, double *Ei, hipStream_t s) {
-    hipLaunchKernelGGL(k_forces, dim3(nblocks(n)), dim3(kBlock), 0, s, n, off, dist, tan, kind, k, sigma, F, Ei);
+hipError_t launch_forces_rows(int n, const int32_t *cnt, int cap_c, const double *dist, const double *tan,
+                              double cutoff, int kind, double k, double sigma, double *F, double *Ei,
+                              unsigned long long *npairs, hipStream_t s) {
+    hipLaunchKernelGGL(k_forces_rows, dim3(nblocks(n)), dim3(kBlock), 0, s, n, cnt, cap_c, dist, tan, cutoff, kind, k,
+                       sigma, F, Ei, npairs);
     return hipGetLastError();
 }
 hipError_t launch_sum(const double *x, int n, double *out, double *scratch, hipStream_t s) {

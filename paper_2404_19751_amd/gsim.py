@@ -25,7 +25,8 @@ PAIR_TIE, PAIR_ZERO, PAIR_GUARD = 1, 2, 4
 EXPORTS = ["gsim_create", "gsim_destroy", "gsim_last_error", "gsim_synchronize", "gsim_mesh_upload",
            "gsim_mesh_info_get", "gsim_particles_set", "gsim_particles_get", "gsim_particles_set_dev",
            "gsim_particles_get_dev", "gsim_geodesic_pairs", "gsim_compute_forces", "gsim_displace_on_surface",
-           "gsim_step", "gsim_timing_enable", "gsim_timing_get", "gsim_counters_get", "gsim_tune_set"]
+           "gsim_step", "gsim_timing_enable", "gsim_timing_get", "gsim_counters_get", "gsim_tune_set",
+           "gsim_source_profile"]
 
 
 class GsimError(RuntimeError):
@@ -91,6 +92,7 @@ def load(path: str = LIB_PATH):
         "gsim_timing_get": ([V, C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)], C.c_int),
         "gsim_counters_get": ([V, V], C.c_int),
         "gsim_tune_set": ([V, C.c_char_p, C.c_double], C.c_int),
+        "gsim_source_profile": ([V, C.c_int, V, C.c_int32], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -244,6 +246,15 @@ class Context:
     def tune(self, **knobs):
         for k, v in knobs.items():
             self._chk(self.L.gsim_tune_set(self.h, k.encode(), float(v)))
+
+    def source_profile_start(self):
+        self._chk(self.L.gsim_source_profile(self.h, 1, None, 0))
+
+    def source_profile_stop(self, mid):
+        n = self._n[mid]
+        out = np.zeros((n, 4), np.int64)
+        self._chk(self.L.gsim_source_profile(self.h, 0, _ptr(out), n))
+        return out
 
     def counters(self) -> dict:
         c = np.zeros(10, np.int64)
