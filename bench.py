@@ -36,6 +36,23 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 FLOPS_PER_WINDOW = 90.0
 
 
+PMC_FILE = os.path.join(ROOT, "profiles", "k_geodesic_bumpy_sphere_n1000_fp32mixed_pmc.json")
+
+
+def measured_traffic():
+    """HBM bytes per k_geodesic launch from the committed counter runs, or
+    None once the kernel source differs from the one the counters saw."""
+    import hashlib
+    try:
+        rec = json.load(open(PMC_FILE))
+        src = open(os.path.join(ROOT, "paper_2404_19751_amd", "csrc", "k_geodesic.hip"), "rb").read()
+    except OSError:
+        return None
+    if hashlib.sha256(src).hexdigest() != rec.get("kernel_source_sha256"):
+        return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(w, budget_s=8.0, max_steps=40):
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
@@ -63,7 +80,19 @@ def main():
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32"])
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
+                    help="only run a plain device-to-device copy of this many MiB (hardware-counter calibration)")
     args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": nbytes}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "sources would shard across GPUs with one all-gather of particle state per step, not built here.",
@@ -91,7 +120,7 @@ def main():
         dt = time.perf_counter() - t0
         cnt = ctx.counters()
         stages = {k: ctx.timing_get(k)[0] for k in
-                  ("prefilter", "geodesic", "geodesic_guard", "compact", "forces", "integrate", "walk")}
+                  ("prefilter", "geodesic", "update")}
         ctx.timing(False)
         ctx.close()
         return dt, cnt, stages
@@ -125,7 +154,8 @@ def main():
         "stage_ms": stages,
         "windows_per_step": win_per_launch,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak, "traffic": None,
+                     "frac": achieved / peak,
+                     "traffic": measured_traffic() if args.precision == "fp32" else None,
                      "kernel": "k_geodesic", "per_unit": f"{FLOPS_PER_WINDOW:.0f} flop/window",
                      "units_per_launch": win_per_launch, "avg_launch_ms": geo_ms},
     }

@@ -188,8 +188,9 @@ gsim_status gsim_timing_get(gsim_ctx *ctx, const char *name, double *avg_ms, int
  * last enabled: [7] neighbour pairs, [8] windows, [9] passes. c10[10]. */
 gsim_status gsim_counters_get(gsim_ctx *ctx, int64_t *c10);
 /* Per-source profile of the geodesic kernel, accumulated over the calls
- * made while it is on: out[n][4] = GPU clock cycles, propagation-loop
- * iterations, windows, bend-vertex launches. gsim_source_profile(ctx, 1,
+ * made while it is on: out[n][8] = GPU clock cycles, propagation-loop
+ * iterations, windows, bend-vertex launches, and the cycles spent in set-up
+ * (prefilter, tables, seeding), propagation, launches and result write-out. gsim_source_profile(ctx, 1,
  * NULL, 0) starts it; gsim_source_profile(ctx, 0, out, n) copies it out
  * (n = particles of the profiled mesh) and stops it. */
 gsim_status gsim_source_profile(gsim_ctx *ctx, int on, int64_t *out, int32_t n);

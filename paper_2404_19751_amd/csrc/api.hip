@@ -232,8 +232,8 @@ gsim_status pairs_device(gsim_ctx *c, MeshState *ms, double cutoff) {
     const int32_t nslots = std::min<int32_t>(n, c->max_slots);
     HIPCHK(c, ensure(c->stack, (size_t)nslots * gp.stack_cap * 64));
     if (c->profile_sources && c->prof_n != n) {
-        HIPCHK(c, ensure(c->prof, sizeof(long long) * 4 * (size_t)n));
-        HIPCHK(c, launch_zero_u64(P<unsigned long long>(c->prof), 4 * (int64_t)n, s));
+        HIPCHK(c, ensure(c->prof, sizeof(long long) * 8 * (size_t)n));
+        HIPCHK(c, launch_zero_u64(P<unsigned long long>(c->prof), 8 * (int64_t)n, s));
         c->prof_n = n;
     }
     pb.xyz = ms->xyz;
@@ -245,20 +245,24 @@ gsim_status pairs_device(gsim_ctx *c, MeshState *ms, double cutoff) {
     pb.cand = P<int32_t>(ms->cand);
     {
         Stage st(c, "prefilter");
-        HIPCHK(c, launch_xyz(m, n, ms->face, ms->bary, ms->xyz, s));
-        HIPCHK(c, launch_prefilter_bin(m, n, pb, s));
-        HIPCHK(c, launch_scan_i32_to_i64(pb.cell_fill, P<int64_t>(ms->tmp64), (int)ncell, P<int64_t>(c->scan_scratch), s));
-        HIPCHK(c, launch_i64_to_i32(P<int64_t>(ms->tmp64), pb.cell_start, (int)ncell, s));
-        HIPCHK(c, launch_zero_i32(pb.cell_fill, ncell, s));
-        HIPCHK(c, launch_bin_scatter(n, pb, s));
-        HIPCHK(c, launch_prefilter_rows(n, cutoff, pb, P<int32_t>(c->pf_over), s));
+        if (ncell <= kSmallCells) {
+            HIPCHK(c, launch_bin_small(m, n, ms->face, ms->bary, pb, s));
+        } else {
+            HIPCHK(c, launch_xyz(m, n, ms->face, ms->bary, ms->xyz, s));
+            HIPCHK(c, launch_prefilter_bin(m, n, pb, s));
+            HIPCHK(c, launch_scan_i32_to_i64(pb.cell_fill, P<int64_t>(ms->tmp64), (int)ncell,
+                                             P<int64_t>(c->scan_scratch), s));
+            HIPCHK(c, launch_i64_to_i32(P<int64_t>(ms->tmp64), pb.cell_start, (int)ncell, s));
+            HIPCHK(c, launch_zero_i32(pb.cell_fill, ncell, s));
+            HIPCHK(c, launch_bin_scatter(n, pb, s));
+        }
     }
     HIPCHK(c, launch_zero_i32(P<int32_t>(c->work), 16, s));
     GeoOut out{P<double>(ms->cdist), P<double>(ms->ctan), P<uint8_t>(ms->cflags)};
     {
         Stage st(c, "geodesic");
-        HIPCHK(c, launch_geodesic(m, n, ms->face, ms->bary, ms->xyz, pb.cand_cnt, pb.cand, cap, pb.order, gp, out,
-                                  P<char>(c->stack), nslots, P<int32_t>(c->work), P<Counters>(c->ctr), fp32,
+        HIPCHK(c, launch_geodesic(m, n, ms->face, ms->bary, ms->xyz, pb, cutoff, gp, out, P<char>(c->stack), nslots,
+                                  P<int32_t>(c->work), P<Counters>(c->ctr), fp32,
                                   c->profile_sources ? P<long long>(c->prof) : nullptr, s));
     }
     ms->pairs_cutoff = cutoff;
@@ -651,17 +655,31 @@ gsim_status gsim_step(gsim_ctx *c, int32_t id, const gsim_potential *pot, const 
         if ((st = begin_call(c)) != GSIM_OK) return st;
         for (int32_t k = 0; k < nsteps; ++k) {
             if ((st = pairs_device(c, ms, pot->cutoff)) != GSIM_OK) return st;
-            if ((st = run_forces(c, ms, pot)) != GSIM_OK) return st;
             {
-                Stage sg(c, "integrate");
-                HIPCHK(c, launch_integrate(ms->dm, n, ms->face, P<double>(ms->F), integ->kind, integ->dt,
-                                           integ->mobility, integ->kT, integ->friction, integ->seed, ms->step,
-                                           P<double>(ms->disp), s));
-            }
-            {
-                Stage sg(c, "walk");
-                HIPCHK(c, launch_walk(ms->dm, n, ms->face, ms->bary, P<double>(ms->disp), ms->vel, nullptr,
-                                      P<uint8_t>(ms->wflags), s));
+                Stage sg(c, "update");
+                UpdateArgs u{};
+                u.face = ms->face;
+                u.bary = ms->bary;
+                u.vel = ms->vel;
+                u.cnt = P<int32_t>(ms->cand_cnt);
+                u.cap = max_candidates_per_source();
+                u.dist = P<double>(ms->cdist);
+                u.tan = P<double>(ms->ctan);
+                u.cutoff = pot->cutoff;
+                u.kind = pot->kind;
+                u.k = pot->k;
+                u.sigma = pot->sigma;
+                u.ikind = integ->kind;
+                u.dt = integ->dt;
+                u.mobility = integ->mobility;
+                u.kT = integ->kT;
+                u.friction = integ->friction;
+                u.seed = integ->seed;
+                u.step = ms->step;
+                u.flags = P<uint8_t>(ms->wflags);
+                u.npairs = &P<Counters>(c->ctr)->nbr_pairs;
+                u.stats = nullptr;
+                HIPCHK(c, launch_update(ms->dm, n, u, s));
             }
             ms->step++;
             ms->pairs_valid = false;
@@ -720,7 +738,7 @@ gsim_status gsim_source_profile(gsim_ctx *c, int on, int64_t *out, int32_t n) {
     if (!c) return GSIM_E_ARG;
     if (out) {
         if (!c->profile_sources || n != c->prof_n) return fail(c, GSIM_E_STATE, "source profiling not active");
-        HIPCHK(c, hipMemcpyAsync(out, c->prof.p, sizeof(long long) * 4 * (size_t)n, hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipMemcpyAsync(out, c->prof.p, sizeof(long long) * 8 * (size_t)n, hipMemcpyDeviceToHost, c->stream));
         HIPCHK(c, hipStreamSynchronize(c->stream));
     }
     c->profile_sources = on != 0;

@@ -18,6 +18,8 @@ struct alignas(16) HeRec {
     double cy;
     double Lp;   // |CA| = length of prev(h)
     double Ln;   // |BC| = length of next(h)
+    double ex, ey;  // (cx, cy) / Lp: axis of the frame on edge A->C, seen from h's frame
+    double ux, uy;  // (L - cx, -cy) / Ln: axis of the frame on edge C->B
     int32_t tn;  // twin(next(h)) : the half-edge entered across BC, -1 on the boundary
     int32_t tp;  // twin(prev(h)) : the half-edge entered across CA
     int32_t opp; // vertex C
@@ -25,16 +27,17 @@ struct alignas(16) HeRec {
     int32_t twin;   // twin(h)
     int32_t pad;
 };
-static_assert(sizeof(HeRec) == 64, "HeRec must be one 64-byte record");
+static_assert(sizeof(HeRec) == 96, "HeRec must be a 96-byte record");
 
 // FP32 copy of the geometric part (FP32-mixed mode).
 struct alignas(16) HeRecF {
     float L, cx, cy, Lp;
-    float Ln;
+    float Ln, ex, ey, ux;
+    float uy;
     int32_t tn, tp;
     int32_t opp_flags;  // (opp << 1) | pseudo
 };
-static_assert(sizeof(HeRecF) == 32, "HeRecF must be 32 bytes");
+static_assert(sizeof(HeRecF) == 48, "HeRecF must be 48 bytes");
 
 enum : uint8_t { VF_PSEUDO = 1, VF_BOUNDARY = 2 };
 enum : uint8_t { GSIM_PAIR_TIE_BIT = 1, GSIM_PAIR_ZERO_BIT = 2, GSIM_PAIR_GUARD_BIT = 4 };
@@ -51,7 +54,8 @@ struct DevMesh {
     int32_t *fan = nullptr;     // [3nf] outgoing half-edges, CCW, boundary fans start clockwise-most
     double *corner = nullptr;   // [3nf] corner angle of face h/3 at the tail of h
     double *fnrm = nullptr;     // [nf][3] unit outward normal
-    double *fpos = nullptr;     // [nf][3][3] the face's vertex positions in slot order
+    double *fpos = nullptr;     // [nf][18]: the face's vertex positions in slot order, then the unit
+                                // directions of its half-edges 3f+0..2
     double bbmin[3], bbmax[3];
     double mean_edge = 0, min_edge = 0, max_edge = 0;
     int32_t n_boundary_edges = 0, n_pseudo = 0;
@@ -120,16 +124,21 @@ hipError_t launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t s);
 hipError_t launch_prefilter_bin(const DevMesh &m, int n, PrefilterBufs &b, hipStream_t s);
 hipError_t launch_scan_i32_to_i64(const int32_t *in, int64_t *out, int n, int64_t *scratch, hipStream_t s);
 
+// Euclidean prefilter (candidate rows, written to pb.cand / pb.cand_cnt) and
+// geodesics, one wavefront per source. pb's cell lists must be current.
 hipError_t launch_geodesic(const DevMesh &m, int n, const int32_t *face, const double *bary, const double *xyz,
-                           const int32_t *cand_cnt, const int32_t *cand, int cap_c, const int32_t *order,
-                           const GeoParams &gp, GeoOut out, char *stack_mem, int32_t nslots, int32_t *work_ctr,
-                           Counters *ctr, bool fp32, long long *prof, hipStream_t s);
+                           const PrefilterBufs &pb, double cutoff, const GeoParams &gp, GeoOut out, char *stack_mem,
+                           int32_t nslots, int32_t *work_ctr, Counters *ctr, bool fp32, long long *prof,
+                           hipStream_t s);
+// positions + cell counting sort in one workgroup (ncell <= kSmallCells)
+constexpr int kSmallCells = 4096;
+hipError_t launch_bin_small(const DevMesh &m, int n, const int32_t *face, const double *bary, PrefilterBufs &b,
+                            hipStream_t s);
 int max_candidates_per_source();
 
 hipError_t launch_bin_scatter(int n, PrefilterBufs &b, hipStream_t s);
 hipError_t launch_i64_to_i32(const int64_t *in, int32_t *out, int n, hipStream_t s);
 
-hipError_t launch_prefilter_rows(int n, double cutoff, PrefilterBufs &b, int32_t *overflow, hipStream_t s);
 hipError_t launch_count_rows(int n, const int32_t *cnt, int cap_c, const double *dist, double cutoff, int32_t *out,
                              hipStream_t s);
 hipError_t launch_compact_rows(int n, const int32_t *cnt, int cap_c, const int32_t *cand, const double *dist,
@@ -142,6 +151,24 @@ hipError_t launch_sum(const double *x, int n, double *out, double *scratch, hipS
 hipError_t launch_integrate(const DevMesh &m, int n, const int32_t *face, const double *F, int kind, double dt,
                             double mobility, double kT, double friction, uint64_t seed, uint64_t step,
                             double *disp, hipStream_t s);
+// fused force + integrator + walk of one time step
+struct UpdateArgs {
+    int32_t *face;
+    double *bary, *vel;
+    const int32_t *cnt;
+    int cap;
+    const double *dist, *tan;
+    double cutoff;
+    int kind;  // potential
+    double k, sigma;
+    int ikind;  // integrator
+    double dt, mobility, kT, friction;
+    uint64_t seed, step;
+    uint8_t *flags;
+    unsigned long long *npairs;  // neighbour pairs, summed
+    unsigned long long *stats;   // walk counters [5] or null
+};
+hipError_t launch_update(const DevMesh &m, int n, const UpdateArgs &u, hipStream_t s);
 hipError_t launch_walk(const DevMesh &m, int n, int32_t *face, double *bary, const double *disp, double *vel,
                        unsigned long long *stats, uint8_t *flags, hipStream_t s);
 

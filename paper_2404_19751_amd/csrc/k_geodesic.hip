@@ -108,17 +108,18 @@ __device__ inline void load_rec(const Rec32 &q, Win<float> &w) {
 // half-edge record in the working precision
 template <typename R>
 struct He {
-    R L, cx, cy, Lp, Ln;
+    R L, cx, cy, Lp, Ln, ex, ey, ux, uy;
     int tn, tp, opp;
     bool pseudo;
 };
 __device__ inline He<double> load_he(const DevMesh &m, int h, double) {
     const HeRec r = m.he[h];
-    return {r.L, r.cx, r.cy, r.Lp, r.Ln, r.tn, r.tp, r.opp, (r.flags & 1) != 0};
+    return {r.L, r.cx, r.cy, r.Lp, r.Ln, r.ex, r.ey, r.ux, r.uy, r.tn, r.tp, r.opp, (r.flags & 1) != 0};
 }
 __device__ inline He<float> load_he(const DevMesh &m, int h, float) {
     const HeRecF r = m.hef[h];
-    return {r.L, r.cx, r.cy, r.Lp, r.Ln, r.tn, r.tp, r.opp_flags >> 1, (r.opp_flags & 1) != 0};
+    return {r.L, r.cx, r.cy, r.Lp, r.Ln, r.ex, r.ey, r.ux, r.uy, r.tn, r.tp, r.opp_flags >> 1,
+            (r.opp_flags & 1) != 0};
 }
 
 struct GeoArgs {
@@ -127,27 +128,30 @@ struct GeoArgs {
     const int32_t *face;
     const double *bary;
     const double *xyz;
-    const int32_t *cand_cnt;  // [n]
-    const int32_t *cand;      // [n][cap_c], each row sorted by j
+    int32_t *cand_cnt;        // [n] out: candidates per source
+    int32_t *cand;            // [n][cap_c] out: candidate rows sorted by j
     int cap_c;
-    const int32_t *order;
+    const int32_t *order;     // particles sorted by cell (also the source order)
+    const int32_t *cell_of, *cell_start;
+    int dims[3];
+    double cut2;              // squared Euclidean prefilter radius
     GeoParams gp;
     GeoOut out;               // [n][cap_c] rows
     void *stack;              // per wave: stack_cap records of 64 bytes
     int32_t *work;
     Counters *ctr;
-    long long *prof;  // optional [n][4]: cycles, loop iterations, windows, launches per source
+    long long *prof;  // optional [n][8]: cycles, loop iterations, windows, launches, setup / loop / launch / result cycles
 };
 
 struct Lds {
     int32_t tj[kMaxCand], tface[kMaxCand], tnext[kMaxCand];
     double tb[kMaxCand][3];
-    double tx3[kMaxCand][3];
+    alignas(16) double cb[kMaxCand][4];  // target position and current pruning bound
     double d1[kMaxCand], d2[kMaxCand], t1x[kMaxCand], t1y[kMaxCand];
     int32_t head[kHash];
     int32_t rkey[kRootCap + 1];
     double rD[kRootCap], rL[kRootCap], rtx[kRootCap], rty[kRootCap];
-    int32_t rcount, dirty;
+    int32_t rcount, dirty, ncand;
     int32_t sel[kRootCap + 1];   // launch list: root slots
     int32_t pref[kRootCap + 2];  // prefix sums of their fan sizes
     alignas(16) unsigned char stk[kStackBytes];
@@ -192,16 +196,14 @@ struct Ctx {
 __device__ inline bool reaches_target(const Lds &L, const Ctx &C, const double P[3], const double u[3], double x0,
                                       double x1, double base) {
     for (int s = 0; s < C.nc; ++s) {
-        const double bound = fmin(C.cut_acc, L.d1[s] * (1.0 + C.tie_rel) + C.lb_slack);
-        const double rem = bound - base;
-        if (!(rem > 0.0)) continue;
-        double q0 = L.tx3[s][0] - P[0], q1 = L.tx3[s][1] - P[1], q2 = L.tx3[s][2] - P[2];
+        const double rem = L.cb[s][3] - base;
+        double q0 = L.cb[s][0] - P[0], q1 = L.cb[s][1] - P[1], q2 = L.cb[s][2] - P[2];
         double t = q0 * u[0] + q1 * u[1] + q2 * u[2];
         t = fmin(fmax(t, x0), x1);
         q0 -= t * u[0];
         q1 -= t * u[1];
         q2 -= t * u[2];
-        if (q0 * q0 + q1 * q1 + q2 * q2 < rem * rem) return true;
+        if (rem > 0.0 && q0 * q0 + q1 * q1 + q2 * q2 < rem * rem) return true;
     }
     return false;
 }
@@ -221,6 +223,7 @@ __device__ inline void target_update(Lds &L, const Ctx &C, bool ok, int slot, do
                 L.d1[slot] = d;
                 L.t1x[slot] = tx;
                 L.t1y[slot] = ty;
+                L.cb[slot][3] = fmin(C.cut_acc, d * (1.0 + C.tie_rel) + C.lb_slack);
             } else if (differ) {
                 L.d2[slot] = fmin(L.d2[slot], d);
             }
@@ -346,17 +349,18 @@ __device__ inline void child_right(const He<R> &h, const Win<R> &w, double txc, 
 }
 
 // Both children of a window. F3: the face's vertices in 3D in the order
-// (A, B, C) = (tail, head, opposite) of the entry half-edge.
+// (A, B, C) = (tail, head, opposite) of the entry half-edge; U3: the unit
+// directions of the half-edges (A->B, B->C, C->A).
 template <typename R>
 __device__ inline void children(const He<R> &h, const Win<R> &w, double txc, bool full, const Ctx &C,
-                                const double F3[3][3], const Lds &L, Win<R> &cl, bool &hl, Win<R> &cr, bool &hr,
-                                int &pruned) {
+                                const double F3[3][3], const double U3[3][3], const Lds &L, Win<R> &cl, bool &hl,
+                                Win<R> &cr, bool &hr, int &pruned) {
     hl = false;
     hr = false;
     if (h.tp >= 0 && (full || (double)w.b0 < txc)) {
         double x0, x1;
         child_left(h, w, txc, full, x0, x1);
-        const R ex = h.cx / h.Lp, ey = h.cy / h.Lp;
+        const R ex = h.ex, ey = h.ey;
         cl.px = ex * w.px + ey * w.py;
         cl.py = ex * w.py - ey * w.px;
         cl.b0 = (R)x0;
@@ -367,10 +371,9 @@ __device__ inline void children(const He<R> &h, const Win<R> &w, double txc, boo
         cl.he = h.tp;
         cl.root = w.root;
         if (x1 - x0 > 1e-12 * (double)h.Lp) {
-            double base = (double)w.sg + (double)seg_dist(cl.px, cl.py, cl.b0, cl.b1);
-            double u[3] = {F3[2][0] - F3[0][0], F3[2][1] - F3[0][1], F3[2][2] - F3[0][2]};
-            double il = 1.0 / sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-            u[0] *= il; u[1] *= il; u[2] *= il;
+            const double base = (double)w.sg + (double)seg_dist(cl.px, cl.py, cl.b0, cl.b1);
+            // edge A -> C is the reverse of half-edge prev = (C -> A)
+            const double u[3] = {-U3[2][0], -U3[2][1], -U3[2][2]};
             if (reaches_target(L, C, F3[0], u, x0, x1, base)) hl = true;
             else ++pruned;
         }
@@ -378,7 +381,7 @@ __device__ inline void children(const He<R> &h, const Win<R> &w, double txc, boo
     if (h.tn >= 0 && (full || (double)w.b1 > txc)) {
         double x0, x1;
         child_right(h, w, txc, full, x0, x1);
-        const R ux = (h.L - h.cx) / h.Ln, uy = -h.cy / h.Ln;
+        const R ux = h.ux, uy = h.uy;
         const R qx = w.px - h.cx, qy = w.py - h.cy;
         cr.px = ux * qx + uy * qy;
         cr.py = ux * qy - uy * qx;
@@ -390,24 +393,25 @@ __device__ inline void children(const He<R> &h, const Win<R> &w, double txc, boo
         cr.he = h.tn;
         cr.root = w.root;
         if (x1 - x0 > 1e-12 * (double)h.Ln) {
-            double base = (double)w.sg + (double)seg_dist(cr.px, cr.py, cr.b0, cr.b1);
-            double u[3] = {F3[1][0] - F3[2][0], F3[1][1] - F3[2][1], F3[1][2] - F3[2][2]};
-            double il = 1.0 / sqrt(u[0] * u[0] + u[1] * u[1] + u[2] * u[2]);
-            u[0] *= il; u[1] *= il; u[2] *= il;
+            const double base = (double)w.sg + (double)seg_dist(cr.px, cr.py, cr.b0, cr.b1);
+            // edge C -> B is the reverse of half-edge next = (B -> C)
+            const double u[3] = {-U3[1][0], -U3[1][1], -U3[1][2]};
             if (reaches_target(L, C, F3[2], u, x0, x1, base)) hr = true;
             else ++pruned;
         }
     }
 }
 
-__device__ inline void face_xyz(const DevMesh &m, int f, int k, double F3[3][3]) {
-    const double *p = m.fpos + 9 * (int64_t)f;
+__device__ inline void face_xyz(const DevMesh &m, int f, int k, double F3[3][3], double U3[3][3]) {
+    const double *p = m.fpos + 18 * (int64_t)f;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
         const int q = (k + i) % 3;
-        F3[i][0] = p[3 * q];
-        F3[i][1] = p[3 * q + 1];
-        F3[i][2] = p[3 * q + 2];
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            F3[i][d] = p[3 * q + d];
+            U3[i][d] = p[9 + 3 * q + d];
+        }
     }
 }
 
@@ -459,8 +463,8 @@ __device__ void launch_roots(const GeoArgs &a, Lds &L, const Ctx &C, Stack<R> &S
             const double vx = a.m.V[3 * (int64_t)v], vy = a.m.V[3 * (int64_t)v + 1], vz = a.m.V[3 * (int64_t)v + 2];
             bool useful = false;
             for (int s = 0; s < C.nc && !useful; ++s) {
-                const double bound = fmin(C.cut_acc, L.d1[s] * (1.0 + C.tie_rel) + C.lb_slack) - D;
-                const double q0 = L.tx3[s][0] - vx, q1 = L.tx3[s][1] - vy, q2 = L.tx3[s][2] - vz;
+                const double bound = L.cb[s][3] - D;
+                const double q0 = L.cb[s][0] - vx, q1 = L.cb[s][1] - vy, q2 = L.cb[s][2] - vz;
                 useful = bound > 0.0 && q0 * q0 + q1 * q1 + q2 * q2 < bound * bound;
             }
             if (useful) deg = a.m.fan_off[v + 1] - a.m.fan_off[v];
@@ -512,11 +516,10 @@ __device__ void launch_roots(const GeoArgs &a, Lds &L, const Ctx &C, Stack<R> &S
             nw.s = R(0);
             nw.he = Rn.twin;
             nw.root = el;
-            double F3[3][3];
-            face_xyz(a.m, h / 3, h % 3, F3);  // (v, u1, u2)
-            double u[3] = {F3[1][0] - F3[2][0], F3[1][1] - F3[2][1], F3[1][2] - F3[2][2]};
-            const double il = 1.0 / Rn.L;
-            u[0] *= il; u[1] *= il; u[2] *= il;
+            double F3[3][3], U3[3][3];
+            face_xyz(a.m, h / 3, h % 3, F3, U3);  // (v, u1, u2)
+            // the window's edge runs u2 -> u1: the reverse of half-edge next(h) = (u1 -> u2)
+            const double u[3] = {-U3[1][0], -U3[1][1], -U3[1][2]};
             want = reaches_target(L, C, F3[2], u, 0.0, Rn.L, D + seg_dist(px, py, 0.0, Rn.L));
         }
         // direct targets in face(h)
@@ -527,7 +530,7 @@ __device__ void launch_roots(const GeoArgs &a, Lds &L, const Ctx &C, Stack<R> &S
             const bool ok = slot >= 0;
             double d = 0;
             if (ok) {
-                const double dx = L.tx3[slot][0] - pv[0], dy = L.tx3[slot][1] - pv[1], dz = L.tx3[slot][2] - pv[2];
+                const double dx = L.cb[slot][0] - pv[0], dy = L.cb[slot][1] - pv[1], dz = L.cb[slot][2] - pv[2];
                 d = D + sqrt(dx * dx + dy * dy + dz * dz);
             }
             target_update(L, C, ok, slot, d, vtx, vty);
@@ -544,6 +547,49 @@ __device__ void launch_roots(const GeoArgs &a, Lds &L, const Ctx &C, Stack<R> &S
     }
 }
 
+// Euclidean prefilter of one source (the lower bound of Sec. 3.1): lanes 0-26
+// scan the 27 cells around it, the hits are rank-sorted by particle index in
+// LDS and written out as the source's candidate row. Returns the true count
+// (more than kMaxCand is an overflow the caller reports).
+__device__ int find_candidates(const GeoArgs &a, Lds &L, int src, int64_t c0) {
+    const int lane = lane_id();
+    if (lane == 0) L.ncand = 0;
+    __syncthreads();
+    const double xi = a.xyz[3 * (int64_t)src], yi = a.xyz[3 * (int64_t)src + 1], zi = a.xyz[3 * (int64_t)src + 2];
+    const int lin = a.cell_of[src];
+    const int cx = lin % a.dims[0], cy = (lin / a.dims[0]) % a.dims[1], cz = lin / (a.dims[0] * a.dims[1]);
+    if (lane < 27) {
+        const int x = cx + lane % 3 - 1, y = cy + (lane / 3) % 3 - 1, z = cz + lane / 9 - 1;
+        if (x >= 0 && x < a.dims[0] && y >= 0 && y < a.dims[1] && z >= 0 && z < a.dims[2]) {
+            const int c = (z * a.dims[1] + y) * a.dims[0] + x;
+            const int e1 = a.cell_start[c + 1];
+            for (int q = a.cell_start[c]; q < e1; ++q) {
+                const int j = a.order[q];
+                if (j == src) continue;
+                const double ex = a.xyz[3 * (int64_t)j] - xi, ey = a.xyz[3 * (int64_t)j + 1] - yi,
+                             ez = a.xyz[3 * (int64_t)j + 2] - zi;
+                if (ex * ex + ey * ey + ez * ez < a.cut2) {
+                    const int pos = atomicAdd(&L.ncand, 1);
+                    if (pos < kMaxCand) L.tnext[pos] = j;
+                }
+            }
+        }
+    }
+    __syncthreads();
+    const int total = L.ncand;
+    const int m = min(total, kMaxCand);
+    for (int s = lane; s < m; s += kWave) {
+        const int j = L.tnext[s];
+        int rank = 0;
+        for (int t = 0; t < m; ++t) rank += L.tnext[t] < j;
+        L.tj[rank] = j;
+    }
+    __syncthreads();
+    for (int s = lane; s < m; s += kWave) a.cand[c0 + s] = L.tj[s];
+    if (lane == 0) a.cand_cnt[src] = total;
+    return total;
+}
+
 // Geodesics from one source to its candidate targets; writes the row and
 // returns whether any pair lies inside the guard band of the cutoff.
 template <typename R>
@@ -552,7 +598,7 @@ __device__ bool run_source(const GeoArgs &a, Lds &L, int src, int64_t c0, int nc
     const int lane = lane_id();
     const long long t_start = clock64();
     const unsigned long long launches0 = st.launches;
-    long long iters = 0;
+    long long iters = 0, t_launch = 0;
     const bool fp32 = sizeof(R) == 4;
     Ctx C;
     C.cutoff = a.gp.cutoff;
@@ -583,14 +629,14 @@ __device__ bool run_source(const GeoArgs &a, Lds &L, int src, int64_t c0, int nc
     }
     __syncthreads();
     for (int s = lane; s < nc; s += kWave) {
-        int j = a.cand[c0 + s];
-        int f = a.face[j];
-        L.tj[s] = j;
+        const int j = L.tj[s];
+        const int f = a.face[j];
         L.tface[s] = f;
         for (int d = 0; d < 3; ++d) {
             L.tb[s][d] = a.bary[3 * (int64_t)j + d];
-            L.tx3[s][d] = a.xyz[3 * (int64_t)j + d];
+            L.cb[s][d] = a.xyz[3 * (int64_t)j + d];
         }
+        L.cb[s][3] = C.cut_acc;
         L.d1[s] = INFINITY;
         L.d2[s] = INFINITY;
         L.t1x[s] = 0.0;
@@ -663,9 +709,9 @@ __device__ bool run_source(const GeoArgs &a, Lds &L, int src, int64_t c0, int nc
                     // source on this edge: the face across contains it as well
                     const He<R> Ht = load_he(a.m, Rh.twin, R(0));
                     w.py = R(0);
-                    double F3[3][3];
-                    face_xyz(a.m, Rh.twin / 3, Rh.twin % 3, F3);
-                    children(Ht, w, 0.0, true, C, F3, L, wa, wantA, wb, wantB, pruned);
+                    double F3[3][3], U3[3][3];
+                    face_xyz(a.m, Rh.twin / 3, Rh.twin % 3, F3, U3);
+                    children(Ht, w, 0.0, true, C, F3, U3, L, wa, wantA, wb, wantB, pruned);
                 }
             }
         }
@@ -711,6 +757,7 @@ __device__ bool run_source(const GeoArgs &a, Lds &L, int src, int64_t c0, int nc
     }
 
     // ---- propagation
+    const long long t_loop = clock64();
     const bool eager = a.gp.eager != 0;
     bool have = false;
     Win<R> w;
@@ -723,7 +770,9 @@ __device__ bool run_source(const GeoArgs &a, Lds &L, int src, int64_t c0, int nc
         // bend-vertex launches: eagerly whenever the table is dirty, else
         // once nothing is left to propagate
         if (L.dirty && (eager || !busy)) {
+            const long long t0 = clock64();
             launch_roots(a, L, C, S, st);
+            t_launch += clock64() - t0;
             if (!busy) busy = S.refill(have, w);
         }
         if (!busy) {
@@ -747,14 +796,14 @@ __device__ bool run_source(const GeoArgs &a, Lds &L, int src, int64_t c0, int nc
         }
         He<R> H;
         double txc = 0.0;
-        double F3[3][3];
+        double F3[3][3], U3[3][3];
         int f = -1, k = 0;
         if (have) {
             // both records depend only on the entry half-edge: issue them together
             f = w.he / 3;
             k = w.he % 3;
             H = load_he(a.m, w.he, R(0));
-            face_xyz(a.m, f, k, F3);
+            face_xyz(a.m, f, k, F3, U3);
             txc = (double)w.px + ((double)H.cx - (double)w.px) * (-(double)w.py) / ((double)H.cy - (double)w.py);
         }
         // targets in face f
@@ -812,7 +861,7 @@ __device__ bool run_source(const GeoArgs &a, Lds &L, int src, int64_t c0, int nc
             }
             root_update(L, ok, have ? H.opp : 0, d, tx, ty, overflow);
         }
-        if (have) children(H, w, txc, false, C, F3, L, cl, hl, cr, hr, pruned);
+        if (have) children(H, w, txc, false, C, F3, U3, L, cl, hl, cr, hr, pruned);
         // keep one child in the lane, push the other
         S.push(hl && hr, cr, overflow);
         if (have) {
@@ -823,6 +872,7 @@ __device__ bool run_source(const GeoArgs &a, Lds &L, int src, int64_t c0, int nc
     }
 
     // ---- results (row of the candidate layout)
+    const long long t_res = clock64();
     const int32_t *T = a.m.T;
     const double *p0 = a.m.V + 3 * (int64_t)T[3 * fs], *p1 = a.m.V + 3 * (int64_t)T[3 * fs + 1];
     const double *nn = a.m.fnrm + 3 * (int64_t)fs;
@@ -849,11 +899,16 @@ __device__ bool run_source(const GeoArgs &a, Lds &L, int src, int64_t c0, int nc
     }
     const bool any_near = __ballot(near_cut) != 0;
     if (a.prof && lane == 0) {
-        long long *q = a.prof + 4 * (int64_t)src;
-        q[0] += clock64() - t_start;
+        long long *q = a.prof + 8 * (int64_t)src;
+        const long long t_end = clock64();
+        q[0] += t_end - t_start;
         q[1] += iters;
         q[2] += (long long)nwin;
         q[3] += (long long)(st.launches - launches0);
+        q[4] += t_loop - t_start;
+        q[5] += t_res - t_loop - t_launch;
+        q[6] += t_launch;
+        q[7] += t_end - t_res;
     }
     st.windows += nwin;
     st.pruned += pruned;
@@ -890,7 +945,7 @@ __global__ __launch_bounds__(kWave) void k_geodesic(GeoArgs a) {
         if (idx < 0) break;
         const int src = a.order[idx];
         const int64_t c0 = (int64_t)src * a.cap_c;
-        const int nc = a.cand_cnt[src];
+        const int nc = find_candidates(a, L, src, c0);
         if (nc <= 0) continue;
         if (nc > kMaxCand) {
             if (lane == 0) ++c_limited;
@@ -923,10 +978,17 @@ __global__ __launch_bounds__(kWave) void k_geodesic(GeoArgs a) {
 }  // namespace
 
 hipError_t launch_geodesic(const DevMesh &m, int n, const int32_t *face, const double *bary, const double *xyz,
-                           const int32_t *cand_cnt, const int32_t *cand, int cap_c, const int32_t *order,
-                           const GeoParams &gp, GeoOut out, char *stack_mem, int32_t nslots, int32_t *work_ctr,
-                           Counters *ctr, bool fp32, long long *prof, hipStream_t s) {
+                           const PrefilterBufs &pb, double cutoff, const GeoParams &gp, GeoOut out, char *stack_mem,
+                           int32_t nslots, int32_t *work_ctr, Counters *ctr, bool fp32, long long *prof,
+                           hipStream_t s) {
     GeoArgs a;
+    a.cell_of = pb.cell_of;
+    a.cell_start = pb.cell_start;
+    for (int d = 0; d < 3; ++d) a.dims[d] = pb.dims[d];
+    a.cut2 = cutoff * cutoff * (1.0 + 1e-12);
+    const int32_t *order = pb.order;
+    int32_t *cand_cnt = pb.cand_cnt, *cand = pb.cand;
+    const int cap_c = pb.cap_c;
     a.prof = prof;
     a.m = m;
     a.n = n;

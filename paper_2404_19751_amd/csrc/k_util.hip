@@ -4,6 +4,7 @@
 #include <cmath>
 
 #include "gsim_internal.h"
+#include "particle_ops.h"
 
 namespace gsim {
 
@@ -124,50 +125,62 @@ __global__ void k_bin_scatter(int n, PrefilterBufs b) {
     b.order[pos] = j;
 }
 
-// Candidate targets of each source: every particle whose Euclidean
-// distance is below the cutoff (the paper's lower bound, Sec. 3.1), from the
-// 27 cells around the source, kept sorted by particle index in a row of
-// fixed capacity. cand_cnt holds the true count; a count above the capacity
-// is reported through `overflow`.
-__global__ void k_candidates_rows(int n, double cut2, PrefilterBufs b, int32_t *__restrict__ overflow) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    const double xi = b.xyz[3 * i], yi = b.xyz[3 * i + 1], zi = b.xyz[3 * i + 2];
-    int lin = b.cell_of[i];
-    int cx = lin % b.dims[0], cy = (lin / b.dims[0]) % b.dims[1], cz = lin / (b.dims[0] * b.dims[1]);
-    int cnt = 0;
-    int32_t *row = b.cand + (int64_t)i * b.cap_c;
-    for (int dz = -1; dz <= 1; ++dz) {
-        int z = cz + dz;
-        if (z < 0 || z >= b.dims[2]) continue;
-        for (int dy = -1; dy <= 1; ++dy) {
-            int y = cy + dy;
-            if (y < 0 || y >= b.dims[1]) continue;
-            for (int dx = -1; dx <= 1; ++dx) {
-                int x = cx + dx;
-                if (x < 0 || x >= b.dims[0]) continue;
-                int c = (z * b.dims[1] + y) * b.dims[0] + x;
-                for (int a = b.cell_start[c]; a < b.cell_start[c + 1]; ++a) {
-                    int j = b.order[a];
-                    if (j == i) continue;
-                    double ex = b.xyz[3 * j] - xi, ey = b.xyz[3 * j + 1] - yi, ez = b.xyz[3 * j + 2] - zi;
-                    if (ex * ex + ey * ey + ez * ez < cut2) {
-                        if (cnt < b.cap_c) {
-                            int p = cnt;
-                            while (p > 0 && row[p - 1] > j) {
-                                row[p] = row[p - 1];
-                                --p;
-                            }
-                            row[p] = j;
-                        }
-                        ++cnt;
-                    }
-                }
-            }
+// Positions and the cell counting sort in a single workgroup: cell counts,
+// their exclusive scan and the scatter all live in LDS.
+constexpr int kBinThreads = 1024;
+__global__ __launch_bounds__(kBinThreads) void k_bin_small(const double *__restrict__ V, const int32_t *__restrict__ T,
+                                                           int n, const int32_t *__restrict__ face,
+                                                           const double *__restrict__ bary, PrefilterBufs b, BB bb) {
+    __shared__ int32_t cnt[kSmallCells];
+    __shared__ int32_t start[kSmallCells];
+    __shared__ int32_t part[kBinThreads];
+    const int t = threadIdx.x;
+    const int ncell = b.dims[0] * b.dims[1] * b.dims[2];
+    for (int c = t; c < ncell; c += kBinThreads) cnt[c] = 0;
+    __syncthreads();
+    for (int j = t; j < n; j += kBinThreads) {
+        const int f = face[j];
+        const double b0 = bary[3 * j], b1 = bary[3 * j + 1], b2 = bary[3 * j + 2];
+        const double *p0 = V + 3 * (int64_t)T[3 * f], *p1 = V + 3 * (int64_t)T[3 * f + 1],
+                     *p2 = V + 3 * (int64_t)T[3 * f + 2];
+        double x[3];
+        for (int d = 0; d < 3; ++d) {
+            x[d] = b0 * p0[d] + b1 * p1[d] + b2 * p2[d];
+            b.xyz[3 * j + d] = x[d];
         }
+        int c3[3];
+        cell_coords(x, b, bb.lo, c3);
+        const int lin = (c3[2] * b.dims[1] + c3[1]) * b.dims[0] + c3[0];
+        b.cell_of[j] = lin;
+        atomicAdd(&cnt[lin], 1);
     }
-    b.cand_cnt[i] = cnt;
-    if (cnt > b.cap_c) atomicAdd(overflow, 1);
+    __syncthreads();
+    // exclusive scan: each thread owns a contiguous chunk of cells
+    const int per = (ncell + kBinThreads - 1) / kBinThreads;
+    const int c0 = t * per, c1 = min(c0 + per, ncell);
+    int sum = 0;
+    for (int c = c0; c < c1; ++c) sum += cnt[c];
+    part[t] = sum;
+    __syncthreads();
+    for (int o = 1; o < kBinThreads; o <<= 1) {
+        const int add = t >= o ? part[t - o] : 0;
+        __syncthreads();
+        part[t] += add;
+        __syncthreads();
+    }
+    int run = part[t] - sum;
+    for (int c = c0; c < c1; ++c) {
+        start[c] = run;
+        b.cell_start[c] = run;
+        run += cnt[c];
+        cnt[c] = 0;
+    }
+    if (t == kBinThreads - 1) b.cell_start[ncell] = part[t];
+    __syncthreads();
+    for (int j = t; j < n; j += kBinThreads) {
+        const int lin = b.cell_of[j];
+        b.order[start[lin] + atomicAdd(&cnt[lin], 1)] = j;
+    }
 }
 
 // ------------------------------------------------------------ compaction
@@ -203,46 +216,17 @@ __global__ void k_compact_rows(int n, const int32_t *__restrict__ cnt, int cap, 
 }
 
 // ------------------------------------------------------------ forces
-// F_i = sum_j U'(d_ij) t_ij and E_i = (1/2) sum_j U(d_ij), ascending j, over
-// the pairs of the row closer than the cutoff.
 __global__ void k_forces_rows(int n, const int32_t *__restrict__ cnt, int cap, const double *__restrict__ dist,
                               const double *__restrict__ tan, double cutoff, int kind, double k, double sigma,
                               double *__restrict__ F, double *__restrict__ Ei, unsigned long long *__restrict__ npairs) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    double fx = 0.0, fy = 0.0, fz = 0.0, e = 0.0;
-    int m = min(cnt[i], cap), np = 0;
-    for (int s = 0; s < m; ++s) {
-        int64_t p = (int64_t)i * cap + s;
-        double d = dist[p];
-        if (!(d < cutoff)) continue;
-        ++np;
-        if (!(d > 0.0)) continue;
-        double U, dU;
-        if (kind == 0) {  // harmonic
-            if (d < sigma) {
-                double x = 1.0 - d / sigma;
-                U = 0.5 * k * x * x;
-                dU = -(k / sigma) * x;
-            } else {
-                U = 0.0;
-                dU = 0.0;
-            }
-        } else if (kind == 1) {  // coulomb
-            U = k / d;
-            dU = -k / (d * d);
-        } else {  // gaussian
-            U = k * exp(-d * d / (2.0 * sigma * sigma));
-            dU = -(d / (sigma * sigma)) * U;
-        }
-        fx += dU * tan[3 * p];
-        fy += dU * tan[3 * p + 1];
-        fz += dU * tan[3 * p + 2];
-        e += 0.5 * U;
-    }
-    F[3 * i] = fx;
-    F[3 * i + 1] = fy;
-    F[3 * i + 2] = fz;
+    double f[3], e;
+    int np;
+    row_force(i, cnt, cap, dist, tan, cutoff, kind, k, sigma, f, e, np);
+    F[3 * i] = f[0];
+    F[3 * i + 1] = f[1];
+    F[3 * i + 2] = f[2];
     Ei[i] = e;
     if (npairs && np) atomicAdd(npairs, (unsigned long long)np);
 }
@@ -273,56 +257,16 @@ __global__ void k_sum_final(const double *__restrict__ part, int nb, double *__r
 }
 
 // ------------------------------------------------------------ integrators
-// Philox4x32-10 (Salmon et al., SC'11): ten multiply-xor rounds, Weyl key
-// schedule.
-__device__ inline void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
-        uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
-        uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
-        c[0] = n0;
-        c[1] = lo1;
-        c[2] = n2;
-        c[3] = lo0;
-        k0 += 0x9E3779B9u;
-        k1 += 0xBB67AE85u;
-    }
-}
-
-__global__ void k_integrate(int n, const double *__restrict__ V, const int32_t *__restrict__ T,
-                            const double *__restrict__ fnrm, const int32_t *__restrict__ face,
-                            const double *__restrict__ F, int kind, double dt, double mob, double kT, double lam,
-                            uint64_t seed, uint64_t step, double *__restrict__ D) {
+__global__ void k_integrate(int n, DevMesh m, const int32_t *__restrict__ face, const double *__restrict__ F, int kind,
+                            double dt, double mob, double kT, double lam, uint64_t seed, uint64_t step,
+                            double *__restrict__ D) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
-    if (kind == 0) {
-        double s = mob * dt;
-        D[3 * i] = s * F[3 * i];
-        D[3 * i + 1] = s * F[3 * i + 1];
-        D[3 * i + 2] = s * F[3 * i + 2];
-        return;
-    }
-    // Brownian: lam D = dt F + sqrt(2 kT lam dt) (eta1 ex + eta2 ey)
-    uint32_t c[4] = {uint32_t(i), uint32_t(step), uint32_t(step >> 32), 0u};
-    philox10(c, uint32_t(seed), uint32_t(seed >> 32));
-    double u1 = (double(c[0] >> 5) * 67108864.0 + double(c[1] >> 6)) * (1.0 / 9007199254740992.0);
-    double u2 = (double(c[2] >> 5) * 67108864.0 + double(c[3] >> 6)) * (1.0 / 9007199254740992.0);
-    double r = sqrt(-2.0 * log(1.0 - u1));
-    double sn, cs;
-    sincos(2.0 * M_PI * u2, &sn, &cs);
-    double e1 = r * cs, e2 = r * sn;
-    int f = face[i];
-    const double *p0 = V + 3 * (int64_t)T[3 * f], *p1 = V + 3 * (int64_t)T[3 * f + 1];
-    double ex[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
-    double l = sqrt(ex[0] * ex[0] + ex[1] * ex[1] + ex[2] * ex[2]);
-    ex[0] /= l;
-    ex[1] /= l;
-    ex[2] /= l;
-    const double *nn = fnrm + 3 * (int64_t)f;
-    double ey[3] = {nn[1] * ex[2] - nn[2] * ex[1], nn[2] * ex[0] - nn[0] * ex[2], nn[0] * ex[1] - nn[1] * ex[0]};
-    double amp = sqrt(2.0 * kT * lam * dt) / lam, a = dt / lam;
-    for (int d = 0; d < 3; ++d) D[3 * i + d] = a * F[3 * i + d] + amp * (e1 * ex[d] + e2 * ey[d]);
+    double f[3] = {F[3 * i], F[3 * i + 1], F[3 * i + 2]}, d[3];
+    displacement(m, face[i], i, f, kind, dt, mob, kT, lam, seed, step, d);
+    D[3 * i] = d[0];
+    D[3 * i + 1] = d[1];
+    D[3 * i + 2] = d[2];
 }
 }  // namespace
 
@@ -364,9 +308,11 @@ hipError_t launch_prefilter_bin(const DevMesh &m, int n, PrefilterBufs &b, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_prefilter_rows(int n, double cutoff, PrefilterBufs &b, int32_t *overflow, hipStream_t s) {
-    double c2 = cutoff * cutoff * (1.0 + 1e-12);
-    hipLaunchKernelGGL(k_candidates_rows, dim3(nblocks(n, 64)), dim3(64), 0, s, n, c2, b, overflow);
+hipError_t launch_bin_small(const DevMesh &m, int n, const int32_t *face, const double *bary, PrefilterBufs &b,
+                            hipStream_t s) {
+    BB bb;
+    for (int d = 0; d < 3; ++d) bb.lo[d] = m.bbmin[d];
+    hipLaunchKernelGGL(k_bin_small, dim3(1), dim3(kBinThreads), 0, s, m.V, m.T, n, face, bary, b, bb);
     return hipGetLastError();
 }
 hipError_t launch_bin_scatter(int n, PrefilterBufs &b, hipStream_t s) {
@@ -407,8 +353,8 @@ hipError_t launch_sum(const double *x, int n, double *out, double *scratch, hipS
 hipError_t launch_integrate(const DevMesh &m, int n, const int32_t *face, const double *F, int kind, double dt,
                             double mobility, double kT, double friction, uint64_t seed, uint64_t step, double *disp,
                             hipStream_t s) {
-    hipLaunchKernelGGL(k_integrate, dim3(nblocks(n)), dim3(kBlock), 0, s, n, m.V, m.T, m.fnrm, face, F, kind, dt,
-                       mobility, kT, friction, seed, step, disp);
+    hipLaunchKernelGGL(k_integrate, dim3(nblocks(n)), dim3(kBlock), 0, s, n, m, face, F, kind, dt, mobility, kT,
+                       friction, seed, step, disp);
     return hipGetLastError();
 }
 

@@ -14,6 +14,7 @@
 #include <cmath>
 
 #include "gsim_internal.h"
+#include "particle_ops.h"
 
 namespace gsim {
 namespace {
@@ -33,25 +34,19 @@ __device__ inline double dot(d3 a, d3 b) { return a.x * b.x + a.y * b.y + a.z * 
 __device__ inline d3 cross(d3 a, d3 b) { return {a.y * b.z - a.z * b.y, a.z * b.x - a.x * b.z, a.x * b.y - a.y * b.x}; }
 __device__ inline d3 unit(d3 a) { return (1.0 / sqrt(dot(a, a))) * a; }
 
-__global__ __launch_bounds__(128) void k_walk(DevMesh m, int n, int32_t *__restrict__ face, double *__restrict__ bary,
-                       const double *__restrict__ disp, double *__restrict__ vel, unsigned long long *__restrict__ stats,
-                       uint8_t *__restrict__ flags) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int f = face[i];
-    double b[3] = {bary[3 * i], bary[3 * i + 1], bary[3 * i + 2]};
+struct WalkCounts {
+    unsigned cross_n, vhit, bhit, cap, near;
+};
+
+// Walk one particle (face f, barycentrics b) by displacement D, carrying the
+// velocity v along (when hv). D and v are projected onto f's plane first.
+__device__ inline void walk_one(const DevMesh &m, int &f, double b[3], d3 D, d3 &v, bool hv, WalkCounts &wc,
+                                uint8_t &fl) {
     d3 nf = ld3(m.fnrm + 3 * (int64_t)f);
-    d3 D = ld3(disp + 3 * (int64_t)i);
     D = D - dot(D, nf) * nf;
-    d3 v = {0, 0, 0};
-    const bool hv = vel != nullptr;
-    if (hv) {
-        v = ld3(vel + 3 * (int64_t)i);
-        v = v - dot(v, nf) * nf;
-    }
+    if (hv) v = v - dot(v, nf) * nf;
     double rem = sqrt(dot(D, D));
-    unsigned cross_n = 0, vhit = 0, bhit = 0, cap = 0, near = 0;
-    uint8_t fl = 0;
+    unsigned &cross_n = wc.cross_n, &vhit = wc.vhit, &bhit = wc.bhit, &cap = wc.cap, &near = wc.near;
     const double lbar = m.mean_edge;
     if (rem > 0.0) {
         d3 u = (1.0 / rem) * D;
@@ -192,6 +187,29 @@ __global__ __launch_bounds__(128) void k_walk(DevMesh m, int n, int32_t *__restr
             onlyk = -1;
         }
     }
+}
+
+__device__ inline void flush_counts(const WalkCounts &wc, unsigned long long *stats) {
+    if (!stats) return;
+    if (wc.cross_n) atomicAdd(&stats[0], (unsigned long long)wc.cross_n);
+    if (wc.vhit) atomicAdd(&stats[1], (unsigned long long)wc.vhit);
+    if (wc.bhit) atomicAdd(&stats[2], (unsigned long long)wc.bhit);
+    if (wc.cap) atomicAdd(&stats[3], (unsigned long long)wc.cap);
+    if (wc.near) atomicAdd(&stats[4], (unsigned long long)wc.near);
+}
+
+__global__ __launch_bounds__(128) void k_walk(DevMesh m, int n, int32_t *__restrict__ face, double *__restrict__ bary,
+                                              const double *__restrict__ disp, double *__restrict__ vel,
+                                              unsigned long long *__restrict__ stats, uint8_t *__restrict__ flags) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int f = face[i];
+    double b[3] = {bary[3 * i], bary[3 * i + 1], bary[3 * i + 2]};
+    const bool hv = vel != nullptr;
+    d3 v = hv ? ld3(vel + 3 * (int64_t)i) : d3{0, 0, 0};
+    WalkCounts wc = {0, 0, 0, 0, 0};
+    uint8_t fl = 0;
+    walk_one(m, f, b, ld3(disp + 3 * (int64_t)i), v, hv, wc, fl);
     face[i] = f;
     bary[3 * i] = b[0];
     bary[3 * i + 1] = b[1];
@@ -202,16 +220,47 @@ __global__ __launch_bounds__(128) void k_walk(DevMesh m, int n, int32_t *__restr
         vel[3 * i + 2] = v.z;
     }
     if (flags) flags[i] = fl;
-    if (stats) {
-        if (cross_n) atomicAdd(&stats[0], (unsigned long long)cross_n);
-        if (vhit) atomicAdd(&stats[1], (unsigned long long)vhit);
-        if (bhit) atomicAdd(&stats[2], (unsigned long long)bhit);
-        if (cap) atomicAdd(&stats[3], (unsigned long long)cap);
-        if (near) atomicAdd(&stats[4], (unsigned long long)near);
-    }
+    flush_counts(wc, stats);
+}
+
+// One full particle update of a time step, fused: the force from the
+// particle's neighbour row (Sec. 3.1 force sum), the displacement of the
+// integrator (Sec. 2.1), and the walk (Sec. 3.2). Rows hold only distances
+// and tangents computed before any particle moves, so particles are
+// independent here.
+__global__ __launch_bounds__(128) void k_update(DevMesh m, int n, UpdateArgs u) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int f = u.face[i];
+    double F[3], E;
+    int np;
+    row_force(i, u.cnt, u.cap, u.dist, u.tan, u.cutoff, u.kind, u.k, u.sigma, F, E, np);
+    double D[3];
+    displacement(m, f, i, F, u.ikind, u.dt, u.mobility, u.kT, u.friction, u.seed, u.step, D);
+    double b[3] = {u.bary[3 * i], u.bary[3 * i + 1], u.bary[3 * i + 2]};
+    d3 v = ld3(u.vel + 3 * (int64_t)i);
+    WalkCounts wc = {0, 0, 0, 0, 0};
+    uint8_t fl = 0;
+    walk_one(m, f, b, d3{D[0], D[1], D[2]}, v, true, wc, fl);
+    u.face[i] = f;
+    u.bary[3 * i] = b[0];
+    u.bary[3 * i + 1] = b[1];
+    u.bary[3 * i + 2] = b[2];
+    u.vel[3 * i] = v.x;
+    u.vel[3 * i + 1] = v.y;
+    u.vel[3 * i + 2] = v.z;
+    if (u.flags) u.flags[i] = fl;
+    if (np && u.npairs) atomicAdd(u.npairs, (unsigned long long)np);
+    flush_counts(wc, u.stats);
 }
 
 }  // namespace
+
+hipError_t launch_update(const DevMesh &m, int n, const UpdateArgs &u, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_update, dim3((n + 127) / 128), dim3(128), 0, s, m, n, u);
+    return hipGetLastError();
+}
 
 hipError_t launch_walk(const DevMesh &m, int n, int32_t *face, double *bary, const double *disp, double *vel,
                        unsigned long long *stats, uint8_t *flags, hipStream_t s) {

@@ -61,10 +61,20 @@ std::string build_host_mesh(int nv, const double *xyz, int nf, const int32_t *tr
     M.corner.assign(ne, 0.0);
     M.theta.assign(nv, 0.0);
     M.fnrm.assign(3 * size_t(nf), 0.0);
-    M.fpos.assign(9 * size_t(nf), 0.0);
+    M.fpos.assign(18 * size_t(nf), 0.0);
     for (int f = 0; f < nf; ++f)
-        for (int k = 0; k < 3; ++k)
-            for (int d = 0; d < 3; ++d) M.fpos[9 * size_t(f) + 3 * k + d] = M.V[3 * size_t(M.T[3 * f + k]) + d];
+        for (int k = 0; k < 3; ++k) {
+            V3 a = P(M.T[3 * f + k]), b = P(M.T[3 * f + (k + 1) % 3]);
+            V3 u = sub(b, a);
+            double l = nrm(u);
+            double *q = M.fpos.data() + 18 * size_t(f);
+            q[3 * k] = a.x;
+            q[3 * k + 1] = a.y;
+            q[3 * k + 2] = a.z;
+            q[9 + 3 * k] = u.x / l;
+            q[9 + 3 * k + 1] = u.y / l;
+            q[9 + 3 * k + 2] = u.z / l;
+        }
     double lsum = 0.0;
     int64_t lcnt = 0;
     M.min_edge = INFINITY;
@@ -152,6 +162,11 @@ std::string build_host_mesh(int nv, const double *xyz, int nf, const int32_t *tr
         r.cy = cy;
         r.Lp = nrm(w);
         r.Ln = nrm(sub(C, B));
+        // the same IEEE operations the kernels would do, so the values agree bit for bit
+        r.ex = cx / r.Lp;
+        r.ey = cy / r.Lp;
+        r.ux = (L - cx) / r.Ln;
+        r.uy = -cy / r.Ln;
         r.tn = M.twin[nxt(h)];
         r.tp = M.twin[prv(h)];
         r.opp = c;
@@ -165,6 +180,10 @@ std::string build_host_mesh(int nv, const double *xyz, int nf, const int32_t *tr
         q.cy = float(cy);
         q.Lp = float(r.Lp);
         q.Ln = float(r.Ln);
+        q.ex = q.cx / q.Lp;
+        q.ey = q.cy / q.Lp;
+        q.ux = (q.L - q.cx) / q.Ln;
+        q.uy = -q.cy / q.Ln;
         q.tn = r.tn;
         q.tp = r.tp;
         q.opp_flags = (c << 1) | r.flags;

@@ -1,0 +1,114 @@
+// Per-particle device operations shared by the force, integrator and fused
+// update kernels: the pair potentials, the force sum over a neighbour row,
+// Philox4x32-10 noise and the displacement of each integrator.
+#pragma once
+#include <cmath>
+
+#include "gsim_internal.h"
+
+namespace gsim {
+
+// U(d) and dU/dd. 0 harmonic: U = (k/2)(1 - d/sigma)^2 for d < sigma;
+// 1 coulomb: U = k/d; 2 gaussian: U = k exp(-d^2 / (2 sigma^2)) (Sec. 2.1).
+__device__ inline void pair_potential(int kind, double d, double k, double sigma, double &U, double &dU) {
+    if (kind == 0) {
+        if (d < sigma) {
+            const double x = 1.0 - d / sigma;
+            U = 0.5 * k * x * x;
+            dU = -(k / sigma) * x;
+        } else {
+            U = 0.0;
+            dU = 0.0;
+        }
+    } else if (kind == 1) {
+        U = k / d;
+        dU = -k / (d * d);
+    } else {
+        U = k * exp(-d * d / (2.0 * sigma * sigma));
+        dU = -(d / (sigma * sigma)) * U;
+    }
+}
+
+// F_i = sum_j U'(d_ij) t_ij and E_i = (1/2) sum_j U(d_ij) over the pairs of
+// row i closer than the cutoff, in ascending j; np = number of such pairs.
+__device__ inline void row_force(int i, const int32_t *__restrict__ cnt, int cap, const double *__restrict__ dist,
+                                 const double *__restrict__ tan, double cutoff, int kind, double k, double sigma,
+                                 double F[3], double &E, int &np) {
+    F[0] = F[1] = F[2] = 0.0;
+    E = 0.0;
+    np = 0;
+    const int m = min(cnt[i], cap);
+    for (int s = 0; s < m; ++s) {
+        const int64_t p = (int64_t)i * cap + s;
+        const double d = dist[p];
+        if (!(d < cutoff)) continue;
+        ++np;
+        if (!(d > 0.0)) continue;
+        double U, dU;
+        pair_potential(kind, d, k, sigma, U, dU);
+        F[0] += dU * tan[3 * p];
+        F[1] += dU * tan[3 * p + 1];
+        F[2] += dU * tan[3 * p + 2];
+        E += 0.5 * U;
+    }
+}
+
+// Philox4x32-10 (Salmon et al., SC'11): ten multiply-xor rounds with a Weyl
+// key schedule.
+__device__ inline void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint32_t hi0 = __umulhi(0xD2511F53u, c[0]), lo0 = 0xD2511F53u * c[0];
+        const uint32_t hi1 = __umulhi(0xCD9E8D57u, c[2]), lo1 = 0xCD9E8D57u * c[2];
+        const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+        c[0] = n0;
+        c[1] = lo1;
+        c[2] = n2;
+        c[3] = lo0;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+}
+
+// Two unit normals for (step, particle): counter (i, step lo, step hi, 0),
+// key (seed lo, seed hi); two 53-bit uniforms and Box-Muller.
+__device__ inline void gaussian_pair(uint64_t seed, uint64_t step, int i, double &e1, double &e2) {
+    uint32_t c[4] = {uint32_t(i), uint32_t(step), uint32_t(step >> 32), 0u};
+    philox10(c, uint32_t(seed), uint32_t(seed >> 32));
+    const double u1 = (double(c[0] >> 5) * 67108864.0 + double(c[1] >> 6)) * (1.0 / 9007199254740992.0);
+    const double u2 = (double(c[2] >> 5) * 67108864.0 + double(c[3] >> 6)) * (1.0 / 9007199254740992.0);
+    const double r = sqrt(-2.0 * log(1.0 - u1));
+    double sn, cs;
+    sincos(2.0 * M_PI * u2, &sn, &cs);
+    e1 = r * cs;
+    e2 = r * sn;
+}
+
+// Displacement of one particle in face f for one step (Sec. 2.1):
+// 0 overdamped D = mobility dt F;
+// 1 Brownian  lam D = dt F + sqrt(2 kT lam dt) (eta1 ex + eta2 ey), with
+//   (ex, ey) the face frame (ex along the face's first edge).
+__device__ inline void displacement(const DevMesh &m, int f, int i, const double F[3], int kind, double dt,
+                                    double mob, double kT, double lam, uint64_t seed, uint64_t step, double D[3]) {
+    if (kind == 0) {
+        const double s = mob * dt;
+        D[0] = s * F[0];
+        D[1] = s * F[1];
+        D[2] = s * F[2];
+        return;
+    }
+    double e1, e2;
+    gaussian_pair(seed, step, i, e1, e2);
+    const double *p0 = m.V + 3 * (int64_t)m.T[3 * f], *p1 = m.V + 3 * (int64_t)m.T[3 * f + 1];
+    double ex[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+    const double l = sqrt(ex[0] * ex[0] + ex[1] * ex[1] + ex[2] * ex[2]);
+    ex[0] /= l;
+    ex[1] /= l;
+    ex[2] /= l;
+    const double *nn = m.fnrm + 3 * (int64_t)f;
+    const double ey[3] = {nn[1] * ex[2] - nn[2] * ex[1], nn[2] * ex[0] - nn[0] * ex[2], nn[0] * ex[1] - nn[1] * ex[0]};
+    const double amp = sqrt(2.0 * kT * lam * dt) / lam, a = dt / lam;
+    for (int d = 0; d < 3; ++d) D[d] = a * F[d] + amp * (e1 * ex[d] + e2 * ey[d]);
+}
+
+}  // namespace gsim

@@ -252,7 +252,7 @@ class Context:
 
     def source_profile_stop(self, mid):
         n = self._n[mid]
-        out = np.zeros((n, 4), np.int64)
+        out = np.zeros((n, 8), np.int64)
         self._chk(self.L.gsim_source_profile(self.h, 0, _ptr(out), n))
         return out
 
