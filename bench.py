@@ -36,6 +36,13 @@ FP32_VECTOR_PEAK_TFLOPS = 157.3
 FLOPS_PER_WINDOW = 90.0
 
 
+WORKLOAD_TEXT = {
+    "c2": "bumpy sphere (icosphere L5, r=1+0.1 sin4t cos3p), 20480 faces, N=1000, harmonic sigma=cutoff=0.15, "
+          "overdamped dt=0.01",
+    "c4": "Gaussian-bump height field 10x10, 199712 faces, open boundary, N=20000, harmonic sigma=cutoff=3 mean "
+          "edges, Brownian kT=0.1 friction=1 dt=0.005",
+}
+
 PMC_FILE = os.path.join(ROOT, "profiles", "k_geodesic_bumpy_sphere_n1000_fp32mixed_pmc.json")
 
 
@@ -78,6 +85,8 @@ def main():
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32"])
+    ap.add_argument("--workload", default="c2", choices=["c2", "c4"],
+                    help="c2: bumpy sphere N=1000 (the default line); c4: open height field N=20000, Brownian")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
@@ -101,9 +110,13 @@ def main():
 
     from paper_2404_19751_amd import gsim, workloads as W
 
-    w = W.workload("c2")
+    w = W.workload(args.workload)
     pot = gsim.potential("harmonic", w.potential["k"], w.potential["sigma"], w.potential["cutoff"])
-    ig = gsim.integrator("overdamped", w.integrator["dt"], w.integrator["mobility"])
+    wi = w.integrator
+    if wi["kind"] == "brownian":
+        ig = gsim.integrator("brownian", wi["dt"], 1.0, wi["kT"], wi["friction"], wi["seed"])
+    else:
+        ig = gsim.integrator("overdamped", wi["dt"], wi["mobility"])
 
     def run(precision):
         ctx = gsim.Context(0, precision)
@@ -145,8 +158,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64" if args.precision == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": "bumpy sphere (icosphere L5, r=1+0.1 sin4t cos3p), 20480 faces, N=1000, "
-                               "harmonic sigma=cutoff=0.15, overdamped dt=0.01",
+        "config": {"workload": WORKLOAD_TEXT[args.workload],
                    "n_particles": n, "faces": w.mesh.nf, "cutoff": w.potential["cutoff"],
                    "precision": args.precision},
         "particle_steps_per_s": n * args.steps / dt,
@@ -155,7 +167,7 @@ def main():
         "windows_per_step": win_per_launch,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
-                     "traffic": measured_traffic() if args.precision == "fp32" else None,
+                     "traffic": measured_traffic() if (args.precision, args.workload) == ("fp32", "c2") else None,
                      "kernel": "k_geodesic", "per_unit": f"{FLOPS_PER_WINDOW:.0f} flop/window",
                      "units_per_launch": win_per_launch, "avg_launch_ms": geo_ms},
     }

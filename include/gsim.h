@@ -162,6 +162,18 @@ gsim_status gsim_displace_on_surface(gsim_ctx *ctx, int32_t mesh_id, const doubl
 gsim_status gsim_step(gsim_ctx *ctx, int32_t mesh_id, const gsim_potential *pot, const gsim_integrator *integ,
                       int32_t nsteps);
 
+/* step_batched: nsteps full time steps of several independent surfaces at
+ * once (the same per-surface work as gsim_step, Sec. 3.1 and 3.2). Every
+ * step is one binning, one geodesic and one update launch for the whole
+ * batch: the persistent geodesic grid takes sources from all surfaces, so
+ * small surfaces share the GPU instead of leaving it idle. mesh_ids[nmesh]
+ * (1..64 distinct meshes, each with particles), pots[nmesh], integs[nmesh].
+ * When timing is off and nsteps >= 2, groups of "graph_steps" steps are
+ * captured once into a HIP graph and replayed (the capture is cached until
+ * the batch, a buffer or a knob changes). gsim_step is the batch of one. */
+gsim_status gsim_step_batched(gsim_ctx *ctx, int32_t nmesh, const int32_t *mesh_ids, const gsim_potential *pots,
+                              const gsim_integrator *integs, int32_t nsteps);
+
 /* ---- tuning ----------------------------------------------------------------
  * Knobs of the geodesic kernel (set by the autotuner or by hand; results stay
  * exact, only the amount of work or the launch shape changes):
@@ -172,8 +184,24 @@ gsim_status gsim_step(gsim_ctx *ctx, int32_t mesh_id, const gsim_potential *pot,
  *   "cone_tol"      closed-cone slack relative to the edge length
  *   "tie_rel"       relative gap under which a pair is flagged as a tie
  *   "tie_dir"       tangents closer than this angle (rad) count as one direction
- *   "guard_rel"     FP32-mixed: relative band around the cutoff recomputed in FP64 */
+ *   "guard_rel"     FP32-mixed: relative band around the cutoff recomputed in FP64
+ *   "lds_stack_kb"  window-stack depth in LDS per wavefront: 4, 8 or 16 KiB (sets
+ *                   how many wavefronts fit on a compute unit)
+ *   "grab"          consecutive sources a wavefront claims at a time (1 .. 64)
+ *   "update_block"  workgroup size of the fused update kernel: 64, 128 or 256
+ *   "graph_steps"   steps captured per HIP graph in step calls (0 = no graphs) */
 gsim_status gsim_tune_set(gsim_ctx *ctx, const char *name, double value);
+
+/* autotune: times the geodesic pass of the given batch (current particle
+ * state, pots[nmesh] cutoffs) for LDS stack depths {4, 8, 16} KiB x sources
+ * per claim {1, 2, 4}, and the fused update kernel for workgroup sizes
+ * {64, 128, 256} on a scratch copy of the particle state (integs[nmesh]);
+ * keeps the fastest of each (best of `reps` runs) in the context. Particle
+ * state is left unchanged; results of later calls do not depend on the
+ * choice. out (may be NULL) receives [lds_stack_kb, grab, update_block,
+ * best geodesic-pass ms]. */
+gsim_status gsim_autotune(gsim_ctx *ctx, int32_t nmesh, const int32_t *mesh_ids, const gsim_potential *pots,
+                          const gsim_integrator *integs, int32_t reps, double *out);
 
 /* ---- instrumentation ------------------------------------------------------
  * Per-kernel timing with HIP events recorded on the context's stream, only

@@ -1,7 +1,15 @@
 // C-ABI of the gsim library: context, mesh upload, particle state and the
 // hot-path entry points. Device memory belongs to the context; host buffers
 // are borrowed for the duration of a call. No exception crosses the ABI.
+//
+// Every hot-path call runs as a batch of surfaces (a single mesh is a batch
+// of one): the host prepares each surface's buffers and fills its
+// descriptor, the descriptor table goes to device memory when it changed,
+// and one binning, one geodesic and one update launch serve the whole
+// batch. Steps queue without host synchronisation; several steps can be
+// captured once into a HIP graph and replayed.
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -24,28 +32,30 @@ struct Buf {
 struct MeshState {
     HostMesh host;
     DevMesh dm;
-    std::vector<Buf> owned;
     // particles
     int n = 0;
     int32_t *face = nullptr;
     double *bary = nullptr, *vel = nullptr, *xyz = nullptr;
     // prefilter
-    Buf cell_of, cell_start, cell_fill, order, cand_cnt, cand_off, cand, tmp64;
+    Buf cell_of, cell_start, cell_fill, order, cand_cnt, cand, tmp64;
     // candidate-layout results
     Buf cdist, ctan, cflags;
     // pairs
     Buf nbr_cnt, off, nbr, dist, tan, flags;
-    int64_t n_cand = 0, n_pairs = 0;
-    double pairs_cutoff = -1.0;
-    bool pairs_valid = false;
+    int64_t n_pairs = 0;
     // forces / integrator
-    Buf F, Ei, E, disp, wflags, guard;
-    uint64_t step = 0;  // steps taken since the state was set: the noise counter
+    Buf F, Ei, E, disp, wflags, step_dev;
+    uint64_t step = 0;  // steps taken since the state was set: the noise counter (host mirror)
 };
 
 struct TimingRec {
     double total_ms = 0.0;
     int64_t n = 0;
+};
+
+struct GraphRec {
+    hipGraphExec_t exec = nullptr;
+    int steps = 0;
 };
 
 }  // namespace
@@ -57,19 +67,29 @@ struct gsim_ctx {
     bool own_stream = false;
     std::string err;
     std::vector<MeshState *> meshes;
-    Buf stack, work, ctr, wstats, scan_scratch, sum_scratch, pf_over, prof;
+    Buf stack, work, ctr, wstats, scan_scratch, sum_scratch, pf_over, prof, desc;
+    SurfDesc *desc_pinned = nullptr;  // staging for descriptor uploads
+    std::vector<SurfDesc> desc_cached;
     bool profile_sources = false;
     int prof_n = 0;
     int64_t passes = 0;
-    int32_t nslots = 0;
     GeoParams gp{};
     Counters last{};
     unsigned long long cum_pairs = 0, cum_windows = 0, cum_passes = 0;
     bool timing = false;
+    bool capturing = false;
     std::map<std::string, TimingRec> times;
     std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> pending;
     std::vector<hipEvent_t> free_events;
-    int max_slots = 2048;
+    // launch shape
+    int max_slots = 65536;
+    int lds_stack_kb = 16;
+    int grab = 1;
+    int update_block = 128;
+    int cus = 256;
+    // graphs
+    int graph_steps = 50;  // steps captured per graph (0: no graphs)
+    std::map<std::string, GraphRec> graphs;
 };
 
 namespace {
@@ -136,19 +156,21 @@ void resolve_timing(gsim_ctx *c) {
     c->pending.clear();
 }
 
+// HIP events around one stage, only while timing is on (never inside a
+// graph capture).
 struct Stage {
     gsim_ctx *c;
     const char *name;
     hipEvent_t a = nullptr, b = nullptr;
     Stage(gsim_ctx *c_, const char *n) : c(c_), name(n) {
-        if (c->timing) {
+        if (c->timing && !c->capturing) {
             a = take_event(c);
             b = take_event(c);
             if (a) (void)hipEventRecord(a, c->stream);
         }
     }
     ~Stage() {
-        if (c->timing && a && b) {
+        if (a && b) {
             (void)hipEventRecord(b, c->stream);
             c->pending.push_back({name, {a, b}});
             if (c->pending.size() > 4096) resolve_timing(c);
@@ -162,8 +184,9 @@ MeshState *get_mesh(gsim_ctx *c, int32_t id) {
 }
 
 bool finite_cutoff(double c) { return c > 0.0 && std::isfinite(c); }
+int pot_kind_ok(const gsim_potential *p) { return p && p->kind >= 0 && p->kind <= 2; }
 
-// ---------------------------------------------------------------- pairs
+// ---------------------------------------------------------------- calls
 // A call (geodesic_pairs, compute_forces, step) zeroes the device counters,
 // queues its work without any host synchronisation, and reads the counters
 // back once at the end.
@@ -185,36 +208,51 @@ gsim_status end_call(gsim_ctx *c) {
     if (over || c->last.limited)
         return fail(c, GSIM_E_LIMIT,
                     std::to_string(over + (long long)c->last.limited) +
-                        " source(s) exceeded a per-source limit (more than " +
-                        std::to_string(max_candidates_per_source()) +
+                        " source(s) exceeded a per-source limit (more than " + std::to_string(kCandCap) +
                         " candidate targets within the cutoff, more than 254 bend vertices, window stack or window "
                         "count); the results of this call are incomplete");
     return GSIM_OK;
 }
 
-// Candidate rows and geodesics for every source, device-only.
-gsim_status pairs_device(gsim_ctx *c, MeshState *ms, double cutoff) {
-    hipStream_t s = c->stream;
-    const int n = ms->n;
-    if (n <= 0) return fail(c, GSIM_E_STATE, "no particles on this mesh");
-    if (!finite_cutoff(cutoff)) return fail(c, GSIM_E_ARG, "cutoff must be positive and finite");
-    DevMesh &m = ms->dm;
-    const int cap = max_candidates_per_source();
-    const bool fp32 = c->prec == GSIM_FP32_MIXED;
-    if (fp32 && 3 * (int64_t)m.nf >= (int64_t(1) << 24))
-        return fail(c, GSIM_E_LIMIT, "FP32-mixed mode packs half-edge ids in 24 bits: mesh too large");
-    // cell grid: cells no smaller than the cutoff, at most 128 per axis
-    PrefilterBufs pb{};
+// ---------------------------------------------------------------- batches
+// Cell grid of one surface: cells no smaller than the cutoff and at most
+// 128 per axis; `small` forces at most kSmallCells cells (one binning
+// workgroup per surface) by widening the cells.
+void choose_grid(const DevMesh &m, double cutoff, bool small, int dims[3], double &cell) {
     double ext = 0.0;
     for (int d = 0; d < 3; ++d) ext = std::max(ext, m.bbmax[d] - m.bbmin[d]);
-    const double cell = std::max(cutoff, ext / 128.0);
-    int64_t ncell = 1;
-    for (int d = 0; d < 3; ++d) {
-        pb.dims[d] = std::max(1, (int)std::ceil((m.bbmax[d] - m.bbmin[d]) / cell));
-        ncell *= pb.dims[d];
+    cell = std::max(cutoff, ext / 128.0);
+    for (;;) {
+        int64_t ncell = 1;
+        for (int d = 0; d < 3; ++d) {
+            dims[d] = std::max(1, (int)std::ceil((m.bbmax[d] - m.bbmin[d]) / cell));
+            ncell *= dims[d];
+        }
+        if (!small || ncell <= kSmallCells) return;
+        cell *= 1.0625;
     }
-    pb.cell = cell;
-    pb.cap_c = cap;
+}
+
+struct Member {
+    MeshState *ms;
+    double cutoff;
+    const gsim_potential *pot;     // may be null (geodesics only)
+    const gsim_integrator *integ;  // may be null
+};
+
+// Buffers and descriptor of one surface of a batch.
+gsim_status prepare_surface(gsim_ctx *c, const Member &mb, bool small, int src_begin, SurfDesc &d) {
+    MeshState *ms = mb.ms;
+    const int n = ms->n;
+    const DevMesh &m = ms->dm;
+    if (n <= 0) return fail(c, GSIM_E_STATE, "no particles on this mesh");
+    if (!finite_cutoff(mb.cutoff)) return fail(c, GSIM_E_ARG, "cutoff must be positive and finite");
+    if (c->prec == GSIM_FP32_MIXED && 3 * (int64_t)m.nf >= (int64_t(1) << 24))
+        return fail(c, GSIM_E_LIMIT, "FP32-mixed mode packs half-edge ids in 24 bits: mesh too large");
+    std::memset(&d, 0, sizeof(d));
+    choose_grid(m, mb.cutoff, small, d.dims, d.cell);
+    const int64_t ncell = (int64_t)d.dims[0] * d.dims[1] * d.dims[2];
+    const size_t cap = kCandCap;
     HIPCHK(c, ensure(ms->cell_of, sizeof(int32_t) * n));
     HIPCHK(c, ensure(ms->cell_start, sizeof(int32_t) * (ncell + 1)));
     HIPCHK(c, ensure(ms->cell_fill, sizeof(int32_t) * ncell));
@@ -225,59 +263,177 @@ gsim_status pairs_device(gsim_ctx *c, MeshState *ms, double cutoff) {
     HIPCHK(c, ensure(ms->ctan, sizeof(double) * 3 * (size_t)n * cap));
     HIPCHK(c, ensure(ms->cflags, (size_t)n * cap));
     HIPCHK(c, ensure(ms->tmp64, sizeof(int64_t) * (std::max<int64_t>(ncell, n) + 1)));
+    HIPCHK(c, ensure(ms->wflags, n));
     HIPCHK(c, ensure(c->scan_scratch, sizeof(int64_t) * ((std::max<int64_t>(ncell, n) + 1023) / 1024 + 2)));
-    GeoParams gp = c->gp;
-    gp.cutoff = cutoff;
-    if (!(gp.launch_delta > 0.0)) gp.launch_delta = 0.5 * m.mean_edge;
-    const int32_t nslots = std::min<int32_t>(n, c->max_slots);
-    HIPCHK(c, ensure(c->stack, (size_t)nslots * gp.stack_cap * 64));
-    if (c->profile_sources && c->prof_n != n) {
-        HIPCHK(c, ensure(c->prof, sizeof(long long) * 8 * (size_t)n));
-        HIPCHK(c, launch_zero_u64(P<unsigned long long>(c->prof), 8 * (int64_t)n, s));
-        c->prof_n = n;
+    d.m = m;
+    d.n = n;
+    d.src_begin = src_begin;
+    d.face = ms->face;
+    d.bary = ms->bary;
+    d.vel = ms->vel;
+    d.xyz = ms->xyz;
+    d.cell_of = P<int32_t>(ms->cell_of);
+    d.cell_start = P<int32_t>(ms->cell_start);
+    d.order = P<int32_t>(ms->order);
+    for (int k = 0; k < 3; ++k) d.lo[k] = m.bbmin[k];
+    d.cand_cnt = P<int32_t>(ms->cand_cnt);
+    d.cand = P<int32_t>(ms->cand);
+    d.cdist = P<double>(ms->cdist);
+    d.ctan = P<double>(ms->ctan);
+    d.cflags = P<uint8_t>(ms->cflags);
+    d.cutoff = mb.cutoff;
+    d.cut2 = mb.cutoff * mb.cutoff * (1.0 + 1e-12);
+    if (mb.pot) {
+        d.pkind = mb.pot->kind;
+        d.pk = mb.pot->k;
+        d.psigma = mb.pot->sigma;
     }
-    pb.xyz = ms->xyz;
-    pb.cell_of = P<int32_t>(ms->cell_of);
-    pb.cell_start = P<int32_t>(ms->cell_start);
-    pb.cell_fill = P<int32_t>(ms->cell_fill);
-    pb.order = P<int32_t>(ms->order);
-    pb.cand_cnt = P<int32_t>(ms->cand_cnt);
-    pb.cand = P<int32_t>(ms->cand);
+    if (mb.integ) {
+        d.ikind = mb.integ->kind;
+        d.dt = mb.integ->dt;
+        d.mobility = mb.integ->mobility;
+        d.kT = mb.integ->kT;
+        d.friction = mb.integ->friction;
+        d.seed = mb.integ->seed;
+    }
+    d.step = P<uint64_t>(ms->step_dev);
+    d.wflags = P<uint8_t>(ms->wflags);
+    return GSIM_OK;
+}
+
+struct Batch {
+    std::vector<Member> mem;
+    std::vector<SurfDesc> desc;
+    BatchIdx bi{};
+    bool small = true;  // every surface bins in one workgroup
+    int nslots = 0;
+    GeoShape shape{};
+};
+
+gsim_status upload_descs(gsim_ctx *c, const std::vector<SurfDesc> &d) {
+    const size_t bytes = sizeof(SurfDesc) * d.size();
+    if (c->desc_cached.size() == d.size() && std::memcmp(c->desc_cached.data(), d.data(), bytes) == 0)
+        return GSIM_OK;
+    if (c->capturing) return fail(c, GSIM_E_STATE, "descriptor change during graph capture");
+    std::memcpy(c->desc_pinned, d.data(), bytes);
+    HIPCHK(c, hipMemcpyAsync(c->desc.p, c->desc_pinned, bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->desc_cached = d;
+    return GSIM_OK;
+}
+
+// Buffers, descriptors and launch shape of a batch.
+gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
+    const int ns = (int)B.mem.size();
+    if (ns < 1 || ns > kMaxBatch) return fail(c, GSIM_E_ARG, "batch size must be 1.." + std::to_string(kMaxBatch));
+    for (int i = 0; i < ns; ++i)
+        for (int j = 0; j < i; ++j)
+            if (B.mem[i].ms == B.mem[j].ms) return fail(c, GSIM_E_ARG, "a mesh appears twice in the batch");
+    // a single surface may use the multi-kernel binning for a fine grid
+    B.small = true;
+    if (ns == 1) {
+        int dims[3];
+        double cell;
+        choose_grid(B.mem[0].ms->dm, B.mem[0].cutoff, false, dims, cell);
+        B.small = (int64_t)dims[0] * dims[1] * dims[2] <= kSmallCells;
+    }
+    B.desc.resize(ns);
+    B.bi.nsurf = ns;
+    int total = 0;
+    for (int i = 0; i < ns; ++i) {
+        B.bi.begin[i] = total;
+        gsim_status st = prepare_surface(c, B.mem[i], B.small || ns > 1, total, B.desc[i]);
+        if (st != GSIM_OK) return st;
+        total += B.mem[i].ms->n;
+    }
+    B.bi.begin[ns] = total;
+    if (c->profile_sources && ns == 1) {
+        const int n = B.mem[0].ms->n;
+        if (c->prof_n != n) {
+            HIPCHK(c, ensure(c->prof, sizeof(long long) * 8 * (size_t)n));
+            HIPCHK(c, launch_zero_u64(P<unsigned long long>(c->prof), 8 * (int64_t)n, c->stream));
+            c->prof_n = n;
+        }
+        B.desc[0].prof = P<long long>(c->prof);
+    }
+    // persistent grid: as many wavefronts as can be resident, at most one per source
+    const bool fp32 = c->prec == GSIM_FP32_MIXED;
+    const int per_cu = std::max(1, geodesic_blocks_per_cu(c->lds_stack_kb, fp32));
+    B.nslots = std::min(std::min(total, c->cus * per_cu), c->max_slots);
+    B.shape.lds_stack_kb = c->lds_stack_kb;
+    B.shape.nslots = B.nslots;
+    B.shape.grab = c->grab;
+    HIPCHK(c, ensure(c->stack, (size_t)std::max(B.nslots, 1) * c->gp.stack_cap * 64));
+    return upload_descs(c, B.desc);
+}
+
+const SurfDesc *desc_dev(gsim_ctx *c) { return static_cast<const SurfDesc *>(c->desc.p); }
+
+// Binning, candidate search and geodesics of every source of the batch.
+gsim_status geodesic_pass(gsim_ctx *c, Batch &B) {
+    hipStream_t s = c->stream;
     {
         Stage st(c, "prefilter");
-        if (ncell <= kSmallCells) {
-            HIPCHK(c, launch_bin_small(m, n, ms->face, ms->bary, pb, s));
+        if (B.small) {
+            HIPCHK(c, launch_bin_batch(desc_dev(c), B.bi.nsurf, s));
         } else {
-            HIPCHK(c, launch_xyz(m, n, ms->face, ms->bary, ms->xyz, s));
-            HIPCHK(c, launch_prefilter_bin(m, n, pb, s));
-            HIPCHK(c, launch_scan_i32_to_i64(pb.cell_fill, P<int64_t>(ms->tmp64), (int)ncell,
-                                             P<int64_t>(c->scan_scratch), s));
-            HIPCHK(c, launch_i64_to_i32(P<int64_t>(ms->tmp64), pb.cell_start, (int)ncell, s));
+            // one surface with a fine grid: multi-kernel counting sort
+            MeshState *ms = B.mem[0].ms;
+            const SurfDesc &d = B.desc[0];
+            const int n = ms->n;
+            const int ncell = d.dims[0] * d.dims[1] * d.dims[2];
+            PrefilterBufs pb{};
+            pb.xyz = ms->xyz;
+            pb.cell_of = d.cell_of;
+            pb.cell_start = d.cell_start;
+            pb.cell_fill = P<int32_t>(ms->cell_fill);
+            pb.order = d.order;
+            pb.cap_c = kCandCap;
+            for (int k = 0; k < 3; ++k) pb.dims[k] = d.dims[k];
+            pb.cell = d.cell;
+            HIPCHK(c, launch_xyz(ms->dm, n, ms->face, ms->bary, ms->xyz, s));
+            HIPCHK(c, launch_prefilter_bin(ms->dm, n, pb, s));
+            HIPCHK(c, launch_scan_i32_to_i64(pb.cell_fill, P<int64_t>(ms->tmp64), ncell, P<int64_t>(c->scan_scratch),
+                                             s));
+            HIPCHK(c, launch_i64_to_i32(P<int64_t>(ms->tmp64), pb.cell_start, ncell, s));
             HIPCHK(c, launch_zero_i32(pb.cell_fill, ncell, s));
             HIPCHK(c, launch_bin_scatter(n, pb, s));
         }
     }
     HIPCHK(c, launch_zero_i32(P<int32_t>(c->work), 16, s));
-    GeoOut out{P<double>(ms->cdist), P<double>(ms->ctan), P<uint8_t>(ms->cflags)};
+    GeoParams gp = c->gp;
+    if (!(gp.launch_delta > 0.0)) gp.launch_delta = 0.5 * B.mem[0].ms->dm.mean_edge;
     {
         Stage st(c, "geodesic");
-        HIPCHK(c, launch_geodesic(m, n, ms->face, ms->bary, ms->xyz, pb, cutoff, gp, out, P<char>(c->stack), nslots,
-                                  P<int32_t>(c->work), P<Counters>(c->ctr), fp32,
-                                  c->profile_sources ? P<long long>(c->prof) : nullptr, s));
+        HIPCHK(c, launch_geodesic(desc_dev(c), B.bi, gp, B.shape, P<char>(c->stack), P<int32_t>(c->work),
+                                  P<Counters>(c->ctr), c->prec == GSIM_FP32_MIXED, s));
     }
-    ms->pairs_cutoff = cutoff;
     c->passes++;
     return GSIM_OK;
+}
+
+gsim_status update_pass(gsim_ctx *c, Batch &B) {
+    Stage sg(c, "update");
+    HIPCHK(c, launch_update_batch(desc_dev(c), B.bi, c->update_block, P<Counters>(c->ctr), c->stream));
+    return GSIM_OK;
+}
+
+gsim_status single(gsim_ctx *c, MeshState *ms, double cutoff, const gsim_potential *pot, Batch &B) {
+    B.mem.assign(1, Member{ms, cutoff, pot, nullptr});
+    gsim_status st = prepare_batch(c, B);
+    if (st != GSIM_OK) return st;
+    return geodesic_pass(c, B);
 }
 
 // Compact the candidate rows into the caller-facing CSR (host sync for the size).
 gsim_status compact_pairs(gsim_ctx *c, MeshState *ms, double cutoff) {
     hipStream_t s = c->stream;
-    const int n = ms->n, cap = max_candidates_per_source();
+    const int n = ms->n, cap = kCandCap;
     Stage st(c, "compact");
     HIPCHK(c, ensure(ms->nbr_cnt, sizeof(int32_t) * (n + 1)));
     HIPCHK(c, ensure(ms->off, sizeof(int64_t) * (n + 1)));
-    HIPCHK(c, launch_count_rows(n, P<int32_t>(ms->cand_cnt), cap, P<double>(ms->cdist), cutoff, P<int32_t>(ms->nbr_cnt), s));
+    HIPCHK(c, launch_count_rows(n, P<int32_t>(ms->cand_cnt), cap, P<double>(ms->cdist), cutoff,
+                                P<int32_t>(ms->nbr_cnt), s));
     HIPCHK(c, launch_scan_i32_to_i64(P<int32_t>(ms->nbr_cnt), P<int64_t>(ms->off), n, P<int64_t>(c->scan_scratch), s));
     int64_t total = 0;
     HIPCHK(c, hipMemcpyAsync(&total, P<int64_t>(ms->off) + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -294,8 +450,6 @@ gsim_status compact_pairs(gsim_ctx *c, MeshState *ms, double cutoff) {
     return GSIM_OK;
 }
 
-int pot_kind_ok(const gsim_potential *p) { return p && p->kind >= 0 && p->kind <= 2; }
-
 gsim_status run_forces(gsim_ctx *c, MeshState *ms, const gsim_potential *pot) {
     const int n = ms->n;
     HIPCHK(c, ensure(ms->F, sizeof(double) * 3 * n));
@@ -303,10 +457,92 @@ gsim_status run_forces(gsim_ctx *c, MeshState *ms, const gsim_potential *pot) {
     HIPCHK(c, ensure(ms->E, sizeof(double) * 4));
     HIPCHK(c, ensure(c->sum_scratch, sizeof(double) * ((n + 255) / 256 + 2)));
     Stage st(c, "forces");
-    HIPCHK(c, launch_forces_rows(n, P<int32_t>(ms->cand_cnt), max_candidates_per_source(), P<double>(ms->cdist),
-                                 P<double>(ms->ctan), pot->cutoff, pot->kind, pot->k, pot->sigma, P<double>(ms->F),
-                                 P<double>(ms->Ei), &P<Counters>(c->ctr)->nbr_pairs, c->stream));
+    HIPCHK(c, launch_forces_rows(n, P<int32_t>(ms->cand_cnt), kCandCap, P<double>(ms->cdist), P<double>(ms->ctan),
+                                 pot->cutoff, pot->kind, pot->k, pot->sigma, P<double>(ms->F), P<double>(ms->Ei),
+                                 &P<Counters>(c->ctr)->nbr_pairs, c->stream));
     HIPCHK(c, launch_sum(P<double>(ms->Ei), n, P<double>(ms->E), P<double>(c->sum_scratch), c->stream));
+    return GSIM_OK;
+}
+
+// Signature of a prepared batch for the graph cache: the descriptor bytes
+// (every buffer address and parameter), the kernel parameters and the launch
+// shape.
+std::string graph_key(gsim_ctx *c, const Batch &B, int steps) {
+    std::string k;
+    auto put = [&](const void *p, size_t nb) { k.append(static_cast<const char *>(p), nb); };
+    put(B.desc.data(), sizeof(SurfDesc) * B.desc.size());
+    put(&B.bi, sizeof(B.bi));
+    put(&c->gp, sizeof(c->gp));
+    put(&B.shape, sizeof(B.shape));
+    put(&B.small, sizeof(B.small));
+    put(&c->update_block, sizeof(int));
+    put(&steps, sizeof(int));
+    void *ptrs[5] = {c->stack.p, c->work.p, c->ctr.p, c->desc.p, c->scan_scratch.p};
+    put(ptrs, sizeof(ptrs));
+    return k;
+}
+
+void drop_graphs(gsim_ctx *c) {
+    for (auto &g : c->graphs)
+        if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
+    c->graphs.clear();
+}
+
+gsim_status enqueue_steps(gsim_ctx *c, Batch &B, int steps) {
+    for (int k = 0; k < steps; ++k) {
+        gsim_status st = geodesic_pass(c, B);
+        if (st != GSIM_OK) return st;
+        if ((st = update_pass(c, B)) != GSIM_OK) return st;
+    }
+    return GSIM_OK;
+}
+
+// Run nsteps full steps of a prepared batch: through a cached HIP graph of
+// graph_steps steps when timing is off, else eagerly (stage events).
+gsim_status run_steps(gsim_ctx *c, Batch &B, int nsteps) {
+    gsim_status st;
+    const int g = c->graph_steps;
+    int done = 0;
+    if (!c->timing && g > 0 && nsteps >= 2) {
+        const int gs = std::min(g, nsteps);
+        const std::string key = graph_key(c, B, gs);
+        auto it = c->graphs.find(key);
+        if (it == c->graphs.end()) {
+            if (c->graphs.size() >= 16) drop_graphs(c);
+            hipGraph_t graph = nullptr;
+            HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            c->capturing = true;
+            st = enqueue_steps(c, B, gs);
+            c->capturing = false;
+            hipError_t e = hipStreamEndCapture(c->stream, &graph);
+            if (st != GSIM_OK) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return st;
+            }
+            HIPCHK(c, e);
+            GraphRec r;
+            r.steps = gs;
+            e = hipGraphInstantiate(&r.exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            HIPCHK(c, e);
+            it = c->graphs.emplace(key, r).first;
+            c->passes -= gs;  // the capture counted passes that have not run
+        }
+        while (nsteps - done >= it->second.steps) {
+            HIPCHK(c, hipGraphLaunch(it->second.exec, c->stream));
+            done += it->second.steps;
+            c->passes += it->second.steps;
+        }
+    }
+    if ((st = enqueue_steps(c, B, nsteps - done)) != GSIM_OK) return st;
+    for (auto &m : B.mem) m.ms->step += (uint64_t)nsteps;
+    return GSIM_OK;
+}
+
+gsim_status check_integ(gsim_ctx *c, const gsim_integrator *integ) {
+    if (!integ) return fail(c, GSIM_E_ARG, "null integrator");
+    if (integ->kind != GSIM_INT_OVERDAMPED && integ->kind != GSIM_INT_BROWNIAN)
+        return fail(c, GSIM_E_ARG, "unknown integrator");
     return GSIM_OK;
 }
 
@@ -344,6 +580,9 @@ gsim_status gsim_create(int device, gsim_precision prec, void *hip_stream, gsim_
         }
         c->own_stream = true;
     }
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        c->cus = cus;
     c->gp.cutoff = 0.0;
     c->gp.launch_delta = 1e300;  // one bucket: every improved bend vertex once the stack drains
     c->gp.cone_tol = 1e-12;
@@ -358,7 +597,9 @@ gsim_status gsim_create(int device, gsim_precision prec, void *hip_stream, gsim_
     c->gp.max_windows = 4000000;
     if (ensure(c->work, sizeof(int32_t) * 16) != hipSuccess || ensure(c->ctr, sizeof(Counters)) != hipSuccess ||
         ensure(c->wstats, sizeof(unsigned long long) * 8) != hipSuccess ||
-        ensure(c->pf_over, sizeof(int32_t) * 4) != hipSuccess) {
+        ensure(c->pf_over, sizeof(int32_t) * 4) != hipSuccess ||
+        ensure(c->desc, sizeof(SurfDesc) * kMaxBatch) != hipSuccess ||
+        hipHostMalloc((void **)&c->desc_pinned, sizeof(SurfDesc) * kMaxBatch, hipHostMallocDefault) != hipSuccess) {
         gsim_destroy(c);
         return GSIM_E_OOM;
     }
@@ -371,13 +612,13 @@ void gsim_destroy(gsim_ctx *c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     resolve_timing(c);
+    drop_graphs(c);
     for (auto e : c->free_events) (void)hipEventDestroy(e);
     for (MeshState *ms : c->meshes) {
         if (!ms) continue;
-        for (Buf *b : {&ms->cell_of, &ms->cell_start, &ms->cell_fill, &ms->order, &ms->cand_cnt, &ms->cand_off,
-                       &ms->cand, &ms->tmp64, &ms->cdist, &ms->ctan, &ms->cflags, &ms->nbr_cnt, &ms->off, &ms->nbr,
-                       &ms->dist, &ms->tan, &ms->flags, &ms->F, &ms->Ei, &ms->E, &ms->disp, &ms->wflags,
-                       &ms->guard})
+        for (Buf *b : {&ms->cell_of, &ms->cell_start, &ms->cell_fill, &ms->order, &ms->cand_cnt, &ms->cand,
+                       &ms->tmp64, &ms->cdist, &ms->ctan, &ms->cflags, &ms->nbr_cnt, &ms->off, &ms->nbr, &ms->dist,
+                       &ms->tan, &ms->flags, &ms->F, &ms->Ei, &ms->E, &ms->disp, &ms->wflags, &ms->step_dev})
             release(*b);
         for (void *p : {(void *)ms->face, (void *)ms->bary, (void *)ms->vel, (void *)ms->xyz})
             if (p) (void)hipFree(p);
@@ -388,8 +629,9 @@ void gsim_destroy(gsim_ctx *c) {
         delete ms;
     }
     for (Buf *b : {&c->stack, &c->work, &c->ctr, &c->wstats, &c->scan_scratch, &c->sum_scratch, &c->pf_over,
-                   &c->prof})
+                   &c->prof, &c->desc})
         release(*b);
+    if (c->desc_pinned) (void)hipHostFree(c->desc_pinned);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }
@@ -418,6 +660,8 @@ gsim_status gsim_mesh_upload(gsim_ctx *c, int32_t nv, const double *xyz, int32_t
         d.nf = nf;
         hipStream_t s = c->stream;
         (void)hipSetDevice(c->device);
+        // the mesh joins the context first so that a failed copy still frees it
+        c->meshes.push_back(ms);
         HIPCHK(c, upload(d.V, H.V.data(), H.V.size(), s));
         HIPCHK(c, upload(d.T, H.T.data(), H.T.size(), s));
         HIPCHK(c, upload(d.he, H.he.data(), H.he.size(), s));
@@ -438,8 +682,9 @@ gsim_status gsim_mesh_upload(gsim_ctx *c, int32_t nv, const double *xyz, int32_t
         d.max_edge = H.max_edge;
         d.n_boundary_edges = H.n_boundary_edges;
         d.n_pseudo = H.n_pseudo;
+        HIPCHK(c, ensure(ms->step_dev, sizeof(uint64_t)));
+        HIPCHK(c, launch_zero_u64(P<unsigned long long>(ms->step_dev), 1, s));
         HIPCHK(c, hipStreamSynchronize(s));
-        c->meshes.push_back(ms);
         *mesh_id = (int32_t)c->meshes.size() - 1;
         return GSIM_OK;
     } catch (const std::bad_alloc &) {
@@ -497,6 +742,16 @@ static gsim_status check_state(gsim_ctx *c, const MeshState *ms, int32_t n, cons
     return GSIM_OK;
 }
 
+static gsim_status reset_state(gsim_ctx *c, MeshState *ms, const double *vel, hipMemcpyKind kind) {
+    hipStream_t s = c->stream;
+    const int n = ms->n;
+    if (vel) HIPCHK(c, hipMemcpyAsync(ms->vel, vel, sizeof(double) * 3 * n, kind, s));
+    else HIPCHK(c, launch_zero_u64(reinterpret_cast<unsigned long long *>(ms->vel), 3 * (int64_t)n, s));
+    HIPCHK(c, launch_zero_u64(P<unsigned long long>(ms->step_dev), 1, s));
+    ms->step = 0;
+    return GSIM_OK;
+}
+
 gsim_status gsim_particles_set(gsim_ctx *c, int32_t id, int32_t n, const int32_t *face, const double *bary,
                                const double *vel) {
     MeshState *ms = get_mesh(c, id);
@@ -507,11 +762,8 @@ gsim_status gsim_particles_set(gsim_ctx *c, int32_t id, int32_t n, const int32_t
     hipStream_t s = c->stream;
     HIPCHK(c, hipMemcpyAsync(ms->face, face, sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
     HIPCHK(c, hipMemcpyAsync(ms->bary, bary, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s));
-    if (vel) HIPCHK(c, hipMemcpyAsync(ms->vel, vel, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s));
-    else HIPCHK(c, hipMemsetAsync(ms->vel, 0, sizeof(double) * 3 * n, s));
+    if ((st = reset_state(c, ms, vel, hipMemcpyHostToDevice)) != GSIM_OK) return st;
     HIPCHK(c, hipStreamSynchronize(s));
-    ms->pairs_valid = false;
-    ms->step = 0;
     return GSIM_OK;
 }
 
@@ -524,11 +776,7 @@ gsim_status gsim_particles_set_dev(gsim_ctx *c, int32_t id, int32_t n, const int
     hipStream_t s = c->stream;
     HIPCHK(c, hipMemcpyAsync(ms->face, face, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
     HIPCHK(c, hipMemcpyAsync(ms->bary, bary, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
-    if (vel) HIPCHK(c, hipMemcpyAsync(ms->vel, vel, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
-    else HIPCHK(c, hipMemsetAsync(ms->vel, 0, sizeof(double) * 3 * n, s));
-    ms->pairs_valid = false;
-    ms->step = 0;
-    return GSIM_OK;
+    return reset_state(c, ms, vel, hipMemcpyDeviceToDevice);
 }
 
 gsim_status gsim_particles_get(gsim_ctx *c, int32_t id, int32_t *face, double *bary, double *vel, double *xyz) {
@@ -565,8 +813,9 @@ gsim_status gsim_geodesic_pairs(gsim_ctx *c, int32_t id, double cutoff, gsim_pai
     if (!ms || !out) return fail(c, GSIM_E_ARG, "bad arguments");
     try {
         gsim_status st;
+        Batch B;
         if ((st = begin_call(c)) != GSIM_OK) return st;
-        if ((st = pairs_device(c, ms, cutoff)) != GSIM_OK) return st;
+        if ((st = single(c, ms, cutoff, nullptr, B)) != GSIM_OK) return st;
         if ((st = compact_pairs(c, ms, cutoff)) != GSIM_OK) return st;
         if ((st = end_call(c)) != GSIM_OK) return st;
         c->last.nbr_pairs = (unsigned long long)ms->n_pairs;
@@ -595,8 +844,9 @@ gsim_status gsim_compute_forces(gsim_ctx *c, int32_t id, const gsim_potential *p
     if (!ms || !pot_kind_ok(pot) || !force) return fail(c, GSIM_E_ARG, "bad arguments");
     try {
         gsim_status st;
+        Batch B;
         if ((st = begin_call(c)) != GSIM_OK) return st;
-        if ((st = pairs_device(c, ms, pot->cutoff)) != GSIM_OK) return st;
+        if ((st = single(c, ms, pot->cutoff, pot, B)) != GSIM_OK) return st;
         if ((st = run_forces(c, ms, pot)) != GSIM_OK) return st;
         if ((st = end_call(c)) != GSIM_OK) return st;
         hipStream_t s = c->stream;
@@ -635,56 +885,162 @@ gsim_status gsim_displace_on_surface(gsim_ctx *c, int32_t id, const double *disp
         stats->cap_hits = (int64_t)h[3];
         stats->near_vertex = (int64_t)h[4];
     }
-    ms->pairs_valid = false;
     return GSIM_OK;
+}
+
+gsim_status gsim_step_batched(gsim_ctx *c, int32_t nmesh, const int32_t *mesh_ids, const gsim_potential *pots,
+                              const gsim_integrator *integs, int32_t nsteps) {
+    if (!c || nmesh < 1 || nmesh > kMaxBatch || !mesh_ids || !pots || !integs || nsteps < 0)
+        return fail(c, GSIM_E_ARG, "bad arguments");
+    try {
+        Batch B;
+        for (int32_t i = 0; i < nmesh; ++i) {
+            MeshState *ms = get_mesh(c, mesh_ids[i]);
+            if (!ms) return fail(c, GSIM_E_ARG, "unknown mesh id in batch");
+            if (!pot_kind_ok(&pots[i])) return fail(c, GSIM_E_ARG, "unknown potential in batch");
+            gsim_status st = check_integ(c, &integs[i]);
+            if (st != GSIM_OK) return st;
+            B.mem.push_back(Member{ms, pots[i].cutoff, &pots[i], &integs[i]});
+        }
+        gsim_status st;
+        if ((st = begin_call(c)) != GSIM_OK) return st;
+        if ((st = prepare_batch(c, B)) != GSIM_OK) return st;
+        if ((st = run_steps(c, B, nsteps)) != GSIM_OK) return st;
+        return end_call(c);
+    } catch (...) {
+        return fail(c, GSIM_E_ARG, "unexpected host error");
+    }
 }
 
 gsim_status gsim_step(gsim_ctx *c, int32_t id, const gsim_potential *pot, const gsim_integrator *integ,
                       int32_t nsteps) {
-    MeshState *ms = get_mesh(c, id);
-    if (!ms || !pot_kind_ok(pot) || !integ || nsteps < 0) return fail(c, GSIM_E_ARG, "bad arguments");
-    if (integ->kind != GSIM_INT_OVERDAMPED && integ->kind != GSIM_INT_BROWNIAN)
-        return fail(c, GSIM_E_ARG, "unknown integrator");
-    if (ms->n <= 0) return fail(c, GSIM_E_STATE, "no particles on this mesh");
-    const int n = ms->n;
-    hipStream_t s = c->stream;
+    if (!get_mesh(c, id)) return fail(c, GSIM_E_ARG, "unknown mesh id");
+    return gsim_step_batched(c, 1, &id, pot, integ, nsteps);
+}
+
+gsim_status gsim_autotune(gsim_ctx *c, int32_t nmesh, const int32_t *mesh_ids, const gsim_potential *pots,
+                          const gsim_integrator *integs, int32_t reps, double *out) {
+    if (!c || nmesh < 1 || nmesh > kMaxBatch || !mesh_ids || !pots || !integs || reps < 1)
+        return fail(c, GSIM_E_ARG, "bad arguments");
     try {
-        HIPCHK(c, ensure(ms->disp, sizeof(double) * 3 * n));
-        HIPCHK(c, ensure(ms->wflags, n));
-        gsim_status st;
-        if ((st = begin_call(c)) != GSIM_OK) return st;
-        for (int32_t k = 0; k < nsteps; ++k) {
-            if ((st = pairs_device(c, ms, pot->cutoff)) != GSIM_OK) return st;
-            {
-                Stage sg(c, "update");
-                UpdateArgs u{};
-                u.face = ms->face;
-                u.bary = ms->bary;
-                u.vel = ms->vel;
-                u.cnt = P<int32_t>(ms->cand_cnt);
-                u.cap = max_candidates_per_source();
-                u.dist = P<double>(ms->cdist);
-                u.tan = P<double>(ms->ctan);
-                u.cutoff = pot->cutoff;
-                u.kind = pot->kind;
-                u.k = pot->k;
-                u.sigma = pot->sigma;
-                u.ikind = integ->kind;
-                u.dt = integ->dt;
-                u.mobility = integ->mobility;
-                u.kT = integ->kT;
-                u.friction = integ->friction;
-                u.seed = integ->seed;
-                u.step = ms->step;
-                u.flags = P<uint8_t>(ms->wflags);
-                u.npairs = &P<Counters>(c->ctr)->nbr_pairs;
-                u.stats = nullptr;
-                HIPCHK(c, launch_update(ms->dm, n, u, s));
-            }
-            ms->step++;
-            ms->pairs_valid = false;
+        Batch B;
+        for (int32_t i = 0; i < nmesh; ++i) {
+            MeshState *ms = get_mesh(c, mesh_ids[i]);
+            if (!ms || !pot_kind_ok(&pots[i])) return fail(c, GSIM_E_ARG, "bad batch member");
+            gsim_status st = check_integ(c, &integs[i]);
+            if (st != GSIM_OK) return st;
+            B.mem.push_back(Member{ms, pots[i].cutoff, &pots[i], &integs[i]});
         }
-        return end_call(c);
+        const bool was_timing = c->timing;
+        c->timing = false;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        HIPCHK(c, hipEventCreate(&e0));
+        HIPCHK(c, hipEventCreate(&e1));
+        struct Cand {
+            int kb, grab;
+        };
+        const Cand cands[] = {{16, 1}, {8, 1}, {4, 1}, {16, 2}, {8, 2}, {4, 2}, {8, 4}, {4, 4}};
+        double best = INFINITY;
+        Cand pick = {c->lds_stack_kb, c->grab};
+        gsim_status st = GSIM_OK;
+        for (const Cand &k : cands) {
+            c->lds_stack_kb = k.kb;
+            c->grab = k.grab;
+            if ((st = begin_call(c)) != GSIM_OK) break;
+            if ((st = prepare_batch(c, B)) != GSIM_OK) break;
+            if ((st = geodesic_pass(c, B)) != GSIM_OK) break;  // warm-up
+            double tmin = INFINITY;
+            for (int r = 0; r < reps && st == GSIM_OK; ++r) {
+                float ms = 0.f;
+                hipError_t e = hipEventRecord(e0, c->stream);
+                if (e == hipSuccess) st = geodesic_pass(c, B);
+                if (e == hipSuccess && st == GSIM_OK) e = hipEventRecord(e1, c->stream);
+                if (e == hipSuccess && st == GSIM_OK) e = hipEventSynchronize(e1);
+                if (e == hipSuccess && st == GSIM_OK) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) st = fail(c, GSIM_E_DEVICE, std::string("autotune timing: ") + hipGetErrorString(e));
+                tmin = std::min(tmin, (double)ms);
+            }
+            if (st != GSIM_OK) break;
+            if ((st = end_call(c)) != GSIM_OK) break;
+            if (tmin < best) {
+                best = tmin;
+                pick = k;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        c->lds_stack_kb = pick.kb;
+        c->grab = pick.grab;
+        c->timing = was_timing;
+        if (st != GSIM_OK) return st;
+        // update workgroup size: timed on a scratch copy of the particle
+        // state (the rows of the last geodesic pass stay valid for it)
+        int best_block = c->update_block;
+        {
+            if ((st = prepare_batch(c, B)) != GSIM_OK) return st;
+            std::vector<SurfDesc> scratch = B.desc;
+            std::vector<Buf> bufs;
+            auto cleanup = [&]() {
+                (void)hipStreamSynchronize(c->stream);
+                for (auto &b : bufs) release(b);
+            };
+            for (auto &d : scratch) {
+                Buf f, b, v, s, w;
+                if (ensure(f, sizeof(int32_t) * d.n) != hipSuccess || ensure(b, sizeof(double) * 3 * d.n) != hipSuccess ||
+                    ensure(v, sizeof(double) * 3 * d.n) != hipSuccess || ensure(s, sizeof(uint64_t)) != hipSuccess ||
+                    ensure(w, d.n) != hipSuccess) {
+                    for (Buf *x : {&f, &b, &v, &s, &w}) bufs.push_back(*x);
+                    cleanup();
+                    return fail(c, GSIM_E_OOM, "autotune scratch allocation failed");
+                }
+                (void)hipMemcpyAsync(f.p, d.face, sizeof(int32_t) * d.n, hipMemcpyDeviceToDevice, c->stream);
+                (void)hipMemcpyAsync(b.p, d.bary, sizeof(double) * 3 * d.n, hipMemcpyDeviceToDevice, c->stream);
+                (void)hipMemcpyAsync(v.p, d.vel, sizeof(double) * 3 * d.n, hipMemcpyDeviceToDevice, c->stream);
+                (void)launch_zero_u64(P<unsigned long long>(s), 1, c->stream);
+                d.face = P<int32_t>(f);
+                d.bary = P<double>(b);
+                d.vel = P<double>(v);
+                d.step = P<uint64_t>(s);
+                d.wflags = P<uint8_t>(w);
+                for (Buf *x : {&f, &b, &v, &s, &w}) bufs.push_back(*x);
+            }
+            if ((st = upload_descs(c, scratch)) != GSIM_OK) {
+                cleanup();
+                return st;
+            }
+            hipEvent_t a0 = nullptr, a1 = nullptr;
+            (void)hipEventCreate(&a0);
+            (void)hipEventCreate(&a1);
+            double bt = INFINITY;
+            for (int blk : {64, 128, 256}) {
+                double tmin = INFINITY;
+                for (int r = 0; r < reps + 1; ++r) {
+                    float ms = 0.f;
+                    (void)hipEventRecord(a0, c->stream);
+                    (void)launch_update_batch(desc_dev(c), B.bi, blk, P<Counters>(c->ctr), c->stream);
+                    (void)hipEventRecord(a1, c->stream);
+                    if (hipEventSynchronize(a1) == hipSuccess && hipEventElapsedTime(&ms, a0, a1) == hipSuccess && r > 0)
+                        tmin = std::min(tmin, (double)ms);
+                }
+                if (tmin < bt) {
+                    bt = tmin;
+                    best_block = blk;
+                }
+            }
+            (void)hipEventDestroy(a0);
+            (void)hipEventDestroy(a1);
+            cleanup();
+            c->desc_cached.clear();  // the table on the device holds the scratch descriptors
+        }
+        c->update_block = best_block;
+        drop_graphs(c);
+        if (out) {
+            out[0] = c->lds_stack_kb;
+            out[1] = c->grab;
+            out[2] = c->update_block;
+            out[3] = best;
+        }
+        return GSIM_OK;
     } catch (...) {
         return fail(c, GSIM_E_ARG, "unexpected host error");
     }
@@ -730,7 +1086,12 @@ gsim_status gsim_tune_set(gsim_ctx *c, const char *name, double value) {
     else if (k == "stack_cap" && value >= 64 && value <= (1 << 22)) c->gp.stack_cap = (int32_t)value;
     else if (k == "max_windows" && value >= 1) c->gp.max_windows = (int32_t)std::min(value, 2.0e9);
     else if (k == "max_slots" && value >= 1 && value <= 65536) c->max_slots = (int)value;
+    else if (k == "lds_stack_kb" && (value == 4 || value == 8 || value == 16)) c->lds_stack_kb = (int)value;
+    else if (k == "grab" && value >= 1 && value <= 64) c->grab = (int)value;
+    else if (k == "update_block" && (value == 64 || value == 128 || value == 256)) c->update_block = (int)value;
+    else if (k == "graph_steps" && value >= 0 && value <= 1000) c->graph_steps = (int)value;
     else return fail(c, GSIM_E_ARG, "unknown tuning knob or value out of range: " + k);
+    drop_graphs(c);
     return GSIM_OK;
 }
 

@@ -124,17 +124,78 @@ hipError_t launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t s);
 hipError_t launch_prefilter_bin(const DevMesh &m, int n, PrefilterBufs &b, hipStream_t s);
 hipError_t launch_scan_i32_to_i64(const int32_t *in, int64_t *out, int n, int64_t *scratch, hipStream_t s);
 
-// Euclidean prefilter (candidate rows, written to pb.cand / pb.cand_cnt) and
-// geodesics, one wavefront per source. pb's cell lists must be current.
-hipError_t launch_geodesic(const DevMesh &m, int n, const int32_t *face, const double *bary, const double *xyz,
-                           const PrefilterBufs &pb, double cutoff, const GeoParams &gp, GeoOut out, char *stack_mem,
-                           int32_t nslots, int32_t *work_ctr, Counters *ctr, bool fp32, long long *prof,
-                           hipStream_t s);
-// positions + cell counting sort in one workgroup (ncell <= kSmallCells)
+// One surface of a batch (a single surface is a batch of one): everything
+// the binning, geodesic and update kernels read or write for it. The host
+// fills it; kernels read it from a device-resident table.
+struct SurfDesc {
+    DevMesh m;
+    int32_t n;          // particles on the surface
+    int32_t src_begin;  // index of its first source in the batch
+    int32_t *face;
+    double *bary, *vel, *xyz;
+    // prefilter cell grid (cells no smaller than the cutoff)
+    int32_t *cell_of, *cell_start, *order;
+    int32_t dims[3];
+    double cell, lo[3];
+    // candidate rows [n][kMaxCand], sorted by j
+    int32_t *cand_cnt, *cand;
+    double *cdist, *ctan;
+    uint8_t *cflags;
+    double cutoff, cut2;
+    // potential and integrator of the fused update
+    int32_t pkind, ikind;
+    double pk, psigma, dt, mobility, kT, friction;
+    uint64_t seed;
+    uint64_t *step;  // device counter: steps since the particles were set
+    uint8_t *wflags;
+    long long *prof;  // optional per-source profile [n][8]
+};
+
+// Capacity of a candidate row: the most Euclidean candidates one source may
+// have (its targets live in an LDS table of the geodesic kernel).
+constexpr int kCandCap = 128;
+
+constexpr int kMaxBatch = 64;
+// Surface boundaries of a batch, passed by value: surface s owns the
+// flattened indices [begin[s], begin[s+1]).
+struct BatchIdx {
+    int32_t nsurf;
+    int32_t begin[kMaxBatch + 1];
+};
+__device__ inline int batch_surface(const BatchIdx &b, int idx) {
+    int lo = 0, hi = b.nsurf - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (b.begin[mid] <= idx) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
+}
+
+// Geodesic launch shape (chosen by hand or by the autotuner; results do not
+// depend on it).
+struct GeoShape {
+    int32_t lds_stack_kb;  // LDS window stack per wavefront: 4, 8 or 16 KiB
+    int32_t nslots;        // resident wavefronts of the persistent grid
+    int32_t grab;          // consecutive sources a wavefront claims at a time
+};
+
+// Candidate search (Euclidean prefilter) and geodesics for every source of
+// the batch, one wavefront per source. The cell lists must be current.
+hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoParams &gp, const GeoShape &shape,
+                           char *stack_mem, int32_t *work_ctr, Counters *ctr, bool fp32, hipStream_t s);
+// LDS bytes of one geodesic workgroup for a stack size (occupancy planning)
+size_t geodesic_lds_bytes(int lds_stack_kb, bool fp32);
+// positions + cell counting sort, one workgroup per surface (every surface's
+// grid must have at most kSmallCells cells)
 constexpr int kSmallCells = 4096;
-hipError_t launch_bin_small(const DevMesh &m, int n, const int32_t *face, const double *bary, PrefilterBufs &b,
-                            hipStream_t s);
-int max_candidates_per_source();
+hipError_t launch_bin_batch(const SurfDesc *desc, int nsurf, hipStream_t s);
+// fused force + integrator + walk for every particle of the batch, then the
+// step counters advance
+hipError_t launch_update_batch(const SurfDesc *desc, const BatchIdx &bi, int block, Counters *ctr,
+                               hipStream_t s);
+// resident geodesic workgroups per compute unit for a stack size (0 on error)
+int geodesic_blocks_per_cu(int lds_stack_kb, bool fp32);
 
 hipError_t launch_bin_scatter(int n, PrefilterBufs &b, hipStream_t s);
 hipError_t launch_i64_to_i32(const int64_t *in, int32_t *out, int n, hipStream_t s);
@@ -151,24 +212,6 @@ hipError_t launch_sum(const double *x, int n, double *out, double *scratch, hipS
 hipError_t launch_integrate(const DevMesh &m, int n, const int32_t *face, const double *F, int kind, double dt,
                             double mobility, double kT, double friction, uint64_t seed, uint64_t step,
                             double *disp, hipStream_t s);
-// fused force + integrator + walk of one time step
-struct UpdateArgs {
-    int32_t *face;
-    double *bary, *vel;
-    const int32_t *cnt;
-    int cap;
-    const double *dist, *tan;
-    double cutoff;
-    int kind;  // potential
-    double k, sigma;
-    int ikind;  // integrator
-    double dt, mobility, kT, friction;
-    uint64_t seed, step;
-    uint8_t *flags;
-    unsigned long long *npairs;  // neighbour pairs, summed
-    unsigned long long *stats;   // walk counters [5] or null
-};
-hipError_t launch_update(const DevMesh &m, int n, const UpdateArgs &u, hipStream_t s);
 hipError_t launch_walk(const DevMesh &m, int n, int32_t *face, double *bary, const double *disp, double *vel,
                        unsigned long long *stats, uint8_t *flags, hipStream_t s);
 

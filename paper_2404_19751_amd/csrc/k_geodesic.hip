@@ -41,7 +41,14 @@
 // stack (ballot/popcount compaction; a per-wave global overflow area takes
 // what does not fit); idle lanes pop. Target and bend-vertex tables live in
 // LDS; their updates are serialised across lanes by a ballot loop (no
-// atomics, deterministic in wave order).
+// atomics, deterministic in wave order). The LDS stack depth is a template
+// parameter: a shallower stack lowers the workgroup's LDS footprint and lets
+// more wavefronts share a compute unit.
+//
+// Batches: the sources of several surfaces (each with its own mesh, cutoff
+// and particles) form one flattened index space served by the same
+// persistent grid; a wavefront finds its source's surface from the batch
+// boundaries and reads that surface's descriptor.
 #include <cmath>
 
 #include "gsim_internal.h"
@@ -50,13 +57,12 @@ namespace gsim {
 namespace {
 
 constexpr int kWave = 64;
-constexpr int kMaxCand = 128;
+constexpr int kMaxCand = kCandCap;
 constexpr int kHash = 256;
 // bend-vertex table: 255 slots so that slot + 1 fits the 8 bits the FP32
 // stack record keeps for it
 constexpr int kRootCap = 255;
 constexpr int kChunks = 8;
-constexpr int kStackBytes = 16384;
 
 template <typename R>
 struct Win {
@@ -123,24 +129,13 @@ __device__ inline He<float> load_he(const DevMesh &m, int h, float) {
 }
 
 struct GeoArgs {
-    DevMesh m;
-    int n;
-    const int32_t *face;
-    const double *bary;
-    const double *xyz;
-    int32_t *cand_cnt;        // [n] out: candidates per source
-    int32_t *cand;            // [n][cap_c] out: candidate rows sorted by j
-    int cap_c;
-    const int32_t *order;     // particles sorted by cell (also the source order)
-    const int32_t *cell_of, *cell_start;
-    int dims[3];
-    double cut2;              // squared Euclidean prefilter radius
+    const SurfDesc *sd;  // [nsurf] surface descriptors
+    BatchIdx bi;         // flattened source index -> surface
     GeoParams gp;
-    GeoOut out;               // [n][cap_c] rows
-    void *stack;              // per wave: stack_cap records of 64 bytes
-    int32_t *work;
+    void *stack;         // per wave: stack_cap records of 64 bytes
+    int32_t *work;       // [kChunks] work counters
     Counters *ctr;
-    long long *prof;  // optional [n][8]: cycles, loop iterations, windows, launches, setup / loop / launch / result cycles
+    int grab;            // consecutive sources claimed at a time
 };
 
 struct Lds {
@@ -154,7 +149,6 @@ struct Lds {
     int32_t rcount, dirty, ncand;
     int32_t sel[kRootCap + 1];   // launch list: root slots
     int32_t pref[kRootCap + 2];  // prefix sums of their fan sizes
-    alignas(16) unsigned char stk[kStackBytes];
 };
 
 __device__ inline int lane_id() { return threadIdx.x; }
@@ -268,7 +262,7 @@ __device__ inline void root_update(Lds &L, bool ok, int v, double d, double tx, 
 template <typename R>
 struct Stack {
     using Rec = typename RecOf<R>::T;
-    static constexpr int kL = kStackBytes / (int)sizeof(Rec);
+    int kL;  // LDS records
     Rec *lds;
     Rec *glb;
     int gcap;
@@ -426,9 +420,11 @@ struct SrcStats {
 // roots are compacted into a list and their fans flattened over the lanes,
 // so one launch round costs a few memory round trips, not one per root.
 template <typename R>
-__device__ void launch_roots(const GeoArgs &a, Lds &L, const Ctx &C, Stack<R> &S, SrcStats &st) {
+__device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, Lds &L, const Ctx &C, Stack<R> &S,
+                             SrcStats &st) {
     const int lane = lane_id();
-    const HeRec *__restrict__ he = a.m.he;
+    const DevMesh &M = sd.m;
+    const HeRec *__restrict__ he = M.he;
     double mn = INFINITY;
     for (int e = lane; e < kRootCap; e += kWave)
         if (L.rkey[e] >= 0 && L.rD[e] < L.rL[e] && L.rD[e] < C.cut_acc) mn = fmin(mn, L.rD[e]);
@@ -460,14 +456,14 @@ __device__ void launch_roots(const GeoArgs &a, Lds &L, const Ctx &C, Stack<R> &S
         if (k < nsel) {
             const int e = L.sel[k], v = L.rkey[e];
             const double D = L.rD[e];
-            const double vx = a.m.V[3 * (int64_t)v], vy = a.m.V[3 * (int64_t)v + 1], vz = a.m.V[3 * (int64_t)v + 2];
+            const double vx = M.V[3 * (int64_t)v], vy = M.V[3 * (int64_t)v + 1], vz = M.V[3 * (int64_t)v + 2];
             bool useful = false;
             for (int s = 0; s < C.nc && !useful; ++s) {
                 const double bound = L.cb[s][3] - D;
                 const double q0 = L.cb[s][0] - vx, q1 = L.cb[s][1] - vy, q2 = L.cb[s][2] - vz;
                 useful = bound > 0.0 && q0 * q0 + q1 * q1 + q2 * q2 < bound * bound;
             }
-            if (useful) deg = a.m.fan_off[v + 1] - a.m.fan_off[v];
+            if (useful) deg = M.fan_off[v + 1] - M.fan_off[v];
         }
         // wave-inclusive scan of deg
         int inc = deg;
@@ -499,7 +495,7 @@ __device__ void launch_roots(const GeoArgs &a, Lds &L, const Ctx &C, Stack<R> &S
         const int v = act ? L.rkey[el] : 0;
         const double D = act ? L.rD[el] : 0.0;
         const double vtx = act ? L.rtx[el] : 0.0, vty = act ? L.rty[el] : 0.0;
-        const int h = act ? a.m.fan[a.m.fan_off[v] + (idx - L.pref[k])] : 0;
+        const int h = act ? M.fan[M.fan_off[v] + (idx - L.pref[k])] : 0;
         const int hn = h - h % 3 + (h % 3 + 1) % 3;
         const HeRec Rh = he[h], Rn = he[hn];
         Win<R> nw;
@@ -517,7 +513,7 @@ __device__ void launch_roots(const GeoArgs &a, Lds &L, const Ctx &C, Stack<R> &S
             nw.he = Rn.twin;
             nw.root = el;
             double F3[3][3], U3[3][3];
-            face_xyz(a.m, h / 3, h % 3, F3, U3);  // (v, u1, u2)
+            face_xyz(M, h / 3, h % 3, F3, U3);  // (v, u1, u2)
             // the window's edge runs u2 -> u1: the reverse of half-edge next(h) = (u1 -> u2)
             const double u[3] = {-U3[1][0], -U3[1][1], -U3[1][2]};
             want = reaches_target(L, C, F3[2], u, 0.0, Rn.L, D + seg_dist(px, py, 0.0, Rn.L));
@@ -525,7 +521,7 @@ __device__ void launch_roots(const GeoArgs &a, Lds &L, const Ctx &C, Stack<R> &S
         // direct targets in face(h)
         const int g = h / 3;
         int slot = act ? first_in_face(L, g) : -1;
-        const double *pv = a.m.V + 3 * (int64_t)v;
+        const double *pv = M.V + 3 * (int64_t)v;
         while (__ballot(slot >= 0)) {
             const bool ok = slot >= 0;
             double d = 0;
@@ -537,11 +533,11 @@ __device__ void launch_roots(const GeoArgs &a, Lds &L, const Ctx &C, Stack<R> &S
             if (ok) slot = next_in_face(L, slot, g);
         }
         // adjacent bend vertices along the two edges at v
-        const int u1 = act ? a.m.T[hn] : 0;  // head of h
-        const bool ok1 = act && (a.m.vflag[u1] & VF_PSEUDO) && D + Rh.L < C.cut_acc;
+        const int u1 = act ? M.T[hn] : 0;  // head of h
+        const bool ok1 = act && (M.vflag[u1] & VF_PSEUDO) && D + Rh.L < C.cut_acc;
         root_update(L, ok1, u1, D + Rh.L, vtx, vty, st.overflow);
         const int u2 = act ? Rh.opp : 0;
-        const bool ok2 = act && (a.m.vflag[u2] & VF_PSEUDO) && D + Rh.Lp < C.cut_acc;
+        const bool ok2 = act && (M.vflag[u2] & VF_PSEUDO) && D + Rh.Lp < C.cut_acc;
         root_update(L, ok2, u2, D + Rh.Lp, vtx, vty, st.overflow);
         S.push(want, nw, st.overflow);
     }
@@ -551,24 +547,24 @@ __device__ void launch_roots(const GeoArgs &a, Lds &L, const Ctx &C, Stack<R> &S
 // scan the 27 cells around it, the hits are rank-sorted by particle index in
 // LDS and written out as the source's candidate row. Returns the true count
 // (more than kMaxCand is an overflow the caller reports).
-__device__ int find_candidates(const GeoArgs &a, Lds &L, int src, int64_t c0) {
+__device__ int find_candidates(const SurfDesc &sd, Lds &L, int src, int64_t c0) {
     const int lane = lane_id();
     if (lane == 0) L.ncand = 0;
     __syncthreads();
-    const double xi = a.xyz[3 * (int64_t)src], yi = a.xyz[3 * (int64_t)src + 1], zi = a.xyz[3 * (int64_t)src + 2];
-    const int lin = a.cell_of[src];
-    const int cx = lin % a.dims[0], cy = (lin / a.dims[0]) % a.dims[1], cz = lin / (a.dims[0] * a.dims[1]);
+    const double xi = sd.xyz[3 * (int64_t)src], yi = sd.xyz[3 * (int64_t)src + 1], zi = sd.xyz[3 * (int64_t)src + 2];
+    const int lin = sd.cell_of[src];
+    const int cx = lin % sd.dims[0], cy = (lin / sd.dims[0]) % sd.dims[1], cz = lin / (sd.dims[0] * sd.dims[1]);
     if (lane < 27) {
         const int x = cx + lane % 3 - 1, y = cy + (lane / 3) % 3 - 1, z = cz + lane / 9 - 1;
-        if (x >= 0 && x < a.dims[0] && y >= 0 && y < a.dims[1] && z >= 0 && z < a.dims[2]) {
-            const int c = (z * a.dims[1] + y) * a.dims[0] + x;
-            const int e1 = a.cell_start[c + 1];
-            for (int q = a.cell_start[c]; q < e1; ++q) {
-                const int j = a.order[q];
+        if (x >= 0 && x < sd.dims[0] && y >= 0 && y < sd.dims[1] && z >= 0 && z < sd.dims[2]) {
+            const int c = (z * sd.dims[1] + y) * sd.dims[0] + x;
+            const int e1 = sd.cell_start[c + 1];
+            for (int q = sd.cell_start[c]; q < e1; ++q) {
+                const int j = sd.order[q];
                 if (j == src) continue;
-                const double ex = a.xyz[3 * (int64_t)j] - xi, ey = a.xyz[3 * (int64_t)j + 1] - yi,
-                             ez = a.xyz[3 * (int64_t)j + 2] - zi;
-                if (ex * ex + ey * ey + ez * ez < a.cut2) {
+                const double ex = sd.xyz[3 * (int64_t)j] - xi, ey = sd.xyz[3 * (int64_t)j + 1] - yi,
+                             ez = sd.xyz[3 * (int64_t)j + 2] - zi;
+                if (ex * ex + ey * ey + ez * ez < sd.cut2) {
                     const int pos = atomicAdd(&L.ncand, 1);
                     if (pos < kMaxCand) L.tnext[pos] = j;
                 }
@@ -585,23 +581,23 @@ __device__ int find_candidates(const GeoArgs &a, Lds &L, int src, int64_t c0) {
         L.tj[rank] = j;
     }
     __syncthreads();
-    for (int s = lane; s < m; s += kWave) a.cand[c0 + s] = L.tj[s];
-    if (lane == 0) a.cand_cnt[src] = total;
+    for (int s = lane; s < m; s += kWave) sd.cand[c0 + s] = L.tj[s];
+    if (lane == 0) sd.cand_cnt[src] = total;
     return total;
 }
 
 // Geodesics from one source to its candidate targets; writes the row and
 // returns whether any pair lies inside the guard band of the cutoff.
 template <typename R>
-__device__ bool run_source(const GeoArgs &a, Lds &L, int src, int64_t c0, int nc, bool guard_mode, int slot_id,
-                           SrcStats &st) {
+__device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigned char *stk, int stk_bytes, int src,
+                           int64_t c0, int nc, bool guard_mode, int slot_id, SrcStats &st) {
     const int lane = lane_id();
     const long long t_start = clock64();
     const unsigned long long launches0 = st.launches;
     long long iters = 0, t_launch = 0;
     const bool fp32 = sizeof(R) == 4;
     Ctx C;
-    C.cutoff = a.gp.cutoff;
+    C.cutoff = sd.cutoff;
     // FP32 results may be off by rounding: everything within the guard band
     // above the cutoff is still propagated and recorded, so that pairs near
     // the cutoff are seen and recomputed in FP64
@@ -611,9 +607,10 @@ __device__ bool run_source(const GeoArgs &a, Lds &L, int src, int64_t c0, int nc
     C.tie_rel = fp32 ? a.gp.tie_rel32 : a.gp.tie_rel;
     C.tie_dir = fp32 ? a.gp.tie_dir32 : a.gp.tie_dir;
     C.nc = nc;
-    const HeRec *__restrict__ he = a.m.he;
+    const HeRec *__restrict__ he = sd.m.he;
     Stack<R> S;
-    S.lds = reinterpret_cast<typename RecOf<R>::T *>(L.stk);
+    S.lds = reinterpret_cast<typename RecOf<R>::T *>(stk);
+    S.kL = stk_bytes / (int)sizeof(typename RecOf<R>::T);
     S.glb = reinterpret_cast<typename RecOf<R>::T *>(reinterpret_cast<Rec64 *>(a.stack) +
                                                       (size_t)slot_id * a.gp.stack_cap);
     S.gcap = fp32 ? 2 * a.gp.stack_cap : a.gp.stack_cap;
@@ -630,11 +627,11 @@ __device__ bool run_source(const GeoArgs &a, Lds &L, int src, int64_t c0, int nc
     __syncthreads();
     for (int s = lane; s < nc; s += kWave) {
         const int j = L.tj[s];
-        const int f = a.face[j];
+        const int f = sd.face[j];
         L.tface[s] = f;
         for (int d = 0; d < 3; ++d) {
-            L.tb[s][d] = a.bary[3 * (int64_t)j + d];
-            L.cb[s][d] = a.xyz[3 * (int64_t)j + d];
+            L.tb[s][d] = sd.bary[3 * (int64_t)j + d];
+            L.cb[s][d] = sd.xyz[3 * (int64_t)j + d];
         }
         L.cb[s][3] = C.cut_acc;
         L.d1[s] = INFINITY;
@@ -649,8 +646,8 @@ __device__ bool run_source(const GeoArgs &a, Lds &L, int src, int64_t c0, int nc
     int pruned = 0;
 
     // ---- seed from the source (root -1, sg = 0), in FP64
-    const int fs = a.face[src];
-    const double sb[3] = {a.bary[3 * (int64_t)src], a.bary[3 * (int64_t)src + 1], a.bary[3 * (int64_t)src + 2]};
+    const int fs = sd.face[src];
+    const double sb[3] = {sd.bary[3 * (int64_t)src], sd.bary[3 * (int64_t)src + 1], sd.bary[3 * (int64_t)src + 2]};
     const HeRec R0 = he[3 * fs];
     const double P[3][2] = {{0.0, 0.0}, {R0.L, 0.0}, {R0.cx, R0.cy}};
     const double sx = sb[1] * P[1][0] + sb[2] * P[2][0], sy = sb[1] * P[1][1] + sb[2] * P[2][1];
@@ -683,8 +680,8 @@ __device__ bool run_source(const GeoArgs &a, Lds &L, int src, int64_t c0, int nc
             const int k = lane, h = 3 * fs + k;
             const HeRec Rh = he[h];
             const double ex = (P[(k + 1) % 3][0] - P[k][0]) / Rh.L, ey = (P[(k + 1) % 3][1] - P[k][1]) / Rh.L;
-            int v = a.m.T[h];
-            if (a.m.vflag[v] & VF_PSEUDO) {
+            int v = sd.m.T[h];
+            if (sd.m.vflag[v] & VF_PSEUDO) {
                 double dx = P[k][0] - sx, dy = P[k][1] - sy;
                 rd = sqrt(dx * dx + dy * dy);
                 rok = rd < C.cut_acc;
@@ -707,10 +704,10 @@ __device__ bool run_source(const GeoArgs &a, Lds &L, int src, int64_t c0, int nc
                     want = seg_dist(Rh.L - hx, -hy, 0.0, Rh.L) < C.cut_acc;
                 } else {
                     // source on this edge: the face across contains it as well
-                    const He<R> Ht = load_he(a.m, Rh.twin, R(0));
+                    const He<R> Ht = load_he(sd.m, Rh.twin, R(0));
                     w.py = R(0);
                     double F3[3][3], U3[3][3];
-                    face_xyz(a.m, Rh.twin / 3, Rh.twin % 3, F3, U3);
+                    face_xyz(sd.m, Rh.twin / 3, Rh.twin % 3, F3, U3);
                     children(Ht, w, 0.0, true, C, F3, U3, L, wa, wantA, wb, wantB, pruned);
                 }
             }
@@ -771,7 +768,7 @@ __device__ bool run_source(const GeoArgs &a, Lds &L, int src, int64_t c0, int nc
         // once nothing is left to propagate
         if (L.dirty && (eager || !busy)) {
             const long long t0 = clock64();
-            launch_roots(a, L, C, S, st);
+            launch_roots(a, sd, L, C, S, st);
             t_launch += clock64() - t0;
             if (!busy) busy = S.refill(have, w);
         }
@@ -802,8 +799,8 @@ __device__ bool run_source(const GeoArgs &a, Lds &L, int src, int64_t c0, int nc
             // both records depend only on the entry half-edge: issue them together
             f = w.he / 3;
             k = w.he % 3;
-            H = load_he(a.m, w.he, R(0));
-            face_xyz(a.m, f, k, F3, U3);
+            H = load_he(sd.m, w.he, R(0));
+            face_xyz(sd.m, f, k, F3, U3);
             txc = (double)w.px + ((double)H.cx - (double)w.px) * (-(double)w.py) / ((double)H.cy - (double)w.py);
         }
         // targets in face f
@@ -873,9 +870,9 @@ __device__ bool run_source(const GeoArgs &a, Lds &L, int src, int64_t c0, int nc
 
     // ---- results (row of the candidate layout)
     const long long t_res = clock64();
-    const int32_t *T = a.m.T;
-    const double *p0 = a.m.V + 3 * (int64_t)T[3 * fs], *p1 = a.m.V + 3 * (int64_t)T[3 * fs + 1];
-    const double *nn = a.m.fnrm + 3 * (int64_t)fs;
+    const int32_t *T = sd.m.T;
+    const double *p0 = sd.m.V + 3 * (int64_t)T[3 * fs], *p1 = sd.m.V + 3 * (int64_t)T[3 * fs + 1];
+    const double *nn = sd.m.fnrm + 3 * (int64_t)fs;
     double ex3[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
     double el = sqrt(ex3[0] * ex3[0] + ex3[1] * ex3[1] + ex3[2] * ex3[2]);
     ex3[0] /= el;
@@ -893,13 +890,13 @@ __device__ bool run_source(const GeoArgs &a, Lds &L, int src, int64_t c0, int nc
         if (d == 0.0) fl |= GSIM_PAIR_ZERO_BIT;
         if (guard_mode) fl |= GSIM_PAIR_GUARD_BIT;
         near_cut |= fabs(d - C.cutoff) <= a.gp.guard_rel * C.cutoff;
-        a.out.dist[o] = d;
-        a.out.flags[o] = fl;
-        for (int q = 0; q < 3; ++q) a.out.tan[3 * o + q] = L.t1x[s] * ex3[q] + L.t1y[s] * ey3[q];
+        sd.cdist[o] = d;
+        sd.cflags[o] = fl;
+        for (int q = 0; q < 3; ++q) sd.ctan[3 * o + q] = L.t1x[s] * ex3[q] + L.t1y[s] * ey3[q];
     }
     const bool any_near = __ballot(near_cut) != 0;
-    if (a.prof && lane == 0) {
-        long long *q = a.prof + 8 * (int64_t)src;
+    if (sd.prof && lane == 0) {
+        long long *q = sd.prof + 8 * (int64_t)src;
         const long long t_end = clock64();
         q[0] += t_end - t_start;
         q[1] += iters;
@@ -917,35 +914,45 @@ __device__ bool run_source(const GeoArgs &a, Lds &L, int src, int64_t c0, int nc
     return any_near;
 }
 
-template <bool kMixed>
+template <bool kMixed, int kStk>
 __global__ __launch_bounds__(kWave) void k_geodesic(GeoArgs a) {
     __shared__ Lds L;
+    __shared__ alignas(16) unsigned char stk[kStk];
     const int lane = lane_id();
+    const int total = a.bi.begin[a.bi.nsurf];
     int chunk = blockIdx.x % kChunks, chunks_left = kChunks;
     SrcStats st;
     st.windows = st.launches = st.stale = 0;
     st.pruned = 0;
     st.overflow = false;
     unsigned long long c_limited = 0;
+    int next = 0, left = 0;  // claimed sources not yet processed
     for (;;) {
-        // ---- next source: XCD-local chunk first, then the others
-        int idx = -1;
-        while (chunks_left > 0) {
-            int lo = (int)(((int64_t)a.n * chunk) / kChunks), hi = (int)(((int64_t)a.n * (chunk + 1)) / kChunks);
-            int t = 0;
-            if (lane == 0) t = atomicAdd(&a.work[chunk], 1);
-            t = __shfl(t, 0);
-            if (lo + t < hi) {
-                idx = lo + t;
-                break;
+        // ---- next source: claim `grab` consecutive ones, XCD-local chunk first
+        if (left == 0) {
+            while (chunks_left > 0) {
+                const int lo = (int)(((int64_t)total * chunk) / kChunks);
+                const int hi = (int)(((int64_t)total * (chunk + 1)) / kChunks);
+                int t = 0;
+                if (lane == 0) t = atomicAdd(&a.work[chunk], a.grab);
+                t = __shfl(t, 0);
+                if (lo + t < hi) {
+                    next = lo + t;
+                    left = min(a.grab, hi - next);
+                    break;
+                }
+                chunk = (chunk + 1) % kChunks;
+                --chunks_left;
             }
-            chunk = (chunk + 1) % kChunks;
-            --chunks_left;
+            if (left == 0) break;
         }
-        if (idx < 0) break;
-        const int src = a.order[idx];
-        const int64_t c0 = (int64_t)src * a.cap_c;
-        const int nc = find_candidates(a, L, src, c0);
+        const int idx = next++;
+        --left;
+        const int si = __builtin_amdgcn_readfirstlane(batch_surface(a.bi, idx));
+        const SurfDesc &sd = a.sd[si];
+        const int src = sd.order[idx - a.bi.begin[si]];
+        const int64_t c0 = (int64_t)src * kMaxCand;
+        const int nc = find_candidates(sd, L, src, c0);
         if (nc <= 0) continue;
         if (nc > kMaxCand) {
             if (lane == 0) ++c_limited;
@@ -954,10 +961,10 @@ __global__ __launch_bounds__(kWave) void k_geodesic(GeoArgs a) {
         st.overflow = false;
         if (kMixed) {
             // FP32 pass; a pair inside the guard band sends the source through FP64
-            if (run_source<float>(a, L, src, c0, nc, false, blockIdx.x, st))
-                run_source<double>(a, L, src, c0, nc, true, blockIdx.x, st);
+            if (run_source<float>(a, sd, L, stk, kStk, src, c0, nc, false, blockIdx.x, st))
+                run_source<double>(a, sd, L, stk, kStk, src, c0, nc, true, blockIdx.x, st);
         } else {
-            run_source<double>(a, L, src, c0, nc, false, blockIdx.x, st);
+            run_source<double>(a, sd, L, stk, kStk, src, c0, nc, false, blockIdx.x, st);
         }
         if (st.overflow) ++c_limited;
     }
@@ -975,40 +982,46 @@ __global__ __launch_bounds__(kWave) void k_geodesic(GeoArgs a) {
     }
 }
 
+template <bool kMixed>
+void launch_variant(int kb, int nslots, const GeoArgs &a, hipStream_t s) {
+    if (kb <= 4) hipLaunchKernelGGL((k_geodesic<kMixed, 4096>), dim3(nslots), dim3(kWave), 0, s, a);
+    else if (kb <= 8) hipLaunchKernelGGL((k_geodesic<kMixed, 8192>), dim3(nslots), dim3(kWave), 0, s, a);
+    else hipLaunchKernelGGL((k_geodesic<kMixed, 16384>), dim3(nslots), dim3(kWave), 0, s, a);
+}
+
 }  // namespace
 
-hipError_t launch_geodesic(const DevMesh &m, int n, const int32_t *face, const double *bary, const double *xyz,
-                           const PrefilterBufs &pb, double cutoff, const GeoParams &gp, GeoOut out, char *stack_mem,
-                           int32_t nslots, int32_t *work_ctr, Counters *ctr, bool fp32, long long *prof,
-                           hipStream_t s) {
+hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoParams &gp, const GeoShape &shape,
+                           char *stack_mem, int32_t *work_ctr, Counters *ctr, bool fp32, hipStream_t s) {
     GeoArgs a;
-    a.cell_of = pb.cell_of;
-    a.cell_start = pb.cell_start;
-    for (int d = 0; d < 3; ++d) a.dims[d] = pb.dims[d];
-    a.cut2 = cutoff * cutoff * (1.0 + 1e-12);
-    const int32_t *order = pb.order;
-    int32_t *cand_cnt = pb.cand_cnt, *cand = pb.cand;
-    const int cap_c = pb.cap_c;
-    a.prof = prof;
-    a.m = m;
-    a.n = n;
-    a.face = face;
-    a.bary = bary;
-    a.xyz = xyz;
-    a.cand_cnt = cand_cnt;
-    a.cand = cand;
-    a.cap_c = cap_c;
-    a.order = order;
+    a.sd = desc;
+    a.bi = bi;
     a.gp = gp;
-    a.out = out;
     a.stack = stack_mem;
     a.work = work_ctr;
     a.ctr = ctr;
-    if (fp32) hipLaunchKernelGGL(k_geodesic<true>, dim3(nslots), dim3(kWave), 0, s, a);
-    else hipLaunchKernelGGL(k_geodesic<false>, dim3(nslots), dim3(kWave), 0, s, a);
+    a.grab = shape.grab < 1 ? 1 : shape.grab;
+    if (shape.nslots < 1 || bi.begin[bi.nsurf] < 1) return hipSuccess;
+    if (fp32) launch_variant<true>(shape.lds_stack_kb, shape.nslots, a, s);
+    else launch_variant<false>(shape.lds_stack_kb, shape.nslots, a, s);
     return hipGetLastError();
 }
 
-int max_candidates_per_source() { return kMaxCand; }
+int geodesic_blocks_per_cu(int lds_stack_kb, bool fp32) {
+    int nb = 0;
+    const void *f;
+    if (lds_stack_kb <= 4) f = fp32 ? (const void *)&k_geodesic<true, 4096> : (const void *)&k_geodesic<false, 4096>;
+    else if (lds_stack_kb <= 8)
+        f = fp32 ? (const void *)&k_geodesic<true, 8192> : (const void *)&k_geodesic<false, 8192>;
+    else f = fp32 ? (const void *)&k_geodesic<true, 16384> : (const void *)&k_geodesic<false, 16384>;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kWave, 0) != hipSuccess) return 0;
+    return nb;
+}
+
+size_t geodesic_lds_bytes(int lds_stack_kb, bool) {
+    const int kb = lds_stack_kb <= 4 ? 4 : (lds_stack_kb <= 8 ? 8 : 16);
+    return sizeof(Lds) + (size_t)kb * 1024;
+}
+
 
 }  // namespace gsim

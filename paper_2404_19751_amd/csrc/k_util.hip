@@ -125,33 +125,35 @@ __global__ void k_bin_scatter(int n, PrefilterBufs b) {
     b.order[pos] = j;
 }
 
-// Positions and the cell counting sort in a single workgroup: cell counts,
-// their exclusive scan and the scatter all live in LDS.
+// Positions and the cell counting sort of one surface per workgroup: cell
+// counts, their exclusive scan and the scatter all live in LDS.
 constexpr int kBinThreads = 1024;
-__global__ __launch_bounds__(kBinThreads) void k_bin_small(const double *__restrict__ V, const int32_t *__restrict__ T,
-                                                           int n, const int32_t *__restrict__ face,
-                                                           const double *__restrict__ bary, PrefilterBufs b, BB bb) {
+__global__ __launch_bounds__(kBinThreads) void k_bin_batch(const SurfDesc *__restrict__ desc) {
     __shared__ int32_t cnt[kSmallCells];
     __shared__ int32_t start[kSmallCells];
     __shared__ int32_t part[kBinThreads];
+    const SurfDesc &sd = desc[blockIdx.x];
+    const double *__restrict__ V = sd.m.V;
+    const int32_t *__restrict__ T = sd.m.T;
+    const int n = sd.n;
     const int t = threadIdx.x;
-    const int ncell = b.dims[0] * b.dims[1] * b.dims[2];
+    const int ncell = sd.dims[0] * sd.dims[1] * sd.dims[2];
     for (int c = t; c < ncell; c += kBinThreads) cnt[c] = 0;
     __syncthreads();
     for (int j = t; j < n; j += kBinThreads) {
-        const int f = face[j];
-        const double b0 = bary[3 * j], b1 = bary[3 * j + 1], b2 = bary[3 * j + 2];
+        const int f = sd.face[j];
+        const double b0 = sd.bary[3 * j], b1 = sd.bary[3 * j + 1], b2 = sd.bary[3 * j + 2];
         const double *p0 = V + 3 * (int64_t)T[3 * f], *p1 = V + 3 * (int64_t)T[3 * f + 1],
                      *p2 = V + 3 * (int64_t)T[3 * f + 2];
-        double x[3];
-        for (int d = 0; d < 3; ++d) {
-            x[d] = b0 * p0[d] + b1 * p1[d] + b2 * p2[d];
-            b.xyz[3 * j + d] = x[d];
-        }
         int c3[3];
-        cell_coords(x, b, bb.lo, c3);
-        const int lin = (c3[2] * b.dims[1] + c3[1]) * b.dims[0] + c3[0];
-        b.cell_of[j] = lin;
+        for (int d = 0; d < 3; ++d) {
+            const double x = b0 * p0[d] + b1 * p1[d] + b2 * p2[d];
+            sd.xyz[3 * j + d] = x;
+            const int q = int(floor((x - sd.lo[d]) / sd.cell));
+            c3[d] = q < 0 ? 0 : (q >= sd.dims[d] ? sd.dims[d] - 1 : q);
+        }
+        const int lin = (c3[2] * sd.dims[1] + c3[1]) * sd.dims[0] + c3[0];
+        sd.cell_of[j] = lin;
         atomicAdd(&cnt[lin], 1);
     }
     __syncthreads();
@@ -171,19 +173,18 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_small(const double *__restr
     int run = part[t] - sum;
     for (int c = c0; c < c1; ++c) {
         start[c] = run;
-        b.cell_start[c] = run;
+        sd.cell_start[c] = run;
         run += cnt[c];
         cnt[c] = 0;
     }
-    if (t == kBinThreads - 1) b.cell_start[ncell] = part[t];
+    if (t == kBinThreads - 1) sd.cell_start[ncell] = part[t];
     __syncthreads();
     for (int j = t; j < n; j += kBinThreads) {
-        const int lin = b.cell_of[j];
-        b.order[start[lin] + atomicAdd(&cnt[lin], 1)] = j;
+        const int lin = sd.cell_of[j];
+        sd.order[start[lin] + atomicAdd(&cnt[lin], 1)] = j;
     }
 }
 
-// ------------------------------------------------------------ compaction
 __global__ void k_count_rows(int n, const int32_t *__restrict__ cnt, int cap, const double *__restrict__ dist,
                              double cutoff, int32_t *__restrict__ out) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -308,11 +309,9 @@ hipError_t launch_prefilter_bin(const DevMesh &m, int n, PrefilterBufs &b, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_bin_small(const DevMesh &m, int n, const int32_t *face, const double *bary, PrefilterBufs &b,
-                            hipStream_t s) {
-    BB bb;
-    for (int d = 0; d < 3; ++d) bb.lo[d] = m.bbmin[d];
-    hipLaunchKernelGGL(k_bin_small, dim3(1), dim3(kBinThreads), 0, s, m.V, m.T, n, face, bary, b, bb);
+hipError_t launch_bin_batch(const SurfDesc *desc, int nsurf, hipStream_t s) {
+    if (nsurf <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bin_batch, dim3(nsurf), dim3(kBinThreads), 0, s, desc);
     return hipGetLastError();
 }
 hipError_t launch_bin_scatter(int n, PrefilterBufs &b, hipStream_t s) {

@@ -227,38 +227,52 @@ __global__ __launch_bounds__(128) void k_walk(DevMesh m, int n, int32_t *__restr
 // particle's neighbour row (Sec. 3.1 force sum), the displacement of the
 // integrator (Sec. 2.1), and the walk (Sec. 3.2). Rows hold only distances
 // and tangents computed before any particle moves, so particles are
-// independent here.
-__global__ __launch_bounds__(128) void k_update(DevMesh m, int n, UpdateArgs u) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int f = u.face[i];
+// independent here. One thread per particle of the flattened batch.
+__global__ __launch_bounds__(256) void k_update_batch(const SurfDesc *__restrict__ desc, BatchIdx bi,
+                                                     unsigned long long *__restrict__ npairs) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= bi.begin[bi.nsurf]) return;
+    const int si = batch_surface(bi, g);
+    const SurfDesc &sd = desc[si];
+    const int i = g - bi.begin[si];
+    int f = sd.face[i];
     double F[3], E;
     int np;
-    row_force(i, u.cnt, u.cap, u.dist, u.tan, u.cutoff, u.kind, u.k, u.sigma, F, E, np);
+    row_force(i, sd.cand_cnt, kCandCap, sd.cdist, sd.ctan, sd.cutoff, sd.pkind, sd.pk, sd.psigma, F, E, np);
     double D[3];
-    displacement(m, f, i, F, u.ikind, u.dt, u.mobility, u.kT, u.friction, u.seed, u.step, D);
-    double b[3] = {u.bary[3 * i], u.bary[3 * i + 1], u.bary[3 * i + 2]};
-    d3 v = ld3(u.vel + 3 * (int64_t)i);
+    displacement(sd.m, f, i, F, sd.ikind, sd.dt, sd.mobility, sd.kT, sd.friction, sd.seed, *sd.step, D);
+    double b[3] = {sd.bary[3 * i], sd.bary[3 * i + 1], sd.bary[3 * i + 2]};
+    d3 v = ld3(sd.vel + 3 * (int64_t)i);
     WalkCounts wc = {0, 0, 0, 0, 0};
     uint8_t fl = 0;
-    walk_one(m, f, b, d3{D[0], D[1], D[2]}, v, true, wc, fl);
-    u.face[i] = f;
-    u.bary[3 * i] = b[0];
-    u.bary[3 * i + 1] = b[1];
-    u.bary[3 * i + 2] = b[2];
-    u.vel[3 * i] = v.x;
-    u.vel[3 * i + 1] = v.y;
-    u.vel[3 * i + 2] = v.z;
-    if (u.flags) u.flags[i] = fl;
-    if (np && u.npairs) atomicAdd(u.npairs, (unsigned long long)np);
-    flush_counts(wc, u.stats);
+    walk_one(sd.m, f, b, d3{D[0], D[1], D[2]}, v, true, wc, fl);
+    sd.face[i] = f;
+    sd.bary[3 * i] = b[0];
+    sd.bary[3 * i + 1] = b[1];
+    sd.bary[3 * i + 2] = b[2];
+    sd.vel[3 * i] = v.x;
+    sd.vel[3 * i + 1] = v.y;
+    sd.vel[3 * i + 2] = v.z;
+    if (sd.wflags) sd.wflags[i] = fl;
+    if (np && npairs) atomicAdd(npairs, (unsigned long long)np);
+}
+
+// The noise counter of every surface moves on by one step (after the
+// update kernel has read it).
+__global__ void k_advance_steps(const SurfDesc *__restrict__ desc, int nsurf) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < nsurf) *desc[s].step += 1;
 }
 
 }  // namespace
 
-hipError_t launch_update(const DevMesh &m, int n, const UpdateArgs &u, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_update, dim3((n + 127) / 128), dim3(128), 0, s, m, n, u);
+hipError_t launch_update_batch(const SurfDesc *desc, const BatchIdx &bi, int block, Counters *ctr, hipStream_t s) {
+    const int total = bi.begin[bi.nsurf];
+    if (total <= 0) return hipSuccess;
+    if (block != 64 && block != 128 && block != 256) block = 128;
+    hipLaunchKernelGGL(k_update_batch, dim3((total + block - 1) / block), dim3(block), 0, s, desc, bi,
+                       &ctr->nbr_pairs);
+    hipLaunchKernelGGL(k_advance_steps, dim3(1), dim3(kMaxBatch), 0, s, desc, bi.nsurf);
     return hipGetLastError();
 }
 

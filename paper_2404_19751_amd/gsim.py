@@ -26,7 +26,7 @@ EXPORTS = ["gsim_create", "gsim_destroy", "gsim_last_error", "gsim_synchronize",
            "gsim_mesh_info_get", "gsim_particles_set", "gsim_particles_get", "gsim_particles_set_dev",
            "gsim_particles_get_dev", "gsim_geodesic_pairs", "gsim_compute_forces", "gsim_displace_on_surface",
            "gsim_step", "gsim_timing_enable", "gsim_timing_get", "gsim_counters_get", "gsim_tune_set",
-           "gsim_source_profile"]
+           "gsim_source_profile", "gsim_step_batched", "gsim_autotune"]
 
 
 class GsimError(RuntimeError):
@@ -93,6 +93,8 @@ def load(path: str = LIB_PATH):
         "gsim_counters_get": ([V, V], C.c_int),
         "gsim_tune_set": ([V, C.c_char_p, C.c_double], C.c_int),
         "gsim_source_profile": ([V, C.c_int, V, C.c_int32], C.c_int),
+        "gsim_step_batched": ([V, C.c_int32, V, V, V, C.c_int32], C.c_int),
+        "gsim_autotune": ([V, C.c_int32, V, V, V, C.c_int32, V], C.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -229,6 +231,24 @@ class Context:
 
     def step(self, mid, pot: PotentialT, integ: IntegratorT, nsteps: int = 1):
         self._chk(self.L.gsim_step(self.h, mid, C.byref(pot), C.byref(integ), int(nsteps)))
+
+    def step_batched(self, mids, pots, integs, nsteps: int = 1):
+        """nsteps steps of several surfaces in one batch (one launch per
+        stage for all of them)."""
+        k = len(mids)
+        ids = (C.c_int32 * k)(*[int(m) for m in mids])
+        pa = (PotentialT * k)(*pots)
+        ia = (IntegratorT * k)(*integs)
+        self._chk(self.L.gsim_step_batched(self.h, k, ids, pa, ia, int(nsteps)))
+
+    def autotune(self, mids, pots, integs, reps: int = 3) -> dict:
+        k = len(mids)
+        ids = (C.c_int32 * k)(*[int(m) for m in mids])
+        pa = (PotentialT * k)(*pots)
+        ia = (IntegratorT * k)(*integs)
+        out = np.zeros(4)
+        self._chk(self.L.gsim_autotune(self.h, k, ids, pa, ia, int(reps), _ptr(out)))
+        return dict(lds_stack_kb=int(out[0]), grab=int(out[1]), update_block=int(out[2]), best_ms=float(out[3]))
 
     def synchronize(self):
         self._chk(self.L.gsim_synchronize(self.h))
