@@ -79,14 +79,116 @@ def cpu_baseline(w, budget_s=8.0, max_steps=40):
             "particle_steps_per_s": steps * len(w.face) / dt}
 
 
+def _gsim_args(gsim, w):
+    p, wi = w.potential, w.integrator
+    pot = gsim.potential(p["kind"], p["k"], p["sigma"], p["cutoff"])
+    if wi["kind"] == "brownian":
+        ig = gsim.integrator("brownian", wi["dt"], 1.0, wi["kT"], wi["friction"], wi["seed"])
+    else:
+        ig = gsim.integrator("overdamped", wi["dt"], wi["mobility"])
+    return pot, ig
+
+
+def bench_c3(args, gsim, W):
+    """16 surfaces (icospheres L3-L6, 12 tori) stepped as one batch (one
+    persistent geodesic launch per step, steps replayed from a HIP graph,
+    autotuned launch shape) against the plain path: each surface stepped on
+    its own, eagerly, in FP64."""
+    ws = W.workload("c3")
+    steps = args.steps
+
+    def load(ctx):
+        mids = []
+        for w in ws:
+            mid = ctx.mesh_upload(w.mesh.V, w.mesh.T)
+            ctx.particles_set(mid, w.face, w.bary)
+            mids.append(mid)
+        return mids
+
+    pots, igs = zip(*[_gsim_args(gsim, w) for w in ws])
+
+    def batched(prec, tune):
+        ctx = gsim.Context(0, prec)
+        mids = load(ctx)
+        pick = ctx.autotune(mids, pots, igs, reps=3) if tune else None
+        ctx.step_batched(mids, pots, igs, max(args.warmup, 2))  # also captures the graph of `warmup` steps
+        ctx.tune(graph_steps=steps)
+        ctx.step_batched(mids, pots, igs, steps)  # capture of the timed graph
+        for m, w in zip(mids, ws):
+            ctx.particles_set(m, w.face, w.bary)
+        ctx.synchronize()
+        c0 = ctx.counters()["cum_pairs"]
+        t0 = time.perf_counter()
+        ctx.step_batched(mids, pots, igs, steps)
+        ctx.synchronize()
+        dt = time.perf_counter() - t0
+        pairs = ctx.counters()["cum_pairs"] - c0
+        # instrumented pass (stage events, no graph) for the kernel times
+        for m, w in zip(mids, ws):
+            ctx.particles_set(m, w.face, w.bary)
+        ctx.timing(True)
+        ctx.step_batched(mids, pots, igs, min(steps, 10))
+        ctx.synchronize()
+        stages = {k: ctx.timing_get(k)[0] for k in ("prefilter", "geodesic", "update")}
+        cnt = ctx.counters()
+        ctx.timing(False)
+        ctx.close()
+        return dict(pairs_per_s=pairs / dt, ms_per_step=1e3 * dt / steps, pairs_per_step=pairs / steps,
+                    stage_ms=stages, windows_per_step=cnt["cum_windows"] / max(cnt["cum_passes"], 1), tuned=pick)
+
+    def single(prec):
+        ctx = gsim.Context(0, prec)
+        ctx.tune(graph_steps=0)
+        mids = load(ctx)
+        for m, p, g in zip(mids, pots, igs):
+            ctx.step(m, p, g, max(args.warmup, 1))
+        for m, w in zip(mids, ws):
+            ctx.particles_set(m, w.face, w.bary)
+        ctx.synchronize()
+        c0 = ctx.counters()["cum_pairs"]
+        t0 = time.perf_counter()
+        for m, p, g in zip(mids, pots, igs):
+            ctx.step(m, p, g, steps)
+        ctx.synchronize()
+        dt = time.perf_counter() - t0
+        pairs = ctx.counters()["cum_pairs"] - c0
+        ctx.close()
+        return dict(pairs_per_s=pairs / dt, ms_per_step=1e3 * dt / steps, pairs_per_step=pairs / steps)
+
+    b32 = batched("fp32", True)
+    b64 = batched("fp64", True)
+    s64 = single("fp64")
+    s32 = single("fp32")
+    n = sum(len(w.face) for w in ws)
+    geo_ms = b32["stage_ms"]["geodesic"]
+    achieved = FLOPS_PER_WINDOW * b32["windows_per_step"] / (geo_ms * 1e-3) / 1e12 if geo_ms > 0 else 0.0
+    return {
+        "metric": METRIC, "value": b32["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1, "steps": steps,
+        "warmup": args.warmup, "ms_per_step": b32["ms_per_step"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32+f64", "data": "synthetic",
+        "config": {"workload": "16 surfaces batched: icospheres L3-L6 and 12 tori R=1 r=0.3 (1938-81920 faces), "
+                               "N per surface at packing 0.3 in [200,4000] (15033 total), harmonic sigma=cutoff=2 "
+                               "mean edges, overdamped dt=0.01 sigma^2; steps replayed from a HIP graph",
+                   "n_particles": n, "surfaces": len(ws)},
+        "particle_steps_per_s": n * steps / (b32["ms_per_step"] * 1e-3 * steps),
+        "batched_fp32": b32, "batched_fp64": b64, "single_surface_fp64": s64, "single_surface_fp32": s32,
+        "batched_fp32_over_single_fp64": b32["pairs_per_s"] / s64["pairs_per_s"],
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None, "kernel": "k_geodesic",
+                     "per_unit": f"{FLOPS_PER_WINDOW:.0f} flop/window",
+                     "units_per_launch": b32["windows_per_step"], "avg_launch_ms": geo_ms},
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32"])
-    ap.add_argument("--workload", default="c2", choices=["c2", "c4"],
-                    help="c2: bumpy sphere N=1000 (the default line); c4: open height field N=20000, Brownian")
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4"],
+                    help="c2: bumpy sphere N=1000 (the default line); c3: 16 surfaces batched; "
+                         "c4: open height field N=20000, Brownian")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
@@ -110,6 +212,9 @@ def main():
 
     from paper_2404_19751_amd import gsim, workloads as W
 
+    if args.workload == "c3":
+        print(json.dumps(bench_c3(args, gsim, W)), flush=True)
+        return
     w = W.workload(args.workload)
     pot = gsim.potential("harmonic", w.potential["k"], w.potential["sigma"], w.potential["cutoff"])
     wi = w.integrator

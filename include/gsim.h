@@ -185,6 +185,9 @@ gsim_status gsim_step_batched(gsim_ctx *ctx, int32_t nmesh, const int32_t *mesh_
  *   "tie_rel"       relative gap under which a pair is flagged as a tie
  *   "tie_dir"       tangents closer than this angle (rad) count as one direction
  *   "guard_rel"     FP32-mixed: relative band around the cutoff recomputed in FP64
+ *   "root_rel32"    FP32-mixed: a bend vertex is re-launched only when its distance
+ *                   improves by more than this fraction (<= 1e-4; distances may then
+ *                   exceed the exact value by this fraction)
  *   "lds_stack_kb"  window-stack depth in LDS per wavefront: 4, 8 or 16 KiB (sets
  *                   how many wavefronts fit on a compute unit)
  *   "grab"          consecutive sources a wavefront claims at a time (1 .. 64)

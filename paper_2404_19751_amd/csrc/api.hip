@@ -83,7 +83,7 @@ struct gsim_ctx {
     std::vector<hipEvent_t> free_events;
     // launch shape
     int max_slots = 65536;
-    int lds_stack_kb = 16;
+    int lds_stack_kb = 4;
     int grab = 1;
     int update_block = 128;
     int cus = 256;
@@ -592,6 +592,7 @@ gsim_status gsim_create(int device, gsim_precision prec, void *hip_stream, gsim_
     c->gp.cone_tol32 = 1e-5;
     c->gp.tie_rel32 = 1e-4;
     c->gp.tie_dir32 = 5e-6;
+    c->gp.root_rel32 = 2e-6;
     c->gp.eager = 0;
     c->gp.stack_cap = 2048;
     c->gp.max_windows = 4000000;
@@ -1083,6 +1084,7 @@ gsim_status gsim_tune_set(gsim_ctx *c, const char *name, double value) {
     else if (k == "tie_rel32" && value >= 0.0) c->gp.tie_rel32 = value;
     else if (k == "tie_dir32" && value >= 0.0) c->gp.tie_dir32 = value;
     else if (k == "guard_rel" && value >= 0.0) c->gp.guard_rel = value;
+    else if (k == "root_rel32" && value >= 0.0 && value <= 1e-4) c->gp.root_rel32 = value;
     else if (k == "stack_cap" && value >= 64 && value <= (1 << 22)) c->gp.stack_cap = (int32_t)value;
     else if (k == "max_windows" && value >= 1) c->gp.max_windows = (int32_t)std::min(value, 2.0e9);
     else if (k == "max_slots" && value >= 1 && value <= 65536) c->max_slots = (int)value;

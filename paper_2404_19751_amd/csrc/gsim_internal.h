@@ -101,6 +101,8 @@ struct GeoParams {
     double tie_dir;       // two candidate tangents closer than this (rad) are the same direction
     double guard_rel;     // FP32 results this close (relative) to the cutoff are recomputed in FP64
     double cone_tol32, tie_rel32, tie_dir32;  // the FP32 pass's counterparts
+    double root_rel32;    // FP32 pass: a bend vertex is re-launched only when its distance improves by more
+                          // than this fraction (FP32 rounding makes equal paths differ by ~1e-7)
     int32_t eager;        // launch bend vertices as soon as they are found
     int32_t stack_cap;    // windows per stack slot
     int32_t max_windows;  // per-source work limit

@@ -181,6 +181,7 @@ __device__ inline int next_in_face(const Lds &L, int s, int f) {
 // Per-source constants shared by the helpers.
 struct Ctx {
     double cutoff, cut_acc, lb_slack, tol, tie_rel, tie_dir;
+    double root_keep;  // 1 - relative improvement below which a bend vertex is not re-launched
     int nc;
 };
 
@@ -226,8 +227,11 @@ __device__ inline void target_update(Lds &L, const Ctx &C, bool ok, int slot, do
     }
 }
 
-// Serialised bend-vertex update (insert or improve); marks the table dirty.
-__device__ inline void root_update(Lds &L, bool ok, int v, double d, double tx, double ty, bool &overflow) {
+// Serialised bend-vertex update (insert or improve): keeps the smallest
+// distance and its tangent; marks the table dirty when the vertex needs a
+// (re-)launch.
+__device__ inline void root_update(Lds &L, const Ctx &C, bool ok, int v, double d, double tx, double ty,
+                                   bool &overflow) {
     uint64_t m = __ballot(ok);
     while (m) {
         int l = __ffsll((unsigned long long)m) - 1;
@@ -251,7 +255,7 @@ __device__ inline void root_update(Lds &L, bool ok, int v, double d, double tx, 
                 L.rD[e] = d;
                 L.rtx[e] = tx;
                 L.rty[e] = ty;
-                L.dirty = 1;
+                if (d < L.rL[e] * C.root_keep) L.dirty = 1;
             }
         }
         m &= m - 1;
@@ -427,7 +431,7 @@ __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, Lds &L, const
     const HeRec *__restrict__ he = M.he;
     double mn = INFINITY;
     for (int e = lane; e < kRootCap; e += kWave)
-        if (L.rkey[e] >= 0 && L.rD[e] < L.rL[e] && L.rD[e] < C.cut_acc) mn = fmin(mn, L.rD[e]);
+        if (L.rkey[e] >= 0 && L.rD[e] < L.rL[e] * C.root_keep && L.rD[e] < C.cut_acc) mn = fmin(mn, L.rD[e]);
     mn = wave_min(mn);
     if (lane == 0) L.dirty = 0;
     if (!(mn < INFINITY)) return;
@@ -437,7 +441,7 @@ __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, Lds &L, const
     bool left = false;
     for (int base = 0; base < kRootCap; base += kWave) {
         const int e = base + lane;
-        const bool cand = e < kRootCap && L.rkey[e] >= 0 && L.rD[e] < L.rL[e] && L.rD[e] < C.cut_acc;
+        const bool cand = e < kRootCap && L.rkey[e] >= 0 && L.rD[e] < L.rL[e] * C.root_keep && L.rD[e] < C.cut_acc;
         const bool sel = cand && L.rD[e] <= thr;
         left |= cand && !sel;
         const uint64_t mk = __ballot(sel);
@@ -535,10 +539,10 @@ __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, Lds &L, const
         // adjacent bend vertices along the two edges at v
         const int u1 = act ? M.T[hn] : 0;  // head of h
         const bool ok1 = act && (M.vflag[u1] & VF_PSEUDO) && D + Rh.L < C.cut_acc;
-        root_update(L, ok1, u1, D + Rh.L, vtx, vty, st.overflow);
+        root_update(L, C, ok1, u1, D + Rh.L, vtx, vty, st.overflow);
         const int u2 = act ? Rh.opp : 0;
         const bool ok2 = act && (M.vflag[u2] & VF_PSEUDO) && D + Rh.Lp < C.cut_acc;
-        root_update(L, ok2, u2, D + Rh.Lp, vtx, vty, st.overflow);
+        root_update(L, C, ok2, u2, D + Rh.Lp, vtx, vty, st.overflow);
         S.push(want, nw, st.overflow);
     }
 }
@@ -606,6 +610,7 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
     C.tol = fp32 ? a.gp.cone_tol32 : a.gp.cone_tol;
     C.tie_rel = fp32 ? a.gp.tie_rel32 : a.gp.tie_rel;
     C.tie_dir = fp32 ? a.gp.tie_dir32 : a.gp.tie_dir;
+    C.root_keep = fp32 ? 1.0 - a.gp.root_rel32 : 1.0;
     C.nc = nc;
     const HeRec *__restrict__ he = sd.m.he;
     Stack<R> S;
@@ -712,7 +717,7 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
                 }
             }
         }
-        root_update(L, rok, rv, rd, rtx, rty, overflow);
+        root_update(L, C, rok, rv, rd, rtx, rty, overflow);
         // on-edge sources: targets and third vertex of the face across
         for (int k = 0; k < 3; ++k) {
             bool on = sb[(k + 2) % 3] <= 0.0 && he[3 * fs + k].twin >= 0;
@@ -746,7 +751,7 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
             bool ok = lane == 0 && (Rt.flags & 1);
             double dx = Rt.cx - ptx, dy = Rt.cy;
             double d = sqrt(dx * dx + dy * dy);
-            root_update(L, ok && d < C.cut_acc, Rt.opp, d, (c * dx - s * dy) / d, (s * dx + c * dy) / d, overflow);
+            root_update(L, C, ok && d < C.cut_acc, Rt.opp, d, (c * dx - s * dy) / d, (s * dx + c * dy) / d, overflow);
         }
         S.push(want, w, overflow);
         S.push(wantA, wa, overflow);
@@ -785,9 +790,10 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
         // ---- process the lane's window
         Win<R> cl, cr;
         bool hl = false, hr = false;
-        // stale: the root's distance improved after this window was made
-        // (compared in the working precision the window was stored in)
-        if (have && w.root >= 0 && w.sg > (R)L.rD[w.root]) {
+        // stale: the root's distance improved (beyond the re-launch tolerance)
+        // after this window was made; compared in the working precision the
+        // window was stored in
+        if (have && w.root >= 0 && w.sg > (R)(L.rD[w.root] / C.root_keep)) {
             have = false;
             ++st.stale;
         }
@@ -856,7 +862,7 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
                     }
                 }
             }
-            root_update(L, ok, have ? H.opp : 0, d, tx, ty, overflow);
+            root_update(L, C, ok, have ? H.opp : 0, d, tx, ty, overflow);
         }
         if (have) children(H, w, txc, false, C, F3, U3, L, cl, hl, cr, hr, pruned);
         // keep one child in the lane, push the other
