@@ -258,3 +258,65 @@ def step(mesh: OracleMesh, face, bary, potential_cfg: dict, integ: dict, step_in
     D = displacement(mesh, face, F, integ, step_index)
     f2, b2, _, st, fl = walk(mesh, face, bary, D)
     return f2, b2, dict(pairs=pr, F=F, E=E, D=D, walk=st, walk_flags=fl)
+
+
+# --------------------------------------------------------------------------
+# FIRE energy minimisation (Bitzek, Koskinen, Gähler, Moseler & Gumbsch,
+# "Structural relaxation made simple", Phys. Rev. Lett. 97, 170201 (2006))
+# --------------------------------------------------------------------------
+FIRE_DEFAULTS = dict(alpha0=0.1, f_alpha=0.99, f_inc=1.1, f_dec=0.5, n_min=5)
+
+
+def fire_init(integ: dict) -> dict:
+    """FIRE state before the first iteration: time step dt0 = integ["dt"],
+    mixing factor alpha0, no iteration with positive power yet."""
+    p = dict(FIRE_DEFAULTS)
+    p.update({k: integ[k] for k in FIRE_DEFAULTS if k in integ})
+    return dict(dt=float(integ["dt"]), alpha=float(p["alpha0"]), n_pos=0)
+
+
+def fire_step(mesh: OracleMesh, face, bary, vel, potential_cfg: dict, integ: dict, state: dict, nthreads=0):
+    """One FIRE iteration on the surface, with unit masses.
+
+    With F the forces at the current positions and P = sum_i F_i . v_i:
+      P > 0:  v <- (1 - alpha) v + alpha |v| F / |F|  (norms over all
+              particles); after more than n_min consecutive such iterations
+              dt <- min(f_inc dt, dt_max) and alpha <- f_alpha alpha;
+      P <= 0: v <- 0, dt <- f_dec dt, alpha <- alpha0.
+    Then the semi-implicit Euler step v <- v + dt F, and each particle walks
+    the displacement D_i = dt v_i (capped at max_disp in length) along the
+    surface, its velocity parallel-transported by the walk. dt_max defaults
+    to 10 dt0 and max_disp to infinity.
+    Returns (face, bary, vel, state, info)."""
+    p = dict(FIRE_DEFAULTS)
+    p.update({k: integ[k] for k in FIRE_DEFAULTS if k in integ})
+    dt_max = float(integ.get("dt_max", 10.0 * integ["dt"]))
+    max_disp = float(integ.get("max_disp", math.inf))
+    pr = geodesic_pairs(mesh, face, bary, potential_cfg["cutoff"], nthreads=nthreads)
+    F, E = forces(face.shape[0], pr, potential_cfg["kind"], potential_cfg.get("k", 1.0),
+                  potential_cfg.get("sigma", 1.0))
+    v = np.array(vel, np.float64, copy=True)
+    dt, alpha, n_pos = state["dt"], state["alpha"], state["n_pos"]
+    P = float(np.sum(F * v))
+    if P > 0.0:
+        vn = math.sqrt(float(np.sum(v * v)))
+        fn = math.sqrt(float(np.sum(F * F)))
+        if fn > 0.0:
+            v = (1.0 - alpha) * v + (alpha * vn / fn) * F
+        n_pos += 1
+        if n_pos > p["n_min"]:
+            dt = min(dt * p["f_inc"], dt_max)
+            alpha *= p["f_alpha"]
+    else:
+        v[:] = 0.0
+        dt *= p["f_dec"]
+        alpha = p["alpha0"]
+        n_pos = 0
+    v = v + dt * F
+    D = dt * v
+    L = np.linalg.norm(D, axis=1)
+    over = L > max_disp
+    D[over] *= (max_disp / L[over])[:, None]
+    f2, b2, v2, st, fl = walk(mesh, face, bary, D, v)
+    new_state = dict(dt=dt, alpha=alpha, n_pos=n_pos)
+    return f2, b2, v2, new_state, dict(pairs=pr, F=F, E=E, D=D, P=P, walk=st, walk_flags=fl)
