@@ -88,16 +88,30 @@ typedef struct {
     double k, sigma, cutoff;
 } gsim_potential;
 
-typedef enum { GSIM_INT_OVERDAMPED = 0, GSIM_INT_BROWNIAN = 1 } gsim_integrator_kind;
+typedef enum { GSIM_INT_OVERDAMPED = 0, GSIM_INT_BROWNIAN = 1, GSIM_INT_FIRE = 2 } gsim_integrator_kind;
 
 /* overdamped: D = mobility dt F.
  * brownian:   friction D = dt F + sqrt(2 kT friction dt) (eta1 ex + eta2 ey),
  *             eta from Philox4x32-10 with counter (particle, step lo, step hi, 0)
- *             and key (seed lo, seed hi), Box-Muller on two 53-bit uniforms. */
+ *             and key (seed lo, seed hi), Box-Muller on two 53-bit uniforms.
+ * fire:       FIRE energy minimisation (Bitzek et al., Phys. Rev. Lett. 97,
+ *             170201 (2006)), unit masses, one step = one iteration: with the
+ *             power P = sum F.v, P > 0 mixes v <- (1 - alpha) v + alpha |v| F/|F|
+ *             (norms over the surface's particles) and after more than n_min
+ *             such iterations in a row sets dt <- min(f_inc dt, dt_max),
+ *             alpha <- f_alpha alpha; P <= 0 sets v <- 0, dt <- f_dec dt,
+ *             alpha <- alpha0. Then v += dt F and each particle walks dt v
+ *             (at most max_disp long), its velocity parallel-transported.
+ *             dt is the initial step; the state restarts when particles are
+ *             set. Zero fields select the defaults in brackets. */
 typedef struct {
     int32_t kind;
     double dt, mobility, kT, friction;
     uint64_t seed;
+    double max_disp;                      /* fire: [no cap] */
+    double dt_max;                        /* fire: [10 dt] */
+    double alpha0, f_alpha, f_inc, f_dec; /* fire: [0.1, 0.99, 1.1, 0.5] */
+    int32_t n_min;                        /* fire: [5] */
 } gsim_integrator;
 
 typedef struct {
@@ -192,7 +206,12 @@ gsim_status gsim_step_batched(gsim_ctx *ctx, int32_t nmesh, const int32_t *mesh_
  *                   how many wavefronts fit on a compute unit)
  *   "grab"          consecutive sources a wavefront claims at a time (1 .. 64)
  *   "update_block"  workgroup size of the fused update kernel: 64, 128 or 256
- *   "graph_steps"   steps captured per HIP graph in step calls (0 = no graphs) */
+ *   "graph_steps"   steps captured per HIP graph in step calls (0 = no graphs)
+ *   All-pairs passes (no cutoff):
+ *   "stack_cap_all" window records per resident wavefront (1024 .. 4M)
+ *   "max_windows_all" per-source work limit
+ *   "bucket"        key width of one processing round (0 = two max edge lengths)
+ *   "dom_rel", "dom_rel32"  margins of the vertex-path domination tests */
 gsim_status gsim_tune_set(gsim_ctx *ctx, const char *name, double value);
 
 /* autotune: times the geodesic pass of the given batch (current particle
@@ -212,12 +231,13 @@ gsim_status gsim_autotune(gsim_ctx *ctx, int32_t nmesh, const int32_t *mesh_ids,
  * "integrate", "walk". avg_ms is the mean launch duration. */
 gsim_status gsim_timing_enable(gsim_ctx *ctx, int on);
 gsim_status gsim_timing_get(gsim_ctx *ctx, const char *name, double *avg_ms, int64_t *launches);
-/* Work counters. Of the last geodesic pass: [0] windows processed,
- * [1] windows pruned at the cutoff, [2] bend-vertex (pseudo-source) launches,
+/* Work counters. Of the last call: [0] windows processed,
+ * [1] windows pruned, [2] bend-vertex (pseudo-source) launches,
  * [3] stale windows dropped, [4] candidate pairs, [5] neighbour pairs,
- * [6] sources over a work limit. Summed over the passes since timing was
- * last enabled: [7] neighbour pairs, [8] windows, [9] passes. c10[10]. */
-gsim_status gsim_counters_get(gsim_ctx *ctx, int64_t *c10);
+ * [6] sources over a work limit, [10] deepest window stack of a source in
+ * all-pairs passes (records). Summed over the calls since timing was last
+ * enabled: [7] neighbour pairs, [8] windows, [9] passes. c[11]. */
+gsim_status gsim_counters_get(gsim_ctx *ctx, int64_t *c);
 /* Per-source profile of the geodesic kernel, accumulated over the calls
  * made while it is on: out[n][8] = GPU clock cycles, propagation-loop
  * iterations, windows, bend-vertex launches, and the cycles spent in set-up

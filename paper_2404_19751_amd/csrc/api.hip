@@ -44,8 +44,12 @@ struct MeshState {
     Buf nbr_cnt, off, nbr, dist, tan, flags;
     int64_t n_pairs = 0;
     // forces / integrator
-    Buf F, Ei, E, disp, wflags, step_dev;
+    Buf F, Ei, E, disp, wflags, step_dev, fire;
     uint64_t step = 0;  // steps taken since the state was set: the noise counter (host mirror)
+    // all-pairs rows and the particles-by-face index
+    int cap = kCandCap;  // row capacity of the last pass
+    int ident_n = -1;    // rows hold the identity lists for this n
+    Buf fstart, forder, fcount;
 };
 
 struct TimingRec {
@@ -67,7 +71,7 @@ struct gsim_ctx {
     bool own_stream = false;
     std::string err;
     std::vector<MeshState *> meshes;
-    Buf stack, work, ctr, wstats, scan_scratch, sum_scratch, pf_over, prof, desc;
+    Buf stack, work, ctr, wstats, scan_scratch, sum_scratch, pf_over, prof, desc, vdist, partials;
     SurfDesc *desc_pinned = nullptr;  // staging for descriptor uploads
     std::vector<SurfDesc> desc_cached;
     bool profile_sources = false;
@@ -86,7 +90,11 @@ struct gsim_ctx {
     int lds_stack_kb = 4;
     int grab = 1;
     int update_block = 128;
+    int stack_cap_all = 1 << 18;  // window records per wavefront in all-pairs passes
+    double stack_budget = 16e9;   // bytes of window stacks an all-pairs pass may hold
+    int max_windows_all = 0;      // per-source window limit in all-pairs passes
     int cus = 256;
+    int max_lds = 65536;  // LDS bytes one workgroup may use
     // graphs
     int graph_steps = 50;  // steps captured per graph (0: no graphs)
     std::map<std::string, GraphRec> graphs;
@@ -246,13 +254,21 @@ gsim_status prepare_surface(gsim_ctx *c, const Member &mb, bool small, int src_b
     const int n = ms->n;
     const DevMesh &m = ms->dm;
     if (n <= 0) return fail(c, GSIM_E_STATE, "no particles on this mesh");
-    if (!finite_cutoff(mb.cutoff)) return fail(c, GSIM_E_ARG, "cutoff must be positive and finite");
+    const bool all = !finite_cutoff(mb.cutoff);
+    if (all && n > kAllPairsMax)
+        return fail(c, GSIM_E_LIMIT, "all-pairs mode holds at most " + std::to_string(kAllPairsMax) +
+                                         " particles per surface");
     if (c->prec == GSIM_FP32_MIXED && 3 * (int64_t)m.nf >= (int64_t(1) << 24))
         return fail(c, GSIM_E_LIMIT, "FP32-mixed mode packs half-edge ids in 24 bits: mesh too large");
     std::memset(&d, 0, sizeof(d));
-    choose_grid(m, mb.cutoff, small, d.dims, d.cell);
+    if (all) {
+        d.dims[0] = d.dims[1] = d.dims[2] = 1;
+        d.cell = 1.0;
+    } else {
+        choose_grid(m, mb.cutoff, small, d.dims, d.cell);
+    }
     const int64_t ncell = (int64_t)d.dims[0] * d.dims[1] * d.dims[2];
-    const size_t cap = kCandCap;
+    const size_t cap = all ? (size_t)n : (size_t)kCandCap;
     HIPCHK(c, ensure(ms->cell_of, sizeof(int32_t) * n));
     HIPCHK(c, ensure(ms->cell_start, sizeof(int32_t) * (ncell + 1)));
     HIPCHK(c, ensure(ms->cell_fill, sizeof(int32_t) * ncell));
@@ -264,7 +280,23 @@ gsim_status prepare_surface(gsim_ctx *c, const Member &mb, bool small, int src_b
     HIPCHK(c, ensure(ms->cflags, (size_t)n * cap));
     HIPCHK(c, ensure(ms->tmp64, sizeof(int64_t) * (std::max<int64_t>(ncell, n) + 1)));
     HIPCHK(c, ensure(ms->wflags, n));
-    HIPCHK(c, ensure(c->scan_scratch, sizeof(int64_t) * ((std::max<int64_t>(ncell, n) + 1023) / 1024 + 2)));
+    const int64_t nscan = std::max<int64_t>(std::max<int64_t>(ncell, n), all ? m.nf : 0);
+    HIPCHK(c, ensure(ms->tmp64, sizeof(int64_t) * (nscan + 1)));
+    HIPCHK(c, ensure(c->scan_scratch, sizeof(int64_t) * ((nscan + 1023) / 1024 + 2)));
+    HIPCHK(c, ensure(ms->F, sizeof(double) * 3 * n));
+    HIPCHK(c, ensure(ms->fire, sizeof(FireState)));
+    if (all) {
+        HIPCHK(c, ensure(ms->fstart, sizeof(int32_t) * (m.nf + 1)));
+        HIPCHK(c, ensure(ms->forder, sizeof(int32_t) * n));
+        HIPCHK(c, ensure(ms->fcount, sizeof(int32_t) * m.nf));
+        if (ms->ident_n != n || ms->cap != (int)cap) {
+            HIPCHK(c, launch_identity_rows(n, (int)cap, P<int32_t>(ms->cand_cnt), P<int32_t>(ms->cand), c->stream));
+            ms->ident_n = n;
+        }
+    } else {
+        ms->ident_n = -1;  // the candidate search rewrites the rows
+    }
+    ms->cap = (int)cap;
     d.m = m;
     d.n = n;
     d.src_begin = src_begin;
@@ -276,13 +308,17 @@ gsim_status prepare_surface(gsim_ctx *c, const Member &mb, bool small, int src_b
     d.cell_start = P<int32_t>(ms->cell_start);
     d.order = P<int32_t>(ms->order);
     for (int k = 0; k < 3; ++k) d.lo[k] = m.bbmin[k];
+    d.cap = (int)cap;
+    d.all_pairs = all ? 1 : 0;
+    d.fstart = all ? P<int32_t>(ms->fstart) : nullptr;
+    d.forder = all ? P<int32_t>(ms->forder) : nullptr;
     d.cand_cnt = P<int32_t>(ms->cand_cnt);
     d.cand = P<int32_t>(ms->cand);
     d.cdist = P<double>(ms->cdist);
     d.ctan = P<double>(ms->ctan);
     d.cflags = P<uint8_t>(ms->cflags);
-    d.cutoff = mb.cutoff;
-    d.cut2 = mb.cutoff * mb.cutoff * (1.0 + 1e-12);
+    d.cutoff = all ? INFINITY : mb.cutoff;
+    d.cut2 = all ? INFINITY : mb.cutoff * mb.cutoff * (1.0 + 1e-12);
     if (mb.pot) {
         d.pkind = mb.pot->kind;
         d.pk = mb.pot->k;
@@ -295,7 +331,17 @@ gsim_status prepare_surface(gsim_ctx *c, const Member &mb, bool small, int src_b
         d.kT = mb.integ->kT;
         d.friction = mb.integ->friction;
         d.seed = mb.integ->seed;
+        const gsim_integrator &g = *mb.integ;
+        d.max_disp = g.max_disp > 0.0 ? g.max_disp : INFINITY;
+        d.dt_max = g.dt_max > 0.0 ? g.dt_max : 10.0 * g.dt;
+        d.alpha0 = g.alpha0 > 0.0 ? g.alpha0 : 0.1;
+        d.f_alpha = g.f_alpha > 0.0 ? g.f_alpha : 0.99;
+        d.f_inc = g.f_inc > 0.0 ? g.f_inc : 1.1;
+        d.f_dec = g.f_dec > 0.0 ? g.f_dec : 0.5;
+        d.n_min = g.n_min > 0 ? g.n_min : 5;
     }
+    d.F = P<double>(ms->F);
+    d.fire = P<FireState>(ms->fire);
     d.step = P<uint64_t>(ms->step_dev);
     d.wflags = P<uint8_t>(ms->wflags);
     return GSIM_OK;
@@ -305,6 +351,11 @@ struct Batch {
     std::vector<Member> mem;
     std::vector<SurfDesc> desc;
     BatchIdx bi{};
+    BatchIdx fire_blk{};  // blocks of kFireBlock particles per surface (FIRE reductions)
+    bool any_fire = false;
+    bool all = false;     // all-pairs surfaces (no cutoff)
+    int tcap = 0;         // all-pairs target-table capacity
+    int64_t vstride = 0;  // all-pairs vertex-table stride
     bool small = true;  // every surface bins in one workgroup
     int nslots = 0;
     GeoShape shape{};
@@ -329,9 +380,13 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
     for (int i = 0; i < ns; ++i)
         for (int j = 0; j < i; ++j)
             if (B.mem[i].ms == B.mem[j].ms) return fail(c, GSIM_E_ARG, "a mesh appears twice in the batch");
+    B.all = !finite_cutoff(B.mem[0].cutoff);
+    for (int i = 1; i < ns; ++i)
+        if (!finite_cutoff(B.mem[i].cutoff) != B.all)
+            return fail(c, GSIM_E_ARG, "a batch mixes cutoff and all-pairs surfaces");
     // a single surface may use the multi-kernel binning for a fine grid
     B.small = true;
-    if (ns == 1) {
+    if (ns == 1 && !B.all) {
         int dims[3];
         double cell;
         choose_grid(B.mem[0].ms->dm, B.mem[0].cutoff, false, dims, cell);
@@ -347,6 +402,20 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
         total += B.mem[i].ms->n;
     }
     B.bi.begin[ns] = total;
+    B.fire_blk.nsurf = ns;
+    B.any_fire = false;
+    int nblk = 0;
+    B.tcap = 0;
+    B.vstride = 0;
+    for (int i = 0; i < ns; ++i) {
+        B.fire_blk.begin[i] = nblk;
+        nblk += (B.mem[i].ms->n + kFireBlock - 1) / kFireBlock;
+        B.any_fire |= B.mem[i].integ && B.mem[i].integ->kind == GSIM_INT_FIRE;
+        B.tcap = std::max(B.tcap, B.mem[i].ms->n);
+        B.vstride = std::max<int64_t>(B.vstride, B.mem[i].ms->dm.nv);
+    }
+    B.fire_blk.begin[ns] = nblk;
+    if (B.any_fire) HIPCHK(c, ensure(c->partials, sizeof(double) * 3 * (size_t)std::max(nblk, 1)));
     if (c->profile_sources && ns == 1) {
         const int n = B.mem[0].ms->n;
         if (c->prof_n != n) {
@@ -358,12 +427,24 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
     }
     // persistent grid: as many wavefronts as can be resident, at most one per source
     const bool fp32 = c->prec == GSIM_FP32_MIXED;
-    const int per_cu = std::max(1, geodesic_blocks_per_cu(c->lds_stack_kb, fp32));
+    if (B.all && (size_t)B.tcap * 32 + 28672 > (size_t)c->max_lds)
+        return fail(c, GSIM_E_LIMIT, "all-pairs target table of " + std::to_string(B.tcap) +
+                                         " particles exceeds the device's LDS per workgroup (" +
+                                         std::to_string(c->max_lds) + " bytes)");
+    const int per_cu = std::max(1, B.all ? geodesic_all_blocks_per_cu(c->lds_stack_kb, B.tcap, fp32)
+                                         : geodesic_blocks_per_cu(c->lds_stack_kb, fp32));
     B.nslots = std::min(std::min(total, c->cus * per_cu), c->max_slots);
+    if (B.all) {
+        // whole-mesh fronts are deep: fewer resident wavefronts rather than more memory
+        const int64_t fit = (int64_t)(c->stack_budget / (64.0 * c->stack_cap_all));
+        B.nslots = (int)std::max<int64_t>(1, std::min<int64_t>(B.nslots, fit));
+    }
     B.shape.lds_stack_kb = c->lds_stack_kb;
     B.shape.nslots = B.nslots;
     B.shape.grab = c->grab;
-    HIPCHK(c, ensure(c->stack, (size_t)std::max(B.nslots, 1) * c->gp.stack_cap * 64));
+    const int cap_rec = B.all ? c->stack_cap_all : c->gp.stack_cap;
+    HIPCHK(c, ensure(c->stack, (size_t)std::max(B.nslots, 1) * cap_rec * 64));
+    if (B.all) HIPCHK(c, ensure(c->vdist, sizeof(double) * (size_t)std::max(B.nslots, 1) * B.vstride));
     return upload_descs(c, B.desc);
 }
 
@@ -372,6 +453,26 @@ const SurfDesc *desc_dev(gsim_ctx *c) { return static_cast<const SurfDesc *>(c->
 // Binning, candidate search and geodesics of every source of the batch.
 gsim_status geodesic_pass(gsim_ctx *c, Batch &B) {
     hipStream_t s = c->stream;
+    if (B.all) {
+        {
+            Stage st(c, "prefilter");
+            for (size_t i = 0; i < B.mem.size(); ++i) {
+                MeshState *ms = B.mem[i].ms;
+                HIPCHK(c, launch_face_sort(B.desc[i], P<int32_t>(ms->fcount), P<int64_t>(ms->tmp64),
+                                           P<int64_t>(c->scan_scratch), s));
+            }
+        }
+        HIPCHK(c, launch_zero_i32(P<int32_t>(c->work), 16, s));
+        GeoParams gp = c->gp;
+        gp.stack_cap = c->stack_cap_all;
+        gp.max_windows = c->max_windows_all;
+        Stage st(c, "geodesic");
+        HIPCHK(c, launch_geodesic_all(desc_dev(c), B.bi, gp, B.shape, P<char>(c->stack), P<double>(c->vdist), B.vstride,
+                                      B.tcap, P<int32_t>(c->work), P<Counters>(c->ctr), c->prec == GSIM_FP32_MIXED,
+                                      s));
+        c->passes++;
+        return GSIM_OK;
+    }
     {
         Stage st(c, "prefilter");
         if (B.small) {
@@ -413,6 +514,10 @@ gsim_status geodesic_pass(gsim_ctx *c, Batch &B) {
 }
 
 gsim_status update_pass(gsim_ctx *c, Batch &B) {
+    if (B.any_fire) {
+        Stage sf(c, "fire");
+        HIPCHK(c, launch_fire_control(desc_dev(c), B.fire_blk, P<double>(c->partials), P<Counters>(c->ctr), c->stream));
+    }
     Stage sg(c, "update");
     HIPCHK(c, launch_update_batch(desc_dev(c), B.bi, c->update_block, P<Counters>(c->ctr), c->stream));
     return GSIM_OK;
@@ -428,7 +533,8 @@ gsim_status single(gsim_ctx *c, MeshState *ms, double cutoff, const gsim_potenti
 // Compact the candidate rows into the caller-facing CSR (host sync for the size).
 gsim_status compact_pairs(gsim_ctx *c, MeshState *ms, double cutoff) {
     hipStream_t s = c->stream;
-    const int n = ms->n, cap = kCandCap;
+    const int n = ms->n, cap = ms->cap;
+    if (!finite_cutoff(cutoff)) cutoff = INFINITY;
     Stage st(c, "compact");
     HIPCHK(c, ensure(ms->nbr_cnt, sizeof(int32_t) * (n + 1)));
     HIPCHK(c, ensure(ms->off, sizeof(int64_t) * (n + 1)));
@@ -452,13 +558,14 @@ gsim_status compact_pairs(gsim_ctx *c, MeshState *ms, double cutoff) {
 
 gsim_status run_forces(gsim_ctx *c, MeshState *ms, const gsim_potential *pot) {
     const int n = ms->n;
+    const double cutoff = finite_cutoff(pot->cutoff) ? pot->cutoff : INFINITY;
     HIPCHK(c, ensure(ms->F, sizeof(double) * 3 * n));
     HIPCHK(c, ensure(ms->Ei, sizeof(double) * n));
     HIPCHK(c, ensure(ms->E, sizeof(double) * 4));
     HIPCHK(c, ensure(c->sum_scratch, sizeof(double) * ((n + 255) / 256 + 2)));
     Stage st(c, "forces");
-    HIPCHK(c, launch_forces_rows(n, P<int32_t>(ms->cand_cnt), kCandCap, P<double>(ms->cdist), P<double>(ms->ctan),
-                                 pot->cutoff, pot->kind, pot->k, pot->sigma, P<double>(ms->F), P<double>(ms->Ei),
+    HIPCHK(c, launch_forces_rows(n, P<int32_t>(ms->cand_cnt), ms->cap, P<double>(ms->cdist), P<double>(ms->ctan),
+                                 cutoff, pot->kind, pot->k, pot->sigma, P<double>(ms->F), P<double>(ms->Ei),
                                  &P<Counters>(c->ctr)->nbr_pairs, c->stream));
     HIPCHK(c, launch_sum(P<double>(ms->Ei), n, P<double>(ms->E), P<double>(c->sum_scratch), c->stream));
     return GSIM_OK;
@@ -541,8 +648,9 @@ gsim_status run_steps(gsim_ctx *c, Batch &B, int nsteps) {
 
 gsim_status check_integ(gsim_ctx *c, const gsim_integrator *integ) {
     if (!integ) return fail(c, GSIM_E_ARG, "null integrator");
-    if (integ->kind != GSIM_INT_OVERDAMPED && integ->kind != GSIM_INT_BROWNIAN)
+    if (integ->kind != GSIM_INT_OVERDAMPED && integ->kind != GSIM_INT_BROWNIAN && integ->kind != GSIM_INT_FIRE)
         return fail(c, GSIM_E_ARG, "unknown integrator");
+    if (!(integ->dt > 0.0) && integ->kind == GSIM_INT_FIRE) return fail(c, GSIM_E_ARG, "FIRE needs dt > 0");
     return GSIM_OK;
 }
 
@@ -583,6 +691,9 @@ gsim_status gsim_create(int device, gsim_precision prec, void *hip_stream, gsim_
     int cus = 0;
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
         c->cus = cus;
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
+        c->max_lds = lds;
     c->gp.cutoff = 0.0;
     c->gp.launch_delta = 1e300;  // one bucket: every improved bend vertex once the stack drains
     c->gp.cone_tol = 1e-12;
@@ -593,9 +704,13 @@ gsim_status gsim_create(int device, gsim_precision prec, void *hip_stream, gsim_
     c->gp.tie_rel32 = 1e-4;
     c->gp.tie_dir32 = 5e-6;
     c->gp.root_rel32 = 2e-6;
+    c->gp.bucket = 0.0;
+    c->gp.dom_rel = 1e-12;
+    c->gp.dom_rel32 = 1e-4;  // FP32 window chains across a whole surface carry errors up to ~1e-5
     c->gp.eager = 0;
     c->gp.stack_cap = 2048;
     c->gp.max_windows = 4000000;
+    c->max_windows_all = 1 << 26;
     if (ensure(c->work, sizeof(int32_t) * 16) != hipSuccess || ensure(c->ctr, sizeof(Counters)) != hipSuccess ||
         ensure(c->wstats, sizeof(unsigned long long) * 8) != hipSuccess ||
         ensure(c->pf_over, sizeof(int32_t) * 4) != hipSuccess ||
@@ -619,7 +734,8 @@ void gsim_destroy(gsim_ctx *c) {
         if (!ms) continue;
         for (Buf *b : {&ms->cell_of, &ms->cell_start, &ms->cell_fill, &ms->order, &ms->cand_cnt, &ms->cand,
                        &ms->tmp64, &ms->cdist, &ms->ctan, &ms->cflags, &ms->nbr_cnt, &ms->off, &ms->nbr, &ms->dist,
-                       &ms->tan, &ms->flags, &ms->F, &ms->Ei, &ms->E, &ms->disp, &ms->wflags, &ms->step_dev})
+                       &ms->tan, &ms->flags, &ms->F, &ms->Ei, &ms->E, &ms->disp, &ms->wflags, &ms->step_dev,
+                       &ms->fire, &ms->fstart, &ms->forder, &ms->fcount})
             release(*b);
         for (void *p : {(void *)ms->face, (void *)ms->bary, (void *)ms->vel, (void *)ms->xyz})
             if (p) (void)hipFree(p);
@@ -630,7 +746,7 @@ void gsim_destroy(gsim_ctx *c) {
         delete ms;
     }
     for (Buf *b : {&c->stack, &c->work, &c->ctr, &c->wstats, &c->scan_scratch, &c->sum_scratch, &c->pf_over,
-                   &c->prof, &c->desc})
+                   &c->prof, &c->desc, &c->vdist, &c->partials})
         release(*b);
     if (c->desc_pinned) (void)hipHostFree(c->desc_pinned);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -749,6 +865,8 @@ static gsim_status reset_state(gsim_ctx *c, MeshState *ms, const double *vel, hi
     if (vel) HIPCHK(c, hipMemcpyAsync(ms->vel, vel, sizeof(double) * 3 * n, kind, s));
     else HIPCHK(c, launch_zero_u64(reinterpret_cast<unsigned long long *>(ms->vel), 3 * (int64_t)n, s));
     HIPCHK(c, launch_zero_u64(P<unsigned long long>(ms->step_dev), 1, s));
+    HIPCHK(c, ensure(ms->fire, sizeof(FireState)));
+    HIPCHK(c, launch_zero_u64(P<unsigned long long>(ms->fire), sizeof(FireState) / 8, s));
     ms->step = 0;
     return GSIM_OK;
 }
@@ -1092,6 +1210,11 @@ gsim_status gsim_tune_set(gsim_ctx *c, const char *name, double value) {
     else if (k == "grab" && value >= 1 && value <= 64) c->grab = (int)value;
     else if (k == "update_block" && (value == 64 || value == 128 || value == 256)) c->update_block = (int)value;
     else if (k == "graph_steps" && value >= 0 && value <= 1000) c->graph_steps = (int)value;
+    else if (k == "stack_cap_all" && value >= 1024 && value <= (1 << 22)) c->stack_cap_all = (int)value;
+    else if (k == "max_windows_all" && value >= 1) c->max_windows_all = (int32_t)std::min(value, 2.0e9);
+    else if (k == "bucket" && value >= 0.0) c->gp.bucket = value;
+    else if (k == "dom_rel" && value >= 0.0) c->gp.dom_rel = value;
+    else if (k == "dom_rel32" && value >= 0.0) c->gp.dom_rel32 = value;
     else return fail(c, GSIM_E_ARG, "unknown tuning knob or value out of range: " + k);
     drop_graphs(c);
     return GSIM_OK;
@@ -1111,6 +1234,7 @@ gsim_status gsim_source_profile(gsim_ctx *c, int on, int64_t *out, int32_t n) {
 
 gsim_status gsim_counters_get(gsim_ctx *c, int64_t *c10) {
     if (!c || !c10) return GSIM_E_ARG;
+    c10[10] = (int64_t)c->last.max_depth;
     c10[7] = (int64_t)c->cum_pairs;
     c10[8] = (int64_t)c->cum_windows;
     c10[9] = (int64_t)c->cum_passes;

@@ -22,10 +22,9 @@ struct alignas(16) HeRec {
     double ux, uy;  // (L - cx, -cy) / Ln: axis of the frame on edge C->B
     int32_t tn;  // twin(next(h)) : the half-edge entered across BC, -1 on the boundary
     int32_t tp;  // twin(prev(h)) : the half-edge entered across CA
-    int32_t opp; // vertex C
-    int32_t flags;  // bit0: C is a pseudo-source vertex
-    int32_t twin;   // twin(h)
-    int32_t pad;
+    int32_t opp_flags;  // (C << 1) | (C is a pseudo-source vertex)
+    int32_t twin;       // twin(h)
+    int32_t tail, head; // vertices A and B
 };
 static_assert(sizeof(HeRec) == 96, "HeRec must be a 96-byte record");
 
@@ -101,6 +100,8 @@ struct GeoParams {
     double tie_dir;       // two candidate tangents closer than this (rad) are the same direction
     double guard_rel;     // FP32 results this close (relative) to the cutoff are recomputed in FP64
     double cone_tol32, tie_rel32, tie_dir32;  // the FP32 pass's counterparts
+    double bucket;        // all-pairs: key width of one processing round (0 = two max edge lengths)
+    double dom_rel, dom_rel32;  // all-pairs: vertex-path domination margins (FP64 pass / FP32 pass)
     double root_rel32;    // FP32 pass: a bend vertex is re-launched only when its distance improves by more
                           // than this fraction (FP32 rounding makes equal paths differ by ~1e-7)
     int32_t eager;        // launch bend vertices as soon as they are found
@@ -115,7 +116,7 @@ struct GeoOut {
 };
 
 struct Counters {   // device-side, int64
-    unsigned long long windows, pruned, launches, stale, cand_pairs, nbr_pairs, limited, pad;
+    unsigned long long windows, pruned, launches, stale, cand_pairs, nbr_pairs, limited, max_depth;
 };
 
 // launchers (return hipError_t of the launch)
@@ -139,15 +140,24 @@ struct SurfDesc {
     int32_t *cell_of, *cell_start, *order;
     int32_t dims[3];
     double cell, lo[3];
-    // candidate rows [n][kMaxCand], sorted by j
+    // candidate rows [n][cap], sorted by j (all-pairs: row i holds every j)
+    int32_t cap;
+    int32_t all_pairs;  // no cutoff: every other particle is a target
     int32_t *cand_cnt, *cand;
     double *cdist, *ctan;
     uint8_t *cflags;
     double cutoff, cut2;
+    // particles by face (all-pairs target lookup): forder[fstart[f] .. fstart[f+1])
+    int32_t *fstart, *forder;
     // potential and integrator of the fused update
     int32_t pkind, ikind;
     double pk, psigma, dt, mobility, kT, friction;
     uint64_t seed;
+    // FIRE: parameters, forces of the current iteration, state on the device
+    double max_disp, dt_max, alpha0, f_alpha, f_inc, f_dec;
+    int32_t n_min;
+    double *F;                // [n][3]
+    struct FireState *fire;
     uint64_t *step;  // device counter: steps since the particles were set
     uint8_t *wflags;
     long long *prof;  // optional per-source profile [n][8]
@@ -156,6 +166,17 @@ struct SurfDesc {
 // Capacity of a candidate row: the most Euclidean candidates one source may
 // have (its targets live in an LDS table of the geodesic kernel).
 constexpr int kCandCap = 128;
+// Most particles on one surface in all-pairs mode (the target table of a
+// source, 32 bytes per target, lives in LDS).
+constexpr int kAllPairsMax = 4096;
+
+// FIRE state of one surface (device memory): time step, mixing factor,
+// consecutive iterations with positive power, and the mixing coefficients
+// of the current iteration (v <- cv v + cf F).
+struct FireState {
+    double dt, alpha, cv, cf;
+    int32_t n_pos, init;
+};
 
 constexpr int kMaxBatch = 64;
 // Surface boundaries of a batch, passed by value: surface s owns the
@@ -186,6 +207,23 @@ struct GeoShape {
 // the batch, one wavefront per source. The cell lists must be current.
 hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoParams &gp, const GeoShape &shape,
                            char *stack_mem, int32_t *work_ctr, Counters *ctr, bool fp32, hipStream_t s);
+// All-pairs geodesics (no cutoff) for every source of the batch: every other
+// particle of the surface is a target. vdist: per resident wavefront a table
+// of vstride vertex distances; tcap: target-table capacity (dynamic LDS).
+hipError_t launch_geodesic_all(const SurfDesc *desc, const BatchIdx &bi, const GeoParams &gp, const GeoShape &shape,
+                               char *stack_mem, double *vdist, int64_t vstride, int tcap, int32_t *work_ctr,
+                               Counters *ctr, bool fp32, hipStream_t s);
+int geodesic_all_blocks_per_cu(int lds_stack_kb, int tcap, bool fp32);
+// particles of one surface sorted by face (counting sort; counts must be zeroed)
+hipError_t launch_face_sort(const SurfDesc &d, int32_t *counts, int64_t *tmp64, int64_t *scan_scratch, hipStream_t s);
+// row i of an all-pairs surface lists every particle j in order
+hipError_t launch_identity_rows(int n, int cap, int32_t *cand_cnt, int32_t *cand, hipStream_t s);
+// FIRE: forces and the power / norm reduction of every FIRE surface (blk:
+// blocks of 256 particles per surface), then the control step
+constexpr int kFireBlock = 256;
+hipError_t launch_fire_control(const SurfDesc *desc, const BatchIdx &blk, double *partials, Counters *ctr,
+                               hipStream_t s);
+
 // LDS bytes of one geodesic workgroup for a stack size (occupancy planning)
 size_t geodesic_lds_bytes(int lds_stack_kb, bool fp32);
 // positions + cell counting sort, one workgroup per surface (every surface's

@@ -52,81 +52,16 @@
 #include <cmath>
 
 #include "gsim_internal.h"
+#include "window.h"
 
 namespace gsim {
 namespace {
 
-constexpr int kWave = 64;
+using namespace wnd;
+
 constexpr int kMaxCand = kCandCap;
 constexpr int kHash = 256;
-// bend-vertex table: 255 slots so that slot + 1 fits the 8 bits the FP32
-// stack record keeps for it
-constexpr int kRootCap = 255;
 constexpr int kChunks = 8;
-
-template <typename R>
-struct Win {
-    R px, py, b0, b1, sg, c, s;
-    int he, root;
-};
-
-// stack records: 64 bytes (FP64) / 32 bytes (FP32, he and root packed)
-struct Rec64 {
-    double v[7];
-    int32_t he, root;
-};
-struct Rec32 {
-    float v[7];
-    uint32_t hr;  // (he << 8) | (root + 1), root + 1 in [0, kRootCap]
-};
-static_assert(sizeof(Rec64) == 64 && sizeof(Rec32) == 32, "stack record sizes");
-template <typename R>
-struct RecOf;
-template <>
-struct RecOf<double> {
-    using T = Rec64;
-};
-template <>
-struct RecOf<float> {
-    using T = Rec32;
-};
-
-__device__ inline void store_rec(Rec64 &q, const Win<double> &w) {
-    q.v[0] = w.px; q.v[1] = w.py; q.v[2] = w.b0; q.v[3] = w.b1; q.v[4] = w.sg; q.v[5] = w.c; q.v[6] = w.s;
-    q.he = w.he;
-    q.root = w.root;
-}
-__device__ inline void load_rec(const Rec64 &q, Win<double> &w) {
-    w.px = q.v[0]; w.py = q.v[1]; w.b0 = q.v[2]; w.b1 = q.v[3]; w.sg = q.v[4]; w.c = q.v[5]; w.s = q.v[6];
-    w.he = q.he;
-    w.root = q.root;
-}
-__device__ inline void store_rec(Rec32 &q, const Win<float> &w) {
-    q.v[0] = w.px; q.v[1] = w.py; q.v[2] = w.b0; q.v[3] = w.b1; q.v[4] = w.sg; q.v[5] = w.c; q.v[6] = w.s;
-    q.hr = ((uint32_t)w.he << 8) | (uint32_t)(w.root + 1);
-}
-__device__ inline void load_rec(const Rec32 &q, Win<float> &w) {
-    w.px = q.v[0]; w.py = q.v[1]; w.b0 = q.v[2]; w.b1 = q.v[3]; w.sg = q.v[4]; w.c = q.v[5]; w.s = q.v[6];
-    w.he = (int)(q.hr >> 8);
-    w.root = (int)(q.hr & 255u) - 1;
-}
-
-// half-edge record in the working precision
-template <typename R>
-struct He {
-    R L, cx, cy, Lp, Ln, ex, ey, ux, uy;
-    int tn, tp, opp;
-    bool pseudo;
-};
-__device__ inline He<double> load_he(const DevMesh &m, int h, double) {
-    const HeRec r = m.he[h];
-    return {r.L, r.cx, r.cy, r.Lp, r.Ln, r.ex, r.ey, r.ux, r.uy, r.tn, r.tp, r.opp, (r.flags & 1) != 0};
-}
-__device__ inline He<float> load_he(const DevMesh &m, int h, float) {
-    const HeRecF r = m.hef[h];
-    return {r.L, r.cx, r.cy, r.Lp, r.Ln, r.ex, r.ey, r.ux, r.uy, r.tn, r.tp, r.opp_flags >> 1,
-            (r.opp_flags & 1) != 0};
-}
 
 struct GeoArgs {
     const SurfDesc *sd;  // [nsurf] surface descriptors
@@ -144,28 +79,11 @@ struct Lds {
     alignas(16) double cb[kMaxCand][4];  // target position and current pruning bound
     double d1[kMaxCand], d2[kMaxCand], t1x[kMaxCand], t1y[kMaxCand];
     int32_t head[kHash];
-    int32_t rkey[kRootCap + 1];
-    double rD[kRootCap], rL[kRootCap], rtx[kRootCap], rty[kRootCap];
-    int32_t rcount, dirty, ncand;
-    int32_t sel[kRootCap + 1];   // launch list: root slots
-    int32_t pref[kRootCap + 2];  // prefix sums of their fan sizes
+    int32_t ncand;
+    Roots R;
 };
 
-__device__ inline int lane_id() { return threadIdx.x; }
-__device__ inline uint64_t lanemask_lt() { return (1ull << threadIdx.x) - 1ull; }
 __device__ inline int hash_face(int f) { return (int)(((uint32_t)f * 2654435761u) >> 24) & (kHash - 1); }
-__device__ inline int hash_vert(int v) { return (int)((((uint32_t)v * 2246822519u) >> 16) % kRootCap); }
-
-__device__ inline double wave_min(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
-    return v;
-}
-
-template <typename R>
-__device__ inline R seg_dist(R px, R py, R b0, R b1) {
-    R dx = px < b0 ? b0 - px : (px > b1 ? px - b1 : R(0));
-    return sqrt(dx * dx + py * py);
-}
 
 __device__ inline int first_in_face(const Lds &L, int f) {
     int s = L.head[hash_face(f)];
@@ -182,6 +100,7 @@ __device__ inline int next_in_face(const Lds &L, int s, int f) {
 struct Ctx {
     double cutoff, cut_acc, lb_slack, tol, tie_rel, tie_dir;
     double root_keep;  // 1 - relative improvement below which a bend vertex is not re-launched
+    RootCfg rc;
     int nc;
 };
 
@@ -204,8 +123,11 @@ __device__ inline bool reaches_target(const Lds &L, const Ctx &C, const double P
 }
 
 // Serialised target update: best distance, its tangent, and the best
-// distance among candidates whose direction differs (tie gap).
-__device__ inline void target_update(Lds &L, const Ctx &C, bool ok, int slot, double d, double tx, double ty) {
+// distance among candidates whose direction differs (tie gap); `alt` is the
+// distance of another-direction path that comes with the candidate (through
+// a bend vertex with a second distance).
+__device__ inline void target_update(Lds &L, const Ctx &C, bool ok, int slot, double d, double tx, double ty,
+                                     double alt) {
     uint64_t m = __ballot(ok);
     while (m) {
         int l = __ffsll((unsigned long long)m) - 1;
@@ -222,128 +144,10 @@ __device__ inline void target_update(Lds &L, const Ctx &C, bool ok, int slot, do
             } else if (differ) {
                 L.d2[slot] = fmin(L.d2[slot], d);
             }
+            L.d2[slot] = fmin(L.d2[slot], alt);
         }
         m &= m - 1;
     }
-}
-
-// Serialised bend-vertex update (insert or improve): keeps the smallest
-// distance and its tangent; marks the table dirty when the vertex needs a
-// (re-)launch.
-__device__ inline void root_update(Lds &L, const Ctx &C, bool ok, int v, double d, double tx, double ty,
-                                   bool &overflow) {
-    uint64_t m = __ballot(ok);
-    while (m) {
-        int l = __ffsll((unsigned long long)m) - 1;
-        if (lane_id() == l) {
-            int e = hash_vert(v), probes = 0;
-            while (L.rkey[e] >= 0 && L.rkey[e] != v && probes < kRootCap) {
-                e = e + 1 == kRootCap ? 0 : e + 1;
-                ++probes;
-            }
-            if (probes >= kRootCap || (L.rkey[e] < 0 && L.rcount >= kRootCap - 1)) {
-                overflow = true;
-            } else if (L.rkey[e] < 0) {
-                L.rkey[e] = v;
-                L.rD[e] = d;
-                L.rL[e] = INFINITY;
-                L.rtx[e] = tx;
-                L.rty[e] = ty;
-                L.rcount++;
-                L.dirty = 1;
-            } else if (d < L.rD[e]) {
-                L.rD[e] = d;
-                L.rtx[e] = tx;
-                L.rty[e] = ty;
-                if (d < L.rL[e] * C.root_keep) L.dirty = 1;
-            }
-        }
-        m &= m - 1;
-    }
-}
-
-// Two-level window stack: LDS first, a per-wave global area for overflow.
-template <typename R>
-struct Stack {
-    using Rec = typename RecOf<R>::T;
-    int kL;  // LDS records
-    Rec *lds;
-    Rec *glb;
-    int gcap;
-    int lsp, gsp;
-
-    __device__ void push(bool want, const Win<R> &w, bool &overflow) {
-        uint64_t m = __ballot(want);
-        int cnt = __popcll(m);
-        if (!cnt) return;
-        int r = __popcll(m & lanemask_lt());
-        int space = kL - lsp;
-        if (want) {
-            if (r < space) {
-                store_rec(lds[lsp + r], w);
-            } else {
-                int pos = gsp + (r - space);
-                if (pos < gcap) store_rec(glb[pos], w);
-                else overflow = true;
-            }
-        }
-        int to_l = min(cnt, space);
-        lsp += to_l;
-        gsp = min(gsp + (cnt - to_l), gcap);
-    }
-    // refill lanes without a window; returns whether any lane holds one
-    __device__ bool refill(bool &have, Win<R> &w) {
-        uint64_t need = __ballot(!have);
-        int nneed = __popcll(need);
-        int r = __popcll(need & lanemask_lt());
-        int take_l = min(nneed, lsp);
-        if (!have && r < take_l) {
-            load_rec(lds[lsp - 1 - r], w);
-            have = true;
-        }
-        lsp -= take_l;
-        if (nneed > take_l && gsp > 0) {
-            __syncthreads();  // make earlier global pushes of other lanes visible
-            int take_g = min(nneed - take_l, gsp);
-            if (!have && r >= take_l && r < take_l + take_g) {
-                load_rec(glb[gsp - 1 - (r - take_l)], w);
-                have = true;
-            }
-            gsp -= take_g;
-        }
-        return __ballot(have) != 0;
-    }
-};
-
-// Child intervals. Left child: across C->A (stored on tp, frame origin A,
-// x towards C). Right child: across B->C (stored on tn, frame origin C, x
-// towards B). The endpoint intersections are evaluated in FP64 in both
-// precisions.
-template <typename R>
-__device__ inline void child_left(const He<R> &h, const Win<R> &w, double txc, bool full, double &x0, double &x1) {
-    if (full) {
-        x0 = 0.0;
-        x1 = (double)h.Lp;
-        return;
-    }
-    const double px = w.px, py = w.py, b0 = w.b0, b1 = w.b1, cx = h.cx, cy = h.cy, Lp = h.Lp;
-    x0 = b0 <= 0.0 ? 0.0 : Lp * (py * b0) / (py * cx + cy * (b0 - px));
-    x1 = b1 >= txc ? Lp : Lp * (py * b1) / (py * cx + cy * (b1 - px));
-    x0 = fmin(fmax(x0, 0.0), Lp);
-    x1 = fmin(fmax(x1, 0.0), Lp);
-}
-template <typename R>
-__device__ inline void child_right(const He<R> &h, const Win<R> &w, double txc, bool full, double &x0, double &x1) {
-    if (full) {
-        x0 = 0.0;
-        x1 = (double)h.Ln;
-        return;
-    }
-    const double px = w.px, py = w.py, b0 = w.b0, b1 = w.b1, cx = h.cx, cy = h.cy, L = h.L, Ln = h.Ln;
-    x0 = b0 <= txc ? 0.0 : Ln * ((px - cx) * (-py) - (py - cy) * (b0 - px)) / ((L - cx) * (-py) + cy * (b0 - px));
-    x1 = b1 >= L ? Ln : Ln * ((px - cx) * (-py) - (py - cy) * (b1 - px)) / ((L - cx) * (-py) + cy * (b1 - px));
-    x0 = fmin(fmax(x0, 0.0), Ln);
-    x1 = fmin(fmax(x1, 0.0), Ln);
 }
 
 // Both children of a window. F3: the face's vertices in 3D in the order
@@ -358,16 +162,7 @@ __device__ inline void children(const He<R> &h, const Win<R> &w, double txc, boo
     if (h.tp >= 0 && (full || (double)w.b0 < txc)) {
         double x0, x1;
         child_left(h, w, txc, full, x0, x1);
-        const R ex = h.ex, ey = h.ey;
-        cl.px = ex * w.px + ey * w.py;
-        cl.py = ex * w.py - ey * w.px;
-        cl.b0 = (R)x0;
-        cl.b1 = (R)x1;
-        cl.sg = w.sg;
-        cl.c = w.c * ex - w.s * ey;
-        cl.s = w.s * ex + w.c * ey;
-        cl.he = h.tp;
-        cl.root = w.root;
+        make_left(h, w, x0, x1, cl);
         if (x1 - x0 > 1e-12 * (double)h.Lp) {
             const double base = (double)w.sg + (double)seg_dist(cl.px, cl.py, cl.b0, cl.b1);
             // edge A -> C is the reverse of half-edge prev = (C -> A)
@@ -379,36 +174,13 @@ __device__ inline void children(const He<R> &h, const Win<R> &w, double txc, boo
     if (h.tn >= 0 && (full || (double)w.b1 > txc)) {
         double x0, x1;
         child_right(h, w, txc, full, x0, x1);
-        const R ux = h.ux, uy = h.uy;
-        const R qx = w.px - h.cx, qy = w.py - h.cy;
-        cr.px = ux * qx + uy * qy;
-        cr.py = ux * qy - uy * qx;
-        cr.b0 = (R)x0;
-        cr.b1 = (R)x1;
-        cr.sg = w.sg;
-        cr.c = w.c * ux - w.s * uy;
-        cr.s = w.s * ux + w.c * uy;
-        cr.he = h.tn;
-        cr.root = w.root;
+        make_right(h, w, x0, x1, cr);
         if (x1 - x0 > 1e-12 * (double)h.Ln) {
             const double base = (double)w.sg + (double)seg_dist(cr.px, cr.py, cr.b0, cr.b1);
             // edge C -> B is the reverse of half-edge next = (B -> C)
             const double u[3] = {-U3[1][0], -U3[1][1], -U3[1][2]};
             if (reaches_target(L, C, F3[2], u, x0, x1, base)) hr = true;
             else ++pruned;
-        }
-    }
-}
-
-__device__ inline void face_xyz(const DevMesh &m, int f, int k, double F3[3][3], double U3[3][3]) {
-    const double *p = m.fpos + 18 * (int64_t)f;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) {
-        const int q = (k + i) % 3;
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-            F3[i][d] = p[3 * q + d];
-            U3[i][d] = p[9 + 3 * q + d];
         }
     }
 }
@@ -431,9 +203,9 @@ __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, Lds &L, const
     const HeRec *__restrict__ he = M.he;
     double mn = INFINITY;
     for (int e = lane; e < kRootCap; e += kWave)
-        if (L.rkey[e] >= 0 && L.rD[e] < L.rL[e] * C.root_keep && L.rD[e] < C.cut_acc) mn = fmin(mn, L.rD[e]);
+        if (L.R.rkey[e] >= 0 && L.R.rD[e] < L.R.rL[e] * C.rc.keep && L.R.rD[e] < C.cut_acc) mn = fmin(mn, L.R.rD[e]);
     mn = wave_min(mn);
-    if (lane == 0) L.dirty = 0;
+    if (lane == 0) L.R.dirty = 0;
     if (!(mn < INFINITY)) return;
     const double thr = mn + a.gp.launch_delta;
     // 1. compact the selected roots, mark them launched
@@ -441,25 +213,25 @@ __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, Lds &L, const
     bool left = false;
     for (int base = 0; base < kRootCap; base += kWave) {
         const int e = base + lane;
-        const bool cand = e < kRootCap && L.rkey[e] >= 0 && L.rD[e] < L.rL[e] * C.root_keep && L.rD[e] < C.cut_acc;
-        const bool sel = cand && L.rD[e] <= thr;
+        const bool cand = e < kRootCap && L.R.rkey[e] >= 0 && L.R.rD[e] < L.R.rL[e] * C.rc.keep && L.R.rD[e] < C.cut_acc;
+        const bool sel = cand && L.R.rD[e] <= thr;
         left |= cand && !sel;
         const uint64_t mk = __ballot(sel);
         if (sel) {
-            L.sel[nsel + __popcll(mk & lanemask_lt())] = e;
-            L.rL[e] = L.rD[e];
+            L.R.sel[nsel + __popcll(mk & lanemask_lt())] = e;
+            L.R.rL[e] = L.R.rD[e];
         }
         nsel += __popcll(mk);
     }
-    if (__ballot(left) != 0 && lane == 0) L.dirty = 1;
+    if (__ballot(left) != 0 && lane == 0) L.R.dirty = 1;
     // 2. per root: is any target within reach (3D bound), and its fan size
     int carry = 0;
     for (int base = 0; base < nsel; base += kWave) {
         const int k = base + lane;
         int deg = 0;
         if (k < nsel) {
-            const int e = L.sel[k], v = L.rkey[e];
-            const double D = L.rD[e];
+            const int e = L.R.sel[k], v = L.R.rkey[e];
+            const double D = L.R.rD[e];
             const double vx = M.V[3 * (int64_t)v], vy = M.V[3 * (int64_t)v + 1], vz = M.V[3 * (int64_t)v + 2];
             bool useful = false;
             for (int s = 0; s < C.nc && !useful; ++s) {
@@ -475,11 +247,11 @@ __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, Lds &L, const
             const int y = __shfl_up(inc, o);
             if (lane >= o) inc += y;
         }
-        if (k < nsel) L.pref[k + 1] = carry + inc;
+        if (k < nsel) L.R.pref[k + 1] = carry + inc;
         st.launches += (unsigned long long)__popcll(__ballot(deg > 0));
         carry += __shfl(inc, kWave - 1);
     }
-    if (lane == 0) L.pref[0] = 0;
+    if (lane == 0) L.R.pref[0] = 0;
     const int total = carry;
     // 3. flattened fans: lane <- (root k, fan position)
     for (int base = 0; base < total; base += kWave) {
@@ -490,16 +262,17 @@ __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, Lds &L, const
             int lo = 0, hi = nsel - 1;  // largest k with pref[k] <= idx
             while (lo < hi) {
                 const int mid = (lo + hi + 1) >> 1;
-                if (L.pref[mid] <= idx) lo = mid;
+                if (L.R.pref[mid] <= idx) lo = mid;
                 else hi = mid - 1;
             }
             k = lo;
         }
-        const int el = act ? L.sel[k] : 0;
-        const int v = act ? L.rkey[el] : 0;
-        const double D = act ? L.rD[el] : 0.0;
-        const double vtx = act ? L.rtx[el] : 0.0, vty = act ? L.rty[el] : 0.0;
-        const int h = act ? M.fan[M.fan_off[v] + (idx - L.pref[k])] : 0;
+        const int el = act ? L.R.sel[k] : 0;
+        const int v = act ? L.R.rkey[el] : 0;
+        const double D = act ? L.R.rD[el] : 0.0;
+        const double vtx = act ? L.R.rtx[el] : 0.0, vty = act ? L.R.rty[el] : 0.0;
+        const double D2 = act ? L.R.rD2[el] : INFINITY;  // the root's other-direction distance
+        const int h = act ? M.fan[M.fan_off[v] + (idx - L.R.pref[k])] : 0;
         const int hn = h - h % 3 + (h % 3 + 1) % 3;
         const HeRec Rh = he[h], Rn = he[hn];
         Win<R> nw;
@@ -533,16 +306,16 @@ __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, Lds &L, const
                 const double dx = L.cb[slot][0] - pv[0], dy = L.cb[slot][1] - pv[1], dz = L.cb[slot][2] - pv[2];
                 d = D + sqrt(dx * dx + dy * dy + dz * dz);
             }
-            target_update(L, C, ok, slot, d, vtx, vty);
+            target_update(L, C, ok, slot, d, vtx, vty, D2 + (d - D));
             if (ok) slot = next_in_face(L, slot, g);
         }
         // adjacent bend vertices along the two edges at v
         const int u1 = act ? M.T[hn] : 0;  // head of h
         const bool ok1 = act && (M.vflag[u1] & VF_PSEUDO) && D + Rh.L < C.cut_acc;
-        root_update(L, C, ok1, u1, D + Rh.L, vtx, vty, st.overflow);
-        const int u2 = act ? Rh.opp : 0;
+        root_update(L.R, C.rc, ok1, u1, D + Rh.L, vtx, vty, D2 + Rh.L, st.overflow);
+        const int u2 = act ? Rh.opp_flags >> 1 : 0;
         const bool ok2 = act && (M.vflag[u2] & VF_PSEUDO) && D + Rh.Lp < C.cut_acc;
-        root_update(L, C, ok2, u2, D + Rh.Lp, vtx, vty, st.overflow);
+        root_update(L.R, C.rc, ok2, u2, D + Rh.Lp, vtx, vty, D2 + Rh.Lp, st.overflow);
         S.push(want, nw, st.overflow);
     }
 }
@@ -611,6 +384,7 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
     C.tie_rel = fp32 ? a.gp.tie_rel32 : a.gp.tie_rel;
     C.tie_dir = fp32 ? a.gp.tie_dir32 : a.gp.tie_dir;
     C.root_keep = fp32 ? 1.0 - a.gp.root_rel32 : 1.0;
+    C.rc = {C.root_keep, C.tie_dir, C.tie_rel};
     C.nc = nc;
     const HeRec *__restrict__ he = sd.m.he;
     Stack<R> S;
@@ -624,10 +398,10 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
 
     // ---- LDS tables
     for (int e = lane; e < kHash; e += kWave) L.head[e] = -1;
-    for (int e = lane; e < kRootCap; e += kWave) L.rkey[e] = -1;
+    for (int e = lane; e < kRootCap; e += kWave) L.R.rkey[e] = -1;
     if (lane == 0) {
-        L.rcount = 0;
-        L.dirty = 0;
+        L.R.rcount = 0;
+        L.R.dirty = 0;
     }
     __syncthreads();
     for (int s = lane; s < nc; s += kWave) {
@@ -671,7 +445,7 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
                     ty = dy / d;
                 }
             }
-            target_update(L, C, ok, slot, d, tx, ty);
+            target_update(L, C, ok, slot, d, tx, ty, INFINITY);
             if (ok) slot = next_in_face(L, slot, fs);
         }
     }
@@ -717,7 +491,7 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
                 }
             }
         }
-        root_update(L, C, rok, rv, rd, rtx, rty, overflow);
+        root_update(L.R, C.rc, rok, rv, rd, rtx, rty, INFINITY, overflow);
         // on-edge sources: targets and third vertex of the face across
         for (int k = 0; k < 3; ++k) {
             bool on = sb[(k + 2) % 3] <= 0.0 && he[3 * fs + k].twin >= 0;
@@ -745,13 +519,14 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
                         ty = s * dx + c * dy;
                     }
                 }
-                target_update(L, C, ok, slot, d, tx, ty);
+                target_update(L, C, ok, slot, d, tx, ty, INFINITY);
                 if (ok) slot = next_in_face(L, slot, g);
             }
-            bool ok = lane == 0 && (Rt.flags & 1);
+            bool ok = lane == 0 && (Rt.opp_flags & 1);
             double dx = Rt.cx - ptx, dy = Rt.cy;
             double d = sqrt(dx * dx + dy * dy);
-            root_update(L, C, ok && d < C.cut_acc, Rt.opp, d, (c * dx - s * dy) / d, (s * dx + c * dy) / d, overflow);
+            root_update(L.R, C.rc, ok && d < C.cut_acc, Rt.opp_flags >> 1, d, (c * dx - s * dy) / d,
+                        (s * dx + c * dy) / d, INFINITY, overflow);
         }
         S.push(want, w, overflow);
         S.push(wantA, wa, overflow);
@@ -771,14 +546,14 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
         bool busy = S.refill(have, w);
         // bend-vertex launches: eagerly whenever the table is dirty, else
         // once nothing is left to propagate
-        if (L.dirty && (eager || !busy)) {
+        if (L.R.dirty && (eager || !busy)) {
             const long long t0 = clock64();
             launch_roots(a, sd, L, C, S, st);
             t_launch += clock64() - t0;
             if (!busy) busy = S.refill(have, w);
         }
         if (!busy) {
-            if (!L.dirty) break;
+            if (!L.R.dirty) break;
             continue;
         }
         nwin += (unsigned long long)__popcll(__ballot(have));
@@ -790,10 +565,10 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
         // ---- process the lane's window
         Win<R> cl, cr;
         bool hl = false, hr = false;
-        // stale: the root's distance improved (beyond the re-launch tolerance)
-        // after this window was made; compared in the working precision the
-        // window was stored in
-        if (have && w.root >= 0 && w.sg > (R)(L.rD[w.root] / C.root_keep)) {
+        // stale: the window comes from an earlier launch of its root, or the
+        // root has improved enough to be launched again (the same test as the
+        // launch itself, so a root is never left without live windows)
+        if (have && w.root >= 0 && is_stale(L.R, w, C.rc)) {
             have = false;
             ++st.stale;
         }
@@ -814,7 +589,7 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
             int slot = have ? first_in_face(L, f) : -1;
             while (__ballot(slot >= 0)) {
                 bool ok = false;
-                double d = 0, tx = 0, ty = 0;
+                double d = 0, tx = 0, ty = 0, alt = INFINITY;
                 if (slot >= 0) {
                     const R qx = (R)L.tb[slot][(k + 1) % 3] * H.L + (R)L.tb[slot][(k + 2) % 3] * H.cx;
                     const R qy = (R)L.tb[slot][(k + 2) % 3] * H.cy;
@@ -831,19 +606,20 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
                             tx = (double)(w.c * dx - w.s * dy);
                             ty = (double)(w.s * dx + w.c * dy);
                         } else {
-                            tx = L.rtx[w.root];
-                            ty = L.rty[w.root];
+                            tx = L.R.rtx[w.root];
+                            ty = L.R.rty[w.root];
+                            alt = L.R.rD2[w.root] + (double)l;
                         }
                     }
                 }
-                target_update(L, C, ok, slot, d, tx, ty);
+                target_update(L, C, ok, slot, d, tx, ty, alt);
                 if (slot >= 0) slot = next_in_face(L, slot, f);
             }
         }
         // third vertex as a bend vertex
         {
             bool ok = false;
-            double d = 0, tx = 0, ty = 0;
+            double d = 0, tx = 0, ty = 0, alt = INFINITY;
             if (have && H.pseudo) {
                 const double sl = C.tol * (double)H.L;
                 if (txc >= (double)w.b0 - sl && txc <= (double)w.b1 + sl) {
@@ -857,12 +633,13 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
                         tx = (double)(w.c * dx - w.s * dy);
                         ty = (double)(w.s * dx + w.c * dy);
                     } else {
-                        tx = L.rtx[w.root];
-                        ty = L.rty[w.root];
+                        tx = L.R.rtx[w.root];
+                        ty = L.R.rty[w.root];
+                        alt = L.R.rD2[w.root] + (double)l;
                     }
                 }
             }
-            root_update(L, C, ok, have ? H.opp : 0, d, tx, ty, overflow);
+            root_update(L.R, C.rc, ok, have ? H.opp : 0, d, tx, ty, alt, overflow);
         }
         if (have) children(H, w, txc, false, C, F3, U3, L, cl, hl, cr, hr, pruned);
         // keep one child in the lane, push the other

@@ -269,6 +269,109 @@ __global__ void k_integrate(int n, DevMesh m, const int32_t *__restrict__ face, 
     D[3 * i + 1] = d[1];
     D[3 * i + 2] = d[2];
 }
+// ------------------------------------------------------------ all-pairs
+__global__ void k_face_count(int n, const int32_t *__restrict__ face, int32_t *__restrict__ counts) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicAdd(&counts[face[i]], 1);
+}
+__global__ void k_face_scatter(int n, const int32_t *__restrict__ face, const int32_t *__restrict__ fstart,
+                               int32_t *__restrict__ counts, int32_t *__restrict__ forder) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        const int f = face[i];
+        forder[fstart[f] + atomicAdd(&counts[f], 1)] = i;
+    }
+}
+__global__ void k_identity_rows(int n, int cap, int32_t *__restrict__ cand_cnt, int32_t *__restrict__ cand) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n * cap) return;
+    const int i = (int)(t / cap), j = (int)(t % cap);
+    cand[t] = j;
+    if (j == 0) cand_cnt[i] = n;
+}
+
+// ------------------------------------------------------------ FIRE
+// Force of every particle of the FIRE surfaces of a batch (kept for the
+// update) and, per block of 256 particles of one surface, the partial sums
+// of the power F.v and of |v|^2 and |F|^2 (fixed-order tree reduction).
+__global__ __launch_bounds__(kFireBlock) void k_fire_partials(const SurfDesc *__restrict__ desc, BatchIdx blk,
+                                                              double *__restrict__ partials,
+                                                              unsigned long long *__restrict__ npairs) {
+    __shared__ double sh[3][kFireBlock];
+    const int b = blockIdx.x, t = threadIdx.x;
+    const int si = batch_surface(blk, b);
+    const SurfDesc &sd = desc[si];
+    const int i = (b - blk.begin[si]) * kFireBlock + t;
+    double p = 0.0, vv = 0.0, ff = 0.0;
+    if (sd.ikind == 2 && i < sd.n) {
+        double F[3], E;
+        int np;
+        row_force(i, sd.cand_cnt, sd.cap, sd.cdist, sd.ctan, sd.cutoff, sd.pkind, sd.pk, sd.psigma, F, E, np);
+        if (np) atomicAdd(npairs, (unsigned long long)np);
+        const double *v = sd.vel + 3 * (int64_t)i;
+        for (int d = 0; d < 3; ++d) {
+            sd.F[3 * (int64_t)i + d] = F[d];
+            p += F[d] * v[d];
+            vv += v[d] * v[d];
+            ff += F[d] * F[d];
+        }
+    }
+    sh[0][t] = p;
+    sh[1][t] = vv;
+    sh[2][t] = ff;
+    __syncthreads();
+    for (int o = kFireBlock / 2; o > 0; o >>= 1) {
+        if (t < o)
+            for (int q = 0; q < 3; ++q) sh[q][t] += sh[q][t + o];
+        __syncthreads();
+    }
+    if (t < 3) partials[3 * (int64_t)b + t] = sh[t][0];
+}
+
+// The FIRE control step of every FIRE surface (Bitzek et al., PRL 97,
+// 170201 (2006)): with the power P = sum F.v of the current iteration,
+// P > 0 mixes the velocities towards the force direction (v <- (1 - alpha) v
+// + alpha |v| F/|F|) and, after more than n_min such iterations in a row,
+// grows dt (up to dt_max) and shrinks alpha; P <= 0 stops the particles, cuts
+// dt and resets alpha. The update kernel then applies v <- cv v + cf F,
+// v += dt F, and walks dt v.
+__global__ void k_fire_control(const SurfDesc *__restrict__ desc, BatchIdx blk, const double *__restrict__ partials) {
+    const int si = blockIdx.x * blockDim.x + threadIdx.x;
+    if (si >= blk.nsurf) return;
+    const SurfDesc &sd = desc[si];
+    if (sd.ikind != 2) return;
+    double P = 0.0, vv = 0.0, ff = 0.0;
+    for (int b = blk.begin[si]; b < blk.begin[si + 1]; ++b) {
+        P += partials[3 * (int64_t)b];
+        vv += partials[3 * (int64_t)b + 1];
+        ff += partials[3 * (int64_t)b + 2];
+    }
+    FireState st = *sd.fire;
+    if (!st.init) {
+        st.dt = sd.dt;
+        st.alpha = sd.alpha0;
+        st.n_pos = 0;
+        st.init = 1;
+    }
+    if (P > 0.0) {
+        st.cv = 1.0 - st.alpha;
+        st.cf = ff > 0.0 ? st.alpha * sqrt(vv) / sqrt(ff) : 0.0;
+        if (!(ff > 0.0)) st.cv = 1.0;
+        st.n_pos += 1;
+        if (st.n_pos > sd.n_min) {
+            st.dt = fmin(st.dt * sd.f_inc, sd.dt_max);
+            st.alpha *= sd.f_alpha;
+        }
+    } else {
+        st.cv = 0.0;
+        st.cf = 0.0;
+        st.dt *= sd.f_dec;
+        st.alpha = sd.alpha0;
+        st.n_pos = 0;
+    }
+    *sd.fire = st;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------ launchers
@@ -357,4 +460,30 @@ hipError_t launch_integrate(const DevMesh &m, int n, const int32_t *face, const 
     return hipGetLastError();
 }
 
+}  // namespace gsim
+
+namespace gsim {
+hipError_t launch_face_sort(const SurfDesc &d, int32_t *counts, int64_t *tmp64, int64_t *scan_scratch, hipStream_t s) {
+    const int n = d.n, nf = d.m.nf;
+    hipError_t e;
+    if ((e = launch_zero_i32(counts, nf, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_face_count, dim3(nblocks(n)), dim3(kBlock), 0, s, n, d.face, counts);
+    if ((e = launch_scan_i32_to_i64(counts, tmp64, nf, scan_scratch, s)) != hipSuccess) return e;
+    if ((e = launch_i64_to_i32(tmp64, d.fstart, nf, s)) != hipSuccess) return e;
+    if ((e = launch_zero_i32(counts, nf, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_face_scatter, dim3(nblocks(n)), dim3(kBlock), 0, s, n, d.face, d.fstart, counts, d.forder);
+    return hipGetLastError();
+}
+hipError_t launch_identity_rows(int n, int cap, int32_t *cand_cnt, int32_t *cand, hipStream_t s) {
+    hipLaunchKernelGGL(k_identity_rows, dim3(nblocks((int64_t)n * cap)), dim3(kBlock), 0, s, n, cap, cand_cnt, cand);
+    return hipGetLastError();
+}
+hipError_t launch_fire_control(const SurfDesc *desc, const BatchIdx &blk, double *partials, Counters *ctr,
+                               hipStream_t s) {
+    const int nb = blk.begin[blk.nsurf];
+    if (nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fire_partials, dim3(nb), dim3(kFireBlock), 0, s, desc, blk, partials, &ctr->nbr_pairs);
+    hipLaunchKernelGGL(k_fire_control, dim3(1), dim3(kMaxBatch), 0, s, desc, blk, partials);
+    return hipGetLastError();
+}
 }  // namespace gsim

@@ -236,13 +236,29 @@ __global__ __launch_bounds__(256) void k_update_batch(const SurfDesc *__restrict
     const SurfDesc &sd = desc[si];
     const int i = g - bi.begin[si];
     int f = sd.face[i];
-    double F[3], E;
-    int np;
-    row_force(i, sd.cand_cnt, kCandCap, sd.cdist, sd.ctan, sd.cutoff, sd.pkind, sd.pk, sd.psigma, F, E, np);
     double D[3];
-    displacement(sd.m, f, i, F, sd.ikind, sd.dt, sd.mobility, sd.kT, sd.friction, sd.seed, *sd.step, D);
-    double b[3] = {sd.bary[3 * i], sd.bary[3 * i + 1], sd.bary[3 * i + 2]};
+    int np = 0;
     d3 v = ld3(sd.vel + 3 * (int64_t)i);
+    if (sd.ikind == 2) {
+        // FIRE: forces and the control step come from the FIRE kernels;
+        // mix, semi-implicit Euler, displacement dt v capped at max_disp
+        const FireState st = *sd.fire;
+        const d3 F = ld3(sd.F + 3 * (int64_t)i);
+        v = st.cv * v + st.cf * F;
+        v = v + st.dt * F;
+        d3 Dv = st.dt * v;
+        const double L = sqrt(dot(Dv, Dv));
+        if (L > sd.max_disp) Dv = (sd.max_disp / L) * Dv;
+        D[0] = Dv.x;
+        D[1] = Dv.y;
+        D[2] = Dv.z;
+        np = 0;
+    } else {
+        double F[3], E;
+        row_force(i, sd.cand_cnt, sd.cap, sd.cdist, sd.ctan, sd.cutoff, sd.pkind, sd.pk, sd.psigma, F, E, np);
+        displacement(sd.m, f, i, F, sd.ikind, sd.dt, sd.mobility, sd.kT, sd.friction, sd.seed, *sd.step, D);
+    }
+    double b[3] = {sd.bary[3 * i], sd.bary[3 * i + 1], sd.bary[3 * i + 2]};
     WalkCounts wc = {0, 0, 0, 0, 0};
     uint8_t fl = 0;
     walk_one(sd.m, f, b, d3{D[0], D[1], D[2]}, v, true, wc, fl);

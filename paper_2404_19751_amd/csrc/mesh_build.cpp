@@ -169,10 +169,10 @@ std::string build_host_mesh(int nv, const double *xyz, int nf, const int32_t *tr
         r.uy = -cy / r.Ln;
         r.tn = M.twin[nxt(h)];
         r.tp = M.twin[prv(h)];
-        r.opp = c;
-        r.flags = (M.vflag[c] & VF_PSEUDO) ? 1 : 0;
+        r.opp_flags = (c << 1) | ((M.vflag[c] & VF_PSEUDO) ? 1 : 0);
         r.twin = M.twin[h];
-        r.pad = 0;
+        r.tail = M.T[h];
+        r.head = M.T[nxt(h)];
         M.he[h] = r;
         HeRecF q;
         q.L = float(L);
@@ -186,7 +186,7 @@ std::string build_host_mesh(int nv, const double *xyz, int nf, const int32_t *tr
         q.uy = -q.cy / q.Ln;
         q.tn = r.tn;
         q.tp = r.tp;
-        q.opp_flags = (c << 1) | r.flags;
+        q.opp_flags = r.opp_flags;
         M.hef[h] = q;
     }
     for (int d = 0; d < 3; ++d) {

@@ -1,0 +1,311 @@
+// Window records and helpers shared by the geodesic kernels (cutoff and
+// all-pairs): the window itself, its stack records, the per-half-edge
+// unfolding record in the working precision, the bend-vertex table, the
+// two-level window stack, and the child intervals on the two far edges of
+// a face (arXiv 2404.19751, Sec. 2.2 MMP paragraph: rays from a pseudo-source
+// image through an interval of an edge, continued across faces).
+#pragma once
+#include <cmath>
+
+#include "gsim_internal.h"
+
+namespace gsim {
+namespace wnd {
+
+constexpr int kWave = 64;
+// bend-vertex table: 255 slots so that slot + 1 fits the 8 bits the FP32
+// stack record keeps for it
+constexpr int kRootCap = 255;
+
+template <typename R>
+struct Win {
+    R px, py, b0, b1, sg, c, s;
+    int he, root;
+};
+
+// stack records: 64 bytes (FP64) / 32 bytes (FP32, he and root packed)
+struct Rec64 {
+    double v[7];
+    int32_t he, root;
+};
+struct Rec32 {
+    float v[7];
+    uint32_t hr;  // (he << 8) | (root + 1), root + 1 in [0, kRootCap]
+};
+static_assert(sizeof(Rec64) == 64 && sizeof(Rec32) == 32, "stack record sizes");
+template <typename R>
+struct RecOf;
+template <>
+struct RecOf<double> {
+    using T = Rec64;
+};
+template <>
+struct RecOf<float> {
+    using T = Rec32;
+};
+
+__device__ inline void store_rec(Rec64 &q, const Win<double> &w) {
+    q.v[0] = w.px; q.v[1] = w.py; q.v[2] = w.b0; q.v[3] = w.b1; q.v[4] = w.sg; q.v[5] = w.c; q.v[6] = w.s;
+    q.he = w.he;
+    q.root = w.root;
+}
+__device__ inline void load_rec(const Rec64 &q, Win<double> &w) {
+    w.px = q.v[0]; w.py = q.v[1]; w.b0 = q.v[2]; w.b1 = q.v[3]; w.sg = q.v[4]; w.c = q.v[5]; w.s = q.v[6];
+    w.he = q.he;
+    w.root = q.root;
+}
+__device__ inline void store_rec(Rec32 &q, const Win<float> &w) {
+    q.v[0] = w.px; q.v[1] = w.py; q.v[2] = w.b0; q.v[3] = w.b1; q.v[4] = w.sg; q.v[5] = w.c; q.v[6] = w.s;
+    q.hr = ((uint32_t)w.he << 8) | (uint32_t)(w.root + 1);
+}
+__device__ inline void load_rec(const Rec32 &q, Win<float> &w) {
+    w.px = q.v[0]; w.py = q.v[1]; w.b0 = q.v[2]; w.b1 = q.v[3]; w.sg = q.v[4]; w.c = q.v[5]; w.s = q.v[6];
+    w.he = (int)(q.hr >> 8);
+    w.root = (int)(q.hr & 255u) - 1;
+}
+
+// half-edge record in the working precision
+template <typename R>
+struct He {
+    R L, cx, cy, Lp, Ln, ex, ey, ux, uy;
+    int tn, tp, opp;
+    bool pseudo;
+};
+__device__ inline He<double> load_he(const DevMesh &m, int h, double) {
+    const HeRec r = m.he[h];
+    return {r.L, r.cx, r.cy, r.Lp, r.Ln, r.ex, r.ey, r.ux, r.uy, r.tn, r.tp, r.opp_flags >> 1, (r.opp_flags & 1) != 0};
+}
+__device__ inline He<float> load_he(const DevMesh &m, int h, float) {
+    const HeRecF r = m.hef[h];
+    return {r.L, r.cx, r.cy, r.Lp, r.Ln, r.ex, r.ey, r.ux, r.uy, r.tn, r.tp, r.opp_flags >> 1,
+            (r.opp_flags & 1) != 0};
+}
+
+// Bend-vertex (pseudo-source) table of one source, in LDS: open addressing
+// on the vertex id; rD the best distance so far, rL the distance of the
+// last launch, (rtx, rty) the initial tangent of the best path, rD2 the
+// best distance of a path leaving the source in another direction (the
+// vertex's own tie gap, passed on to everything reached through it).
+struct Roots {
+    int32_t rkey[kRootCap + 1];
+    double rD[kRootCap], rL[kRootCap], rtx[kRootCap], rty[kRootCap], rD2[kRootCap];
+    int32_t rcount, dirty;
+    int32_t sel[kRootCap + 1];   // launch list: root slots
+    int32_t pref[kRootCap + 2];  // prefix sums of their fan sizes
+};
+
+__device__ inline int lane_id() { return threadIdx.x; }
+__device__ inline uint64_t lanemask_lt() { return (1ull << threadIdx.x) - 1ull; }
+__device__ inline int hash_vert(int v) { return (int)((((uint32_t)v * 2246822519u) >> 16) % kRootCap); }
+
+__device__ inline double wave_min(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+    return v;
+}
+
+template <typename R>
+__device__ inline R seg_dist(R px, R py, R b0, R b1) {
+    R dx = px < b0 ? b0 - px : (px > b1 ? px - b1 : R(0));
+    return sqrt(dx * dx + py * py);
+}
+
+// Parameters of the bend-vertex updates: 1 - re-launch tolerance, the
+// angle under which two initial directions count as one, the tie band.
+struct RootCfg {
+    double keep, tie_dir, tie_rel;
+};
+
+// Serialised bend-vertex update (insert or improve): keeps the smallest
+// distance and its tangent, and the smallest distance of a path in another
+// initial direction (directions closer than tie_dir count as one); `alt` is
+// such a second distance that comes with the candidate (a path through
+// another bend vertex carries that vertex's own second distance). Marks the
+// vertex for a (re-)launch when its distance improved by more than the
+// re-launch tolerance, when the direction of its best path changed, or
+// when a path of another direction has just come within the tie band:
+// everything already reached through the vertex then learns the new
+// tangent or the tie.
+__device__ inline void root_update(Roots &L, const RootCfg &rc, bool ok, int v, double d, double tx, double ty,
+                                   double alt, bool &overflow) {
+    uint64_t m = __ballot(ok);
+    while (m) {
+        int l = __ffsll((unsigned long long)m) - 1;
+        if (lane_id() == l) {
+            int e = hash_vert(v), probes = 0;
+            while (L.rkey[e] >= 0 && L.rkey[e] != v && probes < kRootCap) {
+                e = e + 1 == kRootCap ? 0 : e + 1;
+                ++probes;
+            }
+            if (probes >= kRootCap || (L.rkey[e] < 0 && L.rcount >= kRootCap - 1)) {
+                overflow = true;
+            } else if (L.rkey[e] < 0) {
+                L.rkey[e] = v;
+                L.rD[e] = d;
+                L.rL[e] = INFINITY;
+                L.rtx[e] = tx;
+                L.rty[e] = ty;
+                L.rD2[e] = alt;
+                L.rcount++;
+                L.dirty = 1;
+            } else {
+                const double ax = L.rtx[e], ay = L.rty[e];
+                const bool differ = fabs(ax * ty - ay * tx) > rc.tie_dir || ax * tx + ay * ty < 0.0;
+                const bool tied = L.rD2[e] - L.rD[e] <= rc.tie_rel * L.rD[e];
+                if (d < L.rD[e]) {
+                    if (differ) {
+                        L.rD2[e] = fmin(L.rD2[e], L.rD[e]);
+                        L.rL[e] = INFINITY;  // new direction: launch again however small the gain
+                    }
+                    L.rD[e] = d;
+                    L.rtx[e] = tx;
+                    L.rty[e] = ty;
+                } else if (differ) {
+                    L.rD2[e] = fmin(L.rD2[e], d);
+                }
+                L.rD2[e] = fmin(L.rD2[e], alt);
+                if (!tied && L.rD2[e] - L.rD[e] <= rc.tie_rel * L.rD[e]) L.rL[e] = INFINITY;  // a new tie
+                if (L.rD[e] < L.rL[e] * rc.keep) L.dirty = 1;
+            }
+        }
+        m &= m - 1;
+    }
+}
+
+// A window of bend vertex w.root is stale when it comes from an earlier
+// launch (its sg, rounded like every window of a launch, exceeds that of the
+// last launch rL) or when the vertex has improved enough for a new launch.
+template <typename R>
+__device__ inline bool is_stale(const Roots &L, const Win<R> &w, const RootCfg &rc) {
+    return w.sg > (R)L.rL[w.root] || L.rD[w.root] < L.rL[w.root] * rc.keep;
+}
+
+// Two-level window stack: LDS first, a per-wave global area for overflow.
+template <typename R>
+struct Stack {
+    using Rec = typename RecOf<R>::T;
+    int kL;  // LDS records
+    Rec *lds;
+    Rec *glb;
+    int gcap;
+    int lsp, gsp;
+
+    __device__ void push(bool want, const Win<R> &w, bool &overflow) {
+        uint64_t m = __ballot(want);
+        int cnt = __popcll(m);
+        if (!cnt) return;
+        int r = __popcll(m & lanemask_lt());
+        int space = kL - lsp;
+        if (want) {
+            if (r < space) {
+                store_rec(lds[lsp + r], w);
+            } else {
+                int pos = gsp + (r - space);
+                if (pos < gcap) store_rec(glb[pos], w);
+                else overflow = true;
+            }
+        }
+        int to_l = min(cnt, space);
+        lsp += to_l;
+        gsp = min(gsp + (cnt - to_l), gcap);
+    }
+    // refill lanes without a window; returns whether any lane holds one
+    __device__ bool refill(bool &have, Win<R> &w) {
+        uint64_t need = __ballot(!have);
+        int nneed = __popcll(need);
+        int r = __popcll(need & lanemask_lt());
+        int take_l = min(nneed, lsp);
+        if (!have && r < take_l) {
+            load_rec(lds[lsp - 1 - r], w);
+            have = true;
+        }
+        lsp -= take_l;
+        if (nneed > take_l && gsp > 0) {
+            __syncthreads();  // make earlier global pushes of other lanes visible
+            int take_g = min(nneed - take_l, gsp);
+            if (!have && r >= take_l && r < take_l + take_g) {
+                load_rec(glb[gsp - 1 - (r - take_l)], w);
+                have = true;
+            }
+            gsp -= take_g;
+        }
+        return __ballot(have) != 0;
+    }
+};
+
+// Child intervals. Left child: across C->A (stored on tp, frame origin A,
+// x towards C). Right child: across B->C (stored on tn, frame origin C, x
+// towards B). The endpoint intersections are evaluated in FP64 in both
+// precisions.
+template <typename R>
+__device__ inline void child_left(const He<R> &h, const Win<R> &w, double txc, bool full, double &x0, double &x1) {
+    if (full) {
+        x0 = 0.0;
+        x1 = (double)h.Lp;
+        return;
+    }
+    const double px = w.px, py = w.py, b0 = w.b0, b1 = w.b1, cx = h.cx, cy = h.cy, Lp = h.Lp;
+    x0 = b0 <= 0.0 ? 0.0 : Lp * (py * b0) / (py * cx + cy * (b0 - px));
+    x1 = b1 >= txc ? Lp : Lp * (py * b1) / (py * cx + cy * (b1 - px));
+    x0 = fmin(fmax(x0, 0.0), Lp);
+    x1 = fmin(fmax(x1, 0.0), Lp);
+}
+template <typename R>
+__device__ inline void child_right(const He<R> &h, const Win<R> &w, double txc, bool full, double &x0, double &x1) {
+    if (full) {
+        x0 = 0.0;
+        x1 = (double)h.Ln;
+        return;
+    }
+    const double px = w.px, py = w.py, b0 = w.b0, b1 = w.b1, cx = h.cx, cy = h.cy, L = h.L, Ln = h.Ln;
+    x0 = b0 <= txc ? 0.0 : Ln * ((px - cx) * (-py) - (py - cy) * (b0 - px)) / ((L - cx) * (-py) + cy * (b0 - px));
+    x1 = b1 >= L ? Ln : Ln * ((px - cx) * (-py) - (py - cy) * (b1 - px)) / ((L - cx) * (-py) + cy * (b1 - px));
+    x0 = fmin(fmax(x0, 0.0), Ln);
+    x1 = fmin(fmax(x1, 0.0), Ln);
+}
+
+// Frame changes into the child windows (the interval [x0, x1] already
+// computed): left child on twin(prev(h)) with origin A, right child on
+// twin(next(h)) with origin C.
+template <typename R>
+__device__ inline void make_left(const He<R> &h, const Win<R> &w, double x0, double x1, Win<R> &cl) {
+    const R ex = h.ex, ey = h.ey;
+    cl.px = ex * w.px + ey * w.py;
+    cl.py = ex * w.py - ey * w.px;
+    cl.b0 = (R)x0;
+    cl.b1 = (R)x1;
+    cl.sg = w.sg;
+    cl.c = w.c * ex - w.s * ey;
+    cl.s = w.s * ex + w.c * ey;
+    cl.he = h.tp;
+    cl.root = w.root;
+}
+template <typename R>
+__device__ inline void make_right(const He<R> &h, const Win<R> &w, double x0, double x1, Win<R> &cr) {
+    const R ux = h.ux, uy = h.uy;
+    const R qx = w.px - h.cx, qy = w.py - h.cy;
+    cr.px = ux * qx + uy * qy;
+    cr.py = ux * qy - uy * qx;
+    cr.b0 = (R)x0;
+    cr.b1 = (R)x1;
+    cr.sg = w.sg;
+    cr.c = w.c * ux - w.s * uy;
+    cr.s = w.s * ux + w.c * uy;
+    cr.he = h.tn;
+    cr.root = w.root;
+}
+
+__device__ inline void face_xyz(const DevMesh &m, int f, int k, double F3[3][3], double U3[3][3]) {
+    const double *p = m.fpos + 18 * (int64_t)f;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const int q = (k + i) % 3;
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+            F3[i][d] = p[3 * q + d];
+            U3[i][d] = p[9 + 3 * q + d];
+        }
+    }
+}
+
+}  // namespace wnd
+}  // namespace gsim

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "_libgsim.so")
 OK, E_ARG, E_MESH, E_OOM, E_CAPACITY, E_DEVICE, E_STATE, E_LIMIT = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, FP32_MIXED = 0, 1
 POT = {"harmonic": 0, "coulomb": 1, "gaussian": 2}
-INTEG = {"overdamped": 0, "brownian": 1}
+INTEG = {"overdamped": 0, "brownian": 1, "fire": 2}
 PAIR_TIE, PAIR_ZERO, PAIR_GUARD = 1, 2, 4
 
 EXPORTS = ["gsim_create", "gsim_destroy", "gsim_last_error", "gsim_synchronize", "gsim_mesh_upload",
@@ -52,7 +52,9 @@ class PotentialT(C.Structure):
 
 class IntegratorT(C.Structure):
     _fields_ = [("kind", C.c_int32), ("dt", C.c_double), ("mobility", C.c_double), ("kT", C.c_double),
-                ("friction", C.c_double), ("seed", C.c_uint64)]
+                ("friction", C.c_double), ("seed", C.c_uint64), ("max_disp", C.c_double), ("dt_max", C.c_double),
+                ("alpha0", C.c_double), ("f_alpha", C.c_double), ("f_inc", C.c_double), ("f_dec", C.c_double),
+                ("n_min", C.c_int32)]
 
 
 class WalkStatsT(C.Structure):
@@ -118,8 +120,12 @@ def potential(kind="harmonic", k=1.0, sigma=1.0, cutoff=None) -> PotentialT:
     return PotentialT(POT[kind], float(k), float(sigma), float(cutoff))
 
 
-def integrator(kind="overdamped", dt=0.01, mobility=1.0, kT=0.0, friction=1.0, seed=0) -> IntegratorT:
-    return IntegratorT(INTEG[kind], float(dt), float(mobility), float(kT), float(friction), int(seed))
+def integrator(kind="overdamped", dt=0.01, mobility=1.0, kT=0.0, friction=1.0, seed=0, max_disp=0.0, dt_max=0.0,
+               alpha0=0.0, f_alpha=0.0, f_inc=0.0, f_dec=0.0, n_min=0) -> IntegratorT:
+    """Integrator parameters; for "fire", dt is the initial step and zero
+    FIRE fields select the library defaults."""
+    return IntegratorT(INTEG[kind], float(dt), float(mobility), float(kT), float(friction), int(seed), float(max_disp),
+                       float(dt_max), float(alpha0), float(f_alpha), float(f_inc), float(f_dec), int(n_min))
 
 
 class Context:
@@ -277,8 +283,8 @@ class Context:
         return out
 
     def counters(self) -> dict:
-        c = np.zeros(10, np.int64)
+        c = np.zeros(11, np.int64)
         self._chk(self.L.gsim_counters_get(self.h, _ptr(c)))
         return dict(windows=int(c[0]), pruned=int(c[1]), launches=int(c[2]), stale=int(c[3]), cand_pairs=int(c[4]),
                     nbr_pairs=int(c[5]), limited=int(c[6]), cum_pairs=int(c[7]), cum_windows=int(c[8]),
-                    cum_passes=int(c[9]))
+                    cum_passes=int(c[9]), max_stack_depth=int(c[10]))
