@@ -157,6 +157,8 @@ __device__ inline void vdist_min(double *Dv, int v, double d) {
 // distance of another-direction path that comes with the candidate.
 __device__ inline void target_update(AllLds &L, double *d1, double *d2, double *t1x, double *t1y, const ACtx &C,
                                      bool ok, int j, double d, double tx, double ty, double alt) {
+    // candidates no shorter than both distances (which only decrease) change nothing
+    if (ok && d >= d1[j] && d >= d2[j] && alt >= d2[j]) ok = false;
     uint64_t m = __ballot(ok);
     while (m) {
         const int l = __ffsll((unsigned long long)m) - 1;

@@ -128,6 +128,8 @@ __device__ inline bool reaches_target(const Lds &L, const Ctx &C, const double P
 // a bend vertex with a second distance).
 __device__ inline void target_update(Lds &L, const Ctx &C, bool ok, int slot, double d, double tx, double ty,
                                      double alt) {
+    // candidates no shorter than both distances (which only decrease) change nothing
+    if (ok && d >= L.d1[slot] && d >= L.d2[slot] && alt >= L.d2[slot]) ok = false;
     uint64_t m = __ballot(ok);
     while (m) {
         int l = __ffsll((unsigned long long)m) - 1;

@@ -127,14 +127,34 @@ struct RootCfg {
 // tangent or the tie.
 __device__ inline void root_update(Roots &L, const RootCfg &rc, bool ok, int v, double d, double tx, double ty,
                                    double alt, bool &overflow) {
+    // parallel look-up first: a lane whose vertex is in the table and whose
+    // candidate is no shorter than its best and second distances (which only
+    // decrease) can change nothing and leaves before the serialised part
+    int found = -1;
+    if (ok) {
+        int e = hash_vert(v), probes = 0;
+        while (L.rkey[e] >= 0 && L.rkey[e] != v && probes < kRootCap) {
+            e = e + 1 == kRootCap ? 0 : e + 1;
+            ++probes;
+        }
+        if (probes < kRootCap && L.rkey[e] == v) {
+            found = e;
+            if (d >= L.rD[e] && d >= L.rD2[e] && alt >= L.rD2[e]) ok = false;
+        }
+    }
     uint64_t m = __ballot(ok);
     while (m) {
         int l = __ffsll((unsigned long long)m) - 1;
         if (lane_id() == l) {
-            int e = hash_vert(v), probes = 0;
-            while (L.rkey[e] >= 0 && L.rkey[e] != v && probes < kRootCap) {
-                e = e + 1 == kRootCap ? 0 : e + 1;
-                ++probes;
+            int e = found, probes = 0;
+            if (e < 0) {
+                // not in the table at look-up time: probe again (an earlier
+                // lane of this batch may have inserted it)
+                e = hash_vert(v);
+                while (L.rkey[e] >= 0 && L.rkey[e] != v && probes < kRootCap) {
+                    e = e + 1 == kRootCap ? 0 : e + 1;
+                    ++probes;
+                }
             }
             if (probes >= kRootCap || (L.rkey[e] < 0 && L.rcount >= kRootCap - 1)) {
                 overflow = true;
