@@ -52,8 +52,8 @@ def measured_traffic():
     import hashlib
     try:
         rec = json.load(open(PMC_FILE))
-        src = open(os.path.join(ROOT, "paper_2404_19751_amd", "csrc", "k_geodesic.hip"), "rb").read()
-    except OSError:
+        src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in rec["sources_hashed"])
+    except (OSError, KeyError):
         return None
     if hashlib.sha256(src).hexdigest() != rec.get("kernel_source_sha256"):
         return None
