@@ -84,8 +84,10 @@ def _gsim_args(gsim, w):
     pot = gsim.potential(p["kind"], p["k"], p["sigma"], p["cutoff"])
     if wi["kind"] == "brownian":
         ig = gsim.integrator("brownian", wi["dt"], 1.0, wi["kT"], wi["friction"], wi["seed"])
-    else:
+    elif wi["kind"] == "overdamped":
         ig = gsim.integrator("overdamped", wi["dt"], wi["mobility"])
+    else:
+        ig = gsim.integrator(wi["kind"], wi["dt"])
     return pot, ig
 
 
@@ -180,15 +182,53 @@ def bench_c3(args, gsim, W):
     }
 
 
+def bench_torus_nve(args, gsim, W):
+    """Cost per velocity-Verlet (NVE) step against N on the aspect-3 benchmark
+    torus (4648 faces) for interaction ranges sigma = 1/4 and 1/8, the setting
+    of the paper's Fig. 3 scaling study; steps replayed from HIP graphs. The
+    exponent is the least-squares slope of log(ms/step) against log N."""
+    out = {}
+    for sig in (0.25, 0.125):
+        rows = []
+        for n in (512, 1024, 2048, 4096, 8192, 16384, 32768):
+            w = W.workload(f"torus_nve_{n}_{sig}")
+            pot, ig = _gsim_args(gsim, w)
+            for prec in ("fp64", "fp32"):
+                ctx = gsim.Context(0, prec)
+                mid = ctx.mesh_upload(w.mesh.V, w.mesh.T)
+                ctx.particles_set(mid, w.face, w.bary)
+                ctx.tune(graph_steps=args.steps)
+                ctx.step(mid, pot, ig, args.steps)  # warm-up, captures the graph
+                ctx.synchronize()
+                c0 = ctx.counters()["cum_pairs"]
+                t0 = time.perf_counter()
+                ctx.step(mid, pot, ig, args.steps)
+                ctx.synchronize()
+                dt = time.perf_counter() - t0
+                pairs = ctx.counters()["cum_pairs"] - c0
+                ctx.close()
+                rows.append({"n": n, "precision": prec, "ms_per_step": 1e3 * dt / args.steps,
+                             "pairs_per_step": pairs / args.steps, "pairs_per_s": pairs / dt})
+        fits = {}
+        for prec in ("fp64", "fp32"):
+            xs = np.log([r["n"] for r in rows if r["precision"] == prec])
+            ys = np.log([r["ms_per_step"] for r in rows if r["precision"] == prec])
+            fits[prec] = float(np.polyfit(xs, ys, 1)[0])
+        out[f"sigma_{sig}"] = {"runs": rows, "exponent": fits}
+    return {"workload": "velocity Verlet NVE on the aspect-3 benchmark torus (R=3, r=1, 4648 faces), harmonic "
+                        "repulsion, dt=0.005, from rest, N = 512 .. 32768", "steps": args.steps, "data": "synthetic",
+            "results": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32"])
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "torus_nve"],
                     help="c2: bumpy sphere N=1000 (the default line); c3: 16 surfaces batched; "
-                         "c4: open height field N=20000, Brownian")
+                         "c4: open height field N=20000, Brownian; torus_nve: NVE cost vs N on the benchmark torus")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
@@ -214,6 +254,9 @@ def main():
 
     if args.workload == "c3":
         print(json.dumps(bench_c3(args, gsim, W)), flush=True)
+        return
+    if args.workload == "torus_nve":
+        print(json.dumps(bench_torus_nve(args, gsim, W)), flush=True)
         return
     w = W.workload(args.workload)
     pot = gsim.potential("harmonic", w.potential["k"], w.potential["sigma"], w.potential["cutoff"])

@@ -88,7 +88,12 @@ typedef struct {
     double k, sigma, cutoff;
 } gsim_potential;
 
-typedef enum { GSIM_INT_OVERDAMPED = 0, GSIM_INT_BROWNIAN = 1, GSIM_INT_FIRE = 2 } gsim_integrator_kind;
+typedef enum {
+    GSIM_INT_OVERDAMPED = 0,
+    GSIM_INT_BROWNIAN = 1,
+    GSIM_INT_FIRE = 2,
+    GSIM_INT_VERLET = 3
+} gsim_integrator_kind;
 
 /* overdamped: D = mobility dt F.
  * brownian:   friction D = dt F + sqrt(2 kT friction dt) (eta1 ex + eta2 ey),
@@ -103,7 +108,14 @@ typedef enum { GSIM_INT_OVERDAMPED = 0, GSIM_INT_BROWNIAN = 1, GSIM_INT_FIRE = 2
  *             alpha <- alpha0. Then v += dt F and each particle walks dt v
  *             (at most max_disp long), its velocity parallel-transported.
  *             dt is the initial step; the state restarts when particles are
- *             set. Zero fields select the defaults in brackets. */
+ *             set. Zero fields select the defaults in brackets.
+ * verlet:     velocity Verlet (Newton's equation, Sec. 2.1 Eq. (1); the NVE
+ *             runs of Sec. 4) in leapfrog form with unit masses: the stored
+ *             velocity is the half-step velocity v_{k-1/2}; a step kicks
+ *             v += dt F(x_k) and walks dt v, the velocity parallel-transported
+ *             (Sec. 3.2). The integer-time velocity is v_{k-1/2} + (dt/2) F(x_k).
+ *             The scheme is time-reversible: restarting from
+ *             -(v_{k-1/2} + dt F(x_k)) retraces the trajectory. */
 typedef struct {
     int32_t kind;
     double dt, mobility, kT, friction;

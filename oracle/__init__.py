@@ -320,3 +320,23 @@ def fire_step(mesh: OracleMesh, face, bary, vel, potential_cfg: dict, integ: dic
     f2, b2, v2, st, fl = walk(mesh, face, bary, D, v)
     new_state = dict(dt=dt, alpha=alpha, n_pos=n_pos)
     return f2, b2, v2, new_state, dict(pairs=pr, F=F, E=E, D=D, P=P, walk=st, walk_flags=fl)
+
+
+# --------------------------------------------------------------------------
+# Velocity Verlet (Sec. 2.1: Newton's equation, Eq. (1); the integrator of the
+# paper's NVE benchmark, Sec. 4) in leapfrog form, unit masses
+# --------------------------------------------------------------------------
+def verlet_step(mesh: OracleMesh, face, bary, vel, potential_cfg: dict, integ: dict, nthreads=0):
+    """One step of velocity Verlet in leapfrog form on the surface. The
+    velocity carried between steps is the half-step velocity v_{k-1/2}:
+      v_{k+1/2} = v_{k-1/2} + dt F(x_k),   x_{k+1} = x_k walked by dt v_{k+1/2},
+    the velocity parallel-transported by the walk (the kick and the drift of
+    two successive half steps combined). The velocity at step k is
+    v_k = v_{k-1/2} + (dt/2) F(x_k). Returns (face, bary, vel, info)."""
+    pr = geodesic_pairs(mesh, face, bary, potential_cfg["cutoff"], nthreads=nthreads)
+    F, E = forces(face.shape[0], pr, potential_cfg["kind"], potential_cfg.get("k", 1.0),
+                  potential_cfg.get("sigma", 1.0))
+    dt = float(integ["dt"])
+    v = np.array(vel, np.float64, copy=True) + dt * F
+    f2, b2, v2, st, fl = walk(mesh, face, bary, dt * v, v)
+    return f2, b2, v2, dict(pairs=pr, F=F, E=E, walk=st, walk_flags=fl)

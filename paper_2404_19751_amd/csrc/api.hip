@@ -451,18 +451,18 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
 const SurfDesc *desc_dev(gsim_ctx *c) { return static_cast<const SurfDesc *>(c->desc.p); }
 
 // Binning, candidate search and geodesics of every source of the batch.
-gsim_status geodesic_pass(gsim_ctx *c, Batch &B) {
+gsim_status geodesic_pass(gsim_ctx *c, Batch &B, bool advance) {
     hipStream_t s = c->stream;
     if (B.all) {
         {
             Stage st(c, "prefilter");
+            HIPCHK(c, launch_pass_begin(desc_dev(c), B.bi.nsurf, P<int32_t>(c->work), advance, s));
             for (size_t i = 0; i < B.mem.size(); ++i) {
                 MeshState *ms = B.mem[i].ms;
                 HIPCHK(c, launch_face_sort(B.desc[i], P<int32_t>(ms->fcount), P<int64_t>(ms->tmp64),
                                            P<int64_t>(c->scan_scratch), s));
             }
         }
-        HIPCHK(c, launch_zero_i32(P<int32_t>(c->work), 16, s));
         GeoParams gp = c->gp;
         gp.stack_cap = c->stack_cap_all;
         gp.max_windows = c->max_windows_all;
@@ -476,7 +476,7 @@ gsim_status geodesic_pass(gsim_ctx *c, Batch &B) {
     {
         Stage st(c, "prefilter");
         if (B.small) {
-            HIPCHK(c, launch_bin_batch(desc_dev(c), B.bi.nsurf, s));
+            HIPCHK(c, launch_bin_batch(desc_dev(c), B.bi.nsurf, P<int32_t>(c->work), advance, s));
         } else {
             // one surface with a fine grid: multi-kernel counting sort
             MeshState *ms = B.mem[0].ms;
@@ -492,6 +492,7 @@ gsim_status geodesic_pass(gsim_ctx *c, Batch &B) {
             pb.cap_c = kCandCap;
             for (int k = 0; k < 3; ++k) pb.dims[k] = d.dims[k];
             pb.cell = d.cell;
+            HIPCHK(c, launch_pass_begin(desc_dev(c), 1, P<int32_t>(c->work), advance, s));
             HIPCHK(c, launch_xyz(ms->dm, n, ms->face, ms->bary, ms->xyz, s));
             HIPCHK(c, launch_prefilter_bin(ms->dm, n, pb, s));
             HIPCHK(c, launch_scan_i32_to_i64(pb.cell_fill, P<int64_t>(ms->tmp64), ncell, P<int64_t>(c->scan_scratch),
@@ -501,7 +502,6 @@ gsim_status geodesic_pass(gsim_ctx *c, Batch &B) {
             HIPCHK(c, launch_bin_scatter(n, pb, s));
         }
     }
-    HIPCHK(c, launch_zero_i32(P<int32_t>(c->work), 16, s));
     GeoParams gp = c->gp;
     if (!(gp.launch_delta > 0.0)) gp.launch_delta = 0.5 * B.mem[0].ms->dm.mean_edge;
     {
@@ -527,7 +527,7 @@ gsim_status single(gsim_ctx *c, MeshState *ms, double cutoff, const gsim_potenti
     B.mem.assign(1, Member{ms, cutoff, pot, nullptr});
     gsim_status st = prepare_batch(c, B);
     if (st != GSIM_OK) return st;
-    return geodesic_pass(c, B);
+    return geodesic_pass(c, B, false);
 }
 
 // Compact the candidate rows into the caller-facing CSR (host sync for the size).
@@ -597,7 +597,7 @@ void drop_graphs(gsim_ctx *c) {
 
 gsim_status enqueue_steps(gsim_ctx *c, Batch &B, int steps) {
     for (int k = 0; k < steps; ++k) {
-        gsim_status st = geodesic_pass(c, B);
+        gsim_status st = geodesic_pass(c, B, true);
         if (st != GSIM_OK) return st;
         if ((st = update_pass(c, B)) != GSIM_OK) return st;
     }
@@ -648,7 +648,7 @@ gsim_status run_steps(gsim_ctx *c, Batch &B, int nsteps) {
 
 gsim_status check_integ(gsim_ctx *c, const gsim_integrator *integ) {
     if (!integ) return fail(c, GSIM_E_ARG, "null integrator");
-    if (integ->kind != GSIM_INT_OVERDAMPED && integ->kind != GSIM_INT_BROWNIAN && integ->kind != GSIM_INT_FIRE)
+    if (integ->kind < GSIM_INT_OVERDAMPED || integ->kind > GSIM_INT_VERLET)
         return fail(c, GSIM_E_ARG, "unknown integrator");
     if (!(integ->dt > 0.0) && integ->kind == GSIM_INT_FIRE) return fail(c, GSIM_E_ARG, "FIRE needs dt > 0");
     return GSIM_OK;
@@ -800,7 +800,7 @@ gsim_status gsim_mesh_upload(gsim_ctx *c, int32_t nv, const double *xyz, int32_t
         d.n_boundary_edges = H.n_boundary_edges;
         d.n_pseudo = H.n_pseudo;
         HIPCHK(c, ensure(ms->step_dev, sizeof(uint64_t)));
-        HIPCHK(c, launch_zero_u64(P<unsigned long long>(ms->step_dev), 1, s));
+        HIPCHK(c, launch_fill_u64(P<unsigned long long>(ms->step_dev), 1, ~0ull, s));
         HIPCHK(c, hipStreamSynchronize(s));
         *mesh_id = (int32_t)c->meshes.size() - 1;
         return GSIM_OK;
@@ -864,7 +864,7 @@ static gsim_status reset_state(gsim_ctx *c, MeshState *ms, const double *vel, hi
     const int n = ms->n;
     if (vel) HIPCHK(c, hipMemcpyAsync(ms->vel, vel, sizeof(double) * 3 * n, kind, s));
     else HIPCHK(c, launch_zero_u64(reinterpret_cast<unsigned long long *>(ms->vel), 3 * (int64_t)n, s));
-    HIPCHK(c, launch_zero_u64(P<unsigned long long>(ms->step_dev), 1, s));
+    HIPCHK(c, launch_fill_u64(P<unsigned long long>(ms->step_dev), 1, ~0ull, s));
     HIPCHK(c, ensure(ms->fire, sizeof(FireState)));
     HIPCHK(c, launch_zero_u64(P<unsigned long long>(ms->fire), sizeof(FireState) / 8, s));
     ms->step = 0;
@@ -1067,12 +1067,12 @@ gsim_status gsim_autotune(gsim_ctx *c, int32_t nmesh, const int32_t *mesh_ids, c
             c->grab = k.grab;
             if ((st = begin_call(c)) != GSIM_OK) break;
             if ((st = prepare_batch(c, B)) != GSIM_OK) break;
-            if ((st = geodesic_pass(c, B)) != GSIM_OK) break;  // warm-up
+            if ((st = geodesic_pass(c, B, false)) != GSIM_OK) break;  // warm-up
             double tmin = INFINITY;
             for (int r = 0; r < reps && st == GSIM_OK; ++r) {
                 float ms = 0.f;
                 hipError_t e = hipEventRecord(e0, c->stream);
-                if (e == hipSuccess) st = geodesic_pass(c, B);
+                if (e == hipSuccess) st = geodesic_pass(c, B, false);
                 if (e == hipSuccess && st == GSIM_OK) e = hipEventRecord(e1, c->stream);
                 if (e == hipSuccess && st == GSIM_OK) e = hipEventSynchronize(e1);
                 if (e == hipSuccess && st == GSIM_OK) e = hipEventElapsedTime(&ms, e0, e1);

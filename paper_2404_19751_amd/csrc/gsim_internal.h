@@ -158,7 +158,8 @@ struct SurfDesc {
     int32_t n_min;
     double *F;                // [n][3]
     struct FireState *fire;
-    uint64_t *step;  // device counter: steps since the particles were set
+    uint64_t *step;  // device counter: index of the current step since the particles were set
+                     // (all ones before the first; each step's pass moves it on first)
     uint8_t *wflags;
     long long *prof;  // optional per-source profile [n][8]
 };
@@ -229,9 +230,13 @@ size_t geodesic_lds_bytes(int lds_stack_kb, bool fp32);
 // positions + cell counting sort, one workgroup per surface (every surface's
 // grid must have at most kSmallCells cells)
 constexpr int kSmallCells = 4096;
-hipError_t launch_bin_batch(const SurfDesc *desc, int nsurf, hipStream_t s);
-// fused force + integrator + walk for every particle of the batch, then the
-// step counters advance
+// (also clears the work counters and, when `advance`, moves every surface's
+// step counter on by one)
+hipError_t launch_bin_batch(const SurfDesc *desc, int nsurf, int32_t *work, bool advance, hipStream_t s);
+// the same start of a pass without the binning
+hipError_t launch_pass_begin(const SurfDesc *desc, int nsurf, int32_t *work, bool advance, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s);
+// fused force + integrator + walk for every particle of the batch
 hipError_t launch_update_batch(const SurfDesc *desc, const BatchIdx &bi, int block, Counters *ctr,
                                hipStream_t s);
 // resident geodesic workgroups per compute unit for a stack size (0 on error)

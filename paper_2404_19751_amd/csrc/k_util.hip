@@ -128,11 +128,16 @@ __global__ void k_bin_scatter(int n, PrefilterBufs b) {
 // Positions and the cell counting sort of one surface per workgroup: cell
 // counts, their exclusive scan and the scatter all live in LDS.
 constexpr int kBinThreads = 1024;
-__global__ __launch_bounds__(kBinThreads) void k_bin_batch(const SurfDesc *__restrict__ desc) {
+__global__ __launch_bounds__(kBinThreads) void k_bin_batch(const SurfDesc *__restrict__ desc,
+                                                           int32_t *__restrict__ work, int advance) {
     __shared__ int32_t cnt[kSmallCells];
     __shared__ int32_t start[kSmallCells];
     __shared__ int32_t part[kBinThreads];
     const SurfDesc &sd = desc[blockIdx.x];
+    // start of a pass: the geodesic kernel's work counters, and (in a time
+    // step) the surface's step counter
+    if (blockIdx.x == 0 && threadIdx.x < 16) work[threadIdx.x] = 0;
+    if (advance && threadIdx.x == 0) *sd.step += 1;
     const double *__restrict__ V = sd.m.V;
     const int32_t *__restrict__ T = sd.m.T;
     const int n = sd.n;
@@ -269,6 +274,18 @@ __global__ void k_integrate(int n, DevMesh m, const int32_t *__restrict__ face, 
     D[3 * i + 1] = d[1];
     D[3 * i + 2] = d[2];
 }
+// Start of a pass when the binning runs as several kernels: the work
+// counters and (in a time step) the step counters.
+__global__ void k_pass_begin(const SurfDesc *__restrict__ desc, int nsurf, int32_t *__restrict__ work, int advance) {
+    const int t = threadIdx.x;
+    if (t < 16) work[t] = 0;
+    if (advance && t < nsurf) *desc[t].step += 1;
+}
+__global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
 // ------------------------------------------------------------ all-pairs
 __global__ void k_face_count(int n, const int32_t *__restrict__ face, int32_t *__restrict__ counts) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -412,9 +429,18 @@ hipError_t launch_prefilter_bin(const DevMesh &m, int n, PrefilterBufs &b, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_bin_batch(const SurfDesc *desc, int nsurf, hipStream_t s) {
+hipError_t launch_bin_batch(const SurfDesc *desc, int nsurf, int32_t *work, bool advance, hipStream_t s) {
     if (nsurf <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bin_batch, dim3(nsurf), dim3(kBinThreads), 0, s, desc);
+    hipLaunchKernelGGL(k_bin_batch, dim3(nsurf), dim3(kBinThreads), 0, s, desc, work, advance ? 1 : 0);
+    return hipGetLastError();
+}
+hipError_t launch_pass_begin(const SurfDesc *desc, int nsurf, int32_t *work, bool advance, hipStream_t s) {
+    hipLaunchKernelGGL(k_pass_begin, dim3(1), dim3(kMaxBatch), 0, s, desc, nsurf, work, advance ? 1 : 0);
+    return hipGetLastError();
+}
+hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(n)), dim3(kBlock), 0, s, p, n, v);
     return hipGetLastError();
 }
 hipError_t launch_bin_scatter(int n, PrefilterBufs &b, hipStream_t s) {

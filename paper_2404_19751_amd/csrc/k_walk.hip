@@ -256,7 +256,16 @@ __global__ __launch_bounds__(256) void k_update_batch(const SurfDesc *__restrict
     } else {
         double F[3], E;
         row_force(i, sd.cand_cnt, sd.cap, sd.cdist, sd.ctan, sd.cutoff, sd.pkind, sd.pk, sd.psigma, F, E, np);
-        displacement(sd.m, f, i, F, sd.ikind, sd.dt, sd.mobility, sd.kT, sd.friction, sd.seed, *sd.step, D);
+        if (sd.ikind == 3) {
+            // velocity Verlet in leapfrog form (unit masses): the stored
+            // velocity is v_{k-1/2}; kick by dt F(x_k), drift by dt v_{k+1/2}
+            v = v + sd.dt * d3{F[0], F[1], F[2]};
+            D[0] = sd.dt * v.x;
+            D[1] = sd.dt * v.y;
+            D[2] = sd.dt * v.z;
+        } else {
+            displacement(sd.m, f, i, F, sd.ikind, sd.dt, sd.mobility, sd.kT, sd.friction, sd.seed, *sd.step, D);
+        }
     }
     double b[3] = {sd.bary[3 * i], sd.bary[3 * i + 1], sd.bary[3 * i + 2]};
     WalkCounts wc = {0, 0, 0, 0, 0};
@@ -273,13 +282,6 @@ __global__ __launch_bounds__(256) void k_update_batch(const SurfDesc *__restrict
     if (np && npairs) atomicAdd(npairs, (unsigned long long)np);
 }
 
-// The noise counter of every surface moves on by one step (after the
-// update kernel has read it).
-__global__ void k_advance_steps(const SurfDesc *__restrict__ desc, int nsurf) {
-    const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < nsurf) *desc[s].step += 1;
-}
-
 }  // namespace
 
 hipError_t launch_update_batch(const SurfDesc *desc, const BatchIdx &bi, int block, Counters *ctr, hipStream_t s) {
@@ -288,7 +290,6 @@ hipError_t launch_update_batch(const SurfDesc *desc, const BatchIdx &bi, int blo
     if (block != 64 && block != 128 && block != 256) block = 128;
     hipLaunchKernelGGL(k_update_batch, dim3((total + block - 1) / block), dim3(block), 0, s, desc, bi,
                        &ctr->nbr_pairs);
-    hipLaunchKernelGGL(k_advance_steps, dim3(1), dim3(kMaxBatch), 0, s, desc, bi.nsurf);
     return hipGetLastError();
 }
 

@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "_libgsim.so")
 OK, E_ARG, E_MESH, E_OOM, E_CAPACITY, E_DEVICE, E_STATE, E_LIMIT = 0, -1, -2, -3, -4, -5, -6, -7
 FP64, FP32_MIXED = 0, 1
 POT = {"harmonic": 0, "coulomb": 1, "gaussian": 2}
-INTEG = {"overdamped": 0, "brownian": 1, "fire": 2}
+INTEG = {"overdamped": 0, "brownian": 1, "fire": 2, "verlet": 3}
 PAIR_TIE, PAIR_ZERO, PAIR_GUARD = 1, 2, 4
 
 EXPORTS = ["gsim_create", "gsim_destroy", "gsim_last_error", "gsim_synchronize", "gsim_mesh_upload",

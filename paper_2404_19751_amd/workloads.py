@@ -387,6 +387,13 @@ C3_TORI = [(57, 17), (67, 20), (80, 24), (97, 29), (113, 34), (133, 40), (157, 4
            (260, 78), (310, 93), (367, 110)]
 
 
+def benchmark_torus() -> Mesh:
+    """Torus with radii 1 and 3 (aspect ratio 3) at 83 x 28 quads, 4648
+    faces: a procedural stand-in for the triangulated torus of the paper's
+    scaling benchmarks (about 4600 faces)."""
+    return torus(3.0, 1.0, 83, 28)
+
+
 def packing_count(m: Mesh, sigma: float, phi: float = 0.3, lo: int = 200, hi: int = 4000) -> int:
     """Particles of diameter sigma at packing fraction phi, clamped to [lo, hi]."""
     n = int(round(phi * surface_area(m) / (np.pi * (0.5 * sigma) ** 2)))
@@ -408,6 +415,9 @@ def workload(name: str) -> "Workload | list[Workload]":
         Brownian kT = 0.1, friction 1, dt = 0.005, 1000 steps.
     c5a / c5b  icosphere L6 / the ellipsoid (1, 0.8, 0.6), N = 2000 (seeds
         4 / 5), Coulomb 1/r with no cutoff, FIRE, 500 iterations.
+    torus_nve_<N>_<sigma>  the aspect-3 benchmark torus (4648 faces), N
+        particles (seed 7), harmonic repulsion of range sigma, velocity
+        Verlet (NVE) dt = 0.005, from rest.
     """
     if name == "c1":
         m = icosphere(3)
@@ -437,6 +447,14 @@ def workload(name: str) -> "Workload | list[Workload]":
         sig = 3.0 * le
         return Workload("c4", m, f, b, dict(kind="harmonic", k=1.0, sigma=sig, cutoff=sig),
                         dict(kind="brownian", dt=0.005, kT=0.1, friction=1.0, seed=3), 1000, le)
+    if name.startswith("torus_nve"):
+        # torus_nve_<N>_<sigma>: the NVE scaling workload on an aspect-3 torus
+        _, _, n_s, sig_s = name.split("_")
+        m = benchmark_torus()
+        n, sig = int(n_s), float(sig_s)
+        f, b = random_particles(m.nf, n, 7)
+        return Workload(name, m, f, b, dict(kind="harmonic", k=1.0, sigma=sig, cutoff=sig),
+                        dict(kind="verlet", dt=0.005), 100, mean_edge_length(m))
     if name in ("c5a", "c5b"):
         m = icosphere(6) if name == "c5a" else ellipsoid(6)
         f, b = random_particles(m.nf, 2000, 4 if name == "c5a" else 5)
