@@ -245,7 +245,8 @@ gsim_status gsim_timing_enable(gsim_ctx *ctx, int on);
 gsim_status gsim_timing_get(gsim_ctx *ctx, const char *name, double *avg_ms, int64_t *launches);
 /* Work counters. Of the last call: [0] windows processed,
  * [1] windows pruned, [2] bend-vertex (pseudo-source) launches,
- * [3] stale windows dropped, [4] candidate pairs, [5] neighbour pairs,
+ * [3] stale windows dropped, [4] sources recomputed in FP64 (FP32-mixed
+ * guard band), [5] neighbour pairs,
  * [6] sources over a work limit, [10] deepest window stack of a source in
  * all-pairs passes (records). Summed over the calls since timing was last
  * enabled: [7] neighbour pairs, [8] windows, [9] passes. c[11]. */

@@ -704,6 +704,7 @@ gsim_status gsim_create(int device, gsim_precision prec, void *hip_stream, gsim_
     c->gp.tie_rel32 = 1e-4;
     c->gp.tie_dir32 = 5e-6;
     c->gp.root_rel32 = 2e-6;
+    c->gp.slack32 = 1e-4;
     c->gp.bucket = 0.0;
     c->gp.dom_rel = 1e-12;
     c->gp.dom_rel32 = 1e-4;  // FP32 window chains across a whole surface carry errors up to ~1e-5
@@ -1203,6 +1204,7 @@ gsim_status gsim_tune_set(gsim_ctx *c, const char *name, double value) {
     else if (k == "tie_dir32" && value >= 0.0) c->gp.tie_dir32 = value;
     else if (k == "guard_rel" && value >= 0.0) c->gp.guard_rel = value;
     else if (k == "root_rel32" && value >= 0.0 && value <= 1e-4) c->gp.root_rel32 = value;
+    else if (k == "slack32" && value >= 1e-6 && value <= 1e-2) c->gp.slack32 = value;
     else if (k == "stack_cap" && value >= 64 && value <= (1 << 22)) c->gp.stack_cap = (int32_t)value;
     else if (k == "max_windows" && value >= 1) c->gp.max_windows = (int32_t)std::min(value, 2.0e9);
     else if (k == "max_slots" && value >= 1 && value <= 65536) c->max_slots = (int)value;
@@ -1242,7 +1244,7 @@ gsim_status gsim_counters_get(gsim_ctx *c, int64_t *c10) {
     c10[1] = (int64_t)c->last.pruned;
     c10[2] = (int64_t)c->last.launches;
     c10[3] = (int64_t)c->last.stale;
-    c10[4] = (int64_t)c->last.cand_pairs;
+    c10[4] = (int64_t)c->last.guards;
     c10[5] = (int64_t)c->last.nbr_pairs;
     c10[6] = (int64_t)c->last.limited;
     return GSIM_OK;

@@ -102,6 +102,7 @@ struct GeoParams {
     double cone_tol32, tie_rel32, tie_dir32;  // the FP32 pass's counterparts
     double bucket;        // all-pairs: key width of one processing round (0 = two max edge lengths)
     double dom_rel, dom_rel32;  // all-pairs: vertex-path domination margins (FP64 pass / FP32 pass)
+    double slack32;       // FP32 pass: acceptance slack beyond the cutoff, relative to it
     double root_rel32;    // FP32 pass: a bend vertex is re-launched only when its distance improves by more
                           // than this fraction (FP32 rounding makes equal paths differ by ~1e-7)
     int32_t eager;        // launch bend vertices as soon as they are found
@@ -116,7 +117,7 @@ struct GeoOut {
 };
 
 struct Counters {   // device-side, int64
-    unsigned long long windows, pruned, launches, stale, cand_pairs, nbr_pairs, limited, max_depth;
+    unsigned long long windows, pruned, launches, stale, guards, nbr_pairs, limited, max_depth;
 };
 
 // launchers (return hipError_t of the launch)

@@ -188,7 +188,7 @@ __device__ inline void children(const He<R> &h, const Win<R> &w, double txc, boo
 }
 
 struct SrcStats {
-    unsigned long long windows, launches, stale;
+    unsigned long long windows, launches, stale, guards;
     int pruned;
     bool overflow;
 };
@@ -380,7 +380,7 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
     // FP32 results may be off by rounding: everything within the guard band
     // above the cutoff is still propagated and recorded, so that pairs near
     // the cutoff are seen and recomputed in FP64
-    C.lb_slack = fp32 ? fmax(1e-4, a.gp.guard_rel) * C.cutoff : 0.0;
+    C.lb_slack = fp32 ? fmax(a.gp.slack32, a.gp.guard_rel) * C.cutoff : 0.0;
     C.cut_acc = C.cutoff + C.lb_slack;
     C.tol = fp32 ? a.gp.cone_tol32 : a.gp.cone_tol;
     C.tie_rel = fp32 ? a.gp.tie_rel32 : a.gp.tie_rel;
@@ -699,15 +699,17 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
     return any_near;
 }
 
+// Two waves per SIMD: with the LDS of five workgroups per compute unit, a
+// wavefront may hold at most 256 registers, or the fifth has nowhere to run.
 template <bool kMixed, int kStk>
-__global__ __launch_bounds__(kWave) void k_geodesic(GeoArgs a) {
+__global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
     __shared__ Lds L;
     __shared__ alignas(16) unsigned char stk[kStk];
     const int lane = lane_id();
     const int total = a.bi.begin[a.bi.nsurf];
     int chunk = blockIdx.x % kChunks, chunks_left = kChunks;
     SrcStats st;
-    st.windows = st.launches = st.stale = 0;
+    st.windows = st.launches = st.stale = st.guards = 0;
     st.pruned = 0;
     st.overflow = false;
     unsigned long long c_limited = 0;
@@ -746,8 +748,10 @@ __global__ __launch_bounds__(kWave) void k_geodesic(GeoArgs a) {
         st.overflow = false;
         if (kMixed) {
             // FP32 pass; a pair inside the guard band sends the source through FP64
-            if (run_source<float>(a, sd, L, stk, kStk, src, c0, nc, false, blockIdx.x, st))
+            if (run_source<float>(a, sd, L, stk, kStk, src, c0, nc, false, blockIdx.x, st)) {
                 run_source<double>(a, sd, L, stk, kStk, src, c0, nc, true, blockIdx.x, st);
+                ++st.guards;
+            }
         } else {
             run_source<double>(a, sd, L, stk, kStk, src, c0, nc, false, blockIdx.x, st);
         }
@@ -764,6 +768,7 @@ __global__ __launch_bounds__(kWave) void k_geodesic(GeoArgs a) {
         atomicAdd(&a.ctr->launches, st.launches);
         atomicAdd(&a.ctr->stale, sl);
         atomicAdd(&a.ctr->limited, c_limited);
+        if (st.guards) atomicAdd(&a.ctr->guards, st.guards);
     }
 }
 

@@ -285,6 +285,6 @@ class Context:
     def counters(self) -> dict:
         c = np.zeros(11, np.int64)
         self._chk(self.L.gsim_counters_get(self.h, _ptr(c)))
-        return dict(windows=int(c[0]), pruned=int(c[1]), launches=int(c[2]), stale=int(c[3]), cand_pairs=int(c[4]),
+        return dict(windows=int(c[0]), pruned=int(c[1]), launches=int(c[2]), stale=int(c[3]), guard_sources=int(c[4]),
                     nbr_pairs=int(c[5]), limited=int(c[6]), cum_pairs=int(c[7]), cum_windows=int(c[8]),
                     cum_passes=int(c[9]), max_stack_depth=int(c[10]))
