@@ -71,7 +71,7 @@ struct gsim_ctx {
     bool own_stream = false;
     std::string err;
     std::vector<MeshState *> meshes;
-    Buf stack, work, ctr, wstats, scan_scratch, sum_scratch, pf_over, prof, desc, vdist, partials;
+    Buf stack, work, ctr, wstats, scan_scratch, sum_scratch, pf_over, prof, desc, vdist, roots, partials;
     SurfDesc *desc_pinned = nullptr;  // staging for descriptor uploads
     std::vector<SurfDesc> desc_cached;
     bool profile_sources = false;
@@ -356,6 +356,8 @@ struct Batch {
     bool all = false;     // all-pairs surfaces (no cutoff)
     int tcap = 0;         // all-pairs target-table capacity
     int64_t vstride = 0;  // all-pairs vertex-table stride
+    int64_t rstride = 0;  // all-pairs bend-vertex table bytes per wavefront
+    int32_t rcap = 0;     // its capacity (bend vertices)
     bool small = true;  // every surface bins in one workgroup
     int nslots = 0;
     GeoShape shape{};
@@ -407,13 +409,16 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
     int nblk = 0;
     B.tcap = 0;
     B.vstride = 0;
+    B.rcap = 1;
     for (int i = 0; i < ns; ++i) {
         B.fire_blk.begin[i] = nblk;
         nblk += (B.mem[i].ms->n + kFireBlock - 1) / kFireBlock;
         B.any_fire |= B.mem[i].integ && B.mem[i].integ->kind == GSIM_INT_FIRE;
         B.tcap = std::max(B.tcap, B.mem[i].ms->n);
         B.vstride = std::max<int64_t>(B.vstride, B.mem[i].ms->dm.nv);
+        B.rcap = std::max(B.rcap, B.mem[i].ms->dm.n_pseudo);
     }
+    B.rstride = all_roots_bytes(B.rcap);
     B.fire_blk.begin[ns] = nblk;
     if (B.any_fire) HIPCHK(c, ensure(c->partials, sizeof(double) * 3 * (size_t)std::max(nblk, 1)));
     if (c->profile_sources && ns == 1) {
@@ -427,7 +432,7 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
     }
     // persistent grid: as many wavefronts as can be resident, at most one per source
     const bool fp32 = c->prec == GSIM_FP32_MIXED;
-    if (B.all && (size_t)B.tcap * 32 + 28672 > (size_t)c->max_lds)
+    if (B.all && (size_t)B.tcap * 32 + kAllLdsFixed > (size_t)c->max_lds)
         return fail(c, GSIM_E_LIMIT, "all-pairs target table of " + std::to_string(B.tcap) +
                                          " particles exceeds the device's LDS per workgroup (" +
                                          std::to_string(c->max_lds) + " bytes)");
@@ -436,7 +441,8 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
     B.nslots = std::min(std::min(total, c->cus * per_cu), c->max_slots);
     if (B.all) {
         // whole-mesh fronts are deep: fewer resident wavefronts rather than more memory
-        const int64_t fit = (int64_t)(c->stack_budget / (64.0 * c->stack_cap_all));
+        const double per_slot = 64.0 * c->stack_cap_all + 8.0 * B.vstride + (double)B.rstride;
+        const int64_t fit = (int64_t)(c->stack_budget / per_slot);
         B.nslots = (int)std::max<int64_t>(1, std::min<int64_t>(B.nslots, fit));
     }
     B.shape.lds_stack_kb = c->lds_stack_kb;
@@ -444,7 +450,10 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
     B.shape.grab = c->grab;
     const int cap_rec = B.all ? c->stack_cap_all : c->gp.stack_cap;
     HIPCHK(c, ensure(c->stack, (size_t)std::max(B.nslots, 1) * cap_rec * 64));
-    if (B.all) HIPCHK(c, ensure(c->vdist, sizeof(double) * (size_t)std::max(B.nslots, 1) * B.vstride));
+    if (B.all) {
+        HIPCHK(c, ensure(c->vdist, sizeof(double) * (size_t)std::max(B.nslots, 1) * B.vstride));
+        HIPCHK(c, ensure(c->roots, (size_t)std::max(B.nslots, 1) * B.rstride));
+    }
     return upload_descs(c, B.desc);
 }
 
@@ -468,8 +477,8 @@ gsim_status geodesic_pass(gsim_ctx *c, Batch &B, bool advance) {
         gp.max_windows = c->max_windows_all;
         Stage st(c, "geodesic");
         HIPCHK(c, launch_geodesic_all(desc_dev(c), B.bi, gp, B.shape, P<char>(c->stack), P<double>(c->vdist), B.vstride,
-                                      B.tcap, P<int32_t>(c->work), P<Counters>(c->ctr), c->prec == GSIM_FP32_MIXED,
-                                      s));
+                                      P<char>(c->roots), B.rstride, B.rcap, B.tcap, P<int32_t>(c->work),
+                                      P<Counters>(c->ctr), c->prec == GSIM_FP32_MIXED, s));
         c->passes++;
         return GSIM_OK;
     }
@@ -742,12 +751,13 @@ void gsim_destroy(gsim_ctx *c) {
             if (p) (void)hipFree(p);
         for (void *p : {(void *)ms->dm.V, (void *)ms->dm.T, (void *)ms->dm.he, (void *)ms->dm.hef,
                         (void *)ms->dm.vflag, (void *)ms->dm.theta, (void *)ms->dm.fan_off, (void *)ms->dm.fan,
-                        (void *)ms->dm.corner, (void *)ms->dm.fnrm, (void *)ms->dm.fpos})
+                        (void *)ms->dm.corner, (void *)ms->dm.fnrm, (void *)ms->dm.fpos,
+                        (void *)ms->dm.pidx, (void *)ms->dm.pvert})
             if (p) (void)hipFree(p);
         delete ms;
     }
     for (Buf *b : {&c->stack, &c->work, &c->ctr, &c->wstats, &c->scan_scratch, &c->sum_scratch, &c->pf_over,
-                   &c->prof, &c->desc, &c->vdist, &c->partials})
+                   &c->prof, &c->desc, &c->vdist, &c->roots, &c->partials})
         release(*b);
     if (c->desc_pinned) (void)hipHostFree(c->desc_pinned);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -791,6 +801,8 @@ gsim_status gsim_mesh_upload(gsim_ctx *c, int32_t nv, const double *xyz, int32_t
         HIPCHK(c, upload(d.corner, H.corner.data(), H.corner.size(), s));
         HIPCHK(c, upload(d.fnrm, H.fnrm.data(), H.fnrm.size(), s));
         HIPCHK(c, upload(d.fpos, H.fpos.data(), H.fpos.size(), s));
+        HIPCHK(c, upload(d.pidx, H.pidx.data(), H.pidx.size(), s));
+        HIPCHK(c, upload(d.pvert, H.pvert.data(), H.pvert.size(), s));
         for (int k = 0; k < 3; ++k) {
             d.bbmin[k] = H.bbmin[k];
             d.bbmax[k] = H.bbmax[k];

@@ -55,6 +55,8 @@ struct DevMesh {
     double *fnrm = nullptr;     // [nf][3] unit outward normal
     double *fpos = nullptr;     // [nf][18]: the face's vertex positions in slot order, then the unit
                                 // directions of its half-edges 3f+0..2
+    int32_t *pidx = nullptr;    // [nv] bend-vertex number (0..n_pseudo-1) of a pseudo-source, else -1
+    int32_t *pvert = nullptr;   // [max(n_pseudo,1)] the vertex of each bend-vertex number
     double bbmin[3], bbmax[3];
     double mean_edge = 0, min_edge = 0, max_edge = 0;
     int32_t n_boundary_edges = 0, n_pseudo = 0;
@@ -71,6 +73,7 @@ struct HostMesh {
     std::vector<uint8_t> vflag;
     std::vector<double> theta, corner, fnrm, fpos;
     std::vector<int32_t> fan_off, fan;
+    std::vector<int32_t> pidx, pvert;
     double bbmin[3], bbmax[3];
     double mean_edge = 0, min_edge = 0, max_edge = 0;
     int32_t n_boundary_edges = 0, n_pseudo = 0;
@@ -211,10 +214,18 @@ hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoPa
                            char *stack_mem, int32_t *work_ctr, Counters *ctr, bool fp32, hipStream_t s);
 // All-pairs geodesics (no cutoff) for every source of the batch: every other
 // particle of the surface is a target. vdist: per resident wavefront a table
-// of vstride vertex distances; tcap: target-table capacity (dynamic LDS).
+// of vstride vertex distances; roots: per resident wavefront a bend-vertex
+// table of rstride bytes for rcap bend vertices (all_roots_bytes); tcap:
+// target-table capacity (dynamic LDS).
 hipError_t launch_geodesic_all(const SurfDesc *desc, const BatchIdx &bi, const GeoParams &gp, const GeoShape &shape,
-                               char *stack_mem, double *vdist, int64_t vstride, int tcap, int32_t *work_ctr,
-                               Counters *ctr, bool fp32, hipStream_t s);
+                               char *stack_mem, double *vdist, int64_t vstride, char *roots, int64_t rstride,
+                               int rcap, int tcap, int32_t *work_ctr, Counters *ctr, bool fp32, hipStream_t s);
+// Bytes of one wavefront's bend-vertex table for rcap bend vertices: five
+// doubles and three int32 each, rounded up to 256 bytes.
+inline int64_t all_roots_bytes(int rcap) { return ((int64_t)rcap * 52 + 255) / 256 * 256; }
+// LDS of an all-pairs workgroup besides its target table (the largest
+// window stack and the launch chunk).
+constexpr int kAllLdsFixed = 16384 + 4096;
 int geodesic_all_blocks_per_cu(int lds_stack_kb, int tcap, bool fp32);
 // particles of one surface sorted by face (counting sort; counts must be zeroed)
 hipError_t launch_face_sort(const SurfDesc &d, int32_t *counts, int64_t *tmp64, int64_t *scan_scratch, hipStream_t s);

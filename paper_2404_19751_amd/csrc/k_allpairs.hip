@@ -18,13 +18,15 @@
 //    ahead along one branch; once every target has been reached, windows
 //    whose key exceeds the largest target distance (widened by the tie gap)
 //    are dropped.
-// Bend vertices are launched exactly as in the cutoff kernel.
+// Bend vertices are launched by the rules of the cutoff kernel, from a table
+// that can hold every saddle and boundary vertex of the surface.
 //
 // Mapping: target state (best distance, second-best distance of another
-// direction, tangent) of all n targets in dynamic LDS; the vertex table and
-// the window overflow in per-wavefront global areas (the overflow is
-// two-ended: the current round grows from one end, the next round from the
-// other); targets are found through the surface's particles-by-face index.
+// direction, tangent) of all n targets in dynamic LDS; the vertex table, the
+// bend-vertex table and the window overflow in per-wavefront global areas
+// (the overflow is two-ended: the current round grows from one end, the next
+// round from the other); targets are found through the surface's
+// particles-by-face index.
 #include <cmath>
 
 #include "gsim_internal.h"
@@ -36,6 +38,7 @@ namespace {
 using namespace wnd;
 
 constexpr int kChunks = 8;
+constexpr int kLaunchChunk = 256;  // bend vertices whose fans are flattened at once
 
 struct AllArgs {
     const SurfDesc *sd;
@@ -44,6 +47,9 @@ struct AllArgs {
     void *stack;     // per wavefront: stack_cap records of 64 bytes
     double *vdist;   // per wavefront: vstride vertex distances
     int64_t vstride;
+    char *roots;     // per wavefront: rstride bytes of bend-vertex table for rcap vertices
+    int64_t rstride;
+    int rcap;
     int32_t *work;
     Counters *ctr;
     int tcap;        // target capacity of the dynamic LDS table
@@ -51,10 +57,126 @@ struct AllArgs {
 };
 
 struct AllLds {
-    Roots R;
+    int32_t sel[kLaunchChunk];       // bend vertices of the launch chunk
+    int32_t pref[kLaunchChunk + 1];  // prefix sums of their fan sizes
+    int32_t npend;    // length of the pending-launch list
     int32_t unfound;  // targets not reached yet
     double maxb;      // windows with a larger key cannot improve any target
 };
+
+// Bend-vertex table of one source in the wavefront's global area, indexed by
+// the mesh's bend-vertex number (a whole-mesh propagation may reach every
+// saddle and boundary vertex): rD the best distance so far, rL the distance
+// of the last launch, (rtx, rty) the initial tangent of the best path, rD2
+// the best distance of a path leaving the source in another direction;
+// queued marks a vertex on the pending-launch list pend; sel holds the
+// vertices of one launch.
+struct GRoots {
+    double *rD, *rL, *rtx, *rty, *rD2;
+    int32_t *queued, *pend, *sel;
+};
+
+__device__ inline GRoots groots(const AllArgs &a, int slot) {
+    const int n = a.rcap;
+    GRoots g;
+    g.rD = reinterpret_cast<double *>(a.roots + (int64_t)slot * a.rstride);
+    g.rL = g.rD + n;
+    g.rtx = g.rL + n;
+    g.rty = g.rtx + n;
+    g.rD2 = g.rty + n;
+    g.queued = reinterpret_cast<int32_t *>(g.rD2 + n);
+    g.pend = g.queued + n;
+    g.sel = g.pend + n;
+    return g;
+}
+
+// Bend-vertex update (insert or improve) by the rules of the cutoff
+// kernel's table: keep the smallest distance and its tangent and the
+// smallest distance of another initial direction; queue the vertex for a
+// (re-)launch when it improved by more than the re-launch tolerance, when
+// the direction of its best path changed or when another direction came
+// within the tie band. The lanes load their entries together and leave when
+// their candidate cannot change anything; the others are applied one lane at
+// a time in registers, each result passed to every lane that holds the same
+// vertex, and written back once.
+__device__ inline void groot_update(const GRoots &G, AllLds &L, const RootCfg &rc, bool ok, int e, double d,
+                                    double tx, double ty, double alt) {
+    double cD = INFINITY, cD2 = INFINITY, cL = INFINITY, ax = 0.0, ay = 0.0;
+    int qd = 1;
+    if (ok) {
+        cD = G.rD[e];
+        cD2 = G.rD2[e];
+        if (d >= cD && d >= cD2 && alt >= cD2) ok = false;
+    }
+    uint64_t m = __ballot(ok);
+    if (!m) return;
+    if (ok) {
+        cL = G.rL[e];
+        ax = G.rtx[e];
+        ay = G.rty[e];
+        qd = G.queued[e];
+    }
+    int np = L.npend;  // the pending list's length, kept wave-uniform in a register
+    while (m) {
+        const int l = __ffsll((unsigned long long)m) - 1;
+        int app = 0;
+        if (lane_id() == l) {
+            // a fresh entry has cD = cL = cD2 = infinity: every branch below then inserts
+            const bool differ = fabs(ax * ty - ay * tx) > rc.tie_dir || ax * tx + ay * ty < 0.0;
+            const bool tied = cD2 - cD <= rc.tie_rel * cD;
+            if (d < cD) {
+                if (differ) {
+                    cD2 = fmin(cD2, cD);
+                    cL = INFINITY;  // new direction: launch again however small the gain
+                }
+                cD = d;
+                ax = tx;
+                ay = ty;
+            } else if (differ) {
+                cD2 = fmin(cD2, d);
+            }
+            cD2 = fmin(cD2, alt);
+            if (!tied && cD2 - cD <= rc.tie_rel * cD) cL = INFINITY;  // a new tie
+            if (cD < cL * rc.keep && !qd) {
+                qd = 1;
+                app = 1;
+                G.pend[np] = e;
+            }
+        }
+        np += __shfl(app, l);
+        const int el = __shfl(e, l);
+        const double bD = __shfl(cD, l), bD2 = __shfl(cD2, l), bL = __shfl(cL, l);
+        const double bx = __shfl(ax, l), by = __shfl(ay, l);
+        const int bq = __shfl(qd, l);
+        if (ok && e == el) {
+            cD = bD;
+            cD2 = bD2;
+            cL = bL;
+            ax = bx;
+            ay = by;
+            qd = bq;
+        }
+        m &= m - 1;
+    }
+    if (ok) {
+        G.rD[e] = cD;
+        G.rD2[e] = cD2;
+        G.rL[e] = cL;
+        G.rtx[e] = ax;
+        G.rty[e] = ay;
+        G.queued[e] = qd;
+    }
+    if (lane_id() == 0) L.npend = np;
+    __syncthreads();  // later loads of the table, by any lane, see these values
+}
+
+// A window of bend vertex w.root is stale when it comes from an earlier
+// launch or when the vertex has improved enough for a new launch.
+template <typename R>
+__device__ inline bool gstale(const GRoots &G, const Win<R> &w, const RootCfg &rc) {
+    const double rL = G.rL[w.root];
+    return w.sg > (R)rL || G.rD[w.root] < rL * rc.keep;
+}
 
 // Per-source constants.
 struct ACtx {
@@ -178,6 +300,7 @@ __device__ inline void target_update(AllLds &L, double *d1, double *d2, double *
             }
             d2[j] = fmin(d2[j], alt);
         }
+        lane_step_barrier();
         m &= m - 1;
     }
 }
@@ -244,8 +367,9 @@ __device__ inline bool opposite_dominates(double px, double py, double sg, doubl
 
 // Targets in face g (entry half-edge slot k of g) seen through window w.
 template <typename R>
-__device__ inline void query_face(const SurfDesc &sd, AllLds &L, double *d1, double *d2, double *t1x, double *t1y,
-                                  const ACtx &C, bool have, int src, int g, int k, const He<R> &H, const Win<R> &w) {
+__device__ inline void query_face(const SurfDesc &sd, AllLds &L, const GRoots &G, double *d1, double *d2, double *t1x,
+                                  double *t1y, const ACtx &C, bool have, int src, int g, int k, const He<R> &H,
+                                  const Win<R> &w) {
     int q = 0, q1 = 0;
     if (have) {
         q = sd.fstart[g];
@@ -274,9 +398,9 @@ __device__ inline void query_face(const SurfDesc &sd, AllLds &L, double *d1, dou
                         tx = (double)(w.c * dx - w.s * dy);
                         ty = (double)(w.s * dx + w.c * dy);
                     } else {
-                        tx = L.R.rtx[w.root];
-                        ty = L.R.rty[w.root];
-                        alt = L.R.rD2[w.root] + (double)l;
+                        tx = G.rtx[w.root];
+                        ty = G.rty[w.root];
+                        alt = G.rD2[w.root] + (double)l;
                     }
                 }
             }
@@ -286,126 +410,143 @@ __device__ inline void query_face(const SurfDesc &sd, AllLds &L, double *d1, dou
     }
 }
 
-// Launch the bend vertices whose distance improved (all of them once the
-// round's stack has drained), their fans flattened over the lanes.
+// Launch the pending bend vertices (their distance improved, or their best
+// direction changed, or a tie appeared), their fans flattened over the lanes
+// a chunk of vertices at a time.
 template <typename R>
-__device__ void launch_roots(const AllArgs &a, const SurfDesc &sd, AllLds &L, double *d1, double *d2, double *t1x,
-                             double *t1y, double *Dv, const ACtx &C, RoundStack<R> &S, double T, int src,
-                             SrcStats &st) {
+__device__ void launch_roots(const AllArgs &a, const SurfDesc &sd, AllLds &L, const GRoots &G, double *d1,
+                             double *d2, double *t1x, double *t1y, double *Dv, const ACtx &C, RoundStack<R> &S,
+                             double T, int src, SrcStats &st) {
     const int lane = lane_id();
     const DevMesh &M = sd.m;
     const HeRec *__restrict__ he = M.he;
-    if (lane == 0) L.R.dirty = 0;
+    // take the pending list (its vertices may be queued again while they launch)
+    const int npend = L.npend;
     int nsel = 0;
-    for (int base = 0; base < kRootCap; base += kWave) {
-        const int e = base + lane;
-        const bool sel = e < kRootCap && L.R.rkey[e] >= 0 && L.R.rD[e] < L.R.rL[e] * C.rc.keep &&
-                         L.R.rD[e] < L.maxb;
+    for (int base = 0; base < npend; base += kWave) {
+        const int k = base + lane;
+        int e = 0;
+        bool sel = false;
+        double D = 0.0;
+        if (k < npend) {
+            e = G.pend[k];
+            D = G.rD[e];
+            sel = D < G.rL[e] * C.rc.keep && D < L.maxb;
+            G.queued[e] = 0;
+        }
         const uint64_t mk = __ballot(sel);
         if (sel) {
-            L.R.sel[nsel + __popcll(mk & lanemask_lt())] = e;
-            L.R.rL[e] = L.R.rD[e];
+            G.sel[nsel + __popcll(mk & lanemask_lt())] = e;
+            G.rL[e] = D;
         }
         nsel += __popcll(mk);
     }
-    int carry = 0;
-    for (int base = 0; base < nsel; base += kWave) {
-        const int k = base + lane;
-        int deg = 0;
-        if (k < nsel) {
-            const int v = L.R.rkey[L.R.sel[k]];
-            deg = M.fan_off[v + 1] - M.fan_off[v];
-        }
-        int inc = deg;
-        for (int o = 1; o < kWave; o <<= 1) {
-            const int y = __shfl_up(inc, o);
-            if (lane >= o) inc += y;
-        }
-        if (k < nsel) L.R.pref[k + 1] = carry + inc;
-        st.launches += (unsigned long long)__popcll(__ballot(deg > 0));
-        carry += __shfl(inc, kWave - 1);
-    }
-    if (lane == 0) L.R.pref[0] = 0;
+    if (lane == 0) L.npend = 0;
     __syncthreads();
-    const int total = carry;
-    for (int base = 0; base < total; base += kWave) {
-        const int idx = base + lane;
-        const bool act = idx < total;
-        int k = 0;
-        if (act) {
-            int lo = 0, hi = nsel - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (L.R.pref[mid] <= idx) lo = mid;
-                else hi = mid - 1;
+    for (int c0 = 0; c0 < nsel; c0 += kLaunchChunk) {
+        const int cn = min(kLaunchChunk, nsel - c0);
+        int carry = 0;
+        for (int base = 0; base < cn; base += kWave) {
+            const int k = base + lane;
+            int deg = 0;
+            if (k < cn) {
+                const int e = G.sel[c0 + k];
+                const int v = M.pvert[e];
+                L.sel[k] = e;
+                deg = M.fan_off[v + 1] - M.fan_off[v];
             }
-            k = lo;
+            int inc = deg;
+            for (int o = 1; o < kWave; o <<= 1) {
+                const int y = __shfl_up(inc, o);
+                if (lane >= o) inc += y;
+            }
+            if (k < cn) L.pref[k + 1] = carry + inc;
+            st.launches += (unsigned long long)__popcll(__ballot(deg > 0));
+            carry += __shfl(inc, kWave - 1);
         }
-        const int el = act ? L.R.sel[k] : 0;
-        const int v = act ? L.R.rkey[el] : 0;
-        const double D = act ? L.R.rD[el] : 0.0;
-        const double vtx = act ? L.R.rtx[el] : 0.0, vty = act ? L.R.rty[el] : 0.0;
-        const double D2 = act ? L.R.rD2[el] : INFINITY;
-        const int h = act ? M.fan[M.fan_off[v] + (idx - L.R.pref[k])] : 0;
-        const int hn = h - h % 3 + (h % 3 + 1) % 3;
-        const HeRec Rh = he[h], Rn = he[hn];
-        Win<R> nw;
-        bool want = false;
-        double key = 0.0;
-        if (act && Rn.twin >= 0) {
-            // window across the edge opposite v: twin(next(h)) runs u2 -> u1
-            const double px = Rn.L - Rn.cx, py = -Rn.cy;
-            nw.px = (R)px;
-            nw.py = (R)py;
-            nw.b0 = R(0);
-            nw.b1 = (R)Rn.L;
-            nw.sg = (R)D;
-            nw.c = R(1);
-            nw.s = R(0);
-            nw.he = Rn.twin;
-            nw.root = el;
-            key = D + seg_dist(px, py, 0.0, Rn.L);
-            want = key < L.maxb;
-        }
-        // direct targets in face(h): straight segments inside the face
-        const int g = h / 3;
-        int q = 0, q1 = 0;
-        if (act) {
-            q = sd.fstart[g];
-            q1 = sd.fstart[g + 1];
-        }
-        const double *pv = M.V + 3 * (int64_t)v;
-        while (__ballot(q < q1)) {
-            bool ok = false;
-            int j = 0;
-            double d = 0;
-            if (q < q1) {
-                j = sd.forder[q];
-                if (j != src) {
-                    const double *b = sd.bary + 3 * (int64_t)j;
-                    const int32_t *T = M.T + 3 * (int64_t)g;
-                    double x[3] = {0, 0, 0};
-                    for (int c = 0; c < 3; ++c)
-                        for (int dd = 0; dd < 3; ++dd) x[dd] += b[c] * M.V[3 * (int64_t)T[c] + dd];
-                    const double dx = x[0] - pv[0], dy = x[1] - pv[1], dz = x[2] - pv[2];
-                    d = D + sqrt(dx * dx + dy * dy + dz * dz);
-                    ok = true;
+        if (lane == 0) L.pref[0] = 0;
+        __syncthreads();
+        const int total = carry;
+        for (int base = 0; base < total; base += kWave) {
+            const int idx = base + lane;
+            const bool act = idx < total;
+            int k = 0;
+            if (act) {
+                int lo = 0, hi = cn - 1;
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (L.pref[mid] <= idx) lo = mid;
+                    else hi = mid - 1;
                 }
-                ++q;
+                k = lo;
             }
-            target_update(L, d1, d2, t1x, t1y, C, ok, j, d, vtx, vty, D2 + (d - D));
+            const int el = act ? L.sel[k] : 0;
+            const int v = act ? M.pvert[el] : 0;
+            const double D = act ? G.rD[el] : 0.0;
+            const double vtx = act ? G.rtx[el] : 0.0, vty = act ? G.rty[el] : 0.0;
+            const double D2 = act ? G.rD2[el] : INFINITY;
+            const int h = act ? M.fan[M.fan_off[v] + (idx - L.pref[k])] : 0;
+            const int hn = h - h % 3 + (h % 3 + 1) % 3;
+            const HeRec Rh = he[h], Rn = he[hn];
+            Win<R> nw;
+            bool want = false;
+            double key = 0.0;
+            if (act && Rn.twin >= 0) {
+                // window across the edge opposite v: twin(next(h)) runs u2 -> u1
+                const double px = Rn.L - Rn.cx, py = -Rn.cy;
+                nw.px = (R)px;
+                nw.py = (R)py;
+                nw.b0 = R(0);
+                nw.b1 = (R)Rn.L;
+                nw.sg = (R)D;
+                nw.c = R(1);
+                nw.s = R(0);
+                nw.he = Rn.twin;
+                nw.root = el;
+                key = D + seg_dist(px, py, 0.0, Rn.L);
+                want = key < L.maxb;
+            }
+            // direct targets in face(h): straight segments inside the face
+            const int g = h / 3;
+            int q = 0, q1 = 0;
+            if (act) {
+                q = sd.fstart[g];
+                q1 = sd.fstart[g + 1];
+            }
+            const double *pv = M.V + 3 * (int64_t)v;
+            while (__ballot(q < q1)) {
+                bool ok = false;
+                int j = 0;
+                double d = 0;
+                if (q < q1) {
+                    j = sd.forder[q];
+                    if (j != src) {
+                        const double *b = sd.bary + 3 * (int64_t)j;
+                        const int32_t *Tg = M.T + 3 * (int64_t)g;
+                        double x[3] = {0, 0, 0};
+                        for (int c = 0; c < 3; ++c)
+                            for (int dd = 0; dd < 3; ++dd) x[dd] += b[c] * M.V[3 * (int64_t)Tg[c] + dd];
+                        const double dx = x[0] - pv[0], dy = x[1] - pv[1], dz = x[2] - pv[2];
+                        d = D + sqrt(dx * dx + dy * dy + dz * dz);
+                        ok = true;
+                    }
+                    ++q;
+                }
+                target_update(L, d1, d2, t1x, t1y, C, ok, j, d, vtx, vty, D2 + (d - D));
+            }
+            // the two other vertices of face(h), reached along its edges
+            const int u1 = Rh.head, u2 = Rh.opp_flags >> 1;
+            if (act) {
+                vdist_min(Dv, u1, D + Rh.L);
+                vdist_min(Dv, u2, D + Rh.Lp);
+            }
+            const int e1 = act ? M.pidx[u1] : -1;
+            groot_update(G, L, C.rc, e1 >= 0, e1, D + Rh.L, vtx, vty, D2 + Rh.L);
+            const int e2 = act ? M.pidx[u2] : -1;
+            groot_update(G, L, C.rc, e2 >= 0, e2, D + Rh.Lp, vtx, vty, D2 + Rh.Lp);
+            S.push(want, key >= T, nw, st.overflow);
         }
-        // the two other vertices of face(h), reached along its edges
-        const int u1 = Rh.head, u2 = Rh.opp_flags >> 1;
-        if (act) {
-            vdist_min(Dv, u1, D + Rh.L);
-            vdist_min(Dv, u2, D + Rh.Lp);
-        }
-        const bool ok1 = act && (M.vflag[u1] & VF_PSEUDO);
-        root_update(L.R, C.rc, ok1, u1, D + Rh.L, vtx, vty, D2 + Rh.L, st.overflow);
-        const bool ok2 = act && (M.vflag[u2] & VF_PSEUDO);
-        root_update(L.R, C.rc, ok2, u2, D + Rh.Lp, vtx, vty, D2 + Rh.Lp, st.overflow);
-        S.push(want, key >= T, nw, st.overflow);
+        __syncthreads();  // L.sel / L.pref are rewritten by the next chunk
     }
 }
 
@@ -426,6 +567,7 @@ __device__ void run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
     C.dom_rel = fp32 ? a.gp.dom_rel32 : a.gp.dom_rel;
     C.bucket = a.gp.bucket > 0.0 ? a.gp.bucket : 2.0 * M.max_edge;
     double *Dv = a.vdist + (int64_t)slot * a.vstride;
+    const GRoots G = groots(a, slot);
     RoundStack<R> S;
     S.lds = reinterpret_cast<typename RecOf<R>::T *>(stk);
     S.kL = stk_bytes / (int)sizeof(typename RecOf<R>::T);
@@ -442,10 +584,14 @@ __device__ void run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
         t1x[j] = 0.0;
         t1y[j] = 0.0;
     }
-    for (int e = lane; e < kRootCap; e += kWave) L.R.rkey[e] = -1;
+    for (int e = lane; e < M.n_pseudo; e += kWave) {
+        G.rD[e] = INFINITY;
+        G.rL[e] = INFINITY;
+        G.rD2[e] = INFINITY;
+        G.queued[e] = 0;
+    }
     if (lane == 0) {
-        L.R.rcount = 0;
-        L.R.dirty = 0;
+        L.npend = 0;
         L.unfound = n - 1;
         L.maxb = INFINITY;
     }
@@ -488,8 +634,7 @@ __device__ void run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
     {
         Win<R> w, wa, wb;
         bool want = false, wantA = false, wantB = false;
-        bool rok = false;
-        int rv = 0;
+        int rv = -1;
         double rd = 0, rtx = 0, rty = 0;
         double ka = 0, kb = 0;
         if (lane < 3) {
@@ -501,9 +646,8 @@ __device__ void run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
                 const double dx = P[k][0] - sx, dy = P[k][1] - sy;
                 rd = sqrt(dx * dx + dy * dy);
                 vdist_min(Dv, v, rd);
-                if (M.vflag[v] & VF_PSEUDO) {
-                    rok = true;
-                    rv = v;
+                rv = M.pidx[v];
+                if (rv >= 0) {
                     rtx = rd > 0 ? dx / rd : 0.0;
                     rty = rd > 0 ? dy / rd : 0.0;
                 }
@@ -538,7 +682,7 @@ __device__ void run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
                 }
             }
         }
-        root_update(L.R, C.rc, rok, rv, rd, rtx, rty, INFINITY, overflow);
+        groot_update(G, L, C.rc, rv >= 0, rv, rd, rtx, rty, INFINITY);
         // on-edge sources: targets and third vertex of the face across
         for (int k = 0; k < 3; ++k) {
             const bool on = sb[(k + 2) % 3] <= 0.0 && he[3 * fs + k].twin >= 0;
@@ -578,8 +722,8 @@ __device__ void run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
             const double d = sqrt(dx * dx + dy * dy);
             const int opp = Rt.opp_flags >> 1;
             if (lane == 0) vdist_min(Dv, opp, d);
-            root_update(L.R, C.rc, lane == 0 && (Rt.opp_flags & 1), opp, d, (c * dx - s * dy) / d,
-                        (s * dx + c * dy) / d, INFINITY, overflow);
+            const int eo = lane == 0 ? M.pidx[opp] : -1;
+            groot_update(G, L, C.rc, eo >= 0, eo, d, (c * dx - s * dy) / d, (s * dx + c * dy) / d, INFINITY);
         }
         S.push(want, false, w, overflow);
         S.push(wantA, ka >= T, wa, overflow);
@@ -596,12 +740,12 @@ __device__ void run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
         if (overflow) break;
         depth = max(depth, S.lsp + S.gsp + S.dsp);
         bool busy = S.refill(have, w);
-        if (!busy && L.R.dirty) {
-            launch_roots(a, sd, L, d1, d2, t1x, t1y, Dv, C, S, T, src, st);
+        if (!busy && L.npend > 0) {
+            launch_roots(a, sd, L, G, d1, d2, t1x, t1y, Dv, C, S, T, src, st);
             busy = S.refill(have, w);
         }
         if (!busy) {
-            if (S.dsp == 0 && !L.R.dirty) break;
+            if (S.dsp == 0 && L.npend == 0) break;
             // next round; once every target is reached, bound the keys
             S.next_round();
             T += C.bucket;
@@ -621,7 +765,7 @@ __device__ void run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
             break;
         }
         // stale: from an earlier launch of its root, or a new launch is due
-        if (have && w.root >= 0 && is_stale(L.R, w, C.rc)) {
+        if (have && w.root >= 0 && gstale(G, w, C.rc)) {
             have = false;
             ++st.stale;
         }
@@ -672,7 +816,7 @@ __device__ void run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
                 }
             }
         }
-        query_face(sd, L, d1, d2, t1x, t1y, C, have, src, f, k, H, w);
+        query_face(sd, L, G, d1, d2, t1x, t1y, C, have, src, f, k, H, w);
         // third vertex as a bend vertex
         {
             bool ok = have && H.pseudo && cin;
@@ -684,12 +828,13 @@ __device__ void run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
                     tx = (double)(w.c * (dx / l) - w.s * (dy / l));
                     ty = (double)(w.s * (dx / l) + w.c * (dy / l));
                 } else {
-                    tx = L.R.rtx[w.root];
-                    ty = L.R.rty[w.root];
-                    alt = L.R.rD2[w.root] + (dcv - (double)w.sg);
+                    tx = G.rtx[w.root];
+                    ty = G.rty[w.root];
+                    alt = G.rD2[w.root] + (dcv - (double)w.sg);
                 }
             }
-            root_update(L.R, C.rc, ok, have ? H.opp : 0, dcv, tx, ty, alt, overflow);
+            const int eo = ok ? M.pidx[H.opp] : -1;
+            groot_update(G, L, C.rc, ok, eo, dcv, tx, ty, alt);
         }
         // children, trimmed against the vertex paths and bounded by maxb
         Win<R> cl, cr;
@@ -780,6 +925,8 @@ __device__ void run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
     __syncthreads();
 }
 
+static_assert(sizeof(AllLds) + 16384 <= kAllLdsFixed, "all-pairs LDS besides the target table");
+
 template <bool kMixed, int kStk>
 __global__ __launch_bounds__(kWave) void k_geodesic_all(AllArgs a) {
     __shared__ AllLds L;
@@ -857,8 +1004,8 @@ void launch_variant(int kb, int nslots, size_t dyn, const AllArgs &a, hipStream_
 }  // namespace
 
 hipError_t launch_geodesic_all(const SurfDesc *desc, const BatchIdx &bi, const GeoParams &gp, const GeoShape &shape,
-                               char *stack_mem, double *vdist, int64_t vstride, int tcap, int32_t *work_ctr,
-                               Counters *ctr, bool fp32, hipStream_t s) {
+                               char *stack_mem, double *vdist, int64_t vstride, char *roots, int64_t rstride,
+                               int rcap, int tcap, int32_t *work_ctr, Counters *ctr, bool fp32, hipStream_t s) {
     AllArgs a;
     a.sd = desc;
     a.bi = bi;
@@ -866,6 +1013,9 @@ hipError_t launch_geodesic_all(const SurfDesc *desc, const BatchIdx &bi, const G
     a.stack = stack_mem;
     a.vdist = vdist;
     a.vstride = vstride;
+    a.roots = roots;
+    a.rstride = rstride;
+    a.rcap = rcap;
     a.work = work_ctr;
     a.ctr = ctr;
     a.tcap = tcap;

@@ -148,6 +148,7 @@ __device__ inline void target_update(Lds &L, const Ctx &C, bool ok, int slot, do
             }
             L.d2[slot] = fmin(L.d2[slot], alt);
         }
+        lane_step_barrier();
         m &= m - 1;
     }
 }

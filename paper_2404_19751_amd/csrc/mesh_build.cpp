@@ -142,6 +142,15 @@ std::string build_host_mesh(int nv, const double *xyz, int nf, const int32_t *tr
         M.vflag[v] = fl;
         if (fl & VF_PSEUDO) M.n_pseudo++;
     }
+    // dense numbering of the pseudo-sources (the whole-mesh kernel's bend-vertex table)
+    M.pidx.assign(nv, -1);
+    M.pvert.clear();
+    for (int v = 0; v < nv; ++v)
+        if (M.vflag[v] & VF_PSEUDO) {
+            M.pidx[v] = (int32_t)M.pvert.size();
+            M.pvert.push_back(v);
+        }
+    if (M.pvert.empty()) M.pvert.push_back(-1);
 
     // unfolding records
     M.he.resize(ne);

@@ -13,8 +13,7 @@ namespace gsim {
 namespace wnd {
 
 constexpr int kWave = 64;
-// bend-vertex table: 255 slots so that slot + 1 fits the 8 bits the FP32
-// stack record keeps for it
+// slots of the cutoff kernel's bend-vertex hash table in LDS
 constexpr int kRootCap = 255;
 
 template <typename R>
@@ -23,14 +22,16 @@ struct Win {
     int he, root;
 };
 
-// stack records: 64 bytes (FP64) / 32 bytes (FP32, he and root packed)
+// stack records: 64 bytes (FP64) / 32 bytes (FP32). A window of a bend
+// vertex takes its tangent from the vertex, not from its own frame rotation
+// (c, s), so the FP32 record keeps the bend vertex in the slot of c instead.
 struct Rec64 {
     double v[7];
     int32_t he, root;
 };
 struct Rec32 {
-    float v[7];
-    uint32_t hr;  // (he << 8) | (root + 1), root + 1 in [0, kRootCap]
+    float v[7];   // px, py, b0, b1, sg, then c, s (source windows) or the root's bits, 0
+    uint32_t hr;  // he | (1 << 31) for a window of a bend vertex
 };
 static_assert(sizeof(Rec64) == 64 && sizeof(Rec32) == 32, "stack record sizes");
 template <typename R>
@@ -55,13 +56,19 @@ __device__ inline void load_rec(const Rec64 &q, Win<double> &w) {
     w.root = q.root;
 }
 __device__ inline void store_rec(Rec32 &q, const Win<float> &w) {
-    q.v[0] = w.px; q.v[1] = w.py; q.v[2] = w.b0; q.v[3] = w.b1; q.v[4] = w.sg; q.v[5] = w.c; q.v[6] = w.s;
-    q.hr = ((uint32_t)w.he << 8) | (uint32_t)(w.root + 1);
+    const bool rooted = w.root >= 0;
+    q.v[0] = w.px; q.v[1] = w.py; q.v[2] = w.b0; q.v[3] = w.b1; q.v[4] = w.sg;
+    q.v[5] = rooted ? __int_as_float(w.root) : w.c;
+    q.v[6] = rooted ? 0.0f : w.s;
+    q.hr = (uint32_t)w.he | (rooted ? 0x80000000u : 0u);
 }
 __device__ inline void load_rec(const Rec32 &q, Win<float> &w) {
-    w.px = q.v[0]; w.py = q.v[1]; w.b0 = q.v[2]; w.b1 = q.v[3]; w.sg = q.v[4]; w.c = q.v[5]; w.s = q.v[6];
-    w.he = (int)(q.hr >> 8);
-    w.root = (int)(q.hr & 255u) - 1;
+    const bool rooted = (q.hr >> 31) != 0;
+    w.px = q.v[0]; w.py = q.v[1]; w.b0 = q.v[2]; w.b1 = q.v[3]; w.sg = q.v[4];
+    w.c = rooted ? 1.0f : q.v[5];
+    w.s = rooted ? 0.0f : q.v[6];
+    w.he = (int)(q.hr & 0x7fffffffu);
+    w.root = rooted ? __float_as_int(q.v[5]) : -1;
 }
 
 // half-edge record in the working precision
@@ -95,6 +102,11 @@ struct Roots {
 };
 
 __device__ inline int lane_id() { return threadIdx.x; }
+// Ends one step of a loop that applies the lanes' updates to a shared table
+// one lane at a time: the next lane's loads must see this lane's stores. To
+// the compiler the lanes are separate threads, so without this it may keep a
+// table value in a register from one step to the next.
+__device__ inline void lane_step_barrier() { __asm__ __volatile__("" ::: "memory"); }
 __device__ inline uint64_t lanemask_lt() { return (1ull << threadIdx.x) - 1ull; }
 __device__ inline int hash_vert(int v) { return (int)((((uint32_t)v * 2246822519u) >> 16) % kRootCap); }
 
@@ -187,6 +199,7 @@ __device__ inline void root_update(Roots &L, const RootCfg &rc, bool ok, int v, 
                 if (L.rD[e] < L.rL[e] * rc.keep) L.dirty = 1;
             }
         }
+        lane_step_barrier();
         m &= m - 1;
     }
 }

@@ -63,21 +63,36 @@ def test_allpairs_small(orc, name, mk, n, prec):
         ctx.close()
 
 
-def test_allpairs_bend_vertex_limit():
-    """Whole-mesh propagation on a surface with more saddle vertices than a
-    source's bend-vertex table holds is reported as a limit, not returned
-    incomplete."""
-    from paper_2404_19751_amd import gsim
-    m = W.bumpy_sphere(3, 0.15)
-    f, b = W.random_particles(m.nf, 20, 29)
-    ctx = _ctx("fp64")
+MANY_SADDLES = [
+    ("bumpy_l3", lambda: W.bumpy_sphere(3, 0.15), 40),
+    ("torus_a3", lambda: W.torus(3.0, 1.0, 48, 16), 40),
+]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("name,mk,n", MANY_SADDLES)
+def test_allpairs_many_bend_vertices(orc, name, mk, n, prec):
+    """Whole-mesh propagation on surfaces with hundreds of saddle vertices
+    (every one of them a bend vertex that a source's front reaches): all
+    pairs against the oracle."""
+    m = mk()
+    f, b = W.random_particles(m.nf, n, 29)
+    ctx = _ctx(prec)
     try:
         mid = ctx.mesh_upload(m.V, m.T)
-        assert ctx.mesh_info(mid)["n_pseudo_sources"] > 254
+        npseudo = ctx.mesh_info(mid)["n_pseudo_sources"]
+        assert npseudo > 255
         ctx.particles_set(mid, f, b)
-        with pytest.raises(gsim.GsimError) as e:
-            ctx.geodesic_pairs(mid, math.inf)
-        assert e.value.status == gsim.E_LIMIT
+        log(f"[gpu-all] {name} {prec}: all pairs of {n}, {npseudo} bend vertices")
+        g = ctx.geodesic_pairs(mid, math.inf)
+        cnt = ctx.counters()
+        assert cnt["limited"] == 0, cnt
+        o = orc.geodesic_pairs(orc.OracleMesh(m.V, m.T), f, b, math.inf)
+        if prec == "fp64":
+            err = compare_pairs(g, o, W.mean_edge_length(m), label=name)
+        else:
+            err, _ = compare32(g, o, W.mean_edge_length(m), name)
+        log(f"[gpu-all] {name} {prec}: err {err:.2e} windows {cnt['windows']} launches {cnt['launches']}")
     finally:
         ctx.close()
 
