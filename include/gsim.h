@@ -211,6 +211,8 @@ gsim_status gsim_step_batched(gsim_ctx *ctx, int32_t nmesh, const int32_t *mesh_
  *   "tie_rel"       relative gap under which a pair is flagged as a tie
  *   "tie_dir"       tangents closer than this angle (rad) count as one direction
  *   "guard_rel"     FP32-mixed: relative band around the cutoff recomputed in FP64
+ *   "slack32"       FP32-mixed: windows are kept up to this fraction beyond the
+ *                   cutoff (1e-6 .. 1e-2; the larger of it and guard_rel is used)
  *   "root_rel32"    FP32-mixed: a bend vertex is re-launched only when its distance
  *                   improves by more than this fraction (<= 1e-4; distances may then
  *                   exceed the exact value by this fraction)
@@ -219,7 +221,10 @@ gsim_status gsim_step_batched(gsim_ctx *ctx, int32_t nmesh, const int32_t *mesh_
  *   "grab"          consecutive sources a wavefront claims at a time (1 .. 64)
  *   "update_block"  workgroup size of the fused update kernel: 64, 128 or 256
  *   "graph_steps"   steps captured per HIP graph in step calls (0 = no graphs)
- *   All-pairs passes (no cutoff):
+ *   "whole_mesh"    1: finite-cutoff passes also run on the whole-mesh kernel
+ *                   below (windows pruned at the cutoff; no limit on candidates or
+ *                   bend vertices per source; at most 4096 particles per surface)
+ *   Whole-mesh passes (no cutoff, or "whole_mesh" = 1):
  *   "stack_cap_all" window records per resident wavefront (1024 .. 4M)
  *   "max_windows_all" per-source work limit
  *   "bucket"        key width of one processing round (0 = two max edge lengths)

@@ -94,6 +94,7 @@ struct gsim_ctx {
     double stack_budget = 16e9;   // bytes of window stacks an all-pairs pass may hold
     int max_windows_all = 0;      // per-source window limit in all-pairs passes
     int cus = 256;
+    bool whole_mesh = false;  // finite-cutoff passes on the whole-mesh kernel
     int max_lds = 65536;  // LDS bytes one workgroup may use
     // graphs
     int graph_steps = 50;  // steps captured per graph (0: no graphs)
@@ -217,8 +218,10 @@ gsim_status end_call(gsim_ctx *c) {
         return fail(c, GSIM_E_LIMIT,
                     std::to_string(over + (long long)c->last.limited) +
                         " source(s) exceeded a per-source limit (more than " + std::to_string(kCandCap) +
-                        " candidate targets within the cutoff, more than 254 bend vertices, window stack or window "
-                        "count); the results of this call are incomplete");
+                        " candidate targets within the cutoff, more than 254 bend vertices within it, window stack "
+                        "or window count); the results of this call are incomplete. Passes of the whole-mesh kernel "
+                        "(the \"whole_mesh\" knob, up to " + std::to_string(kAllPairsMax) +
+                        " particles) have neither of the first two limits");
     return GSIM_OK;
 }
 
@@ -254,12 +257,11 @@ gsim_status prepare_surface(gsim_ctx *c, const Member &mb, bool small, int src_b
     const int n = ms->n;
     const DevMesh &m = ms->dm;
     if (n <= 0) return fail(c, GSIM_E_STATE, "no particles on this mesh");
-    const bool all = !finite_cutoff(mb.cutoff);
+    const bool fin = finite_cutoff(mb.cutoff);
+    const bool all = !fin || c->whole_mesh;  // rows of every target, whole-mesh kernel
     if (all && n > kAllPairsMax)
-        return fail(c, GSIM_E_LIMIT, "all-pairs mode holds at most " + std::to_string(kAllPairsMax) +
-                                         " particles per surface");
-    if (c->prec == GSIM_FP32_MIXED && 3 * (int64_t)m.nf >= (int64_t(1) << 24))
-        return fail(c, GSIM_E_LIMIT, "FP32-mixed mode packs half-edge ids in 24 bits: mesh too large");
+        return fail(c, GSIM_E_LIMIT, "whole-mesh passes (no cutoff, or the \"whole_mesh\" knob) hold at most " +
+                                         std::to_string(kAllPairsMax) + " particles per surface");
     std::memset(&d, 0, sizeof(d));
     if (all) {
         d.dims[0] = d.dims[1] = d.dims[2] = 1;
@@ -317,8 +319,8 @@ gsim_status prepare_surface(gsim_ctx *c, const Member &mb, bool small, int src_b
     d.cdist = P<double>(ms->cdist);
     d.ctan = P<double>(ms->ctan);
     d.cflags = P<uint8_t>(ms->cflags);
-    d.cutoff = all ? INFINITY : mb.cutoff;
-    d.cut2 = all ? INFINITY : mb.cutoff * mb.cutoff * (1.0 + 1e-12);
+    d.cutoff = fin ? mb.cutoff : INFINITY;
+    d.cut2 = fin ? mb.cutoff * mb.cutoff * (1.0 + 1e-12) : INFINITY;
     if (mb.pot) {
         d.pkind = mb.pot->kind;
         d.pk = mb.pot->k;
@@ -382,9 +384,9 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
     for (int i = 0; i < ns; ++i)
         for (int j = 0; j < i; ++j)
             if (B.mem[i].ms == B.mem[j].ms) return fail(c, GSIM_E_ARG, "a mesh appears twice in the batch");
-    B.all = !finite_cutoff(B.mem[0].cutoff);
+    B.all = !finite_cutoff(B.mem[0].cutoff) || c->whole_mesh;
     for (int i = 1; i < ns; ++i)
-        if (!finite_cutoff(B.mem[i].cutoff) != B.all)
+        if ((!finite_cutoff(B.mem[i].cutoff) || c->whole_mesh) != B.all)
             return fail(c, GSIM_E_ARG, "a batch mixes cutoff and all-pairs surfaces");
     // a single surface may use the multi-kernel binning for a fine grid
     B.small = true;
@@ -1229,6 +1231,7 @@ gsim_status gsim_tune_set(gsim_ctx *c, const char *name, double value) {
     else if (k == "bucket" && value >= 0.0) c->gp.bucket = value;
     else if (k == "dom_rel" && value >= 0.0) c->gp.dom_rel = value;
     else if (k == "dom_rel32" && value >= 0.0) c->gp.dom_rel32 = value;
+    else if (k == "whole_mesh" && (value == 0.0 || value == 1.0)) c->whole_mesh = value != 0.0;
     else return fail(c, GSIM_E_ARG, "unknown tuning knob or value out of range: " + k);
     drop_graphs(c);
     return GSIM_OK;

@@ -181,11 +181,12 @@ __device__ inline bool gstale(const GRoots &G, const Win<R> &w, const RootCfg &r
 // Per-source constants.
 struct ACtx {
     double tol, tie_rel, tie_dir, root_keep, dom_rel, bucket;
+    double cutoff;  // infinity for all pairs
     RootCfg rc;
 };
 
 struct SrcStats {
-    unsigned long long windows, launches, stale;
+    unsigned long long windows, launches, stale, guards;
     int pruned, depth;
     bool overflow;
 };
@@ -550,9 +551,16 @@ __device__ void launch_roots(const AllArgs &a, const SurfDesc &sd, AllLds &L, co
     }
 }
 
+// One source's whole-mesh propagation and its row of results. With a
+// finite cutoff, windows whose key reaches it are dropped (in FP32 a little
+// beyond it, by the acceptance slack) and the row keeps every target; the
+// pairs at or beyond the cutoff are left out downstream. Returns whether an
+// FP32 result lies within the guard band around the cutoff (the caller then
+// recomputes the source in FP64; `guard` marks that recompute).
 template <typename R>
-__device__ void run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double *d1, double *d2, double *t1x,
-                        double *t1y, unsigned char *stk, int stk_bytes, int src, int slot, SrcStats &st) {
+__device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double *d1, double *d2, double *t1x,
+                        double *t1y, unsigned char *stk, int stk_bytes, int src, int slot, bool guard,
+                        SrcStats &st) {
     const int lane = lane_id();
     const bool fp32 = sizeof(R) == 4;
     const int n = sd.n;
@@ -566,6 +574,7 @@ __device__ void run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
     C.rc = {C.root_keep, C.tie_dir, C.tie_rel};
     C.dom_rel = fp32 ? a.gp.dom_rel32 : a.gp.dom_rel;
     C.bucket = a.gp.bucket > 0.0 ? a.gp.bucket : 2.0 * M.max_edge;
+    C.cutoff = sd.cutoff;
     double *Dv = a.vdist + (int64_t)slot * a.vstride;
     const GRoots G = groots(a, slot);
     RoundStack<R> S;
@@ -593,7 +602,8 @@ __device__ void run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
     if (lane == 0) {
         L.npend = 0;
         L.unfound = n - 1;
-        L.maxb = INFINITY;
+        L.maxb = C.cutoff < INFINITY ? C.cutoff * (fp32 ? 1.0 + fmax(a.gp.slack32, a.gp.guard_rel) : 1.0)
+                                     : INFINITY;
     }
     __threadfence_block();
     __syncthreads();
@@ -754,7 +764,7 @@ __device__ void run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
                 for (int j = lane; j < n; j += kWave)
                     if (j != src) mx = fmax(mx, d1[j]);
                 for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
-                if (lane == 0) L.maxb = mx * (1.0 + C.tie_rel) + 1e-12 * mx;
+                if (lane == 0) L.maxb = fmin(L.maxb, mx * (1.0 + C.tie_rel) + 1e-12 * mx);
             }
             __syncthreads();
             continue;
@@ -902,14 +912,16 @@ __device__ void run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
                            nn[0] * ex3[1] - nn[1] * ex3[0]};
     const bool ovf = __ballot(overflow) != 0;
     const int64_t c0 = (int64_t)src * sd.cap;
+    bool near_cut = false;
     for (int j = lane; j < n; j += kWave) {
         const int64_t o = c0 + j;
         double d = d1[j];
-        uint8_t fl = 0;
+        uint8_t fl = guard ? GSIM_PAIR_GUARD_BIT : 0;
         if (j == src) d = INFINITY;
         else if (ovf) d = NAN;
         if (j != src && d2[j] - d <= C.tie_rel * d) fl |= GSIM_PAIR_TIE_BIT;
         if (d == 0.0) fl |= GSIM_PAIR_ZERO_BIT;
+        near_cut |= C.cutoff < INFINITY && fabs(d - C.cutoff) <= a.gp.guard_rel * C.cutoff;
         sd.cdist[o] = d;
         sd.cflags[o] = fl;
         for (int qd = 0; qd < 3; ++qd) sd.ctan[3 * o + qd] = t1x[j] * ex3[qd] + t1y[j] * ey3[qd];
@@ -923,6 +935,7 @@ __device__ void run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
     st.overflow |= ovf;
     st.depth = max(st.depth, depth);
     __syncthreads();
+    return fp32 && !ovf && __ballot(near_cut) != 0;
 }
 
 static_assert(sizeof(AllLds) + 16384 <= kAllLdsFixed, "all-pairs LDS besides the target table");
@@ -937,7 +950,7 @@ __global__ __launch_bounds__(kWave) void k_geodesic_all(AllArgs a) {
     const int total = a.bi.begin[a.bi.nsurf];
     int chunk = blockIdx.x % kChunks, chunks_left = kChunks;
     SrcStats st;
-    st.windows = st.launches = st.stale = 0;
+    st.windows = st.launches = st.stale = st.guards = 0;
     st.pruned = 0;
     st.depth = 0;
     st.overflow = false;
@@ -968,8 +981,14 @@ __global__ __launch_bounds__(kWave) void k_geodesic_all(AllArgs a) {
         const int src = idx - a.bi.begin[si];
         if (lane == 0) sd.cand_cnt[src] = sd.n;
         st.overflow = false;
-        if (kMixed) run_all<float>(a, sd, L, d1, d2, t1x, t1y, stk, kStk, src, blockIdx.x, st);
-        else run_all<double>(a, sd, L, d1, d2, t1x, t1y, stk, kStk, src, blockIdx.x, st);
+        bool again = !kMixed;
+        if (kMixed) again = run_all<float>(a, sd, L, d1, d2, t1x, t1y, stk, kStk, src, blockIdx.x, false, st);
+        if (again) {
+            // FP64 (the plain path, or the recompute of an FP32 source whose
+            // results come too close to the cutoff to decide in FP32)
+            run_all<double>(a, sd, L, d1, d2, t1x, t1y, stk, kStk, src, blockIdx.x, kMixed, st);
+            st.guards += kMixed ? 1 : 0;
+        }
         if (st.overflow) ++c_limited;
     }
     unsigned long long pr = (unsigned long long)st.pruned, sl = st.stale;
@@ -982,6 +1001,7 @@ __global__ __launch_bounds__(kWave) void k_geodesic_all(AllArgs a) {
         atomicAdd(&a.ctr->pruned, pr);
         atomicAdd(&a.ctr->launches, st.launches);
         atomicAdd(&a.ctr->stale, sl);
+        atomicAdd(&a.ctr->guards, st.guards);
         atomicAdd(&a.ctr->limited, c_limited);
         atomicMax(&a.ctr->max_depth, (unsigned long long)st.depth);
     }
