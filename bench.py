@@ -220,15 +220,89 @@ def bench_torus_nve(args, gsim, W):
             "results": out}
 
 
+def bench_vsweep(args, gsim, W):
+    """Cost per velocity-Verlet (NVE) step of N = 100 particles against the
+    number of mesh vertices V at fixed span, interaction range span / 10
+    (the paper's Sec. 4 mesh-size study): a sphere and tori of aspect ratio 3
+    and 20. "submesh": windows pruned at the range (the cutoff kernel, or the
+    whole-mesh kernel with the cutoff where a source's patch exceeds the
+    cutoff kernel's limits); "full": every source's windows cover the whole
+    mesh (no cutoff; the potential still vanishes beyond the range). FP64,
+    steps replayed from HIP graphs. The exponent is the least-squares slope of
+    log(ms/step) against log V; the full-mesh runs stop at a surface's first
+    level whose step takes longer than a few seconds."""
+    import math
+    out = {}
+    for surf, spec in W.VSWEEP.items():
+        rows = []
+        full_open = True
+        for lv in spec["levels"]:
+            w = W.workload(f"vsweep_{surf}_{lv}")
+            nv = int(len(w.mesh.V))
+            for mode in ("submesh", "full"):
+                if mode == "full" and not full_open:
+                    continue
+                cut = w.potential["cutoff"] if mode == "submesh" else math.inf
+                pot = gsim.potential("harmonic", 1.0, w.potential["sigma"], cut)
+                ig = gsim.integrator("verlet", w.integrator["dt"])
+                kernel = "cutoff" if mode == "submesh" else "whole_mesh"
+                for attempt in (0, 1):
+                    ctx = gsim.Context(0, "fp64")
+                    if attempt:
+                        ctx.tune(whole_mesh=1)
+                        kernel = "whole_mesh"
+                    mid = ctx.mesh_upload(w.mesh.V, w.mesh.T)
+                    ctx.particles_set(mid, w.face, w.bary)
+                    try:
+                        t0 = time.perf_counter()
+                        ctx.step(mid, pot, ig, 1)
+                        ctx.synchronize()
+                        t1 = time.perf_counter() - t0
+                        break
+                    except gsim.GsimError as e:
+                        ctx.close()
+                        if e.status != gsim.E_LIMIT or attempt:
+                            raise
+                k = max(2, min(10, int(2.0 / max(t1, 1e-4))))
+                ctx.tune(graph_steps=k)
+                ctx.step(mid, pot, ig, k)  # captures the graph
+                ctx.synchronize()
+                c0 = ctx.counters()
+                t0 = time.perf_counter()
+                ctx.step(mid, pot, ig, k)
+                ctx.synchronize()
+                dt = time.perf_counter() - t0
+                c1 = ctx.counters()
+                ctx.close()
+                ms = 1e3 * dt / k
+                rows.append({"level": lv, "V": nv, "faces": int(w.mesh.nf), "mode": mode, "kernel": kernel,
+                             "ms_per_step": ms, "steps": k,
+                             "pairs_per_step": (c1["cum_pairs"] - c0["cum_pairs"]) / k,
+                             "windows_per_step": (c1["cum_windows"] - c0["cum_windows"]) / k})
+                print(f"[vsweep] {surf} V={nv} {mode} ({kernel}): {ms:.3f} ms/step", file=sys.stderr, flush=True)
+                if mode == "full" and ms > 1500.0:
+                    full_open = False
+        fits = {}
+        for mode in ("submesh", "full"):
+            pts = [(r["V"], r["ms_per_step"]) for r in rows if r["mode"] == mode]
+            if len(pts) >= 3:
+                fits[mode] = float(np.polyfit(np.log([p[0] for p in pts]), np.log([p[1] for p in pts]), 1)[0])
+        out[surf] = {"span": spec["span"], "range": spec["span"] / 10.0, "runs": rows, "exponent": fits}
+    return {"workload": "fixed-N mesh-size sweep: N=100, velocity Verlet NVE, harmonic range span/10, sphere and "
+                        "tori of aspect 3 and 20 refined at fixed span", "data": "synthetic", "precision": "fp64",
+            "results": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32"])
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "torus_nve"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "torus_nve", "vsweep"],
                     help="c2: bumpy sphere N=1000 (the default line); c3: 16 surfaces batched; "
-                         "c4: open height field N=20000, Brownian; torus_nve: NVE cost vs N on the benchmark torus")
+                         "c4: open height field N=20000, Brownian; torus_nve: NVE cost vs N on the benchmark torus; "
+                         "vsweep: NVE cost vs mesh size at N=100, full mesh and submeshed")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
@@ -257,6 +331,9 @@ def main():
         return
     if args.workload == "torus_nve":
         print(json.dumps(bench_torus_nve(args, gsim, W)), flush=True)
+        return
+    if args.workload == "vsweep":
+        print(json.dumps(bench_vsweep(args, gsim, W)), flush=True)
         return
     w = W.workload(args.workload)
     pot = gsim.potential("harmonic", w.potential["k"], w.potential["sigma"], w.potential["cutoff"])

@@ -394,6 +394,30 @@ def benchmark_torus() -> Mesh:
     return torus(3.0, 1.0, 83, 28)
 
 
+# Mesh-size sweep at fixed N (the paper's Sec. 4 study of cost against the
+# number of vertices): each surface refined at fixed span, the interaction
+# range one tenth of the span. Regular (u, v) tori with the quad aspect
+# matched at the tube's centre line stand in for isotropic remeshing.
+VSWEEP = {
+    "sphere": dict(span=2.0, levels=[2, 3, 4, 5, 6]),
+    "torus3": dict(span=8.0, levels=[12, 17, 24, 34, 48, 68, 96]),
+    "torus20": dict(span=42.0, levels=[6, 8, 12, 17, 24, 34]),
+}
+
+
+def vsweep_mesh(surface: str, level: int) -> Mesh:
+    """sphere: icosphere of radius 1 at `level`; torus3 / torus20: tube
+    radius 1 around a circle of radius 3 / 20 with `level` quads around the
+    tube and 3 / 20 times as many around the ring."""
+    if surface == "sphere":
+        return icosphere(level)
+    if surface == "torus3":
+        return torus(3.0, 1.0, 3 * level, level)
+    if surface == "torus20":
+        return torus(20.0, 1.0, 20 * level, level)
+    raise KeyError(surface)
+
+
 def packing_count(m: Mesh, sigma: float, phi: float = 0.3, lo: int = 200, hi: int = 4000) -> int:
     """Particles of diameter sigma at packing fraction phi, clamped to [lo, hi]."""
     n = int(round(phi * surface_area(m) / (np.pi * (0.5 * sigma) ** 2)))
@@ -418,6 +442,9 @@ def workload(name: str) -> "Workload | list[Workload]":
     torus_nve_<N>_<sigma>  the aspect-3 benchmark torus (4648 faces), N
         particles (seed 7), harmonic repulsion of range sigma, velocity
         Verlet (NVE) dt = 0.005, from rest.
+    vsweep_<surface>_<level>  a mesh of the fixed-N sweep (VSWEEP), N = 100
+        (seed 11), harmonic repulsion of range span / 10 with that cutoff,
+        velocity Verlet dt = range / 200, from rest.
     """
     if name == "c1":
         m = icosphere(3)
@@ -455,6 +482,13 @@ def workload(name: str) -> "Workload | list[Workload]":
         f, b = random_particles(m.nf, n, 7)
         return Workload(name, m, f, b, dict(kind="harmonic", k=1.0, sigma=sig, cutoff=sig),
                         dict(kind="verlet", dt=0.005), 100, mean_edge_length(m))
+    if name.startswith("vsweep_"):
+        _, surf, lv = name.split("_")
+        m = vsweep_mesh(surf, int(lv))
+        rng = VSWEEP[surf]["span"] / 10.0
+        f, b = random_particles(m.nf, 100, 11)
+        return Workload(name, m, f, b, dict(kind="harmonic", k=1.0, sigma=rng, cutoff=rng),
+                        dict(kind="verlet", dt=rng / 200.0), 10, mean_edge_length(m))
     if name in ("c5a", "c5b"):
         m = icosphere(6) if name == "c5a" else ellipsoid(6)
         f, b = random_particles(m.nf, 2000, 4 if name == "c5a" else 5)
