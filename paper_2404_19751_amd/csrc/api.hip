@@ -95,6 +95,10 @@ struct gsim_ctx {
     int max_windows_all = 0;      // per-source window limit in all-pairs passes
     int cus = 256;
     bool whole_mesh = false;  // finite-cutoff passes on the whole-mesh kernel
+    // layout the bend-vertex tables were last emptied for
+    void *roots_p = nullptr;
+    int64_t roots_stride = 0;
+    int32_t roots_rcap = 0, roots_slots = 0;
     int max_lds = 65536;  // LDS bytes one workgroup may use
     // graphs
     int graph_steps = 50;  // steps captured per graph (0: no graphs)
@@ -358,7 +362,7 @@ struct Batch {
     bool all = false;     // all-pairs surfaces (no cutoff)
     int tcap = 0;         // all-pairs target-table capacity
     int64_t vstride = 0;  // all-pairs vertex-table stride
-    int64_t rstride = 0;  // all-pairs bend-vertex table bytes per wavefront
+    int64_t rstride = 0;  // bend-vertex table bytes per wavefront
     int32_t rcap = 0;     // its capacity (bend vertices)
     bool small = true;  // every surface bins in one workgroup
     int nslots = 0;
@@ -420,7 +424,7 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
         B.vstride = std::max<int64_t>(B.vstride, B.mem[i].ms->dm.nv);
         B.rcap = std::max(B.rcap, B.mem[i].ms->dm.n_pseudo);
     }
-    B.rstride = all_roots_bytes(B.rcap);
+    B.rstride = bend_table_bytes(B.rcap);
     B.fire_blk.begin[ns] = nblk;
     if (B.any_fire) HIPCHK(c, ensure(c->partials, sizeof(double) * 3 * (size_t)std::max(nblk, 1)));
     if (c->profile_sources && ns == 1) {
@@ -447,14 +451,28 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
         const int64_t fit = (int64_t)(c->stack_budget / per_slot);
         B.nslots = (int)std::max<int64_t>(1, std::min<int64_t>(B.nslots, fit));
     }
+    {
+        // the bend-vertex tables of the resident wavefronts stay within a budget too
+        const int64_t fit = (int64_t)(c->stack_budget / (double)std::max<int64_t>(B.rstride, 1));
+        B.nslots = (int)std::max<int64_t>(1, std::min<int64_t>(B.nslots, fit));
+    }
     B.shape.lds_stack_kb = c->lds_stack_kb;
     B.shape.nslots = B.nslots;
     B.shape.grab = c->grab;
     const int cap_rec = B.all ? c->stack_cap_all : c->gp.stack_cap;
     HIPCHK(c, ensure(c->stack, (size_t)std::max(B.nslots, 1) * cap_rec * 64));
-    if (B.all) {
-        HIPCHK(c, ensure(c->vdist, sizeof(double) * (size_t)std::max(B.nslots, 1) * B.vstride));
-        HIPCHK(c, ensure(c->roots, (size_t)std::max(B.nslots, 1) * B.rstride));
+    if (B.all) HIPCHK(c, ensure(c->vdist, sizeof(double) * (size_t)std::max(B.nslots, 1) * B.vstride));
+    // bend-vertex tables: emptied once here, left empty by the kernels
+    const int nsl = std::max(B.nslots, 1);
+    HIPCHK(c, ensure(c->roots, (size_t)nsl * B.rstride));
+    if (c->roots.p != c->roots_p || B.rstride != c->roots_stride || B.rcap != c->roots_rcap ||
+        nsl > c->roots_slots) {
+        if (c->capturing) return fail(c, GSIM_E_STATE, "bend-vertex tables change during graph capture");
+        HIPCHK(c, launch_bend_init(P<char>(c->roots), nsl, B.rstride, B.rcap, c->stream));
+        c->roots_p = c->roots.p;
+        c->roots_stride = B.rstride;
+        c->roots_rcap = B.rcap;
+        c->roots_slots = nsl;
     }
     return upload_descs(c, B.desc);
 }
@@ -517,7 +535,8 @@ gsim_status geodesic_pass(gsim_ctx *c, Batch &B, bool advance) {
     if (!(gp.launch_delta > 0.0)) gp.launch_delta = 0.5 * B.mem[0].ms->dm.mean_edge;
     {
         Stage st(c, "geodesic");
-        HIPCHK(c, launch_geodesic(desc_dev(c), B.bi, gp, B.shape, P<char>(c->stack), P<int32_t>(c->work),
+        HIPCHK(c, launch_geodesic(desc_dev(c), B.bi, gp, B.shape, P<char>(c->stack), P<char>(c->roots), B.rstride,
+                                  B.rcap, P<int32_t>(c->work),
                                   P<Counters>(c->ctr), c->prec == GSIM_FP32_MIXED, s));
     }
     c->passes++;
@@ -595,8 +614,11 @@ std::string graph_key(gsim_ctx *c, const Batch &B, int steps) {
     put(&B.small, sizeof(B.small));
     put(&c->update_block, sizeof(int));
     put(&steps, sizeof(int));
-    void *ptrs[5] = {c->stack.p, c->work.p, c->ctr.p, c->desc.p, c->scan_scratch.p};
+    void *ptrs[8] = {c->stack.p, c->work.p, c->ctr.p, c->desc.p, c->scan_scratch.p, c->vdist.p, c->roots.p,
+                     c->partials.p};
     put(ptrs, sizeof(ptrs));
+    const int64_t sizes[4] = {B.rstride, B.rcap, B.tcap, B.vstride};
+    put(sizes, sizeof(sizes));
     return k;
 }
 

@@ -211,18 +211,24 @@ struct GeoShape {
 // Candidate search (Euclidean prefilter) and geodesics for every source of
 // the batch, one wavefront per source. The cell lists must be current.
 hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoParams &gp, const GeoShape &shape,
-                           char *stack_mem, int32_t *work_ctr, Counters *ctr, bool fp32, hipStream_t s);
+                           char *stack_mem, char *roots, int64_t rstride, int rcap, int32_t *work_ctr, Counters *ctr,
+                           bool fp32, hipStream_t s);
 // All-pairs geodesics (no cutoff) for every source of the batch: every other
 // particle of the surface is a target. vdist: per resident wavefront a table
 // of vstride vertex distances; roots: per resident wavefront a bend-vertex
-// table of rstride bytes for rcap bend vertices (all_roots_bytes); tcap:
+// table of rstride bytes for rcap bend vertices (bend_table_bytes); tcap:
 // target-table capacity (dynamic LDS).
 hipError_t launch_geodesic_all(const SurfDesc *desc, const BatchIdx &bi, const GeoParams &gp, const GeoShape &shape,
                                char *stack_mem, double *vdist, int64_t vstride, char *roots, int64_t rstride,
                                int rcap, int tcap, int32_t *work_ctr, Counters *ctr, bool fp32, hipStream_t s);
-// Bytes of one wavefront's bend-vertex table for rcap bend vertices: five
-// doubles and three int32 each, rounded up to 256 bytes.
-inline int64_t all_roots_bytes(int rcap) { return ((int64_t)rcap * 52 + 255) / 256 * 256; }
+// Bytes of one wavefront's bend-vertex table for rcap bend vertices (both
+// geodesic kernels): five doubles and four int32 each, rounded up to 256
+// bytes.
+__host__ __device__ inline int64_t bend_table_bytes(int rcap) { return ((int64_t)rcap * 56 + 255) / 256 * 256; }
+// Set nslots bend-vertex tables (rstride bytes, rcap vertices each) to
+// empty: every distance infinite, nothing queued. The kernels leave them
+// empty again after each source.
+hipError_t launch_bend_init(char *roots, int nslots, int64_t rstride, int rcap, hipStream_t s);
 // LDS of an all-pairs workgroup besides its target table (the largest
 // window stack and the launch chunk).
 constexpr int kAllLdsFixed = 16384 + 4096;

@@ -38,7 +38,6 @@ namespace {
 using namespace wnd;
 
 constexpr int kChunks = 8;
-constexpr int kLaunchChunk = 256;  // bend vertices whose fans are flattened at once
 
 struct AllArgs {
     const SurfDesc *sd;
@@ -47,7 +46,7 @@ struct AllArgs {
     void *stack;     // per wavefront: stack_cap records of 64 bytes
     double *vdist;   // per wavefront: vstride vertex distances
     int64_t vstride;
-    char *roots;     // per wavefront: rstride bytes of bend-vertex table for rcap vertices
+    char *roots;     // per wavefront: a bend-vertex table (rstride bytes, rcap vertices)
     int64_t rstride;
     int rcap;
     int32_t *work;
@@ -57,126 +56,10 @@ struct AllArgs {
 };
 
 struct AllLds {
-    int32_t sel[kLaunchChunk];       // bend vertices of the launch chunk
-    int32_t pref[kLaunchChunk + 1];  // prefix sums of their fan sizes
-    int32_t npend;    // length of the pending-launch list
+    BendLds B;
     int32_t unfound;  // targets not reached yet
     double maxb;      // windows with a larger key cannot improve any target
 };
-
-// Bend-vertex table of one source in the wavefront's global area, indexed by
-// the mesh's bend-vertex number (a whole-mesh propagation may reach every
-// saddle and boundary vertex): rD the best distance so far, rL the distance
-// of the last launch, (rtx, rty) the initial tangent of the best path, rD2
-// the best distance of a path leaving the source in another direction;
-// queued marks a vertex on the pending-launch list pend; sel holds the
-// vertices of one launch.
-struct GRoots {
-    double *rD, *rL, *rtx, *rty, *rD2;
-    int32_t *queued, *pend, *sel;
-};
-
-__device__ inline GRoots groots(const AllArgs &a, int slot) {
-    const int n = a.rcap;
-    GRoots g;
-    g.rD = reinterpret_cast<double *>(a.roots + (int64_t)slot * a.rstride);
-    g.rL = g.rD + n;
-    g.rtx = g.rL + n;
-    g.rty = g.rtx + n;
-    g.rD2 = g.rty + n;
-    g.queued = reinterpret_cast<int32_t *>(g.rD2 + n);
-    g.pend = g.queued + n;
-    g.sel = g.pend + n;
-    return g;
-}
-
-// Bend-vertex update (insert or improve) by the rules of the cutoff
-// kernel's table: keep the smallest distance and its tangent and the
-// smallest distance of another initial direction; queue the vertex for a
-// (re-)launch when it improved by more than the re-launch tolerance, when
-// the direction of its best path changed or when another direction came
-// within the tie band. The lanes load their entries together and leave when
-// their candidate cannot change anything; the others are applied one lane at
-// a time in registers, each result passed to every lane that holds the same
-// vertex, and written back once.
-__device__ inline void groot_update(const GRoots &G, AllLds &L, const RootCfg &rc, bool ok, int e, double d,
-                                    double tx, double ty, double alt) {
-    double cD = INFINITY, cD2 = INFINITY, cL = INFINITY, ax = 0.0, ay = 0.0;
-    int qd = 1;
-    if (ok) {
-        cD = G.rD[e];
-        cD2 = G.rD2[e];
-        if (d >= cD && d >= cD2 && alt >= cD2) ok = false;
-    }
-    uint64_t m = __ballot(ok);
-    if (!m) return;
-    if (ok) {
-        cL = G.rL[e];
-        ax = G.rtx[e];
-        ay = G.rty[e];
-        qd = G.queued[e];
-    }
-    int np = L.npend;  // the pending list's length, kept wave-uniform in a register
-    while (m) {
-        const int l = __ffsll((unsigned long long)m) - 1;
-        int app = 0;
-        if (lane_id() == l) {
-            // a fresh entry has cD = cL = cD2 = infinity: every branch below then inserts
-            const bool differ = fabs(ax * ty - ay * tx) > rc.tie_dir || ax * tx + ay * ty < 0.0;
-            const bool tied = cD2 - cD <= rc.tie_rel * cD;
-            if (d < cD) {
-                if (differ) {
-                    cD2 = fmin(cD2, cD);
-                    cL = INFINITY;  // new direction: launch again however small the gain
-                }
-                cD = d;
-                ax = tx;
-                ay = ty;
-            } else if (differ) {
-                cD2 = fmin(cD2, d);
-            }
-            cD2 = fmin(cD2, alt);
-            if (!tied && cD2 - cD <= rc.tie_rel * cD) cL = INFINITY;  // a new tie
-            if (cD < cL * rc.keep && !qd) {
-                qd = 1;
-                app = 1;
-                G.pend[np] = e;
-            }
-        }
-        np += __shfl(app, l);
-        const int el = __shfl(e, l);
-        const double bD = __shfl(cD, l), bD2 = __shfl(cD2, l), bL = __shfl(cL, l);
-        const double bx = __shfl(ax, l), by = __shfl(ay, l);
-        const int bq = __shfl(qd, l);
-        if (ok && e == el) {
-            cD = bD;
-            cD2 = bD2;
-            cL = bL;
-            ax = bx;
-            ay = by;
-            qd = bq;
-        }
-        m &= m - 1;
-    }
-    if (ok) {
-        G.rD[e] = cD;
-        G.rD2[e] = cD2;
-        G.rL[e] = cL;
-        G.rtx[e] = ax;
-        G.rty[e] = ay;
-        G.queued[e] = qd;
-    }
-    if (lane_id() == 0) L.npend = np;
-    __syncthreads();  // later loads of the table, by any lane, see these values
-}
-
-// A window of bend vertex w.root is stale when it comes from an earlier
-// launch or when the vertex has improved enough for a new launch.
-template <typename R>
-__device__ inline bool gstale(const GRoots &G, const Win<R> &w, const RootCfg &rc) {
-    const double rL = G.rL[w.root];
-    return w.sg > (R)rL || G.rD[w.root] < rL * rc.keep;
-}
 
 // Per-source constants.
 struct ACtx {
@@ -368,7 +251,7 @@ __device__ inline bool opposite_dominates(double px, double py, double sg, doubl
 
 // Targets in face g (entry half-edge slot k of g) seen through window w.
 template <typename R>
-__device__ inline void query_face(const SurfDesc &sd, AllLds &L, const GRoots &G, double *d1, double *d2, double *t1x,
+__device__ inline void query_face(const SurfDesc &sd, AllLds &L, const BendTable &G, double *d1, double *d2, double *t1x,
                                   double *t1y, const ACtx &C, bool have, int src, int g, int k, const He<R> &H,
                                   const Win<R> &w) {
     int q = 0, q1 = 0;
@@ -415,14 +298,14 @@ __device__ inline void query_face(const SurfDesc &sd, AllLds &L, const GRoots &G
 // direction changed, or a tie appeared), their fans flattened over the lanes
 // a chunk of vertices at a time.
 template <typename R>
-__device__ void launch_roots(const AllArgs &a, const SurfDesc &sd, AllLds &L, const GRoots &G, double *d1,
+__device__ void launch_roots(const AllArgs &a, const SurfDesc &sd, AllLds &L, const BendTable &G, double *d1,
                              double *d2, double *t1x, double *t1y, double *Dv, const ACtx &C, RoundStack<R> &S,
                              double T, int src, SrcStats &st) {
     const int lane = lane_id();
     const DevMesh &M = sd.m;
     const HeRec *__restrict__ he = M.he;
     // take the pending list (its vertices may be queued again while they launch)
-    const int npend = L.npend;
+    const int npend = L.B.npend;
     int nsel = 0;
     for (int base = 0; base < npend; base += kWave) {
         const int k = base + lane;
@@ -442,7 +325,7 @@ __device__ void launch_roots(const AllArgs &a, const SurfDesc &sd, AllLds &L, co
         }
         nsel += __popcll(mk);
     }
-    if (lane == 0) L.npend = 0;
+    if (lane == 0) L.B.npend = 0;
     __syncthreads();
     for (int c0 = 0; c0 < nsel; c0 += kLaunchChunk) {
         const int cn = min(kLaunchChunk, nsel - c0);
@@ -453,7 +336,7 @@ __device__ void launch_roots(const AllArgs &a, const SurfDesc &sd, AllLds &L, co
             if (k < cn) {
                 const int e = G.sel[c0 + k];
                 const int v = M.pvert[e];
-                L.sel[k] = e;
+                L.B.sel[k] = e;
                 deg = M.fan_off[v + 1] - M.fan_off[v];
             }
             int inc = deg;
@@ -461,11 +344,11 @@ __device__ void launch_roots(const AllArgs &a, const SurfDesc &sd, AllLds &L, co
                 const int y = __shfl_up(inc, o);
                 if (lane >= o) inc += y;
             }
-            if (k < cn) L.pref[k + 1] = carry + inc;
+            if (k < cn) L.B.pref[k + 1] = carry + inc;
             st.launches += (unsigned long long)__popcll(__ballot(deg > 0));
             carry += __shfl(inc, kWave - 1);
         }
-        if (lane == 0) L.pref[0] = 0;
+        if (lane == 0) L.B.pref[0] = 0;
         __syncthreads();
         const int total = carry;
         for (int base = 0; base < total; base += kWave) {
@@ -476,17 +359,17 @@ __device__ void launch_roots(const AllArgs &a, const SurfDesc &sd, AllLds &L, co
                 int lo = 0, hi = cn - 1;
                 while (lo < hi) {
                     const int mid = (lo + hi + 1) >> 1;
-                    if (L.pref[mid] <= idx) lo = mid;
+                    if (L.B.pref[mid] <= idx) lo = mid;
                     else hi = mid - 1;
                 }
                 k = lo;
             }
-            const int el = act ? L.sel[k] : 0;
+            const int el = act ? L.B.sel[k] : 0;
             const int v = act ? M.pvert[el] : 0;
             const double D = act ? G.rD[el] : 0.0;
             const double vtx = act ? G.rtx[el] : 0.0, vty = act ? G.rty[el] : 0.0;
             const double D2 = act ? G.rD2[el] : INFINITY;
-            const int h = act ? M.fan[M.fan_off[v] + (idx - L.pref[k])] : 0;
+            const int h = act ? M.fan[M.fan_off[v] + (idx - L.B.pref[k])] : 0;
             const int hn = h - h % 3 + (h % 3 + 1) % 3;
             const HeRec Rh = he[h], Rn = he[hn];
             Win<R> nw;
@@ -542,12 +425,12 @@ __device__ void launch_roots(const AllArgs &a, const SurfDesc &sd, AllLds &L, co
                 vdist_min(Dv, u2, D + Rh.Lp);
             }
             const int e1 = act ? M.pidx[u1] : -1;
-            groot_update(G, L, C.rc, e1 >= 0, e1, D + Rh.L, vtx, vty, D2 + Rh.L);
+            bend_update(G, L.B, C.rc, e1 >= 0, e1, D + Rh.L, vtx, vty, D2 + Rh.L);
             const int e2 = act ? M.pidx[u2] : -1;
-            groot_update(G, L, C.rc, e2 >= 0, e2, D + Rh.Lp, vtx, vty, D2 + Rh.Lp);
+            bend_update(G, L.B, C.rc, e2 >= 0, e2, D + Rh.Lp, vtx, vty, D2 + Rh.Lp);
             S.push(want, key >= T, nw, st.overflow);
         }
-        __syncthreads();  // L.sel / L.pref are rewritten by the next chunk
+        __syncthreads();  // the chunk arrays are rewritten by the next chunk
     }
 }
 
@@ -576,7 +459,7 @@ __device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
     C.bucket = a.gp.bucket > 0.0 ? a.gp.bucket : 2.0 * M.max_edge;
     C.cutoff = sd.cutoff;
     double *Dv = a.vdist + (int64_t)slot * a.vstride;
-    const GRoots G = groots(a, slot);
+    const BendTable G = bend_table(a.roots, a.rstride, slot, a.rcap);
     RoundStack<R> S;
     S.lds = reinterpret_cast<typename RecOf<R>::T *>(stk);
     S.kL = stk_bytes / (int)sizeof(typename RecOf<R>::T);
@@ -593,14 +476,9 @@ __device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
         t1x[j] = 0.0;
         t1y[j] = 0.0;
     }
-    for (int e = lane; e < M.n_pseudo; e += kWave) {
-        G.rD[e] = INFINITY;
-        G.rL[e] = INFINITY;
-        G.rD2[e] = INFINITY;
-        G.queued[e] = 0;
-    }
     if (lane == 0) {
-        L.npend = 0;
+        L.B.npend = 0;
+        L.B.ntouched = 0;
         L.unfound = n - 1;
         L.maxb = C.cutoff < INFINITY ? C.cutoff * (fp32 ? 1.0 + fmax(a.gp.slack32, a.gp.guard_rel) : 1.0)
                                      : INFINITY;
@@ -692,7 +570,7 @@ __device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
                 }
             }
         }
-        groot_update(G, L, C.rc, rv >= 0, rv, rd, rtx, rty, INFINITY);
+        bend_update(G, L.B, C.rc, rv >= 0, rv, rd, rtx, rty, INFINITY);
         // on-edge sources: targets and third vertex of the face across
         for (int k = 0; k < 3; ++k) {
             const bool on = sb[(k + 2) % 3] <= 0.0 && he[3 * fs + k].twin >= 0;
@@ -733,7 +611,7 @@ __device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
             const int opp = Rt.opp_flags >> 1;
             if (lane == 0) vdist_min(Dv, opp, d);
             const int eo = lane == 0 ? M.pidx[opp] : -1;
-            groot_update(G, L, C.rc, eo >= 0, eo, d, (c * dx - s * dy) / d, (s * dx + c * dy) / d, INFINITY);
+            bend_update(G, L.B, C.rc, eo >= 0, eo, d, (c * dx - s * dy) / d, (s * dx + c * dy) / d, INFINITY);
         }
         S.push(want, false, w, overflow);
         S.push(wantA, ka >= T, wa, overflow);
@@ -750,12 +628,12 @@ __device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
         if (overflow) break;
         depth = max(depth, S.lsp + S.gsp + S.dsp);
         bool busy = S.refill(have, w);
-        if (!busy && L.npend > 0) {
+        if (!busy && L.B.npend > 0) {
             launch_roots(a, sd, L, G, d1, d2, t1x, t1y, Dv, C, S, T, src, st);
             busy = S.refill(have, w);
         }
         if (!busy) {
-            if (S.dsp == 0 && L.npend == 0) break;
+            if (S.dsp == 0 && L.B.npend == 0) break;
             // next round; once every target is reached, bound the keys
             S.next_round();
             T += C.bucket;
@@ -775,7 +653,7 @@ __device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
             break;
         }
         // stale: from an earlier launch of its root, or a new launch is due
-        if (have && w.root >= 0 && gstale(G, w, C.rc)) {
+        if (have && w.root >= 0 && bend_stale(G.rD[w.root], G.rL[w.root], w, C.rc)) {
             have = false;
             ++st.stale;
         }
@@ -844,7 +722,7 @@ __device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
                 }
             }
             const int eo = ok ? M.pidx[H.opp] : -1;
-            groot_update(G, L, C.rc, ok, eo, dcv, tx, ty, alt);
+            bend_update(G, L.B, C.rc, ok, eo, dcv, tx, ty, alt);
         }
         // children, trimmed against the vertex paths and bounded by maxb
         Win<R> cl, cr;
@@ -934,7 +812,7 @@ __device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
     st.pruned += pruned;
     st.overflow |= ovf;
     st.depth = max(st.depth, depth);
-    __syncthreads();
+    bend_reset(G, L.B);
     return fp32 && !ovf && __ballot(near_cut) != 0;
 }
 

@@ -71,6 +71,9 @@ struct GeoArgs {
     int32_t *work;       // [kChunks] work counters
     Counters *ctr;
     int grab;            // consecutive sources claimed at a time
+    char *roots;         // per wave: a bend-vertex table (rstride bytes, rcap vertices)
+    int64_t rstride;
+    int rcap;
 };
 
 struct Lds {
@@ -80,7 +83,7 @@ struct Lds {
     double d1[kMaxCand], d2[kMaxCand], t1x[kMaxCand], t1y[kMaxCand];
     int32_t head[kHash];
     int32_t ncand;
-    Roots R;
+    BendLds B;
 };
 
 __device__ inline int hash_face(int f) { return (int)(((uint32_t)f * 2654435761u) >> 24) & (kHash - 1); }
@@ -102,22 +105,31 @@ struct Ctx {
     double root_keep;  // 1 - relative improvement below which a bend vertex is not re-launched
     RootCfg rc;
     int nc;
+    int nc4;  // nc rounded up to a multiple of 4 (the padded bound table)
 };
 
 // Could a path of length `base` to the edge slice P + x u (x in [x0, x1])
 // still improve some candidate target? (3D distance as the lower bound of
-// the rest of the path.)
+// the rest of the path.) Targets are tested four at a time, so that their
+// independent load and arithmetic chains overlap; the bound table is padded
+// to a multiple of four with entries that no path can reach.
 __device__ inline bool reaches_target(const Lds &L, const Ctx &C, const double P[3], const double u[3], double x0,
                                       double x1, double base) {
-    for (int s = 0; s < C.nc; ++s) {
-        const double rem = L.cb[s][3] - base;
-        double q0 = L.cb[s][0] - P[0], q1 = L.cb[s][1] - P[1], q2 = L.cb[s][2] - P[2];
-        double t = q0 * u[0] + q1 * u[1] + q2 * u[2];
-        t = fmin(fmax(t, x0), x1);
-        q0 -= t * u[0];
-        q1 -= t * u[1];
-        q2 -= t * u[2];
-        if (rem > 0.0 && q0 * q0 + q1 * q1 + q2 * q2 < rem * rem) return true;
+    for (int s0 = 0; s0 < C.nc4; s0 += 4) {
+        bool hit = false;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const double *cb = L.cb[s0 + i];
+            const double rem = cb[3] - base;
+            double q0 = cb[0] - P[0], q1 = cb[1] - P[1], q2 = cb[2] - P[2];
+            double t = q0 * u[0] + q1 * u[1] + q2 * u[2];
+            t = fmin(fmax(t, x0), x1);
+            q0 -= t * u[0];
+            q1 -= t * u[1];
+            q2 -= t * u[2];
+            hit |= rem > 0.0 && q0 * q0 + q1 * q1 + q2 * q2 < rem * rem;
+        }
+        if (hit) return true;
     }
     return false;
 }
@@ -194,132 +206,154 @@ struct SrcStats {
     bool overflow;
 };
 
-// Launch the dirty bend vertices (distance improved since their last
-// launch) within launch_delta of the smallest such distance. The selected
-// roots are compacted into a list and their fans flattened over the lanes,
-// so one launch round costs a few memory round trips, not one per root.
+// Launch the pending bend vertices (distance improved since their last
+// launch, direction changed or a tie appeared) within launch_delta of the
+// smallest such distance; the others stay pending. The selected vertices
+// are compacted into a list and their fans flattened over the lanes, a chunk
+// of vertices at a time, so one launch round costs a few memory round trips,
+// not one per vertex.
 template <typename R>
-__device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, Lds &L, const Ctx &C, Stack<R> &S,
-                             SrcStats &st) {
+__device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, Lds &L, const BendTable &G, const Ctx &C,
+                             Stack<R> &S, SrcStats &st) {
     const int lane = lane_id();
     const DevMesh &M = sd.m;
     const HeRec *__restrict__ he = M.he;
+    const int npend = L.B.npend;
     double mn = INFINITY;
-    for (int e = lane; e < kRootCap; e += kWave)
-        if (L.R.rkey[e] >= 0 && L.R.rD[e] < L.R.rL[e] * C.rc.keep && L.R.rD[e] < C.cut_acc) mn = fmin(mn, L.R.rD[e]);
+    for (int k = lane; k < npend; k += kWave) {
+        const int e = G.pend[k];
+        const double D = G.rD[e];
+        if (D < G.rL[e] * C.rc.keep && D < C.cut_acc) mn = fmin(mn, D);
+    }
     mn = wave_min(mn);
-    if (lane == 0) L.R.dirty = 0;
-    if (!(mn < INFINITY)) return;
     const double thr = mn + a.gp.launch_delta;
-    // 1. compact the selected roots, mark them launched
-    int nsel = 0;
-    bool left = false;
-    for (int base = 0; base < kRootCap; base += kWave) {
-        const int e = base + lane;
-        const bool cand = e < kRootCap && L.R.rkey[e] >= 0 && L.R.rD[e] < L.R.rL[e] * C.rc.keep && L.R.rD[e] < C.cut_acc;
-        const bool sel = cand && L.R.rD[e] <= thr;
-        left |= cand && !sel;
-        const uint64_t mk = __ballot(sel);
-        if (sel) {
-            L.R.sel[nsel + __popcll(mk & lanemask_lt())] = e;
-            L.R.rL[e] = L.R.rD[e];
-        }
-        nsel += __popcll(mk);
-    }
-    if (__ballot(left) != 0 && lane == 0) L.R.dirty = 1;
-    // 2. per root: is any target within reach (3D bound), and its fan size
-    int carry = 0;
-    for (int base = 0; base < nsel; base += kWave) {
+    // 1. split the pending list: launch now (marked launched), keep pending
+    //    (compacted in place: a kept entry never moves past its own slot), or
+    //    drop (nothing left to launch)
+    int nsel = 0, nkeep = 0;
+    for (int base = 0; base < npend; base += kWave) {
         const int k = base + lane;
-        int deg = 0;
-        if (k < nsel) {
-            const int e = L.R.sel[k], v = L.R.rkey[e];
-            const double D = L.R.rD[e];
-            const double vx = M.V[3 * (int64_t)v], vy = M.V[3 * (int64_t)v + 1], vz = M.V[3 * (int64_t)v + 2];
-            bool useful = false;
-            for (int s = 0; s < C.nc && !useful; ++s) {
-                const double bound = L.cb[s][3] - D;
-                const double q0 = L.cb[s][0] - vx, q1 = L.cb[s][1] - vy, q2 = L.cb[s][2] - vz;
-                useful = bound > 0.0 && q0 * q0 + q1 * q1 + q2 * q2 < bound * bound;
-            }
-            if (useful) deg = M.fan_off[v + 1] - M.fan_off[v];
+        int e = 0;
+        bool sel = false, keep = false;
+        double D = 0.0;
+        if (k < npend) {
+            e = G.pend[k];
+            D = G.rD[e];
+            const bool cand = D < G.rL[e] * C.rc.keep && D < C.cut_acc;
+            sel = cand && D <= thr;
+            keep = cand && !sel;
         }
-        // wave-inclusive scan of deg
-        int inc = deg;
-        for (int o = 1; o < kWave; o <<= 1) {
-            const int y = __shfl_up(inc, o);
-            if (lane >= o) inc += y;
+        const uint64_t ms = __ballot(sel), mk = __ballot(keep);
+        if (sel) {
+            G.sel[nsel + __popcll(ms & lanemask_lt())] = e;
+            G.rL[e] = D;
         }
-        if (k < nsel) L.R.pref[k + 1] = carry + inc;
-        st.launches += (unsigned long long)__popcll(__ballot(deg > 0));
-        carry += __shfl(inc, kWave - 1);
+        if (keep) G.pend[nkeep + __popcll(mk & lanemask_lt())] = e;
+        if (k < npend && !keep) G.queued[e] = 0;
+        nsel += __popcll(ms);
+        nkeep += __popcll(mk);
     }
-    if (lane == 0) L.R.pref[0] = 0;
-    const int total = carry;
-    // 3. flattened fans: lane <- (root k, fan position)
-    for (int base = 0; base < total; base += kWave) {
-        const int idx = base + lane;
-        const bool act = idx < total;
-        int k = 0;
-        if (act) {
-            int lo = 0, hi = nsel - 1;  // largest k with pref[k] <= idx
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (L.R.pref[mid] <= idx) lo = mid;
-                else hi = mid - 1;
+    if (lane == 0) L.B.npend = nkeep;
+    __syncthreads();
+    for (int c0 = 0; c0 < nsel; c0 += kLaunchChunk) {
+        const int cn = min(kLaunchChunk, nsel - c0);
+        // 2. per vertex: is any target within reach (3D bound), and its fan size
+        int carry = 0;
+        for (int base = 0; base < cn; base += kWave) {
+            const int k = base + lane;
+            int deg = 0;
+            if (k < cn) {
+                const int e = G.sel[c0 + k], v = M.pvert[e];
+                L.B.sel[k] = e;
+                const double D = G.rD[e];
+                const double vx = M.V[3 * (int64_t)v], vy = M.V[3 * (int64_t)v + 1], vz = M.V[3 * (int64_t)v + 2];
+                bool useful = false;
+                for (int s = 0; s < C.nc && !useful; ++s) {
+                    const double bound = L.cb[s][3] - D;
+                    const double q0 = L.cb[s][0] - vx, q1 = L.cb[s][1] - vy, q2 = L.cb[s][2] - vz;
+                    useful = bound > 0.0 && q0 * q0 + q1 * q1 + q2 * q2 < bound * bound;
+                }
+                if (useful) deg = M.fan_off[v + 1] - M.fan_off[v];
             }
-            k = lo;
-        }
-        const int el = act ? L.R.sel[k] : 0;
-        const int v = act ? L.R.rkey[el] : 0;
-        const double D = act ? L.R.rD[el] : 0.0;
-        const double vtx = act ? L.R.rtx[el] : 0.0, vty = act ? L.R.rty[el] : 0.0;
-        const double D2 = act ? L.R.rD2[el] : INFINITY;  // the root's other-direction distance
-        const int h = act ? M.fan[M.fan_off[v] + (idx - L.R.pref[k])] : 0;
-        const int hn = h - h % 3 + (h % 3 + 1) % 3;
-        const HeRec Rh = he[h], Rn = he[hn];
-        Win<R> nw;
-        bool want = false;
-        if (act && Rn.twin >= 0) {
-            // window across the edge opposite v: twin(next(h)) runs u2 -> u1
-            const double px = Rn.L - Rn.cx, py = -Rn.cy;
-            nw.px = (R)px;
-            nw.py = (R)py;
-            nw.b0 = R(0);
-            nw.b1 = (R)Rn.L;
-            nw.sg = (R)D;
-            nw.c = R(1);
-            nw.s = R(0);
-            nw.he = Rn.twin;
-            nw.root = el;
-            double F3[3][3], U3[3][3];
-            face_xyz(M, h / 3, h % 3, F3, U3);  // (v, u1, u2)
-            // the window's edge runs u2 -> u1: the reverse of half-edge next(h) = (u1 -> u2)
-            const double u[3] = {-U3[1][0], -U3[1][1], -U3[1][2]};
-            want = reaches_target(L, C, F3[2], u, 0.0, Rn.L, D + seg_dist(px, py, 0.0, Rn.L));
-        }
-        // direct targets in face(h)
-        const int g = h / 3;
-        int slot = act ? first_in_face(L, g) : -1;
-        const double *pv = M.V + 3 * (int64_t)v;
-        while (__ballot(slot >= 0)) {
-            const bool ok = slot >= 0;
-            double d = 0;
-            if (ok) {
-                const double dx = L.cb[slot][0] - pv[0], dy = L.cb[slot][1] - pv[1], dz = L.cb[slot][2] - pv[2];
-                d = D + sqrt(dx * dx + dy * dy + dz * dz);
+            // wave-inclusive scan of deg
+            int inc = deg;
+            for (int o = 1; o < kWave; o <<= 1) {
+                const int y = __shfl_up(inc, o);
+                if (lane >= o) inc += y;
             }
-            target_update(L, C, ok, slot, d, vtx, vty, D2 + (d - D));
-            if (ok) slot = next_in_face(L, slot, g);
+            if (k < cn) L.B.pref[k + 1] = carry + inc;
+            st.launches += (unsigned long long)__popcll(__ballot(deg > 0));
+            carry += __shfl(inc, kWave - 1);
         }
-        // adjacent bend vertices along the two edges at v
-        const int u1 = act ? M.T[hn] : 0;  // head of h
-        const bool ok1 = act && (M.vflag[u1] & VF_PSEUDO) && D + Rh.L < C.cut_acc;
-        root_update(L.R, C.rc, ok1, u1, D + Rh.L, vtx, vty, D2 + Rh.L, st.overflow);
-        const int u2 = act ? Rh.opp_flags >> 1 : 0;
-        const bool ok2 = act && (M.vflag[u2] & VF_PSEUDO) && D + Rh.Lp < C.cut_acc;
-        root_update(L.R, C.rc, ok2, u2, D + Rh.Lp, vtx, vty, D2 + Rh.Lp, st.overflow);
-        S.push(want, nw, st.overflow);
+        if (lane == 0) L.B.pref[0] = 0;
+        __syncthreads();
+        const int total = carry;
+        // 3. flattened fans: lane <- (vertex k, fan position)
+        for (int base = 0; base < total; base += kWave) {
+            const int idx = base + lane;
+            const bool act = idx < total;
+            int k = 0;
+            if (act) {
+                int lo = 0, hi = cn - 1;  // largest k with pref[k] <= idx
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if (L.B.pref[mid] <= idx) lo = mid;
+                    else hi = mid - 1;
+                }
+                k = lo;
+            }
+            const int el = act ? L.B.sel[k] : 0;
+            const int v = act ? M.pvert[el] : 0;
+            const double D = act ? G.rD[el] : 0.0;
+            const double vtx = act ? G.rtx[el] : 0.0, vty = act ? G.rty[el] : 0.0;
+            const double D2 = act ? G.rD2[el] : INFINITY;  // the vertex's other-direction distance
+            const int h = act ? M.fan[M.fan_off[v] + (idx - L.B.pref[k])] : 0;
+            const int hn = h - h % 3 + (h % 3 + 1) % 3;
+            const HeRec Rh = he[h], Rn = he[hn];
+            Win<R> nw;
+            bool want = false;
+            if (act && Rn.twin >= 0) {
+                // window across the edge opposite v: twin(next(h)) runs u2 -> u1
+                const double px = Rn.L - Rn.cx, py = -Rn.cy;
+                nw.px = (R)px;
+                nw.py = (R)py;
+                nw.b0 = R(0);
+                nw.b1 = (R)Rn.L;
+                nw.sg = (R)D;
+                nw.c = R(1);
+                nw.s = R(0);
+                nw.he = Rn.twin;
+                nw.root = el;
+                double F3[3][3], U3[3][3];
+                face_xyz(M, h / 3, h % 3, F3, U3);  // (v, u1, u2)
+                // the window's edge runs u2 -> u1: the reverse of half-edge next(h) = (u1 -> u2)
+                const double u[3] = {-U3[1][0], -U3[1][1], -U3[1][2]};
+                want = reaches_target(L, C, F3[2], u, 0.0, Rn.L, D + seg_dist(px, py, 0.0, Rn.L));
+            }
+            // direct targets in face(h)
+            const int g = h / 3;
+            int slot = act ? first_in_face(L, g) : -1;
+            const double *pv = M.V + 3 * (int64_t)v;
+            while (__ballot(slot >= 0)) {
+                const bool ok = slot >= 0;
+                double d = 0;
+                if (ok) {
+                    const double dx = L.cb[slot][0] - pv[0], dy = L.cb[slot][1] - pv[1], dz = L.cb[slot][2] - pv[2];
+                    d = D + sqrt(dx * dx + dy * dy + dz * dz);
+                }
+                target_update(L, C, ok, slot, d, vtx, vty, D2 + (d - D));
+                if (ok) slot = next_in_face(L, slot, g);
+            }
+            // adjacent bend vertices along the two edges at v
+            const int u1 = act ? M.T[hn] : 0;  // head of h
+            const int e1 = act && D + Rh.L < C.cut_acc ? M.pidx[u1] : -1;
+            bend_update(G, L.B, C.rc, e1 >= 0, e1, D + Rh.L, vtx, vty, D2 + Rh.L);
+            const int u2 = act ? Rh.opp_flags >> 1 : 0;
+            const int e2 = act && D + Rh.Lp < C.cut_acc ? M.pidx[u2] : -1;
+            bend_update(G, L.B, C.rc, e2 >= 0, e2, D + Rh.Lp, vtx, vty, D2 + Rh.Lp);
+            S.push(want, nw, st.overflow);
+        }
+        __syncthreads();  // the chunk arrays are rewritten by the next chunk
     }
 }
 
@@ -389,7 +423,9 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
     C.root_keep = fp32 ? 1.0 - a.gp.root_rel32 : 1.0;
     C.rc = {C.root_keep, C.tie_dir, C.tie_rel};
     C.nc = nc;
+    C.nc4 = (nc + 3) & ~3;
     const HeRec *__restrict__ he = sd.m.he;
+    const BendTable G = bend_table(a.roots, a.rstride, slot_id, a.rcap);
     Stack<R> S;
     S.lds = reinterpret_cast<typename RecOf<R>::T *>(stk);
     S.kL = stk_bytes / (int)sizeof(typename RecOf<R>::T);
@@ -401,10 +437,9 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
 
     // ---- LDS tables
     for (int e = lane; e < kHash; e += kWave) L.head[e] = -1;
-    for (int e = lane; e < kRootCap; e += kWave) L.R.rkey[e] = -1;
     if (lane == 0) {
-        L.R.rcount = 0;
-        L.R.dirty = 0;
+        L.B.npend = 0;
+        L.B.ntouched = 0;
     }
     __syncthreads();
     for (int s = lane; s < nc; s += kWave) {
@@ -421,6 +456,10 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
         L.t1x[s] = 0.0;
         L.t1y[s] = 0.0;
         L.tnext[s] = atomicExch(&L.head[hash_face(f)], s);
+    }
+    if (nc + lane < C.nc4) {
+        L.cb[nc + lane][0] = L.cb[nc + lane][1] = L.cb[nc + lane][2] = 0.0;
+        L.cb[nc + lane][3] = -INFINITY;  // padding: never reachable
     }
     __syncthreads();
 
@@ -462,12 +501,12 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
             const int k = lane, h = 3 * fs + k;
             const HeRec Rh = he[h];
             const double ex = (P[(k + 1) % 3][0] - P[k][0]) / Rh.L, ey = (P[(k + 1) % 3][1] - P[k][1]) / Rh.L;
-            int v = sd.m.T[h];
-            if (sd.m.vflag[v] & VF_PSEUDO) {
+            const int pe = sd.m.pidx[sd.m.T[h]];
+            if (pe >= 0) {
                 double dx = P[k][0] - sx, dy = P[k][1] - sy;
                 rd = sqrt(dx * dx + dy * dy);
                 rok = rd < C.cut_acc;
-                rv = v;
+                rv = pe;
                 rtx = rd > 0 ? dx / rd : 0.0;
                 rty = rd > 0 ? dy / rd : 0.0;
             }
@@ -494,7 +533,7 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
                 }
             }
         }
-        root_update(L.R, C.rc, rok, rv, rd, rtx, rty, INFINITY, overflow);
+        bend_update(G, L.B, C.rc, rok, rv, rd, rtx, rty, INFINITY);
         // on-edge sources: targets and third vertex of the face across
         for (int k = 0; k < 3; ++k) {
             bool on = sb[(k + 2) % 3] <= 0.0 && he[3 * fs + k].twin >= 0;
@@ -525,11 +564,10 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
                 target_update(L, C, ok, slot, d, tx, ty, INFINITY);
                 if (ok) slot = next_in_face(L, slot, g);
             }
-            bool ok = lane == 0 && (Rt.opp_flags & 1);
             double dx = Rt.cx - ptx, dy = Rt.cy;
             double d = sqrt(dx * dx + dy * dy);
-            root_update(L.R, C.rc, ok && d < C.cut_acc, Rt.opp_flags >> 1, d, (c * dx - s * dy) / d,
-                        (s * dx + c * dy) / d, INFINITY, overflow);
+            const int pe = lane == 0 && (Rt.opp_flags & 1) && d < C.cut_acc ? sd.m.pidx[Rt.opp_flags >> 1] : -1;
+            bend_update(G, L.B, C.rc, pe >= 0, pe, d, (c * dx - s * dy) / d, (s * dx + c * dy) / d, INFINITY);
         }
         S.push(want, w, overflow);
         S.push(wantA, wa, overflow);
@@ -549,14 +587,14 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
         bool busy = S.refill(have, w);
         // bend-vertex launches: eagerly whenever the table is dirty, else
         // once nothing is left to propagate
-        if (L.R.dirty && (eager || !busy)) {
+        if (L.B.npend > 0 && (eager || !busy)) {
             const long long t0 = clock64();
-            launch_roots(a, sd, L, C, S, st);
+            launch_roots(a, sd, L, G, C, S, st);
             t_launch += clock64() - t0;
             if (!busy) busy = S.refill(have, w);
         }
         if (!busy) {
-            if (!L.R.dirty) break;
+            if (L.B.npend == 0) break;
             continue;
         }
         nwin += (unsigned long long)__popcll(__ballot(have));
@@ -568,23 +606,30 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
         // ---- process the lane's window
         Win<R> cl, cr;
         bool hl = false, hr = false;
-        // stale: the window comes from an earlier launch of its root, or the
-        // root has improved enough to be launched again (the same test as the
-        // launch itself, so a root is never left without live windows)
-        if (have && w.root >= 0 && is_stale(L.R, w, C.rc)) {
-            have = false;
-            ++st.stale;
-        }
         He<R> H;
         double txc = 0.0;
         double F3[3][3], U3[3][3];
         int f = -1, k = 0;
         if (have) {
-            // both records depend only on the entry half-edge: issue them together
+            // the records depend only on the entry half-edge and the root:
+            // issue them together
             f = w.he / 3;
             k = w.he % 3;
             H = load_he(sd.m, w.he, R(0));
             face_xyz(sd.m, f, k, F3, U3);
+            double rD = 0.0, rL = INFINITY;
+            if (w.root >= 0) {
+                rD = G.rD[w.root];
+                rL = G.rL[w.root];
+            }
+            // stale: the window comes from an earlier launch of its root, or
+            // the root has improved enough to be launched again (the same
+            // test as the launch itself, so a root is never left without
+            // live windows)
+            if (w.root >= 0 && bend_stale(rD, rL, w, C.rc)) {
+                have = false;
+                ++st.stale;
+            }
             txc = (double)w.px + ((double)H.cx - (double)w.px) * (-(double)w.py) / ((double)H.cy - (double)w.py);
         }
         // targets in face f
@@ -609,9 +654,9 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
                             tx = (double)(w.c * dx - w.s * dy);
                             ty = (double)(w.s * dx + w.c * dy);
                         } else {
-                            tx = L.R.rtx[w.root];
-                            ty = L.R.rty[w.root];
-                            alt = L.R.rD2[w.root] + (double)l;
+                            tx = G.rtx[w.root];
+                            ty = G.rty[w.root];
+                            alt = G.rD2[w.root] + (double)l;
                         }
                     }
                 }
@@ -636,13 +681,14 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
                         tx = (double)(w.c * dx - w.s * dy);
                         ty = (double)(w.s * dx + w.c * dy);
                     } else {
-                        tx = L.R.rtx[w.root];
-                        ty = L.R.rty[w.root];
-                        alt = L.R.rD2[w.root] + (double)l;
+                        tx = G.rtx[w.root];
+                        ty = G.rty[w.root];
+                        alt = G.rD2[w.root] + (double)l;
                     }
                 }
             }
-            root_update(L.R, C.rc, ok, have ? H.opp : 0, d, tx, ty, alt, overflow);
+            const int pe = ok ? sd.m.pidx[H.opp] : -1;
+            bend_update(G, L.B, C.rc, ok, pe, d, tx, ty, alt);
         }
         if (have) children(H, w, txc, false, C, F3, U3, L, cl, hl, cr, hr, pruned);
         // keep one child in the lane, push the other
@@ -696,7 +742,7 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
     st.windows += nwin;
     st.pruned += pruned;
     st.overflow |= ovf;
-    __syncthreads();
+    bend_reset(G, L.B);
     return any_near;
 }
 
@@ -783,7 +829,8 @@ void launch_variant(int kb, int nslots, const GeoArgs &a, hipStream_t s) {
 }  // namespace
 
 hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoParams &gp, const GeoShape &shape,
-                           char *stack_mem, int32_t *work_ctr, Counters *ctr, bool fp32, hipStream_t s) {
+                           char *stack_mem, char *roots, int64_t rstride, int rcap, int32_t *work_ctr, Counters *ctr,
+                           bool fp32, hipStream_t s) {
     GeoArgs a;
     a.sd = desc;
     a.bi = bi;
@@ -792,6 +839,9 @@ hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoPa
     a.work = work_ctr;
     a.ctr = ctr;
     a.grab = shape.grab < 1 ? 1 : shape.grab;
+    a.roots = roots;
+    a.rstride = rstride;
+    a.rcap = rcap;
     if (shape.nslots < 1 || bi.begin[bi.nsurf] < 1) return hipSuccess;
     if (fp32) launch_variant<true>(shape.lds_stack_kb, shape.nslots, a, s);
     else launch_variant<false>(shape.lds_stack_kb, shape.nslots, a, s);

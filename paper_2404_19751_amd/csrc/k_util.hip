@@ -5,6 +5,7 @@
 
 #include "gsim_internal.h"
 #include "particle_ops.h"
+#include "window.h"
 
 namespace gsim {
 
@@ -31,6 +32,19 @@ __global__ void k_zero_i32(int32_t *p, int64_t n) {
 __global__ void k_zero_u64(unsigned long long *p, int64_t n) {
     int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0ull;
+}
+
+// Empty bend-vertex tables: entry e of slot s gets infinite distances and
+// is not queued (the tangent fields are written on insertion).
+__global__ void k_bend_init(char *roots, int64_t rstride, int rcap, int64_t n) {
+    const int64_t i = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const int slot = (int)(i / rcap), e = (int)(i % rcap);
+    const wnd::BendTable g = wnd::bend_table(roots, rstride, slot, rcap);
+    g.rD[e] = INFINITY;
+    g.rL[e] = INFINITY;
+    g.rD2[e] = INFINITY;
+    g.queued[e] = 0;
 }
 
 // ------------------------------------------------------------ scans
@@ -402,6 +416,13 @@ hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_zero_i32, dim3(nblocks(n)), dim3(kBlock), 0, s, p, n);
     return hipGetLastError();
 }
+hipError_t launch_bend_init(char *roots, int nslots, int64_t rstride, int rcap, hipStream_t s) {
+    const int64_t n = (int64_t)nslots * rcap;
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_bend_init, dim3(nblocks(n)), dim3(kBlock), 0, s, roots, rstride, rcap, n);
+    return hipGetLastError();
+}
+
 hipError_t launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_zero_u64, dim3(nblocks(n)), dim3(kBlock), 0, s, p, n);

@@ -13,8 +13,8 @@ namespace gsim {
 namespace wnd {
 
 constexpr int kWave = 64;
-// slots of the cutoff kernel's bend-vertex hash table in LDS
-constexpr int kRootCap = 255;
+// bend vertices whose fans one launch step flattens over the lanes
+constexpr int kLaunchChunk = 256;
 
 template <typename R>
 struct Win {
@@ -88,19 +88,6 @@ __device__ inline He<float> load_he(const DevMesh &m, int h, float) {
             (r.opp_flags & 1) != 0};
 }
 
-// Bend-vertex (pseudo-source) table of one source, in LDS: open addressing
-// on the vertex id; rD the best distance so far, rL the distance of the
-// last launch, (rtx, rty) the initial tangent of the best path, rD2 the
-// best distance of a path leaving the source in another direction (the
-// vertex's own tie gap, passed on to everything reached through it).
-struct Roots {
-    int32_t rkey[kRootCap + 1];
-    double rD[kRootCap], rL[kRootCap], rtx[kRootCap], rty[kRootCap], rD2[kRootCap];
-    int32_t rcount, dirty;
-    int32_t sel[kRootCap + 1];   // launch list: root slots
-    int32_t pref[kRootCap + 2];  // prefix sums of their fan sizes
-};
-
 __device__ inline int lane_id() { return threadIdx.x; }
 // Ends one step of a loop that applies the lanes' updates to a shared table
 // one lane at a time: the next lane's loads must see this lane's stores. To
@@ -108,7 +95,6 @@ __device__ inline int lane_id() { return threadIdx.x; }
 // table value in a register from one step to the next.
 __device__ inline void lane_step_barrier() { __asm__ __volatile__("" ::: "memory"); }
 __device__ inline uint64_t lanemask_lt() { return (1ull << threadIdx.x) - 1ull; }
-__device__ inline int hash_vert(int v) { return (int)((((uint32_t)v * 2246822519u) >> 16) % kRootCap); }
 
 __device__ inline double wave_min(double v) {
     for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
@@ -127,89 +113,157 @@ struct RootCfg {
     double keep, tie_dir, tie_rel;
 };
 
-// Serialised bend-vertex update (insert or improve): keeps the smallest
-// distance and its tangent, and the smallest distance of a path in another
-// initial direction (directions closer than tie_dir count as one); `alt` is
-// such a second distance that comes with the candidate (a path through
-// another bend vertex carries that vertex's own second distance). Marks the
-// vertex for a (re-)launch when its distance improved by more than the
-// re-launch tolerance, when the direction of its best path changed, or
-// when a path of another direction has just come within the tie band:
-// everything already reached through the vertex then learns the new
-// tangent or the tie.
-__device__ inline void root_update(Roots &L, const RootCfg &rc, bool ok, int v, double d, double tx, double ty,
-                                   double alt, bool &overflow) {
-    // parallel look-up first: a lane whose vertex is in the table and whose
-    // candidate is no shorter than its best and second distances (which only
-    // decrease) can change nothing and leaves before the serialised part
-    int found = -1;
+// Bend-vertex (pseudo-source) table of one source, in a per-wavefront
+// global area indexed by the mesh's bend-vertex number (pidx), so a source
+// may reach any number of saddle and boundary vertices: rD the best distance
+// so far, rL the distance of the last launch, (rtx, rty) the initial tangent
+// of the best path, rD2 the best distance of a path leaving the source in
+// another direction (the vertex's own tie gap, passed on to everything
+// reached through it). queued marks a vertex on the pending-launch list
+// pend; touched lists the vertices the source has reached, whose entries
+// are reset when the source is done (a fresh entry has rD = rL = rD2 =
+// infinity and queued = 0, so every source starts from an empty table
+// without a sweep over the mesh); sel receives the vertices of a launch.
+struct BendTable {
+    double *rD, *rL, *rtx, *rty, *rD2;
+    int32_t *queued, *pend, *touched, *sel;
+};
+
+__device__ inline BendTable bend_table(char *base, int64_t stride, int slot, int rcap) {
+    BendTable g;
+    g.rD = reinterpret_cast<double *>(base + (int64_t)slot * stride);
+    g.rL = g.rD + rcap;
+    g.rtx = g.rL + rcap;
+    g.rty = g.rtx + rcap;
+    g.rD2 = g.rty + rcap;
+    g.queued = reinterpret_cast<int32_t *>(g.rD2 + rcap);
+    g.pend = g.queued + rcap;
+    g.touched = g.pend + rcap;
+    g.sel = g.touched + rcap;
+    return g;
+}
+
+// Wave-uniform state of the table and the LDS of one launch chunk.
+struct BendLds {
+    int32_t npend, ntouched;
+    int32_t sel[kLaunchChunk];       // bend vertices of the chunk
+    int32_t pref[kLaunchChunk + 1];  // prefix sums of their fan sizes
+};
+
+// Bend-vertex update (insert or improve): keep the smallest distance and
+// its tangent, and the smallest distance of a path in another initial
+// direction (directions closer than tie_dir count as one); `alt` is such a
+// second distance that comes with the candidate (a path through another bend
+// vertex carries that vertex's own second distance). Queue the vertex for a
+// (re-)launch when its distance improved by more than the re-launch
+// tolerance, when the direction of its best path changed, or when a path of
+// another direction has just come within the tie band: everything already
+// reached through the vertex then learns the new tangent or the tie.
+// The lanes load their entries together and leave when their candidate
+// cannot change anything (the stored distances only decrease); the others
+// are applied one lane at a time in registers, each result passed to every
+// lane holding the same vertex, and written back once.
+__device__ inline void bend_update(const BendTable &G, BendLds &L, const RootCfg &rc, bool ok, int e, double d,
+                                   double tx, double ty, double alt) {
+    double cD = INFINITY, cD2 = INFINITY, cL = INFINITY, ax = 0.0, ay = 0.0;
+    int qd = 1;
     if (ok) {
-        int e = hash_vert(v), probes = 0;
-        while (L.rkey[e] >= 0 && L.rkey[e] != v && probes < kRootCap) {
-            e = e + 1 == kRootCap ? 0 : e + 1;
-            ++probes;
-        }
-        if (probes < kRootCap && L.rkey[e] == v) {
-            found = e;
-            if (d >= L.rD[e] && d >= L.rD2[e] && alt >= L.rD2[e]) ok = false;
-        }
+        cD = G.rD[e];
+        cD2 = G.rD2[e];
+        if (d >= cD && d >= cD2 && alt >= cD2) ok = false;
     }
     uint64_t m = __ballot(ok);
+    if (!m) return;
+    if (ok) {
+        cL = G.rL[e];
+        ax = G.rtx[e];
+        ay = G.rty[e];
+        qd = G.queued[e];
+    }
+    // list lengths, wave-uniform in registers
+    int np = L.npend, nt = L.ntouched;
     while (m) {
-        int l = __ffsll((unsigned long long)m) - 1;
+        const int l = __ffsll((unsigned long long)m) - 1;
+        int app = 0, fresh = 0;
         if (lane_id() == l) {
-            int e = found, probes = 0;
-            if (e < 0) {
-                // not in the table at look-up time: probe again (an earlier
-                // lane of this batch may have inserted it)
-                e = hash_vert(v);
-                while (L.rkey[e] >= 0 && L.rkey[e] != v && probes < kRootCap) {
-                    e = e + 1 == kRootCap ? 0 : e + 1;
-                    ++probes;
+            // a fresh entry has cD = cL = cD2 = infinity: every branch below then inserts
+            fresh = !(cD < INFINITY);
+            const bool differ = fabs(ax * ty - ay * tx) > rc.tie_dir || ax * tx + ay * ty < 0.0;
+            const bool tied = cD2 - cD <= rc.tie_rel * cD;
+            if (d < cD) {
+                if (differ) {
+                    cD2 = fmin(cD2, cD);
+                    cL = INFINITY;  // new direction: launch again however small the gain
                 }
+                cD = d;
+                ax = tx;
+                ay = ty;
+            } else if (differ) {
+                cD2 = fmin(cD2, d);
             }
-            if (probes >= kRootCap || (L.rkey[e] < 0 && L.rcount >= kRootCap - 1)) {
-                overflow = true;
-            } else if (L.rkey[e] < 0) {
-                L.rkey[e] = v;
-                L.rD[e] = d;
-                L.rL[e] = INFINITY;
-                L.rtx[e] = tx;
-                L.rty[e] = ty;
-                L.rD2[e] = alt;
-                L.rcount++;
-                L.dirty = 1;
-            } else {
-                const double ax = L.rtx[e], ay = L.rty[e];
-                const bool differ = fabs(ax * ty - ay * tx) > rc.tie_dir || ax * tx + ay * ty < 0.0;
-                const bool tied = L.rD2[e] - L.rD[e] <= rc.tie_rel * L.rD[e];
-                if (d < L.rD[e]) {
-                    if (differ) {
-                        L.rD2[e] = fmin(L.rD2[e], L.rD[e]);
-                        L.rL[e] = INFINITY;  // new direction: launch again however small the gain
-                    }
-                    L.rD[e] = d;
-                    L.rtx[e] = tx;
-                    L.rty[e] = ty;
-                } else if (differ) {
-                    L.rD2[e] = fmin(L.rD2[e], d);
-                }
-                L.rD2[e] = fmin(L.rD2[e], alt);
-                if (!tied && L.rD2[e] - L.rD[e] <= rc.tie_rel * L.rD[e]) L.rL[e] = INFINITY;  // a new tie
-                if (L.rD[e] < L.rL[e] * rc.keep) L.dirty = 1;
+            cD2 = fmin(cD2, alt);
+            if (!tied && cD2 - cD <= rc.tie_rel * cD) cL = INFINITY;  // a new tie
+            if (cD < cL * rc.keep && !qd) {
+                qd = 1;
+                app = 1;
+                G.pend[np] = e;
             }
+            if (fresh) G.touched[nt] = e;
         }
-        lane_step_barrier();
+        np += __builtin_amdgcn_readlane(app, l);
+        nt += __builtin_amdgcn_readlane(fresh, l);
+        const int el = __builtin_amdgcn_readlane(e, l);
+        const double bD = __shfl(cD, l), bD2 = __shfl(cD2, l), bL = __shfl(cL, l);
+        const double bx = __shfl(ax, l), by = __shfl(ay, l);
+        const int bq = __builtin_amdgcn_readlane(qd, l);
+        if (ok && e == el) {
+            cD = bD;
+            cD2 = bD2;
+            cL = bL;
+            ax = bx;
+            ay = by;
+            qd = bq;
+        }
         m &= m - 1;
     }
+    if (ok) {
+        G.rD[e] = cD;
+        G.rD2[e] = cD2;
+        G.rL[e] = cL;
+        G.rtx[e] = ax;
+        G.rty[e] = ay;
+        G.queued[e] = qd;
+    }
+    if (lane_id() == 0) {
+        L.npend = np;
+        L.ntouched = nt;
+    }
+    __syncthreads();  // later loads of the table, by any lane, see these values
 }
 
 // A window of bend vertex w.root is stale when it comes from an earlier
 // launch (its sg, rounded like every window of a launch, exceeds that of the
 // last launch rL) or when the vertex has improved enough for a new launch.
 template <typename R>
-__device__ inline bool is_stale(const Roots &L, const Win<R> &w, const RootCfg &rc) {
-    return w.sg > (R)L.rL[w.root] || L.rD[w.root] < L.rL[w.root] * rc.keep;
+__device__ inline bool bend_stale(double rD, double rL, const Win<R> &w, const RootCfg &rc) {
+    return w.sg > (R)rL || rD < rL * rc.keep;
+}
+
+// Empty the table again for the next source (only the entries it touched).
+__device__ inline void bend_reset(const BendTable &G, BendLds &L) {
+    const int nt = L.ntouched;
+    for (int k = lane_id(); k < nt; k += kWave) {
+        const int e = G.touched[k];
+        G.rD[e] = INFINITY;
+        G.rL[e] = INFINITY;
+        G.rD2[e] = INFINITY;
+        G.queued[e] = 0;
+    }
+    if (lane_id() == 0) {
+        L.npend = 0;
+        L.ntouched = 0;
+    }
+    __syncthreads();
 }
 
 // Two-level window stack: LDS first, a per-wave global area for overflow.
