@@ -43,15 +43,18 @@ WORKLOAD_TEXT = {
           "edges, Brownian kT=0.1 friction=1 dt=0.005",
 }
 
-PMC_FILE = os.path.join(ROOT, "profiles", "k_geodesic_bumpy_sphere_n1000_fp32mixed_pmc.json")
+def pmc_file(precision):
+    tag = "fp64" if precision == "fp64" else "fp32mixed"
+    return os.path.join(ROOT, "profiles", f"k_geodesic_bumpy_sphere_n1000_{tag}_pmc.json")
 
 
-def measured_traffic():
-    """HBM bytes per k_geodesic launch from the committed counter runs, or
-    None once the kernel source differs from the one the counters saw."""
+def measured_traffic(precision):
+    """HBM bytes per k_geodesic launch from the committed counter runs of the
+    bumpy-sphere workload in this precision, or None once the kernel source
+    differs from the one the counters saw."""
     import hashlib
     try:
-        rec = json.load(open(PMC_FILE))
+        rec = json.load(open(pmc_file(precision)))
         src = b"".join(open(os.path.join(ROOT, f), "rb").read() for f in rec["sources_hashed"])
     except (OSError, KeyError):
         return None
@@ -298,7 +301,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32"])
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
+                    help="precision of the headline line (the other one is timed beside it unless --no-compare)")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "torus_nve", "vsweep"],
                     help="c2: bumpy sphere N=1000 (the default line); c3: 16 surfaces batched; "
                          "c4: open height field N=20000, Brownian; torus_nve: NVE cost vs N on the benchmark torus; "
@@ -392,7 +396,7 @@ def main():
         "windows_per_step": win_per_launch,
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
                      "frac": achieved / peak,
-                     "traffic": measured_traffic() if (args.precision, args.workload) == ("fp32", "c2") else None,
+                     "traffic": measured_traffic(args.precision) if args.workload == "c2" else None,
                      "kernel": "k_geodesic", "per_unit": f"{FLOPS_PER_WINDOW:.0f} flop/window",
                      "units_per_launch": win_per_launch, "avg_launch_ms": geo_ms},
     }

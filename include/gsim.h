@@ -204,7 +204,8 @@ gsim_status gsim_step_batched(gsim_ctx *ctx, int32_t nmesh, const int32_t *mesh_
  * Knobs of the geodesic kernel (set by the autotuner or by hand; results stay
  * exact, only the amount of work or the launch shape changes):
  *   "launch_delta"  bend-vertex launch bucket width (0 = half the mean edge)
- *   "stack_cap"     window-stack capacity per resident wavefront (64 .. 4M)
+ *   "stack_cap"     window-stack capacity per resident wavefront, cutoff passes
+ *                   (64 .. 4M records of 64 bytes; default 16384)
  *   "max_slots"     resident wavefronts of the persistent grid (1 .. 65536)
  *   "max_windows"   per-source work limit (GSIM_E_LIMIT beyond it)
  *   "cone_tol"      closed-cone slack relative to the edge length
@@ -252,8 +253,8 @@ gsim_status gsim_timing_get(gsim_ctx *ctx, const char *name, double *avg_ms, int
  * [1] windows pruned, [2] bend-vertex (pseudo-source) launches,
  * [3] stale windows dropped, [4] sources recomputed in FP64 (FP32-mixed
  * guard band), [5] neighbour pairs,
- * [6] sources over a work limit, [10] deepest window stack of a source in
- * all-pairs passes (records). Summed over the calls since timing was last
+ * [6] sources over a work limit, [10] deepest window stack of a source
+ * (records, LDS and overflow together). Summed over the calls since timing was last
  * enabled: [7] neighbour pairs, [8] windows, [9] passes. c[11]. */
 gsim_status gsim_counters_get(gsim_ctx *ctx, int64_t *c);
 /* Per-source profile of the geodesic kernel, accumulated over the calls

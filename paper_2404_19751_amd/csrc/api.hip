@@ -100,6 +100,7 @@ struct gsim_ctx {
     int64_t roots_stride = 0;
     int32_t roots_rcap = 0, roots_slots = 0;
     int max_lds = 65536;  // LDS bytes one workgroup may use
+    int lds_cu = 163840;  // LDS bytes of one compute unit
     // graphs
     int graph_steps = 50;  // steps captured per graph (0: no graphs)
     std::map<std::string, GraphRec> graphs;
@@ -222,10 +223,9 @@ gsim_status end_call(gsim_ctx *c) {
         return fail(c, GSIM_E_LIMIT,
                     std::to_string(over + (long long)c->last.limited) +
                         " source(s) exceeded a per-source limit (more than " + std::to_string(kCandCap) +
-                        " candidate targets within the cutoff, more than 254 bend vertices within it, window stack "
-                        "or window count); the results of this call are incomplete. Passes of the whole-mesh kernel "
-                        "(the \"whole_mesh\" knob, up to " + std::to_string(kAllPairsMax) +
-                        " particles) have neither of the first two limits");
+                        " candidate targets within the cutoff, window stack or window count); the results of this "
+                        "call are incomplete. Passes of the whole-mesh kernel (the \"whole_mesh\" knob, up to " +
+                        std::to_string(kAllPairsMax) + " particles) have no limit on candidates");
     return GSIM_OK;
 }
 
@@ -459,6 +459,18 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
     B.shape.lds_stack_kb = c->lds_stack_kb;
     B.shape.nslots = B.nslots;
     B.shape.grab = c->grab;
+    B.shape.pad_lds = 0;
+    if (!B.all) {
+        // fewer sources than resident slots: pad each workgroup's LDS so that
+        // at most the needed number fit on a compute unit and the grid spreads
+        // over all of them instead of filling some
+        const int want = (B.nslots + c->cus - 1) / c->cus;
+        const size_t stat = geodesic_lds_bytes(c->lds_stack_kb, fp32);
+        if (want < per_cu && want > 0) {
+            const size_t each = (size_t)c->lds_cu / (size_t)want;
+            if (each > stat) B.shape.pad_lds = (int32_t)std::min(each - stat, (size_t)c->max_lds - stat);
+        }
+    }
     const int cap_rec = B.all ? c->stack_cap_all : c->gp.stack_cap;
     HIPCHK(c, ensure(c->stack, (size_t)std::max(B.nslots, 1) * cap_rec * 64));
     if (B.all) HIPCHK(c, ensure(c->vdist, sizeof(double) * (size_t)std::max(B.nslots, 1) * B.vstride));
@@ -727,6 +739,9 @@ gsim_status gsim_create(int device, gsim_precision prec, void *hip_stream, gsim_
     int lds = 0;
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, device) == hipSuccess && lds > 0)
         c->max_lds = lds;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device) == hipSuccess &&
+        lds > 0)
+        c->lds_cu = lds;
     c->gp.cutoff = 0.0;
     c->gp.launch_delta = 1e300;  // one bucket: every improved bend vertex once the stack drains
     c->gp.cone_tol = 1e-12;
@@ -742,7 +757,7 @@ gsim_status gsim_create(int device, gsim_precision prec, void *hip_stream, gsim_
     c->gp.dom_rel = 1e-12;
     c->gp.dom_rel32 = 1e-4;  // FP32 window chains across a whole surface carry errors up to ~1e-5
     c->gp.eager = 0;
-    c->gp.stack_cap = 2048;
+    c->gp.stack_cap = 16384;  // 1 MiB of overflow per resident wavefront (wide patches run deep)
     c->gp.max_windows = 4000000;
     c->max_windows_all = 1 << 26;
     if (ensure(c->work, sizeof(int32_t) * 16) != hipSuccess || ensure(c->ctr, sizeof(Counters)) != hipSuccess ||

@@ -206,6 +206,7 @@ struct GeoShape {
     int32_t lds_stack_kb;  // LDS window stack per wavefront: 4, 8 or 16 KiB
     int32_t nslots;        // resident wavefronts of the persistent grid
     int32_t grab;          // consecutive sources a wavefront claims at a time
+    int32_t pad_lds;       // extra LDS bytes per workgroup (spreads a small grid over every compute unit)
 };
 
 // Candidate search (Euclidean prefilter) and geodesics for every source of

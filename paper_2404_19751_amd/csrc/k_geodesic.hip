@@ -203,6 +203,7 @@ __device__ inline void children(const He<R> &h, const Win<R> &w, double txc, boo
 struct SrcStats {
     unsigned long long windows, launches, stale, guards;
     int pruned;
+    int depth;  // deepest window stack (records)
     bool overflow;
 };
 
@@ -584,6 +585,7 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
         ++iters;
         if (__ballot(overflow)) overflow = true;
         if (overflow) break;
+        st.depth = max(st.depth, S.lsp + S.gsp);
         bool busy = S.refill(have, w);
         // bend-vertex launches: eagerly whenever the table is dirty, else
         // once nothing is left to propagate
@@ -609,6 +611,7 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
         He<R> H;
         double txc = 0.0;
         double F3[3][3], U3[3][3];
+        double wtx = 0.0, wty = 0.0, wD2 = INFINITY;  // the root's tangent and other-direction distance
         int f = -1, k = 0;
         if (have) {
             // the records depend only on the entry half-edge and the root:
@@ -621,6 +624,9 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
             if (w.root >= 0) {
                 rD = G.rD[w.root];
                 rL = G.rL[w.root];
+                wtx = G.rtx[w.root];
+                wty = G.rty[w.root];
+                wD2 = G.rD2[w.root];
             }
             // stale: the window comes from an earlier launch of its root, or
             // the root has improved enough to be launched again (the same
@@ -632,6 +638,9 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
             }
             txc = (double)w.px + ((double)H.cx - (double)w.px) * (-(double)w.py) / ((double)H.cy - (double)w.py);
         }
+        // the third vertex's bend-vertex number, loaded now so that the target
+        // queries cover its latency
+        const int pe3 = have && H.pseudo ? sd.m.pidx[H.opp] : -1;
         // targets in face f
         {
             int slot = have ? first_in_face(L, f) : -1;
@@ -654,9 +663,9 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
                             tx = (double)(w.c * dx - w.s * dy);
                             ty = (double)(w.s * dx + w.c * dy);
                         } else {
-                            tx = G.rtx[w.root];
-                            ty = G.rty[w.root];
-                            alt = G.rD2[w.root] + (double)l;
+                            tx = wtx;
+                            ty = wty;
+                            alt = wD2 + (double)l;
                         }
                     }
                 }
@@ -681,14 +690,13 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
                         tx = (double)(w.c * dx - w.s * dy);
                         ty = (double)(w.s * dx + w.c * dy);
                     } else {
-                        tx = G.rtx[w.root];
-                        ty = G.rty[w.root];
-                        alt = G.rD2[w.root] + (double)l;
+                        tx = wtx;
+                        ty = wty;
+                        alt = wD2 + (double)l;
                     }
                 }
             }
-            const int pe = ok ? sd.m.pidx[H.opp] : -1;
-            bend_update(G, L.B, C.rc, ok, pe, d, tx, ty, alt);
+            bend_update(G, L.B, C.rc, ok, pe3, d, tx, ty, alt);
         }
         if (have) children(H, w, txc, false, C, F3, U3, L, cl, hl, cr, hr, pruned);
         // keep one child in the lane, push the other
@@ -758,6 +766,7 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
     SrcStats st;
     st.windows = st.launches = st.stale = st.guards = 0;
     st.pruned = 0;
+    st.depth = 0;
     st.overflow = false;
     unsigned long long c_limited = 0;
     int next = 0, left = 0;  // claimed sources not yet processed
@@ -815,15 +824,16 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
         atomicAdd(&a.ctr->launches, st.launches);
         atomicAdd(&a.ctr->stale, sl);
         atomicAdd(&a.ctr->limited, c_limited);
+        atomicMax(&a.ctr->max_depth, (unsigned long long)st.depth);
         if (st.guards) atomicAdd(&a.ctr->guards, st.guards);
     }
 }
 
 template <bool kMixed>
-void launch_variant(int kb, int nslots, const GeoArgs &a, hipStream_t s) {
-    if (kb <= 4) hipLaunchKernelGGL((k_geodesic<kMixed, 4096>), dim3(nslots), dim3(kWave), 0, s, a);
-    else if (kb <= 8) hipLaunchKernelGGL((k_geodesic<kMixed, 8192>), dim3(nslots), dim3(kWave), 0, s, a);
-    else hipLaunchKernelGGL((k_geodesic<kMixed, 16384>), dim3(nslots), dim3(kWave), 0, s, a);
+void launch_variant(int kb, int nslots, size_t pad, const GeoArgs &a, hipStream_t s) {
+    if (kb <= 4) hipLaunchKernelGGL((k_geodesic<kMixed, 4096>), dim3(nslots), dim3(kWave), pad, s, a);
+    else if (kb <= 8) hipLaunchKernelGGL((k_geodesic<kMixed, 8192>), dim3(nslots), dim3(kWave), pad, s, a);
+    else hipLaunchKernelGGL((k_geodesic<kMixed, 16384>), dim3(nslots), dim3(kWave), pad, s, a);
 }
 
 }  // namespace
@@ -843,8 +853,9 @@ hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoPa
     a.rstride = rstride;
     a.rcap = rcap;
     if (shape.nslots < 1 || bi.begin[bi.nsurf] < 1) return hipSuccess;
-    if (fp32) launch_variant<true>(shape.lds_stack_kb, shape.nslots, a, s);
-    else launch_variant<false>(shape.lds_stack_kb, shape.nslots, a, s);
+    const size_t pad = shape.pad_lds > 0 ? (size_t)shape.pad_lds : 0;
+    if (fp32) launch_variant<true>(shape.lds_stack_kb, shape.nslots, pad, a, s);
+    else launch_variant<false>(shape.lds_stack_kb, shape.nslots, pad, a, s);
     return hipGetLastError();
 }
 
