@@ -227,11 +227,8 @@ __global__ __launch_bounds__(128) void k_walk(DevMesh m, int n, int32_t *__restr
 // particle's neighbour row (Sec. 3.1 force sum), the displacement of the
 // integrator (Sec. 2.1), and the walk (Sec. 3.2). Rows hold only distances
 // and tangents computed before any particle moves, so particles are
-// independent here. One thread per particle of the flattened batch.
-__global__ __launch_bounds__(256) void k_update_batch(const SurfDesc *__restrict__ desc, BatchIdx bi,
-                                                     unsigned long long *__restrict__ npairs) {
-    const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= bi.begin[bi.nsurf]) return;
+// independent here. Returns the particle's neighbour-pair count.
+__device__ inline int update_one(const SurfDesc *__restrict__ desc, const BatchIdx &bi, int g) {
     const int si = batch_surface(bi, g);
     const SurfDesc &sd = desc[si];
     const int i = g - bi.begin[si];
@@ -279,7 +276,18 @@ __global__ __launch_bounds__(256) void k_update_batch(const SurfDesc *__restrict
     sd.vel[3 * i + 1] = v.y;
     sd.vel[3 * i + 2] = v.z;
     if (sd.wflags) sd.wflags[i] = fl;
-    if (np && npairs) atomicAdd(npairs, (unsigned long long)np);
+    return np;
+}
+
+// One thread per particle of the flattened batch.
+__global__ __launch_bounds__(256) void k_update_batch(const SurfDesc *__restrict__ desc, BatchIdx bi,
+                                                     unsigned long long *__restrict__ npairs) {
+    const int g = blockIdx.x * blockDim.x + threadIdx.x;
+    const int np = g < bi.begin[bi.nsurf] ? update_one(desc, bi, g) : 0;
+    // the pair count: one atomic per wavefront, not one per particle
+    unsigned long long t = (unsigned long long)np;
+    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
+    if ((threadIdx.x & 63) == 0 && t && npairs) atomicAdd(npairs, t);
 }
 
 }  // namespace
