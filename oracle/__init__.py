@@ -5,8 +5,9 @@ benchmark's ``cpu_baseline`` leg may import this package. It shares no code
 with the HIP library (``paper_2404_19751_amd``) and never calls it.
 
 The heavy parts (mesh structure, brute-force unfolding geodesics, the shift
-walk, Philox) are plain C in ``oracle.c``; the force sum and the integrators
-are written here in numpy, each following the passage it cites.
+walk, Philox, the restricted Voronoi neighbours of Sec. 5) are plain C in
+``oracle.c``; the force sum and the integrators are written here in numpy,
+each following the passage it cites.
 """
 from __future__ import annotations
 
@@ -61,6 +62,8 @@ def lib():
         L.orc_walk.argtypes = [P, C.c_int, P, P, P, P, P, P]
         L.orc_walk.restype = C.c_int
         L.orc_philox4x32_10.argtypes = [P, P, P]
+        L.orc_voronoi_pairs.argtypes = [P, C.c_int, P, C.c_double, P]
+        L.orc_voronoi_pairs.restype = C.c_int
         _lib = L
     return _lib
 
@@ -340,3 +343,28 @@ def verlet_step(mesh: OracleMesh, face, bary, vel, potential_cfg: dict, integ: d
     v = np.array(vel, np.float64, copy=True) + dt * F
     f2, b2, v2, st, fl = walk(mesh, face, bary, dt * v, v)
     return f2, b2, v2, dict(pairs=pr, F=F, E=E, walk=st, walk_flags=fl)
+
+
+def positions(mesh: OracleMesh, face, bary):
+    """3D points of (face, barycentric) positions: the barycentric
+    combination of the face's vertices (Sec. 3.2 particle state)."""
+    T = mesh.T[np.asarray(face)]
+    return np.einsum("ik,ikd->id", np.asarray(bary, np.float64), mesh.V[T])
+
+
+def voronoi_neighbours(mesh: OracleMesh, face, bary, tol_rel=1e-10):
+    """Restricted Voronoi neighbours of the particles on the surface (Sec. 5,
+    the in-surface Voronoi diagram from which the paper counts each
+    particle's neighbours): a boolean n x n adjacency matrix. Two particles
+    are neighbours when the surface points equidistant (3D) from both and no
+    farther from either than from any other particle form a set longer than
+    tol_rel times the mean edge length."""
+    xyz = np.ascontiguousarray(positions(mesh, face, bary))
+    n = len(xyz)
+    adj = np.zeros((n, n), np.uint8)
+    lbar = float(np.mean(np.linalg.norm(mesh.V[mesh.T[:, [1, 2, 0]]] - mesh.V[mesh.T], axis=2)))
+    rc = lib().orc_voronoi_pairs(mesh._h, n, _p(xyz), tol_rel * lbar, _p(adj))
+    if rc:
+        raise ValueError("bad argument")
+    return adj.astype(bool)
+

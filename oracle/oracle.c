@@ -877,3 +877,164 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
     }
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
+
+/* ------------------------------------------------------------------------
+ * Restricted Voronoi neighbours (Sec. 5: the in-surface Voronoi diagram,
+ * generated there as a restricted Euclidean Voronoi diagram, whose cells
+ * give each particle's number of neighbours). The plain definition: the cell
+ * of particle i is the set of surface points no farther (3D distance) from
+ * x_i than from any other particle; i and j are neighbours when the surface
+ * points equidistant from x_i and x_j and no farther from them than from any
+ * other particle form a set of positive length. In one triangle that set is
+ * the triangle cut by the bisector plane of x_i and x_j, clipped by the
+ * half-spaces {|x - x_i| <= |x - x_k|} of every other particle k.
+ * ---------------------------------------------------------------------- */
+
+/* squared distance from p to the triangle (a, b, c): the closest point is a
+ * vertex, a point of an edge, or the projection into the interior */
+static double point_tri_dist2(const double *p, const double *a, const double *b, const double *c) {
+    double ab[3], ac[3], ap[3], q[3];
+    sub3(b, a, ab);
+    sub3(c, a, ac);
+    sub3(p, a, ap);
+    const double d1 = dot3(ab, ap), d2 = dot3(ac, ap);
+    if (d1 <= 0.0 && d2 <= 0.0) return dot3(ap, ap);
+    double bp[3];
+    sub3(p, b, bp);
+    const double d3 = dot3(ab, bp), d4 = dot3(ac, bp);
+    if (d3 >= 0.0 && d4 <= d3) return dot3(bp, bp);
+    const double vc = d1 * d4 - d3 * d2;
+    if (vc <= 0.0 && d1 >= 0.0 && d3 <= 0.0) {
+        const double v = d1 / (d1 - d3);
+        for (int k = 0; k < 3; ++k) q[k] = a[k] + v * ab[k];
+    } else {
+        double cp[3];
+        sub3(p, c, cp);
+        const double d5 = dot3(ab, cp), d6 = dot3(ac, cp);
+        if (d6 >= 0.0 && d5 <= d6) return dot3(cp, cp);
+        const double vb = d5 * d2 - d1 * d6;
+        if (vb <= 0.0 && d2 >= 0.0 && d6 <= 0.0) {
+            const double w = d2 / (d2 - d6);
+            for (int k = 0; k < 3; ++k) q[k] = a[k] + w * ac[k];
+        } else {
+            const double va = d3 * d6 - d5 * d4;
+            if (va <= 0.0 && (d4 - d3) >= 0.0 && (d5 - d6) >= 0.0) {
+                const double w = (d4 - d3) / ((d4 - d3) + (d5 - d6));
+                for (int k = 0; k < 3; ++k) q[k] = b[k] + w * (c[k] - b[k]);
+            } else {
+                const double den = 1.0 / (va + vb + vc);
+                const double v = vb * den, w = vc * den;
+                for (int k = 0; k < 3; ++k) q[k] = a[k] + ab[k] * v + ac[k] * w;
+            }
+        }
+    }
+    double d[3];
+    sub3(p, q, d);
+    return dot3(d, d);
+}
+
+static double dist2(const double *a, const double *b) {
+    double d[3];
+    sub3(a, b, d);
+    return dot3(d, d);
+}
+
+int orc_voronoi_pairs(const orc_mesh *m, int n, const double *xyz, double tol, unsigned char *adj) {
+    if (!m || n < 2 || !xyz || !adj) return 1;
+    memset(adj, 0, (size_t)n * (size_t)n);
+    int *cand = (int *)malloc(sizeof(int) * (size_t)n);
+    if (!cand) return 1;
+    for (int f = 0; f < m->nf; ++f) {
+        const double *A = m->V + 3 * (size_t)m->T[3 * f], *B = m->V + 3 * (size_t)m->T[3 * f + 1],
+                     *Cv = m->V + 3 * (size_t)m->T[3 * f + 2];
+        const double *P[3] = {A, B, Cv};
+        /* a particle can be nearest somewhere in the triangle only if its
+         * distance to the triangle is at most the smallest, over particles,
+         * of the farthest vertex distance (distance is convex, so the
+         * farthest point of the triangle is a vertex) */
+        double mT2 = INFINITY;
+        for (int j = 0; j < n; ++j) {
+            double far2 = 0.0;
+            for (int k = 0; k < 3; ++k) {
+                const double d2 = dist2(P[k], xyz + 3 * (size_t)j);
+                if (d2 > far2) far2 = d2;
+            }
+            if (far2 < mT2) mT2 = far2;
+        }
+        int nc = 0;
+        for (int i = 0; i < n; ++i)
+            if (point_tri_dist2(xyz + 3 * (size_t)i, A, B, Cv) <= mT2 * (1.0 + 1e-9)) cand[nc++] = i;
+        for (int a = 0; a < nc; ++a)
+            for (int b = a + 1; b < nc; ++b) {
+                const int i = cand[a], j = cand[b];
+                const double *xi = xyz + 3 * (size_t)i, *xj = xyz + 3 * (size_t)j;
+                if (adj[(size_t)i * n + j]) continue;
+                /* bisector plane: g(x) = 2 (xj - xi).x - (|xj|^2 - |xi|^2) */
+                double nrmv[3];
+                sub3(xj, xi, nrmv);
+                const double rhs = dot3(xj, xj) - dot3(xi, xi);
+                double g[3];
+                for (int k = 0; k < 3; ++k) g[k] = 2.0 * dot3(nrmv, P[k]) - rhs;
+                if (g[0] == 0.0 && g[1] == 0.0 && g[2] == 0.0) continue; /* triangle in the plane */
+                double pts[6][3];
+                int np = 0;
+                for (int k = 0; k < 3; ++k) {
+                    const int k2 = (k + 1) % 3;
+                    if (g[k] == 0.0) {
+                        memcpy(pts[np++], P[k], sizeof(double) * 3);
+                    } else if ((g[k] < 0.0 && g[k2] > 0.0) || (g[k] > 0.0 && g[k2] < 0.0)) {
+                        const double t = g[k] / (g[k] - g[k2]);
+                        for (int d = 0; d < 3; ++d) pts[np][d] = P[k][d] + t * (P[k2][d] - P[k][d]);
+                        ++np;
+                    }
+                }
+                if (np < 2) continue;
+                /* the segment between the two points farthest apart */
+                int s0 = 0, s1 = 1;
+                double best = -1.0;
+                for (int u = 0; u < np; ++u)
+                    for (int v = u + 1; v < np; ++v) {
+                        const double d2 = dist2(pts[u], pts[v]);
+                        if (d2 > best) {
+                            best = d2;
+                            s0 = u;
+                            s1 = v;
+                        }
+                    }
+                const double *S = pts[s0], *E = pts[s1];
+                double dir[3];
+                sub3(E, S, dir);
+                const double len = norm3(dir);
+                if (!(len > tol)) continue;
+                /* clip t in [0, 1] by |x - xi|^2 <= |x - xk|^2 for every other k:
+                 * 2 (xk - xi).x <= |xk|^2 - |xi|^2, linear in t */
+                double t0 = 0.0, t1 = 1.0;
+                for (int k = 0; k < n && t0 < t1; ++k) {
+                    if (k == i || k == j) continue;
+                    const double *xk = xyz + 3 * (size_t)k;
+                    double w[3];
+                    sub3(xk, xi, w);
+                    const double c = dot3(xk, xk) - dot3(xi, xi);
+                    const double h0 = 2.0 * dot3(w, S) - c;    /* at t = 0; allowed where <= 0 */
+                    const double h1 = 2.0 * dot3(w, dir);      /* slope */
+                    if (h1 == 0.0) {
+                        if (h0 > 0.0) t1 = t0 - 1.0;
+                    } else {
+                        const double tz = -h0 / h1;
+                        if (h1 > 0.0) {
+                            if (tz < t1) t1 = tz;
+                        } else {
+                            if (tz > t0) t0 = tz;
+                        }
+                    }
+                }
+                if ((t1 - t0) * len > tol) {
+                    adj[(size_t)i * n + j] = 1;
+                    adj[(size_t)j * n + i] = 1;
+                }
+            }
+    }
+    free(cand);
+    return 0;
+}
+

@@ -19,7 +19,11 @@
  *    trimming, and the shortest kept (Dijkstra over the bend vertices);
  *  - the per-particle straight walk across faces with parallel transport of
  *    the velocity (Sec. 3.2, the shift algorithm and its steps (a)-(d));
- *  - Philox4x32-10 (Salmon et al., SC'11) for Brownian noise (Sec. 2.1).
+ *  - Philox4x32-10 (Salmon et al., SC'11) for Brownian noise (Sec. 2.1);
+ *  - the in-surface (restricted Euclidean) Voronoi neighbours of the
+ *    particles, from which Sec. 5 counts coordination numbers and defects:
+ *    per triangle, the bisector segment of every candidate pair clipped by
+ *    the half-spaces of every other particle.
  */
 #ifndef GSIM_ORACLE_H
 #define GSIM_ORACLE_H
@@ -62,6 +66,12 @@ void orc_pairs_free(orc_pairs *p);
  * NULL): bit0 vertex hit, bit1 near-vertex pass, bit2 cap hit, bit3 boundary. */
 int orc_walk(const orc_mesh *m, int n, int *face, double *bary, const double *disp, double *vel, int64_t *stats,
              uint8_t *flags);
+
+/* Restricted Voronoi neighbours (Sec. 5): adj[n][n] = 1 where the surface
+ * points equidistant (3D) from particles i and j and no farther from them
+ * than from any other particle form a set longer than tol. xyz[n][3] are
+ * points on the mesh. 0 = ok, 1 = bad argument. */
+int orc_voronoi_pairs(const orc_mesh *m, int n, const double *xyz, double tol, unsigned char *adj);
 
 /* Philox4x32-10: out[4] for counter ctr[4] and key key[2]. */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
