@@ -296,6 +296,88 @@ def bench_vsweep(args, gsim, W):
             "results": out}
 
 
+def bench_quench(args, gsim, W):
+    """The crystallization study of Sec. 5 as a batched workload: 64
+    independent gradient-descent quenches of N = 500 particles on the
+    aspect-3 torus (each its own surface of one batch, stepped by one launch
+    per stage and replayed from HIP graphs), against the same quenches one
+    surface at a time; then the in-surface Voronoi neighbours of every
+    relaxed state give the 5- and 7-fold defects, the net defect charge
+    sum(6 - z) (zero on a torus) and its split between the inner (negative
+    Gaussian curvature) and outer halves of the torus."""
+    M = 64
+    ws = [W.workload(f"quench_{k}") for k in range(M)]
+    w0 = ws[0]
+    p, wi = w0.potential, w0.integrator
+    pot = gsim.potential("harmonic", p["k"], p["sigma"], p["cutoff"])
+    ig = gsim.integrator("overdamped", wi["dt"], wi["mobility"])
+    steps = w0.steps
+    ctx = gsim.Context(0, "fp64")
+    mids = []
+    for w in ws:
+        mid = ctx.mesh_upload(w.mesh.V, w.mesh.T)
+        ctx.particles_set(mid, w.face, w.bary)
+        mids.append(mid)
+    ctx.step_batched(mids, [pot] * M, [ig] * M, 2)  # warm-up, graph capture
+    for mid, w in zip(mids, ws):
+        ctx.particles_set(mid, w.face, w.bary)
+    ctx.synchronize()
+    t0 = time.perf_counter()
+    ctx.step_batched(mids, [pot] * M, [ig] * M, steps)
+    ctx.synchronize()
+    t_batch = time.perf_counter() - t0
+    print(f"[quench] {M} tori x {steps} steps batched: {t_batch:.3f} s", file=sys.stderr, flush=True)
+    # one surface at a time (4 of them, scaled)
+    t_single = 0.0
+    for k in range(4):
+        c1 = gsim.Context(0, "fp64")
+        m1 = c1.mesh_upload(ws[k].mesh.V, ws[k].mesh.T)
+        c1.particles_set(m1, ws[k].face, ws[k].bary)
+        c1.step(m1, pot, ig, 2)
+        c1.particles_set(m1, ws[k].face, ws[k].bary)
+        c1.synchronize()
+        t0 = time.perf_counter()
+        c1.step(m1, pot, ig, steps)
+        c1.synchronize()
+        t_single += time.perf_counter() - t0
+        c1.close()
+    t_single *= M / 4
+    # defects of the relaxed states
+    R = 3.0
+    t0 = time.perf_counter()
+    n5 = n7 = 0
+    q_in = q_out = 0.0
+    n_in = n_out = 0
+    net = []
+    for mid in mids:
+        off, nbr = ctx.voronoi_neighbours(mid)
+        z = np.diff(off)
+        _, _, _, xyz = ctx.particles_get(mid)
+        rho = np.hypot(xyz[:, 0], xyz[:, 1])
+        q = 6 - z
+        n5 += int((z == 5).sum())
+        n7 += int((z == 7).sum())
+        net.append(int(q.sum()))
+        q_in += float(q[rho < R].sum())
+        q_out += float(q[rho >= R].sum())
+        n_in += int((rho < R).sum())
+        n_out += int((rho >= R).sum())
+    t_vor = time.perf_counter() - t0
+    ctx.close()
+    n = 500
+    return {"workload": "64 gradient-descent quenches of N=500 on the aspect-3 torus (R=3, r=1, 4648 faces), harmonic "
+                        "repulsion of range 1.2 lattice spacings, 400 steps each; in-surface Voronoi defects",
+            "data": "synthetic", "precision": "fp64",
+            "batched": {"quenches_per_s": M / t_batch, "particle_steps_per_s": M * n * steps / t_batch,
+                        "ms_per_step": 1e3 * t_batch / steps},
+            "one_surface_at_a_time": {"quenches_per_s": M / t_single, "particle_steps_per_s": M * n * steps / t_single},
+            "batched_speedup": t_single / t_batch,
+            "voronoi_ms_per_surface": 1e3 * t_vor / M,
+            "defects": {"five_fold_per_quench": n5 / M, "seven_fold_per_quench": n7 / M,
+                        "net_charge_per_quench": sorted(set(net)),
+                        "mean_charge_inner_half": q_in / max(n_in, 1), "mean_charge_outer_half": q_out / max(n_out, 1)}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -303,10 +385,11 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
                     help="precision of the headline line (the other one is timed beside it unless --no-compare)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "torus_nve", "vsweep"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "torus_nve", "vsweep", "quench"],
                     help="c2: bumpy sphere N=1000 (the default line); c3: 16 surfaces batched; "
                          "c4: open height field N=20000, Brownian; torus_nve: NVE cost vs N on the benchmark torus; "
-                         "vsweep: NVE cost vs mesh size at N=100, full mesh and submeshed")
+                         "vsweep: NVE cost vs mesh size at N=100, full mesh and submeshed; "
+                         "quench: 64 batched torus quenches with Voronoi defect statistics")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
@@ -338,6 +421,9 @@ def main():
         return
     if args.workload == "vsweep":
         print(json.dumps(bench_vsweep(args, gsim, W)), flush=True)
+        return
+    if args.workload == "quench":
+        print(json.dumps(bench_quench(args, gsim, W)), flush=True)
         return
     w = W.workload(args.workload)
     pot = gsim.potential("harmonic", w.potential["k"], w.potential["sigma"], w.potential["cutoff"])

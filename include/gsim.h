@@ -167,6 +167,20 @@ gsim_status gsim_particles_get_dev(gsim_ctx *ctx, int32_t mesh_id, int32_t *face
  * the CSR is then copied to the caller's host buffers. */
 gsim_status gsim_geodesic_pairs(gsim_ctx *ctx, int32_t mesh_id, double cutoff, gsim_pairs *out);
 
+/* voronoi_neighbours: the in-surface Voronoi neighbours of the particles
+ * (Sec. 5: the restricted Euclidean Voronoi diagram on the surface, from
+ * which coordination numbers and 5/7-fold defects are read). The cell of a
+ * particle is the set of surface points no farther (3D distance) from it
+ * than from any other particle; two particles are neighbours when their cells
+ * share a boundary longer than 1e-10 mean edge lengths. Output CSR in host
+ * buffers: off[n+1] (int64), nbr[count] (int32, ascending per row, both
+ * directions present). count receives the number of entries; capacity is
+ * nbr's length (GSIM_E_CAPACITY, with count filled in, when too small).
+ * At most 32768 particles; GSIM_E_LIMIT when a face has more than 64
+ * candidate particles or a cell piece more than 16 vertices. */
+gsim_status gsim_voronoi_neighbours(gsim_ctx *ctx, int32_t mesh_id, int64_t *off, int32_t *nbr, int64_t capacity,
+                                    int64_t *count);
+
 /* compute_forces: F_i = sum_j U'(d_ij) t_ij (Sec. 3.1 force sum; with t_ij
  * pointing from i towards j a repulsive potential pushes i away from j) and
  * E = (1/2) sum_i sum_j U(d_ij). force[n][3] host buffer; energy may be NULL.

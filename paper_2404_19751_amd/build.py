@@ -8,7 +8,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "_libgsim.so")
-SOURCES = ["api.hip", "mesh_build.cpp", "k_util.hip", "k_geodesic.hip", "k_allpairs.hip", "k_walk.hip"]
+SOURCES = ["api.hip", "mesh_build.cpp", "k_util.hip", "k_geodesic.hip", "k_allpairs.hip", "k_walk.hip",
+           "k_voronoi.hip"]
 ARCH = os.environ.get("GSIM_OFFLOAD_ARCH", "gfx950")
 
 

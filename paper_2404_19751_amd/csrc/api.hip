@@ -32,6 +32,7 @@ struct Buf {
 struct MeshState {
     HostMesh host;
     DevMesh dm;
+    double area = 0.0;  // surface area (computed when first needed)
     // particles
     int n = 0;
     int32_t *face = nullptr;
@@ -71,7 +72,7 @@ struct gsim_ctx {
     bool own_stream = false;
     std::string err;
     std::vector<MeshState *> meshes;
-    Buf stack, work, ctr, wstats, scan_scratch, sum_scratch, pf_over, prof, desc, vdist, roots, partials;
+    Buf stack, work, ctr, wstats, scan_scratch, sum_scratch, pf_over, prof, desc, vdist, roots, partials, vbits;
     SurfDesc *desc_pinned = nullptr;  // staging for descriptor uploads
     std::vector<SurfDesc> desc_cached;
     bool profile_sources = false;
@@ -796,7 +797,7 @@ void gsim_destroy(gsim_ctx *c) {
         delete ms;
     }
     for (Buf *b : {&c->stack, &c->work, &c->ctr, &c->wstats, &c->scan_scratch, &c->sum_scratch, &c->pf_over,
-                   &c->prof, &c->desc, &c->vdist, &c->roots, &c->partials})
+                   &c->prof, &c->desc, &c->vdist, &c->roots, &c->partials, &c->vbits})
         release(*b);
     if (c->desc_pinned) (void)hipHostFree(c->desc_pinned);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -1003,6 +1004,96 @@ gsim_status gsim_geodesic_pairs(gsim_ctx *c, int32_t id, double cutoff, gsim_pai
             HIPCHK(c, hipMemcpyAsync(out->tan, ms->tan.p, sizeof(double) * 3 * P_, hipMemcpyDeviceToHost, s));
             if (out->flags) HIPCHK(c, hipMemcpyAsync(out->flags, ms->flags.p, P_, hipMemcpyDeviceToHost, s));
         }
+        HIPCHK(c, hipStreamSynchronize(s));
+        return GSIM_OK;
+    } catch (...) {
+        return fail(c, GSIM_E_ARG, "unexpected host error");
+    }
+}
+
+gsim_status gsim_voronoi_neighbours(gsim_ctx *c, int32_t id, int64_t *off, int32_t *nbr, int64_t capacity,
+                                    int64_t *count) {
+    MeshState *ms = get_mesh(c, id);
+    if (!ms || !off || !count) return fail(c, GSIM_E_ARG, "bad arguments");
+    const int n = ms->n;
+    if (n < 2) return fail(c, GSIM_E_STATE, "fewer than two particles on this mesh");
+    if (n > kVoronoiMax)
+        return fail(c, GSIM_E_LIMIT, "Voronoi neighbours hold at most " + std::to_string(kVoronoiMax) + " particles");
+    try {
+        hipStream_t s = c->stream;
+        const DevMesh &m = ms->dm;
+        if (!(ms->area > 0.0)) {
+            double A = 0.0;
+            const HostMesh &H = ms->host;
+            for (int f = 0; f < H.nf; ++f) {
+                const double *p0 = &H.V[3 * (size_t)H.T[3 * f]], *p1 = &H.V[3 * (size_t)H.T[3 * f + 1]],
+                             *p2 = &H.V[3 * (size_t)H.T[3 * f + 2]];
+                const double u[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+                const double v[3] = {p2[0] - p0[0], p2[1] - p0[1], p2[2] - p0[2]};
+                const double x = u[1] * v[2] - u[2] * v[1], y = u[2] * v[0] - u[0] * v[2], z = u[0] * v[1] - u[1] * v[0];
+                A += 0.5 * std::sqrt(x * x + y * y + z * z);
+            }
+            ms->area = A;
+        }
+        // particle cell grid: cells about one and a half mean spacings wide
+        int dims[3];
+        double cell;
+        choose_grid(m, 1.5 * std::sqrt(ms->area / n), false, dims, cell);
+        const int64_t ncell = (int64_t)dims[0] * dims[1] * dims[2];
+        HIPCHK(c, ensure(ms->cell_of, sizeof(int32_t) * n));
+        HIPCHK(c, ensure(ms->cell_start, sizeof(int32_t) * (ncell + 1)));
+        HIPCHK(c, ensure(ms->cell_fill, sizeof(int32_t) * ncell));
+        HIPCHK(c, ensure(ms->order, sizeof(int32_t) * n));
+        HIPCHK(c, ensure(ms->tmp64, sizeof(int64_t) * (std::max<int64_t>(ncell, n) + 1)));
+        HIPCHK(c, ensure(c->scan_scratch, sizeof(int64_t) * ((std::max<int64_t>(ncell, n) + 1023) / 1024 + 2)));
+        const int64_t words = (n + 63) / 64;
+        HIPCHK(c, ensure(c->vbits, sizeof(unsigned long long) * (size_t)n * words));
+        HIPCHK(c, ensure(ms->nbr_cnt, sizeof(int32_t) * (n + 1)));
+        HIPCHK(c, ensure(ms->off, sizeof(int64_t) * (n + 1)));
+        HIPCHK(c, ensure(c->wstats, sizeof(unsigned long long) * 8));
+        PrefilterBufs pb{};
+        pb.xyz = ms->xyz;
+        pb.cell_of = P<int32_t>(ms->cell_of);
+        pb.cell_start = P<int32_t>(ms->cell_start);
+        pb.cell_fill = P<int32_t>(ms->cell_fill);
+        pb.order = P<int32_t>(ms->order);
+        pb.cap_c = kCandCap;
+        for (int k = 0; k < 3; ++k) pb.dims[k] = dims[k];
+        pb.cell = cell;
+        int32_t *err = P<int32_t>(c->wstats);
+        {
+            Stage st(c, "voronoi");
+            HIPCHK(c, launch_xyz(m, n, ms->face, ms->bary, ms->xyz, s));
+            HIPCHK(c, launch_prefilter_bin(m, n, pb, s));
+            HIPCHK(c, launch_scan_i32_to_i64(pb.cell_fill, P<int64_t>(ms->tmp64), (int)ncell,
+                                             P<int64_t>(c->scan_scratch), s));
+            HIPCHK(c, launch_i64_to_i32(P<int64_t>(ms->tmp64), pb.cell_start, (int)ncell, s));
+            HIPCHK(c, launch_zero_i32(pb.cell_fill, ncell, s));
+            HIPCHK(c, launch_bin_scatter(n, pb, s));
+            HIPCHK(c, launch_zero_u64(P<unsigned long long>(c->vbits), (int64_t)n * words, s));
+            HIPCHK(c, launch_zero_i32(err, 2, s));
+            HIPCHK(c, launch_voronoi_faces(m, n, ms->xyz, pb.cell_start, pb.order, dims, m.bbmin, cell,
+                                           P<unsigned long long>(c->vbits), words, 1e-10 * m.mean_edge, err, s));
+            HIPCHK(c, launch_voronoi_count(P<unsigned long long>(c->vbits), n, words, P<int32_t>(ms->nbr_cnt), s));
+            HIPCHK(c, launch_scan_i32_to_i64(P<int32_t>(ms->nbr_cnt), P<int64_t>(ms->off), n,
+                                             P<int64_t>(c->scan_scratch), s));
+        }
+        int32_t errs[2] = {0, 0};
+        int64_t total = 0;
+        HIPCHK(c, hipMemcpyAsync(errs, err, sizeof(errs), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(&total, P<int64_t>(ms->off) + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        if (errs[0] || errs[1])
+            return fail(c, GSIM_E_LIMIT, std::to_string(errs[0]) + " face(s) with more than 64 candidate particles, " +
+                                             std::to_string(errs[1]) + " cell piece(s) with more than 16 vertices");
+        *count = total;
+        if (capacity < total || (total && !nbr))
+            return fail(c, GSIM_E_CAPACITY, "neighbour buffer too small: " + std::to_string(total) + " needed");
+        HIPCHK(c, ensure(ms->nbr, sizeof(int32_t) * (total + 1)));
+        HIPCHK(c, launch_voronoi_fill(P<unsigned long long>(c->vbits), n, words, P<int64_t>(ms->off), P<int32_t>(ms->nbr),
+                                      s));
+        HIPCHK(c, hipMemcpyAsync(off, ms->off.p, sizeof(int64_t) * (n + 1), hipMemcpyDeviceToHost, s));
+        if (total) HIPCHK(c, hipMemcpyAsync(nbr, ms->nbr.p, sizeof(int32_t) * total, hipMemcpyDeviceToHost, s));
         HIPCHK(c, hipStreamSynchronize(s));
         return GSIM_OK;
     } catch (...) {

@@ -222,6 +222,18 @@ hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoPa
 hipError_t launch_geodesic_all(const SurfDesc *desc, const BatchIdx &bi, const GeoParams &gp, const GeoShape &shape,
                                char *stack_mem, double *vdist, int64_t vstride, char *roots, int64_t rstride,
                                int rcap, int tcap, int32_t *work_ctr, Counters *ctr, bool fp32, hipStream_t s);
+// In-surface Voronoi neighbours (k_voronoi.hip): at most kVoronoiMax
+// particles (an n x n adjacency bitset). launch_voronoi_faces marks every
+// pair of particles whose cells share a boundary longer than tol; cell lists
+// of a grid with origin lo (cell size `cell`, dims) over xyz; err[0] counts
+// faces with too many candidates, err[1] cells with too many vertices.
+constexpr int kVoronoiMax = 32768;
+hipError_t launch_voronoi_faces(const DevMesh &m, int n, const double *xyz, const int32_t *cell_start,
+                                const int32_t *order, const int dims[3], const double lo[3], double cell,
+                                unsigned long long *bits, int64_t words, double tol, int32_t *err, hipStream_t s);
+hipError_t launch_voronoi_count(const unsigned long long *bits, int n, int64_t words, int32_t *cnt, hipStream_t s);
+hipError_t launch_voronoi_fill(const unsigned long long *bits, int n, int64_t words, const int64_t *off, int32_t *nbr,
+                               hipStream_t s);
 // Bytes of one wavefront's bend-vertex table for rcap bend vertices (both
 // geodesic kernels): five doubles and four int32 each, rounded up to 256
 // bytes.

@@ -26,7 +26,7 @@ EXPORTS = ["gsim_create", "gsim_destroy", "gsim_last_error", "gsim_synchronize",
            "gsim_mesh_info_get", "gsim_particles_set", "gsim_particles_get", "gsim_particles_set_dev",
            "gsim_particles_get_dev", "gsim_geodesic_pairs", "gsim_compute_forces", "gsim_displace_on_surface",
            "gsim_step", "gsim_timing_enable", "gsim_timing_get", "gsim_counters_get", "gsim_tune_set",
-           "gsim_source_profile", "gsim_step_batched", "gsim_autotune"]
+           "gsim_source_profile", "gsim_step_batched", "gsim_autotune", "gsim_voronoi_neighbours"]
 
 
 class GsimError(RuntimeError):
@@ -88,6 +88,7 @@ def load(path: str = LIB_PATH):
         "gsim_particles_get_dev": ([V, C.c_int32, V, V, V], C.c_int),
         "gsim_geodesic_pairs": ([V, C.c_int32, C.c_double, C.POINTER(PairsT)], C.c_int),
         "gsim_compute_forces": ([V, C.c_int32, C.POINTER(PotentialT), V, V], C.c_int),
+        "gsim_voronoi_neighbours": ([V, C.c_int32, V, V, C.c_int64, V], C.c_int),
         "gsim_displace_on_surface": ([V, C.c_int32, V, C.c_int, C.POINTER(WalkStatsT)], C.c_int),
         "gsim_step": ([V, C.c_int32, C.POINTER(PotentialT), C.POINTER(IntegratorT), C.c_int32], C.c_int),
         "gsim_timing_enable": ([V, C.c_int], C.c_int),
@@ -227,6 +228,18 @@ class Context:
         E = C.c_double()
         self._chk(self.L.gsim_compute_forces(self.h, mid, C.byref(pot), _ptr(F), C.c_void_p(C.addressof(E))))
         return F, E.value
+
+    def voronoi_neighbours(self, mid):
+        """In-surface Voronoi neighbours: (off[n+1], nbr) CSR, rows ascending."""
+        n = self._n[mid]
+        off = np.empty(n + 1, np.int64)
+        cnt = C.c_int64(0)
+        st = self.L.gsim_voronoi_neighbours(self.h, mid, _ptr(off), None, 0, C.byref(cnt))
+        if st not in (OK, E_CAPACITY):
+            self._chk(st)
+        nbr = np.empty(max(cnt.value, 1), np.int32)
+        self._chk(self.L.gsim_voronoi_neighbours(self.h, mid, _ptr(off), _ptr(nbr), cnt.value, C.byref(cnt)))
+        return off, nbr[:cnt.value]
 
     def displace_on_surface(self, mid, disp, transport_velocity=True) -> dict:
         disp = np.ascontiguousarray(disp, np.float64)

@@ -445,6 +445,10 @@ def workload(name: str) -> "Workload | list[Workload]":
     vsweep_<surface>_<level>  a mesh of the fixed-N sweep (VSWEEP), N = 100
         (seed 11), harmonic repulsion of range span / 10 with that cutoff,
         velocity Verlet dt = range / 200, from rest.
+    quench_<k>  quench k of the crystallization study (Sec. 5): the aspect-3
+        benchmark torus, N = 500 (seed 200 + k), harmonic repulsion of range
+        1.2 lattice spacings of a triangular lattice of that density,
+        gradient descent (overdamped, dt = 0.05 range^2), 400 steps.
     """
     if name == "c1":
         m = icosphere(3)
@@ -489,6 +493,15 @@ def workload(name: str) -> "Workload | list[Workload]":
         f, b = random_particles(m.nf, 100, 11)
         return Workload(name, m, f, b, dict(kind="harmonic", k=1.0, sigma=rng, cutoff=rng),
                         dict(kind="verlet", dt=rng / 200.0), 10, mean_edge_length(m))
+    if name.startswith("quench_"):
+        k = int(name.split("_")[1])
+        m = benchmark_torus()
+        n = 500
+        f, b = random_particles(m.nf, n, 200 + k)
+        a = math.sqrt(2.0 * surface_area(m) / (math.sqrt(3.0) * n))
+        sig = 1.2 * a
+        return Workload(name, m, f, b, dict(kind="harmonic", k=1.0, sigma=sig, cutoff=sig),
+                        dict(kind="overdamped", dt=0.05 * sig * sig, mobility=1.0), 400, mean_edge_length(m))
     if name in ("c5a", "c5b"):
         m = icosphere(6) if name == "c5a" else ellipsoid(6)
         f, b = random_particles(m.nf, 2000, 4 if name == "c5a" else 5)

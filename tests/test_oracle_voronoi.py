@@ -26,7 +26,7 @@ def test_icosahedron_points_have_five_neighbours(orc):
 def test_cube_face_centres_are_octahedral(orc):
     """The 6 face centres of a cube: each neighbours the 4 centres of the
     adjacent faces and not the opposite one."""
-    m = W.cube(4)
+    m = W.cube(3)
     om = orc.OracleMesh(m.V, m.T)
     c = 0.5 * (m.V.min(0) + m.V.max(0))
     h = 0.5 * (m.V.max(0) - m.V.min(0))
