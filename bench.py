@@ -296,6 +296,51 @@ def bench_vsweep(args, gsim, W):
             "results": out}
 
 
+def bench_c5(args, gsim, W):
+    """All-pairs Coulomb with FIRE on the icosphere L6 (81,920 faces, N = 2000):
+    every iteration propagates every source over the whole mesh (3,998,000
+    pairs). Two timed iterations per precision after one warm-up; the CPU
+    oracle is timed on a sample of sources and scaled to all 2000."""
+    import math
+    w = W.workload("c5a")
+    wi = w.integrator
+    pot = gsim.potential("coulomb", 1.0, 1.0, math.inf)
+    ig = gsim.integrator("fire", wi["dt"], max_disp=wi["max_disp"])
+    n = len(w.face)
+    out = {}
+    for prec in ("fp64", "fp32"):
+        ctx = gsim.Context(0, prec)
+        mid = ctx.mesh_upload(w.mesh.V, w.mesh.T)
+        ctx.particles_set(mid, w.face, w.bary)
+        ctx.step(mid, pot, ig, 1)
+        ctx.synchronize()
+        ctx.timing(True)
+        t0 = time.perf_counter()
+        ctx.step(mid, pot, ig, 2)
+        ctx.synchronize()
+        dt = time.perf_counter() - t0
+        c = ctx.counters()
+        geo = ctx.timing_get("geodesic")[0]
+        ctx.close()
+        out[prec] = {"pairs_per_s": 2 * n * (n - 1) / dt, "s_per_iteration": dt / 2, "geodesic_ms": geo,
+                     "windows_per_iteration": c["cum_windows"] / 2, "windows_per_s": c["cum_windows"] / dt}
+        print(f"[c5] {prec}: {dt / 2:.3f} s per iteration", file=sys.stderr, flush=True)
+    line = {"workload": "C5: icosphere L6 (81920 faces), N=2000, Coulomb all pairs, FIRE", "data": "synthetic",
+            "pairs_per_iteration": n * (n - 1), "results": out}
+    if not args.no_cpu_baseline:
+        import numpy as np
+        import oracle
+        om = oracle.OracleMesh(w.mesh.V, w.mesh.T)
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        src = (np.arange(threads, dtype=np.int32) * (n // threads)).astype(np.int32)  # one source per thread
+        t0 = time.perf_counter()
+        oracle.geodesic_pairs(om, w.face, w.bary, math.inf, sources=src)
+        t = time.perf_counter() - t0
+        line["cpu_baseline"] = {"value": len(src) * (n - 1) / t, "unit": "pairs/s", "cores": threads,
+                                "kind": "oracle", "sample": f"rows of {len(src)} sources over the whole mesh, {t:.1f} s"}
+    return line
+
+
 def bench_quench(args, gsim, W):
     """The crystallization study of Sec. 5 as a batched workload: 64
     independent gradient-descent quenches of N = 500 particles on the
@@ -385,11 +430,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
                     help="precision of the headline line (the other one is timed beside it unless --no-compare)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "torus_nve", "vsweep", "quench"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "torus_nve", "vsweep", "quench"],
                     help="c2: bumpy sphere N=1000 (the default line); c3: 16 surfaces batched; "
                          "c4: open height field N=20000, Brownian; torus_nve: NVE cost vs N on the benchmark torus; "
                          "vsweep: NVE cost vs mesh size at N=100, full mesh and submeshed; "
-                         "quench: 64 batched torus quenches with Voronoi defect statistics")
+                         "quench: 64 batched torus quenches with Voronoi defect statistics; "
+                         "c5: all-pairs Coulomb FIRE on the L6 sphere")
     ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison leg")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
@@ -424,6 +470,9 @@ def main():
         return
     if args.workload == "quench":
         print(json.dumps(bench_quench(args, gsim, W)), flush=True)
+        return
+    if args.workload == "c5":
+        print(json.dumps(bench_c5(args, gsim, W)), flush=True)
         return
     w = W.workload(args.workload)
     pot = gsim.potential("harmonic", w.potential["k"], w.potential["sigma"], w.potential["cutoff"])

@@ -673,7 +673,11 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
                 if (slot >= 0) slot = next_in_face(L, slot, f);
             }
         }
-        // third vertex as a bend vertex
+        // third vertex as a bend vertex: the candidate now, its table entry
+        // loaded now and applied after the children (whose arithmetic covers
+        // the load's latency)
+        bool ok3 = false;
+        double d3 = 0, tx3 = 0, ty3 = 0, alt3 = INFINITY, pD = INFINITY, pD2 = INFINITY;
         {
             bool ok = false;
             double d = 0, tx = 0, ty = 0, alt = INFINITY;
@@ -696,9 +700,18 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
                     }
                 }
             }
-            bend_update(G, L.B, C.rc, ok, pe3, d, tx, ty, alt);
+            ok3 = ok;
+            d3 = d;
+            tx3 = tx;
+            ty3 = ty;
+            alt3 = alt;
+            if (ok) {
+                pD = G.rD[pe3];
+                pD2 = G.rD2[pe3];
+            }
         }
         if (have) children(H, w, txc, false, C, F3, U3, L, cl, hl, cr, hr, pruned);
+        bend_update_loaded(G, L.B, C.rc, ok3, pe3, d3, tx3, ty3, alt3, pD, pD2);
         // keep one child in the lane, push the other
         S.push(hl && hr, cr, overflow);
         if (have) {

@@ -163,14 +163,18 @@ struct BendLds {
 // cannot change anything (the stored distances only decrease); the others
 // are applied one lane at a time in registers, each result passed to every
 // lane holding the same vertex, and written back once.
-__device__ inline void bend_update(const BendTable &G, BendLds &L, const RootCfg &rc, bool ok, int e, double d,
-                                   double tx, double ty, double alt) {
-    double cD = INFINITY, cD2 = INFINITY, cL = INFINITY, ax = 0.0, ay = 0.0;
+// bend_update_loaded takes the entry's rD and rD2 loaded by the caller
+// (earlier, so that their latency overlaps other work; no other update of
+// the table may come in between).
+__device__ inline void bend_update_loaded(const BendTable &G, BendLds &L, const RootCfg &rc, bool ok, int e, double d,
+                                          double tx, double ty, double alt, double cD, double cD2) {
+    double cL = INFINITY, ax = 0.0, ay = 0.0;
     int qd = 1;
-    if (ok) {
-        cD = G.rD[e];
-        cD2 = G.rD2[e];
-        if (d >= cD && d >= cD2 && alt >= cD2) ok = false;
+    if (!ok) {
+        cD = INFINITY;
+        cD2 = INFINITY;
+    } else if (d >= cD && d >= cD2 && alt >= cD2) {
+        ok = false;
     }
     uint64_t m = __ballot(ok);
     if (!m) return;
@@ -239,6 +243,15 @@ __device__ inline void bend_update(const BendTable &G, BendLds &L, const RootCfg
         L.ntouched = nt;
     }
     __syncthreads();  // later loads of the table, by any lane, see these values
+}
+__device__ inline void bend_update(const BendTable &G, BendLds &L, const RootCfg &rc, bool ok, int e, double d,
+                                   double tx, double ty, double alt) {
+    double cD = INFINITY, cD2 = INFINITY;
+    if (ok) {
+        cD = G.rD[e];
+        cD2 = G.rD2[e];
+    }
+    bend_update_loaded(G, L, rc, ok, e, d, tx, ty, alt, cD, cD2);
 }
 
 // A window of bend vertex w.root is stale when it comes from an earlier
