@@ -39,11 +39,13 @@
 // one region of the mesh); each lane holds one live window in registers; a
 // lane with two children keeps one and pushes the other onto an LDS window
 // stack (ballot/popcount compaction; a per-wave global overflow area takes
-// what does not fit); idle lanes pop. Target and bend-vertex tables live in
-// LDS; their updates are serialised across lanes by a ballot loop (no
-// atomics, deterministic in wave order). The LDS stack depth is a template
-// parameter: a shallower stack lowers the workgroup's LDS footprint and lets
-// more wavefronts share a compute unit.
+// what does not fit); idle lanes pop. The target table lives in LDS and its
+// updates are serialised across lanes by a ballot loop (no atomics,
+// deterministic in wave order); the bend-vertex table is a per-wavefront
+// table in global memory indexed by the mesh's bend-vertex number (any
+// number of bend vertices per source), emptied through its touched list. The
+// LDS stack depth is a template parameter: a shallower stack lowers the
+// workgroup's LDS footprint and lets more wavefronts share a compute unit.
 //
 // Batches: the sources of several surfaces (each with its own mesh, cutoff
 // and particles) form one flattened index space served by the same
@@ -767,8 +769,8 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
     return any_near;
 }
 
-// Two waves per SIMD: with the LDS of five workgroups per compute unit, a
-// wavefront may hold at most 256 registers, or the fifth has nowhere to run.
+// Two waves per SIMD: with up to eight workgroups' LDS on a compute unit, a
+// wavefront may hold at most 256 registers.
 template <bool kMixed, int kStk>
 __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
     __shared__ Lds L;
