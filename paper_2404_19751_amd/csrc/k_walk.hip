@@ -58,8 +58,10 @@ __device__ inline void walk_one(const DevMesh &m, int &f, double b[3], d3 D, d3 
                 fl |= 4;
                 break;
             }
-            const int32_t *t = m.T + 3 * (int64_t)f;
-            d3 P[3] = {ld3(m.V + 3 * (int64_t)t[0]), ld3(m.V + 3 * (int64_t)t[1]), ld3(m.V + 3 * (int64_t)t[2])};
+            // the face's vertices in slot order (one record: no dependent
+            // load through the vertex indices)
+            const double *fp = m.fpos + 18 * (int64_t)f;
+            d3 P[3] = {ld3(fp), ld3(fp + 3), ld3(fp + 6)};
             nf = ld3(m.fnrm + 3 * (int64_t)f);
             double twoA = sqrt(dot(cross(P[1] - P[0], P[2] - P[0]), cross(P[1] - P[0], P[2] - P[0])));
             double rate[3], s[3];
@@ -84,7 +86,7 @@ __device__ inline void walk_one(const DevMesh &m, int &f, double b[3], d3 D, d3 
             if (gap <= kVertexTol * lbar) {
                 // through the vertex where b[k1] and b[k2] vanish together
                 const int ws = 3 - k1 - k2;
-                const int wv = t[ws];
+                const int wv = m.T[3 * (int64_t)f + ws];
                 rem -= s1;
                 ++vhit;
                 fl |= 1;

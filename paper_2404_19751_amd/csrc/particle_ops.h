@@ -38,18 +38,35 @@ __device__ inline void row_force(int i, const int32_t *__restrict__ cnt, int cap
     E = 0.0;
     np = 0;
     const int m = min(cnt[i], cap);
-    for (int s = 0; s < m; ++s) {
-        const int64_t p = (int64_t)i * cap + s;
-        const double d = dist[p];
-        if (!(d < cutoff)) continue;
+    auto add = [&](double d, double t0, double t1, double t2) {
+        if (!(d < cutoff)) return;
         ++np;
-        if (!(d > 0.0)) continue;
+        if (!(d > 0.0)) return;
         double U, dU;
         pair_potential(kind, d, k, sigma, U, dU);
-        F[0] += dU * tan[3 * p];
-        F[1] += dU * tan[3 * p + 1];
-        F[2] += dU * tan[3 * p + 2];
+        F[0] += dU * t0;
+        F[1] += dU * t1;
+        F[2] += dU * t2;
         E += 0.5 * U;
+    };
+    int s = 0;
+    // four entries' loads issued together, then summed in ascending order
+    for (; s + 4 <= m; s += 4) {
+        const int64_t p = (int64_t)i * cap + s;
+        double d[4], t[4][3];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            d[q] = dist[p + q];
+            t[q][0] = tan[3 * (p + q)];
+            t[q][1] = tan[3 * (p + q) + 1];
+            t[q][2] = tan[3 * (p + q) + 2];
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) add(d[q], t[q][0], t[q][1], t[q][2]);
+    }
+    for (; s < m; ++s) {
+        const int64_t p = (int64_t)i * cap + s;
+        add(dist[p], tan[3 * p], tan[3 * p + 1], tan[3 * p + 2]);
     }
 }
 
