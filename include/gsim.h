@@ -236,6 +236,9 @@ gsim_status gsim_step_batched(gsim_ctx *ctx, int32_t nmesh, const int32_t *mesh_
  *   "grab"          consecutive sources a wavefront claims at a time (1 .. 64)
  *   "update_block"  workgroup size of the fused update kernel: 64, 128 or 256
  *   "graph_steps"   steps captured per HIP graph in step calls (0 = no graphs)
+ *   "time_geodesic_only"  1: while timing is on, record events around the
+ *                   geodesic stage only (each event record costs the stream a few
+ *                   microseconds)
  *   "whole_mesh"    1: finite-cutoff passes also run on the whole-mesh kernel
  *                   below (windows pruned at the cutoff; no limit on candidates or
  *                   bend vertices per source; at most 4096 particles per surface)
@@ -259,8 +262,8 @@ gsim_status gsim_autotune(gsim_ctx *ctx, int32_t nmesh, const int32_t *mesh_ids,
 
 /* ---- instrumentation ------------------------------------------------------
  * Per-kernel timing with HIP events recorded on the context's stream, only
- * while enabled. name: "prefilter", "geodesic", "compact", "forces",
- * "integrate", "walk". avg_ms is the mean launch duration. */
+ * while enabled. name: "prefilter", "geodesic", "fire", "update", "compact",
+ * "forces", "walk", "voronoi". avg_ms is the mean duration of the stage. */
 gsim_status gsim_timing_enable(gsim_ctx *ctx, int on);
 gsim_status gsim_timing_get(gsim_ctx *ctx, const char *name, double *avg_ms, int64_t *launches);
 /* Work counters. Of the last call: [0] windows processed,

@@ -82,6 +82,7 @@ struct gsim_ctx {
     Counters last{};
     unsigned long long cum_pairs = 0, cum_windows = 0, cum_passes = 0;
     bool timing = false;
+    bool time_geodesic_only = false;  // time only the geodesic stage
     bool capturing = false;
     std::map<std::string, TimingRec> times;
     std::vector<std::pair<std::string, std::pair<hipEvent_t, hipEvent_t>>> pending;
@@ -172,13 +173,14 @@ void resolve_timing(gsim_ctx *c) {
 }
 
 // HIP events around one stage, only while timing is on (never inside a
-// graph capture).
+// graph capture). Every event record costs the stream a few microseconds, so
+// with `time_geodesic_only` only the geodesic stage is timed.
 struct Stage {
     gsim_ctx *c;
     const char *name;
     hipEvent_t a = nullptr, b = nullptr;
     Stage(gsim_ctx *c_, const char *n) : c(c_), name(n) {
-        if (c->timing && !c->capturing) {
+        if (c->timing && !c->capturing && (!c->time_geodesic_only || std::strcmp(n, "geodesic") == 0)) {
             a = take_event(c);
             b = take_event(c);
             if (a) (void)hipEventRecord(a, c->stream);
@@ -1360,6 +1362,7 @@ gsim_status gsim_tune_set(gsim_ctx *c, const char *name, double value) {
     else if (k == "dom_rel" && value >= 0.0) c->gp.dom_rel = value;
     else if (k == "dom_rel32" && value >= 0.0) c->gp.dom_rel32 = value;
     else if (k == "whole_mesh" && (value == 0.0 || value == 1.0)) c->whole_mesh = value != 0.0;
+    else if (k == "time_geodesic_only" && (value == 0.0 || value == 1.0)) c->time_geodesic_only = value != 0.0;
     else return fail(c, GSIM_E_ARG, "unknown tuning knob or value out of range: " + k);
     drop_graphs(c);
     return GSIM_OK;
