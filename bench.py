@@ -75,7 +75,7 @@ def measured_traffic(precision):
     return rec["traffic_bytes_per_launch"]
 
 
-def cpu_baseline(w, budget_s=8.0, max_steps=40):
+def cpu_baseline(w, budget_s=10.0, max_steps=500):
     import oracle
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     om = oracle.OracleMesh(w.mesh.V, w.mesh.T)

@@ -116,3 +116,34 @@ def test_voronoi_after_quench_torus(orc):
     assert int(np.sum(6 - z)) == 0
     log(f"[gpu-voronoi] quenched torus: 5-fold {int((z == 5).sum())}, 6-fold {int((z == 6).sum())}, "
         f"7-fold {int((z == 7).sum())}")
+
+
+def test_voronoi_api_limits():
+    """Two-phase capacity protocol, and the error paths: fewer than two
+    particles, and more than the bitset holds."""
+    import ctypes as C
+
+    from paper_2404_19751_amd import gsim
+    m = W.icosphere(3)
+    ctx = gsim.Context(0, "fp64")
+    try:
+        mid = ctx.mesh_upload(m.V, m.T)
+        f, b = W.random_particles(m.nf, 50, 103)
+        ctx.particles_set(mid, f, b)
+        off = np.empty(51, np.int64)
+        cnt = C.c_int64(0)
+        st = ctx.L.gsim_voronoi_neighbours(ctx.h, mid, off.ctypes.data_as(C.c_void_p), None, 0, C.byref(cnt))
+        assert st == gsim.E_CAPACITY and cnt.value > 0
+        off2, nbr = ctx.voronoi_neighbours(mid)
+        assert off2[-1] == cnt.value == len(nbr)
+        ctx.particles_set(mid, f[:1], b[:1])
+        with pytest.raises(gsim.GsimError) as e:
+            ctx.voronoi_neighbours(mid)
+        assert e.value.status == gsim.E_STATE
+        f2, b2 = W.random_particles(m.nf, 40000, 105)
+        ctx.particles_set(mid, f2, b2)
+        with pytest.raises(gsim.GsimError) as e:
+            ctx.voronoi_neighbours(mid)
+        assert e.value.status == gsim.E_LIMIT
+    finally:
+        ctx.close()
