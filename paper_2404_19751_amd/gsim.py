@@ -168,6 +168,7 @@ class Context:
         T = np.ascontiguousarray(T, np.int32)
         mid = C.c_int32()
         self._chk(self.L.gsim_mesh_upload(self.h, V.shape[0], _ptr(V), T.shape[0], _ptr(T), C.byref(mid)))
+        self._n[mid.value] = 0
         return mid.value
 
     def mesh_info(self, mid: int) -> dict:

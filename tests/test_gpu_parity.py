@@ -240,3 +240,48 @@ def test_bad_particles_rejected(ctx):
         ctx.particles_set(mid, np.array([m.nf + 3], np.int32), np.array([[0.2, 0.3, 0.5]]))
     with pytest.raises(gsim.GsimError):
         ctx.particles_set(mid, np.array([0], np.int32), np.array([[1.0, 0.0, 0.0]]))  # on a vertex
+
+
+def test_pairs_capacity_protocol_and_empty_state(ctx, orc):
+    """Two-phase output sizing through the C-ABI: a buffer one pair too small
+    returns E_CAPACITY with the required count and writes nothing past it;
+    the exact size then returns the same CSR as the binding. A mesh without
+    particles reports E_STATE; an empty particle set is an argument error."""
+    import ctypes as C
+
+    from paper_2404_19751_amd import gsim
+    w = W.workload("c1")
+    mid = ctx.mesh_upload(w.mesh.V, w.mesh.T)
+    with pytest.raises(gsim.GsimError) as e:
+        ctx.geodesic_pairs(mid, 0.3)
+    assert e.value.status == gsim.E_STATE
+    st = ctx.L.gsim_particles_set(ctx.h, mid, 0, np.zeros(1, np.int32).ctypes.data_as(C.c_void_p),
+                                  np.zeros(3).ctypes.data_as(C.c_void_p), None)
+    assert st == gsim.E_ARG
+    ctx.particles_set(mid, w.face, w.bary)
+    cut = w.potential["cutoff"]
+    ref = ctx.geodesic_pairs(mid, cut)
+    P = len(ref["nbr"])
+    assert P > 0
+    n = len(w.face)
+
+    def call(cap):
+        off = np.empty(n + 1, np.int64)
+        nbr = np.full(cap + 4, -7, np.int32)
+        dist = np.full(cap + 4, -7.0)
+        tan = np.full((cap + 4, 3), -7.0)
+        flags = np.full(cap + 4, 0xEE, np.uint8)
+        pt = gsim.PairsT(cap, 0, off.ctypes.data, nbr.ctypes.data, dist.ctypes.data, tan.ctypes.data,
+                         flags.ctypes.data)
+        st = ctx.L.gsim_geodesic_pairs(ctx.h, mid, float(cut), C.byref(pt))
+        return st, int(pt.count), off, nbr, dist, tan, flags
+
+    st, cnt, _, nbr, dist, _, flags = call(P - 1)
+    assert st == gsim.E_CAPACITY and cnt == P
+    assert np.all(nbr[P - 1:] == -7) and np.all(dist[P - 1:] == -7.0) and np.all(flags[P - 1:] == 0xEE)
+    st, cnt, off, nbr, dist, tan, flags = call(P)
+    assert st == gsim.OK and cnt == P
+    assert np.array_equal(off, ref["off"]) and np.array_equal(nbr[:P], ref["nbr"])
+    assert np.array_equal(dist[:P], ref["dist"]) and np.array_equal(tan[:P], ref["tan"])
+    assert np.array_equal(flags[:P], ref["flags"])
+    assert np.all(nbr[P:] == -7)

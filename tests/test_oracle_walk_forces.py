@@ -242,3 +242,19 @@ def test_overdamped_and_brownian_displacement(orc):
     ig2 = dict(ig, friction=2.0)
     D2 = orc.displacement(om, f, np.zeros((10, 3)), ig2, step=5)
     assert np.allclose(D2, D0 / math.sqrt(2.0), atol=1e-15)  # amplitude sqrt(2 kT dt / lambda)
+
+
+def test_force_error_scale_is_first_order_bound():
+    """The force-error scale used by the GPU comparisons, |U'| + d |U''|,
+    against central differences of the oracle's U' (away from the harmonic
+    cutoff's kink), for the three potentials."""
+    import oracle as orc
+    from tests.util import force_scale
+    d = np.linspace(0.05, 0.95, 37)
+    for kind in ("harmonic", "coulomb", "gaussian"):
+        h = 1e-6 * d
+        _, up = orc.potential(kind, d + h, 1.3, 1.0)
+        _, um = orc.potential(kind, d - h, 1.3, 1.0)
+        _, u0 = orc.potential(kind, d, 1.3, 1.0)
+        want = np.abs(u0) + d * np.abs((up - um) / (2 * h))
+        assert np.allclose(force_scale(kind, d, 1.3, 1.0), want, rtol=1e-6), kind

@@ -42,3 +42,20 @@ def interior_points(m, n, seed, margin=0.05):
     b = np.stack([1 - s, s * (1 - u[:, 2]), s * u[:, 2]], 1)
     b = margin + (1 - 3 * margin) * b
     return f, b
+
+
+def force_scale(kind, d, k, sigma):
+    """Per-pair scale of a force error: |U'(d)| + d |U''(d)|. A relative
+    error e in d and in d*t moves U'(d) t by at most about e times this, so a
+    force error is measured against its sum over a particle's pairs; |U'|
+    alone vanishes at the harmonic cutoff while U'' does not."""
+    d = np.asarray(d, np.float64)
+    if kind == "harmonic":
+        inside = d < sigma
+        return np.where(inside, (k / sigma) * np.abs(1.0 - d / sigma) + d * k / (sigma * sigma), 0.0)
+    if kind == "coulomb":
+        return k / (d * d) + 2.0 * k / (d * d)
+    if kind == "gaussian":
+        U = k * np.exp(-d * d / (2.0 * sigma * sigma))
+        return (d / (sigma * sigma)) * U + d * np.abs(d * d / sigma ** 4 - 1.0 / (sigma * sigma)) * U
+    raise KeyError(kind)
