@@ -110,10 +110,38 @@ struct gsim_ctx {
 
 namespace {
 
-gsim_status fail(gsim_ctx *c, gsim_status s, const std::string &msg) {
-    if (c) c->err = msg;
+// Records the message for gsim_last_error. Never throws: a message that
+// cannot be stored leaves the error text empty.
+gsim_status fail(gsim_ctx *c, gsim_status s, const std::string &msg) noexcept {
+    if (c) {
+        try {
+            c->err = msg;
+        } catch (...) {
+            c->err.clear();
+        }
+    }
     return s;
 }
+gsim_status fail(gsim_ctx *c, gsim_status s, const char *msg) noexcept {
+    if (c) {
+        try {
+            c->err = msg;
+        } catch (...) {
+            c->err.clear();
+        }
+    }
+    return s;
+}
+
+// The handlers that end every entry point's try block: no C++ exception
+// crosses the C ABI.
+#define GSIM_CATCH(c)                                                     \
+    catch (const std::bad_alloc &) {                                      \
+        return fail(c, GSIM_E_OOM, "host memory exhausted");              \
+    }                                                                     \
+    catch (...) {                                                         \
+        return fail(c, GSIM_E_ARG, "unexpected host error");              \
+    }
 
 #define HIPCHK(c, x)                                                                              \
     do {                                                                                          \
@@ -779,7 +807,10 @@ void gsim_destroy(gsim_ctx *c) {
     if (!c) return;
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
-    resolve_timing(c);
+    try {
+        resolve_timing(c);
+    } catch (...) {
+    }
     drop_graphs(c);
     for (auto e : c->free_events) (void)hipEventDestroy(e);
     for (MeshState *ms : c->meshes) {
@@ -809,9 +840,12 @@ void gsim_destroy(gsim_ctx *c) {
 const char *gsim_last_error(const gsim_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
 gsim_status gsim_synchronize(gsim_ctx *c) {
-    if (!c) return GSIM_E_ARG;
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    return GSIM_OK;
+    try {
+        if (!c) return GSIM_E_ARG;
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        return GSIM_OK;
+    }
+    GSIM_CATCH(c)
 }
 
 gsim_status gsim_mesh_upload(gsim_ctx *c, int32_t nv, const double *xyz, int32_t nf, const int32_t *tri,
@@ -867,21 +901,24 @@ gsim_status gsim_mesh_upload(gsim_ctx *c, int32_t nv, const double *xyz, int32_t
 }
 
 gsim_status gsim_mesh_info_get(gsim_ctx *c, int32_t id, gsim_mesh_info *out) {
-    MeshState *ms = get_mesh(c, id);
-    if (!ms || !out) return fail(c, GSIM_E_ARG, "unknown mesh id");
-    const DevMesh &d = ms->dm;
-    out->nv = d.nv;
-    out->nf = d.nf;
-    out->n_boundary_edges = d.n_boundary_edges;
-    out->n_pseudo_sources = d.n_pseudo;
-    out->mean_edge = d.mean_edge;
-    out->min_edge = d.min_edge;
-    out->max_edge = d.max_edge;
-    for (int k = 0; k < 3; ++k) {
-        out->bbox_min[k] = d.bbmin[k];
-        out->bbox_max[k] = d.bbmax[k];
+    try {
+        MeshState *ms = get_mesh(c, id);
+        if (!ms || !out) return fail(c, GSIM_E_ARG, "unknown mesh id");
+        const DevMesh &d = ms->dm;
+        out->nv = d.nv;
+        out->nf = d.nf;
+        out->n_boundary_edges = d.n_boundary_edges;
+        out->n_pseudo_sources = d.n_pseudo;
+        out->mean_edge = d.mean_edge;
+        out->min_edge = d.min_edge;
+        out->max_edge = d.max_edge;
+        for (int k = 0; k < 3; ++k) {
+            out->bbox_min[k] = d.bbmin[k];
+            out->bbox_max[k] = d.bbmax[k];
+        }
+        return GSIM_OK;
     }
-    return GSIM_OK;
+    GSIM_CATCH(c)
 }
 
 static gsim_status alloc_particles(gsim_ctx *c, MeshState *ms, int32_t n) {
@@ -928,58 +965,70 @@ static gsim_status reset_state(gsim_ctx *c, MeshState *ms, const double *vel, hi
 
 gsim_status gsim_particles_set(gsim_ctx *c, int32_t id, int32_t n, const int32_t *face, const double *bary,
                                const double *vel) {
-    MeshState *ms = get_mesh(c, id);
-    if (!ms || n < 1 || !face || !bary) return fail(c, GSIM_E_ARG, "bad particle arguments");
-    gsim_status st = check_state(c, ms, n, face, bary);
-    if (st != GSIM_OK) return st;
-    if ((st = alloc_particles(c, ms, n)) != GSIM_OK) return st;
-    hipStream_t s = c->stream;
-    HIPCHK(c, hipMemcpyAsync(ms->face, face, sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(ms->bary, bary, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s));
-    if ((st = reset_state(c, ms, vel, hipMemcpyHostToDevice)) != GSIM_OK) return st;
-    HIPCHK(c, hipStreamSynchronize(s));
-    return GSIM_OK;
+    try {
+        MeshState *ms = get_mesh(c, id);
+        if (!ms || n < 1 || !face || !bary) return fail(c, GSIM_E_ARG, "bad particle arguments");
+        gsim_status st = check_state(c, ms, n, face, bary);
+        if (st != GSIM_OK) return st;
+        if ((st = alloc_particles(c, ms, n)) != GSIM_OK) return st;
+        hipStream_t s = c->stream;
+        HIPCHK(c, hipMemcpyAsync(ms->face, face, sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(ms->bary, bary, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s));
+        if ((st = reset_state(c, ms, vel, hipMemcpyHostToDevice)) != GSIM_OK) return st;
+        HIPCHK(c, hipStreamSynchronize(s));
+        return GSIM_OK;
+    }
+    GSIM_CATCH(c)
 }
 
 gsim_status gsim_particles_set_dev(gsim_ctx *c, int32_t id, int32_t n, const int32_t *face, const double *bary,
                                    const double *vel) {
-    MeshState *ms = get_mesh(c, id);
-    if (!ms || n < 1 || !face || !bary) return fail(c, GSIM_E_ARG, "bad particle arguments");
-    gsim_status st = alloc_particles(c, ms, n);
-    if (st != GSIM_OK) return st;
-    hipStream_t s = c->stream;
-    HIPCHK(c, hipMemcpyAsync(ms->face, face, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
-    HIPCHK(c, hipMemcpyAsync(ms->bary, bary, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
-    return reset_state(c, ms, vel, hipMemcpyDeviceToDevice);
+    try {
+        MeshState *ms = get_mesh(c, id);
+        if (!ms || n < 1 || !face || !bary) return fail(c, GSIM_E_ARG, "bad particle arguments");
+        gsim_status st = alloc_particles(c, ms, n);
+        if (st != GSIM_OK) return st;
+        hipStream_t s = c->stream;
+        HIPCHK(c, hipMemcpyAsync(ms->face, face, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(ms->bary, bary, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
+        return reset_state(c, ms, vel, hipMemcpyDeviceToDevice);
+    }
+    GSIM_CATCH(c)
 }
 
 gsim_status gsim_particles_get(gsim_ctx *c, int32_t id, int32_t *face, double *bary, double *vel, double *xyz) {
-    MeshState *ms = get_mesh(c, id);
-    if (!ms) return fail(c, GSIM_E_ARG, "unknown mesh id");
-    if (ms->n <= 0) return fail(c, GSIM_E_STATE, "no particles on this mesh");
-    hipStream_t s = c->stream;
-    const int n = ms->n;
-    if (face) HIPCHK(c, hipMemcpyAsync(face, ms->face, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
-    if (bary) HIPCHK(c, hipMemcpyAsync(bary, ms->bary, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s));
-    if (vel) HIPCHK(c, hipMemcpyAsync(vel, ms->vel, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s));
-    if (xyz) {
-        HIPCHK(c, launch_xyz(ms->dm, n, ms->face, ms->bary, ms->xyz, s));
-        HIPCHK(c, hipMemcpyAsync(xyz, ms->xyz, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s));
+    try {
+        MeshState *ms = get_mesh(c, id);
+        if (!ms) return fail(c, GSIM_E_ARG, "unknown mesh id");
+        if (ms->n <= 0) return fail(c, GSIM_E_STATE, "no particles on this mesh");
+        hipStream_t s = c->stream;
+        const int n = ms->n;
+        if (face) HIPCHK(c, hipMemcpyAsync(face, ms->face, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+        if (bary) HIPCHK(c, hipMemcpyAsync(bary, ms->bary, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s));
+        if (vel) HIPCHK(c, hipMemcpyAsync(vel, ms->vel, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s));
+        if (xyz) {
+            HIPCHK(c, launch_xyz(ms->dm, n, ms->face, ms->bary, ms->xyz, s));
+            HIPCHK(c, hipMemcpyAsync(xyz, ms->xyz, sizeof(double) * 3 * n, hipMemcpyDeviceToHost, s));
+        }
+        HIPCHK(c, hipStreamSynchronize(s));
+        return GSIM_OK;
     }
-    HIPCHK(c, hipStreamSynchronize(s));
-    return GSIM_OK;
+    GSIM_CATCH(c)
 }
 
 gsim_status gsim_particles_get_dev(gsim_ctx *c, int32_t id, int32_t *face, double *bary, double *vel) {
-    MeshState *ms = get_mesh(c, id);
-    if (!ms) return fail(c, GSIM_E_ARG, "unknown mesh id");
-    if (ms->n <= 0) return fail(c, GSIM_E_STATE, "no particles on this mesh");
-    hipStream_t s = c->stream;
-    const int n = ms->n;
-    if (face) HIPCHK(c, hipMemcpyAsync(face, ms->face, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
-    if (bary) HIPCHK(c, hipMemcpyAsync(bary, ms->bary, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
-    if (vel) HIPCHK(c, hipMemcpyAsync(vel, ms->vel, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
-    return GSIM_OK;
+    try {
+        MeshState *ms = get_mesh(c, id);
+        if (!ms) return fail(c, GSIM_E_ARG, "unknown mesh id");
+        if (ms->n <= 0) return fail(c, GSIM_E_STATE, "no particles on this mesh");
+        hipStream_t s = c->stream;
+        const int n = ms->n;
+        if (face) HIPCHK(c, hipMemcpyAsync(face, ms->face, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
+        if (bary) HIPCHK(c, hipMemcpyAsync(bary, ms->bary, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
+        if (vel) HIPCHK(c, hipMemcpyAsync(vel, ms->vel, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
+        return GSIM_OK;
+    }
+    GSIM_CATCH(c)
 }
 
 gsim_status gsim_geodesic_pairs(gsim_ctx *c, int32_t id, double cutoff, gsim_pairs *out) {
@@ -1311,73 +1360,85 @@ gsim_status gsim_autotune(gsim_ctx *c, int32_t nmesh, const int32_t *mesh_ids, c
 }
 
 gsim_status gsim_timing_enable(gsim_ctx *c, int on) {
-    if (!c) return GSIM_E_ARG;
-    resolve_timing(c);
-    c->timing = on != 0;
-    if (on) {
-        c->times.clear();
-        c->cum_pairs = c->cum_windows = c->cum_passes = 0;
+    try {
+        if (!c) return GSIM_E_ARG;
+        resolve_timing(c);
+        c->timing = on != 0;
+        if (on) {
+            c->times.clear();
+            c->cum_pairs = c->cum_windows = c->cum_passes = 0;
+        }
+        return GSIM_OK;
     }
-    return GSIM_OK;
+    GSIM_CATCH(c)
 }
 
 gsim_status gsim_timing_get(gsim_ctx *c, const char *name, double *avg_ms, int64_t *launches) {
-    if (!c || !name) return GSIM_E_ARG;
-    resolve_timing(c);
-    auto it = c->times.find(name);
-    if (it == c->times.end()) {
-        if (avg_ms) *avg_ms = 0.0;
-        if (launches) *launches = 0;
+    try {
+        if (!c || !name) return GSIM_E_ARG;
+        resolve_timing(c);
+        auto it = c->times.find(name);
+        if (it == c->times.end()) {
+            if (avg_ms) *avg_ms = 0.0;
+            if (launches) *launches = 0;
+            return GSIM_OK;
+        }
+        if (avg_ms) *avg_ms = it->second.n ? it->second.total_ms / double(it->second.n) : 0.0;
+        if (launches) *launches = it->second.n;
         return GSIM_OK;
     }
-    if (avg_ms) *avg_ms = it->second.n ? it->second.total_ms / double(it->second.n) : 0.0;
-    if (launches) *launches = it->second.n;
-    return GSIM_OK;
+    GSIM_CATCH(c)
 }
 
 gsim_status gsim_tune_set(gsim_ctx *c, const char *name, double value) {
-    if (!c || !name) return GSIM_E_ARG;
-    std::string k(name);
-    if (k == "launch_delta") c->gp.launch_delta = value;
-    else if (k == "cone_tol" && value >= 0.0) c->gp.cone_tol = value;
-    else if (k == "tie_rel" && value >= 0.0) c->gp.tie_rel = value;
-    else if (k == "tie_dir" && value >= 0.0) c->gp.tie_dir = value;
-    else if (k == "eager") c->gp.eager = value != 0.0;
-    else if (k == "cone_tol32" && value >= 0.0) c->gp.cone_tol32 = value;
-    else if (k == "tie_rel32" && value >= 0.0) c->gp.tie_rel32 = value;
-    else if (k == "tie_dir32" && value >= 0.0) c->gp.tie_dir32 = value;
-    else if (k == "guard_rel" && value >= 0.0) c->gp.guard_rel = value;
-    else if (k == "root_rel32" && value >= 0.0 && value <= 1e-4) c->gp.root_rel32 = value;
-    else if (k == "slack32" && value >= 1e-6 && value <= 1e-2) c->gp.slack32 = value;
-    else if (k == "stack_cap" && value >= 64 && value <= (1 << 22)) c->gp.stack_cap = (int32_t)value;
-    else if (k == "max_windows" && value >= 1) c->gp.max_windows = (int32_t)std::min(value, 2.0e9);
-    else if (k == "max_slots" && value >= 1 && value <= 65536) c->max_slots = (int)value;
-    else if (k == "lds_stack_kb" && (value == 4 || value == 8 || value == 16)) c->lds_stack_kb = (int)value;
-    else if (k == "grab" && value >= 1 && value <= 64) c->grab = (int)value;
-    else if (k == "update_block" && (value == 64 || value == 128 || value == 256)) c->update_block = (int)value;
-    else if (k == "graph_steps" && value >= 0 && value <= 1000) c->graph_steps = (int)value;
-    else if (k == "stack_cap_all" && value >= 1024 && value <= (1 << 22)) c->stack_cap_all = (int)value;
-    else if (k == "max_windows_all" && value >= 1) c->max_windows_all = (int32_t)std::min(value, 2.0e9);
-    else if (k == "bucket" && value >= 0.0) c->gp.bucket = value;
-    else if (k == "dom_rel" && value >= 0.0) c->gp.dom_rel = value;
-    else if (k == "dom_rel32" && value >= 0.0) c->gp.dom_rel32 = value;
-    else if (k == "whole_mesh" && (value == 0.0 || value == 1.0)) c->whole_mesh = value != 0.0;
-    else if (k == "time_geodesic_only" && (value == 0.0 || value == 1.0)) c->time_geodesic_only = value != 0.0;
-    else return fail(c, GSIM_E_ARG, "unknown tuning knob or value out of range: " + k);
-    drop_graphs(c);
-    return GSIM_OK;
+    try {
+        if (!c || !name) return GSIM_E_ARG;
+        std::string k(name);
+        if (k == "launch_delta") c->gp.launch_delta = value;
+        else if (k == "cone_tol" && value >= 0.0) c->gp.cone_tol = value;
+        else if (k == "tie_rel" && value >= 0.0) c->gp.tie_rel = value;
+        else if (k == "tie_dir" && value >= 0.0) c->gp.tie_dir = value;
+        else if (k == "eager") c->gp.eager = value != 0.0;
+        else if (k == "cone_tol32" && value >= 0.0) c->gp.cone_tol32 = value;
+        else if (k == "tie_rel32" && value >= 0.0) c->gp.tie_rel32 = value;
+        else if (k == "tie_dir32" && value >= 0.0) c->gp.tie_dir32 = value;
+        else if (k == "guard_rel" && value >= 0.0) c->gp.guard_rel = value;
+        else if (k == "root_rel32" && value >= 0.0 && value <= 1e-4) c->gp.root_rel32 = value;
+        else if (k == "slack32" && value >= 1e-6 && value <= 1e-2) c->gp.slack32 = value;
+        else if (k == "stack_cap" && value >= 64 && value <= (1 << 22)) c->gp.stack_cap = (int32_t)value;
+        else if (k == "max_windows" && value >= 1) c->gp.max_windows = (int32_t)std::min(value, 2.0e9);
+        else if (k == "max_slots" && value >= 1 && value <= 65536) c->max_slots = (int)value;
+        else if (k == "lds_stack_kb" && (value == 4 || value == 8 || value == 16)) c->lds_stack_kb = (int)value;
+        else if (k == "grab" && value >= 1 && value <= 64) c->grab = (int)value;
+        else if (k == "update_block" && (value == 64 || value == 128 || value == 256)) c->update_block = (int)value;
+        else if (k == "graph_steps" && value >= 0 && value <= 1000) c->graph_steps = (int)value;
+        else if (k == "stack_cap_all" && value >= 1024 && value <= (1 << 22)) c->stack_cap_all = (int)value;
+        else if (k == "max_windows_all" && value >= 1) c->max_windows_all = (int32_t)std::min(value, 2.0e9);
+        else if (k == "bucket" && value >= 0.0) c->gp.bucket = value;
+        else if (k == "dom_rel" && value >= 0.0) c->gp.dom_rel = value;
+        else if (k == "dom_rel32" && value >= 0.0) c->gp.dom_rel32 = value;
+        else if (k == "whole_mesh" && (value == 0.0 || value == 1.0)) c->whole_mesh = value != 0.0;
+        else if (k == "time_geodesic_only" && (value == 0.0 || value == 1.0)) c->time_geodesic_only = value != 0.0;
+        else return fail(c, GSIM_E_ARG, "unknown tuning knob or value out of range: " + k);
+        drop_graphs(c);
+        return GSIM_OK;
+    }
+    GSIM_CATCH(c)
 }
 
 gsim_status gsim_source_profile(gsim_ctx *c, int on, int64_t *out, int32_t n) {
-    if (!c) return GSIM_E_ARG;
-    if (out) {
-        if (!c->profile_sources || n != c->prof_n) return fail(c, GSIM_E_STATE, "source profiling not active");
-        HIPCHK(c, hipMemcpyAsync(out, c->prof.p, sizeof(long long) * 8 * (size_t)n, hipMemcpyDeviceToHost, c->stream));
-        HIPCHK(c, hipStreamSynchronize(c->stream));
+    try {
+        if (!c) return GSIM_E_ARG;
+        if (out) {
+            if (!c->profile_sources || n != c->prof_n) return fail(c, GSIM_E_STATE, "source profiling not active");
+            HIPCHK(c, hipMemcpyAsync(out, c->prof.p, sizeof(long long) * 8 * (size_t)n, hipMemcpyDeviceToHost, c->stream));
+            HIPCHK(c, hipStreamSynchronize(c->stream));
+        }
+        c->profile_sources = on != 0;
+        c->prof_n = 0;
+        return GSIM_OK;
     }
-    c->profile_sources = on != 0;
-    c->prof_n = 0;
-    return GSIM_OK;
+    GSIM_CATCH(c)
 }
 
 gsim_status gsim_counters_get(gsim_ctx *c, int64_t *c10) {
