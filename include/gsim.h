@@ -204,10 +204,17 @@ gsim_status gsim_step(gsim_ctx *ctx, int32_t mesh_id, const gsim_potential *pot,
 
 /* step_batched: nsteps full time steps of several independent surfaces at
  * once (the same per-surface work as gsim_step, Sec. 3.1 and 3.2). Every
- * step is one binning, one geodesic and one update launch for the whole
+ * step is one binning, one geodesic and one update (or commit) launch for the whole
  * batch: the persistent geodesic grid takes sources from all surfaces, so
  * small surfaces share the GPU instead of leaving it idle. mesh_ids[nmesh]
  * (1..64 distinct meshes, each with particles), pots[nmesh], integs[nmesh].
+ * With a finite cutoff, no FIRE surface in the batch and at most four
+ * particles per compute unit in all, the update is fused into the geodesic
+ * launch ("fuse_update", default 1): each source's wavefront moves its
+ * particle (force from its row, integrator, walk) into a next-state array as
+ * soon as its row is final; the next step's binning, or a commit launch after
+ * the last step, makes that the current state. The results are bit-identical
+ * to the separate update launch.
  * When timing is off and nsteps >= 2, groups of "graph_steps" steps are
  * captured once into a HIP graph and replayed (the capture is cached until
  * the batch, a buffer or a knob changes). gsim_step is the batch of one. */
@@ -234,7 +241,10 @@ gsim_status gsim_step_batched(gsim_ctx *ctx, int32_t nmesh, const int32_t *mesh_
  *   "lds_stack_kb"  window-stack depth in LDS per wavefront: 4, 8 or 16 KiB (sets
  *                   how many wavefronts fit on a compute unit)
  *   "grab"          consecutive sources a wavefront claims at a time (1 .. 64)
- *   "update_block"  workgroup size of the fused update kernel: 64, 128 or 256
+ *   "update_block"  workgroup size of the separate update kernel: 64, 128 or 256
+ *   "fuse_update"   1 (default): time steps with a cutoff and few enough particles
+ *                   move each particle inside the geodesic launch; 0: always a
+ *                   separate update launch per step
  *   "graph_steps"   steps captured per HIP graph in step calls (0 = no graphs)
  *   "time_geodesic_only"  1: while timing is on, record events around the
  *                   geodesic stage only (each event record costs the stream a few
@@ -262,7 +272,7 @@ gsim_status gsim_autotune(gsim_ctx *ctx, int32_t nmesh, const int32_t *mesh_ids,
 
 /* ---- instrumentation ------------------------------------------------------
  * Per-kernel timing with HIP events recorded on the context's stream, only
- * while enabled. name: "prefilter", "geodesic", "fire", "update", "compact",
+ * while enabled. name: "prefilter", "geodesic", "fire", "update", "commit", "compact",
  * "forces", "walk", "voronoi". avg_ms is the mean duration of the stage. */
 gsim_status gsim_timing_enable(gsim_ctx *ctx, int on);
 gsim_status gsim_timing_get(gsim_ctx *ctx, const char *name, double *avg_ms, int64_t *launches);

@@ -46,6 +46,7 @@ struct MeshState {
     int64_t n_pairs = 0;
     // forces / integrator
     Buf F, Ei, E, disp, wflags, step_dev, fire;
+    Buf face_nx, bary_nx, vel_nx;  // next state of a fused time step
     uint64_t step = 0;  // steps taken since the state was set: the noise counter (host mirror)
     // all-pairs rows and the particles-by-face index
     int cap = kCandCap;  // row capacity of the last pass
@@ -97,6 +98,7 @@ struct gsim_ctx {
     int max_windows_all = 0;      // per-source window limit in all-pairs passes
     int cus = 256;
     bool whole_mesh = false;  // finite-cutoff passes on the whole-mesh kernel
+    bool fuse_update = true;  // time steps move each particle inside the cutoff kernel
     // layout the bend-vertex tables were last emptied for
     void *roots_p = nullptr;
     int64_t roots_stride = 0;
@@ -377,6 +379,14 @@ gsim_status prepare_surface(gsim_ctx *c, const Member &mb, bool small, int src_b
         d.f_dec = g.f_dec > 0.0 ? g.f_dec : 0.5;
         d.n_min = g.n_min > 0 ? g.n_min : 5;
     }
+    if (!all && mb.integ && mb.integ->kind != GSIM_INT_FIRE) {
+        HIPCHK(c, ensure(ms->face_nx, sizeof(int32_t) * n));
+        HIPCHK(c, ensure(ms->bary_nx, sizeof(double) * 3 * n));
+        HIPCHK(c, ensure(ms->vel_nx, sizeof(double) * 3 * n));
+        d.face_out = P<int32_t>(ms->face_nx);
+        d.bary_out = P<double>(ms->bary_nx);
+        d.vel_out = P<double>(ms->vel_nx);
+    }
     d.F = P<double>(ms->F);
     d.fire = P<FireState>(ms->fire);
     d.step = P<uint64_t>(ms->step_dev);
@@ -396,6 +406,7 @@ struct Batch {
     int64_t rstride = 0;  // bend-vertex table bytes per wavefront
     int32_t rcap = 0;     // its capacity (bend vertices)
     bool small = true;  // every surface bins in one workgroup
+    bool fused = false; // time steps move the particles inside the cutoff kernel
     int nslots = 0;
     GeoShape shape{};
 };
@@ -487,6 +498,13 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
         const int64_t fit = (int64_t)(c->stack_budget / (double)std::max<int64_t>(B.rstride, 1));
         B.nslots = (int)std::max<int64_t>(1, std::min<int64_t>(B.nslots, fit));
     }
+    // time steps move the particles inside the geodesic launch when there is
+    // at most one source per SIMD (four per compute unit): each wavefront's
+    // one source then only grows by a walk, and the separate update launch
+    // goes. With more sources, every one of them would carry the serial move
+    // (measured: a loss from two wavefronts per SIMD on).
+    B.fused = c->fuse_update && !B.all && !B.any_fire && total <= B.nslots && total <= 4 * c->cus;
+    for (int i = 0; i < ns; ++i) B.fused = B.fused && B.mem[i].integ != nullptr;
     B.shape.lds_stack_kb = c->lds_stack_kb;
     B.shape.nslots = B.nslots;
     B.shape.grab = c->grab;
@@ -523,7 +541,9 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
 const SurfDesc *desc_dev(gsim_ctx *c) { return static_cast<const SurfDesc *>(c->desc.p); }
 
 // Binning, candidate search and geodesics of every source of the batch.
-gsim_status geodesic_pass(gsim_ctx *c, Batch &B, bool advance) {
+// commit_in: the state to bin is in the next-state arrays (the previous
+// fused step of the same call wrote it there).
+gsim_status geodesic_pass(gsim_ctx *c, Batch &B, bool advance, bool commit_in = false) {
     hipStream_t s = c->stream;
     if (B.all) {
         {
@@ -548,7 +568,7 @@ gsim_status geodesic_pass(gsim_ctx *c, Batch &B, bool advance) {
     {
         Stage st(c, "prefilter");
         if (B.small) {
-            HIPCHK(c, launch_bin_batch(desc_dev(c), B.bi.nsurf, P<int32_t>(c->work), advance, s));
+            HIPCHK(c, launch_bin_batch(desc_dev(c), B.bi.nsurf, P<int32_t>(c->work), advance, commit_in, s));
         } else {
             // one surface with a fine grid: multi-kernel counting sort
             MeshState *ms = B.mem[0].ms;
@@ -565,6 +585,7 @@ gsim_status geodesic_pass(gsim_ctx *c, Batch &B, bool advance) {
             for (int k = 0; k < 3; ++k) pb.dims[k] = d.dims[k];
             pb.cell = d.cell;
             HIPCHK(c, launch_pass_begin(desc_dev(c), 1, P<int32_t>(c->work), advance, s));
+            if (commit_in) HIPCHK(c, launch_commit_batch(desc_dev(c), B.bi, s));
             HIPCHK(c, launch_xyz(ms->dm, n, ms->face, ms->bary, ms->xyz, s));
             HIPCHK(c, launch_prefilter_bin(ms->dm, n, pb, s));
             HIPCHK(c, launch_scan_i32_to_i64(pb.cell_fill, P<int64_t>(ms->tmp64), ncell, P<int64_t>(c->scan_scratch),
@@ -579,14 +600,15 @@ gsim_status geodesic_pass(gsim_ctx *c, Batch &B, bool advance) {
     {
         Stage st(c, "geodesic");
         HIPCHK(c, launch_geodesic(desc_dev(c), B.bi, gp, B.shape, P<char>(c->stack), P<char>(c->roots), B.rstride,
-                                  B.rcap, P<int32_t>(c->work),
-                                  P<Counters>(c->ctr), c->prec == GSIM_FP32_MIXED, s));
+                                  B.rcap, P<int32_t>(c->work), P<Counters>(c->ctr), c->prec == GSIM_FP32_MIXED,
+                                  advance && B.fused, s));
     }
     c->passes++;
     return GSIM_OK;
 }
 
 gsim_status update_pass(gsim_ctx *c, Batch &B) {
+    if (B.fused) return GSIM_OK;  // the particles moved inside the geodesic pass
     if (B.any_fire) {
         Stage sf(c, "fire");
         HIPCHK(c, launch_fire_control(desc_dev(c), B.fire_blk, P<double>(c->partials), P<Counters>(c->ctr), c->stream));
@@ -655,6 +677,7 @@ std::string graph_key(gsim_ctx *c, const Batch &B, int steps) {
     put(&c->gp, sizeof(c->gp));
     put(&B.shape, sizeof(B.shape));
     put(&B.small, sizeof(B.small));
+    put(&B.fused, sizeof(B.fused));
     put(&c->update_block, sizeof(int));
     put(&steps, sizeof(int));
     void *ptrs[8] = {c->stack.p, c->work.p, c->ctr.p, c->desc.p, c->scan_scratch.p, c->vdist.p, c->roots.p,
@@ -673,9 +696,15 @@ void drop_graphs(gsim_ctx *c) {
 
 gsim_status enqueue_steps(gsim_ctx *c, Batch &B, int steps) {
     for (int k = 0; k < steps; ++k) {
-        gsim_status st = geodesic_pass(c, B, true);
+        gsim_status st = geodesic_pass(c, B, true, B.fused && k > 0);
         if (st != GSIM_OK) return st;
         if ((st = update_pass(c, B)) != GSIM_OK) return st;
+    }
+    if (B.fused && steps > 0) {
+        // the next step's binning commits a fused step's state; after the
+        // last one a commit launch does
+        Stage sc(c, "commit");
+        HIPCHK(c, launch_commit_batch(desc_dev(c), B.bi, c->stream));
     }
     return GSIM_OK;
 }
@@ -818,7 +847,8 @@ void gsim_destroy(gsim_ctx *c) {
         for (Buf *b : {&ms->cell_of, &ms->cell_start, &ms->cell_fill, &ms->order, &ms->cand_cnt, &ms->cand,
                        &ms->tmp64, &ms->cdist, &ms->ctan, &ms->cflags, &ms->nbr_cnt, &ms->off, &ms->nbr, &ms->dist,
                        &ms->tan, &ms->flags, &ms->F, &ms->Ei, &ms->E, &ms->disp, &ms->wflags, &ms->step_dev,
-                       &ms->fire, &ms->fstart, &ms->forder, &ms->fcount})
+                       &ms->fire, &ms->fstart, &ms->forder, &ms->fcount, &ms->face_nx, &ms->bary_nx,
+                       &ms->vel_nx})
             release(*b);
         for (void *p : {(void *)ms->face, (void *)ms->bary, (void *)ms->vel, (void *)ms->xyz})
             if (p) (void)hipFree(p);
@@ -1418,6 +1448,7 @@ gsim_status gsim_tune_set(gsim_ctx *c, const char *name, double value) {
         else if (k == "dom_rel" && value >= 0.0) c->gp.dom_rel = value;
         else if (k == "dom_rel32" && value >= 0.0) c->gp.dom_rel32 = value;
         else if (k == "whole_mesh" && (value == 0.0 || value == 1.0)) c->whole_mesh = value != 0.0;
+    else if (k == "fuse_update" && (value == 0.0 || value == 1.0)) c->fuse_update = value != 0.0;
         else if (k == "time_geodesic_only" && (value == 0.0 || value == 1.0)) c->time_geodesic_only = value != 0.0;
         else return fail(c, GSIM_E_ARG, "unknown tuning knob or value out of range: " + k);
         drop_graphs(c);

@@ -140,6 +140,11 @@ struct SurfDesc {
     int32_t src_begin;  // index of its first source in the batch
     int32_t *face;
     double *bary, *vel, *xyz;
+    // next state, written by the cutoff kernel's fused update (time steps
+    // with a cutoff and a non-FIRE integrator) while other sources still
+    // read the current one; a commit kernel copies it back after the pass
+    int32_t *face_out;
+    double *bary_out, *vel_out;
     // prefilter cell grid (cells no smaller than the cutoff)
     int32_t *cell_of, *cell_start, *order;
     int32_t dims[3];
@@ -211,9 +216,11 @@ struct GeoShape {
 
 // Candidate search (Euclidean prefilter) and geodesics for every source of
 // the batch, one wavefront per source. The cell lists must be current.
+// With `fuse`, each source particle is also moved (force from its row,
+// integrator, walk) into the next-state arrays once its row is final.
 hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoParams &gp, const GeoShape &shape,
                            char *stack_mem, char *roots, int64_t rstride, int rcap, int32_t *work_ctr, Counters *ctr,
-                           bool fp32, hipStream_t s);
+                           bool fp32, bool fuse, hipStream_t s);
 // All-pairs geodesics (no cutoff) for every source of the batch: every other
 // particle of the surface is a target. vdist: per resident wavefront a table
 // of vstride vertex distances; roots: per resident wavefront a bend-vertex
@@ -263,13 +270,17 @@ size_t geodesic_lds_bytes(int lds_stack_kb, bool fp32);
 constexpr int kSmallCells = 4096;
 // (also clears the work counters and, when `advance`, moves every surface's
 // step counter on by one)
-hipError_t launch_bin_batch(const SurfDesc *desc, int nsurf, int32_t *work, bool advance, hipStream_t s);
+// commit: take the state from the next-state arrays first (fused time steps)
+hipError_t launch_bin_batch(const SurfDesc *desc, int nsurf, int32_t *work, bool advance, bool commit,
+                            hipStream_t s);
 // the same start of a pass without the binning
 hipError_t launch_pass_begin(const SurfDesc *desc, int nsurf, int32_t *work, bool advance, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s);
 // fused force + integrator + walk for every particle of the batch
 hipError_t launch_update_batch(const SurfDesc *desc, const BatchIdx &bi, int block, Counters *ctr,
                                hipStream_t s);
+// next state -> current state for every particle of the batch
+hipError_t launch_commit_batch(const SurfDesc *desc, const BatchIdx &bi, hipStream_t s);
 // resident geodesic workgroups per compute unit for a stack size (0 on error)
 int geodesic_blocks_per_cu(int lds_stack_kb, bool fp32);
 

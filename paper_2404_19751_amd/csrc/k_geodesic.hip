@@ -51,9 +51,17 @@
 // and particles) form one flattened index space served by the same
 // persistent grid; a wavefront finds its source's surface from the batch
 // boundaries and reads that surface's descriptor.
+//
+// Fused update (time steps with few sources): once a source's row is final,
+// lane 0 of its wavefront applies the force sum over the row (Sec. 3.1),
+// the integrator (Sec. 2.1) and the walk (Sec. 3.2) to that particle and
+// writes its new state into next-state arrays, which no source reads during
+// the pass; the row is read back with the same code as the separate update
+// kernel, so the trajectory is bit-identical to it.
 #include <cmath>
 
 #include "gsim_internal.h"
+#include "walk.h"
 #include "window.h"
 
 namespace gsim {
@@ -76,6 +84,7 @@ struct GeoArgs {
     char *roots;         // per wave: a bend-vertex table (rstride bytes, rcap vertices)
     int64_t rstride;
     int rcap;
+    int fuse;  // move each source particle once its row is final (time steps)
 };
 
 struct Lds {
@@ -769,6 +778,18 @@ __device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigne
     return any_near;
 }
 
+// The fused update of one source particle (lane 0): force from its row,
+// integrator, walk, new state into the next-state arrays; returns its pair
+// count. Not inlined: inlined, the walk's registers push the propagation
+// loop into spilling (measured slower).
+__device__ __noinline__ int fused_move(const SurfDesc &sd, int src) {
+    double F[3], E;
+    int np = 0;
+    row_force(src, sd.cand_cnt, sd.cap, sd.cdist, sd.ctan, sd.cutoff, sd.pkind, sd.pk, sd.psigma, F, E, np);
+    move_particle(sd, src, F, sd.face_out, sd.bary_out, sd.vel_out);
+    return np;
+}
+
 // Two waves per SIMD: with up to eight workgroups' LDS on a compute unit, a
 // wavefront may hold at most 256 registers.
 template <bool kMixed, int kStk>
@@ -784,6 +805,7 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
     st.depth = 0;
     st.overflow = false;
     unsigned long long c_limited = 0;
+    unsigned long long fused_np = 0;  // neighbour pairs of the moved particles (lane 0)
     int next = 0, left = 0;  // claimed sources not yet processed
     for (;;) {
         // ---- next source: claim `grab` consecutive ones, XCD-local chunk first
@@ -811,22 +833,29 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
         const int src = sd.order[idx - a.bi.begin[si]];
         const int64_t c0 = (int64_t)src * kMaxCand;
         const int nc = find_candidates(sd, L, src, c0);
-        if (nc <= 0) continue;
         if (nc > kMaxCand) {
             if (lane == 0) ++c_limited;
-            continue;
-        }
-        st.overflow = false;
-        if (kMixed) {
-            // FP32 pass; a pair inside the guard band sends the source through FP64
-            if (run_source<float>(a, sd, L, stk, kStk, src, c0, nc, false, blockIdx.x, st)) {
-                run_source<double>(a, sd, L, stk, kStk, src, c0, nc, true, blockIdx.x, st);
-                ++st.guards;
+        } else if (nc > 0) {
+            st.overflow = false;
+            if (kMixed) {
+                // FP32 pass; a pair inside the guard band sends the source through FP64
+                if (run_source<float>(a, sd, L, stk, kStk, src, c0, nc, false, blockIdx.x, st)) {
+                    run_source<double>(a, sd, L, stk, kStk, src, c0, nc, true, blockIdx.x, st);
+                    ++st.guards;
+                }
+            } else {
+                run_source<double>(a, sd, L, stk, kStk, src, c0, nc, false, blockIdx.x, st);
             }
-        } else {
-            run_source<double>(a, sd, L, stk, kStk, src, c0, nc, false, blockIdx.x, st);
+            if (st.overflow) ++c_limited;
         }
-        if (st.overflow) ++c_limited;
+        if (a.fuse) {
+            // the row is final: move the source particle (the same force sum,
+            // integrator and walk as the separate update kernel, read back
+            // from the row this wavefront has just written) into the
+            // next-state arrays, which no source reads during the pass
+            __syncthreads();
+            if (lane == 0) fused_np += (unsigned long long)fused_move(sd, src);
+        }
     }
     unsigned long long pr = (unsigned long long)st.pruned, sl = st.stale;
     for (int o = 32; o > 0; o >>= 1) {
@@ -841,6 +870,7 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
         atomicAdd(&a.ctr->limited, c_limited);
         atomicMax(&a.ctr->max_depth, (unsigned long long)st.depth);
         if (st.guards) atomicAdd(&a.ctr->guards, st.guards);
+        if (fused_np) atomicAdd(&a.ctr->nbr_pairs, fused_np);
     }
 }
 
@@ -855,7 +885,7 @@ void launch_variant(int kb, int nslots, size_t pad, const GeoArgs &a, hipStream_
 
 hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoParams &gp, const GeoShape &shape,
                            char *stack_mem, char *roots, int64_t rstride, int rcap, int32_t *work_ctr, Counters *ctr,
-                           bool fp32, hipStream_t s) {
+                           bool fp32, bool fuse, hipStream_t s) {
     GeoArgs a;
     a.sd = desc;
     a.bi = bi;
@@ -867,6 +897,7 @@ hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoPa
     a.roots = roots;
     a.rstride = rstride;
     a.rcap = rcap;
+    a.fuse = fuse ? 1 : 0;
     if (shape.nslots < 1 || bi.begin[bi.nsurf] < 1) return hipSuccess;
     const size_t pad = shape.pad_lds > 0 ? (size_t)shape.pad_lds : 0;
     if (fp32) launch_variant<true>(shape.lds_stack_kb, shape.nslots, pad, a, s);

@@ -140,10 +140,12 @@ __global__ void k_bin_scatter(int n, PrefilterBufs b) {
 }
 
 // Positions and the cell counting sort of one surface per workgroup: cell
-// counts, their exclusive scan and the scatter all live in LDS.
+// counts, their exclusive scan and the scatter all live in LDS. With
+// `commit`, the particle state is first taken from the next-state arrays that
+// the previous pass's fused update wrote (and copied into the current ones).
 constexpr int kBinThreads = 1024;
 __global__ __launch_bounds__(kBinThreads) void k_bin_batch(const SurfDesc *__restrict__ desc,
-                                                           int32_t *__restrict__ work, int advance) {
+                                                           int32_t *__restrict__ work, int advance, int commit) {
     __shared__ int32_t cnt[kSmallCells];
     __shared__ int32_t start[kSmallCells];
     __shared__ int32_t part[kBinThreads];
@@ -160,8 +162,17 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_batch(const SurfDesc *__res
     for (int c = t; c < ncell; c += kBinThreads) cnt[c] = 0;
     __syncthreads();
     for (int j = t; j < n; j += kBinThreads) {
-        const int f = sd.face[j];
-        const double b0 = sd.bary[3 * j], b1 = sd.bary[3 * j + 1], b2 = sd.bary[3 * j + 2];
+        const int32_t *face = commit ? sd.face_out : sd.face;
+        const double *bary = commit ? sd.bary_out : sd.bary;
+        const int f = face[j];
+        const double b0 = bary[3 * j], b1 = bary[3 * j + 1], b2 = bary[3 * j + 2];
+        if (commit) {
+            sd.face[j] = f;
+            sd.bary[3 * j] = b0;
+            sd.bary[3 * j + 1] = b1;
+            sd.bary[3 * j + 2] = b2;
+            for (int q = 0; q < 3; ++q) sd.vel[3 * j + q] = sd.vel_out[3 * j + q];
+        }
         const double *p0 = V + 3 * (int64_t)T[3 * f], *p1 = V + 3 * (int64_t)T[3 * f + 1],
                      *p2 = V + 3 * (int64_t)T[3 * f + 2];
         int c3[3];
@@ -450,9 +461,11 @@ hipError_t launch_prefilter_bin(const DevMesh &m, int n, PrefilterBufs &b, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_bin_batch(const SurfDesc *desc, int nsurf, int32_t *work, bool advance, hipStream_t s) {
+hipError_t launch_bin_batch(const SurfDesc *desc, int nsurf, int32_t *work, bool advance, bool commit,
+                            hipStream_t s) {
     if (nsurf <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_bin_batch, dim3(nsurf), dim3(kBinThreads), 0, s, desc, work, advance ? 1 : 0);
+    hipLaunchKernelGGL(k_bin_batch, dim3(nsurf), dim3(kBinThreads), 0, s, desc, work, advance ? 1 : 0,
+                       commit ? 1 : 0);
     return hipGetLastError();
 }
 hipError_t launch_pass_begin(const SurfDesc *desc, int nsurf, int32_t *work, bool advance, hipStream_t s) {

@@ -3,10 +3,12 @@ workload and precision mode: neighbour sets (bit-exact), distances (relative
 error), initial tangents (the log-map vector d*t, relative to
 max(d, 1e-3 of the mean edge); pairs flagged as near-ties are measured
 against the nearest direction of the oracle's tie set), forces (|dF_i|
-relative to sum_j |U'(d_ij)|, particles with a near-tie pair excluded, since
-their force may legitimately take either direction), the energy, and one
-step's faces and barycentric coordinates (particles whose walk the oracle
-flags as passing within the hit tolerance of a vertex or edge excluded).
+relative to sum_j (|U'(d_ij)| + d_ij |U''(d_ij)|), what the per-pair bounds
+imply to first order: over particles without a near-tie pair, whose force
+may legitimately take either direction, and over all particles with the
+GPU's direction taken for tie pairs), the energy, and one step's faces and
+barycentric coordinates (particles whose walk the oracle flags as passing
+within the hit tolerance of a vertex or edge excluded).
 
 Each case prints one `[error-report]` JSON line and asserts the bounds: 1e-12
 (FP64; forces 1e-11) and 1e-5 (FP32-mixed) relative."""
