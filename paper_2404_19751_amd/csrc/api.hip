@@ -205,20 +205,24 @@ void resolve_timing(gsim_ctx *c) {
 // HIP events around one stage, only while timing is on (never inside a
 // graph capture). Every event record costs the stream a few microseconds, so
 // with `time_geodesic_only` only the geodesic stage is timed.
+// A stage of one kernel (`by_kernel`) hands its two events to that kernel's
+// launch instead, which has the dispatch itself record them: no extra stream
+// commands, and the interval is the kernel's own execution.
 struct Stage {
     gsim_ctx *c;
     const char *name;
+    bool by_kernel;
     hipEvent_t a = nullptr, b = nullptr;
-    Stage(gsim_ctx *c_, const char *n) : c(c_), name(n) {
+    Stage(gsim_ctx *c_, const char *n, bool by_kernel_ = false) : c(c_), name(n), by_kernel(by_kernel_) {
         if (c->timing && !c->capturing && (!c->time_geodesic_only || std::strcmp(n, "geodesic") == 0)) {
             a = take_event(c);
             b = take_event(c);
-            if (a) (void)hipEventRecord(a, c->stream);
+            if (a && !by_kernel) (void)hipEventRecord(a, c->stream);
         }
     }
     ~Stage() {
         if (a && b) {
-            (void)hipEventRecord(b, c->stream);
+            if (!by_kernel) (void)hipEventRecord(b, c->stream);
             c->pending.push_back({name, {a, b}});
             if (c->pending.size() > 4096) resolve_timing(c);
         }
@@ -598,10 +602,10 @@ gsim_status geodesic_pass(gsim_ctx *c, Batch &B, bool advance, bool commit_in = 
     GeoParams gp = c->gp;
     if (!(gp.launch_delta > 0.0)) gp.launch_delta = 0.5 * B.mem[0].ms->dm.mean_edge;
     {
-        Stage st(c, "geodesic");
+        Stage st(c, "geodesic", true);
         HIPCHK(c, launch_geodesic(desc_dev(c), B.bi, gp, B.shape, P<char>(c->stack), P<char>(c->roots), B.rstride,
                                   B.rcap, P<int32_t>(c->work), P<Counters>(c->ctr), c->prec == GSIM_FP32_MIXED,
-                                  advance && B.fused, s));
+                                  advance && B.fused, s, st.a, st.b));
     }
     c->passes++;
     return GSIM_OK;

@@ -217,10 +217,11 @@ struct GeoShape {
 // Candidate search (Euclidean prefilter) and geodesics for every source of
 // the batch, one wavefront per source. The cell lists must be current.
 // With `fuse`, each source particle is also moved (force from its row,
-// integrator, walk) into the next-state arrays once its row is final.
+// integrator, walk) into the next-state arrays once its row is final. Non-null
+// ev0/ev1 are recorded by the dispatch at the kernel's start and end.
 hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoParams &gp, const GeoShape &shape,
                            char *stack_mem, char *roots, int64_t rstride, int rcap, int32_t *work_ctr, Counters *ctr,
-                           bool fp32, bool fuse, hipStream_t s);
+                           bool fp32, bool fuse, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // All-pairs geodesics (no cutoff) for every source of the batch: every other
 // particle of the surface is a target. vdist: per resident wavefront a table
 // of vstride vertex distances; roots: per resident wavefront a bend-vertex

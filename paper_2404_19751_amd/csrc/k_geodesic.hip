@@ -58,6 +58,8 @@
 // writes its new state into next-state arrays, which no source reads during
 // the pass; the row is read back with the same code as the separate update
 // kernel, so the trajectory is bit-identical to it.
+#include <hip/hip_ext.h>
+
 #include <cmath>
 
 #include "gsim_internal.h"
@@ -874,18 +876,24 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
     }
 }
 
+template <bool kMixed, int kStk>
+void launch_one(int nslots, size_t pad, const GeoArgs &a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (ev0 || ev1)
+        hipExtLaunchKernelGGL((k_geodesic<kMixed, kStk>), dim3(nslots), dim3(kWave), (uint32_t)pad, s, ev0, ev1, 0, a);
+    else hipLaunchKernelGGL((k_geodesic<kMixed, kStk>), dim3(nslots), dim3(kWave), pad, s, a);
+}
 template <bool kMixed>
-void launch_variant(int kb, int nslots, size_t pad, const GeoArgs &a, hipStream_t s) {
-    if (kb <= 4) hipLaunchKernelGGL((k_geodesic<kMixed, 4096>), dim3(nslots), dim3(kWave), pad, s, a);
-    else if (kb <= 8) hipLaunchKernelGGL((k_geodesic<kMixed, 8192>), dim3(nslots), dim3(kWave), pad, s, a);
-    else hipLaunchKernelGGL((k_geodesic<kMixed, 16384>), dim3(nslots), dim3(kWave), pad, s, a);
+void launch_variant(int kb, int nslots, size_t pad, const GeoArgs &a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (kb <= 4) launch_one<kMixed, 4096>(nslots, pad, a, s, ev0, ev1);
+    else if (kb <= 8) launch_one<kMixed, 8192>(nslots, pad, a, s, ev0, ev1);
+    else launch_one<kMixed, 16384>(nslots, pad, a, s, ev0, ev1);
 }
 
 }  // namespace
 
 hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoParams &gp, const GeoShape &shape,
                            char *stack_mem, char *roots, int64_t rstride, int rcap, int32_t *work_ctr, Counters *ctr,
-                           bool fp32, bool fuse, hipStream_t s) {
+                           bool fp32, bool fuse, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     GeoArgs a;
     a.sd = desc;
     a.bi = bi;
@@ -900,8 +908,8 @@ hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoPa
     a.fuse = fuse ? 1 : 0;
     if (shape.nslots < 1 || bi.begin[bi.nsurf] < 1) return hipSuccess;
     const size_t pad = shape.pad_lds > 0 ? (size_t)shape.pad_lds : 0;
-    if (fp32) launch_variant<true>(shape.lds_stack_kb, shape.nslots, pad, a, s);
-    else launch_variant<false>(shape.lds_stack_kb, shape.nslots, pad, a, s);
+    if (fp32) launch_variant<true>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
+    else launch_variant<false>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
     return hipGetLastError();
 }
 
