@@ -143,24 +143,29 @@ __global__ void k_bin_scatter(int n, PrefilterBufs b) {
 // counts, their exclusive scan and the scatter all live in LDS. With
 // `commit`, the particle state is first taken from the next-state arrays that
 // the previous pass's fused update wrote (and copied into the current ones).
+// Vertex positions come from the face record (one load after the face index);
+// the scan runs within each wavefront by shuffles, then across the
+// wavefronts through LDS (one barrier).
 constexpr int kBinThreads = 1024;
+constexpr int kBinWaves = kBinThreads / 64;
 __global__ __launch_bounds__(kBinThreads) void k_bin_batch(const SurfDesc *__restrict__ desc,
                                                            int32_t *__restrict__ work, int advance, int commit) {
     __shared__ int32_t cnt[kSmallCells];
     __shared__ int32_t start[kSmallCells];
-    __shared__ int32_t part[kBinThreads];
+    __shared__ int32_t wsum[kBinWaves];
     const SurfDesc &sd = desc[blockIdx.x];
     // start of a pass: the geodesic kernel's work counters, and (in a time
     // step) the surface's step counter
     if (blockIdx.x == 0 && threadIdx.x < 16) work[threadIdx.x] = 0;
     if (advance && threadIdx.x == 0) *sd.step += 1;
-    const double *__restrict__ V = sd.m.V;
-    const int32_t *__restrict__ T = sd.m.T;
+    const double *__restrict__ fpos = sd.m.fpos;
     const int n = sd.n;
     const int t = threadIdx.x;
+    const int lane = t & 63, wid = t >> 6;
     const int ncell = sd.dims[0] * sd.dims[1] * sd.dims[2];
     for (int c = t; c < ncell; c += kBinThreads) cnt[c] = 0;
     __syncthreads();
+    int my_lin = 0;  // the cell of particle t (the first of the thread's particles)
     for (int j = t; j < n; j += kBinThreads) {
         const int32_t *face = commit ? sd.face_out : sd.face;
         const double *bary = commit ? sd.bary_out : sd.bary;
@@ -173,8 +178,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_batch(const SurfDesc *__res
             sd.bary[3 * j + 2] = b2;
             for (int q = 0; q < 3; ++q) sd.vel[3 * j + q] = sd.vel_out[3 * j + q];
         }
-        const double *p0 = V + 3 * (int64_t)T[3 * f], *p1 = V + 3 * (int64_t)T[3 * f + 1],
-                     *p2 = V + 3 * (int64_t)T[3 * f + 2];
+        const double *p0 = fpos + 18 * (int64_t)f, *p1 = p0 + 3, *p2 = p0 + 6;
         int c3[3];
         for (int d = 0; d < 3; ++d) {
             const double x = b0 * p0[d] + b1 * p1[d] + b2 * p2[d];
@@ -184,6 +188,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_batch(const SurfDesc *__res
         }
         const int lin = (c3[2] * sd.dims[1] + c3[1]) * sd.dims[0] + c3[0];
         sd.cell_of[j] = lin;
+        if (j == t) my_lin = lin;
         atomicAdd(&cnt[lin], 1);
     }
     __syncthreads();
@@ -192,25 +197,25 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_batch(const SurfDesc *__res
     const int c0 = t * per, c1 = min(c0 + per, ncell);
     int sum = 0;
     for (int c = c0; c < c1; ++c) sum += cnt[c];
-    part[t] = sum;
-    __syncthreads();
-    for (int o = 1; o < kBinThreads; o <<= 1) {
-        const int add = t >= o ? part[t - o] : 0;
-        __syncthreads();
-        part[t] += add;
-        __syncthreads();
+    int incl = sum;
+    for (int o = 1; o < 64; o <<= 1) {
+        const int y = __shfl_up(incl, o);
+        if (lane >= o) incl += y;
     }
-    int run = part[t] - sum;
+    if (lane == 63) wsum[wid] = incl;
+    __syncthreads();
+    int run = incl - sum;
+    for (int w = 0; w < wid; ++w) run += wsum[w];
     for (int c = c0; c < c1; ++c) {
         start[c] = run;
         sd.cell_start[c] = run;
         run += cnt[c];
         cnt[c] = 0;
     }
-    if (t == kBinThreads - 1) sd.cell_start[ncell] = part[t];
+    if (t == kBinThreads - 1) sd.cell_start[ncell] = run;
     __syncthreads();
     for (int j = t; j < n; j += kBinThreads) {
-        const int lin = sd.cell_of[j];
+        const int lin = j == t ? my_lin : sd.cell_of[j];
         sd.order[start[lin] + atomicAdd(&cnt[lin], 1)] = j;
     }
 }
