@@ -25,6 +25,8 @@
  *  - Every call returns a gsim_status; nothing throws or aborts across the
  *    ABI. gsim_last_error() describes the last failure on a context.
  *  - A context is not thread-safe; its precision is fixed at creation.
+ *  - Every call makes the context's device current for its duration and then
+ *    restores the caller's current device.
  */
 #ifndef GSIM_H
 #define GSIM_H

@@ -111,6 +111,22 @@ struct gsim_ctx {
 };
 
 namespace {
+// Makes the context's device current for one call and gives the caller's
+// device back afterwards.
+struct DeviceGuard {
+    int prev = -1;
+    explicit DeviceGuard(const gsim_ctx *c) {
+        int cur = -1;
+        if (c && hipGetDevice(&cur) == hipSuccess && cur != c->device && hipSetDevice(c->device) == hipSuccess)
+            prev = cur;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+}  // namespace
+
+namespace {
 
 // Records the message for gsim_last_error. Never throws: a message that
 // cannot be stored leaves the error text empty.
@@ -874,6 +890,7 @@ void gsim_destroy(gsim_ctx *c) {
 const char *gsim_last_error(const gsim_ctx *c) { return c ? c->err.c_str() : "null context"; }
 
 gsim_status gsim_synchronize(gsim_ctx *c) {
+    DeviceGuard dg(c);
     try {
         if (!c) return GSIM_E_ARG;
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -884,6 +901,7 @@ gsim_status gsim_synchronize(gsim_ctx *c) {
 
 gsim_status gsim_mesh_upload(gsim_ctx *c, int32_t nv, const double *xyz, int32_t nf, const int32_t *tri,
                              int32_t *mesh_id) {
+    DeviceGuard dg(c);
     if (!c || !mesh_id || !xyz || !tri || nv < 3 || nf < 1) return fail(c, GSIM_E_ARG, "bad mesh arguments");
     try {
         MeshState *ms = new MeshState();
@@ -897,7 +915,6 @@ gsim_status gsim_mesh_upload(gsim_ctx *c, int32_t nv, const double *xyz, int32_t
         d.nv = nv;
         d.nf = nf;
         hipStream_t s = c->stream;
-        (void)hipSetDevice(c->device);
         // the mesh joins the context first so that a failed copy still frees it
         c->meshes.push_back(ms);
         HIPCHK(c, upload(d.V, H.V.data(), H.V.size(), s));
@@ -999,6 +1016,7 @@ static gsim_status reset_state(gsim_ctx *c, MeshState *ms, const double *vel, hi
 
 gsim_status gsim_particles_set(gsim_ctx *c, int32_t id, int32_t n, const int32_t *face, const double *bary,
                                const double *vel) {
+    DeviceGuard dg(c);
     try {
         MeshState *ms = get_mesh(c, id);
         if (!ms || n < 1 || !face || !bary) return fail(c, GSIM_E_ARG, "bad particle arguments");
@@ -1017,6 +1035,7 @@ gsim_status gsim_particles_set(gsim_ctx *c, int32_t id, int32_t n, const int32_t
 
 gsim_status gsim_particles_set_dev(gsim_ctx *c, int32_t id, int32_t n, const int32_t *face, const double *bary,
                                    const double *vel) {
+    DeviceGuard dg(c);
     try {
         MeshState *ms = get_mesh(c, id);
         if (!ms || n < 1 || !face || !bary) return fail(c, GSIM_E_ARG, "bad particle arguments");
@@ -1031,6 +1050,7 @@ gsim_status gsim_particles_set_dev(gsim_ctx *c, int32_t id, int32_t n, const int
 }
 
 gsim_status gsim_particles_get(gsim_ctx *c, int32_t id, int32_t *face, double *bary, double *vel, double *xyz) {
+    DeviceGuard dg(c);
     try {
         MeshState *ms = get_mesh(c, id);
         if (!ms) return fail(c, GSIM_E_ARG, "unknown mesh id");
@@ -1051,6 +1071,7 @@ gsim_status gsim_particles_get(gsim_ctx *c, int32_t id, int32_t *face, double *b
 }
 
 gsim_status gsim_particles_get_dev(gsim_ctx *c, int32_t id, int32_t *face, double *bary, double *vel) {
+    DeviceGuard dg(c);
     try {
         MeshState *ms = get_mesh(c, id);
         if (!ms) return fail(c, GSIM_E_ARG, "unknown mesh id");
@@ -1066,6 +1087,7 @@ gsim_status gsim_particles_get_dev(gsim_ctx *c, int32_t id, int32_t *face, doubl
 }
 
 gsim_status gsim_geodesic_pairs(gsim_ctx *c, int32_t id, double cutoff, gsim_pairs *out) {
+    DeviceGuard dg(c);
     MeshState *ms = get_mesh(c, id);
     if (!ms || !out) return fail(c, GSIM_E_ARG, "bad arguments");
     try {
@@ -1098,6 +1120,7 @@ gsim_status gsim_geodesic_pairs(gsim_ctx *c, int32_t id, double cutoff, gsim_pai
 
 gsim_status gsim_voronoi_neighbours(gsim_ctx *c, int32_t id, int64_t *off, int32_t *nbr, int64_t capacity,
                                     int64_t *count) {
+    DeviceGuard dg(c);
     MeshState *ms = get_mesh(c, id);
     if (!ms || !off || !count) return fail(c, GSIM_E_ARG, "bad arguments");
     const int n = ms->n;
@@ -1187,6 +1210,7 @@ gsim_status gsim_voronoi_neighbours(gsim_ctx *c, int32_t id, int64_t *off, int32
 }
 
 gsim_status gsim_compute_forces(gsim_ctx *c, int32_t id, const gsim_potential *pot, double *force, double *energy) {
+    DeviceGuard dg(c);
     MeshState *ms = get_mesh(c, id);
     if (!ms || !pot_kind_ok(pot) || !force) return fail(c, GSIM_E_ARG, "bad arguments");
     try {
@@ -1208,6 +1232,7 @@ gsim_status gsim_compute_forces(gsim_ctx *c, int32_t id, const gsim_potential *p
 
 gsim_status gsim_displace_on_surface(gsim_ctx *c, int32_t id, const double *disp, int transport_velocity,
                                      gsim_walk_stats *stats) {
+    DeviceGuard dg(c);
     MeshState *ms = get_mesh(c, id);
     if (!ms || !disp) return fail(c, GSIM_E_ARG, "bad arguments");
     if (ms->n <= 0) return fail(c, GSIM_E_STATE, "no particles on this mesh");
@@ -1237,6 +1262,7 @@ gsim_status gsim_displace_on_surface(gsim_ctx *c, int32_t id, const double *disp
 
 gsim_status gsim_step_batched(gsim_ctx *c, int32_t nmesh, const int32_t *mesh_ids, const gsim_potential *pots,
                               const gsim_integrator *integs, int32_t nsteps) {
+    DeviceGuard dg(c);
     if (!c || nmesh < 1 || nmesh > kMaxBatch || !mesh_ids || !pots || !integs || nsteps < 0)
         return fail(c, GSIM_E_ARG, "bad arguments");
     try {
@@ -1261,12 +1287,14 @@ gsim_status gsim_step_batched(gsim_ctx *c, int32_t nmesh, const int32_t *mesh_id
 
 gsim_status gsim_step(gsim_ctx *c, int32_t id, const gsim_potential *pot, const gsim_integrator *integ,
                       int32_t nsteps) {
+    DeviceGuard dg(c);
     if (!get_mesh(c, id)) return fail(c, GSIM_E_ARG, "unknown mesh id");
     return gsim_step_batched(c, 1, &id, pot, integ, nsteps);
 }
 
 gsim_status gsim_autotune(gsim_ctx *c, int32_t nmesh, const int32_t *mesh_ids, const gsim_potential *pots,
                           const gsim_integrator *integs, int32_t reps, double *out) {
+    DeviceGuard dg(c);
     if (!c || nmesh < 1 || nmesh > kMaxBatch || !mesh_ids || !pots || !integs || reps < 1)
         return fail(c, GSIM_E_ARG, "bad arguments");
     try {
@@ -1394,6 +1422,7 @@ gsim_status gsim_autotune(gsim_ctx *c, int32_t nmesh, const int32_t *mesh_ids, c
 }
 
 gsim_status gsim_timing_enable(gsim_ctx *c, int on) {
+    DeviceGuard dg(c);
     try {
         if (!c) return GSIM_E_ARG;
         resolve_timing(c);
@@ -1408,6 +1437,7 @@ gsim_status gsim_timing_enable(gsim_ctx *c, int on) {
 }
 
 gsim_status gsim_timing_get(gsim_ctx *c, const char *name, double *avg_ms, int64_t *launches) {
+    DeviceGuard dg(c);
     try {
         if (!c || !name) return GSIM_E_ARG;
         resolve_timing(c);
@@ -1425,6 +1455,7 @@ gsim_status gsim_timing_get(gsim_ctx *c, const char *name, double *avg_ms, int64
 }
 
 gsim_status gsim_tune_set(gsim_ctx *c, const char *name, double value) {
+    DeviceGuard dg(c);
     try {
         if (!c || !name) return GSIM_E_ARG;
         std::string k(name);
@@ -1462,6 +1493,7 @@ gsim_status gsim_tune_set(gsim_ctx *c, const char *name, double value) {
 }
 
 gsim_status gsim_source_profile(gsim_ctx *c, int on, int64_t *out, int32_t n) {
+    DeviceGuard dg(c);
     try {
         if (!c) return GSIM_E_ARG;
         if (out) {
