@@ -86,7 +86,6 @@ struct GeoArgs {
     char *roots;         // per wave: a bend-vertex table (rstride bytes, rcap vertices)
     int64_t rstride;
     int rcap;
-    int fuse;  // move each source particle once its row is final (time steps)
 };
 
 struct Lds {
@@ -794,7 +793,10 @@ __device__ __noinline__ int fused_move(const SurfDesc &sd, int src) {
 
 // Two waves per SIMD: with up to eight workgroups' LDS on a compute unit, a
 // wavefront may hold at most 256 registers.
-template <bool kMixed, int kStk>
+// kFuse: the instantiation with the fused particle update; the others carry
+// none of its code, which would otherwise change the register allocation of
+// every launch.
+template <bool kMixed, int kStk, bool kFuse>
 __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
     __shared__ Lds L;
     __shared__ alignas(16) unsigned char stk[kStk];
@@ -850,7 +852,7 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
             }
             if (st.overflow) ++c_limited;
         }
-        if (a.fuse) {
+        if (kFuse) {
             // the row is final: move the source particle (the same force sum,
             // integrator and walk as the separate update kernel, read back
             // from the row this wavefront has just written) into the
@@ -876,17 +878,18 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
     }
 }
 
-template <bool kMixed, int kStk>
+template <bool kMixed, int kStk, bool kFuse>
 void launch_one(int nslots, size_t pad, const GeoArgs &a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (ev0 || ev1)
-        hipExtLaunchKernelGGL((k_geodesic<kMixed, kStk>), dim3(nslots), dim3(kWave), (uint32_t)pad, s, ev0, ev1, 0, a);
-    else hipLaunchKernelGGL((k_geodesic<kMixed, kStk>), dim3(nslots), dim3(kWave), pad, s, a);
+        hipExtLaunchKernelGGL((k_geodesic<kMixed, kStk, kFuse>), dim3(nslots), dim3(kWave), (uint32_t)pad, s, ev0, ev1,
+                              0, a);
+    else hipLaunchKernelGGL((k_geodesic<kMixed, kStk, kFuse>), dim3(nslots), dim3(kWave), pad, s, a);
 }
-template <bool kMixed>
+template <bool kMixed, bool kFuse>
 void launch_variant(int kb, int nslots, size_t pad, const GeoArgs &a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-    if (kb <= 4) launch_one<kMixed, 4096>(nslots, pad, a, s, ev0, ev1);
-    else if (kb <= 8) launch_one<kMixed, 8192>(nslots, pad, a, s, ev0, ev1);
-    else launch_one<kMixed, 16384>(nslots, pad, a, s, ev0, ev1);
+    if (kb <= 4) launch_one<kMixed, 4096, kFuse>(nslots, pad, a, s, ev0, ev1);
+    else if (kb <= 8) launch_one<kMixed, 8192, kFuse>(nslots, pad, a, s, ev0, ev1);
+    else launch_one<kMixed, 16384, kFuse>(nslots, pad, a, s, ev0, ev1);
 }
 
 }  // namespace
@@ -905,21 +908,24 @@ hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoPa
     a.roots = roots;
     a.rstride = rstride;
     a.rcap = rcap;
-    a.fuse = fuse ? 1 : 0;
+
     if (shape.nslots < 1 || bi.begin[bi.nsurf] < 1) return hipSuccess;
     const size_t pad = shape.pad_lds > 0 ? (size_t)shape.pad_lds : 0;
-    if (fp32) launch_variant<true>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
-    else launch_variant<false>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
+    if (fp32 && fuse) launch_variant<true, true>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
+    else if (fp32) launch_variant<true, false>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
+    else if (fuse) launch_variant<false, true>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
+    else launch_variant<false, false>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
     return hipGetLastError();
 }
 
 int geodesic_blocks_per_cu(int lds_stack_kb, bool fp32) {
     int nb = 0;
     const void *f;
-    if (lds_stack_kb <= 4) f = fp32 ? (const void *)&k_geodesic<true, 4096> : (const void *)&k_geodesic<false, 4096>;
+    if (lds_stack_kb <= 4)
+        f = fp32 ? (const void *)&k_geodesic<true, 4096, false> : (const void *)&k_geodesic<false, 4096, false>;
     else if (lds_stack_kb <= 8)
-        f = fp32 ? (const void *)&k_geodesic<true, 8192> : (const void *)&k_geodesic<false, 8192>;
-    else f = fp32 ? (const void *)&k_geodesic<true, 16384> : (const void *)&k_geodesic<false, 16384>;
+        f = fp32 ? (const void *)&k_geodesic<true, 8192, false> : (const void *)&k_geodesic<false, 8192, false>;
+    else f = fp32 ? (const void *)&k_geodesic<true, 16384, false> : (const void *)&k_geodesic<false, 16384, false>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kWave, 0) != hipSuccess) return 0;
     return nb;
 }
