@@ -414,9 +414,11 @@ __device__ int find_candidates(const SurfDesc &sd, Lds &L, int src, int64_t c0) 
 }
 
 // Geodesics from one source to its candidate targets; writes the row and
-// returns whether any pair lies inside the guard band of the cutoff.
+// returns whether any pair lies inside the guard band of the cutoff. Always
+// inlined: the FP32-mixed kernel holds both precisions' loops, and a call to
+// the FP64 one would make the FP32 loop spill registers around it.
 template <typename R>
-__device__ bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigned char *stk, int stk_bytes, int src,
+__device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigned char *stk, int stk_bytes, int src,
                            int64_t c0, int nc, bool guard_mode, int slot_id, SrcStats &st) {
     const int lane = lane_id();
     const long long t_start = clock64();
