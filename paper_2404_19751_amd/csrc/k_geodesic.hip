@@ -783,9 +783,10 @@ __device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &
 
 // The fused update of one source particle (lane 0): force from its row,
 // integrator, walk, new state into the next-state arrays; returns its pair
-// count. Not inlined: inlined, the walk's registers push the propagation
-// loop into spilling (measured slower).
-__device__ __noinline__ int fused_move(const SurfDesc &sd, int src) {
+// count. It runs after the source loop (a fused launch has one workgroup per
+// source), where nothing of the propagation is live, so it costs the loop no
+// registers.
+__device__ __attribute__((always_inline)) inline int fused_move(const SurfDesc &sd, int src) {
     double F[3], E;
     int np = 0;
     row_force(src, sd.cand_cnt, sd.cap, sd.cdist, sd.ctan, sd.cutoff, sd.pkind, sd.pk, sd.psigma, F, E, np);
@@ -811,7 +812,8 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
     st.depth = 0;
     st.overflow = false;
     unsigned long long c_limited = 0;
-    unsigned long long fused_np = 0;  // neighbour pairs of the moved particles (lane 0)
+    unsigned long long fused_np = 0;  // neighbour pairs of the moved particle (lane 0)
+    int fused_src = -1, fused_si = 0;  // the source a fused launch's workgroup took
     int next = 0, left = 0;  // claimed sources not yet processed
     for (;;) {
         // ---- next source: claim `grab` consecutive ones, XCD-local chunk first
@@ -855,13 +857,19 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
             if (st.overflow) ++c_limited;
         }
         if (kFuse) {
-            // the row is final: move the source particle (the same force sum,
-            // integrator and walk as the separate update kernel, read back
-            // from the row this wavefront has just written) into the
-            // next-state arrays, which no source reads during the pass
-            __syncthreads();
-            if (lane == 0) fused_np += (unsigned long long)fused_move(sd, src);
+            // one source per workgroup: its particle is moved below
+            fused_src = src;
+            fused_si = si;
+            break;
         }
+    }
+    if (kFuse && fused_src >= 0) {
+        // the row is final: move the source particle (the same force sum,
+        // integrator and walk as the separate update kernel, read back from
+        // the row this wavefront has just written) into the next-state
+        // arrays, which no source reads during the pass
+        __syncthreads();
+        if (lane == 0) fused_np += (unsigned long long)fused_move(a.sd[fused_si], fused_src);
     }
     unsigned long long pr = (unsigned long long)st.pruned, sl = st.stale;
     for (int o = 32; o > 0; o >>= 1) {
@@ -906,7 +914,7 @@ hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoPa
     a.stack = stack_mem;
     a.work = work_ctr;
     a.ctr = ctr;
-    a.grab = shape.grab < 1 ? 1 : shape.grab;
+    a.grab = shape.grab < 1 || fuse ? 1 : shape.grab;  // a fused launch takes one source per workgroup
     a.roots = roots;
     a.rstride = rstride;
     a.rcap = rcap;
