@@ -796,11 +796,15 @@ __device__ __attribute__((always_inline)) inline int fused_move(const SurfDesc &
 
 // Two waves per SIMD: with up to eight workgroups' LDS on a compute unit, a
 // wavefront may hold at most 256 registers.
-// kFuse: the instantiation with the fused particle update; the others carry
-// none of its code, which would otherwise change the register allocation of
-// every launch.
-template <bool kMixed, int kStk, bool kFuse>
+// kMode 0: a persistent grid whose workgroups claim sources until none is
+// left; 1: one workgroup per source (a launch with no more sources than
+// resident slots), which carries no loop state through the propagation and
+// compiles to fewer registers; 2: as 1, and the source particle is then moved
+// (the fused update). Only mode 2 holds the update's code, which would
+// otherwise change the register allocation of every launch.
+template <bool kMixed, int kStk, int kMode>
 __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
+    constexpr bool kOne = kMode >= 1, kFuse = kMode == 2;
     __shared__ Lds L;
     __shared__ alignas(16) unsigned char stk[kStk];
     const int lane = lane_id();
@@ -856,8 +860,8 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
             }
             if (st.overflow) ++c_limited;
         }
-        if (kFuse) {
-            // one source per workgroup: its particle is moved below
+        if (kOne) {
+            // one source per workgroup (in mode 2 its particle is moved below)
             fused_src = src;
             fused_si = si;
             break;
@@ -888,18 +892,25 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
     }
 }
 
-template <bool kMixed, int kStk, bool kFuse>
+template <bool kMixed, int kStk, int kMode>
 void launch_one(int nslots, size_t pad, const GeoArgs &a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (ev0 || ev1)
-        hipExtLaunchKernelGGL((k_geodesic<kMixed, kStk, kFuse>), dim3(nslots), dim3(kWave), (uint32_t)pad, s, ev0, ev1,
+        hipExtLaunchKernelGGL((k_geodesic<kMixed, kStk, kMode>), dim3(nslots), dim3(kWave), (uint32_t)pad, s, ev0, ev1,
                               0, a);
-    else hipLaunchKernelGGL((k_geodesic<kMixed, kStk, kFuse>), dim3(nslots), dim3(kWave), pad, s, a);
+    else hipLaunchKernelGGL((k_geodesic<kMixed, kStk, kMode>), dim3(nslots), dim3(kWave), pad, s, a);
 }
-template <bool kMixed, bool kFuse>
-void launch_variant(int kb, int nslots, size_t pad, const GeoArgs &a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-    if (kb <= 4) launch_one<kMixed, 4096, kFuse>(nslots, pad, a, s, ev0, ev1);
-    else if (kb <= 8) launch_one<kMixed, 8192, kFuse>(nslots, pad, a, s, ev0, ev1);
-    else launch_one<kMixed, 16384, kFuse>(nslots, pad, a, s, ev0, ev1);
+template <bool kMixed, int kMode>
+void launch_stack(int kb, int nslots, size_t pad, const GeoArgs &a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (kb <= 4) launch_one<kMixed, 4096, kMode>(nslots, pad, a, s, ev0, ev1);
+    else if (kb <= 8) launch_one<kMixed, 8192, kMode>(nslots, pad, a, s, ev0, ev1);
+    else launch_one<kMixed, 16384, kMode>(nslots, pad, a, s, ev0, ev1);
+}
+template <bool kMixed>
+void launch_variant(int mode, int kb, int nslots, size_t pad, const GeoArgs &a, hipStream_t s, hipEvent_t ev0,
+                    hipEvent_t ev1) {
+    if (mode == 2) launch_stack<kMixed, 2>(kb, nslots, pad, a, s, ev0, ev1);
+    else if (mode == 1) launch_stack<kMixed, 1>(kb, nslots, pad, a, s, ev0, ev1);
+    else launch_stack<kMixed, 0>(kb, nslots, pad, a, s, ev0, ev1);
 }
 
 }  // namespace
@@ -914,17 +925,20 @@ hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoPa
     a.stack = stack_mem;
     a.work = work_ctr;
     a.ctr = ctr;
-    a.grab = shape.grab < 1 || fuse ? 1 : shape.grab;  // a fused launch takes one source per workgroup
+    // one workgroup per source when there are no more sources than slots
+    // (always so when fused: the update requires it)
+    const int total = bi.begin[bi.nsurf];
+    const int mode = fuse ? 2 : (total <= shape.nslots ? 1 : 0);
+    a.grab = shape.grab < 1 || mode > 0 ? 1 : shape.grab;
     a.roots = roots;
     a.rstride = rstride;
     a.rcap = rcap;
 
-    if (shape.nslots < 1 || bi.begin[bi.nsurf] < 1) return hipSuccess;
+    if (shape.nslots < 1 || total < 1) return hipSuccess;
+    if (fuse && total > shape.nslots) return hipErrorInvalidValue;  // the fused update needs a slot per source
     const size_t pad = shape.pad_lds > 0 ? (size_t)shape.pad_lds : 0;
-    if (fp32 && fuse) launch_variant<true, true>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
-    else if (fp32) launch_variant<true, false>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
-    else if (fuse) launch_variant<false, true>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
-    else launch_variant<false, false>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
+    if (fp32) launch_variant<true>(mode, shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
+    else launch_variant<false>(mode, shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
     return hipGetLastError();
 }
 
@@ -932,10 +946,10 @@ int geodesic_blocks_per_cu(int lds_stack_kb, bool fp32) {
     int nb = 0;
     const void *f;
     if (lds_stack_kb <= 4)
-        f = fp32 ? (const void *)&k_geodesic<true, 4096, false> : (const void *)&k_geodesic<false, 4096, false>;
+        f = fp32 ? (const void *)&k_geodesic<true, 4096, 0> : (const void *)&k_geodesic<false, 4096, 0>;
     else if (lds_stack_kb <= 8)
-        f = fp32 ? (const void *)&k_geodesic<true, 8192, false> : (const void *)&k_geodesic<false, 8192, false>;
-    else f = fp32 ? (const void *)&k_geodesic<true, 16384, false> : (const void *)&k_geodesic<false, 16384, false>;
+        f = fp32 ? (const void *)&k_geodesic<true, 8192, 0> : (const void *)&k_geodesic<false, 8192, 0>;
+    else f = fp32 ? (const void *)&k_geodesic<true, 16384, 0> : (const void *)&k_geodesic<false, 16384, 0>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kWave, 0) != hipSuccess) return 0;
     return nb;
 }
