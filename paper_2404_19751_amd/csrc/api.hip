@@ -840,7 +840,7 @@ gsim_status gsim_create(int device, gsim_precision prec, void *hip_stream, gsim_
     c->gp.stack_cap = 16384;  // 1 MiB of overflow per resident wavefront (wide patches run deep)
     c->gp.max_windows = 4000000;
     c->max_windows_all = 1 << 26;
-    if (ensure(c->work, sizeof(int32_t) * 16) != hipSuccess || ensure(c->ctr, sizeof(Counters)) != hipSuccess ||
+    if (ensure(c->work, sizeof(int32_t) * kWorkInts) != hipSuccess || ensure(c->ctr, sizeof(Counters)) != hipSuccess ||
         ensure(c->wstats, sizeof(unsigned long long) * 8) != hipSuccess ||
         ensure(c->pf_over, sizeof(int32_t) * 4) != hipSuccess ||
         ensure(c->desc, sizeof(SurfDesc) * kMaxBatch) != hipSuccess ||

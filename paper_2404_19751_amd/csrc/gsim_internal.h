@@ -269,6 +269,12 @@ size_t geodesic_lds_bytes(int lds_stack_kb, bool fp32);
 // positions + cell counting sort, one workgroup per surface (every surface's
 // grid must have at most kSmallCells cells)
 constexpr int kSmallCells = 4096;
+// Work counters of the persistent geodesic grids: one per XCD chunk, each on
+// a 128-byte line of its own so that claims on different chunks do not
+// contend.
+constexpr int kWorkChunks = 8;
+constexpr int kWorkStride = 32;  // int32 entries between two chunks' counters
+constexpr int kWorkInts = kWorkChunks * kWorkStride;
 // (also clears the work counters and, when `advance`, moves every surface's
 // step counter on by one)
 // commit: take the state from the next-state arrays first (fused time steps)

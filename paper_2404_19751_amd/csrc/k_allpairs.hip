@@ -38,6 +38,7 @@ namespace {
 using namespace wnd;
 
 constexpr int kChunks = 8;
+static_assert(kChunks == kWorkChunks, "one work counter per chunk");
 
 struct AllArgs {
     const SurfDesc *sd;
@@ -840,7 +841,7 @@ __global__ __launch_bounds__(kWave) void k_geodesic_all(AllArgs a) {
                 const int lo = (int)(((int64_t)total * chunk) / kChunks);
                 const int hi = (int)(((int64_t)total * (chunk + 1)) / kChunks);
                 int t = 0;
-                if (lane == 0) t = atomicAdd(&a.work[chunk], a.grab);
+                if (lane == 0) t = atomicAdd(&a.work[chunk * kWorkStride], a.grab);
                 t = __shfl(t, 0);
                 if (lo + t < hi) {
                     next = lo + t;

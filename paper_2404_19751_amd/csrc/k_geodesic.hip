@@ -74,6 +74,7 @@ using namespace wnd;
 constexpr int kMaxCand = kCandCap;
 constexpr int kHash = 256;
 constexpr int kChunks = 8;
+static_assert(kChunks == kWorkChunks, "one work counter per chunk");
 
 struct GeoArgs {
     const SurfDesc *sd;  // [nsurf] surface descriptors
@@ -819,6 +820,20 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
     unsigned long long fused_np = 0;  // neighbour pairs of the moved particle (lane 0)
     int fused_src = -1, fused_si = 0;  // the source a fused launch's workgroup took
     int next = 0, left = 0;  // claimed sources not yet processed
+    if (kOne) {
+        // one workgroup per source, no claims: workgroup b takes position
+        // b / 8 of chunk b mod 8, where chunk c holds the sources of the
+        // workgroups with b mod 8 = c (a bijection onto the sources in cell
+        // order, each chunk a contiguous region)
+        if ((int)blockIdx.x < total) {
+            const int c = (int)blockIdx.x % kChunks;
+            int start = 0;
+            for (int k = 0; k < c; ++k) start += (total - k + kChunks - 1) / kChunks;
+            next = start + (int)blockIdx.x / kChunks;
+            left = 1;
+        }
+        chunks_left = 0;
+    }
     for (;;) {
         // ---- next source: claim `grab` consecutive ones, XCD-local chunk first
         if (left == 0) {
@@ -826,7 +841,7 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
                 const int lo = (int)(((int64_t)total * chunk) / kChunks);
                 const int hi = (int)(((int64_t)total * (chunk + 1)) / kChunks);
                 int t = 0;
-                if (lane == 0) t = atomicAdd(&a.work[chunk], a.grab);
+                if (lane == 0) t = atomicAdd(&a.work[chunk * kWorkStride], a.grab);
                 t = __shfl(t, 0);
                 if (lo + t < hi) {
                     next = lo + t;

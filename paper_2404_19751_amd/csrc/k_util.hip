@@ -156,7 +156,7 @@ __global__ __launch_bounds__(kBinThreads) void k_bin_batch(const SurfDesc *__res
     const SurfDesc &sd = desc[blockIdx.x];
     // start of a pass: the geodesic kernel's work counters, and (in a time
     // step) the surface's step counter
-    if (blockIdx.x == 0 && threadIdx.x < 16) work[threadIdx.x] = 0;
+    if (blockIdx.x == 0 && threadIdx.x < kWorkChunks) work[threadIdx.x * kWorkStride] = 0;
     if (advance && threadIdx.x == 0) *sd.step += 1;
     const double *__restrict__ fpos = sd.m.fpos;
     const int n = sd.n;
@@ -308,7 +308,7 @@ __global__ void k_integrate(int n, DevMesh m, const int32_t *__restrict__ face, 
 // counters and (in a time step) the step counters.
 __global__ void k_pass_begin(const SurfDesc *__restrict__ desc, int nsurf, int32_t *__restrict__ work, int advance) {
     const int t = threadIdx.x;
-    if (t < 16) work[t] = 0;
+    if (t < kWorkChunks) work[t * kWorkStride] = 0;
     if (advance && t < nsurf) *desc[t].step += 1;
 }
 __global__ void k_fill_u64(unsigned long long *p, int64_t n, unsigned long long v) {
