@@ -258,7 +258,7 @@ int pot_kind_ok(const gsim_potential *p) { return p && p->kind >= 0 && p->kind <
 // queues its work without any host synchronisation, and reads the counters
 // back once at the end.
 gsim_status begin_call(gsim_ctx *c) {
-    HIPCHK(c, launch_zero_u64(P<unsigned long long>(c->ctr), 8, c->stream));
+    HIPCHK(c, launch_zero_u64(P<unsigned long long>(c->ctr), 8 * kCtrSlots * kCtrStride, c->stream));
     HIPCHK(c, launch_zero_i32(P<int32_t>(c->pf_over), 1, c->stream));
     c->passes = 0;
     return GSIM_OK;
@@ -266,9 +266,23 @@ gsim_status begin_call(gsim_ctx *c) {
 
 gsim_status end_call(gsim_ctx *c) {
     int32_t over = 0;
-    HIPCHK(c, hipMemcpyAsync(&c->last, c->ctr.p, sizeof(Counters), hipMemcpyDeviceToHost, c->stream));
+    Counters slots[kCtrSlots * kCtrStride];
+    HIPCHK(c, hipMemcpyAsync(slots, c->ctr.p, sizeof(slots), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipMemcpyAsync(&over, c->pf_over.p, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    Counters &L = c->last;
+    L = Counters{};
+    for (int k = 0; k < kCtrSlots; ++k) {
+        const Counters &q = slots[k * kCtrStride];
+        L.windows += q.windows;
+        L.pruned += q.pruned;
+        L.launches += q.launches;
+        L.stale += q.stale;
+        L.guards += q.guards;
+        L.nbr_pairs += q.nbr_pairs;
+        L.limited += q.limited;
+        L.max_depth = std::max(L.max_depth, q.max_depth);
+    }
     c->cum_pairs += c->last.nbr_pairs;
     c->cum_windows += c->last.windows;
     c->cum_passes += c->passes;
@@ -840,7 +854,7 @@ gsim_status gsim_create(int device, gsim_precision prec, void *hip_stream, gsim_
     c->gp.stack_cap = 16384;  // 1 MiB of overflow per resident wavefront (wide patches run deep)
     c->gp.max_windows = 4000000;
     c->max_windows_all = 1 << 26;
-    if (ensure(c->work, sizeof(int32_t) * kWorkInts) != hipSuccess || ensure(c->ctr, sizeof(Counters)) != hipSuccess ||
+    if (ensure(c->work, sizeof(int32_t) * kWorkInts) != hipSuccess || ensure(c->ctr, sizeof(Counters) * kCtrSlots * kCtrStride) != hipSuccess ||
         ensure(c->wstats, sizeof(unsigned long long) * 8) != hipSuccess ||
         ensure(c->pf_over, sizeof(int32_t) * 4) != hipSuccess ||
         ensure(c->desc, sizeof(SurfDesc) * kMaxBatch) != hipSuccess ||

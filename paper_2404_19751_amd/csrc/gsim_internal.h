@@ -122,6 +122,12 @@ struct GeoOut {
 struct Counters {   // device-side, int64
     unsigned long long windows, pruned, launches, stale, guards, nbr_pairs, limited, max_depth;
 };
+// The device counters are kCtrSlots copies, 128 bytes apart: the geodesic
+// grid's workgroups add into the copy of their XCD chunk (fewer atomics on
+// one line), the other kernels into the first; the host sums them (max_depth:
+// the maximum).
+constexpr int kCtrSlots = 8;
+constexpr int kCtrStride = 2;  // Counters between two slots
 
 // launchers (return hipError_t of the launch)
 hipError_t launch_xyz(const DevMesh &m, int n, const int32_t *face, const double *bary, double *xyz,

@@ -895,15 +895,16 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
         pr += __shfl_xor(pr, o);
         sl += __shfl_xor(sl, o);
     }
+    Counters *ctr = a.ctr + ((int)blockIdx.x % kCtrSlots) * kCtrStride;
     if (lane == 0) {
-        atomicAdd(&a.ctr->windows, st.windows);
-        atomicAdd(&a.ctr->pruned, pr);
-        atomicAdd(&a.ctr->launches, st.launches);
-        atomicAdd(&a.ctr->stale, sl);
-        atomicAdd(&a.ctr->limited, c_limited);
-        atomicMax(&a.ctr->max_depth, (unsigned long long)st.depth);
-        if (st.guards) atomicAdd(&a.ctr->guards, st.guards);
-        if (fused_np) atomicAdd(&a.ctr->nbr_pairs, fused_np);
+        atomicAdd(&ctr->windows, st.windows);
+        atomicAdd(&ctr->pruned, pr);
+        atomicAdd(&ctr->launches, st.launches);
+        atomicAdd(&ctr->stale, sl);
+        atomicAdd(&ctr->limited, c_limited);
+        atomicMax(&ctr->max_depth, (unsigned long long)st.depth);
+        if (st.guards) atomicAdd(&ctr->guards, st.guards);
+        if (fused_np) atomicAdd(&ctr->nbr_pairs, fused_np);
     }
 }
 
