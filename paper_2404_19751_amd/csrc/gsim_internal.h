@@ -122,11 +122,11 @@ struct GeoOut {
 struct Counters {   // device-side, int64
     unsigned long long windows, pruned, launches, stale, guards, nbr_pairs, limited, max_depth;
 };
-// The device counters are kCtrSlots copies, 128 bytes apart: the geodesic
-// grid's workgroups add into the copy of their XCD chunk (fewer atomics on
-// one line), the other kernels into the first; the host sums them (max_depth:
-// the maximum).
-constexpr int kCtrSlots = 8;
+// The device counters are kCtrSlots copies, 128 bytes apart: each workgroup
+// of the geodesic grid adds into copy (workgroup mod kCtrSlots), so that its
+// end-of-workgroup atomics do not serialise on one line; the other kernels
+// add into the first; the host sums them (max_depth: the maximum).
+constexpr int kCtrSlots = 64;
 constexpr int kCtrStride = 2;  // Counters between two slots
 
 // launchers (return hipError_t of the launch)

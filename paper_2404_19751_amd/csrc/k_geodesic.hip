@@ -897,12 +897,13 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
     }
     Counters *ctr = a.ctr + ((int)blockIdx.x % kCtrSlots) * kCtrStride;
     if (lane == 0) {
-        atomicAdd(&ctr->windows, st.windows);
-        atomicAdd(&ctr->pruned, pr);
-        atomicAdd(&ctr->launches, st.launches);
-        atomicAdd(&ctr->stale, sl);
-        atomicAdd(&ctr->limited, c_limited);
-        atomicMax(&ctr->max_depth, (unsigned long long)st.depth);
+        // only the counts that are not zero
+        if (st.windows) atomicAdd(&ctr->windows, st.windows);
+        if (pr) atomicAdd(&ctr->pruned, pr);
+        if (st.launches) atomicAdd(&ctr->launches, st.launches);
+        if (sl) atomicAdd(&ctr->stale, sl);
+        if (c_limited) atomicAdd(&ctr->limited, c_limited);
+        if (st.depth) atomicMax(&ctr->max_depth, (unsigned long long)st.depth);
         if (st.guards) atomicAdd(&ctr->guards, st.guards);
         if (fused_np) atomicAdd(&ctr->nbr_pairs, fused_np);
     }
