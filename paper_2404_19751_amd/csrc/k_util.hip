@@ -255,16 +255,17 @@ __global__ void k_compact_rows(int n, const int32_t *__restrict__ cnt, int cap, 
 __global__ void k_forces_rows(int n, const int32_t *__restrict__ cnt, int cap, const double *__restrict__ dist,
                               const double *__restrict__ tan, double cutoff, int kind, double k, double sigma,
                               double *__restrict__ F, double *__restrict__ Ei, unsigned long long *__restrict__ npairs) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double f[3], e;
-    int np;
-    row_force(i, cnt, cap, dist, tan, cutoff, kind, k, sigma, f, e, np);
-    F[3 * i] = f[0];
-    F[3 * i + 1] = f[1];
-    F[3 * i + 2] = f[2];
-    Ei[i] = e;
-    if (npairs && np) atomicAdd(npairs, (unsigned long long)np);
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int np = 0;
+    if (i < n) {
+        double f[3], e;
+        row_force(i, cnt, cap, dist, tan, cutoff, kind, k, sigma, f, e, np);
+        F[3 * i] = f[0];
+        F[3 * i + 1] = f[1];
+        F[3 * i + 2] = f[2];
+        Ei[i] = e;
+    }
+    if (npairs) wave_atomic_add(npairs, (unsigned long long)np);
 }
 
 // deterministic two-level sum
@@ -350,11 +351,10 @@ __global__ __launch_bounds__(kFireBlock) void k_fire_partials(const SurfDesc *__
     const SurfDesc &sd = desc[si];
     const int i = (b - blk.begin[si]) * kFireBlock + t;
     double p = 0.0, vv = 0.0, ff = 0.0;
+    int np = 0;
     if (sd.ikind == 2 && i < sd.n) {
         double F[3], E;
-        int np;
         row_force(i, sd.cand_cnt, sd.cap, sd.cdist, sd.ctan, sd.cutoff, sd.pkind, sd.pk, sd.psigma, F, E, np);
-        if (np) atomicAdd(npairs, (unsigned long long)np);
         const double *v = sd.vel + 3 * (int64_t)i;
         for (int d = 0; d < 3; ++d) {
             sd.F[3 * (int64_t)i + d] = F[d];
@@ -363,6 +363,7 @@ __global__ __launch_bounds__(kFireBlock) void k_fire_partials(const SurfDesc *__
             ff += F[d] * F[d];
         }
     }
+    wave_atomic_add(npairs, (unsigned long long)np);
     sh[0][t] = p;
     sh[1][t] = vv;
     sh[2][t] = ff;

@@ -9,37 +9,39 @@
 namespace gsim {
 namespace {
 
+// every lane of the wavefront calls it (wavefront sums, one atomic each)
 __device__ inline void flush_counts(const WalkCounts &wc, unsigned long long *stats) {
     if (!stats) return;
-    if (wc.cross_n) atomicAdd(&stats[0], (unsigned long long)wc.cross_n);
-    if (wc.vhit) atomicAdd(&stats[1], (unsigned long long)wc.vhit);
-    if (wc.bhit) atomicAdd(&stats[2], (unsigned long long)wc.bhit);
-    if (wc.cap) atomicAdd(&stats[3], (unsigned long long)wc.cap);
-    if (wc.near) atomicAdd(&stats[4], (unsigned long long)wc.near);
+    wave_atomic_add(&stats[0], wc.cross_n);
+    wave_atomic_add(&stats[1], wc.vhit);
+    wave_atomic_add(&stats[2], wc.bhit);
+    wave_atomic_add(&stats[3], wc.cap);
+    wave_atomic_add(&stats[4], wc.near);
 }
 
 __global__ __launch_bounds__(128) void k_walk(DevMesh m, int n, int32_t *__restrict__ face, double *__restrict__ bary,
                                               const double *__restrict__ disp, double *__restrict__ vel,
                                               unsigned long long *__restrict__ stats, uint8_t *__restrict__ flags) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int f = face[i];
-    double b[3] = {bary[3 * i], bary[3 * i + 1], bary[3 * i + 2]};
-    const bool hv = vel != nullptr;
-    d3 v = hv ? ld3(vel + 3 * (int64_t)i) : d3{0, 0, 0};
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
     WalkCounts wc = {0, 0, 0, 0, 0};
-    uint8_t fl = 0;
-    walk_one(m, f, b, ld3(disp + 3 * (int64_t)i), v, hv, wc, fl);
-    face[i] = f;
-    bary[3 * i] = b[0];
-    bary[3 * i + 1] = b[1];
-    bary[3 * i + 2] = b[2];
-    if (hv) {
-        vel[3 * i] = v.x;
-        vel[3 * i + 1] = v.y;
-        vel[3 * i + 2] = v.z;
+    if (i < n) {
+        int f = face[i];
+        double b[3] = {bary[3 * i], bary[3 * i + 1], bary[3 * i + 2]};
+        const bool hv = vel != nullptr;
+        d3 v = hv ? ld3(vel + 3 * (int64_t)i) : d3{0, 0, 0};
+        uint8_t fl = 0;
+        walk_one(m, f, b, ld3(disp + 3 * (int64_t)i), v, hv, wc, fl);
+        face[i] = f;
+        bary[3 * i] = b[0];
+        bary[3 * i + 1] = b[1];
+        bary[3 * i + 2] = b[2];
+        if (hv) {
+            vel[3 * i] = v.x;
+            vel[3 * i + 1] = v.y;
+            vel[3 * i + 2] = v.z;
+        }
+        if (flags) flags[i] = fl;
     }
-    if (flags) flags[i] = fl;
     flush_counts(wc, stats);
 }
 
