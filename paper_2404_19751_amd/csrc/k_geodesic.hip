@@ -692,7 +692,8 @@ __device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &
         // loaded now and applied after the children (whose arithmetic covers
         // the load's latency)
         bool ok3 = false;
-        double d3 = 0, tx3 = 0, ty3 = 0, alt3 = INFINITY, pD = INFINITY, pD2 = INFINITY;
+        double d3 = 0, tx3 = 0, ty3 = 0, alt3 = INFINITY;
+        BendEntry pE;
         {
             bool ok = false;
             double d = 0, tx = 0, ty = 0, alt = INFINITY;
@@ -720,13 +721,10 @@ __device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &
             tx3 = tx;
             ty3 = ty;
             alt3 = alt;
-            if (ok) {
-                pD = G.rD[pe3];
-                pD2 = G.rD2[pe3];
-            }
+            if (ok) pE = bend_load(G, pe3);
         }
         if (have) children(H, w, txc, false, C, F3, U3, L, cl, hl, cr, hr, pruned);
-        bend_update_loaded(G, L.B, C.rc, ok3, pe3, d3, tx3, ty3, alt3, pD, pD2);
+        bend_update_loaded(G, L.B, C.rc, ok3, pe3, d3, tx3, ty3, alt3, pE);
         // keep one child in the lane, push the other
         S.push(hl && hr, cr, overflow);
         if (have) {

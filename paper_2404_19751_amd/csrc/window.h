@@ -163,13 +163,27 @@ struct BendLds {
 // cannot change anything (the stored distances only decrease); the others
 // are applied one lane at a time in registers, each result passed to every
 // lane holding the same vertex, and written back once.
-// bend_update_loaded takes the entry's rD and rD2 loaded by the caller
-// (earlier, so that their latency overlaps other work; no other update of
-// the table may come in between).
+// bend_update_loaded takes the entry loaded by the caller (bend_load,
+// earlier, so that its latency overlaps other work; no other update of the
+// table may come in between).
+struct BendEntry {
+    double D = INFINITY, D2 = INFINITY, L = INFINITY, tx = 0.0, ty = 0.0;
+    int q = 1;
+};
+__device__ inline BendEntry bend_load(const BendTable &G, int e) {
+    BendEntry c;
+    c.D = G.rD[e];
+    c.D2 = G.rD2[e];
+    c.L = G.rL[e];
+    c.tx = G.rtx[e];
+    c.ty = G.rty[e];
+    c.q = G.queued[e];
+    return c;
+}
 __device__ inline void bend_update_loaded(const BendTable &G, BendLds &L, const RootCfg &rc, bool ok, int e, double d,
-                                          double tx, double ty, double alt, double cD, double cD2) {
-    double cL = INFINITY, ax = 0.0, ay = 0.0;
-    int qd = 1;
+                                          double tx, double ty, double alt, const BendEntry &c) {
+    double cD = c.D, cD2 = c.D2, cL = c.L, ax = c.tx, ay = c.ty;
+    int qd = c.q;
     if (!ok) {
         cD = INFINITY;
         cD2 = INFINITY;
@@ -178,12 +192,6 @@ __device__ inline void bend_update_loaded(const BendTable &G, BendLds &L, const 
     }
     uint64_t m = __ballot(ok);
     if (!m) return;
-    if (ok) {
-        cL = G.rL[e];
-        ax = G.rtx[e];
-        ay = G.rty[e];
-        qd = G.queued[e];
-    }
     // list lengths, wave-uniform in registers
     int np = L.npend, nt = L.ntouched;
     while (m) {
@@ -246,12 +254,9 @@ __device__ inline void bend_update_loaded(const BendTable &G, BendLds &L, const 
 }
 __device__ inline void bend_update(const BendTable &G, BendLds &L, const RootCfg &rc, bool ok, int e, double d,
                                    double tx, double ty, double alt) {
-    double cD = INFINITY, cD2 = INFINITY;
-    if (ok) {
-        cD = G.rD[e];
-        cD2 = G.rD2[e];
-    }
-    bend_update_loaded(G, L, rc, ok, e, d, tx, ty, alt, cD, cD2);
+    BendEntry c;
+    if (ok) c = bend_load(G, e);
+    bend_update_loaded(G, L, rc, ok, e, d, tx, ty, alt, c);
 }
 
 // A window of bend vertex w.root is stale when it comes from an earlier
