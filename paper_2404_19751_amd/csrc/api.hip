@@ -889,7 +889,7 @@ void gsim_destroy(gsim_ctx *c) {
         for (void *p : {(void *)ms->dm.V, (void *)ms->dm.T, (void *)ms->dm.he, (void *)ms->dm.hef,
                         (void *)ms->dm.vflag, (void *)ms->dm.theta, (void *)ms->dm.fan_off, (void *)ms->dm.fan,
                         (void *)ms->dm.corner, (void *)ms->dm.fnrm, (void *)ms->dm.fpos,
-                        (void *)ms->dm.pidx, (void *)ms->dm.pvert})
+                        (void *)ms->dm.pidx, (void *)ms->dm.pvert, (void *)ms->dm.prec})
             if (p) (void)hipFree(p);
         delete ms;
     }
@@ -944,6 +944,7 @@ gsim_status gsim_mesh_upload(gsim_ctx *c, int32_t nv, const double *xyz, int32_t
         HIPCHK(c, upload(d.fpos, H.fpos.data(), H.fpos.size(), s));
         HIPCHK(c, upload(d.pidx, H.pidx.data(), H.pidx.size(), s));
         HIPCHK(c, upload(d.pvert, H.pvert.data(), H.pvert.size(), s));
+        HIPCHK(c, upload(d.prec, H.prec.data(), H.prec.size(), s));
         for (int k = 0; k < 3; ++k) {
             d.bbmin[k] = H.bbmin[k];
             d.bbmax[k] = H.bbmax[k];

@@ -41,6 +41,14 @@ static_assert(sizeof(HeRecF) == 48, "HeRecF must be 48 bytes");
 enum : uint8_t { VF_PSEUDO = 1, VF_BOUNDARY = 2 };
 enum : uint8_t { GSIM_PAIR_TIE_BIT = 1, GSIM_PAIR_ZERO_BIT = 2, GSIM_PAIR_GUARD_BIT = 4 };
 
+// Per bend vertex (dense number): its position and its fan of outgoing
+// half-edges, read together when the vertex is launched.
+struct PseudoRec {
+    double x, y, z;
+    int32_t v, fan_beg, fan_deg, pad;
+};
+static_assert(sizeof(PseudoRec) == 40, "PseudoRec must be a 40-byte record");
+
 struct DevMesh {
     int32_t nv = 0, nf = 0;
     double *V = nullptr;        // [nv][3]
@@ -57,6 +65,7 @@ struct DevMesh {
                                 // directions of its half-edges 3f+0..2
     int32_t *pidx = nullptr;    // [nv] bend-vertex number (0..n_pseudo-1) of a pseudo-source, else -1
     int32_t *pvert = nullptr;   // [max(n_pseudo,1)] the vertex of each bend-vertex number
+    PseudoRec *prec = nullptr;  // [max(n_pseudo,1)] its position and fan
     double bbmin[3], bbmax[3];
     double mean_edge = 0, min_edge = 0, max_edge = 0;
     int32_t n_boundary_edges = 0, n_pseudo = 0;
@@ -74,6 +83,7 @@ struct HostMesh {
     std::vector<double> theta, corner, fnrm, fpos;
     std::vector<int32_t> fan_off, fan;
     std::vector<int32_t> pidx, pvert;
+    std::vector<PseudoRec> prec;
     double bbmin[3], bbmax[3];
     double mean_edge = 0, min_edge = 0, max_edge = 0;
     int32_t n_boundary_edges = 0, n_pseudo = 0;

@@ -233,11 +233,24 @@ __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, Lds &L, const
     const DevMesh &M = sd.m;
     const HeRec *__restrict__ he = M.he;
     const int npend = L.B.npend;
+    // the first wavefront's worth of pending entries is read once for both
+    // passes below
+    int e0 = 0;
+    double D0 = 0.0, L0 = INFINITY;
+    if (lane < npend) {
+        e0 = G.pend[lane];
+        D0 = G.rD[e0];
+        L0 = G.rL[e0];
+    }
     double mn = INFINITY;
     for (int k = lane; k < npend; k += kWave) {
-        const int e = G.pend[k];
-        const double D = G.rD[e];
-        if (D < G.rL[e] * C.rc.keep && D < C.cut_acc) mn = fmin(mn, D);
+        double D = D0, Lr = L0;
+        if (k >= kWave) {
+            const int e = G.pend[k];
+            D = G.rD[e];
+            Lr = G.rL[e];
+        }
+        if (D < Lr * C.rc.keep && D < C.cut_acc) mn = fmin(mn, D);
     }
     mn = wave_min(mn);
     const double thr = mn + a.gp.launch_delta;
@@ -251,15 +264,24 @@ __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, Lds &L, const
         bool sel = false, keep = false;
         double D = 0.0;
         if (k < npend) {
-            e = G.pend[k];
-            D = G.rD[e];
-            const bool cand = D < G.rL[e] * C.rc.keep && D < C.cut_acc;
+            double Lr = L0;
+            if (base == 0) {
+                e = e0;
+                D = D0;
+            } else {
+                e = G.pend[k];
+                D = G.rD[e];
+                Lr = G.rL[e];
+            }
+            const bool cand = D < Lr * C.rc.keep && D < C.cut_acc;
             sel = cand && D <= thr;
             keep = cand && !sel;
         }
         const uint64_t ms = __ballot(sel), mk = __ballot(keep);
         if (sel) {
-            G.sel[nsel + __popcll(ms & lanemask_lt())] = e;
+            const int pos = nsel + __popcll(ms & lanemask_lt());
+            G.sel[pos] = e;
+            if (pos < kLaunchChunk) L.B.sel[pos] = e;  // the first chunk also through LDS
             G.rL[e] = D;
         }
         if (keep) G.pend[nkeep + __popcll(mk & lanemask_lt())] = e;
@@ -277,17 +299,22 @@ __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, Lds &L, const
             const int k = base + lane;
             int deg = 0;
             if (k < cn) {
-                const int e = G.sel[c0 + k], v = M.pvert[e];
-                L.B.sel[k] = e;
+                int e;
+                if (c0 == 0) {
+                    e = L.B.sel[k];
+                } else {
+                    e = G.sel[c0 + k];
+                    L.B.sel[k] = e;
+                }
+                const PseudoRec pr = M.prec[e];
                 const double D = G.rD[e];
-                const double vx = M.V[3 * (int64_t)v], vy = M.V[3 * (int64_t)v + 1], vz = M.V[3 * (int64_t)v + 2];
                 bool useful = false;
                 for (int s = 0; s < C.nc && !useful; ++s) {
                     const double bound = L.cb[s][3] - D;
-                    const double q0 = L.cb[s][0] - vx, q1 = L.cb[s][1] - vy, q2 = L.cb[s][2] - vz;
+                    const double q0 = L.cb[s][0] - pr.x, q1 = L.cb[s][1] - pr.y, q2 = L.cb[s][2] - pr.z;
                     useful = bound > 0.0 && q0 * q0 + q1 * q1 + q2 * q2 < bound * bound;
                 }
-                if (useful) deg = M.fan_off[v + 1] - M.fan_off[v];
+                if (useful) deg = pr.fan_deg;
             }
             // wave-inclusive scan of deg
             int inc = deg;
@@ -317,11 +344,12 @@ __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, Lds &L, const
                 k = lo;
             }
             const int el = act ? L.B.sel[k] : 0;
-            const int v = act ? M.pvert[el] : 0;
+            PseudoRec pr{0.0, 0.0, 0.0, 0, 0, 0, 0};
+            if (act) pr = M.prec[el];
             const double D = act ? G.rD[el] : 0.0;
             const double vtx = act ? G.rtx[el] : 0.0, vty = act ? G.rty[el] : 0.0;
             const double D2 = act ? G.rD2[el] : INFINITY;  // the vertex's other-direction distance
-            const int h = act ? M.fan[M.fan_off[v] + (idx - L.B.pref[k])] : 0;
+            const int h = act ? M.fan[pr.fan_beg + (idx - L.B.pref[k])] : 0;
             const int hn = h - h % 3 + (h % 3 + 1) % 3;
             const HeRec Rh = he[h], Rn = he[hn];
             Win<R> nw;
@@ -347,19 +375,18 @@ __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, Lds &L, const
             // direct targets in face(h)
             const int g = h / 3;
             int slot = act ? first_in_face(L, g) : -1;
-            const double *pv = M.V + 3 * (int64_t)v;
             while (__ballot(slot >= 0)) {
                 const bool ok = slot >= 0;
                 double d = 0;
                 if (ok) {
-                    const double dx = L.cb[slot][0] - pv[0], dy = L.cb[slot][1] - pv[1], dz = L.cb[slot][2] - pv[2];
+                    const double dx = L.cb[slot][0] - pr.x, dy = L.cb[slot][1] - pr.y, dz = L.cb[slot][2] - pr.z;
                     d = D + sqrt(dx * dx + dy * dy + dz * dz);
                 }
                 target_update(L, C, ok, slot, d, vtx, vty, D2 + (d - D));
                 if (ok) slot = next_in_face(L, slot, g);
             }
             // adjacent bend vertices along the two edges at v
-            const int u1 = act ? M.T[hn] : 0;  // head of h
+            const int u1 = act ? Rh.head : 0;  // head of h
             const int e1 = act && D + Rh.L < C.cut_acc ? M.pidx[u1] : -1;
             bend_update(G, L.B, C.rc, e1 >= 0, e1, D + Rh.L, vtx, vty, D2 + Rh.L);
             const int u2 = act ? Rh.opp_flags >> 1 : 0;

@@ -151,6 +151,18 @@ std::string build_host_mesh(int nv, const double *xyz, int nf, const int32_t *tr
             M.pvert.push_back(v);
         }
     if (M.pvert.empty()) M.pvert.push_back(-1);
+    M.prec.assign(M.pvert.size(), PseudoRec{0.0, 0.0, 0.0, -1, 0, 0, 0});
+    for (size_t e = 0; e < M.pvert.size(); ++e) {
+        const int v = M.pvert[e];
+        if (v < 0) continue;
+        PseudoRec &r = M.prec[e];
+        r.x = M.V[3 * size_t(v)];
+        r.y = M.V[3 * size_t(v) + 1];
+        r.z = M.V[3 * size_t(v) + 2];
+        r.v = v;
+        r.fan_beg = M.fan_off[v];
+        r.fan_deg = M.fan_off[v + 1] - M.fan_off[v];
+    }
 
     // unfolding records
     M.he.resize(ne);
