@@ -324,7 +324,7 @@ __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, Lds &L, const
             }
             if (k < cn) L.B.pref[k + 1] = carry + inc;
             st.launches += (unsigned long long)__popcll(__ballot(deg > 0));
-            carry += __shfl(inc, kWave - 1);
+            carry += __builtin_amdgcn_readlane(inc, kWave - 1);
         }
         if (lane == 0) L.B.pref[0] = 0;
         __syncthreads();
@@ -867,7 +867,7 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
                 const int hi = (int)(((int64_t)total * (chunk + 1)) / kChunks);
                 int t = 0;
                 if (lane == 0) t = atomicAdd(&a.work[chunk * kWorkStride], a.grab);
-                t = __shfl(t, 0);
+                t = __builtin_amdgcn_readlane(t, 0);
                 if (lo + t < hi) {
                     next = lo + t;
                     left = min(a.grab, hi - next);

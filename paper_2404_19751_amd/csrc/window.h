@@ -166,6 +166,14 @@ struct BendLds {
 // bend_update_loaded takes the entry loaded by the caller (bend_load,
 // earlier, so that its latency overlaps other work; no other update of the
 // table may come in between).
+// Lane l's value of x (l wave-uniform): two scalar reads instead of a
+// cross-lane permute.
+__device__ inline double readlane_d(double x, int l) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
 struct BendEntry {
     double D = INFINITY, D2 = INFINITY, L = INFINITY, tx = 0.0, ty = 0.0;
     int q = 1;
@@ -225,8 +233,8 @@ __device__ inline void bend_update_loaded(const BendTable &G, BendLds &L, const 
         np += __builtin_amdgcn_readlane(app, l);
         nt += __builtin_amdgcn_readlane(fresh, l);
         const int el = __builtin_amdgcn_readlane(e, l);
-        const double bD = __shfl(cD, l), bD2 = __shfl(cD2, l), bL = __shfl(cL, l);
-        const double bx = __shfl(ax, l), by = __shfl(ay, l);
+        const double bD = readlane_d(cD, l), bD2 = readlane_d(cD2, l), bL = readlane_d(cL, l);
+        const double bx = readlane_d(ax, l), by = readlane_d(ay, l);
         const int bq = __builtin_amdgcn_readlane(qd, l);
         if (ok && e == el) {
             cD = bD;
