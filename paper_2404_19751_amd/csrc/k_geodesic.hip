@@ -34,9 +34,11 @@
 // recomputed at once in FP64 by the same wavefront, so neighbour sets stay
 // exact.
 //
-// Mapping to CDNA4: one wavefront per source (persistent grid; sources in
-// spatial cell order from eight per-XCD work chunks so each XCD's L2 serves
-// one region of the mesh); each lane holds one live window in registers; a
+// Mapping to CDNA4: one wavefront per source (one workgroup per source when
+// there are no more sources than resident slots, else a persistent grid that
+// claims them; either way sources in spatial cell order from eight per-XCD
+// chunks so each XCD's L2 serves one region of the mesh); each lane holds one
+// live window in registers; a
 // lane with two children keeps one and pushes the other onto an LDS window
 // stack (ballot/popcount compaction; a per-wave global overflow area takes
 // what does not fit); idle lanes pop. The target table lives in LDS and its
@@ -48,12 +50,13 @@
 // workgroup's LDS footprint and lets more wavefronts share a compute unit.
 //
 // Batches: the sources of several surfaces (each with its own mesh, cutoff
-// and particles) form one flattened index space served by the same
-// persistent grid; a wavefront finds its source's surface from the batch
-// boundaries and reads that surface's descriptor.
+// and particles) form one flattened index space served by the same grid; a
+// wavefront finds its source's surface from the batch boundaries and reads
+// that surface's descriptor. The grid's statistics go into one of several
+// counter slots (by workgroup), so that they do not serialise on one line.
 //
-// Fused update (time steps with few sources): once a source's row is final,
-// lane 0 of its wavefront applies the force sum over the row (Sec. 3.1),
+// Fused update (time steps with few sources, one workgroup per source): once
+// the source's row is final, lane 0 applies the force sum over the row (Sec. 3.1),
 // the integrator (Sec. 2.1) and the walk (Sec. 3.2) to that particle and
 // writes its new state into next-state arrays, which no source reads during
 // the pass; the row is read back with the same code as the separate update
