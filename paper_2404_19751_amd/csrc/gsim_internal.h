@@ -241,11 +241,13 @@ hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoPa
 // All-pairs geodesics (no cutoff) for every source of the batch: every other
 // particle of the surface is a target. vdist: per resident wavefront a table
 // of vstride vertex distances; roots: per resident wavefront a bend-vertex
-// table of rstride bytes for rcap bend vertices (bend_table_bytes); tcap:
-// target-table capacity (dynamic LDS).
+// table of rstride bytes for rcap bend vertices (bend_table_bytes); ttan:
+// per resident wavefront tcap target tangents; tcap: target capacity (the
+// target distances take 16 bytes of dynamic LDS each).
 hipError_t launch_geodesic_all(const SurfDesc *desc, const BatchIdx &bi, const GeoParams &gp, const GeoShape &shape,
                                char *stack_mem, double *vdist, int64_t vstride, char *roots, int64_t rstride,
-                               int rcap, int tcap, int32_t *work_ctr, Counters *ctr, bool fp32, hipStream_t s);
+                               int rcap, double2 *ttan, int tcap, int32_t *work_ctr, Counters *ctr, bool fp32,
+                               hipStream_t s);
 // In-surface Voronoi neighbours (k_voronoi.hip): at most kVoronoiMax
 // particles (an n x n adjacency bitset). launch_voronoi_faces marks every
 // pair of particles whose cells share a boundary longer than tol; cell lists

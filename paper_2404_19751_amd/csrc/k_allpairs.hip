@@ -21,8 +21,9 @@
 // Bend vertices are launched by the rules of the cutoff kernel, from a table
 // that can hold every saddle and boundary vertex of the surface.
 //
-// Mapping: target state (best distance, second-best distance of another
-// direction, tangent) of all n targets in dynamic LDS; the vertex table, the
+// Mapping: the two distances of all n targets (best, and best of another
+// direction) in dynamic LDS (16 bytes a target, so that four workgroups fit
+// a compute unit at n = 2000); their tangents, the vertex table, the
 // bend-vertex table and the window overflow in per-wavefront global areas
 // (the overflow is two-ended: the current round grows from one end, the next
 // round from the other); targets are found through the surface's
@@ -52,7 +53,8 @@ struct AllArgs {
     int rcap;
     int32_t *work;
     Counters *ctr;
-    int tcap;        // target capacity of the dynamic LDS table
+    double2 *ttan;   // per wavefront: tcap target tangents
+    int tcap;        // target capacity (the distances in dynamic LDS, the tangents in ttan)
     int grab;
 };
 
@@ -159,35 +161,70 @@ __device__ inline void vdist_min(double *Dv, int v, double d) {
     atomicMin(reinterpret_cast<unsigned long long *>(Dv + v), (unsigned long long)__double_as_longlong(d));
 }
 
-// Serialised target update: best distance, its tangent, and the best
-// distance among candidates whose direction differs (tie gap); `alt` is the
-// distance of another-direction path that comes with the candidate.
-__device__ inline void target_update(AllLds &L, double *d1, double *d2, double *t1x, double *t1y, const ACtx &C,
-                                     bool ok, int j, double d, double tx, double ty, double alt) {
-    // candidates no shorter than both distances (which only decrease) change nothing
-    if (ok && d >= d1[j] && d >= d2[j] && alt >= d2[j]) ok = false;
+// Target update: best distance, its tangent, and the best distance among
+// candidates whose direction differs (tie gap); `alt` is the distance of an
+// another-direction path that comes with the candidate. The lanes load their
+// targets together and leave when their candidate cannot change anything
+// (the stored distances only decrease); the others are applied one lane at a
+// time in registers, each result passed to every lane holding the same
+// target, and written back once (the tangent only where the best distance
+// fell).
+__device__ inline void target_update(AllLds &L, double *d1, double *d2, double2 *tt, const ACtx &C, bool ok, int j,
+                                     double d, double tx, double ty, double alt) {
+    double c1 = INFINITY, c2 = INFINITY;
+    if (ok) {
+        c1 = d1[j];
+        c2 = d2[j];
+        if (d >= c1 && d >= c2 && alt >= c2) ok = false;
+    }
     uint64_t m = __ballot(ok);
+    if (!m) return;
+    const double c1_in = c1, c2_in = c2;
+    double ax = 0.0, ay = 0.0;
+    if (ok && c1 < INFINITY) {
+        const double2 t = tt[j];
+        ax = t.x;
+        ay = t.y;
+    }
+    int reached = 0;  // targets found for the first time
     while (m) {
         const int l = __ffsll((unsigned long long)m) - 1;
+        int first = 0;
         if (lane_id() == l) {
-            const double c1 = d1[j];
-            const double ax = t1x[j], ay = t1y[j];
             const bool found = c1 < INFINITY;
             const bool differ = !found || fabs(ax * ty - ay * tx) > C.tie_dir || ax * tx + ay * ty < 0.0;
             if (d < c1) {
-                if (differ) d2[j] = fmin(d2[j], c1);
-                d1[j] = d;
-                t1x[j] = tx;
-                t1y[j] = ty;
-                if (!found) L.unfound--;
+                if (differ) c2 = fmin(c2, c1);
+                c1 = d;
+                ax = tx;
+                ay = ty;
+                first = !found;
             } else if (differ) {
-                d2[j] = fmin(d2[j], d);
+                c2 = fmin(c2, d);
             }
-            d2[j] = fmin(d2[j], alt);
+            c2 = fmin(c2, alt);
         }
-        lane_step_barrier();
+        reached += __builtin_amdgcn_readlane(first, l);
+        const int jl = __builtin_amdgcn_readlane(j, l);
+        const double b1 = readlane_d(c1, l), b2 = readlane_d(c2, l);
+        const double bx = readlane_d(ax, l), by = readlane_d(ay, l);
+        if (ok && j == jl) {
+            c1 = b1;
+            c2 = b2;
+            ax = bx;
+            ay = by;
+        }
         m &= m - 1;
     }
+    if (ok) {
+        if (c1 < c1_in) {
+            d1[j] = c1;
+            tt[j] = make_double2(ax, ay);
+        }
+        if (c2 < c2_in) d2[j] = c2;
+    }
+    if (lane_id() == 0 && reached) L.unfound -= reached;
+    lane_step_barrier();
 }
 
 // Trim a child interval [x0, x1] on an edge S -> E (length Lc, child frame
@@ -252,8 +289,8 @@ __device__ inline bool opposite_dominates(double px, double py, double sg, doubl
 
 // Targets in face g (entry half-edge slot k of g) seen through window w.
 template <typename R>
-__device__ inline void query_face(const SurfDesc &sd, AllLds &L, const BendTable &G, double *d1, double *d2, double *t1x,
-                                  double *t1y, const ACtx &C, bool have, int src, int g, int k, const He<R> &H,
+__device__ inline void query_face(const SurfDesc &sd, AllLds &L, const BendTable &G, double *d1, double *d2, double2 *tt,
+                                  const ACtx &C, bool have, int src, int g, int k, const He<R> &H,
                                   const Win<R> &w) {
     int q = 0, q1 = 0;
     if (have) {
@@ -291,7 +328,7 @@ __device__ inline void query_face(const SurfDesc &sd, AllLds &L, const BendTable
             }
             ++q;
         }
-        target_update(L, d1, d2, t1x, t1y, C, ok, j, d, tx, ty, alt);
+        target_update(L, d1, d2, tt, C, ok, j, d, tx, ty, alt);
     }
 }
 
@@ -300,7 +337,7 @@ __device__ inline void query_face(const SurfDesc &sd, AllLds &L, const BendTable
 // a chunk of vertices at a time.
 template <typename R>
 __device__ void launch_roots(const AllArgs &a, const SurfDesc &sd, AllLds &L, const BendTable &G, double *d1,
-                             double *d2, double *t1x, double *t1y, double *Dv, const ACtx &C, RoundStack<R> &S,
+                             double *d2, double2 *tt, double *Dv, const ACtx &C, RoundStack<R> &S,
                              double T, int src, SrcStats &st) {
     const int lane = lane_id();
     const DevMesh &M = sd.m;
@@ -417,7 +454,7 @@ __device__ void launch_roots(const AllArgs &a, const SurfDesc &sd, AllLds &L, co
                     }
                     ++q;
                 }
-                target_update(L, d1, d2, t1x, t1y, C, ok, j, d, vtx, vty, D2 + (d - D));
+                target_update(L, d1, d2, tt, C, ok, j, d, vtx, vty, D2 + (d - D));
             }
             // the two other vertices of face(h), reached along its edges
             const int u1 = Rh.head, u2 = Rh.opp_flags >> 1;
@@ -442,8 +479,8 @@ __device__ void launch_roots(const AllArgs &a, const SurfDesc &sd, AllLds &L, co
 // FP32 result lies within the guard band around the cutoff (the caller then
 // recomputes the source in FP64; `guard` marks that recompute).
 template <typename R>
-__device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double *d1, double *d2, double *t1x,
-                        double *t1y, unsigned char *stk, int stk_bytes, int src, int slot, bool guard,
+__device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double *d1, double *d2, double2 *tt,
+                        unsigned char *stk, int stk_bytes, int src, int slot, bool guard,
                         SrcStats &st) {
     const int lane = lane_id();
     const bool fp32 = sizeof(R) == 4;
@@ -474,8 +511,7 @@ __device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
     for (int j = lane; j < n; j += kWave) {
         d1[j] = INFINITY;
         d2[j] = INFINITY;
-        t1x[j] = 0.0;
-        t1y[j] = 0.0;
+        tt[j] = make_double2(0.0, 0.0);
     }
     if (lane == 0) {
         L.B.npend = 0;
@@ -517,7 +553,7 @@ __device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
                 }
                 ++q;
             }
-            target_update(L, d1, d2, t1x, t1y, C, ok, j, d, tx, ty, INFINITY);
+            target_update(L, d1, d2, tt, C, ok, j, d, tx, ty, INFINITY);
         }
     }
     {
@@ -605,7 +641,7 @@ __device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
                     }
                     ++q;
                 }
-                target_update(L, d1, d2, t1x, t1y, C, ok, j, d, tx, ty, INFINITY);
+                target_update(L, d1, d2, tt, C, ok, j, d, tx, ty, INFINITY);
             }
             const double dx = Rt.cx - ptx, dy = Rt.cy;
             const double d = sqrt(dx * dx + dy * dy);
@@ -630,7 +666,7 @@ __device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
         depth = max(depth, S.lsp + S.gsp + S.dsp);
         bool busy = S.refill(have, w);
         if (!busy && L.B.npend > 0) {
-            launch_roots(a, sd, L, G, d1, d2, t1x, t1y, Dv, C, S, T, src, st);
+            launch_roots(a, sd, L, G, d1, d2, tt, Dv, C, S, T, src, st);
             busy = S.refill(have, w);
         }
         if (!busy) {
@@ -705,7 +741,7 @@ __device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
                 }
             }
         }
-        query_face(sd, L, G, d1, d2, t1x, t1y, C, have, src, f, k, H, w);
+        query_face(sd, L, G, d1, d2, tt, C, have, src, f, k, H, w);
         // third vertex as a bend vertex
         {
             bool ok = have && H.pseudo && cin;
@@ -792,6 +828,7 @@ __device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
     const bool ovf = __ballot(overflow) != 0;
     const int64_t c0 = (int64_t)src * sd.cap;
     bool near_cut = false;
+    __syncthreads();  // every lane's tangent stores are visible
     for (int j = lane; j < n; j += kWave) {
         const int64_t o = c0 + j;
         double d = d1[j];
@@ -803,7 +840,8 @@ __device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
         near_cut |= C.cutoff < INFINITY && fabs(d - C.cutoff) <= a.gp.guard_rel * C.cutoff;
         sd.cdist[o] = d;
         sd.cflags[o] = fl;
-        for (int qd = 0; qd < 3; ++qd) sd.ctan[3 * o + qd] = t1x[j] * ex3[qd] + t1y[j] * ey3[qd];
+        const double2 t = tt[j];
+        for (int qd = 0; qd < 3; ++qd) sd.ctan[3 * o + qd] = t.x * ex3[qd] + t.y * ey3[qd];
     }
     if (sd.prof && lane == 0) {
         long long *qp = sd.prof + 8 * (int64_t)src;
@@ -824,7 +862,8 @@ __global__ __launch_bounds__(kWave) void k_geodesic_all(AllArgs a) {
     __shared__ AllLds L;
     __shared__ alignas(16) unsigned char stk[kStk];
     extern __shared__ double tdyn[];
-    double *d1 = tdyn, *d2 = tdyn + a.tcap, *t1x = tdyn + 2 * a.tcap, *t1y = tdyn + 3 * a.tcap;
+    double *d1 = tdyn, *d2 = tdyn + a.tcap;
+    double2 *tt = a.ttan + (size_t)blockIdx.x * a.tcap;
     const int lane = lane_id();
     const int total = a.bi.begin[a.bi.nsurf];
     int chunk = blockIdx.x % kChunks, chunks_left = kChunks;
@@ -861,11 +900,11 @@ __global__ __launch_bounds__(kWave) void k_geodesic_all(AllArgs a) {
         if (lane == 0) sd.cand_cnt[src] = sd.n;
         st.overflow = false;
         bool again = !kMixed;
-        if (kMixed) again = run_all<float>(a, sd, L, d1, d2, t1x, t1y, stk, kStk, src, blockIdx.x, false, st);
+        if (kMixed) again = run_all<float>(a, sd, L, d1, d2, tt, stk, kStk, src, blockIdx.x, false, st);
         if (again) {
             // FP64 (the plain path, or the recompute of an FP32 source whose
             // results come too close to the cutoff to decide in FP32)
-            run_all<double>(a, sd, L, d1, d2, t1x, t1y, stk, kStk, src, blockIdx.x, kMixed, st);
+            run_all<double>(a, sd, L, d1, d2, tt, stk, kStk, src, blockIdx.x, kMixed, st);
             st.guards += kMixed ? 1 : 0;
         }
         if (st.overflow) ++c_limited;
@@ -904,7 +943,8 @@ void launch_variant(int kb, int nslots, size_t dyn, const AllArgs &a, hipStream_
 
 hipError_t launch_geodesic_all(const SurfDesc *desc, const BatchIdx &bi, const GeoParams &gp, const GeoShape &shape,
                                char *stack_mem, double *vdist, int64_t vstride, char *roots, int64_t rstride,
-                               int rcap, int tcap, int32_t *work_ctr, Counters *ctr, bool fp32, hipStream_t s) {
+                               int rcap, double2 *ttan, int tcap, int32_t *work_ctr, Counters *ctr, bool fp32,
+                               hipStream_t s) {
     AllArgs a;
     a.sd = desc;
     a.bi = bi;
@@ -920,7 +960,8 @@ hipError_t launch_geodesic_all(const SurfDesc *desc, const BatchIdx &bi, const G
     a.tcap = tcap;
     a.grab = shape.grab < 1 ? 1 : shape.grab;
     if (shape.nslots < 1 || bi.begin[bi.nsurf] < 1) return hipSuccess;
-    const size_t dyn = sizeof(double) * 4 * (size_t)tcap;
+    a.ttan = ttan;
+    const size_t dyn = sizeof(double) * 2 * (size_t)tcap;
     if (fp32) launch_variant<true>(shape.lds_stack_kb, shape.nslots, dyn, a, s);
     else launch_variant<false>(shape.lds_stack_kb, shape.nslots, dyn, a, s);
     return hipGetLastError();
@@ -929,7 +970,7 @@ hipError_t launch_geodesic_all(const SurfDesc *desc, const BatchIdx &bi, const G
 int geodesic_all_blocks_per_cu(int lds_stack_kb, int tcap, bool fp32) {
     int nb = 0;
     const void *f = fp32 ? kernel_of<true>(lds_stack_kb) : kernel_of<false>(lds_stack_kb);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kWave, sizeof(double) * 4 * (size_t)tcap) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kWave, sizeof(double) * 2 * (size_t)tcap) != hipSuccess)
         return 0;
     return nb;
 }
