@@ -73,7 +73,7 @@ struct gsim_ctx {
     bool own_stream = false;
     std::string err;
     std::vector<MeshState *> meshes;
-    Buf stack, work, ctr, wstats, scan_scratch, sum_scratch, pf_over, prof, desc, vdist, ttan, roots, partials, vbits;
+    Buf stack, work, ctr, wstats, scan_scratch, sum_scratch, pf_over, prof, desc, vdist, ttab, roots, partials, vbits;
     SurfDesc *desc_pinned = nullptr;  // staging for descriptor uploads
     std::vector<SurfDesc> desc_cached;
     bool profile_sources = false;
@@ -94,7 +94,7 @@ struct gsim_ctx {
     int grab = 1;
     int update_block = 128;
     int stack_cap_all = 1 << 18;  // window records per wavefront in all-pairs passes
-    double stack_budget = 24e9;   // bytes of window stacks an all-pairs pass may hold
+    double stack_budget = 40e9;   // bytes of window stacks an all-pairs pass may hold
     int max_windows_all = 0;      // per-source window limit in all-pairs passes
     int cus = 256;
     bool whole_mesh = false;  // finite-cutoff passes on the whole-mesh kernel
@@ -514,11 +514,7 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
     }
     // persistent grid: as many wavefronts as can be resident, at most one per source
     const bool fp32 = c->prec == GSIM_FP32_MIXED;
-    if (B.all && (size_t)B.tcap * 16 + kAllLdsFixed > (size_t)c->max_lds)
-        return fail(c, GSIM_E_LIMIT, "all-pairs target table of " + std::to_string(B.tcap) +
-                                         " particles exceeds the device's LDS per workgroup (" +
-                                         std::to_string(c->max_lds) + " bytes)");
-    const int per_cu = std::max(1, B.all ? geodesic_all_blocks_per_cu(c->lds_stack_kb, B.tcap, fp32)
+    const int per_cu = std::max(1, B.all ? geodesic_all_blocks_per_cu(c->lds_stack_kb, fp32)
                                          : geodesic_blocks_per_cu(c->lds_stack_kb, fp32));
     B.nslots = std::min(std::min(total, c->cus * per_cu), c->max_slots);
     if (B.all) {
@@ -558,7 +554,7 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
     HIPCHK(c, ensure(c->stack, (size_t)std::max(B.nslots, 1) * cap_rec * 64));
     if (B.all) {
         HIPCHK(c, ensure(c->vdist, sizeof(double) * (size_t)std::max(B.nslots, 1) * B.vstride));
-        HIPCHK(c, ensure(c->ttan, 2 * sizeof(double) * (size_t)std::max(B.nslots, 1) * B.tcap));
+        HIPCHK(c, ensure(c->ttab, 4 * sizeof(double) * (size_t)std::max(B.nslots, 1) * B.tcap));
     }
     // bend-vertex tables: emptied once here, left empty by the kernels
     const int nsl = std::max(B.nslots, 1);
@@ -597,7 +593,7 @@ gsim_status geodesic_pass(gsim_ctx *c, Batch &B, bool advance, bool commit_in = 
         gp.max_windows = c->max_windows_all;
         Stage st(c, "geodesic");
         HIPCHK(c, launch_geodesic_all(desc_dev(c), B.bi, gp, B.shape, P<char>(c->stack), P<double>(c->vdist), B.vstride,
-                                      P<char>(c->roots), B.rstride, B.rcap, P<double2>(c->ttan), B.tcap,
+                                      P<char>(c->roots), B.rstride, B.rcap, P<double2>(c->ttab), B.tcap,
                                       P<int32_t>(c->work), P<Counters>(c->ctr), c->prec == GSIM_FP32_MIXED, s));
         c->passes++;
         return GSIM_OK;
@@ -717,7 +713,7 @@ std::string graph_key(gsim_ctx *c, const Batch &B, int steps) {
     put(&B.fused, sizeof(B.fused));
     put(&c->update_block, sizeof(int));
     put(&steps, sizeof(int));
-    void *ptrs[9] = {c->stack.p, c->work.p, c->ctr.p, c->desc.p, c->scan_scratch.p, c->vdist.p, c->ttan.p,
+    void *ptrs[9] = {c->stack.p, c->work.p, c->ctr.p, c->desc.p, c->scan_scratch.p, c->vdist.p, c->ttab.p,
                      c->roots.p, c->partials.p};
     put(ptrs, sizeof(ptrs));
     const int64_t sizes[4] = {B.rstride, B.rcap, B.tcap, B.vstride};
@@ -897,7 +893,7 @@ void gsim_destroy(gsim_ctx *c) {
         delete ms;
     }
     for (Buf *b : {&c->stack, &c->work, &c->ctr, &c->wstats, &c->scan_scratch, &c->sum_scratch, &c->pf_over,
-                   &c->prof, &c->desc, &c->vdist, &c->ttan, &c->roots, &c->partials, &c->vbits})
+                   &c->prof, &c->desc, &c->vdist, &c->ttab, &c->roots, &c->partials, &c->vbits})
         release(*b);
     if (c->desc_pinned) (void)hipHostFree(c->desc_pinned);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);

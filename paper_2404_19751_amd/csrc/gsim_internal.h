@@ -241,12 +241,11 @@ hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoPa
 // All-pairs geodesics (no cutoff) for every source of the batch: every other
 // particle of the surface is a target. vdist: per resident wavefront a table
 // of vstride vertex distances; roots: per resident wavefront a bend-vertex
-// table of rstride bytes for rcap bend vertices (bend_table_bytes); ttan:
-// per resident wavefront tcap target tangents; tcap: target capacity (the
-// target distances take 16 bytes of dynamic LDS each).
+// table of rstride bytes for rcap bend vertices (bend_table_bytes); ttab:
+// per resident wavefront the state of tcap targets (4 doubles each).
 hipError_t launch_geodesic_all(const SurfDesc *desc, const BatchIdx &bi, const GeoParams &gp, const GeoShape &shape,
                                char *stack_mem, double *vdist, int64_t vstride, char *roots, int64_t rstride,
-                               int rcap, double2 *ttan, int tcap, int32_t *work_ctr, Counters *ctr, bool fp32,
+                               int rcap, double2 *ttab, int tcap, int32_t *work_ctr, Counters *ctr, bool fp32,
                                hipStream_t s);
 // In-surface Voronoi neighbours (k_voronoi.hip): at most kVoronoiMax
 // particles (an n x n adjacency bitset). launch_voronoi_faces marks every
@@ -268,10 +267,7 @@ __host__ __device__ inline int64_t bend_table_bytes(int rcap) { return ((int64_t
 // empty: every distance infinite, nothing queued. The kernels leave them
 // empty again after each source.
 hipError_t launch_bend_init(char *roots, int nslots, int64_t rstride, int rcap, hipStream_t s);
-// LDS of an all-pairs workgroup besides its target table (the largest
-// window stack and the launch chunk).
-constexpr int kAllLdsFixed = 16384 + 4096;
-int geodesic_all_blocks_per_cu(int lds_stack_kb, int tcap, bool fp32);
+int geodesic_all_blocks_per_cu(int lds_stack_kb, bool fp32);
 // particles of one surface sorted by face (counting sort; counts must be zeroed)
 hipError_t launch_face_sort(const SurfDesc &d, int32_t *counts, int64_t *tmp64, int64_t *scan_scratch, hipStream_t s);
 // row i of an all-pairs surface lists every particle j in order

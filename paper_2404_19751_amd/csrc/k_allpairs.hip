@@ -21,9 +21,8 @@
 // Bend vertices are launched by the rules of the cutoff kernel, from a table
 // that can hold every saddle and boundary vertex of the surface.
 //
-// Mapping: the two distances of all n targets (best, and best of another
-// direction) in dynamic LDS (16 bytes a target, so that four workgroups fit
-// a compute unit at n = 2000); their tangents, the vertex table, the
+// Mapping: the state of all n targets (best distance, best distance of
+// another direction, tangent; 32 bytes each), the vertex table, the
 // bend-vertex table and the window overflow in per-wavefront global areas
 // (the overflow is two-ended: the current round grows from one end, the next
 // round from the other); targets are found through the surface's
@@ -53,8 +52,8 @@ struct AllArgs {
     int rcap;
     int32_t *work;
     Counters *ctr;
-    double2 *ttan;   // per wavefront: tcap target tangents
-    int tcap;        // target capacity (the distances in dynamic LDS, the tangents in ttan)
+    double2 *ttab;   // per wavefront: tcap target distances (best, tie), then tcap tangents
+    int tcap;
     int grab;
 };
 
@@ -169,12 +168,13 @@ __device__ inline void vdist_min(double *Dv, int v, double d) {
 // time in registers, each result passed to every lane holding the same
 // target, and written back once (the tangent only where the best distance
 // fell).
-__device__ inline void target_update(AllLds &L, double *d1, double *d2, double2 *tt, const ACtx &C, bool ok, int j,
-                                     double d, double tx, double ty, double alt) {
+__device__ inline void target_update(AllLds &L, double2 *td, double2 *tt, const ACtx &C, bool ok, int j, double d,
+                                     double tx, double ty, double alt) {
     double c1 = INFINITY, c2 = INFINITY;
     if (ok) {
-        c1 = d1[j];
-        c2 = d2[j];
+        const double2 c = td[j];
+        c1 = c.x;
+        c2 = c.y;
         if (d >= c1 && d >= c2 && alt >= c2) ok = false;
     }
     uint64_t m = __ballot(ok);
@@ -217,11 +217,8 @@ __device__ inline void target_update(AllLds &L, double *d1, double *d2, double2 
         m &= m - 1;
     }
     if (ok) {
-        if (c1 < c1_in) {
-            d1[j] = c1;
-            tt[j] = make_double2(ax, ay);
-        }
-        if (c2 < c2_in) d2[j] = c2;
+        if (c1 < c1_in || c2 < c2_in) td[j] = make_double2(c1, c2);
+        if (c1 < c1_in) tt[j] = make_double2(ax, ay);
     }
     if (lane_id() == 0 && reached) L.unfound -= reached;
     lane_step_barrier();
@@ -289,7 +286,7 @@ __device__ inline bool opposite_dominates(double px, double py, double sg, doubl
 
 // Targets in face g (entry half-edge slot k of g) seen through window w.
 template <typename R>
-__device__ inline void query_face(const SurfDesc &sd, AllLds &L, const BendTable &G, double *d1, double *d2, double2 *tt,
+__device__ inline void query_face(const SurfDesc &sd, AllLds &L, const BendTable &G, double2 *td, double2 *tt,
                                   const ACtx &C, bool have, int src, int g, int k, const He<R> &H,
                                   const Win<R> &w) {
     int q = 0, q1 = 0;
@@ -328,7 +325,7 @@ __device__ inline void query_face(const SurfDesc &sd, AllLds &L, const BendTable
             }
             ++q;
         }
-        target_update(L, d1, d2, tt, C, ok, j, d, tx, ty, alt);
+        target_update(L, td, tt, C, ok, j, d, tx, ty, alt);
     }
 }
 
@@ -336,8 +333,8 @@ __device__ inline void query_face(const SurfDesc &sd, AllLds &L, const BendTable
 // direction changed, or a tie appeared), their fans flattened over the lanes
 // a chunk of vertices at a time.
 template <typename R>
-__device__ void launch_roots(const AllArgs &a, const SurfDesc &sd, AllLds &L, const BendTable &G, double *d1,
-                             double *d2, double2 *tt, double *Dv, const ACtx &C, RoundStack<R> &S,
+__device__ void launch_roots(const AllArgs &a, const SurfDesc &sd, AllLds &L, const BendTable &G, double2 *td,
+                             double2 *tt, double *Dv, const ACtx &C, RoundStack<R> &S,
                              double T, int src, SrcStats &st) {
     const int lane = lane_id();
     const DevMesh &M = sd.m;
@@ -454,7 +451,7 @@ __device__ void launch_roots(const AllArgs &a, const SurfDesc &sd, AllLds &L, co
                     }
                     ++q;
                 }
-                target_update(L, d1, d2, tt, C, ok, j, d, vtx, vty, D2 + (d - D));
+                target_update(L, td, tt, C, ok, j, d, vtx, vty, D2 + (d - D));
             }
             // the two other vertices of face(h), reached along its edges
             const int u1 = Rh.head, u2 = Rh.opp_flags >> 1;
@@ -477,11 +474,13 @@ __device__ void launch_roots(const AllArgs &a, const SurfDesc &sd, AllLds &L, co
 // beyond it, by the acceptance slack) and the row keeps every target; the
 // pairs at or beyond the cutoff are left out downstream. Returns whether an
 // FP32 result lies within the guard band around the cutoff (the caller then
-// recomputes the source in FP64; `guard` marks that recompute).
+// recomputes the source in FP64; `guard` marks that recompute). Inlined:
+// as a call, the FP32 kernel spills around it and holds one wave per SIMD.
 template <typename R>
-__device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double *d1, double *d2, double2 *tt,
-                        unsigned char *stk, int stk_bytes, int src, int slot, bool guard,
-                        SrcStats &st) {
+__device__ __attribute__((always_inline)) inline bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L,
+                                                              double2 *td, double2 *tt, unsigned char *stk,
+                                                              int stk_bytes, int src, int slot, bool guard,
+                                                              SrcStats &st) {
     const int lane = lane_id();
     const bool fp32 = sizeof(R) == 4;
     const int n = sd.n;
@@ -509,8 +508,7 @@ __device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
     // ---- tables
     for (int v = lane; v < M.nv; v += kWave) Dv[v] = INFINITY;
     for (int j = lane; j < n; j += kWave) {
-        d1[j] = INFINITY;
-        d2[j] = INFINITY;
+        td[j] = make_double2(INFINITY, INFINITY);
         tt[j] = make_double2(0.0, 0.0);
     }
     if (lane == 0) {
@@ -553,7 +551,7 @@ __device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
                 }
                 ++q;
             }
-            target_update(L, d1, d2, tt, C, ok, j, d, tx, ty, INFINITY);
+            target_update(L, td, tt, C, ok, j, d, tx, ty, INFINITY);
         }
     }
     {
@@ -641,7 +639,7 @@ __device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
                     }
                     ++q;
                 }
-                target_update(L, d1, d2, tt, C, ok, j, d, tx, ty, INFINITY);
+                target_update(L, td, tt, C, ok, j, d, tx, ty, INFINITY);
             }
             const double dx = Rt.cx - ptx, dy = Rt.cy;
             const double d = sqrt(dx * dx + dy * dy);
@@ -666,7 +664,7 @@ __device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
         depth = max(depth, S.lsp + S.gsp + S.dsp);
         bool busy = S.refill(have, w);
         if (!busy && L.B.npend > 0) {
-            launch_roots(a, sd, L, G, d1, d2, tt, Dv, C, S, T, src, st);
+            launch_roots(a, sd, L, G, td, tt, Dv, C, S, T, src, st);
             busy = S.refill(have, w);
         }
         if (!busy) {
@@ -675,9 +673,10 @@ __device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
             S.next_round();
             T += C.bucket;
             if (L.unfound == 0) {
+                __syncthreads();  // every lane's target stores are visible
                 double mx = 0.0;
                 for (int j = lane; j < n; j += kWave)
-                    if (j != src) mx = fmax(mx, d1[j]);
+                    if (j != src) mx = fmax(mx, td[j].x);
                 for (int o = 32; o > 0; o >>= 1) mx = fmax(mx, __shfl_xor(mx, o));
                 if (lane == 0) L.maxb = fmin(L.maxb, mx * (1.0 + C.tie_rel) + 1e-12 * mx);
             }
@@ -741,7 +740,7 @@ __device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
                 }
             }
         }
-        query_face(sd, L, G, d1, d2, tt, C, have, src, f, k, H, w);
+        query_face(sd, L, G, td, tt, C, have, src, f, k, H, w);
         // third vertex as a bend vertex
         {
             bool ok = have && H.pseudo && cin;
@@ -831,11 +830,12 @@ __device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
     __syncthreads();  // every lane's tangent stores are visible
     for (int j = lane; j < n; j += kWave) {
         const int64_t o = c0 + j;
-        double d = d1[j];
+        const double2 dd = td[j];
+        double d = dd.x;
         uint8_t fl = guard ? GSIM_PAIR_GUARD_BIT : 0;
         if (j == src) d = INFINITY;
         else if (ovf) d = NAN;
-        if (j != src && d2[j] - d <= C.tie_rel * d) fl |= GSIM_PAIR_TIE_BIT;
+        if (j != src && dd.y - d <= C.tie_rel * d) fl |= GSIM_PAIR_TIE_BIT;
         if (d == 0.0) fl |= GSIM_PAIR_ZERO_BIT;
         near_cut |= C.cutoff < INFINITY && fabs(d - C.cutoff) <= a.gp.guard_rel * C.cutoff;
         sd.cdist[o] = d;
@@ -855,15 +855,11 @@ __device__ bool run_all(const AllArgs &a, const SurfDesc &sd, AllLds &L, double 
     return fp32 && !ovf && __ballot(near_cut) != 0;
 }
 
-static_assert(sizeof(AllLds) + 16384 <= kAllLdsFixed, "all-pairs LDS besides the target table");
-
 template <bool kMixed, int kStk>
 __global__ __launch_bounds__(kWave) void k_geodesic_all(AllArgs a) {
     __shared__ AllLds L;
     __shared__ alignas(16) unsigned char stk[kStk];
-    extern __shared__ double tdyn[];
-    double *d1 = tdyn, *d2 = tdyn + a.tcap;
-    double2 *tt = a.ttan + (size_t)blockIdx.x * a.tcap;
+    double2 *td = a.ttab + (size_t)blockIdx.x * 2 * a.tcap, *tt = td + a.tcap;
     const int lane = lane_id();
     const int total = a.bi.begin[a.bi.nsurf];
     int chunk = blockIdx.x % kChunks, chunks_left = kChunks;
@@ -900,11 +896,11 @@ __global__ __launch_bounds__(kWave) void k_geodesic_all(AllArgs a) {
         if (lane == 0) sd.cand_cnt[src] = sd.n;
         st.overflow = false;
         bool again = !kMixed;
-        if (kMixed) again = run_all<float>(a, sd, L, d1, d2, tt, stk, kStk, src, blockIdx.x, false, st);
+        if (kMixed) again = run_all<float>(a, sd, L, td, tt, stk, kStk, src, blockIdx.x, false, st);
         if (again) {
             // FP64 (the plain path, or the recompute of an FP32 source whose
             // results come too close to the cutoff to decide in FP32)
-            run_all<double>(a, sd, L, d1, d2, tt, stk, kStk, src, blockIdx.x, kMixed, st);
+            run_all<double>(a, sd, L, td, tt, stk, kStk, src, blockIdx.x, kMixed, st);
             st.guards += kMixed ? 1 : 0;
         }
         if (st.overflow) ++c_limited;
@@ -933,17 +929,17 @@ const void *kernel_of(int kb) {
 }
 
 template <bool kMixed>
-void launch_variant(int kb, int nslots, size_t dyn, const AllArgs &a, hipStream_t s) {
-    if (kb <= 4) hipLaunchKernelGGL((k_geodesic_all<kMixed, 4096>), dim3(nslots), dim3(kWave), dyn, s, a);
-    else if (kb <= 8) hipLaunchKernelGGL((k_geodesic_all<kMixed, 8192>), dim3(nslots), dim3(kWave), dyn, s, a);
-    else hipLaunchKernelGGL((k_geodesic_all<kMixed, 16384>), dim3(nslots), dim3(kWave), dyn, s, a);
+void launch_variant(int kb, int nslots, const AllArgs &a, hipStream_t s) {
+    if (kb <= 4) hipLaunchKernelGGL((k_geodesic_all<kMixed, 4096>), dim3(nslots), dim3(kWave), 0, s, a);
+    else if (kb <= 8) hipLaunchKernelGGL((k_geodesic_all<kMixed, 8192>), dim3(nslots), dim3(kWave), 0, s, a);
+    else hipLaunchKernelGGL((k_geodesic_all<kMixed, 16384>), dim3(nslots), dim3(kWave), 0, s, a);
 }
 
 }  // namespace
 
 hipError_t launch_geodesic_all(const SurfDesc *desc, const BatchIdx &bi, const GeoParams &gp, const GeoShape &shape,
                                char *stack_mem, double *vdist, int64_t vstride, char *roots, int64_t rstride,
-                               int rcap, double2 *ttan, int tcap, int32_t *work_ctr, Counters *ctr, bool fp32,
+                               int rcap, double2 *ttab, int tcap, int32_t *work_ctr, Counters *ctr, bool fp32,
                                hipStream_t s) {
     AllArgs a;
     a.sd = desc;
@@ -960,17 +956,16 @@ hipError_t launch_geodesic_all(const SurfDesc *desc, const BatchIdx &bi, const G
     a.tcap = tcap;
     a.grab = shape.grab < 1 ? 1 : shape.grab;
     if (shape.nslots < 1 || bi.begin[bi.nsurf] < 1) return hipSuccess;
-    a.ttan = ttan;
-    const size_t dyn = sizeof(double) * 2 * (size_t)tcap;
-    if (fp32) launch_variant<true>(shape.lds_stack_kb, shape.nslots, dyn, a, s);
-    else launch_variant<false>(shape.lds_stack_kb, shape.nslots, dyn, a, s);
+    a.ttab = ttab;
+    if (fp32) launch_variant<true>(shape.lds_stack_kb, shape.nslots, a, s);
+    else launch_variant<false>(shape.lds_stack_kb, shape.nslots, a, s);
     return hipGetLastError();
 }
 
-int geodesic_all_blocks_per_cu(int lds_stack_kb, int tcap, bool fp32) {
+int geodesic_all_blocks_per_cu(int lds_stack_kb, bool fp32) {
     int nb = 0;
     const void *f = fp32 ? kernel_of<true>(lds_stack_kb) : kernel_of<false>(lds_stack_kb);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kWave, sizeof(double) * 2 * (size_t)tcap) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kWave, 0) != hipSuccess)
         return 0;
     return nb;
 }
