@@ -1497,7 +1497,7 @@ gsim_status gsim_tune_set(gsim_ctx *c, const char *name, double value) {
         else if (k == "dom_rel" && value >= 0.0) c->gp.dom_rel = value;
         else if (k == "dom_rel32" && value >= 0.0) c->gp.dom_rel32 = value;
         else if (k == "whole_mesh" && (value == 0.0 || value == 1.0)) c->whole_mesh = value != 0.0;
-    else if (k == "fuse_update" && (value == 0.0 || value == 1.0)) c->fuse_update = value != 0.0;
+        else if (k == "fuse_update" && (value == 0.0 || value == 1.0)) c->fuse_update = value != 0.0;
         else if (k == "time_geodesic_only" && (value == 0.0 || value == 1.0)) c->time_geodesic_only = value != 0.0;
         else return fail(c, GSIM_E_ARG, "unknown tuning knob or value out of range: " + k);
         drop_graphs(c);

@@ -232,35 +232,44 @@ __device__ inline void target_update(AllLds &L, double2 *td, double2 *tt, const 
 // is [x0, x*). Likewise h(x) = f(x) - (Lc - x) - DE is non-decreasing and
 // the part dominated by the path through E is (x**, x1]. The vertex path
 // lengths are widened by the factor 1 + rel first, so only parts dominated
-// beyond the rounding error of the working precision are cut.
+// beyond the rounding error of the working precision are cut. f0 and f1
+// return f at the final ends (each square root is taken once per end).
 __device__ inline bool vertex_trim(double px, double py, double sg, double Lc, double DS, double DE, double rel,
-                                   double &x0, double &x1) {
+                                   double &x0, double &x1, double &f0, double &f1) {
     // the vertex paths count as shorter only by more than `rel` of their length
     DS *= 1.0 + rel;
     DE *= 1.0 + rel;
     const double eps_x = 1e-9 * Lc;
     auto f = [&](double x) { return sg + sqrt((x - px) * (x - px) + py * py); };
+    f0 = f(x0);
+    f1 = f(x1);
     if (DS < INFINITY) {
-        if (f(x1) - x1 - DS > 0.0) return false;
-        if (f(x0) - x0 - DS > 0.0) {
+        if (f1 - x1 - DS > 0.0) return false;
+        if (f0 - x0 - DS > 0.0) {
             // g(x*) = 0: sqrt((x - px)^2 + py^2) = dl + x, dl = DS - sg
             const double dl = DS - sg;
             const double den = 2.0 * (px + dl);
             if (den > 0.0) {
                 const double xs = (px * px + py * py - dl * dl) / den;
-                if (xs - eps_x > x0) x0 = fmin(x1, xs - eps_x);
+                if (xs - eps_x > x0) {
+                    x0 = fmin(x1, xs - eps_x);
+                    f0 = f(x0);
+                }
             }
         }
     }
     if (DE < INFINITY) {
-        if (f(x0) - (Lc - x0) - DE > 0.0) return false;
-        if (f(x1) - (Lc - x1) - DE > 0.0) {
+        if (f0 - (Lc - x0) - DE > 0.0) return false;
+        if (f1 - (Lc - x1) - DE > 0.0) {
             // h(x**) = 0: sqrt((x - px)^2 + py^2) = mm - x, mm = DE + Lc - sg
             const double mm = DE + Lc - sg;
             const double den = 2.0 * (px - mm);
             if (den < 0.0) {
                 const double xs = (px * px + py * py - mm * mm) / den;
-                if (xs + eps_x < x1) x1 = fmax(x0, xs + eps_x);
+                if (xs + eps_x < x1) {
+                    x1 = fmax(x0, xs + eps_x);
+                    f1 = f(x1);
+                }
             }
         }
     }
@@ -272,16 +281,13 @@ __device__ inline bool vertex_trim(double px, double py, double sg, double Lc, d
 // the edge), i.e. DO + |O - X| < f(X)? The points of the edge line where that
 // holds are the line's intersection with one branch region of a hyperbola
 // with foci p and O, which is convex: domination at both ends means
-// domination everywhere in between.
-__device__ inline bool opposite_dominates(double px, double py, double sg, double ox, double oy, double DO, double rel,
-                                          double x0, double x1) {
+// domination everywhere in between. f0, f1: f at the two ends.
+__device__ inline bool opposite_dominates(double ox, double oy, double DO, double rel, double x0, double x1, double f0,
+                                          double f1) {
     if (!(DO < INFINITY)) return false;
     DO *= 1.0 + rel;
-    auto dom = [&](double x) {
-        const double f = sg + sqrt((x - px) * (x - px) + py * py);
-        return DO + sqrt((x - ox) * (x - ox) + oy * oy) < f;
-    };
-    return dom(x0) && dom(x1);
+    auto dom = [&](double x, double f) { return DO + sqrt((x - ox) * (x - ox) + oy * oy) < f; };
+    return dom(x0, f0) && dom(x1, f1);
 }
 
 // Targets in face g (entry half-edge slot k of g) seen through window w.
@@ -772,10 +778,11 @@ __device__ __attribute__((always_inline)) inline bool run_all(const AllArgs &a, 
                 make_left(H, w, x0, x1, cl);
                 // edge A -> C: S = A, E = C; the face's third vertex B sits at
                 // (ex L, -ey L) in the child frame
+                double f0, f1;
                 if (x1 - x0 > 1e-12 * (double)H.Lp &&
-                    vertex_trim(cl.px, cl.py, cl.sg, H.Lp, DA, DC, C.dom_rel, x0, x1) &&
-                    !opposite_dominates(cl.px, cl.py, cl.sg, (double)H.ex * (double)H.L,
-                                        -(double)H.ey * (double)H.L, DB, C.dom_rel, x0, x1)) {
+                    vertex_trim(cl.px, cl.py, cl.sg, H.Lp, DA, DC, C.dom_rel, x0, x1, f0, f1) &&
+                    !opposite_dominates((double)H.ex * (double)H.L, -(double)H.ey * (double)H.L, DB, C.dom_rel, x0,
+                                        x1, f0, f1)) {
                     cl.b0 = (R)x0;
                     cl.b1 = (R)x1;
                     kl = (double)cl.sg + (double)seg_dist(cl.px, cl.py, cl.b0, cl.b1);
@@ -790,10 +797,10 @@ __device__ __attribute__((always_inline)) inline bool run_all(const AllArgs &a, 
                 // edge C -> B: S = C, E = B; the third vertex A sits at
                 // (-ux cx - uy cy, uy cx - ux cy) in the child frame
                 const double ux = H.ux, uy = H.uy, hcx = H.cx, hcy = H.cy;
+                double f0, f1;
                 if (x1 - x0 > 1e-12 * (double)H.Ln &&
-                    vertex_trim(cr.px, cr.py, cr.sg, H.Ln, DC, DB, C.dom_rel, x0, x1) &&
-                    !opposite_dominates(cr.px, cr.py, cr.sg, -ux * hcx - uy * hcy, uy * hcx - ux * hcy, DA,
-                                        C.dom_rel, x0, x1)) {
+                    vertex_trim(cr.px, cr.py, cr.sg, H.Ln, DC, DB, C.dom_rel, x0, x1, f0, f1) &&
+                    !opposite_dominates(-ux * hcx - uy * hcy, uy * hcx - ux * hcy, DA, C.dom_rel, x0, x1, f0, f1)) {
                     cr.b0 = (R)x0;
                     cr.b1 = (R)x1;
                     kr = (double)cr.sg + (double)seg_dist(cr.px, cr.py, cr.b0, cr.b1);
