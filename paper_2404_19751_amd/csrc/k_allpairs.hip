@@ -281,13 +281,30 @@ __device__ inline bool vertex_trim(double px, double py, double sg, double Lc, d
 // the edge), i.e. DO + |O - X| < f(X)? The points of the edge line where that
 // holds are the line's intersection with one branch region of a hyperbola
 // with foci p and O, which is convex: domination at both ends means
-// domination everywhere in between. f0, f1: f at the two ends.
+// domination everywhere in between. f0, f1: f at the two ends. The test at
+// a point compares squares (f - DO > 0 and |O - X|^2 < (f - DO)^2): no
+// square root, and its rounding stays far inside the widening by rel.
 __device__ inline bool opposite_dominates(double ox, double oy, double DO, double rel, double x0, double x1, double f0,
                                           double f1) {
     if (!(DO < INFINITY)) return false;
     DO *= 1.0 + rel;
-    auto dom = [&](double x, double f) { return DO + sqrt((x - ox) * (x - ox) + oy * oy) < f; };
+    auto dom = [&](double x, double f) {
+        const double r = f - DO;
+        return r > 0.0 && (x - ox) * (x - ox) + oy * oy < r * r;
+    };
     return dom(x0, f0) && dom(x1, f1);
+}
+
+// Key (smallest distance) of a child window on [x0, x1] whose distance at
+// the ends is f0, f1. In FP64 the ends are the window's own, so the key
+// reuses them; FP32 windows take it from their rounded fields.
+template <typename R>
+__device__ inline double child_key(const Win<R> &c, double f0, double f1) {
+    if constexpr (sizeof(R) == 8) {
+        return c.px < c.b0 ? f0 : (c.px > c.b1 ? f1 : c.sg + fabs(c.py));
+    } else {
+        return (double)c.sg + (double)seg_dist(c.px, c.py, c.b0, c.b1);
+    }
 }
 
 // Targets in face g (entry half-edge slot k of g) seen through window w.
@@ -785,7 +802,7 @@ __device__ __attribute__((always_inline)) inline bool run_all(const AllArgs &a, 
                                         x1, f0, f1)) {
                     cl.b0 = (R)x0;
                     cl.b1 = (R)x1;
-                    kl = (double)cl.sg + (double)seg_dist(cl.px, cl.py, cl.b0, cl.b1);
+                    kl = child_key(cl, f0, f1);
                     hl = kl < maxb;
                 }
                 if (!hl) ++pruned;
@@ -803,7 +820,7 @@ __device__ __attribute__((always_inline)) inline bool run_all(const AllArgs &a, 
                     !opposite_dominates(-ux * hcx - uy * hcy, uy * hcx - ux * hcy, DA, C.dom_rel, x0, x1, f0, f1)) {
                     cr.b0 = (R)x0;
                     cr.b1 = (R)x1;
-                    kr = (double)cr.sg + (double)seg_dist(cr.px, cr.py, cr.b0, cr.b1);
+                    kr = child_key(cr, f0, f1);
                     hr = kr < maxb;
                 }
                 if (!hr) ++pruned;
