@@ -253,7 +253,8 @@ gsim_status gsim_step_batched(gsim_ctx *ctx, int32_t nmesh, const int32_t *mesh_
  *                   microseconds)
  *   "whole_mesh"    1: finite-cutoff passes also run on the whole-mesh kernel
  *                   below (windows pruned at the cutoff; no limit on candidates or
- *                   bend vertices per source)
+ *                   bend vertices per source; at most 46,340 particles per
+ *                   surface, whose n x n pair rows take 37 bytes each)
  *   Whole-mesh passes (no cutoff, or "whole_mesh" = 1):
  *   "stack_cap_all" window records per resident wavefront (1024 .. 4M)
  *   "max_windows_all" per-source work limit

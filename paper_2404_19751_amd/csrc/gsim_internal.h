@@ -192,9 +192,9 @@ struct SurfDesc {
 // Capacity of a candidate row: the most Euclidean candidates one source may
 // have (its targets live in an LDS table of the geodesic kernel).
 constexpr int kCandCap = 128;
-// Most particles on one surface in all-pairs mode (the target table of a
-// source, 32 bytes per target, lives in LDS).
-constexpr int kAllPairsMax = 4096;
+// Most particles on one surface in all-pairs mode: the n x n pair slots of
+// the row arrays (37 bytes each) stay within 32-bit indices.
+constexpr int kAllPairsMax = 46340;
 
 // FIRE state of one surface (device memory): time step, mixing factor,
 // consecutive iterations with positive power, and the mixing coefficients

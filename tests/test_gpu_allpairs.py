@@ -227,3 +227,39 @@ def test_fire_state_carries_over(orc):
 
 
 SMALL_MESHES = [("icosphere3", lambda: W.icosphere(3)), ("torus", lambda: W.torus(1.0, 0.3, 30, 12))]
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_allpairs_5000_particles(orc, prec):
+    """More particles than a target table in LDS could hold (the table lives
+    in global memory): 5000 particles on the level-4 icosphere, 24,995,000
+    pairs in one launch; sampled rows, including sources and targets with
+    indices beyond 4096, against the oracle."""
+    m = W.icosphere(4)
+    f, b = W.random_particles(m.nf, 5000, 11)
+    ctx = _ctx(prec)
+    try:
+        mid = ctx.mesh_upload(m.V, m.T)
+        ctx.particles_set(mid, f, b)
+        log(f"[gpu-all] icosphere4 n=5000 {prec}: all pairs")
+        g = ctx.geodesic_pairs(mid, math.inf)
+        cnt = ctx.counters()
+        log(f"[gpu-all] icosphere4 n=5000 {prec}: {len(g['dist'])} pairs, counters {cnt}")
+        assert cnt["limited"] == 0
+        assert len(g["dist"]) == 5000 * 4999
+        srcs = np.array([0, 4100, 4999], np.int32)
+        o = orc.geodesic_pairs(orc.OracleMesh(m.V, m.T), f, b, math.inf, sources=srcs)
+        sub = {"off": [0], "nbr": [], "dist": [], "tan": [], "flags": []}
+        for i in srcs:
+            a, bb = g["off"][i], g["off"][i + 1]
+            for key in ("nbr", "dist", "tan", "flags"):
+                sub[key].append(g[key][a:bb])
+            sub["off"].append(sub["off"][-1] + bb - a)
+        gs = {k: (np.concatenate(v) if k != "off" else np.array(v, np.int64)) for k, v in sub.items()}
+        if prec == "fp64":
+            err = compare_pairs(gs, o, W.mean_edge_length(m), label="icosphere4 n=5000")
+        else:
+            err, _ = compare32(gs, o, W.mean_edge_length(m), "icosphere4 n=5000")
+        log(f"[gpu-all] icosphere4 n=5000 {prec}: sampled rows err {err:.2e}")
+    finally:
+        ctx.close()
