@@ -258,7 +258,8 @@ gsim_status gsim_step_batched(gsim_ctx *ctx, int32_t nmesh, const int32_t *mesh_
  *   Whole-mesh passes (no cutoff, or "whole_mesh" = 1):
  *   "stack_cap_all" window records per resident wavefront (1024 .. 4M)
  *   "max_windows_all" per-source work limit
- *   "bucket"        key width of one processing round (0 = 16 max edge lengths)
+ *   "bucket"        key width of one processing round (0 = 16 max edge lengths,
+ *                   4 on a surface with saddle or boundary vertices)
  *   "dom_rel", "dom_rel32"  margins of the vertex-path domination tests */
 gsim_status gsim_tune_set(gsim_ctx *ctx, const char *name, double value);
 

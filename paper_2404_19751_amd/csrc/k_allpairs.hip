@@ -516,7 +516,9 @@ __device__ __attribute__((always_inline)) inline bool run_all(const AllArgs &a, 
     C.root_keep = fp32 ? 1.0 - a.gp.root_rel32 : 1.0;
     C.rc = {C.root_keep, C.tie_dir, C.tie_rel};
     C.dom_rel = fp32 ? a.gp.dom_rel32 : a.gp.dom_rel;
-    C.bucket = a.gp.bucket > 0.0 ? a.gp.bucket : 16.0 * M.max_edge;
+    // rounds: wide ones mean fewer round changes, but on a surface with bend
+    // vertices they launch vertices before their distances settle
+    C.bucket = a.gp.bucket > 0.0 ? a.gp.bucket : (M.n_pseudo > 0 ? 4.0 : 16.0) * M.max_edge;
     C.cutoff = sd.cutoff;
     double *Dv = a.vdist + (int64_t)slot * a.vstride;
     const BendTable G = bend_table(a.roots, a.rstride, slot, a.rcap);
