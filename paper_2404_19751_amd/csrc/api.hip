@@ -835,6 +835,10 @@ gsim_status gsim_create(int device, gsim_precision prec, void *hip_stream, gsim_
     if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, device) == hipSuccess &&
         lds > 0)
         c->lds_cu = lds;
+    // whole-mesh window stacks: at most a quarter of the device's memory
+    size_t mem_free = 0, mem_total = 0;
+    if (hipMemGetInfo(&mem_free, &mem_total) == hipSuccess && mem_total > 0)
+        c->stack_budget = std::min(c->stack_budget, 0.25 * (double)mem_total);
     c->gp.cutoff = 0.0;
     c->gp.launch_delta = 1e300;  // one bucket: every improved bend vertex once the stack drains
     c->gp.cone_tol = 1e-12;
