@@ -50,7 +50,7 @@ def lib():
         L.orc_mesh_build.restype = C.c_int
         L.orc_mesh_free.argtypes = [P]
         L.orc_mesh_export.argtypes = [P, P, P, P, P]
-        L.orc_geodesic_pairs.argtypes = [P, C.c_int, P, P, C.c_double, C.c_int, P, C.c_int]
+        L.orc_geodesic_pairs.argtypes = [P, C.c_int, P, P, C.c_double, C.c_int, P, C.c_int, C.c_double]
         L.orc_geodesic_pairs.restype = P
         L.orc_pairs_count.argtypes = [P]
         L.orc_pairs_count.restype = C.c_int64
@@ -110,26 +110,32 @@ class OracleMesh:
 
 
 class Pairs:
-    def __init__(self, off, nbr, dist, tan, flags, tie_off, tie_tan, counters):
+    def __init__(self, off, nbr, dist, tan, flags, tie_off, tie_tan, counters, tie_rel):
         self.off, self.nbr, self.dist, self.tan, self.flags = off, nbr, dist, tan, flags
-        self.tie_off, self.tie_tan, self.counters = tie_off, tie_tan, counters
+        self.tie_off, self.tie_tan, self.counters, self.tie_rel = tie_off, tie_tan, counters, tie_rel
 
     def ties(self, p):
         return self.tie_tan[self.tie_off[p]:self.tie_off[p + 1]]
 
 
-def geodesic_pairs(mesh: OracleMesh, face, bary, cutoff, sources=None, nthreads=0) -> Pairs:
+def geodesic_pairs(mesh: OracleMesh, face, bary, cutoff, sources=None, nthreads=0, tie_rel=1e-9) -> Pairs:
     """Exact geodesic distances d_ij < cutoff and initial unit tangents t_ij
     (3D, in the plane of the source's face) for every source i (Sec. 3.1:
     lengths l_ij and tangents relative to the source; submeshing by the
-    Euclidean lower bound). ``cutoff = inf`` asks for all pairs."""
+    Euclidean lower bound). ``cutoff = inf`` asks for all pairs.
+
+    Where several shortest paths leave the source in different directions
+    (the cut locus), the tangent is not unique: ``ties(p)`` lists the
+    initial direction of every path within ``tie_rel * d`` of the shortest
+    (1e-9 by default; the FP32-mixed comparisons use 1e-5, their distance
+    tolerance), and such a pair is flagged (bit 0)."""
     face = np.ascontiguousarray(face, np.int32)
     bary = np.ascontiguousarray(bary, np.float64)
     src = None if sources is None else np.ascontiguousarray(sources, np.int32)
     nsrc = face.shape[0] if src is None else src.shape[0]
     L = lib()
     h = L.orc_geodesic_pairs(mesh._h, face.shape[0], _p(face), _p(bary), float(cutoff if math.isfinite(cutoff) else -1.0),
-                             nsrc, None if src is None else _p(src), int(nthreads))
+                             nsrc, None if src is None else _p(src), int(nthreads), float(tie_rel))
     if not h:
         raise ValueError("oracle rejected the particle state")
     try:
@@ -149,7 +155,7 @@ def geodesic_pairs(mesh: OracleMesh, face, bary, cutoff, sources=None, nthreads=
         L.orc_pairs_free(h)
     return Pairs(off, nbr, dist, tan, flags, tie_off, tie_tan,
                  dict(windows=int(cnt[0]), pruned=int(cnt[1]), roots=int(cnt[2]), improvements=int(cnt[3]),
-                      rejected=int(cnt[4])))
+                      rejected=int(cnt[4])), float(tie_rel))
 
 
 def walk(mesh: OracleMesh, face, bary, disp, vel=None):

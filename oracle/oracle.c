@@ -24,9 +24,8 @@
 
 #define TWO_PI 6.283185307179586476925286766559
 #define PSEUDO_TOL 1e-9   /* angle sum >= 2 pi - tol counts as saddle (safe superset) */
-#define TIE_REL 1e-9      /* candidates within this relative gap form the tie set */
+#define TIE_REL 1e-9      /* default: candidates within this relative gap form the tie set */
 #define DIR_DUP 1e-6      /* tangents closer than this angle are one direction */
-#define MAXT 6            /* tie-set capacity per target / per bend vertex */
 #define SEG_MIN_REL 1e-12 /* cone slices shorter than this (x edge length) are dropped */
 #define CONE_EPS 1e-12    /* closed-cone slack for membership tests */
 #define MAX_DEPTH 200000
@@ -210,7 +209,9 @@ void orc_mesh_export(const orc_mesh *m, int *twin, double *theta, unsigned char 
  * unfolding and bend only at saddle or boundary vertices).
  * ====================================================================== */
 typedef struct { double d, t[2]; } tang_t;
-typedef struct { double best; int nt; tang_t e[MAXT]; } cand_t;
+/* best distance and the tie set: every direction within the band of it
+ * (a growable array, so no direction is ever dropped) */
+typedef struct { double best; int nt, cap; tang_t *e; } cand_t;
 
 typedef struct {
     int h;             /* entry half-edge (X -> Y) of face h/3 */
@@ -242,19 +243,22 @@ typedef struct {
     double *hk; int *hv; int hn, hcap;
     owin *stk; int scap;
     int64_t cnt[5];
+    double band;       /* tie band: directions within band * d of the best are kept */
+    cand_t root;       /* copy of the tie set of the vertex being expanded */
 } work_t;
 
 static void cand_reset(cand_t *c) { c->best = INFINITY; c->nt = 0; }
 
-/* Add candidate distance d with tangent t (2D, source-face frame). */
-static void cand_add(cand_t *c, double d, const double *t) {
-    double tol = TIE_REL * (d < c->best ? d : c->best);
+/* Add candidate distance d with tangent t (2D, source-face frame); the set
+ * keeps every direction whose distance is within rel * d of the best. */
+static void cand_add(cand_t *c, double d, const double *t, double rel) {
+    double tol = rel * (d < c->best ? d : c->best);
     if (d > c->best + tol) return;
     if (d < c->best) {
         c->best = d;
         int k = 0;
         for (int i = 0; i < c->nt; i++)
-            if (c->e[i].d <= d + TIE_REL * d) c->e[k++] = c->e[i];
+            if (c->e[i].d <= d + rel * d) c->e[k++] = c->e[i];
         c->nt = k;
     }
     for (int i = 0; i < c->nt; i++) {
@@ -265,10 +269,12 @@ static void cand_add(cand_t *c, double d, const double *t) {
             return;
         }
     }
-    if (c->nt < MAXT) {
-        c->e[c->nt].d = d; c->e[c->nt].t[0] = t[0]; c->e[c->nt].t[1] = t[1];
-        c->nt++;
+    if (c->nt == c->cap) {
+        c->cap = c->cap ? 2 * c->cap : 4;
+        c->e = (tang_t *)realloc(c->e, sizeof(tang_t) * c->cap);
     }
+    c->e[c->nt].d = d; c->e[c->nt].t[0] = t[0]; c->e[c->nt].t[1] = t[1];
+    c->nt++;
 }
 
 static void heap_push(work_t *w, double k, int v) {
@@ -361,9 +367,9 @@ static void add_target(ctx_t *c, work_t *w, int j, double d, const double *q, co
     if (!root) {
         double l = len2(q), t[2] = {0.0, 0.0};
         if (l > 0.0) { t[0] = q[0] / l; t[1] = q[1] / l; }
-        cand_add(&w->tc[j], d, t);
+        cand_add(&w->tc[j], d, t, w->band);
     } else {
-        for (int i = 0; i < root->nt; i++) cand_add(&w->tc[j], d, root->e[i].t);
+        for (int i = 0; i < root->nt; i++) cand_add(&w->tc[j], d, root->e[i].t, w->band);
     }
 }
 
@@ -374,9 +380,9 @@ static void add_root(ctx_t *c, work_t *w, int v, double d, const double *q, cons
     if (!root) {
         double l = len2(q), t[2] = {0.0, 0.0};
         if (l > 0.0) { t[0] = q[0] / l; t[1] = q[1] / l; }
-        cand_add(&w->rc[v], d, t);
+        cand_add(&w->rc[v], d, t, w->band);
     } else {
-        for (int i = 0; i < root->nt; i++) cand_add(&w->rc[v], d, root->e[i].t);
+        for (int i = 0; i < root->nt; i++) cand_add(&w->rc[v], d, root->e[i].t, w->band);
     }
     if (w->rc[v].best < before) {
         w->cnt[3]++;
@@ -542,8 +548,9 @@ static int cmp_int(const void *a, const void *b) {
 typedef struct { int n; int32_t *nbr; double *dist, *tan; uint8_t *flags; int *nt; double *tt; } row_t;
 
 orc_pairs *orc_geodesic_pairs(const orc_mesh *m, int n, const int *face, const double *bary, double cutoff,
-                              int nsrc, const int *src, int nthreads) {
+                              int nsrc, const int *src, int nthreads, double tie_rel) {
     if (!m || n < 0 || (n > 0 && (!face || !bary))) return NULL;
+    if (!(tie_rel > 0.0)) tie_rel = TIE_REL;
     for (int j = 0; j < n; j++)
         if (face[j] < 0 || face[j] >= m->nf) return NULL;
     int all = !(cutoff > 0.0) || !isfinite(cutoff);
@@ -570,10 +577,11 @@ orc_pairs *orc_geodesic_pairs(const orc_mesh *m, int n, const int *face, const d
     {
         work_t w;
         memset(&w, 0, sizeof w);
-        w.tc = (cand_t *)malloc(sizeof(cand_t) * (n > 0 ? n : 1));
+        w.band = tie_rel;
+        w.tc = (cand_t *)calloc(n > 0 ? n : 1, sizeof(cand_t));
         w.t_touched = (int *)malloc(sizeof(int) * (n > 0 ? n : 1));
         w.t_mark = (unsigned char *)calloc(n > 0 ? n : 1, 1);
-        w.rc = (cand_t *)malloc(sizeof(cand_t) * m->nv);
+        w.rc = (cand_t *)calloc(m->nv, sizeof(cand_t));
         w.r_touched = (int *)malloc(sizeof(int) * m->nv);
         w.r_mark = (unsigned char *)calloc(m->nv, 1);
         w.r_done = (unsigned char *)calloc(m->nv, 1);
@@ -594,8 +602,16 @@ orc_pairs *orc_geodesic_pairs(const orc_mesh *m, int n, const int *face, const d
                     if (!(k < c.U)) break;
                     w.r_done[v] = 1;
                     w.cnt[2]++;
-                    cand_t root = w.rc[v];
-                    expand_vertex(&c, &w, v, root.best, &root);
+                    /* the vertex's own set may grow while it is expanded: expand a copy */
+                    const cand_t *rv = &w.rc[v];
+                    if (w.root.cap < rv->nt) {
+                        w.root.cap = rv->nt;
+                        w.root.e = (tang_t *)realloc(w.root.e, sizeof(tang_t) * w.root.cap);
+                    }
+                    w.root.best = rv->best;
+                    w.root.nt = rv->nt;
+                    memcpy(w.root.e, rv->e, sizeof(tang_t) * rv->nt);
+                    expand_vertex(&c, &w, v, w.root.best, &w.root);
                 }
             }
             /* collect */
@@ -641,6 +657,9 @@ orc_pairs *orc_geodesic_pairs(const orc_mesh *m, int n, const int *face, const d
         {
             for (int z = 0; z < 5; z++) res->counters[z] += w.cnt[z];
         }
+        for (int j = 0; j < n; j++) free(w.tc[j].e);
+        for (int v = 0; v < m->nv; v++) free(w.rc[v].e);
+        free(w.root.e);
         free(w.tc); free(w.t_touched); free(w.t_mark); free(w.rc); free(w.r_touched); free(w.r_mark);
         free(w.r_done); free(w.hk); free(w.hv); free(w.stk); free(gdist);
     }
@@ -891,7 +910,9 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
  * ---------------------------------------------------------------------- */
 
 /* squared distance from p to the triangle (a, b, c): the closest point is a
- * vertex, a point of an edge, or the projection into the interior */
+ * vertex, a point of an edge, or the projection into the interior, chosen by
+ * the Voronoi regions of the triangle's features (the closest-point method
+ * of C. Ericson, Real-Time Collision Detection, 2005, Sec. 5.1.5) */
 static double point_tri_dist2(const double *p, const double *a, const double *b, const double *c) {
     double ab[3], ac[3], ap[3], q[3];
     sub3(b, a, ab);

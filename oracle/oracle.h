@@ -46,9 +46,12 @@ void orc_mesh_export(const orc_mesh *m, int *twin, double *theta, unsigned char 
 /* Geodesic neighbour pairs (i -> j, j != i, d_ij < cutoff) for the sources
  * listed in `src` (all particles if src == NULL). cutoff <= 0 or infinite
  * means "all pairs" (only sensible on small meshes). nthreads <= 0: OpenMP
- * default. Returns NULL on bad input. */
+ * default. tie_rel: every initial direction of a path within tie_rel * d of
+ * the shortest is kept in the pair's tie set (<= 0: 1e-9); a pair whose set
+ * has more than one direction is flagged as a tie. Returns NULL on bad
+ * input. */
 orc_pairs *orc_geodesic_pairs(const orc_mesh *m, int n, const int *face, const double *bary, double cutoff,
-                              int nsrc, const int *src, int nthreads);
+                              int nsrc, const int *src, int nthreads, double tie_rel);
 int64_t orc_pairs_count(const orc_pairs *p);
 int64_t orc_pairs_tie_count(const orc_pairs *p);
 /* off[nsrc+1], nbr[P], dist[P], tan[P][3], flags[P], tie_off[P+1], tie_tan[T][3] */

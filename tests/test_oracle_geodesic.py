@@ -171,6 +171,51 @@ def test_prism_wraparound_and_ties(orc):
     assert pr.flags[p] & 1 and pr.tie_off[p + 1] - pr.tie_off[p] == 2
 
 
+def test_prism_tie_band(orc):
+    """Two routes round a prism that differ by a relative gap g between 1e-9
+    and 1e-4: a tie set of band tie_rel holds both initial directions when
+    tie_rel >= g and only the shorter one when tie_rel < g; each direction is
+    the developed closed form (the tie sets of the FP32-mixed comparisons)."""
+    n, R = 6, 1.0
+    m = W.prism(n, R, 1.0, nz=3)
+    om = orc.OracleMesh(m.V, m.T)
+    side = 2 * R * math.sin(math.pi / n)
+    C = n * side
+    a = np.array([R, 0.0])
+    c = np.array([R * math.cos(2 * math.pi / n), R * math.sin(2 * math.pi / n)])
+    s0, z0, z1 = 0.4, 0.2, 0.55
+    delta = 1e-5 * C
+    s1 = s0 + C / 2 - delta  # the +s route is shorter by about 2 delta (C/2) / L
+
+    def pt(s, z):
+        k = int(s // side) % n
+        t = (s - (s // side) * side) / side
+        A = np.array([R * math.cos(2 * math.pi * k / n), R * math.sin(2 * math.pi * k / n)])
+        B = np.array([R * math.cos(2 * math.pi * (k + 1) / n), R * math.sin(2 * math.pi * (k + 1) / n)])
+        q = (1 - t) * A + t * B
+        return (q[0], q[1], z)
+
+    f, b = place(m, [pt(s0, z0), pt(s1, z1)])
+    L1 = math.hypot(C / 2 - delta, z1 - z0)
+    L2 = math.hypot(C / 2 + delta, z1 - z0)
+    gap = (L2 - L1) / L1
+    assert 1e-9 < gap < 1e-4
+    es = np.array([c[0] - a[0], c[1] - a[1], 0.0]) / side  # +s along the source's side face
+    ez = np.array([0.0, 0.0, 1.0])
+    t1 = ((C / 2 - delta) * es + (z1 - z0) * ez) / L1
+    t2 = (-(C / 2 + delta) * es + (z1 - z0) * ez) / L2
+    for band, want in ((1e-9, [t1]), (0.5 * gap, [t1]), (2.0 * gap, [t1, t2]), (1e-4, [t1, t2])):
+        pr = orc.geodesic_pairs(om, f, b, math.inf, tie_rel=band)
+        p = pair_dict(pr, 0)[1]
+        assert abs(pr.dist[p] - L1) < 1e-12
+        assert np.linalg.norm(pr.tan[p] - t1) < 1e-12
+        ts = pr.ties(p)
+        assert len(ts) == len(want), (band, ts)
+        assert bool(pr.flags[p] & 1) == (len(want) > 1)
+        for t in want:
+            assert min(np.linalg.norm(ts - t, axis=1)) < 1e-12
+
+
 # ------------------------------------------------------------------ CF5 ----
 def _cone_point(m, theta, n, r, phi):
     a = theta / n
