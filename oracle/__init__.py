@@ -50,13 +50,14 @@ def lib():
         L.orc_mesh_build.restype = C.c_int
         L.orc_mesh_free.argtypes = [P]
         L.orc_mesh_export.argtypes = [P, P, P, P, P]
-        L.orc_geodesic_pairs.argtypes = [P, C.c_int, P, P, C.c_double, C.c_int, P, C.c_int, C.c_double]
+        L.orc_geodesic_pairs.argtypes = [P, C.c_int, P, P, C.c_double, C.c_int, P, C.c_int, C.c_double,
+                                         C.c_double]
         L.orc_geodesic_pairs.restype = P
         L.orc_pairs_count.argtypes = [P]
         L.orc_pairs_count.restype = C.c_int64
         L.orc_pairs_tie_count.argtypes = [P]
         L.orc_pairs_tie_count.restype = C.c_int64
-        L.orc_pairs_export.argtypes = [P] * 8
+        L.orc_pairs_export.argtypes = [P] * 9
         L.orc_pairs_counters.argtypes = [P, P]
         L.orc_pairs_free.argtypes = [P]
         L.orc_walk.argtypes = [P, C.c_int, P, P, P, P, P, P]
@@ -110,15 +111,22 @@ class OracleMesh:
 
 
 class Pairs:
-    def __init__(self, off, nbr, dist, tan, flags, tie_off, tie_tan, counters, tie_rel):
+    def __init__(self, off, nbr, dist, tan, flags, tie_off, tie_tan, tie_dist, counters, tie_rel, cone_slack):
         self.off, self.nbr, self.dist, self.tan, self.flags = off, nbr, dist, tan, flags
-        self.tie_off, self.tie_tan, self.counters, self.tie_rel = tie_off, tie_tan, counters, tie_rel
+        self.tie_off, self.tie_tan, self.tie_dist = tie_off, tie_tan, tie_dist
+        self.counters, self.tie_rel, self.cone_slack = counters, tie_rel, cone_slack
 
     def ties(self, p):
+        """Initial directions of the pair's tie set."""
         return self.tie_tan[self.tie_off[p]:self.tie_off[p + 1]]
 
+    def tie_lengths(self, p):
+        """Length of the shortest path found in each direction of ties(p)."""
+        return self.tie_dist[self.tie_off[p]:self.tie_off[p + 1]]
 
-def geodesic_pairs(mesh: OracleMesh, face, bary, cutoff, sources=None, nthreads=0, tie_rel=1e-9) -> Pairs:
+
+def geodesic_pairs(mesh: OracleMesh, face, bary, cutoff, sources=None, nthreads=0, tie_rel=1e-9,
+                   cone_slack=0.0) -> Pairs:
     """Exact geodesic distances d_ij < cutoff and initial unit tangents t_ij
     (3D, in the plane of the source's face) for every source i (Sec. 3.1:
     lengths l_ij and tangents relative to the source; submeshing by the
@@ -128,14 +136,23 @@ def geodesic_pairs(mesh: OracleMesh, face, bary, cutoff, sources=None, nthreads=
     (the cut locus), the tangent is not unique: ``ties(p)`` lists the
     initial direction of every path within ``tie_rel * d`` of the shortest
     (1e-9 by default; the FP32-mixed comparisons use 1e-5, their distance
-    tolerance), and such a pair is flagged (bit 0)."""
+    tolerance), and such a pair is flagged (bit 0).
+
+    ``cone_slack`` (the sine of an angle; 0 means exact cones up to 1e-12)
+    widens the test of whether a target lies in a straight link's cone, so
+    that the tie set also holds the directions of straight links to points
+    within that angle of the target: the resolution of a computation in
+    reduced precision, whose cone tests are perturbed by its rounding. The
+    reported distance then may fall short of the exact one by a term of
+    second order in that angle."""
     face = np.ascontiguousarray(face, np.int32)
     bary = np.ascontiguousarray(bary, np.float64)
     src = None if sources is None else np.ascontiguousarray(sources, np.int32)
     nsrc = face.shape[0] if src is None else src.shape[0]
     L = lib()
     h = L.orc_geodesic_pairs(mesh._h, face.shape[0], _p(face), _p(bary), float(cutoff if math.isfinite(cutoff) else -1.0),
-                             nsrc, None if src is None else _p(src), int(nthreads), float(tie_rel))
+                             nsrc, None if src is None else _p(src), int(nthreads), float(tie_rel),
+                             float(cone_slack))
     if not h:
         raise ValueError("oracle rejected the particle state")
     try:
@@ -148,14 +165,15 @@ def geodesic_pairs(mesh: OracleMesh, face, bary, cutoff, sources=None, nthreads=
         flags = np.empty(P, np.uint8)
         tie_off = np.empty(P + 1, np.int64)
         tie_tan = np.empty((Tn, 3), np.float64)
-        L.orc_pairs_export(h, _p(off), _p(nbr), _p(dist), _p(tan), _p(flags), _p(tie_off), _p(tie_tan))
+        tie_dist = np.empty(Tn, np.float64)
+        L.orc_pairs_export(h, _p(off), _p(nbr), _p(dist), _p(tan), _p(flags), _p(tie_off), _p(tie_tan), _p(tie_dist))
         cnt = np.empty(5, np.int64)
         L.orc_pairs_counters(h, _p(cnt))
     finally:
         L.orc_pairs_free(h)
-    return Pairs(off, nbr, dist, tan, flags, tie_off, tie_tan,
+    return Pairs(off, nbr, dist, tan, flags, tie_off, tie_tan, tie_dist,
                  dict(windows=int(cnt[0]), pruned=int(cnt[1]), roots=int(cnt[2]), improvements=int(cnt[3]),
-                      rejected=int(cnt[4])), float(tie_rel))
+                      rejected=int(cnt[4])), float(tie_rel), float(cone_slack))
 
 
 def walk(mesh: OracleMesh, face, bary, disp, vel=None):

@@ -25,7 +25,8 @@
 #define TWO_PI 6.283185307179586476925286766559
 #define PSEUDO_TOL 1e-9   /* angle sum >= 2 pi - tol counts as saddle (safe superset) */
 #define TIE_REL 1e-9      /* default: candidates within this relative gap form the tie set */
-#define DIR_DUP 1e-6      /* tangents closer than this angle are one direction */
+#define DIR_DUP 1e-11     /* tangents closer than this angle are one direction: the same straight
+                             link reached by two enumeration routes, which agree to rounding */
 #define SEG_MIN_REL 1e-12 /* cone slices shorter than this (x edge length) are dropped */
 #define CONE_EPS 1e-12    /* closed-cone slack for membership tests */
 #define MAX_DEPTH 200000
@@ -227,7 +228,7 @@ struct orc_pairs {
     double *dist, *tan;
     uint8_t *flags;
     int64_t *tie_off;
-    double *tie_tan;
+    double *tie_tan, *tie_dist;
     int64_t count, tcount;
     int64_t counters[5];
 };
@@ -265,7 +266,8 @@ static void cand_add(cand_t *c, double d, const double *t, double rel) {
         double cr = c->e[i].t[0] * t[1] - c->e[i].t[1] * t[0];
         double dt = c->e[i].t[0] * t[0] + c->e[i].t[1] * t[1];
         if (fabs(atan2(cr, dt)) < DIR_DUP) {
-            if (d < c->e[i].d) c->e[i].d = d;
+            /* one direction: it keeps the shorter path's length and tangent */
+            if (d < c->e[i].d) { c->e[i].d = d; c->e[i].t[0] = t[0]; c->e[i].t[1] = t[1]; }
             return;
         }
     }
@@ -345,10 +347,11 @@ static double point_seg_dist0(const double *A, const double *B) {
     return len2(p);
 }
 
-/* q inside the closed cone spanned CCW from direction r to direction l */
-static int in_cone(const double *r, const double *l, const double *q) {
+/* q inside the closed cone spanned CCW from direction r to direction l,
+ * widened on both sides by the angle whose sine is eps */
+static int in_cone(const double *r, const double *l, const double *q, double eps) {
     double nq = len2(q);
-    return cross2(r, q) >= -CONE_EPS * len2(r) * nq && cross2(q, l) >= -CONE_EPS * len2(l) * nq;
+    return cross2(r, q) >= -eps * len2(r) * nq && cross2(q, l) >= -eps * len2(l) * nq;
 }
 
 typedef struct {
@@ -357,6 +360,7 @@ typedef struct {
     const int *fp_off, *fp;  /* particles per face */
     int src;
     double U;                /* prune bound */
+    double cone;             /* angular slack (sine) of the target membership test */
 } ctx_t;
 
 /* record candidate for target j (via root with distance D, tangent set ts or,
@@ -398,7 +402,7 @@ static void targets_in_face(ctx_t *c, work_t *w, int g, int slot_x, const double
         const double *b = c->bary + 3 * j;
         double bx = b[slot_x], by = b[(slot_x + 1) % 3], bz = b[(slot_x + 2) % 3];
         double q[2] = {bx * X[0] + by * Y[0] + bz * Z[0], bx * X[1] + by * Y[1] + bz * Z[1]};
-        if (cr && !in_cone(cr, cl, q)) continue;
+        if (cr && !in_cone(cr, cl, q, c->cone)) continue;
         add_target(c, w, j, D + len2(q), q, root);
     }
 }
@@ -418,7 +422,7 @@ static void drain(ctx_t *c, work_t *w, int *sn, double D, const cand_t *root) {
         const double *r = x.B, *l = x.A;
         targets_in_face(c, w, g, k, x.X, x.Y, Z, D, root, r, l);
         int vz = m->T[he_prev(h)];
-        if (in_cone(r, l, Z)) add_root(c, w, vz, D + len2(Z), Z, root);
+        if (in_cone(r, l, Z, CONE_EPS)) add_root(c, w, vz, D + len2(Z), Z, root);
         /* child across Y->Z: entry tail Z, head Y */
         int t1 = m->twin[he_next(h)];
         if (t1 >= 0) {
@@ -545,12 +549,13 @@ static int cmp_int(const void *a, const void *b) {
     return (x > y) - (x < y);
 }
 
-typedef struct { int n; int32_t *nbr; double *dist, *tan; uint8_t *flags; int *nt; double *tt; } row_t;
+typedef struct { int n; int32_t *nbr; double *dist, *tan; uint8_t *flags; int *nt; double *tt, *td; } row_t;
 
 orc_pairs *orc_geodesic_pairs(const orc_mesh *m, int n, const int *face, const double *bary, double cutoff,
-                              int nsrc, const int *src, int nthreads, double tie_rel) {
+                              int nsrc, const int *src, int nthreads, double tie_rel, double cone_slack) {
     if (!m || n < 0 || (n > 0 && (!face || !bary))) return NULL;
     if (!(tie_rel > 0.0)) tie_rel = TIE_REL;
+    if (!(cone_slack > CONE_EPS)) cone_slack = CONE_EPS;
     for (int j = 0; j < n; j++)
         if (face[j] < 0 || face[j] >= m->nf) return NULL;
     int all = !(cutoff > 0.0) || !isfinite(cutoff);
@@ -592,6 +597,7 @@ orc_pairs *orc_geodesic_pairs(const orc_mesh *m, int n, const int *face, const d
             ctx_t c;
             c.m = m; c.face = face; c.bary = bary; c.fp_off = fp_off; c.fp = fp; c.src = i;
             c.U = all ? graph_bound(m, face[i], bary + 3 * i, gdist, &w) : cutoff;
+            c.cone = cone_slack;
             w.hn = 0; w.nt_touched = 0; w.nr_touched = 0;
             if (expand_source(&c, &w) != 0) {
                 w.cnt[4]++;
@@ -629,6 +635,7 @@ orc_pairs *orc_geodesic_pairs(const orc_mesh *m, int n, const int *face, const d
             rw->flags = (uint8_t *)malloc(cnt + 1);
             rw->nt = (int *)malloc(sizeof(int) * (cnt + 1));
             rw->tt = (double *)malloc(sizeof(double) * 3 * (tcnt + 1));
+            rw->td = (double *)malloc(sizeof(double) * (tcnt + 1));
             const double *ex = m->ex + 3 * face[i], *ey = m->ey + 3 * face[i];
             int q = 0, tq = 0;
             for (int a = 0; a < w.nt_touched; a++) {
@@ -646,8 +653,10 @@ orc_pairs *orc_geodesic_pairs(const orc_mesh *m, int n, const int *face, const d
                 if (cj->best == 0.0) fl |= 2;
                 rw->flags[q] = fl;
                 rw->nt[q] = cj->nt;
-                for (int e = 0; e < cj->nt; e++, tq++)
+                for (int e = 0; e < cj->nt; e++, tq++) {
                     for (int d = 0; d < 3; d++) rw->tt[3 * tq + d] = cj->e[e].t[0] * ex[d] + cj->e[e].t[1] * ey[d];
+                    rw->td[tq] = cj->e[e].d;
+                }
                 q++;
             }
             for (int a = 0; a < w.nt_touched; a++) w.t_mark[w.t_touched[a]] = 0;
@@ -679,6 +688,7 @@ orc_pairs *orc_geodesic_pairs(const orc_mesh *m, int n, const int *face, const d
     res->flags = (uint8_t *)malloc(tot + 1);
     res->tie_off = (int64_t *)malloc(sizeof(int64_t) * (tot + 1));
     res->tie_tan = (double *)malloc(sizeof(double) * 3 * (ttot + 1));
+    res->tie_dist = (double *)malloc(sizeof(double) * (ttot + 1));
     int64_t p = 0, tp = 0;
     res->tie_off[0] = 0;
     for (int s = 0; s < nsrc; s++) {
@@ -688,10 +698,13 @@ orc_pairs *orc_geodesic_pairs(const orc_mesh *m, int n, const int *face, const d
             res->nbr[p] = rw->nbr[q]; res->dist[p] = rw->dist[q];
             memcpy(res->tan + 3 * p, rw->tan + 3 * q, sizeof(double) * 3);
             res->flags[p] = rw->flags[q];
-            for (int e = 0; e < rw->nt[q]; e++, tq++, tp++) memcpy(res->tie_tan + 3 * tp, rw->tt + 3 * tq, sizeof(double) * 3);
+            for (int e = 0; e < rw->nt[q]; e++, tq++, tp++) {
+                memcpy(res->tie_tan + 3 * tp, rw->tt + 3 * tq, sizeof(double) * 3);
+                res->tie_dist[tp] = rw->td[tq];
+            }
             res->tie_off[p + 1] = tp;
         }
-        free(rw->nbr); free(rw->dist); free(rw->tan); free(rw->flags); free(rw->nt); free(rw->tt);
+        free(rw->nbr); free(rw->dist); free(rw->tan); free(rw->flags); free(rw->nt); free(rw->tt); free(rw->td);
     }
     free(rows); free(fp_off); free(fp);
     return res;
@@ -700,7 +713,7 @@ orc_pairs *orc_geodesic_pairs(const orc_mesh *m, int n, const int *face, const d
 int64_t orc_pairs_count(const orc_pairs *p) { return p->count; }
 int64_t orc_pairs_tie_count(const orc_pairs *p) { return p->tcount; }
 void orc_pairs_export(const orc_pairs *p, int64_t *off, int32_t *nbr, double *dist, double *tan, uint8_t *flags,
-                      int64_t *tie_off, double *tie_tan) {
+                      int64_t *tie_off, double *tie_tan, double *tie_dist) {
     if (off) memcpy(off, p->off, sizeof(int64_t) * (p->nsrc + 1));
     if (nbr) memcpy(nbr, p->nbr, sizeof(int32_t) * p->count);
     if (dist) memcpy(dist, p->dist, sizeof(double) * p->count);
@@ -708,11 +721,13 @@ void orc_pairs_export(const orc_pairs *p, int64_t *off, int32_t *nbr, double *di
     if (flags) memcpy(flags, p->flags, p->count);
     if (tie_off) memcpy(tie_off, p->tie_off, sizeof(int64_t) * (p->count + 1));
     if (tie_tan) memcpy(tie_tan, p->tie_tan, sizeof(double) * 3 * p->tcount);
+    if (tie_dist) memcpy(tie_dist, p->tie_dist, sizeof(double) * p->tcount);
 }
 void orc_pairs_counters(const orc_pairs *p, int64_t *c5) { memcpy(c5, p->counters, sizeof(int64_t) * 5); }
 void orc_pairs_free(orc_pairs *p) {
     if (!p) return;
     free(p->off); free(p->nbr); free(p->dist); free(p->tan); free(p->flags); free(p->tie_off); free(p->tie_tan);
+    free(p->tie_dist);
     free(p);
 }
 

@@ -48,15 +48,20 @@ void orc_mesh_export(const orc_mesh *m, int *twin, double *theta, unsigned char 
  * means "all pairs" (only sensible on small meshes). nthreads <= 0: OpenMP
  * default. tie_rel: every initial direction of a path within tie_rel * d of
  * the shortest is kept in the pair's tie set (<= 0: 1e-9); a pair whose set
- * has more than one direction is flagged as a tie. Returns NULL on bad
- * input. */
+ * has more than one direction is flagged as a tie. cone_slack: a target
+ * counts as inside a straight link's cone when its direction is within the
+ * angle whose sine is cone_slack (<= 1e-12: 1e-12), so the tie set also
+ * holds the directions of straight links to points that close to the
+ * target (the resolution of a reduced-precision computation). Returns NULL
+ * on bad input. */
 orc_pairs *orc_geodesic_pairs(const orc_mesh *m, int n, const int *face, const double *bary, double cutoff,
-                              int nsrc, const int *src, int nthreads, double tie_rel);
+                              int nsrc, const int *src, int nthreads, double tie_rel, double cone_slack);
 int64_t orc_pairs_count(const orc_pairs *p);
 int64_t orc_pairs_tie_count(const orc_pairs *p);
-/* off[nsrc+1], nbr[P], dist[P], tan[P][3], flags[P], tie_off[P+1], tie_tan[T][3] */
+/* off[nsrc+1], nbr[P], dist[P], tan[P][3], flags[P], tie_off[P+1], tie_tan[T][3]
+ * and tie_dist[T] (the length of the shortest path found in each direction) */
 void orc_pairs_export(const orc_pairs *p, int64_t *off, int32_t *nbr, double *dist, double *tan, uint8_t *flags,
-                      int64_t *tie_off, double *tie_tan);
+                      int64_t *tie_off, double *tie_tan, double *tie_dist);
 /* counters: [0] windows processed, [1] windows pruned by the bound,
  * [2] roots expanded, [3] pseudo-source distance improvements, [4] sources
  * rejected (position on a vertex) */

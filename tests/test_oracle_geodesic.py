@@ -285,6 +285,48 @@ def test_l_shape_reflex_corner(orc):
                 assert np.linalg.norm(pr.tan[got[j]] - (c - s) / np.linalg.norm(c - s)) < 1e-9
 
 
+def test_l_shape_cone_slack(orc):
+    """A target behind the reflex corner, an angle a = 2.2e-6 rad (seen from
+    the source) past the corner's shadow line: its geodesic bends at the
+    corner. With a cone slack (sine of an angle) below a, the tie set holds
+    only that direction; with a slack above a it also holds the straight
+    line's direction, whose length is shorter by a term of order a^2."""
+    m = W.l_shape(4)
+    om = orc.OracleMesh(m.V, m.T)
+    s = np.array([1.6, 0.5, 0.0])
+    c = np.array([1.0, 1.0, 0.0])
+    uc = (c - s) / np.linalg.norm(c - s)
+    r1, r2, th = float(np.linalg.norm(c - s)), 0.6, 5e-6
+    ok = None
+    for sgn in (1.0, -1.0):
+        a = sgn * th
+        ur = np.array([uc[0] * math.cos(a) - uc[1] * math.sin(a), uc[0] * math.sin(a) + uc[1] * math.cos(a), 0.0])
+        t = c + r2 * ur
+        # the point of the straight segment nearest the corner lies in the
+        # removed quadrant: the segment leaves the region
+        q = s + ((c - s) @ (t - s)) / ((t - s) @ (t - s)) * (t - s)
+        if q[0] > 1.0 and q[1] > 1.0:
+            ok = t
+    assert ok is not None
+    t = ok
+    ul = (t - s) / np.linalg.norm(t - s)
+    ang = math.atan2(np.cross(uc, ul)[2], uc @ ul)
+    assert 2e-6 < abs(ang) < 2.5e-6
+    f, b = place(m, [s, t])
+    for slack, want in ((0.0, [uc]), (1e-7, [uc]), (1e-5, [uc, ul])):
+        pr = orc.geodesic_pairs(om, f, b, math.inf, cone_slack=slack)
+        p = pair_dict(pr, 0)[1]
+        ts = pr.ties(p)
+        assert len(ts) == len(want), (slack, ts)
+        for u in want:
+            assert min(np.linalg.norm(ts - u, axis=1)) < 1e-12
+        exact = r1 + r2
+        if len(want) == 1:
+            assert abs(pr.dist[p] - exact) < 1e-12
+        else:
+            assert abs(pr.dist[p] - np.linalg.norm(t - s)) < 1e-12 and 0 < exact - pr.dist[p] < 1e-10
+
+
 # ------------------------------------------------------------- CF7 / CF8 ----
 def test_tetrahedron(orc):
     m = W.tetrahedron(1.0)
