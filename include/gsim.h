@@ -47,7 +47,10 @@ typedef enum {
     GSIM_E_CAPACITY = -4, /* caller buffer too small: the required count is reported */
     GSIM_E_DEVICE = -5,   /* HIP runtime error */
     GSIM_E_STATE = -6,    /* e.g. no particles set on the mesh */
-    GSIM_E_LIMIT = -7     /* a per-source work limit was exceeded (see gsim_last_error) */
+    GSIM_E_LIMIT = -7,    /* a per-source work limit was exceeded (see gsim_last_error) */
+    GSIM_E_NONFINITE = -8 /* some particles met a non-finite (NaN or infinite) force, displacement or
+                             velocity: they were left where they were, the call's other results stand,
+                             and gsim_particle_flags marks them with GSIM_PF_NONFINITE */
 } gsim_status;
 
 typedef enum { GSIM_FP64 = 0, GSIM_FP32_MIXED = 1 } gsim_precision;
@@ -128,9 +131,23 @@ typedef struct {
     int32_t n_min;                        /* fire: [5] */
 } gsim_integrator;
 
+/* Statistics of one walk: edge crossings, passes through a vertex, boundary
+ * reflections, walks stopped by the 10^4-crossing cap, passes within 1e-9
+ * mean edge lengths of a vertex, and particles left in place because their
+ * displacement or velocity was not finite. */
 typedef struct {
-    int64_t crossings, vertex_hits, boundary_hits, cap_hits, near_vertex;
+    int64_t crossings, vertex_hits, boundary_hits, cap_hits, near_vertex, nonfinite;
 } gsim_walk_stats;
+
+/* Per-particle flags (gsim_particle_flags): what the last walk, step or
+ * force call on the mesh met for each particle. */
+enum {
+    GSIM_PF_VERTEX = 1,      /* the walk passed through a vertex (straightest rule, or reversal on the boundary) */
+    GSIM_PF_NEAR_VERTEX = 2, /* the walk passed within 1e-9 mean edge lengths of a vertex */
+    GSIM_PF_CAP = 4,         /* the walk stopped at the 10^4-crossing cap */
+    GSIM_PF_BOUNDARY = 8,    /* the walk was reflected at a boundary edge */
+    GSIM_PF_NONFINITE = 16   /* a non-finite force, displacement or velocity: the particle stayed */
+};
 
 /* ---- context ------------------------------------------------------------ */
 /* device: HIP device ordinal. hip_stream: a hipStream_t to run on, or NULL for
@@ -150,16 +167,29 @@ gsim_status gsim_mesh_upload(gsim_ctx *ctx, int32_t nv, const double *xyz, int32
 gsim_status gsim_mesh_info_get(gsim_ctx *ctx, int32_t mesh_id, gsim_mesh_info *out);
 
 /* ---- particle state -------------------------------------------------------
- * face[n], bary[n][3], vel[n][3] (NULL = zero velocities). */
+ * A position is a face and a barycentric triple (Sec. 3, mesh-space models).
+ * face[n], bary[n][3], vel[n][3] (NULL = zero velocities). The state is
+ * checked before it is taken: every face index in [0, nf), every triple in
+ * [0, 1] summing to 1 within 1e-9 and not on a vertex (two zero
+ * coordinates), every velocity finite; otherwise GSIM_E_ARG and the previous
+ * state is kept. Setting the particles restarts the step counter, the FIRE
+ * state and the per-particle flags. */
 gsim_status gsim_particles_set(gsim_ctx *ctx, int32_t mesh_id, int32_t n, const int32_t *face, const double *bary,
                                const double *vel);
 /* any output pointer may be NULL; xyz[n][3] receives the 3D positions */
 gsim_status gsim_particles_get(gsim_ctx *ctx, int32_t mesh_id, int32_t *face, double *bary, double *vel,
                                double *xyz);
+/* The same with device arrays (e.g. torch tensors' data_ptr), checked on the
+ * device with the same rules before anything uses them (the call waits for
+ * the check). */
 gsim_status gsim_particles_set_dev(gsim_ctx *ctx, int32_t mesh_id, int32_t n, const int32_t *face_dev,
                                    const double *bary_dev, const double *vel_dev);
 gsim_status gsim_particles_get_dev(gsim_ctx *ctx, int32_t mesh_id, int32_t *face_dev, double *bary_dev,
                                    double *vel_dev);
+/* flags[n]: the GSIM_PF_* bits of each particle from the last walk, step or
+ * force call on the mesh (zero after gsim_particles_set). */
+gsim_status gsim_particle_flags(gsim_ctx *ctx, int32_t mesh_id, uint8_t *flags);
+gsim_status gsim_particle_flags_dev(gsim_ctx *ctx, int32_t mesh_id, uint8_t *flags_dev);
 
 /* ---- hot path -------------------------------------------------------------
  * geodesic_pairs: exact polyhedral geodesic distance and initial unit tangent
@@ -168,6 +198,10 @@ gsim_status gsim_particles_get_dev(gsim_ctx *ctx, int32_t mesh_id, int32_t *face
  * Euclidean prefilter, window propagation and target query run on the GPU;
  * the CSR is then copied to the caller's host buffers. */
 gsim_status gsim_geodesic_pairs(gsim_ctx *ctx, int32_t mesh_id, double cutoff, gsim_pairs *out);
+/* The same, with every buffer of `out` (off, nbr, dist, tan, flags) in device
+ * memory, written on the context's stream (the call waits only to learn the
+ * pair count; the copies into `out` are ordered on the stream). */
+gsim_status gsim_geodesic_pairs_dev(gsim_ctx *ctx, int32_t mesh_id, double cutoff, gsim_pairs *out);
 
 /* voronoi_neighbours: the in-surface Voronoi neighbours of the particles
  * (Sec. 5: the restricted Euclidean Voronoi diagram on the surface, from
@@ -186,21 +220,37 @@ gsim_status gsim_voronoi_neighbours(gsim_ctx *ctx, int32_t mesh_id, int64_t *off
 /* compute_forces: F_i = sum_j U'(d_ij) t_ij (Sec. 3.1 force sum; with t_ij
  * pointing from i towards j a repulsive potential pushes i away from j) and
  * E = (1/2) sum_i sum_j U(d_ij). force[n][3] host buffer; energy may be NULL.
- * Recomputes the pairs for the potential's cutoff. */
+ * Recomputes the pairs for the potential's cutoff. A particle whose force or
+ * energy is not finite is flagged (GSIM_PF_NONFINITE) and the call returns
+ * GSIM_E_NONFINITE with every force written. */
 gsim_status gsim_compute_forces(gsim_ctx *ctx, int32_t mesh_id, const gsim_potential *pot, double *force,
                                 double *energy);
+/* The same into device buffers force_dev[n][3] and energy_dev[1] (may be
+ * NULL), copied on the context's stream. */
+gsim_status gsim_compute_forces_dev(gsim_ctx *ctx, int32_t mesh_id, const gsim_potential *pot, double *force_dev,
+                                    double *energy_dev);
 
 /* displace_on_surface: the shift (Sec. 3.2). disp[n][3] host buffer; its
  * component normal to the particle's face is removed first. With
  * transport_velocity != 0 the stored velocities are parallel-transported
- * along the walk. stats may be NULL. */
+ * along the walk. stats may be NULL. A particle whose displacement (or
+ * transported velocity) is not finite stays where it is, is flagged
+ * (GSIM_PF_NONFINITE), and the call returns GSIM_E_NONFINITE after moving
+ * the others. */
 gsim_status gsim_displace_on_surface(gsim_ctx *ctx, int32_t mesh_id, const double *disp, int transport_velocity,
                                      gsim_walk_stats *stats);
+/* The same with disp_dev[n][3] in device memory, read by the walk kernel in
+ * place (no staging copy). */
+gsim_status gsim_displace_on_surface_dev(gsim_ctx *ctx, int32_t mesh_id, const double *disp_dev,
+                                         int transport_velocity, gsim_walk_stats *stats);
 
 /* step: nsteps full time steps on device (prefilter, window propagation,
  * query, forces, integrator, walk); state stays in device memory. The noise
  * counter of step k is the number of steps taken on this mesh since its
- * particles were last set (so a run can be resumed bit-identically). */
+ * particles were last set (so a run can be resumed bit-identically). A
+ * particle that meets a non-finite force, displacement or velocity stays
+ * where it is and is flagged; the call then returns GSIM_E_NONFINITE at its
+ * end (the other particles' steps stand). */
 gsim_status gsim_step(gsim_ctx *ctx, int32_t mesh_id, const gsim_potential *pot, const gsim_integrator *integ,
                       int32_t nsteps);
 
@@ -285,8 +335,9 @@ gsim_status gsim_timing_get(gsim_ctx *ctx, const char *name, double *avg_ms, int
  * [3] stale windows dropped, [4] sources recomputed in FP64 (FP32-mixed
  * guard band), [5] neighbour pairs,
  * [6] sources over a work limit, [10] deepest window stack of a source
- * (records, LDS and overflow together). Summed over the calls since timing was last
- * enabled: [7] neighbour pairs, [8] windows, [9] passes. c[11]. */
+ * (records, LDS and overflow together), [11] particles that met a non-finite
+ * value. Summed over the calls since timing was last enabled: [7] neighbour
+ * pairs, [8] windows, [9] passes. c[12]. */
 gsim_status gsim_counters_get(gsim_ctx *ctx, int64_t *c);
 /* Per-source profile of the geodesic kernel, accumulated over the calls
  * made while it is on: out[n][8] = GPU clock cycles, propagation-loop

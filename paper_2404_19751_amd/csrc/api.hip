@@ -253,12 +253,20 @@ MeshState *get_mesh(gsim_ctx *c, int32_t id) {
 bool finite_cutoff(double c) { return c > 0.0 && std::isfinite(c); }
 int pot_kind_ok(const gsim_potential *p) { return p && p->kind >= 0 && p->kind <= 2; }
 
+// GSIM_E_NONFINITE when `count` particles met a non-finite value.
+gsim_status nonfinite_status(gsim_ctx *c, unsigned long long count) {
+    if (!count) return GSIM_OK;
+    return fail(c, GSIM_E_NONFINITE,
+                std::to_string(count) + " particle(s) met a non-finite force, displacement or velocity and were left "
+                                        "in place; gsim_particle_flags marks them (GSIM_PF_NONFINITE)");
+}
+
 // ---------------------------------------------------------------- calls
 // A call (geodesic_pairs, compute_forces, step) zeroes the device counters,
 // queues its work without any host synchronisation, and reads the counters
 // back once at the end.
 gsim_status begin_call(gsim_ctx *c) {
-    HIPCHK(c, launch_zero_u64(P<unsigned long long>(c->ctr), 8 * kCtrSlots * kCtrStride, c->stream));
+    HIPCHK(c, launch_zero_u64(P<unsigned long long>(c->ctr), (int64_t)kCtrWords * kCtrSlots * kCtrStride, c->stream));
     HIPCHK(c, launch_zero_i32(P<int32_t>(c->pf_over), 1, c->stream));
     c->passes = 0;
     return GSIM_OK;
@@ -282,6 +290,7 @@ gsim_status end_call(gsim_ctx *c) {
         L.nbr_pairs += q.nbr_pairs;
         L.limited += q.limited;
         L.max_depth = std::max(L.max_depth, q.max_depth);
+        L.nonfinite += q.nonfinite;
     }
     c->cum_pairs += c->last.nbr_pairs;
     c->cum_windows += c->last.windows;
@@ -293,7 +302,7 @@ gsim_status end_call(gsim_ctx *c) {
                         " candidate targets within the cutoff, window stack or window count); the results of this "
                         "call are incomplete. Passes of the whole-mesh kernel (the \"whole_mesh\" knob, up to " +
                         std::to_string(kAllPairsMax) + " particles) have no limit on candidates");
-    return GSIM_OK;
+    return nonfinite_status(c, c->last.nonfinite);
 }
 
 // ---------------------------------------------------------------- batches
@@ -691,10 +700,12 @@ gsim_status run_forces(gsim_ctx *c, MeshState *ms, const gsim_potential *pot) {
     HIPCHK(c, ensure(ms->Ei, sizeof(double) * n));
     HIPCHK(c, ensure(ms->E, sizeof(double) * 4));
     HIPCHK(c, ensure(c->sum_scratch, sizeof(double) * ((n + 255) / 256 + 2)));
+    HIPCHK(c, ensure(ms->wflags, n));
     Stage st(c, "forces");
     HIPCHK(c, launch_forces_rows(n, P<int32_t>(ms->cand_cnt), ms->cap, P<double>(ms->cdist), P<double>(ms->ctan),
                                  cutoff, pot->kind, pot->k, pot->sigma, P<double>(ms->F), P<double>(ms->Ei),
-                                 &P<Counters>(c->ctr)->nbr_pairs, c->stream));
+                                 &P<Counters>(c->ctr)->nbr_pairs, P<uint8_t>(ms->wflags),
+                                 &P<Counters>(c->ctr)->nonfinite, c->stream));
     HIPCHK(c, launch_sum(P<double>(ms->Ei), n, P<double>(ms->E), P<double>(c->sum_scratch), c->stream));
     return GSIM_OK;
 }
@@ -1005,7 +1016,10 @@ static gsim_status alloc_particles(gsim_ctx *c, MeshState *ms, int32_t n) {
     return GSIM_OK;
 }
 
-static gsim_status check_state(gsim_ctx *c, const MeshState *ms, int32_t n, const int32_t *face, const double *bary) {
+static gsim_status check_state(gsim_ctx *c, const MeshState *ms, int32_t n, const int32_t *face, const double *bary,
+                               const double *vel) {
+    for (int32_t i = 0; vel && i < 3 * n; ++i)
+        if (!std::isfinite(vel[i])) return fail(c, GSIM_E_ARG, "velocity not finite");
     for (int32_t i = 0; i < n; ++i) {
         if (face[i] < 0 || face[i] >= ms->dm.nf) return fail(c, GSIM_E_ARG, "face index out of range");
         const double *b = bary + 3 * (size_t)i;
@@ -1028,6 +1042,9 @@ static gsim_status reset_state(gsim_ctx *c, MeshState *ms, const double *vel, hi
     HIPCHK(c, launch_fill_u64(P<unsigned long long>(ms->step_dev), 1, ~0ull, s));
     HIPCHK(c, ensure(ms->fire, sizeof(FireState)));
     HIPCHK(c, launch_zero_u64(P<unsigned long long>(ms->fire), sizeof(FireState) / 8, s));
+    // no flags until a walk, step or force call sets them
+    HIPCHK(c, ensure(ms->wflags, (size_t)n + 4));
+    HIPCHK(c, launch_zero_i32(P<int32_t>(ms->wflags), (n + 3) / 4, s));
     ms->step = 0;
     return GSIM_OK;
 }
@@ -1038,7 +1055,7 @@ gsim_status gsim_particles_set(gsim_ctx *c, int32_t id, int32_t n, const int32_t
     try {
         MeshState *ms = get_mesh(c, id);
         if (!ms || n < 1 || !face || !bary) return fail(c, GSIM_E_ARG, "bad particle arguments");
-        gsim_status st = check_state(c, ms, n, face, bary);
+        gsim_status st = check_state(c, ms, n, face, bary, vel);
         if (st != GSIM_OK) return st;
         if ((st = alloc_particles(c, ms, n)) != GSIM_OK) return st;
         hipStream_t s = c->stream;
@@ -1057,9 +1074,20 @@ gsim_status gsim_particles_set_dev(gsim_ctx *c, int32_t id, int32_t n, const int
     try {
         MeshState *ms = get_mesh(c, id);
         if (!ms || n < 1 || !face || !bary) return fail(c, GSIM_E_ARG, "bad particle arguments");
+        hipStream_t s = c->stream;
+        // the same checks as the host path, on the device, before the state is taken
+        int32_t *bad = P<int32_t>(c->wstats);
+        int32_t hb[3] = {0, 0, 0};
+        HIPCHK(c, launch_zero_i32(bad, 3, s));
+        HIPCHK(c, launch_validate_state(ms->dm.nf, n, face, bary, vel, bad, s));
+        HIPCHK(c, hipMemcpyAsync(hb, bad, sizeof(hb), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        if (hb[0] || hb[1] || hb[2])
+            return fail(c, GSIM_E_ARG, std::to_string(hb[0]) + " face index(es) out of range, " + std::to_string(hb[1]) +
+                                           " barycentric triple(s) not in [0,1], not summing to 1 or on a vertex, " +
+                                           std::to_string(hb[2]) + " non-finite velocity(ies); state unchanged");
         gsim_status st = alloc_particles(c, ms, n);
         if (st != GSIM_OK) return st;
-        hipStream_t s = c->stream;
         HIPCHK(c, hipMemcpyAsync(ms->face, face, sizeof(int32_t) * n, hipMemcpyDeviceToDevice, s));
         HIPCHK(c, hipMemcpyAsync(ms->bary, bary, sizeof(double) * 3 * n, hipMemcpyDeviceToDevice, s));
         return reset_state(c, ms, vel, hipMemcpyDeviceToDevice);
@@ -1104,7 +1132,9 @@ gsim_status gsim_particles_get_dev(gsim_ctx *c, int32_t id, int32_t *face, doubl
     GSIM_CATCH(c)
 }
 
-gsim_status gsim_geodesic_pairs(gsim_ctx *c, int32_t id, double cutoff, gsim_pairs *out) {
+// a1-a3 for one surface and the CSR into the caller's buffers (host or
+// device memory, by `kind`).
+static gsim_status pairs_to(gsim_ctx *c, int32_t id, double cutoff, gsim_pairs *out, hipMemcpyKind kind) {
     DeviceGuard dg(c);
     MeshState *ms = get_mesh(c, id);
     if (!ms || !out) return fail(c, GSIM_E_ARG, "bad arguments");
@@ -1122,18 +1152,25 @@ gsim_status gsim_geodesic_pairs(gsim_ctx *c, int32_t id, double cutoff, gsim_pai
             return fail(c, GSIM_E_CAPACITY, "pair buffers too small: " + std::to_string(ms->n_pairs) + " needed");
         hipStream_t s = c->stream;
         const int64_t P_ = ms->n_pairs;
-        HIPCHK(c, hipMemcpyAsync(out->off, ms->off.p, sizeof(int64_t) * (ms->n + 1), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(out->off, ms->off.p, sizeof(int64_t) * (ms->n + 1), kind, s));
         if (P_) {
-            HIPCHK(c, hipMemcpyAsync(out->nbr, ms->nbr.p, sizeof(int32_t) * P_, hipMemcpyDeviceToHost, s));
-            HIPCHK(c, hipMemcpyAsync(out->dist, ms->dist.p, sizeof(double) * P_, hipMemcpyDeviceToHost, s));
-            HIPCHK(c, hipMemcpyAsync(out->tan, ms->tan.p, sizeof(double) * 3 * P_, hipMemcpyDeviceToHost, s));
-            if (out->flags) HIPCHK(c, hipMemcpyAsync(out->flags, ms->flags.p, P_, hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipMemcpyAsync(out->nbr, ms->nbr.p, sizeof(int32_t) * P_, kind, s));
+            HIPCHK(c, hipMemcpyAsync(out->dist, ms->dist.p, sizeof(double) * P_, kind, s));
+            HIPCHK(c, hipMemcpyAsync(out->tan, ms->tan.p, sizeof(double) * 3 * P_, kind, s));
+            if (out->flags) HIPCHK(c, hipMemcpyAsync(out->flags, ms->flags.p, P_, kind, s));
         }
-        HIPCHK(c, hipStreamSynchronize(s));
+        if (kind == hipMemcpyDeviceToHost) HIPCHK(c, hipStreamSynchronize(s));
         return GSIM_OK;
-    } catch (...) {
-        return fail(c, GSIM_E_ARG, "unexpected host error");
     }
+    GSIM_CATCH(c)
+}
+
+gsim_status gsim_geodesic_pairs(gsim_ctx *c, int32_t id, double cutoff, gsim_pairs *out) {
+    return pairs_to(c, id, cutoff, out, hipMemcpyDeviceToHost);
+}
+
+gsim_status gsim_geodesic_pairs_dev(gsim_ctx *c, int32_t id, double cutoff, gsim_pairs *out) {
+    return pairs_to(c, id, cutoff, out, hipMemcpyDeviceToDevice);
 }
 
 gsim_status gsim_voronoi_neighbours(gsim_ctx *c, int32_t id, int64_t *off, int32_t *nbr, int64_t capacity,
@@ -1227,7 +1264,10 @@ gsim_status gsim_voronoi_neighbours(gsim_ctx *c, int32_t id, int64_t *off, int32
     }
 }
 
-gsim_status gsim_compute_forces(gsim_ctx *c, int32_t id, const gsim_potential *pot, double *force, double *energy) {
+// a1-a4 for one surface, the forces and the energy into the caller's
+// buffers (host or device memory, by `kind`).
+static gsim_status forces_to(gsim_ctx *c, int32_t id, const gsim_potential *pot, double *force, double *energy,
+                             hipMemcpyKind kind) {
     DeviceGuard dg(c);
     MeshState *ms = get_mesh(c, id);
     if (!ms || !pot_kind_ok(pot) || !force) return fail(c, GSIM_E_ARG, "bad arguments");
@@ -1237,32 +1277,34 @@ gsim_status gsim_compute_forces(gsim_ctx *c, int32_t id, const gsim_potential *p
         if ((st = begin_call(c)) != GSIM_OK) return st;
         if ((st = single(c, ms, pot->cutoff, pot, B)) != GSIM_OK) return st;
         if ((st = run_forces(c, ms, pot)) != GSIM_OK) return st;
-        if ((st = end_call(c)) != GSIM_OK) return st;
         hipStream_t s = c->stream;
-        HIPCHK(c, hipMemcpyAsync(force, ms->F.p, sizeof(double) * 3 * ms->n, hipMemcpyDeviceToHost, s));
-        if (energy) HIPCHK(c, hipMemcpyAsync(energy, ms->E.p, sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(c, hipStreamSynchronize(s));
-        return GSIM_OK;
-    } catch (...) {
-        return fail(c, GSIM_E_ARG, "unexpected host error");
+        HIPCHK(c, hipMemcpyAsync(force, ms->F.p, sizeof(double) * 3 * ms->n, kind, s));
+        if (energy) HIPCHK(c, hipMemcpyAsync(energy, ms->E.p, sizeof(double), kind, s));
+        // the counters are read (a synchronisation) after the copies are queued
+        return end_call(c);
     }
+    GSIM_CATCH(c)
 }
 
-gsim_status gsim_displace_on_surface(gsim_ctx *c, int32_t id, const double *disp, int transport_velocity,
-                                     gsim_walk_stats *stats) {
-    DeviceGuard dg(c);
-    MeshState *ms = get_mesh(c, id);
-    if (!ms || !disp) return fail(c, GSIM_E_ARG, "bad arguments");
-    if (ms->n <= 0) return fail(c, GSIM_E_STATE, "no particles on this mesh");
+gsim_status gsim_compute_forces(gsim_ctx *c, int32_t id, const gsim_potential *pot, double *force, double *energy) {
+    return forces_to(c, id, pot, force, energy, hipMemcpyDeviceToHost);
+}
+
+gsim_status gsim_compute_forces_dev(gsim_ctx *c, int32_t id, const gsim_potential *pot, double *force,
+                                    double *energy) {
+    return forces_to(c, id, pot, force, energy, hipMemcpyDeviceToDevice);
+}
+
+// The walk of every particle by disp (device memory) and its statistics.
+static gsim_status walk_dev(gsim_ctx *c, MeshState *ms, const double *disp, int transport_velocity,
+                            gsim_walk_stats *stats) {
     const int n = ms->n;
     hipStream_t s = c->stream;
-    HIPCHK(c, ensure(ms->disp, sizeof(double) * 3 * n));
     HIPCHK(c, ensure(ms->wflags, n));
-    HIPCHK(c, hipMemcpyAsync(ms->disp.p, disp, sizeof(double) * 3 * n, hipMemcpyHostToDevice, s));
     HIPCHK(c, launch_zero_u64(P<unsigned long long>(c->wstats), 8, s));
     {
         Stage st(c, "walk");
-        HIPCHK(c, launch_walk(ms->dm, n, ms->face, ms->bary, P<double>(ms->disp), transport_velocity ? ms->vel : nullptr,
+        HIPCHK(c, launch_walk(ms->dm, n, ms->face, ms->bary, disp, transport_velocity ? ms->vel : nullptr,
                               P<unsigned long long>(c->wstats), P<uint8_t>(ms->wflags), s));
     }
     unsigned long long h[8];
@@ -1274,8 +1316,59 @@ gsim_status gsim_displace_on_surface(gsim_ctx *c, int32_t id, const double *disp
         stats->boundary_hits = (int64_t)h[2];
         stats->cap_hits = (int64_t)h[3];
         stats->near_vertex = (int64_t)h[4];
+        stats->nonfinite = (int64_t)h[5];
     }
-    return GSIM_OK;
+    return nonfinite_status(c, h[5]);
+}
+
+gsim_status gsim_displace_on_surface(gsim_ctx *c, int32_t id, const double *disp, int transport_velocity,
+                                     gsim_walk_stats *stats) {
+    DeviceGuard dg(c);
+    MeshState *ms = get_mesh(c, id);
+    if (!ms || !disp) return fail(c, GSIM_E_ARG, "bad arguments");
+    if (ms->n <= 0) return fail(c, GSIM_E_STATE, "no particles on this mesh");
+    try {
+        HIPCHK(c, ensure(ms->disp, sizeof(double) * 3 * ms->n));
+        HIPCHK(c, hipMemcpyAsync(ms->disp.p, disp, sizeof(double) * 3 * ms->n, hipMemcpyHostToDevice, c->stream));
+        return walk_dev(c, ms, P<double>(ms->disp), transport_velocity, stats);
+    }
+    GSIM_CATCH(c)
+}
+
+gsim_status gsim_displace_on_surface_dev(gsim_ctx *c, int32_t id, const double *disp, int transport_velocity,
+                                         gsim_walk_stats *stats) {
+    DeviceGuard dg(c);
+    MeshState *ms = get_mesh(c, id);
+    if (!ms || !disp) return fail(c, GSIM_E_ARG, "bad arguments");
+    if (ms->n <= 0) return fail(c, GSIM_E_STATE, "no particles on this mesh");
+    try {
+        return walk_dev(c, ms, disp, transport_velocity, stats);
+    }
+    GSIM_CATCH(c)
+}
+
+// Per-particle flags of the last walk, step or force call on the mesh
+// (host or device buffer, by `kind`).
+static gsim_status flags_to(gsim_ctx *c, int32_t id, uint8_t *flags, hipMemcpyKind kind) {
+    DeviceGuard dg(c);
+    MeshState *ms = get_mesh(c, id);
+    if (!ms || !flags) return fail(c, GSIM_E_ARG, "bad arguments");
+    if (ms->n <= 0) return fail(c, GSIM_E_STATE, "no particles on this mesh");
+    try {
+        hipStream_t s = c->stream;
+        HIPCHK(c, hipMemcpyAsync(flags, ms->wflags.p, ms->n, kind, s));
+        if (kind == hipMemcpyDeviceToHost) HIPCHK(c, hipStreamSynchronize(s));
+        return GSIM_OK;
+    }
+    GSIM_CATCH(c)
+}
+
+gsim_status gsim_particle_flags(gsim_ctx *c, int32_t id, uint8_t *flags) {
+    return flags_to(c, id, flags, hipMemcpyDeviceToHost);
+}
+
+gsim_status gsim_particle_flags_dev(gsim_ctx *c, int32_t id, uint8_t *flags) {
+    return flags_to(c, id, flags, hipMemcpyDeviceToDevice);
 }
 
 gsim_status gsim_step_batched(gsim_ctx *c, int32_t nmesh, const int32_t *mesh_ids, const gsim_potential *pots,
@@ -1528,6 +1621,7 @@ gsim_status gsim_source_profile(gsim_ctx *c, int on, int64_t *out, int32_t n) {
 
 gsim_status gsim_counters_get(gsim_ctx *c, int64_t *c10) {
     if (!c || !c10) return GSIM_E_ARG;
+    c10[11] = (int64_t)c->last.nonfinite;
     c10[10] = (int64_t)c->last.max_depth;
     c10[7] = (int64_t)c->cum_pairs;
     c10[8] = (int64_t)c->cum_windows;

@@ -40,6 +40,9 @@ static_assert(sizeof(HeRecF) == 48, "HeRecF must be 48 bytes");
 
 enum : uint8_t { VF_PSEUDO = 1, VF_BOUNDARY = 2 };
 enum : uint8_t { GSIM_PAIR_TIE_BIT = 1, GSIM_PAIR_ZERO_BIT = 2, GSIM_PAIR_GUARD_BIT = 4 };
+// Per-particle flags of the last walk, step or force call (the same bits as
+// the public GSIM_PF_* values).
+enum : uint8_t { PF_VERTEX = 1, PF_NEAR_VERTEX = 2, PF_CAP = 4, PF_BOUNDARY = 8, PF_NONFINITE = 16 };
 
 // Per bend vertex (dense number): its position and its fan of outgoing
 // half-edges, read together when the vertex is launched.
@@ -129,15 +132,18 @@ struct GeoOut {
     uint8_t *flags; // [cand_cap]
 };
 
-struct Counters {   // device-side, int64
+struct alignas(128) Counters {  // device-side, int64; one 128-byte line
     unsigned long long windows, pruned, launches, stale, guards, nbr_pairs, limited, max_depth;
+    unsigned long long nonfinite;  // particles that met a non-finite force, displacement or velocity
 };
-// The device counters are kCtrSlots copies, 128 bytes apart: each workgroup
+static_assert(sizeof(Counters) == 128, "one counter slot per 128-byte line");
+// The device counters are kCtrSlots copies, one line each: each workgroup
 // of the geodesic grid adds into copy (workgroup mod kCtrSlots), so that its
 // end-of-workgroup atomics do not serialise on one line; the other kernels
 // add into the first; the host sums them (max_depth: the maximum).
 constexpr int kCtrSlots = 64;
-constexpr int kCtrStride = 2;  // Counters between two slots
+constexpr int kCtrStride = 1;  // Counters between two slots
+constexpr int kCtrWords = (int)(sizeof(Counters) / 8);  // 64-bit words of one slot
 
 // launchers (return hipError_t of the launch)
 hipError_t launch_xyz(const DevMesh &m, int n, const int32_t *face, const double *bary, double *xyz,
@@ -313,13 +319,27 @@ hipError_t launch_count_rows(int n, const int32_t *cnt, int cap_c, const double 
 hipError_t launch_compact_rows(int n, const int32_t *cnt, int cap_c, const int32_t *cand, const double *dist,
                                const double *tan, const uint8_t *flags, double cutoff, const int64_t *off,
                                int32_t *nbr, double *odist, double *otan, uint8_t *oflags, hipStream_t s);
+// F_i and E_i from the rows; pflags[i] (may be null) receives PF_NONFINITE
+// when either is not finite, and nonfinite counts such particles.
 hipError_t launch_forces_rows(int n, const int32_t *cnt, int cap_c, const double *dist, const double *tan,
                               double cutoff, int kind, double k, double sigma, double *F, double *Ei,
-                              unsigned long long *npairs, hipStream_t s);
+                              unsigned long long *npairs, uint8_t *pflags, unsigned long long *nonfinite,
+                              hipStream_t s);
+// Checks a particle state before it is used: bad[0] counts face indices
+// outside [0, nf), bad[1] barycentric triples that are not finite, outside
+// [0, 1], do not sum to 1 within 1e-9 or put the particle on a vertex,
+// bad[2] velocities (vel may be null) that are not finite. bad[0..2] must be
+// zero beforehand.
+hipError_t launch_validate_state(int nf, int n, const int32_t *face, const double *bary, const double *vel,
+                                 int32_t *bad, hipStream_t s);
 hipError_t launch_sum(const double *x, int n, double *out, double *scratch, hipStream_t s);
 hipError_t launch_integrate(const DevMesh &m, int n, const int32_t *face, const double *F, int kind, double dt,
                             double mobility, double kT, double friction, uint64_t seed, uint64_t step,
                             double *disp, hipStream_t s);
+// The walk of every particle; stats[8] (zeroed beforehand) receive the
+// crossings, vertex hits, boundary hits, crossing-cap hits, near-vertex
+// passes and the particles left in place because their displacement or
+// velocity was not finite; flags[n] (may be null) the PF_* bits.
 hipError_t launch_walk(const DevMesh &m, int n, int32_t *face, double *bary, const double *disp, double *vel,
                        unsigned long long *stats, uint8_t *flags, hipStream_t s);
 

@@ -254,9 +254,11 @@ __global__ void k_compact_rows(int n, const int32_t *__restrict__ cnt, int cap, 
 // ------------------------------------------------------------ forces
 __global__ void k_forces_rows(int n, const int32_t *__restrict__ cnt, int cap, const double *__restrict__ dist,
                               const double *__restrict__ tan, double cutoff, int kind, double k, double sigma,
-                              double *__restrict__ F, double *__restrict__ Ei, unsigned long long *__restrict__ npairs) {
+                              double *__restrict__ F, double *__restrict__ Ei, unsigned long long *__restrict__ npairs,
+                              uint8_t *__restrict__ pflags, unsigned long long *__restrict__ nonfinite) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     int np = 0;
+    bool bad = false;
     if (i < n) {
         double f[3], e;
         row_force(i, cnt, cap, dist, tan, cutoff, kind, k, sigma, f, e, np);
@@ -264,8 +266,39 @@ __global__ void k_forces_rows(int n, const int32_t *__restrict__ cnt, int cap, c
         F[3 * i + 1] = f[1];
         F[3 * i + 2] = f[2];
         Ei[i] = e;
+        bad = !(isfinite(f[0]) && isfinite(f[1]) && isfinite(f[2]) && isfinite(e));
+        if (pflags) pflags[i] = bad ? PF_NONFINITE : 0;
     }
     if (npairs) wave_atomic_add(npairs, (unsigned long long)np);
+    if (nonfinite) wave_atomic_add(nonfinite, bad ? 1ull : 0ull);
+}
+
+// A particle state is usable when every face index is in range and every
+// barycentric triple lies in the face, sums to 1 and is not a vertex (the
+// conditions the host path checks too), and every velocity is finite.
+__global__ void k_validate_state(int nf, int n, const int32_t *__restrict__ face, const double *__restrict__ bary,
+                                 const double *__restrict__ vel, int32_t *__restrict__ bad) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    int bf = 0, bb = 0, bv = 0;
+    if (i < n) {
+        const int f = face[i];
+        bf = f < 0 || f >= nf;
+        const double b0 = bary[3 * (int64_t)i], b1 = bary[3 * (int64_t)i + 1], b2 = bary[3 * (int64_t)i + 2];
+        // written so that NaN fails every comparison
+        const bool in01 = b0 >= 0.0 && b0 <= 1.0 && b1 >= 0.0 && b1 <= 1.0 && b2 >= 0.0 && b2 <= 1.0;
+        const int zeros = (b0 == 0.0) + (b1 == 0.0) + (b2 == 0.0);
+        bb = !(in01 && fabs(b0 + b1 + b2 - 1.0) <= 1e-9 && zeros < 2);
+        if (vel) {
+            const double *v = vel + 3 * (int64_t)i;
+            bv = !(isfinite(v[0]) && isfinite(v[1]) && isfinite(v[2]));
+        }
+    }
+    const unsigned long long mf = __ballot(bf), mb = __ballot(bb), mv = __ballot(bv);
+    if ((threadIdx.x & 63) == 0) {
+        if (mf) atomicAdd(&bad[0], __popcll(mf));
+        if (mb) atomicAdd(&bad[1], __popcll(mb));
+        if (mv) atomicAdd(&bad[2], __popcll(mv));
+    }
 }
 
 // deterministic two-level sum
@@ -506,9 +539,16 @@ hipError_t launch_compact_rows(int n, const int32_t *cnt, int cap_c, const int32
 }
 hipError_t launch_forces_rows(int n, const int32_t *cnt, int cap_c, const double *dist, const double *tan,
                               double cutoff, int kind, double k, double sigma, double *F, double *Ei,
-                              unsigned long long *npairs, hipStream_t s) {
+                              unsigned long long *npairs, uint8_t *pflags, unsigned long long *nonfinite,
+                              hipStream_t s) {
     hipLaunchKernelGGL(k_forces_rows, dim3(nblocks(n)), dim3(kBlock), 0, s, n, cnt, cap_c, dist, tan, cutoff, kind, k,
-                       sigma, F, Ei, npairs);
+                       sigma, F, Ei, npairs, pflags, nonfinite);
+    return hipGetLastError();
+}
+hipError_t launch_validate_state(int nf, int n, const int32_t *face, const double *bary, const double *vel,
+                                 int32_t *bad, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_validate_state, dim3(nblocks(n)), dim3(kBlock), 0, s, nf, n, face, bary, vel, bad);
     return hipGetLastError();
 }
 hipError_t launch_sum(const double *x, int n, double *out, double *scratch, hipStream_t s) {

@@ -17,13 +17,14 @@ __device__ inline void flush_counts(const WalkCounts &wc, unsigned long long *st
     wave_atomic_add(&stats[2], wc.bhit);
     wave_atomic_add(&stats[3], wc.cap);
     wave_atomic_add(&stats[4], wc.near);
+    wave_atomic_add(&stats[5], wc.nonfinite);
 }
 
 __global__ __launch_bounds__(128) void k_walk(DevMesh m, int n, int32_t *__restrict__ face, double *__restrict__ bary,
                                               const double *__restrict__ disp, double *__restrict__ vel,
                                               unsigned long long *__restrict__ stats, uint8_t *__restrict__ flags) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    WalkCounts wc = {0, 0, 0, 0, 0};
+    WalkCounts wc = {0, 0, 0, 0, 0, 0};
     if (i < n) {
         int f = face[i];
         double b[3] = {bary[3 * i], bary[3 * i + 1], bary[3 * i + 2]};
@@ -49,8 +50,9 @@ __global__ __launch_bounds__(128) void k_walk(DevMesh m, int n, int32_t *__restr
 // particle's neighbour row (Sec. 3.1 force sum), the displacement of the
 // integrator (Sec. 2.1), and the walk (Sec. 3.2). Rows hold only distances
 // and tangents computed before any particle moves, so particles are
-// independent here. Returns the particle's neighbour-pair count.
-__device__ inline int update_one(const SurfDesc *__restrict__ desc, const BatchIdx &bi, int g) {
+// independent here. Returns the particle's neighbour-pair count; nonfin is
+// set when a non-finite value kept the particle in place.
+__device__ inline int update_one(const SurfDesc *__restrict__ desc, const BatchIdx &bi, int g, bool &nonfin) {
     const int si = batch_surface(bi, g);
     const SurfDesc &sd = desc[si];
     const int i = g - bi.begin[si];
@@ -58,7 +60,7 @@ __device__ inline int update_one(const SurfDesc *__restrict__ desc, const BatchI
         double F[3], E;
         int np = 0;
         row_force(i, sd.cand_cnt, sd.cap, sd.cdist, sd.ctan, sd.cutoff, sd.pkind, sd.pk, sd.psigma, F, E, np);
-        move_particle(sd, i, F, sd.face, sd.bary, sd.vel);
+        nonfin = (move_particle(sd, i, F, sd.face, sd.bary, sd.vel) & PF_NONFINITE) != 0;
         return np;
     }
     // FIRE: forces and the control step come from the FIRE kernels; mix,
@@ -72,19 +74,19 @@ __device__ inline int update_one(const SurfDesc *__restrict__ desc, const BatchI
     const double L = sqrt(dot(Dv, Dv));
     if (L > sd.max_disp) Dv = (sd.max_disp / L) * Dv;
     const double D[3] = {Dv.x, Dv.y, Dv.z};
-    walk_store(sd, i, sd.face[i], D, v, sd.face, sd.bary, sd.vel);
+    nonfin = (walk_store(sd, i, sd.face[i], D, v, sd.face, sd.bary, sd.vel) & PF_NONFINITE) != 0;
     return 0;
 }
 
 // One thread per particle of the flattened batch.
 __global__ __launch_bounds__(256) void k_update_batch(const SurfDesc *__restrict__ desc, BatchIdx bi,
-                                                     unsigned long long *__restrict__ npairs) {
+                                                     Counters *__restrict__ ctr) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    const int np = g < bi.begin[bi.nsurf] ? update_one(desc, bi, g) : 0;
-    // the pair count: one atomic per wavefront, not one per particle
-    unsigned long long t = (unsigned long long)np;
-    for (int o = 32; o > 0; o >>= 1) t += __shfl_xor(t, o);
-    if ((threadIdx.x & 63) == 0 && t && npairs) atomicAdd(npairs, t);
+    bool nonfin = false;
+    const int np = g < bi.begin[bi.nsurf] ? update_one(desc, bi, g, nonfin) : 0;
+    // the counts: one atomic per wavefront, not one per particle
+    wave_atomic_add(&ctr->nbr_pairs, (unsigned long long)np);
+    wave_atomic_add(&ctr->nonfinite, nonfin ? 1ull : 0ull);
 }
 
 // The state that the cutoff kernel's fused update wrote (the next-state
@@ -115,8 +117,7 @@ hipError_t launch_update_batch(const SurfDesc *desc, const BatchIdx &bi, int blo
     const int total = bi.begin[bi.nsurf];
     if (total <= 0) return hipSuccess;
     if (block != 64 && block != 128 && block != 256) block = 128;
-    hipLaunchKernelGGL(k_update_batch, dim3((total + block - 1) / block), dim3(block), 0, s, desc, bi,
-                       &ctr->nbr_pairs);
+    hipLaunchKernelGGL(k_update_batch, dim3((total + block - 1) / block), dim3(block), 0, s, desc, bi, ctr);
     return hipGetLastError();
 }
 

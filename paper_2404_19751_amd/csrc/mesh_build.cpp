@@ -27,6 +27,8 @@ inline double nrm(V3 a) { return std::sqrt(dot(a, a)); }
 
 std::string build_host_mesh(int nv, const double *xyz, int nf, const int32_t *tri, HostMesh &M) {
     if (nv < 3 || nf < 1 || !xyz || !tri) return "empty mesh";
+    for (size_t i = 0; i < 3 * (size_t)nv; ++i)
+        if (!std::isfinite(xyz[i])) return "vertex coordinate not finite";
     const int ne = 3 * nf;
     M.nv = nv;
     M.nf = nf;

@@ -1,13 +1,5 @@
 // Per-particle device operations shared by the force, integrator and fused
 // update kernels: the pair potentials, the force sum over a neighbour row,
-// One atomic add per wavefront: the lanes' values are summed by shuffles
-// first, so that a grid's counts do not serialise on one address. Every lane
-// of the wavefront must call it (lane = threadIdx.x mod 64).
-__device__ inline void wave_atomic_add(unsigned long long *p, unsigned long long v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
-    if ((threadIdx.x & 63) == 0 && v) atomicAdd(p, v);
-}
-
 // Philox4x32-10 noise and the displacement of each integrator.
 #pragma once
 #include <cmath>
@@ -15,6 +7,14 @@ __device__ inline void wave_atomic_add(unsigned long long *p, unsigned long long
 #include "gsim_internal.h"
 
 namespace gsim {
+
+// One atomic add per wavefront: the lanes' values are summed by shuffles
+// first, so that a grid's counts do not serialise on one address. Every lane
+// of the wavefront must call it (lane = threadIdx.x mod 64).
+__device__ inline void wave_atomic_add(unsigned long long *p, unsigned long long v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    if ((threadIdx.x & 63) == 0 && v) atomicAdd(p, v);
+}
 
 // U(d) and dU/dd. 0 harmonic: U = (k/2)(1 - d/sigma)^2 for d < sigma;
 // 1 coulomb: U = k/d; 2 gaussian: U = k exp(-d^2 / (2 sigma^2)) (Sec. 2.1).

@@ -8,7 +8,8 @@
 // vertex leaves along the straightest direction (Polthier-Schmies: equal
 // angle on both sides, i.e. half the vertex's angle sum). At a boundary edge
 // the remaining displacement is reflected in the face plane; at a boundary
-// vertex it is reversed.
+// vertex it is reversed. A particle whose displacement or velocity is not
+// finite is left where it is and flagged.
 //
 // One lane per particle, FP64 throughout; the face-crossing loop is
 // latency-bound on the face/vertex records, which stay in L2.
@@ -38,13 +39,21 @@ __device__ inline d3 cross(d3 a, d3 b) { return {a.y * b.z - a.z * b.y, a.z * b.
 __device__ inline d3 unit(d3 a) { return (1.0 / sqrt(dot(a, a))) * a; }
 
 struct WalkCounts {
-    unsigned cross_n, vhit, bhit, cap, near;
+    unsigned cross_n, vhit, bhit, cap, near, nonfinite;
 };
+
+__device__ inline bool finite3(d3 a) { return isfinite(a.x) && isfinite(a.y) && isfinite(a.z); }
 
 // Walk one particle (face f, barycentrics b) by displacement D, carrying the
 // velocity v along (when hv). D and v are projected onto f's plane first.
 __device__ inline void walk_one(const DevMesh &m, int &f, double b[3], d3 D, d3 &v, bool hv, WalkCounts &wc,
                                 uint8_t &fl) {
+    if (!finite3(D) || (hv && !finite3(v))) {
+        // a non-finite force, displacement or velocity: the particle stays
+        wc.nonfinite = 1;
+        fl |= PF_NONFINITE;
+        return;
+    }
     d3 nf = ld3(m.fnrm + 3 * (int64_t)f);
     D = D - dot(D, nf) * nf;
     if (hv) v = v - dot(v, nf) * nf;
@@ -196,11 +205,11 @@ __device__ inline void walk_one(const DevMesh &m, int &f, double b[3], d3 D, d3 
 
 // The walk of particle i by D (the velocity v carried along) and the store
 // of its new state into (face_o, bary_o, vel_o), which may be the arrays the
-// state was read from.
-__device__ inline void walk_store(const SurfDesc &sd, int i, int f, const double D[3], d3 v, int32_t *face_o,
-                                  double *bary_o, double *vel_o) {
+// state was read from. Returns the particle's PF_* flags.
+__device__ inline uint8_t walk_store(const SurfDesc &sd, int i, int f, const double D[3], d3 v, int32_t *face_o,
+                                     double *bary_o, double *vel_o) {
     double b[3] = {sd.bary[3 * i], sd.bary[3 * i + 1], sd.bary[3 * i + 2]};
-    WalkCounts wc = {0, 0, 0, 0, 0};
+    WalkCounts wc = {0, 0, 0, 0, 0, 0};
     uint8_t fl = 0;
     walk_one(sd.m, f, b, d3{D[0], D[1], D[2]}, v, true, wc, fl);
     face_o[i] = f;
@@ -211,14 +220,16 @@ __device__ inline void walk_store(const SurfDesc &sd, int i, int f, const double
     vel_o[3 * i + 1] = v.y;
     vel_o[3 * i + 2] = v.z;
     if (sd.wflags) sd.wflags[i] = fl;
+    return fl;
 }
 
 // One time step of particle i from its force F (Sec. 2.1 integrators other
 // than FIRE): overdamped or Brownian displacement, or velocity Verlet in
 // leapfrog form (unit masses: the stored velocity is v_{k-1/2}; kick by
-// dt F(x_k), drift by dt v_{k+1/2}); then the walk.
-__device__ inline void move_particle(const SurfDesc &sd, int i, const double F[3], int32_t *face_o, double *bary_o,
-                                     double *vel_o) {
+// dt F(x_k), drift by dt v_{k+1/2}); then the walk. Returns the particle's
+// PF_* flags.
+__device__ inline uint8_t move_particle(const SurfDesc &sd, int i, const double F[3], int32_t *face_o,
+                                        double *bary_o, double *vel_o) {
     const int f = sd.face[i];
     d3 v = ld3(sd.vel + 3 * (int64_t)i);
     double D[3];
@@ -230,7 +241,7 @@ __device__ inline void move_particle(const SurfDesc &sd, int i, const double F[3
     } else {
         displacement(sd.m, f, i, F, sd.ikind, sd.dt, sd.mobility, sd.kT, sd.friction, sd.seed, *sd.step, D);
     }
-    walk_store(sd, i, f, D, v, face_o, bary_o, vel_o);
+    return walk_store(sd, i, f, D, v, face_o, bary_o, vel_o);
 }
 
 }  // namespace gsim

@@ -16,17 +16,20 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "_libgsim.so")
 
-OK, E_ARG, E_MESH, E_OOM, E_CAPACITY, E_DEVICE, E_STATE, E_LIMIT = 0, -1, -2, -3, -4, -5, -6, -7
+OK, E_ARG, E_MESH, E_OOM, E_CAPACITY, E_DEVICE, E_STATE, E_LIMIT, E_NONFINITE = 0, -1, -2, -3, -4, -5, -6, -7, -8
 FP64, FP32_MIXED = 0, 1
 POT = {"harmonic": 0, "coulomb": 1, "gaussian": 2}
 INTEG = {"overdamped": 0, "brownian": 1, "fire": 2, "verlet": 3}
 PAIR_TIE, PAIR_ZERO, PAIR_GUARD = 1, 2, 4
+PF_VERTEX, PF_NEAR_VERTEX, PF_CAP, PF_BOUNDARY, PF_NONFINITE = 1, 2, 4, 8, 16
 
 EXPORTS = ["gsim_create", "gsim_destroy", "gsim_last_error", "gsim_synchronize", "gsim_mesh_upload",
            "gsim_mesh_info_get", "gsim_particles_set", "gsim_particles_get", "gsim_particles_set_dev",
            "gsim_particles_get_dev", "gsim_geodesic_pairs", "gsim_compute_forces", "gsim_displace_on_surface",
            "gsim_step", "gsim_timing_enable", "gsim_timing_get", "gsim_counters_get", "gsim_tune_set",
-           "gsim_source_profile", "gsim_step_batched", "gsim_autotune", "gsim_voronoi_neighbours"]
+           "gsim_source_profile", "gsim_step_batched", "gsim_autotune", "gsim_voronoi_neighbours",
+           "gsim_geodesic_pairs_dev", "gsim_compute_forces_dev", "gsim_displace_on_surface_dev",
+           "gsim_particle_flags", "gsim_particle_flags_dev"]
 
 
 class GsimError(RuntimeError):
@@ -59,7 +62,7 @@ class IntegratorT(C.Structure):
 
 class WalkStatsT(C.Structure):
     _fields_ = [("crossings", C.c_int64), ("vertex_hits", C.c_int64), ("boundary_hits", C.c_int64),
-                ("cap_hits", C.c_int64), ("near_vertex", C.c_int64)]
+                ("cap_hits", C.c_int64), ("near_vertex", C.c_int64), ("nonfinite", C.c_int64)]
 
 
 _lib = None
@@ -73,6 +76,15 @@ def load(path: str = LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise RuntimeError(f"gsim HIP library not built: {path} is missing")
+    # PyTorch ships its own HIP runtime under the same soname as the system
+    # one. Loaded first, it is the runtime this library binds to as well;
+    # loaded after the library has started the system runtime, it brings a
+    # second runtime into the process and sees no GPU. So torch, when it is
+    # installed, goes first.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = C.CDLL(path)
     V = C.c_void_p
     sig = {
@@ -87,7 +99,12 @@ def load(path: str = LIB_PATH):
         "gsim_particles_set_dev": ([V, C.c_int32, C.c_int32, V, V, V], C.c_int),
         "gsim_particles_get_dev": ([V, C.c_int32, V, V, V], C.c_int),
         "gsim_geodesic_pairs": ([V, C.c_int32, C.c_double, C.POINTER(PairsT)], C.c_int),
+        "gsim_geodesic_pairs_dev": ([V, C.c_int32, C.c_double, C.POINTER(PairsT)], C.c_int),
         "gsim_compute_forces": ([V, C.c_int32, C.POINTER(PotentialT), V, V], C.c_int),
+        "gsim_compute_forces_dev": ([V, C.c_int32, C.POINTER(PotentialT), V, V], C.c_int),
+        "gsim_displace_on_surface_dev": ([V, C.c_int32, V, C.c_int, C.POINTER(WalkStatsT)], C.c_int),
+        "gsim_particle_flags": ([V, C.c_int32, V], C.c_int),
+        "gsim_particle_flags_dev": ([V, C.c_int32, V], C.c_int),
         "gsim_voronoi_neighbours": ([V, C.c_int32, V, V, C.c_int64, V], C.c_int),
         "gsim_displace_on_surface": ([V, C.c_int32, V, C.c_int, C.POINTER(WalkStatsT)], C.c_int),
         "gsim_step": ([V, C.c_int32, C.POINTER(PotentialT), C.POINTER(IntegratorT), C.c_int32], C.c_int),
@@ -113,6 +130,11 @@ def _ptr(a):
     if hasattr(a, "data_ptr"):
         return C.c_void_p(a.data_ptr())
     return a.ctypes.data_as(C.c_void_p)
+
+
+def _walk_stats(ws: WalkStatsT) -> dict:
+    return dict(crossings=ws.crossings, vertex_hits=ws.vertex_hits, boundary_hits=ws.boundary_hits,
+                cap_hits=ws.cap_hits, near_vertex=ws.near_vertex, nonfinite=ws.nonfinite)
 
 
 def potential(kind="harmonic", k=1.0, sigma=1.0, cutoff=None) -> PotentialT:
@@ -223,6 +245,38 @@ class Context:
             return dict(off=off, nbr=nbr[:P], dist=dist[:P], tan=tan[:P], flags=flags[:P])
         raise GsimError(E_CAPACITY, "pair buffer sizing failed")
 
+    def geodesic_pairs_dev(self, mid, cutoff, off, nbr, dist, tan, flags=None) -> int:
+        """The pairs into device tensors (off[n+1] int64, nbr int32, dist
+        float64, tan [cap][3] float64, flags uint8), ordered on the context's
+        stream; returns the pair count (GsimError E_CAPACITY, with the count
+        in its message, when the tensors are too small)."""
+        pt = PairsT(int(nbr.shape[0]), 0, off.data_ptr(), nbr.data_ptr(), dist.data_ptr(), tan.data_ptr(),
+                    None if flags is None else flags.data_ptr())
+        self._chk(self.L.gsim_geodesic_pairs_dev(self.h, mid, float(cutoff), C.byref(pt)))
+        return int(pt.count)
+
+    def compute_forces_dev(self, mid, pot: PotentialT, force, energy=None):
+        """Forces into a device tensor force[n][3] (float64) and the energy
+        into energy[1] (optional), on the context's stream."""
+        self._chk(self.L.gsim_compute_forces_dev(self.h, mid, C.byref(pot), _ptr(force), _ptr(energy)))
+
+    def displace_on_surface_dev(self, mid, disp, transport_velocity=True) -> dict:
+        """The shift by a device tensor disp[n][3] (float64)."""
+        ws = WalkStatsT()
+        self._chk(self.L.gsim_displace_on_surface_dev(self.h, mid, _ptr(disp), int(bool(transport_velocity)),
+                                                      C.byref(ws)))
+        return _walk_stats(ws)
+
+    def particle_flags(self, mid):
+        """GSIM_PF_* bits of each particle from the last walk, step or force
+        call on the mesh."""
+        out = np.empty(self._n[mid], np.uint8)
+        self._chk(self.L.gsim_particle_flags(self.h, mid, _ptr(out)))
+        return out
+
+    def particle_flags_dev(self, mid, out):
+        self._chk(self.L.gsim_particle_flags_dev(self.h, mid, _ptr(out)))
+
     def compute_forces(self, mid, pot: PotentialT):
         n = self._n[mid]
         F = np.empty((n, 3))
@@ -246,8 +300,7 @@ class Context:
         disp = np.ascontiguousarray(disp, np.float64)
         ws = WalkStatsT()
         self._chk(self.L.gsim_displace_on_surface(self.h, mid, _ptr(disp), int(bool(transport_velocity)), C.byref(ws)))
-        return dict(crossings=ws.crossings, vertex_hits=ws.vertex_hits, boundary_hits=ws.boundary_hits,
-                    cap_hits=ws.cap_hits, near_vertex=ws.near_vertex)
+        return _walk_stats(ws)
 
     def step(self, mid, pot: PotentialT, integ: IntegratorT, nsteps: int = 1):
         self._chk(self.L.gsim_step(self.h, mid, C.byref(pot), C.byref(integ), int(nsteps)))
@@ -297,8 +350,8 @@ class Context:
         return out
 
     def counters(self) -> dict:
-        c = np.zeros(11, np.int64)
+        c = np.zeros(12, np.int64)
         self._chk(self.L.gsim_counters_get(self.h, _ptr(c)))
         return dict(windows=int(c[0]), pruned=int(c[1]), launches=int(c[2]), stale=int(c[3]), guard_sources=int(c[4]),
                     nbr_pairs=int(c[5]), limited=int(c[6]), cum_pairs=int(c[7]), cum_windows=int(c[8]),
-                    cum_passes=int(c[9]), max_stack_depth=int(c[10]))
+                    cum_passes=int(c[9]), max_stack_depth=int(c[10]), nonfinite=int(c[11]))
