@@ -15,8 +15,12 @@ import pytest
 from paper_2404_19751_amd import workloads as W
 from tests.test_gpu_fp32 import compare32
 from tests.test_gpu_parity import compare_pairs
+from tests.util import oracle_band
 
 pytestmark = pytest.mark.gpu
+# sampled source rows of the N = 2000 all-pairs workloads: 64 sources spread
+# over the whole index range (the first and the last included)
+C5_ROWS = np.unique(np.linspace(0, 1999, 64).round().astype(np.int32))
 
 
 def log(*a):
@@ -52,7 +56,7 @@ def test_allpairs_small(orc, name, mk, n, prec):
         g = ctx.geodesic_pairs(mid, math.inf)
         cnt = ctx.counters()
         assert cnt["limited"] == 0, cnt
-        o = orc.geodesic_pairs(orc.OracleMesh(m.V, m.T), f, b, math.inf)
+        o = orc.geodesic_pairs(orc.OracleMesh(m.V, m.T), f, b, math.inf, **oracle_band(prec))
         assert len(o.dist) == n * (n - 1)
         if prec == "fp64":
             err = compare_pairs(g, o, W.mean_edge_length(m), label=name)
@@ -87,7 +91,7 @@ def test_allpairs_many_bend_vertices(orc, name, mk, n, prec):
         g = ctx.geodesic_pairs(mid, math.inf)
         cnt = ctx.counters()
         assert cnt["limited"] == 0, cnt
-        o = orc.geodesic_pairs(orc.OracleMesh(m.V, m.T), f, b, math.inf)
+        o = orc.geodesic_pairs(orc.OracleMesh(m.V, m.T), f, b, math.inf, **oracle_band(prec))
         if prec == "fp64":
             err = compare_pairs(g, o, W.mean_edge_length(m), label=name)
         else:
@@ -100,8 +104,8 @@ def test_allpairs_many_bend_vertices(orc, name, mk, n, prec):
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 @pytest.mark.parametrize("name", ["c5a", "c5b"])
 def test_c5_sampled_rows(orc, name, prec):
-    """Full-size all-pairs launch (N = 2000 on 81,920 faces); rows of sampled
-    sources against the oracle's rows for the same sources."""
+    """Full-size all-pairs launch (N = 2000 on 81,920 faces); the rows of 64
+    sampled sources against the oracle's rows for the same sources."""
     w = W.workload(name)
     ctx = _ctx(prec)
     try:
@@ -116,8 +120,9 @@ def test_c5_sampled_rows(orc, name, prec):
         assert cnt["limited"] == 0
         n = len(w.face)
         assert len(g["dist"]) == n * (n - 1)
-        srcs = np.array([0, 517, 1203, 1999], np.int32)
-        o = orc.geodesic_pairs(orc.OracleMesh(w.mesh.V, w.mesh.T), w.face, w.bary, math.inf, sources=srcs)
+        srcs = C5_ROWS
+        o = orc.geodesic_pairs(orc.OracleMesh(w.mesh.V, w.mesh.T), w.face, w.bary, math.inf, sources=srcs,
+                               **oracle_band(prec))
         # the GPU rows of the sampled sources, as a pairs structure of their own
         sub = {"off": [0], "nbr": [], "dist": [], "tan": [], "flags": []}
         for i in srcs:
@@ -248,7 +253,7 @@ def test_allpairs_5000_particles(orc, prec):
         assert cnt["limited"] == 0
         assert len(g["dist"]) == 5000 * 4999
         srcs = np.array([0, 4100, 4999], np.int32)
-        o = orc.geodesic_pairs(orc.OracleMesh(m.V, m.T), f, b, math.inf, sources=srcs)
+        o = orc.geodesic_pairs(orc.OracleMesh(m.V, m.T), f, b, math.inf, sources=srcs, **oracle_band(prec))
         sub = {"off": [0], "nbr": [], "dist": [], "tan": [], "flags": []}
         for i in srcs:
             a, bb = g["off"][i], g["off"][i + 1]

@@ -148,8 +148,11 @@ def c3():
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_c3_batch_step(c3, orc, prec):
     """The 16-surface batch (icospheres L3-L6 and 12 tori, 15,033 particles):
-    one batched step against the oracle's step of every surface (FP64), and
-    the FP32-mixed pairs of every surface against the oracle's."""
+    one batched step against the oracle's step of every surface. FP64: faces
+    bit-exact, barycentrics within 1e-11. FP32-mixed: the pairs of every
+    surface against the oracle's (tie band 1e-5), and the step of every
+    particle without a near-tie pair on the oracle's face with barycentrics
+    within the force tolerance's bound."""
     gs = _gs()
     ctx = gs.Context(0, prec)
     try:
@@ -168,14 +171,32 @@ def test_c3_batch_step(c3, orc, prec):
                 assert np.abs(bg[ok] - bo[ok]).max() < 1e-11, w.name
         else:
             from tests.test_gpu_fp32 import compare32
+            from tests.util import oracle_band, step_within_force_bound
+            gp = []
             for k, w in enumerate(c3):
                 om = orc.OracleMesh(w.mesh.V, w.mesh.T)
                 g = ctx.geodesic_pairs(mids[k], w.potential["cutoff"])
-                o = orc.geodesic_pairs(om, w.face, w.bary, w.potential["cutoff"])
+                o = orc.geodesic_pairs(om, w.face, w.bary, w.potential["cutoff"], **oracle_band("fp32"))
                 compare32(g, o, w.mean_edge, w.name)
-            log("[gpu-batch] c3 fp32: 3 batched steps")
-            ctx.step_batched(mids, pots, igs, 3)
+                gp.append((g, o))
+            log("[gpu-batch] c3 fp32: one batched step")
+            ctx.step_batched(mids, pots, igs, 1)
             assert ctx.counters()["limited"] == 0
+            tot, tot_same, worst = 0, 0, 0.0
+            for k, w in enumerate(c3):
+                om = orc.OracleMesh(w.mesh.V, w.mesh.T)
+                fo, bo, info = orc.step(om, w.face, w.bary, w.potential, w.integrator, 0)
+                fg, bg, _, _ = ctx.particles_get(mids[k])
+                g, o = gp[k]
+                ig = w.integrator
+                n_cmp, n_same, ratio = step_within_force_bound(w.mesh.V, w.mesh.T, o, g, w.potential,
+                                                               ig["mobility"] * ig["dt"], 1e-5, fo, bo, fg, bg,
+                                                               info["walk_flags"])
+                assert n_same == n_cmp and ratio <= 1.0, (w.name, n_cmp, n_same, ratio)
+                tot, tot_same, worst = tot + n_cmp, tot_same + n_same, max(worst, ratio)
+            log(f"[gpu-batch] c3 fp32 step: {tot} particles compared, all on the oracle's face, "
+                f"barycentric error / bound {worst:.3f}")
+            assert tot > 0.5 * sum(len(w.face) for w in c3)
     finally:
         ctx.close()
 

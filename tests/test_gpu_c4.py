@@ -14,6 +14,7 @@ import pytest
 from paper_2404_19751_amd import workloads as W
 from tests.test_gpu_fp32 import compare32
 from tests.test_gpu_parity import compare_pairs
+from tests.util import oracle_band, step_within_force_bound
 
 pytestmark = pytest.mark.gpu
 
@@ -29,8 +30,9 @@ def c4(orc):
     om = orc.OracleMesh(w.mesh.V, w.mesh.T)
     log(f"[gpu-c4] oracle pairs: nf={w.mesh.nf} n={len(w.face)} cutoff={w.potential['cutoff']:.5f}")
     o = orc.geodesic_pairs(om, w.face, w.bary, w.potential["cutoff"])
+    o32 = orc.geodesic_pairs(om, w.face, w.bary, w.potential["cutoff"], **oracle_band("fp32"))
     log(f"[gpu-c4] oracle pairs done: {len(o.dist)} pairs")
-    return w, om, o
+    return w, om, o, o32
 
 
 def _ctx(prec):
@@ -40,7 +42,7 @@ def _ctx(prec):
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_c4_pairs_full(c4, prec):
-    w, om, o = c4
+    w, om, o, o32 = c4
     ctx = _ctx(prec)
     try:
         mid = ctx.mesh_upload(w.mesh.V, w.mesh.T)
@@ -55,7 +57,7 @@ def test_c4_pairs_full(c4, prec):
             err = compare_pairs(g, o, w.mean_edge, label="c4")
             log(f"[gpu-c4] fp64: pairs={len(o.dist)} max_rel_err={err:.3e} {cnt}")
         else:
-            d_err, t_err = compare32(g, o, w.mean_edge, "c4")
+            d_err, t_err = compare32(g, o32, w.mean_edge, "c4")
             log(f"[gpu-c4] fp32: pairs={len(o.dist)} dist_err={d_err:.2e} tan_err={t_err:.2e} {cnt}")
     finally:
         ctx.close()
@@ -66,7 +68,7 @@ def test_c4_brownian_step_and_stage_parity(c4, orc):
     then 20 more GPU steps and a stage-parity check of the pairs on the state
     they reach (bit-exact neighbour sets from the same FP64 state)."""
     from paper_2404_19751_amd import gsim
-    w, om, o = c4
+    w, om, o, _ = c4
     ctx = _ctx("fp64")
     try:
         mid = ctx.mesh_upload(w.mesh.V, w.mesh.T)
@@ -94,5 +96,31 @@ def test_c4_brownian_step_and_stage_parity(c4, orc):
         o2 = orc.geodesic_pairs(om, fg, bg, p["cutoff"])
         err = compare_pairs(g, o2, w.mean_edge, label="c4-step21")
         log(f"[gpu-c4] stage parity after 21 steps: pairs={len(o2.dist)} err={err:.2e}")
+    finally:
+        ctx.close()
+
+
+def test_c4_fp32_step_within_force_bound(c4, orc):
+    """One FP32-mixed Brownian step against the oracle's FP64 step, for every
+    particle without a near-tie pair: same face, barycentrics within what the
+    force tolerance allows (the noise is the same on both sides)."""
+    from paper_2404_19751_amd import gsim
+    w, om, _, o32 = c4
+    ctx = _ctx("fp32")
+    try:
+        mid = ctx.mesh_upload(w.mesh.V, w.mesh.T)
+        ctx.particles_set(mid, w.face, w.bary)
+        p, ig = w.potential, w.integrator
+        g = ctx.geodesic_pairs(mid, p["cutoff"])
+        log("[gpu-c4] fp32: one Brownian step")
+        ctx.step(mid, gsim.potential(p["kind"], p["k"], p["sigma"], p["cutoff"]),
+                 gsim.integrator(ig["kind"], ig["dt"], 1.0, ig["kT"], ig["friction"], ig["seed"]), 1)
+        fg, bg, _, _ = ctx.particles_get(mid)
+        fo, bo, info = orc.step(om, w.face, w.bary, p, ig, 0)
+        n_cmp, n_same, ratio = step_within_force_bound(w.mesh.V, w.mesh.T, o32, g, p, ig["dt"] / ig["friction"], 1e-5,
+                                                       fo, bo, fg, bg, info["walk_flags"])
+        log(f"[gpu-c4] fp32 step: {n_cmp} particles compared, {n_same} on the oracle's face, "
+            f"barycentric error / bound {ratio:.3f}")
+        assert n_cmp > 0.5 * len(w.face) and n_same == n_cmp and ratio <= 1.0
     finally:
         ctx.close()

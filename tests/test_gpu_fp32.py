@@ -8,6 +8,7 @@ import numpy as np
 import pytest
 
 from paper_2404_19751_amd import workloads as W
+from tests.util import CONE32, TIE32, oracle_band, tangent_errors
 
 pytestmark = pytest.mark.gpu
 RTOL32 = 1e-5
@@ -27,17 +28,21 @@ def ctx32():
 
 
 def compare32(g, o, lbar, label):
+    """FP32-mixed pairs against the oracle run with the FP32 tie sets
+    (tie_rel and cone_slack 1e-5): bit-exact neighbour sets; distances within
+    1e-5 relative; log-map tangents within 1e-5, a pair flagged as a near-tie
+    by either side against the nearest direction of the oracle's tie set."""
+    assert o.tie_rel >= TIE32 and o.cone_slack >= CONE32, f"{label}: oracle tie sets narrower than the FP32 ones"
     assert np.array_equal(g["off"], o.off), f"{label}: neighbour counts differ"
     assert np.array_equal(g["nbr"], o.nbr), f"{label}: neighbour sets differ"
     rel = np.abs(g["dist"] - o.dist) / o.dist
     assert rel.max(initial=0) <= RTOL32, f"{label}: dist rel err {rel.max()}"
-    scale = np.maximum(o.dist, 1e-3 * lbar)
-    err = np.linalg.norm(o.dist[:, None] * (g["tan"] - o.tan), axis=1) / scale
-    # a pair flagged as a near-tie (gap below 1e-4 d) may take the other direction
-    amb = ((g["flags"] & 1) != 0) | ((o.flags & 1) != 0)
-    print(f"[gpu-fp32] {label}: {amb.sum()} of {len(amb)} pairs flagged as near-ties", flush=True)
-    assert err[~amb].max(initial=0) <= RTOL32, f"{label}: tangent err {err[~amb].max()}"
-    return rel.max(initial=0), err[~amb].max(initial=0)
+    err, tie = tangent_errors(g, o, lbar)
+    print(f"[gpu-fp32] {label}: {tie.sum()} of {len(tie)} pairs flagged as near-ties, their tangent err "
+          f"{err[tie].max(initial=0):.2e}", flush=True)
+    assert err[~tie].max(initial=0) <= RTOL32, f"{label}: tangent err {err[~tie].max()}"
+    assert err[tie].max(initial=0) <= RTOL32, f"{label}: tie tangent err {err[tie].max()}"
+    return rel.max(initial=0), err.max(initial=0)
 
 
 @pytest.mark.parametrize("name", ["c1", "c2"])
@@ -48,7 +53,7 @@ def test_pairs_fp32(ctx32, orc, name):
     ctx32.particles_set(mid, w.face, w.bary)
     log(f"[gpu-fp32] {name} pairs")
     g = ctx32.geodesic_pairs(mid, w.potential["cutoff"])
-    o = orc.geodesic_pairs(om, w.face, w.bary, w.potential["cutoff"])
+    o = orc.geodesic_pairs(om, w.face, w.bary, w.potential["cutoff"], **oracle_band("fp32"))
     d_err, t_err = compare32(g, o, w.mean_edge, name)
     log(f"[gpu-fp32] {name}: pairs={len(o.dist)} dist_err={d_err:.2e} tan_err={t_err:.2e} {ctx32.counters()}")
 
@@ -65,7 +70,7 @@ def test_small_fp32(ctx32, orc, name, mk, n, cut):
     mid = ctx32.mesh_upload(m.V, m.T)
     ctx32.particles_set(mid, f, b)
     g = ctx32.geodesic_pairs(mid, cut)
-    o = orc.geodesic_pairs(om, f, b, cut)
+    o = orc.geodesic_pairs(om, f, b, cut, **oracle_band("fp32"))
     compare32(g, o, W.mean_edge_length(m), name)
 
 

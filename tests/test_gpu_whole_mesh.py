@@ -12,6 +12,7 @@ import pytest
 
 from paper_2404_19751_amd import workloads as W
 from tests.test_gpu_fp32 import compare32
+from tests.util import oracle_band
 from tests.test_gpu_parity import compare_pairs
 
 pytestmark = pytest.mark.gpu
@@ -34,13 +35,15 @@ def torus_case(orc):
     m = W.torus(3.0, 1.0, 48, 16)
     f, b = W.random_particles(m.nf, 300, 37)
     cut = 5.0
-    o = orc.geodesic_pairs(orc.OracleMesh(m.V, m.T), f, b, cut)
-    return m, f, b, cut, o
+    om = orc.OracleMesh(m.V, m.T)
+    o = orc.geodesic_pairs(om, f, b, cut)
+    o32 = orc.geodesic_pairs(om, f, b, cut, **oracle_band("fp32"))
+    return m, f, b, cut, o, o32
 
 
 @pytest.mark.parametrize("prec", ["fp64", "fp32"])
 def test_whole_mesh_cutoff_matches_oracle(torus_case, prec):
-    m, f, b, cut, o = torus_case
+    m, f, b, cut, o, o32 = torus_case
     ctx = _ctx(prec, True)
     try:
         mid = ctx.mesh_upload(m.V, m.T)
@@ -53,7 +56,7 @@ def test_whole_mesh_cutoff_matches_oracle(torus_case, prec):
         if prec == "fp64":
             err = compare_pairs(g, o, W.mean_edge_length(m), label="torus_a3")
         else:
-            err, _ = compare32(g, o, W.mean_edge_length(m), "torus_a3")
+            err, _ = compare32(g, o32, W.mean_edge_length(m), "torus_a3")
         log(f"[gpu-whole] torus a3 {prec}: {len(o.dist)} pairs, err {err:.2e}, counters {cnt}")
     finally:
         ctx.close()
@@ -63,7 +66,7 @@ def test_cutoff_kernel_reports_the_limit(torus_case):
     """The same case on the cutoff kernel exceeds its per-source candidate
     rows: a limit error, not a partial result."""
     from paper_2404_19751_amd import gsim
-    m, f, b, cut, o = torus_case
+    m, f, b, cut, o, _ = torus_case
     ctx = _ctx("fp64", False)
     try:
         mid = ctx.mesh_upload(m.V, m.T)
@@ -112,7 +115,7 @@ def test_whole_mesh_agrees_with_cutoff_kernel():
 def test_whole_mesh_fp32_guard_band(torus_case, orc):
     """Cutoffs a hair above and below a true pair distance in FP32-mixed
     mode: the FP64 recompute decides membership exactly as the oracle does."""
-    m, f, b, cut, o = torus_case
+    m, f, b, cut, o, _ = torus_case
     om = orc.OracleMesh(m.V, m.T)
     d = float(np.sort(o.dist)[len(o.dist) // 2])
     ctx = _ctx("fp32", True)
