@@ -243,6 +243,19 @@ gsim_status gsim_displace_on_surface(gsim_ctx *ctx, int32_t mesh_id, const doubl
  * place (no staging copy). */
 gsim_status gsim_displace_on_surface_dev(gsim_ctx *ctx, int32_t mesh_id, const double *disp_dev,
                                          int transport_velocity, gsim_walk_stats *stats);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid it): the walk of
+ * gsim_displace_on_surface_dev without any allocation. It reads disp_dev and
+ * moves the particles already set on the mesh; flags_dev[n] (device memory,
+ * may be NULL) receives each particle's GSIM_PF_* bits. Its statistics go
+ * through a scratch array of 512 KiB that each GPU holds for the whole
+ * process (one row of counts per 256 particles, summed in a fixed order),
+ * which limits a call to 2,097,152 particles (GSIM_E_LIMIT beyond). Calls on
+ * one GPU share that array: calls that overlap in time on one GPU, from any
+ * context or stream, race and must be ordered by the caller. The result
+ * equals gsim_displace_on_surface_dev's bit for bit. */
+gsim_status gsim_displace_on_surface_noalloc(gsim_ctx *ctx, int32_t mesh_id, const double *disp_dev,
+                                             int transport_velocity, uint8_t *flags_dev, gsim_walk_stats *stats);
 
 /* step: nsteps full time steps on device (prefilter, window propagation,
  * query, forces, integrator, walk); state stays in device memory. The noise

@@ -13,6 +13,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -109,6 +110,39 @@ struct gsim_ctx {
     int graph_steps = 50;  // steps captured per graph (0: no graphs)
     std::map<std::string, GraphRec> graphs;
 };
+
+// ---- scratch of the allocation-free walk (gsim_displace_on_surface_noalloc)
+// One row of 8 walk counts per workgroup of kWalkBlock particles, then the
+// 8 totals: 512 KiB, enough for kNoAllocMaxParticles particles. Every GPU the
+// library runs on holds its own copy until the process ends. Host code never
+// passes the array's name to a kernel (that is a host-side stand-in, not a
+// device address): it uses the address hipGetSymbolAddress gave for the
+// device, looked up once per device when the first context on it is made.
+constexpr int kNoAllocBlocks = 8192;
+constexpr int64_t kNoAllocMaxParticles = (int64_t)kNoAllocBlocks * kWalkBlock;  // 2,097,152
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned long long scratch[8 * (kNoAllocBlocks + 1)];
+static std::mutex g_scratch_mu;
+static unsigned long long *g_scratch[kMaxDevices] = {};
+
+// The device address of `scratch` on `device` (the current device), looked
+// up on the first call for that device.
+static hipError_t scratch_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (g_scratch[device]) return hipSuccess;
+    void *p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch[device] = static_cast<unsigned long long *>(p);
+    return hipSuccess;
+}
+
+static unsigned long long *scratch_of(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    return g_scratch[device];
+}
 
 namespace {
 // Makes the context's device current for one call and gives the caller's
@@ -824,7 +858,7 @@ gsim_status gsim_create(int device, gsim_precision prec, void *hip_stream, gsim_
     if (!c) return GSIM_E_OOM;
     c->device = device;
     c->prec = prec;
-    if (hipSetDevice(device) != hipSuccess) {
+    if (hipSetDevice(device) != hipSuccess || scratch_setup(device) != hipSuccess) {
         delete c;
         return GSIM_E_DEVICE;
     }
@@ -1343,6 +1377,41 @@ gsim_status gsim_displace_on_surface_dev(gsim_ctx *c, int32_t id, const double *
     if (ms->n <= 0) return fail(c, GSIM_E_STATE, "no particles on this mesh");
     try {
         return walk_dev(c, ms, disp, transport_velocity, stats);
+    }
+    GSIM_CATCH(c)
+}
+
+gsim_status gsim_displace_on_surface_noalloc(gsim_ctx *c, int32_t id, const double *disp, int transport_velocity,
+                                             uint8_t *flags, gsim_walk_stats *stats) {
+    DeviceGuard dg(c);
+    MeshState *ms = get_mesh(c, id);
+    if (!ms || !disp) return fail(c, GSIM_E_ARG, "bad arguments");
+    if (ms->n <= 0) return fail(c, GSIM_E_STATE, "no particles on this mesh");
+    if (ms->n > kNoAllocMaxParticles)
+        return fail(c, GSIM_E_LIMIT, "the allocation-free walk takes at most " + std::to_string(kNoAllocMaxParticles) +
+                                         " particles per call (" + std::to_string(ms->n) + " on this mesh)");
+    unsigned long long *part = scratch_of(c->device);
+    if (!part) return fail(c, GSIM_E_STATE, "walk scratch not set up on this device");
+    try {
+        // no allocation: the context's particle state, the caller's buffers
+        // and the device's scratch array only; every row of the scratch the
+        // kernels read is written by this call first
+        hipStream_t s = c->stream;
+        unsigned long long *tot = part + 8 * (int64_t)kNoAllocBlocks;
+        HIPCHK(c, launch_walk_blocks(ms->dm, ms->n, ms->face, ms->bary, disp, transport_velocity ? ms->vel : nullptr,
+                                     flags, part, tot, s));
+        unsigned long long h[8];
+        HIPCHK(c, hipMemcpyAsync(h, tot, sizeof(h), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        if (stats) {
+            stats->crossings = (int64_t)h[0];
+            stats->vertex_hits = (int64_t)h[1];
+            stats->boundary_hits = (int64_t)h[2];
+            stats->cap_hits = (int64_t)h[3];
+            stats->near_vertex = (int64_t)h[4];
+            stats->nonfinite = (int64_t)h[5];
+        }
+        return nonfinite_status(c, h[5]);
     }
     GSIM_CATCH(c)
 }

@@ -342,5 +342,12 @@ hipError_t launch_integrate(const DevMesh &m, int n, const int32_t *face, const 
 // velocity was not finite; flags[n] (may be null) the PF_* bits.
 hipError_t launch_walk(const DevMesh &m, int n, int32_t *face, double *bary, const double *disp, double *vel,
                        unsigned long long *stats, uint8_t *flags, hipStream_t s);
+// The same walk with its statistics reduced without atomics: one row of 8
+// counts per workgroup of kWalkBlock particles in part[ceil(n / kWalkBlock)][8],
+// then their column sums, in a fixed order, in tot[8]. Nothing needs
+// clearing beforehand; flags may be null.
+constexpr int kWalkBlock = 256;
+hipError_t launch_walk_blocks(const DevMesh &m, int n, int32_t *face, double *bary, const double *disp, double *vel,
+                              uint8_t *flags, unsigned long long *part, unsigned long long *tot, hipStream_t s);
 
 }  // namespace gsim

@@ -46,6 +46,70 @@ __global__ __launch_bounds__(128) void k_walk(DevMesh m, int n, int32_t *__restr
     flush_counts(wc, stats);
 }
 
+// The walk of every particle with its statistics in per-workgroup partial
+// rows instead of atomics: part[blockIdx][0..7] = crossings, vertex hits,
+// boundary hits, cap hits, near-vertex passes, non-finite particles, 0, 0.
+// Every row is written, so nothing needs clearing beforehand.
+__global__ __launch_bounds__(kWalkBlock) void k_walk_blocks(DevMesh m, int n, int32_t *__restrict__ face,
+                                                           double *__restrict__ bary, const double *__restrict__ disp,
+                                                           double *__restrict__ vel, uint8_t *__restrict__ flags,
+                                                           unsigned long long *__restrict__ part) {
+    __shared__ unsigned long long sh[6][kWalkBlock / 64];
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    WalkCounts wc = {0, 0, 0, 0, 0, 0};
+    if (i < n) {
+        int f = face[i];
+        double b[3] = {bary[3 * i], bary[3 * i + 1], bary[3 * i + 2]};
+        const bool hv = vel != nullptr;
+        d3 v = hv ? ld3(vel + 3 * (int64_t)i) : d3{0, 0, 0};
+        uint8_t fl = 0;
+        walk_one(m, f, b, ld3(disp + 3 * (int64_t)i), v, hv, wc, fl);
+        face[i] = f;
+        bary[3 * i] = b[0];
+        bary[3 * i + 1] = b[1];
+        bary[3 * i + 2] = b[2];
+        if (hv) {
+            vel[3 * i] = v.x;
+            vel[3 * i + 1] = v.y;
+            vel[3 * i + 2] = v.z;
+        }
+        if (flags) flags[i] = fl;
+    }
+    unsigned long long c[6] = {wc.cross_n, wc.vhit, wc.bhit, wc.cap, wc.near, wc.nonfinite};
+    const int wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) {
+        unsigned long long x = c[k];
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o);
+        if ((threadIdx.x & 63) == 0) sh[k][wv] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x < 8) {
+        unsigned long long t = 0;
+        if (threadIdx.x < 6)
+            for (int w = 0; w < kWalkBlock / 64; ++w) t += sh[threadIdx.x][w];
+        part[8 * (int64_t)blockIdx.x + threadIdx.x] = t;
+    }
+}
+
+// tot[0..7] = the column sums of part[nb][8], in a fixed order.
+__global__ __launch_bounds__(256) void k_walk_total(const unsigned long long *__restrict__ part, int nb,
+                                                   unsigned long long *__restrict__ tot) {
+    __shared__ unsigned long long sh[8][256];
+    for (int k = 0; k < 8; ++k) {
+        unsigned long long t = 0;
+        for (int r = threadIdx.x; r < nb; r += 256) t += part[8 * (int64_t)r + k];
+        sh[k][threadIdx.x] = t;
+    }
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o)
+            for (int k = 0; k < 8; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x < 8) tot[threadIdx.x] = sh[threadIdx.x][0];
+}
+
 // One full particle update of a time step, fused: the force from the
 // particle's neighbour row (Sec. 3.1 force sum), the displacement of the
 // integrator (Sec. 2.1), and the walk (Sec. 3.2). Rows hold only distances
@@ -118,6 +182,15 @@ hipError_t launch_update_batch(const SurfDesc *desc, const BatchIdx &bi, int blo
     if (total <= 0) return hipSuccess;
     if (block != 64 && block != 128 && block != 256) block = 128;
     hipLaunchKernelGGL(k_update_batch, dim3((total + block - 1) / block), dim3(block), 0, s, desc, bi, ctr);
+    return hipGetLastError();
+}
+
+hipError_t launch_walk_blocks(const DevMesh &m, int n, int32_t *face, double *bary, const double *disp, double *vel,
+                              uint8_t *flags, unsigned long long *part, unsigned long long *tot, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const int nb = (n + kWalkBlock - 1) / kWalkBlock;
+    hipLaunchKernelGGL(k_walk_blocks, dim3(nb), dim3(kWalkBlock), 0, s, m, n, face, bary, disp, vel, flags, part);
+    hipLaunchKernelGGL(k_walk_total, dim3(1), dim3(256), 0, s, part, nb, tot);
     return hipGetLastError();
 }
 

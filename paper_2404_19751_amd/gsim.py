@@ -29,7 +29,7 @@ EXPORTS = ["gsim_create", "gsim_destroy", "gsim_last_error", "gsim_synchronize",
            "gsim_step", "gsim_timing_enable", "gsim_timing_get", "gsim_counters_get", "gsim_tune_set",
            "gsim_source_profile", "gsim_step_batched", "gsim_autotune", "gsim_voronoi_neighbours",
            "gsim_geodesic_pairs_dev", "gsim_compute_forces_dev", "gsim_displace_on_surface_dev",
-           "gsim_particle_flags", "gsim_particle_flags_dev"]
+           "gsim_particle_flags", "gsim_particle_flags_dev", "gsim_displace_on_surface_noalloc"]
 
 
 class GsimError(RuntimeError):
@@ -103,6 +103,7 @@ def load(path: str = LIB_PATH):
         "gsim_compute_forces": ([V, C.c_int32, C.POINTER(PotentialT), V, V], C.c_int),
         "gsim_compute_forces_dev": ([V, C.c_int32, C.POINTER(PotentialT), V, V], C.c_int),
         "gsim_displace_on_surface_dev": ([V, C.c_int32, V, C.c_int, C.POINTER(WalkStatsT)], C.c_int),
+        "gsim_displace_on_surface_noalloc": ([V, C.c_int32, V, C.c_int, V, C.POINTER(WalkStatsT)], C.c_int),
         "gsim_particle_flags": ([V, C.c_int32, V], C.c_int),
         "gsim_particle_flags_dev": ([V, C.c_int32, V], C.c_int),
         "gsim_voronoi_neighbours": ([V, C.c_int32, V, V, C.c_int64, V], C.c_int),
@@ -265,6 +266,15 @@ class Context:
         ws = WalkStatsT()
         self._chk(self.L.gsim_displace_on_surface_dev(self.h, mid, _ptr(disp), int(bool(transport_velocity)),
                                                       C.byref(ws)))
+        return _walk_stats(ws)
+
+    def displace_on_surface_noalloc(self, mid, disp, flags=None, transport_velocity=True) -> dict:
+        """The shift by a device tensor disp[n][3] with no device allocation;
+        flags (a uint8 device tensor [n], optional) receives the GSIM_PF_*
+        bits."""
+        ws = WalkStatsT()
+        self._chk(self.L.gsim_displace_on_surface_noalloc(self.h, mid, _ptr(disp), int(bool(transport_velocity)),
+                                                          _ptr(flags), C.byref(ws)))
         return _walk_stats(ws)
 
     def particle_flags(self, mid):
