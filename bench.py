@@ -1,17 +1,23 @@
 """Benchmark: full time steps of the geodesic-interaction hot path on one GPU.
 
-Workload (the bumpy closed surface): icosphere level 5 with the radial map
-r = 1 + 0.1 sin(4 theta) cos(3 phi) (20,480 faces, 4,060 saddle vertices),
-N = 1000 particles (face-uniform, barycentric-uniform, seed 1), harmonic
-repulsion k = 1, sigma = cutoff = 0.15, overdamped dt = 0.01, mobility 1.
-A step is one pass of the whole hot path: Euclidean prefilter, window
-propagation + target query (geodesic pairs), force sum, integrator, walk.
+Default line (the largest single-GPU workload): the Gaussian-bump height
+field on [0,10]^2 (316 x 316 cells split on diagonals, 199,712 faces, open
+boundary), N = 20,000 particles (face-uniform, barycentric-uniform, seed 3),
+harmonic repulsion k = 1, sigma = cutoff = 3 mean edge lengths, Brownian
+dynamics kT = 0.1, friction 1, dt = 0.005. A step is one pass of the whole
+hot path: Euclidean prefilter, window propagation + target query (geodesic
+pairs), force sum, integrator, walk.
 
 Prints ONE JSON line. ``value`` = geodesic neighbour pairs per second over the
-timed steps (inputs resident in device memory); ``particle_steps_per_s`` is
-the second number of the metric. ``roofline`` is for the dominant kernel
-(window propagation), ``cpu_baseline`` times the CPU oracle on a bounded
-sample of the same workload.
+timed FP64 steps (inputs resident in device memory); ``particle_steps_per_s``
+is the second number of the metric; ``fp32`` is the FP32-mixed leg of the
+same workload. ``c3`` holds the batched 16-surface workload (batched
+FP32-mixed against single-surface FP64, the throughput target) and ``c5``
+the all-pairs Coulomb FIRE iteration on 81,920 faces in both precisions,
+each with its own roofline. ``roofline`` is for the dominant kernel (window
+propagation), ``update_roofline`` for the force + integrator + walk kernel,
+and ``cpu_baseline`` times the CPU oracle on a bounded sample of the same
+workload on the host's cores and on one thread.
 """
 from __future__ import annotations
 
@@ -30,6 +36,16 @@ sys.path.insert(0, ROOT)
 METRIC = "geodesic pairs/sec + particle-steps/sec, FP32-mixed vs FP64 on one MI355X at 1e-5 rel err"
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+HBM_PEAK_GBPS = 8000.0
+# algorithmic HBM bytes of one particle's time step in the update kernel
+# (force sum, integrator, walk): its row (count 4 B, then per pair distance
+# 8 B and tangent 24 B), its state read and written (face 4 B + barycentrics
+# 24 B, twice), its velocity read and written (2 x 24 B), and the vertex
+# positions and normal (96 B) of every face the walk visits (the start face
+# and one per edge crossing)
+UPDATE_BYTES_PARTICLE = 4 + 56 + 48 + 96
+UPDATE_BYTES_PAIR = 32
+UPDATE_BYTES_CROSSING = 96
 # algorithmic floating-point work of one window propagation step (C's
 # intercept, two child intervals with their frame changes and lower bounds,
 # the bend-vertex test); divisions and square roots count as one
@@ -43,9 +59,12 @@ WORKLOAD_TEXT = {
           "edges, Brownian kT=0.1 friction=1 dt=0.005",
 }
 
-def pmc_file(precision):
+PMC_NAME = {"c2": "bumpy_sphere_n1000", "c4": "height_field_n20000"}
+
+
+def pmc_file(workload, precision):
     tag = "fp64" if precision == "fp64" else "fp32mixed"
-    return os.path.join(ROOT, "profiles", f"k_geodesic_bumpy_sphere_n1000_{tag}_pmc.json")
+    return os.path.join(ROOT, "profiles", f"k_geodesic_{PMC_NAME.get(workload, workload)}_{tag}_pmc.json")
 
 
 def code_hash(texts):
@@ -61,23 +80,56 @@ def code_hash(texts):
     return h.hexdigest()
 
 
-def measured_traffic(precision):
-    """HBM bytes per k_geodesic launch from the committed counter runs of the
-    bumpy-sphere workload in this precision, or None once the kernel code
-    differs from the one the counters saw."""
+def measured_counters(workload, precision):
+    """The committed counter record of k_geodesic on this workload and
+    precision (HBM traffic per launch, LDS bandwidth, occupancy), or None
+    when there is none or the kernel code differs from the one the counters
+    saw."""
     try:
-        rec = json.load(open(pmc_file(precision)))
+        rec = json.load(open(pmc_file(workload, precision)))
         src = [open(os.path.join(ROOT, f)).read() for f in rec["sources_hashed"]]
-    except (OSError, KeyError):
+    except (OSError, KeyError, ValueError):
         return None
     if code_hash(src) != rec.get("kernel_code_sha256"):
         return None
-    return rec["traffic_bytes_per_launch"]
+    return rec
 
 
-def cpu_baseline(w, budget_s=10.0, max_steps=500):
+def host_cpu():
+    """Cores this process may use and the CPU model (lscpu, else /proc/cpuinfo)."""
+    import subprocess
+    try:
+        nproc = len(os.sched_getaffinity(0))
+    except AttributeError:
+        nproc = os.cpu_count() or 1
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for ln in out.splitlines():
+            if ln.strip().lower().startswith("model name"):
+                model = ln.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if model is None:
+        try:
+            for ln in open("/proc/cpuinfo"):
+                if ln.lower().startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+    return nproc, model
+
+
+def cpu_baseline(w, budget_s=10.0, max_steps=500, single_sources=64):
+    """The FP64 oracle on the host: full steps (pairs, forces, integrator,
+    walk) of the same workload for about budget_s seconds on every core the
+    process may use, then the pairs of single_sources sources spread over the
+    particle range on one thread (the paper's own regime: one core)."""
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    nproc, model = host_cpu()
+    threads = int(os.environ.get("OMP_NUM_THREADS", nproc))
     om = oracle.OracleMesh(w.mesh.V, w.mesh.T)
     f, b = w.face.copy(), w.bary.copy()
     pairs = 0
@@ -88,10 +140,28 @@ def cpu_baseline(w, budget_s=10.0, max_steps=500):
         pairs += len(info["pairs"].dist)
         steps += 1
     dt = time.perf_counter() - t0
+    n = len(w.face)
+    # the geodesic stage alone (the GPU's pairs/s counts the whole step; the
+    # oracle's force sum and integrators are plain Python loops)
+    t2 = time.perf_counter()
+    o2 = oracle.geodesic_pairs(om, w.face, w.bary, w.potential["cutoff"], nthreads=threads)
+    dt2 = time.perf_counter() - t2
+    src = np.unique(np.linspace(0, n - 1, single_sources).round().astype(np.int32))
+    reps, p1 = 0, 0
+    t1 = time.perf_counter()
+    while reps == 0 or time.perf_counter() - t1 < 1.0:
+        p1 += len(oracle.geodesic_pairs(om, w.face, w.bary, w.potential["cutoff"], sources=src, nthreads=1).dist)
+        reps += 1
+    dt1 = time.perf_counter() - t1
     return {"value": pairs / dt, "unit": "pairs/s", "cores": threads, "kind": "oracle",
             "sample": f"first {steps} full FP64 oracle steps (pairs+forces+walk) of the same workload, "
-                      f"{dt:.1f} s wall, OpenMP over sources",
-            "particle_steps_per_s": steps * len(w.face) / dt}
+                      f"{dt:.1f} s wall, OpenMP over sources on {threads} threads",
+            "particle_steps_per_s": steps * n / dt, "nproc": nproc, "cpu_model": model,
+            "pairs_only": {"value": len(o2.dist) / dt2, "unit": "pairs/s", "cores": threads,
+                           "sample": f"the geodesic pairs of all {n} sources once, {dt2:.2f} s"},
+            "single_thread": {"value": p1 / dt1, "unit": "pairs/s", "cores": 1, "sources_per_s": reps * len(src) / dt1,
+                              "sample": f"geodesic pairs of {len(src)} sources spread over the {n} particles, "
+                                        f"one thread, {reps} repetitions in {dt1:.2f} s"}}
 
 
 def _gsim_args(gsim, w):
@@ -308,11 +378,14 @@ def bench_vsweep(args, gsim, W):
             "results": out}
 
 
-def bench_c5(args, gsim, W):
+def bench_c5(args, gsim, W, with_cpu=True):
     """All-pairs Coulomb with FIRE on the icosphere L6 (81,920 faces, N = 2000):
     every iteration propagates every source over the whole mesh (3,998,000
-    pairs). Two timed iterations per precision after one warm-up; the CPU
-    oracle is timed on a sample of sources and scaled to all 2000."""
+    pairs). Two timed iterations per precision after one warm-up. With
+    --c5-fire K, each precision then runs K FIRE iterations from the same
+    start and the end energies are compared, and at the FP64 run's end state
+    the FP32-mixed energy and forces are compared with the FP64 ones (the
+    same state in both). The CPU oracle is timed on a sample of sources."""
     import math
     w = W.workload("c5a")
     wi = w.integrator
@@ -320,6 +393,7 @@ def bench_c5(args, gsim, W):
     ig = gsim.integrator("fire", wi["dt"], max_disp=wi["max_disp"])
     n = len(w.face)
     out = {}
+    ends = {}
     for prec in ("fp64", "fp32"):
         ctx = gsim.Context(0, prec)
         mid = ctx.mesh_upload(w.mesh.V, w.mesh.T)
@@ -333,23 +407,71 @@ def bench_c5(args, gsim, W):
         dt = time.perf_counter() - t0
         c = ctx.counters()
         geo = ctx.timing_get("geodesic")[0]
-        ctx.close()
+        ctx.timing(False)
+        wpi = c["cum_windows"] / 2
+        pk = FP64_VECTOR_PEAK_TFLOPS if prec == "fp64" else FP32_VECTOR_PEAK_TFLOPS
+        ach = FLOPS_PER_WINDOW * wpi / (geo * 1e-3) / 1e12 if geo > 0 else 0.0
+        rec = measured_counters("c5a", prec)
         out[prec] = {"pairs_per_s": 2 * n * (n - 1) / dt, "s_per_iteration": dt / 2, "geodesic_ms": geo,
-                     "windows_per_iteration": c["cum_windows"] / 2, "windows_per_s": c["cum_windows"] / dt}
+                     "windows_per_iteration": wpi, "windows_per_s": c["cum_windows"] / dt,
+                     "roofline": {"bound": "alu", "achieved": ach, "peak": pk, "unit": "TFLOP/s", "frac": ach / pk,
+                                  "traffic": rec["traffic_bytes_per_launch"] if rec else None,
+                                  "kernel": "k_geodesic_all", "per_unit": f"{FLOPS_PER_WINDOW:.0f} flop/window",
+                                  "units_per_launch": wpi, "avg_launch_ms": geo}}
         print(f"[c5] {prec}: {dt / 2:.3f} s per iteration", file=sys.stderr, flush=True)
+        if args.c5_fire:
+            ctx.particles_set(mid, w.face, w.bary)
+            ctx.tune(graph_steps=0)
+            done = 0
+            t0 = time.perf_counter()
+            while done < args.c5_fire:
+                k = min(10, args.c5_fire - done)
+                ctx.step(mid, pot, ig, k)
+                ctx.synchronize()
+                done += k
+                print(f"[c5] {prec}: {done} FIRE iterations, {time.perf_counter() - t0:.0f} s", file=sys.stderr,
+                      flush=True)
+            _, E = ctx.compute_forces(mid, pot)
+            f, b, _, _ = ctx.particles_get(mid)
+            ends[prec] = (E, f, b)
+            out[prec]["fire"] = {"iterations": args.c5_fire, "end_energy": E, "s": time.perf_counter() - t0}
+        ctx.close()
     line = {"workload": "C5: icosphere L6 (81920 faces), N=2000, Coulomb all pairs, FIRE", "data": "synthetic",
-            "pairs_per_iteration": n * (n - 1), "results": out}
-    if not args.no_cpu_baseline:
-        import numpy as np
+            "pairs_per_iteration": n * (n - 1), "results": out,
+            "fp32_over_fp64": out["fp32"]["pairs_per_s"] / out["fp64"]["pairs_per_s"]}
+    if ends:
+        E64, f64, b64 = ends["fp64"]
+        E32 = ends["fp32"][0]
+        # the same state (the FP64 run's end) in both precisions
+        same = {}
+        for prec in ("fp64", "fp32"):
+            ctx = gsim.Context(0, prec)
+            mid = ctx.mesh_upload(w.mesh.V, w.mesh.T)
+            ctx.particles_set(mid, f64, b64)
+            same[prec] = ctx.compute_forces(mid, pot)
+            ctx.close()
+        F64, e64 = same["fp64"]
+        F32, e32 = same["fp32"]
+        fn = np.linalg.norm(F64, axis=1)
+        line["fire_end"] = {"iterations": args.c5_fire, "energy_fp64_run": E64, "energy_fp32_run": E32,
+                            "energy_rel_diff_of_runs": abs(E32 - E64) / abs(E64),
+                            "same_state_energy_rel_err": abs(e32 - e64) / abs(e64),
+                            "same_state_force_rel_err_max": float(np.max(np.linalg.norm(F32 - F64, axis=1) /
+                                                                         np.maximum(fn, 1e-300))),
+                            "same_state_force_rel_err_median": float(np.median(np.linalg.norm(F32 - F64, axis=1) /
+                                                                               np.maximum(fn, 1e-300)))}
+    if with_cpu and not args.no_cpu_baseline:
         import oracle
         om = oracle.OracleMesh(w.mesh.V, w.mesh.T)
-        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        nproc, model = host_cpu()
+        threads = int(os.environ.get("OMP_NUM_THREADS", nproc))
         src = (np.arange(threads, dtype=np.int32) * (n // threads)).astype(np.int32)  # one source per thread
         t0 = time.perf_counter()
         oracle.geodesic_pairs(om, w.face, w.bary, math.inf, sources=src)
         t = time.perf_counter() - t0
         line["cpu_baseline"] = {"value": len(src) * (n - 1) / t, "unit": "pairs/s", "cores": threads,
-                                "kind": "oracle", "sample": f"rows of {len(src)} sources over the whole mesh, {t:.1f} s"}
+                                "kind": "oracle", "nproc": nproc, "cpu_model": model,
+                                "sample": f"rows of {len(src)} sources over the whole mesh, {t:.1f} s"}
     return line
 
 
@@ -435,6 +557,123 @@ def bench_quench(args, gsim, W):
                         "mean_charge_inner_half": q_in / max(n_in, 1), "mean_charge_outer_half": q_out / max(n_out, 1)}}
 
 
+def bench_single(args, gsim, W, name):
+    """Timed eager steps of one workload (c2 or c4) in the headline
+    precision, the other precision beside it, the stage times, the rooflines
+    of the geodesic and update kernels, and the CPU oracle baseline."""
+    w = W.workload(name)
+    pot, ig = _gsim_args(gsim, w)
+
+    def run(precision):
+        # timed region: eager steps with HIP events around the geodesic stage
+        # only (on the library's stream; every event record costs the stream
+        # a few microseconds, so the other stages are timed in a separate
+        # short run afterwards)
+        ctx = gsim.Context(0, precision)
+        mid = ctx.mesh_upload(w.mesh.V, w.mesh.T)
+        ctx.particles_set(mid, w.face, w.bary)
+        for _ in range(args.warmup):
+            ctx.step(mid, pot, ig, 1)
+        ctx.synchronize()
+        ctx.tune(time_geodesic_only=1)
+        ctx.timing(True)
+        ctx.synchronize()
+        t0 = time.perf_counter()
+        ctx.step(mid, pot, ig, args.steps)
+        ctx.synchronize()
+        dt = time.perf_counter() - t0
+        cnt = ctx.counters()
+        geo = ctx.timing_get("geodesic")[0]
+        ctx.timing(False)
+        ctx.tune(time_geodesic_only=0)
+        ctx.timing(True)
+        k = min(args.steps, 20)
+        ctx.step(mid, pot, ig, k)
+        ctx.synchronize()
+        stages = {st: v for st in ("prefilter", "geodesic", "update", "commit") for v, nl in [ctx.timing_get(st)] if nl}
+        cst = ctx.counters()
+        ctx.timing(False)
+        ctx.close()
+        return dt, cnt, geo, stages, dict(steps=k, pairs=cst["cum_pairs"], crossings=cst["crossings"])
+
+    def update_roofline(stages, stage_cnt):
+        """HBM roofline of the update kernel (a4-a6) from its stage time and
+        the algorithmic bytes of the particles' steps (pairs and crossings
+        per step averaged over the stage run)."""
+        ms = stages.get("update")
+        if not ms:
+            return None
+        k = stage_cnt["steps"]
+        pairs = stage_cnt["pairs"] / k
+        cross = stage_cnt["crossings"] / k
+        nbytes = n * UPDATE_BYTES_PARTICLE + pairs * UPDATE_BYTES_PAIR + cross * UPDATE_BYTES_CROSSING
+        gbps = nbytes / (ms * 1e-3) / 1e9
+        return {"bound": "hbm", "achieved": gbps, "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS,
+                "traffic": None, "kernel": "k_update_batch",
+                "per_unit": f"{UPDATE_BYTES_PARTICLE} B/particle + {UPDATE_BYTES_PAIR} B/pair + "
+                            f"{UPDATE_BYTES_CROSSING} B/edge crossing",
+                "units_per_launch": {"particles": n, "pairs": pairs, "crossings": cross},
+                "bytes_per_launch": nbytes, "avg_launch_ms": ms}
+
+    n = len(w.face)
+    dt, cnt, geo_ms, stages, scnt = run(args.precision)
+    pairs = cnt["cum_pairs"]
+    win_per_launch = cnt["cum_windows"] / max(cnt["cum_passes"], 1)
+    achieved = FLOPS_PER_WINDOW * win_per_launch / (geo_ms * 1e-3) / 1e12 if geo_ms > 0 else 0.0
+    peak = FP64_VECTOR_PEAK_TFLOPS if args.precision == "fp64" else FP32_VECTOR_PEAK_TFLOPS
+    rec = measured_counters(name, args.precision)
+    line = {
+        "metric": METRIC,
+        "value": pairs / dt,
+        "unit": "pairs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD_TEXT[name],
+                   "n_particles": n, "faces": w.mesh.nf, "cutoff": w.potential["cutoff"],
+                   "precision": args.precision},
+        "particle_steps_per_s": n * args.steps / dt,
+        "pairs_per_step": pairs / args.steps,
+        "stage_ms": stages,
+        "stage_ms_note": "all stages timed in a separate run of up to 20 steps after the timed region; with the "
+                         "update fused into the geodesic launch there is no update stage, and the commit runs once "
+                         "per call",
+        "windows_per_step": win_per_launch,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                     "frac": achieved / peak,
+                     "traffic": rec["traffic_bytes_per_launch"] if rec else None,
+                     "kernel": "k_geodesic", "per_unit": f"{FLOPS_PER_WINDOW:.0f} flop/window",
+                     "units_per_launch": win_per_launch, "avg_launch_ms": geo_ms},
+        "update_roofline": update_roofline(stages, scnt),
+    }
+    if rec:
+        line["roofline"]["counters"] = {k: rec[k] for k in ("lds", "occupancy", "hbm_gbps", "valu_busy",
+                                                             "source") if k in rec}
+    if not args.no_compare:
+        other = "fp64" if args.precision == "fp32" else "fp32"
+        dt2, cnt2, geo2, st2, scnt2 = run(other)
+        w2 = cnt2["cum_windows"] / max(cnt2["cum_passes"], 1)
+        pk2 = FP64_VECTOR_PEAK_TFLOPS if other == "fp64" else FP32_VECTOR_PEAK_TFLOPS
+        a2 = FLOPS_PER_WINDOW * w2 / (geo2 * 1e-3) / 1e12 if geo2 > 0 else 0.0
+        rec2 = measured_counters(name, other)
+        line[other] = {"pairs_per_s": cnt2["cum_pairs"] / dt2, "particle_steps_per_s": n * args.steps / dt2,
+                       "ms_per_step": 1e3 * dt2 / args.steps, "stage_ms": st2, "windows_per_step": w2,
+                       "roofline": {"bound": "alu", "achieved": a2, "peak": pk2, "unit": "TFLOP/s", "frac": a2 / pk2,
+                                    "traffic": rec2["traffic_bytes_per_launch"] if rec2 else None,
+                                    "kernel": "k_geodesic", "avg_launch_ms": geo2, "units_per_launch": w2},
+                       "update_roofline": update_roofline(st2, scnt2)}
+        line[f"{other}_over_{args.precision}"] = (cnt2["cum_pairs"] / dt2) / (pairs / dt)
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = cpu_baseline(w)
+    return line
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -442,13 +681,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
                     help="precision of the headline line (the other one is timed beside it unless --no-compare)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c4", "c5", "torus_nve", "vsweep", "quench"],
-                    help="c2: bumpy sphere N=1000 (the default line); c3: 16 surfaces batched; "
-                         "c4: open height field N=20000, Brownian; torus_nve: NVE cost vs N on the benchmark torus; "
+    ap.add_argument("--workload", default="c4", choices=["c2", "c3", "c4", "c5", "torus_nve", "vsweep", "quench"],
+                    help="c4: open height field N=20000, Brownian (the default line, with the c3 and c5 legs); "
+                         "c2: bumpy sphere N=1000; c3: 16 surfaces batched; "
+                         "torus_nve: NVE cost vs N on the benchmark torus; "
                          "vsweep: NVE cost vs mesh size at N=100, full mesh and submeshed; "
                          "quench: 64 batched torus quenches with Voronoi defect statistics; "
                          "c5: all-pairs Coulomb FIRE on the L6 sphere")
-    ap.add_argument("--no-compare", action="store_true", help="skip the FP64 comparison leg")
+    ap.add_argument("--no-compare", action="store_true", help="skip the other precision's leg")
+    ap.add_argument("--no-legs", action="store_true", help="default line only: skip the c3 and c5 legs")
+    ap.add_argument("--c5-fire", type=int, default=0, metavar="K",
+                    help="c5: also run K FIRE iterations per precision and compare the end energies")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MB",
                     help="only run a plain device-to-device copy of this many MiB (hardware-counter calibration)")
@@ -486,84 +729,10 @@ def main():
     if args.workload == "c5":
         print(json.dumps(bench_c5(args, gsim, W)), flush=True)
         return
-    w = W.workload(args.workload)
-    pot = gsim.potential("harmonic", w.potential["k"], w.potential["sigma"], w.potential["cutoff"])
-    wi = w.integrator
-    if wi["kind"] == "brownian":
-        ig = gsim.integrator("brownian", wi["dt"], 1.0, wi["kT"], wi["friction"], wi["seed"])
-    else:
-        ig = gsim.integrator("overdamped", wi["dt"], wi["mobility"])
-
-    def run(precision):
-        # timed region: eager steps with HIP events around the geodesic stage
-        # only (on the library's stream; every event record costs the stream
-        # a few microseconds, so the other stages are timed in a separate
-        # short run afterwards)
-        ctx = gsim.Context(0, precision)
-        mid = ctx.mesh_upload(w.mesh.V, w.mesh.T)
-        ctx.particles_set(mid, w.face, w.bary)
-        for _ in range(args.warmup):
-            ctx.step(mid, pot, ig, 1)
-        ctx.synchronize()
-        ctx.tune(time_geodesic_only=1)
-        ctx.timing(True)
-        ctx.synchronize()
-        t0 = time.perf_counter()
-        ctx.step(mid, pot, ig, args.steps)
-        ctx.synchronize()
-        dt = time.perf_counter() - t0
-        cnt = ctx.counters()
-        geo = ctx.timing_get("geodesic")[0]
-        ctx.timing(False)
-        ctx.tune(time_geodesic_only=0)
-        ctx.timing(True)
-        ctx.step(mid, pot, ig, min(args.steps, 20))
-        ctx.synchronize()
-        stages = {k: v for k in ("prefilter", "geodesic", "update", "commit") for v, n in [ctx.timing_get(k)] if n}
-        ctx.timing(False)
-        ctx.close()
-        return dt, cnt, geo, stages
-
-    dt, cnt, geo_ms, stages = run(args.precision)
-    pairs = cnt["cum_pairs"]
-    n = len(w.face)
-    win_per_launch = cnt["cum_windows"] / max(cnt["cum_passes"], 1)
-    achieved = FLOPS_PER_WINDOW * win_per_launch / (geo_ms * 1e-3) / 1e12 if geo_ms > 0 else 0.0
-    peak = FP64_VECTOR_PEAK_TFLOPS if args.precision == "fp64" else FP32_VECTOR_PEAK_TFLOPS
-    line = {
-        "metric": METRIC,
-        "value": pairs / dt,
-        "unit": "pairs/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * dt / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32+f64",
-        "data": "synthetic",
-        "config": {"workload": WORKLOAD_TEXT[args.workload],
-                   "n_particles": n, "faces": w.mesh.nf, "cutoff": w.potential["cutoff"],
-                   "precision": args.precision},
-        "particle_steps_per_s": n * args.steps / dt,
-        "pairs_per_step": pairs / args.steps,
-        "stage_ms": stages,
-        "stage_ms_note": "all stages timed in a separate 20-step run after the timed region; with the update fused into the geodesic launch there is no update stage, and the commit runs once per call",
-        "windows_per_step": win_per_launch,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                     "frac": achieved / peak,
-                     "traffic": measured_traffic(args.precision) if args.workload == "c2" else None,
-                     "kernel": "k_geodesic", "per_unit": f"{FLOPS_PER_WINDOW:.0f} flop/window",
-                     "units_per_launch": win_per_launch, "avg_launch_ms": geo_ms},
-    }
-    if not args.no_compare:
-        other = "fp64" if args.precision == "fp32" else "fp32"
-        dt2, cnt2, _, st2 = run(other)
-        line[other] = {"pairs_per_s": cnt2["cum_pairs"] / dt2, "particle_steps_per_s": n * args.steps / dt2,
-                       "ms_per_step": 1e3 * dt2 / args.steps, "stage_ms": st2}
-    if not args.no_cpu_baseline:
-        line["cpu_baseline"] = cpu_baseline(w)
+    line = bench_single(args, gsim, W, args.workload)
+    if args.workload == "c4" and not args.no_legs:
+        line["c3"] = bench_c3(args, gsim, W)
+        line["c5"] = bench_c5(args, gsim, W, with_cpu=False)
     print(json.dumps(line), flush=True)
 
 

@@ -349,8 +349,9 @@ gsim_status gsim_timing_get(gsim_ctx *ctx, const char *name, double *avg_ms, int
  * guard band), [5] neighbour pairs,
  * [6] sources over a work limit, [10] deepest window stack of a source
  * (records, LDS and overflow together), [11] particles that met a non-finite
- * value. Summed over the calls since timing was last enabled: [7] neighbour
- * pairs, [8] windows, [9] passes. c[12]. */
+ * value, [12] edge crossings of the walks of time steps. Summed over the
+ * calls since timing was last enabled: [7] neighbour pairs, [8] windows,
+ * [9] passes. c[13]. */
 gsim_status gsim_counters_get(gsim_ctx *ctx, int64_t *c);
 /* Per-source profile of the geodesic kernel, accumulated over the calls
  * made while it is on: out[n][8] = GPU clock cycles, propagation-loop

@@ -325,6 +325,7 @@ gsim_status end_call(gsim_ctx *c) {
         L.limited += q.limited;
         L.max_depth = std::max(L.max_depth, q.max_depth);
         L.nonfinite += q.nonfinite;
+        L.crossings += q.crossings;
     }
     c->cum_pairs += c->last.nbr_pairs;
     c->cum_windows += c->last.windows;
@@ -1690,6 +1691,7 @@ gsim_status gsim_source_profile(gsim_ctx *c, int on, int64_t *out, int32_t n) {
 
 gsim_status gsim_counters_get(gsim_ctx *c, int64_t *c10) {
     if (!c || !c10) return GSIM_E_ARG;
+    c10[12] = (int64_t)c->last.crossings;
     c10[11] = (int64_t)c->last.nonfinite;
     c10[10] = (int64_t)c->last.max_depth;
     c10[7] = (int64_t)c->cum_pairs;

@@ -135,6 +135,7 @@ struct GeoOut {
 struct alignas(128) Counters {  // device-side, int64; one 128-byte line
     unsigned long long windows, pruned, launches, stale, guards, nbr_pairs, limited, max_depth;
     unsigned long long nonfinite;  // particles that met a non-finite force, displacement or velocity
+    unsigned long long crossings;  // edge crossings of the walks of time steps
 };
 static_assert(sizeof(Counters) == 128, "one counter slot per 128-byte line");
 // The device counters are kCtrSlots copies, one line each: each workgroup

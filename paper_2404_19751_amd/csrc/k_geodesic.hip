@@ -812,14 +812,14 @@ __device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &
 
 // The fused update of one source particle (lane 0): force from its row,
 // integrator, walk, new state into the next-state arrays; returns its pair
-// count (nonfin: a non-finite value kept it in place). It runs after the
-// source loop (a fused launch has one workgroup per source), where nothing
-// of the propagation is live, so it costs the loop no registers.
-__device__ __attribute__((always_inline)) inline int fused_move(const SurfDesc &sd, int src, bool &nonfin) {
+// count (wc: the walk's counts). It runs after the source loop (a fused
+// launch has one workgroup per source), where nothing of the propagation is
+// live, so it costs the loop no registers.
+__device__ __attribute__((always_inline)) inline int fused_move(const SurfDesc &sd, int src, WalkCounts &wc) {
     double F[3], E;
     int np = 0;
     row_force(src, sd.cand_cnt, sd.cap, sd.cdist, sd.ctan, sd.cutoff, sd.pkind, sd.pk, sd.psigma, F, E, np);
-    nonfin = (move_particle(sd, src, F, sd.face_out, sd.bary_out, sd.vel_out) & PF_NONFINITE) != 0;
+    move_particle(sd, src, F, sd.face_out, sd.bary_out, sd.vel_out, wc);
     return np;
 }
 
@@ -846,7 +846,7 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
     st.overflow = false;
     unsigned long long c_limited = 0;
     unsigned long long fused_np = 0;  // neighbour pairs of the moved particle (lane 0)
-    bool fused_nonfin = false;        // it met a non-finite value (lane 0)
+    WalkCounts fused_wc = {0, 0, 0, 0, 0, 0};  // its walk's counts (lane 0)
     int fused_src = -1, fused_si = 0;  // the source a fused launch's workgroup took
     int next = 0, left = 0;  // claimed sources not yet processed
     if (kOne) {
@@ -917,7 +917,7 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
         // the row this wavefront has just written) into the next-state
         // arrays, which no source reads during the pass
         __syncthreads();
-        if (lane == 0) fused_np += (unsigned long long)fused_move(a.sd[fused_si], fused_src, fused_nonfin);
+        if (lane == 0) fused_np += (unsigned long long)fused_move(a.sd[fused_si], fused_src, fused_wc);
     }
     unsigned long long pr = (unsigned long long)st.pruned, sl = st.stale;
     for (int o = 32; o > 0; o >>= 1) {
@@ -935,7 +935,8 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
         if (st.depth) atomicMax(&ctr->max_depth, (unsigned long long)st.depth);
         if (st.guards) atomicAdd(&ctr->guards, st.guards);
         if (fused_np) atomicAdd(&ctr->nbr_pairs, fused_np);
-        if (fused_nonfin) atomicAdd(&ctr->nonfinite, 1ull);
+        if (fused_wc.nonfinite) atomicAdd(&ctr->nonfinite, 1ull);
+        if (fused_wc.cross_n) atomicAdd(&ctr->crossings, (unsigned long long)fused_wc.cross_n);
     }
 }
 

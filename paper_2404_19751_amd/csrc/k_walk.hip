@@ -114,9 +114,9 @@ __global__ __launch_bounds__(256) void k_walk_total(const unsigned long long *__
 // particle's neighbour row (Sec. 3.1 force sum), the displacement of the
 // integrator (Sec. 2.1), and the walk (Sec. 3.2). Rows hold only distances
 // and tangents computed before any particle moves, so particles are
-// independent here. Returns the particle's neighbour-pair count; nonfin is
-// set when a non-finite value kept the particle in place.
-__device__ inline int update_one(const SurfDesc *__restrict__ desc, const BatchIdx &bi, int g, bool &nonfin) {
+// independent here. Returns the particle's neighbour-pair count; wc receives
+// the walk's counts.
+__device__ inline int update_one(const SurfDesc *__restrict__ desc, const BatchIdx &bi, int g, WalkCounts &wc) {
     const int si = batch_surface(bi, g);
     const SurfDesc &sd = desc[si];
     const int i = g - bi.begin[si];
@@ -124,7 +124,7 @@ __device__ inline int update_one(const SurfDesc *__restrict__ desc, const BatchI
         double F[3], E;
         int np = 0;
         row_force(i, sd.cand_cnt, sd.cap, sd.cdist, sd.ctan, sd.cutoff, sd.pkind, sd.pk, sd.psigma, F, E, np);
-        nonfin = (move_particle(sd, i, F, sd.face, sd.bary, sd.vel) & PF_NONFINITE) != 0;
+        move_particle(sd, i, F, sd.face, sd.bary, sd.vel, wc);
         return np;
     }
     // FIRE: forces and the control step come from the FIRE kernels; mix,
@@ -138,7 +138,7 @@ __device__ inline int update_one(const SurfDesc *__restrict__ desc, const BatchI
     const double L = sqrt(dot(Dv, Dv));
     if (L > sd.max_disp) Dv = (sd.max_disp / L) * Dv;
     const double D[3] = {Dv.x, Dv.y, Dv.z};
-    nonfin = (walk_store(sd, i, sd.face[i], D, v, sd.face, sd.bary, sd.vel) & PF_NONFINITE) != 0;
+    walk_store(sd, i, sd.face[i], D, v, sd.face, sd.bary, sd.vel, wc);
     return 0;
 }
 
@@ -146,11 +146,12 @@ __device__ inline int update_one(const SurfDesc *__restrict__ desc, const BatchI
 __global__ __launch_bounds__(256) void k_update_batch(const SurfDesc *__restrict__ desc, BatchIdx bi,
                                                      Counters *__restrict__ ctr) {
     const int g = blockIdx.x * blockDim.x + threadIdx.x;
-    bool nonfin = false;
-    const int np = g < bi.begin[bi.nsurf] ? update_one(desc, bi, g, nonfin) : 0;
+    WalkCounts wc = {0, 0, 0, 0, 0, 0};
+    const int np = g < bi.begin[bi.nsurf] ? update_one(desc, bi, g, wc) : 0;
     // the counts: one atomic per wavefront, not one per particle
     wave_atomic_add(&ctr->nbr_pairs, (unsigned long long)np);
-    wave_atomic_add(&ctr->nonfinite, nonfin ? 1ull : 0ull);
+    wave_atomic_add(&ctr->nonfinite, wc.nonfinite);
+    wave_atomic_add(&ctr->crossings, wc.cross_n);
 }
 
 // The state that the cutoff kernel's fused update wrote (the next-state

@@ -205,11 +205,12 @@ __device__ inline void walk_one(const DevMesh &m, int &f, double b[3], d3 D, d3 
 
 // The walk of particle i by D (the velocity v carried along) and the store
 // of its new state into (face_o, bary_o, vel_o), which may be the arrays the
-// state was read from. Returns the particle's PF_* flags.
+// state was read from. Returns the particle's PF_* flags; wc receives the
+// walk's counts.
 __device__ inline uint8_t walk_store(const SurfDesc &sd, int i, int f, const double D[3], d3 v, int32_t *face_o,
-                                     double *bary_o, double *vel_o) {
+                                     double *bary_o, double *vel_o, WalkCounts &wc) {
     double b[3] = {sd.bary[3 * i], sd.bary[3 * i + 1], sd.bary[3 * i + 2]};
-    WalkCounts wc = {0, 0, 0, 0, 0, 0};
+    wc = WalkCounts{0, 0, 0, 0, 0, 0};
     uint8_t fl = 0;
     walk_one(sd.m, f, b, d3{D[0], D[1], D[2]}, v, true, wc, fl);
     face_o[i] = f;
@@ -227,9 +228,9 @@ __device__ inline uint8_t walk_store(const SurfDesc &sd, int i, int f, const dou
 // than FIRE): overdamped or Brownian displacement, or velocity Verlet in
 // leapfrog form (unit masses: the stored velocity is v_{k-1/2}; kick by
 // dt F(x_k), drift by dt v_{k+1/2}); then the walk. Returns the particle's
-// PF_* flags.
+// PF_* flags; wc receives the walk's counts.
 __device__ inline uint8_t move_particle(const SurfDesc &sd, int i, const double F[3], int32_t *face_o,
-                                        double *bary_o, double *vel_o) {
+                                        double *bary_o, double *vel_o, WalkCounts &wc) {
     const int f = sd.face[i];
     d3 v = ld3(sd.vel + 3 * (int64_t)i);
     double D[3];
@@ -241,7 +242,7 @@ __device__ inline uint8_t move_particle(const SurfDesc &sd, int i, const double 
     } else {
         displacement(sd.m, f, i, F, sd.ikind, sd.dt, sd.mobility, sd.kT, sd.friction, sd.seed, *sd.step, D);
     }
-    return walk_store(sd, i, f, D, v, face_o, bary_o, vel_o);
+    return walk_store(sd, i, f, D, v, face_o, bary_o, vel_o, wc);
 }
 
 }  // namespace gsim

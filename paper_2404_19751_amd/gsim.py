@@ -360,8 +360,9 @@ class Context:
         return out
 
     def counters(self) -> dict:
-        c = np.zeros(12, np.int64)
+        c = np.zeros(13, np.int64)
         self._chk(self.L.gsim_counters_get(self.h, _ptr(c)))
         return dict(windows=int(c[0]), pruned=int(c[1]), launches=int(c[2]), stale=int(c[3]), guard_sources=int(c[4]),
                     nbr_pairs=int(c[5]), limited=int(c[6]), cum_pairs=int(c[7]), cum_windows=int(c[8]),
-                    cum_passes=int(c[9]), max_stack_depth=int(c[10]), nonfinite=int(c[11]))
+                    cum_passes=int(c[9]), max_stack_depth=int(c[10]), nonfinite=int(c[11]),
+                    crossings=int(c[12]))
