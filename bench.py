@@ -269,11 +269,13 @@ def bench_c3(args, gsim, W):
 
 def bench_torus_nve(args, gsim, W):
     """Cost per velocity-Verlet (NVE) step against N on the aspect-3 benchmark
-    torus (4648 faces) for interaction ranges sigma = 1/4 and 1/8, the setting
-    of the paper's Fig. 3 scaling study; steps replayed from HIP graphs. The
-    exponent is the least-squares slope of log(ms/step) against log N."""
+    torus (4648 faces) for interaction ranges sigma = 1, 1/2, 1/4 and 1/8, the
+    setting of the paper's Fig. 3 scaling study (sigma = 1 its main curve);
+    steps replayed from HIP graphs, as many as about half a second takes
+    (at least 2, at most --steps). The exponent is the least-squares slope of
+    log(ms/step) against log N."""
     out = {}
-    for sig in (0.25, 0.125):
+    for sig in (1.0, 0.5, 0.25, 0.125):
         rows = []
         for n in (512, 1024, 2048, 4096, 8192, 16384, 32768):
             w = W.workload(f"torus_nve_{n}_{sig}")
@@ -282,26 +284,36 @@ def bench_torus_nve(args, gsim, W):
                 ctx = gsim.Context(0, prec)
                 mid = ctx.mesh_upload(w.mesh.V, w.mesh.T)
                 ctx.particles_set(mid, w.face, w.bary)
-                ctx.tune(graph_steps=args.steps)
-                ctx.step(mid, pot, ig, args.steps)  # warm-up, captures the graph
+                t0 = time.perf_counter()
+                ctx.step(mid, pot, ig, 1)
+                ctx.synchronize()
+                t1 = time.perf_counter() - t0
+                k = max(2, min(args.steps, int(0.5 / max(t1, 1e-5))))
+                ctx.tune(graph_steps=k)
+                ctx.step(mid, pot, ig, k)  # warm-up, captures the graph
                 ctx.synchronize()
                 c0 = ctx.counters()["cum_pairs"]
                 t0 = time.perf_counter()
-                ctx.step(mid, pot, ig, args.steps)
+                ctx.step(mid, pot, ig, k)
                 ctx.synchronize()
                 dt = time.perf_counter() - t0
                 pairs = ctx.counters()["cum_pairs"] - c0
                 ctx.close()
-                rows.append({"n": n, "precision": prec, "ms_per_step": 1e3 * dt / args.steps,
-                             "pairs_per_step": pairs / args.steps, "pairs_per_s": pairs / dt})
+                rows.append({"n": n, "precision": prec, "steps": k, "ms_per_step": 1e3 * dt / k,
+                             "pairs_per_step": pairs / k, "pairs_per_s": pairs / dt})
+                print(f"[torus_nve] sigma={sig} n={n} {prec}: {1e3 * dt / k:.3f} ms/step ({k} steps)",
+                      file=sys.stderr, flush=True)
         fits = {}
         for prec in ("fp64", "fp32"):
             xs = np.log([r["n"] for r in rows if r["precision"] == prec])
             ys = np.log([r["ms_per_step"] for r in rows if r["precision"] == prec])
             fits[prec] = float(np.polyfit(xs, ys, 1)[0])
+            big = [r for r in rows if r["precision"] == prec and r["n"] >= 4096]
+            fits[prec + "_n_ge_4096"] = float(np.polyfit(np.log([r["n"] for r in big]),
+                                                         np.log([r["ms_per_step"] for r in big]), 1)[0])
         out[f"sigma_{sig}"] = {"runs": rows, "exponent": fits}
     return {"workload": "velocity Verlet NVE on the aspect-3 benchmark torus (R=3, r=1, 4648 faces), harmonic "
-                        "repulsion, dt=0.005, from rest, N = 512 .. 32768", "steps": args.steps, "data": "synthetic",
+                        "repulsion of range sigma, dt=0.005, from rest, N = 512 .. 32768", "data": "synthetic",
             "results": out}
 
 

@@ -317,7 +317,13 @@ gsim_status gsim_step_batched(gsim_ctx *ctx, int32_t nmesh, const int32_t *mesh_
  *   "whole_mesh"    1: finite-cutoff passes also run on the whole-mesh kernel
  *                   below (windows pruned at the cutoff; no limit on candidates or
  *                   bend vertices per source; at most 46,340 particles per
- *                   surface, whose n x n pair rows take 37 bytes each)
+ *                   surface, whose n x n pair rows take 37 bytes each). Without
+ *                   it, the cutoff kernel takes up to 4096 Euclidean candidates
+ *                   per source: up to 128 in an LDS table, more with the targets
+ *                   in global memory and rows sized from a count of the
+ *                   candidates at the start of each call (GSIM_E_LIMIT beyond
+ *                   4096, or when moving particles outgrow that count within a
+ *                   call by more than a quarter plus 32)
  *   Whole-mesh passes (no cutoff, or "whole_mesh" = 1):
  *   "stack_cap_all" window records per resident wavefront (1024 .. 4M)
  *   "max_windows_all" per-source work limit

@@ -75,6 +75,7 @@ struct gsim_ctx {
     std::string err;
     std::vector<MeshState *> meshes;
     Buf stack, work, ctr, wstats, scan_scratch, sum_scratch, pf_over, prof, desc, vdist, ttab, roots, partials, vbits;
+    Buf gtab;  // big-candidate target arrays of the resident wavefronts
     SurfDesc *desc_pinned = nullptr;  // staging for descriptor uploads
     std::vector<SurfDesc> desc_cached;
     bool profile_sources = false;
@@ -333,10 +334,10 @@ gsim_status end_call(gsim_ctx *c) {
     if (over || c->last.limited)
         return fail(c, GSIM_E_LIMIT,
                     std::to_string(over + (long long)c->last.limited) +
-                        " source(s) exceeded a per-source limit (more than " + std::to_string(kCandCap) +
-                        " candidate targets within the cutoff, window stack or window count); the results of this "
-                        "call are incomplete. Passes of the whole-mesh kernel (the \"whole_mesh\" knob, up to " +
-                        std::to_string(kAllPairsMax) + " particles) have no limit on candidates");
+                        " source(s) exceeded a per-source limit (more candidate targets within the cutoff than "
+                        "the row capacity set at the start of the call, window stack or window count); the results "
+                        "of this call are incomplete. Passes of the whole-mesh kernel (the \"whole_mesh\" knob, up "
+                        "to " + std::to_string(kAllPairsMax) + " particles) have no limit on candidates");
     return nonfinite_status(c, c->last.nonfinite);
 }
 
@@ -357,6 +358,77 @@ void choose_grid(const DevMesh &m, double cutoff, bool small, int dims[3], doubl
         if (!small || ncell <= kSmallCells) return;
         cell *= 1.0625;
     }
+}
+
+// Surface area of a mesh (computed once).
+double surface_area(MeshState *ms) {
+    if (!(ms->area > 0.0)) {
+        double A = 0.0;
+        const HostMesh &H = ms->host;
+        for (int f = 0; f < H.nf; ++f) {
+            const double *p0 = &H.V[3 * (size_t)H.T[3 * f]], *p1 = &H.V[3 * (size_t)H.T[3 * f + 1]],
+                         *p2 = &H.V[3 * (size_t)H.T[3 * f + 2]];
+            const double u[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+            const double v[3] = {p2[0] - p0[0], p2[1] - p0[1], p2[2] - p0[2]};
+            const double x = u[1] * v[2] - u[2] * v[1], y = u[2] * v[0] - u[0] * v[2], z = u[0] * v[1] - u[1] * v[0];
+            A += 0.5 * std::sqrt(x * x + y * y + z * z);
+        }
+        ms->area = A;
+    }
+    return ms->area;
+}
+
+// Row capacity of a cutoff pass over the current particle state: kCandCap
+// (the LDS target table) while no source can have more Euclidean
+// candidates, else the largest count with headroom for the particles' moves
+// during the call (the big-candidate kernel). The count runs on the device
+// only when the density makes more than kCandCap plausible: three times
+// the mean count of a flat disk of radius cutoff.
+gsim_status row_capacity(gsim_ctx *c, MeshState *ms, double cutoff, int &cap) {
+    const int n = ms->n;
+    cap = kCandCap;
+    const double mean = n * M_PI * cutoff * cutoff / std::max(surface_area(ms), 1e-300);
+    if (3.0 * mean + 16.0 <= kCandCap) return GSIM_OK;
+    if (c->capturing) return fail(c, GSIM_E_STATE, "candidate count during graph capture");
+    hipStream_t s = c->stream;
+    int dims[3];
+    double cell;
+    choose_grid(ms->dm, cutoff, false, dims, cell);
+    const int64_t ncell = (int64_t)dims[0] * dims[1] * dims[2];
+    HIPCHK(c, ensure(ms->cell_of, sizeof(int32_t) * n));
+    HIPCHK(c, ensure(ms->cell_start, sizeof(int32_t) * (ncell + 1)));
+    HIPCHK(c, ensure(ms->cell_fill, sizeof(int32_t) * ncell));
+    HIPCHK(c, ensure(ms->order, sizeof(int32_t) * n));
+    HIPCHK(c, ensure(ms->tmp64, sizeof(int64_t) * (std::max<int64_t>(ncell, n) + 1)));
+    HIPCHK(c, ensure(c->scan_scratch, sizeof(int64_t) * ((std::max<int64_t>(ncell, n) + 1023) / 1024 + 2)));
+    HIPCHK(c, ensure(ms->nbr_cnt, sizeof(int32_t) * (n + 1)));
+    PrefilterBufs pb{};
+    pb.xyz = ms->xyz;
+    pb.cell_of = P<int32_t>(ms->cell_of);
+    pb.cell_start = P<int32_t>(ms->cell_start);
+    pb.cell_fill = P<int32_t>(ms->cell_fill);
+    pb.order = P<int32_t>(ms->order);
+    pb.cap_c = kCandCap;
+    for (int k = 0; k < 3; ++k) pb.dims[k] = dims[k];
+    pb.cell = cell;
+    HIPCHK(c, launch_xyz(ms->dm, n, ms->face, ms->bary, ms->xyz, s));
+    HIPCHK(c, launch_prefilter_bin(ms->dm, n, pb, s));
+    HIPCHK(c, launch_scan_i32_to_i64(pb.cell_fill, P<int64_t>(ms->tmp64), (int)ncell, P<int64_t>(c->scan_scratch), s));
+    HIPCHK(c, launch_i64_to_i32(P<int64_t>(ms->tmp64), pb.cell_start, (int)ncell, s));
+    HIPCHK(c, launch_zero_i32(pb.cell_fill, ncell, s));
+    HIPCHK(c, launch_bin_scatter(n, pb, s));
+    HIPCHK(c, launch_count_candidates(n, pb, cutoff * cutoff * (1.0 + 1e-12), P<int32_t>(ms->nbr_cnt), s));
+    std::vector<int32_t> cnt(n);
+    HIPCHK(c, hipMemcpyAsync(cnt.data(), ms->nbr_cnt.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    const int mx = *std::max_element(cnt.begin(), cnt.end());
+    if (mx <= kCandCap) return GSIM_OK;
+    if (mx > kBigCandMax)
+        return fail(c, GSIM_E_LIMIT, "a source has " + std::to_string(mx) + " Euclidean candidates within the cutoff; "
+                                     "the cutoff kernel takes at most " + std::to_string(kBigCandMax) +
+                                     " (the \"whole_mesh\" knob has no such limit)");
+    cap = std::min(kBigCandMax, (mx + mx / 4 + 32 + 63) / 64 * 64);
+    return GSIM_OK;
 }
 
 struct Member {
@@ -385,7 +457,12 @@ gsim_status prepare_surface(gsim_ctx *c, const Member &mb, bool small, int src_b
         choose_grid(m, mb.cutoff, small, d.dims, d.cell);
     }
     const int64_t ncell = (int64_t)d.dims[0] * d.dims[1] * d.dims[2];
-    const size_t cap = all ? (size_t)n : (size_t)kCandCap;
+    int rowcap = kCandCap;
+    if (!all) {
+        gsim_status st = row_capacity(c, ms, mb.cutoff, rowcap);
+        if (st != GSIM_OK) return st;
+    }
+    const size_t cap = all ? (size_t)n : (size_t)rowcap;
     HIPCHK(c, ensure(ms->cell_of, sizeof(int32_t) * n));
     HIPCHK(c, ensure(ms->cell_start, sizeof(int32_t) * (ncell + 1)));
     HIPCHK(c, ensure(ms->cell_fill, sizeof(int32_t) * ncell));
@@ -485,6 +562,8 @@ struct Batch {
     int32_t rcap = 0;     // its capacity (bend vertices)
     bool small = true;  // every surface bins in one workgroup
     bool fused = false; // time steps move the particles inside the cutoff kernel
+    bool big = false;   // some surface has more candidates per source than the LDS table holds
+    int gcap = 0;       // its widest row (big-candidate target arrays per wavefront)
     int nslots = 0;
     GeoShape shape{};
 };
@@ -530,6 +609,13 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
         total += B.mem[i].ms->n;
     }
     B.bi.begin[ns] = total;
+    B.big = false;
+    B.gcap = 0;
+    for (int i = 0; i < ns && !B.all; ++i)
+        if (B.desc[i].cap > kCandCap) {
+            B.big = true;
+            B.gcap = std::max(B.gcap, (int)B.desc[i].cap);
+        }
     B.fire_blk.nsurf = ns;
     B.any_fire = false;
     int nblk = 0;
@@ -559,7 +645,7 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
     // persistent grid: as many wavefronts as can be resident, at most one per source
     const bool fp32 = c->prec == GSIM_FP32_MIXED;
     const int per_cu = std::max(1, B.all ? geodesic_all_blocks_per_cu(c->lds_stack_kb, fp32)
-                                         : geodesic_blocks_per_cu(c->lds_stack_kb, fp32));
+                                         : geodesic_blocks_per_cu(c->lds_stack_kb, fp32, B.big));
     B.nslots = std::min(std::min(total, c->cus * per_cu), c->max_slots);
     if (B.all) {
         // whole-mesh fronts are deep: fewer resident wavefronts rather than more memory
@@ -588,7 +674,7 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
         // at most the needed number fit on a compute unit and the grid spreads
         // over all of them instead of filling some
         const int want = (B.nslots + c->cus - 1) / c->cus;
-        const size_t stat = geodesic_lds_bytes(c->lds_stack_kb, fp32);
+        const size_t stat = geodesic_lds_bytes(c->lds_stack_kb, fp32, B.big);
         if (want < per_cu && want > 0) {
             const size_t each = (size_t)c->lds_cu / (size_t)want;
             if (each > stat) B.shape.pad_lds = (int32_t)std::min(each - stat, (size_t)c->max_lds - stat);
@@ -596,6 +682,7 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
     }
     const int cap_rec = B.all ? c->stack_cap_all : c->gp.stack_cap;
     HIPCHK(c, ensure(c->stack, (size_t)std::max(B.nslots, 1) * cap_rec * 64));
+    if (B.big) HIPCHK(c, ensure(c->gtab, (size_t)std::max(B.nslots, 1) * (size_t)geodesic_gtab_bytes(B.gcap)));
     if (B.all) {
         HIPCHK(c, ensure(c->vdist, sizeof(double) * (size_t)std::max(B.nslots, 1) * B.vstride));
         HIPCHK(c, ensure(c->ttab, 4 * sizeof(double) * (size_t)std::max(B.nslots, 1) * B.tcap));
@@ -678,7 +765,8 @@ gsim_status geodesic_pass(gsim_ctx *c, Batch &B, bool advance, bool commit_in = 
         Stage st(c, "geodesic", true);
         HIPCHK(c, launch_geodesic(desc_dev(c), B.bi, gp, B.shape, P<char>(c->stack), P<char>(c->roots), B.rstride,
                                   B.rcap, P<int32_t>(c->work), P<Counters>(c->ctr), c->prec == GSIM_FP32_MIXED,
-                                  advance && B.fused, s, st.a, st.b));
+                                  advance && B.fused, s, st.a, st.b, B.big ? P<char>(c->gtab) : nullptr,
+                                  B.big ? B.gcap : 0));
     }
     c->passes++;
     return GSIM_OK;
@@ -757,10 +845,12 @@ std::string graph_key(gsim_ctx *c, const Batch &B, int steps) {
     put(&B.shape, sizeof(B.shape));
     put(&B.small, sizeof(B.small));
     put(&B.fused, sizeof(B.fused));
+    put(&B.big, sizeof(B.big));
+    put(&B.gcap, sizeof(B.gcap));
     put(&c->update_block, sizeof(int));
     put(&steps, sizeof(int));
-    void *ptrs[9] = {c->stack.p, c->work.p, c->ctr.p, c->desc.p, c->scan_scratch.p, c->vdist.p, c->ttab.p,
-                     c->roots.p, c->partials.p};
+    void *ptrs[10] = {c->stack.p, c->work.p, c->ctr.p, c->desc.p, c->scan_scratch.p, c->vdist.p, c->ttab.p,
+                      c->roots.p, c->partials.p, c->gtab.p};
     put(ptrs, sizeof(ptrs));
     const int64_t sizes[4] = {B.rstride, B.rcap, B.tcap, B.vstride};
     put(sizes, sizeof(sizes));
@@ -891,7 +981,7 @@ gsim_status gsim_create(int device, gsim_precision prec, void *hip_stream, gsim_
     c->gp.tie_rel = 1e-9;
     c->gp.guard_rel = 1e-4;
     c->gp.tie_dir = 1e-6;
-    c->gp.cone_tol32 = 1e-5;
+    c->gp.cone_tol32 = 1e-6;  // 16 times the FP32 rounding of window interval ends
     c->gp.tie_rel32 = 1e-4;
     c->gp.tie_dir32 = 5e-6;
     c->gp.root_rel32 = 2e-6;
@@ -943,7 +1033,7 @@ void gsim_destroy(gsim_ctx *c) {
         delete ms;
     }
     for (Buf *b : {&c->stack, &c->work, &c->ctr, &c->wstats, &c->scan_scratch, &c->sum_scratch, &c->pf_over,
-                   &c->prof, &c->desc, &c->vdist, &c->ttab, &c->roots, &c->partials, &c->vbits})
+                   &c->prof, &c->desc, &c->vdist, &c->ttab, &c->roots, &c->partials, &c->vbits, &c->gtab})
         release(*b);
     if (c->desc_pinned) (void)hipHostFree(c->desc_pinned);
     if (c->own_stream) (void)hipStreamDestroy(c->stream);
@@ -1220,19 +1310,7 @@ gsim_status gsim_voronoi_neighbours(gsim_ctx *c, int32_t id, int64_t *off, int32
     try {
         hipStream_t s = c->stream;
         const DevMesh &m = ms->dm;
-        if (!(ms->area > 0.0)) {
-            double A = 0.0;
-            const HostMesh &H = ms->host;
-            for (int f = 0; f < H.nf; ++f) {
-                const double *p0 = &H.V[3 * (size_t)H.T[3 * f]], *p1 = &H.V[3 * (size_t)H.T[3 * f + 1]],
-                             *p2 = &H.V[3 * (size_t)H.T[3 * f + 2]];
-                const double u[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
-                const double v[3] = {p2[0] - p0[0], p2[1] - p0[1], p2[2] - p0[2]};
-                const double x = u[1] * v[2] - u[2] * v[1], y = u[2] * v[0] - u[0] * v[2], z = u[0] * v[1] - u[1] * v[0];
-                A += 0.5 * std::sqrt(x * x + y * y + z * z);
-            }
-            ms->area = A;
-        }
+        surface_area(ms);
         // particle cell grid: cells about one and a half mean spacings wide
         int dims[3];
         double cell;

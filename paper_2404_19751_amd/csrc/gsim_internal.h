@@ -197,8 +197,11 @@ struct SurfDesc {
 };
 
 // Capacity of a candidate row: the most Euclidean candidates one source may
-// have (its targets live in an LDS table of the geodesic kernel).
+// have with its targets in an LDS table of the geodesic kernel. Batches with
+// more use the kernel's big-candidate instantiation (targets in global
+// memory, rows as wide as the largest count needs), up to kBigCandMax.
 constexpr int kCandCap = 128;
+constexpr int kBigCandMax = 4096;
 // Most particles on one surface in all-pairs mode: the n x n pair slots of
 // the row arrays (37 bytes each) stay within 32-bit indices.
 constexpr int kAllPairsMax = 46340;
@@ -242,9 +245,15 @@ struct GeoShape {
 // With `fuse`, each source particle is also moved (force from its row,
 // integrator, walk) into the next-state arrays once its row is final. Non-null
 // ev0/ev1 are recorded by the dispatch at the kernel's start and end.
+// gcap > 0 selects the big-candidate instantiation: every surface's rows are
+// sd.cap wide (at most kBigCandMax) and each resident wavefront keeps its
+// source's target arrays for up to gcap targets in gtab
+// (geodesic_gtab_bytes(gcap) bytes per wavefront).
 hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoParams &gp, const GeoShape &shape,
                            char *stack_mem, char *roots, int64_t rstride, int rcap, int32_t *work_ctr, Counters *ctr,
-                           bool fp32, bool fuse, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                           bool fp32, bool fuse, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
+                           char *gtab = nullptr, int gcap = 0);
+int64_t geodesic_gtab_bytes(int gcap);
 // All-pairs geodesics (no cutoff) for every source of the batch: every other
 // particle of the surface is a target. vdist: per resident wavefront a table
 // of vstride vertex distances; roots: per resident wavefront a bend-vertex
@@ -286,7 +295,7 @@ hipError_t launch_fire_control(const SurfDesc *desc, const BatchIdx &blk, double
                                hipStream_t s);
 
 // LDS bytes of one geodesic workgroup for a stack size (occupancy planning)
-size_t geodesic_lds_bytes(int lds_stack_kb, bool fp32);
+size_t geodesic_lds_bytes(int lds_stack_kb, bool fp32, bool big = false);
 // positions + cell counting sort, one workgroup per surface (every surface's
 // grid must have at most kSmallCells cells)
 constexpr int kSmallCells = 4096;
@@ -310,7 +319,7 @@ hipError_t launch_update_batch(const SurfDesc *desc, const BatchIdx &bi, int blo
 // next state -> current state for every particle of the batch
 hipError_t launch_commit_batch(const SurfDesc *desc, const BatchIdx &bi, hipStream_t s);
 // resident geodesic workgroups per compute unit for a stack size (0 on error)
-int geodesic_blocks_per_cu(int lds_stack_kb, bool fp32);
+int geodesic_blocks_per_cu(int lds_stack_kb, bool fp32, bool big = false);
 
 hipError_t launch_bin_scatter(int n, PrefilterBufs &b, hipStream_t s);
 hipError_t launch_i64_to_i32(const int64_t *in, int32_t *out, int n, hipStream_t s);
@@ -333,6 +342,9 @@ hipError_t launch_forces_rows(int n, const int32_t *cnt, int cap_c, const double
 // zero beforehand.
 hipError_t launch_validate_state(int nf, int n, const int32_t *face, const double *bary, const double *vel,
                                  int32_t *bad, hipStream_t s);
+// cnt[i] = the particles j != i within sqrt(cut2) of particle i, from the
+// cell lists in b (cells no smaller than the cutoff)
+hipError_t launch_count_candidates(int n, const PrefilterBufs &b, double cut2, int32_t *cnt, hipStream_t s);
 hipError_t launch_sum(const double *x, int n, double *out, double *scratch, hipStream_t s);
 hipError_t launch_integrate(const DevMesh &m, int n, const int32_t *face, const double *F, int kind, double dt,
                             double mobility, double kT, double friction, uint64_t seed, uint64_t step,

@@ -64,6 +64,7 @@
 #include <hip/hip_ext.h>
 
 #include <cmath>
+#include <type_traits>
 
 #include "gsim_internal.h"
 #include "walk.h"
@@ -76,6 +77,7 @@ using namespace wnd;
 
 constexpr int kMaxCand = kCandCap;
 constexpr int kHash = 256;
+constexpr int kBigStk = 8192;  // LDS window stack of the big-candidate instantiation
 constexpr int kChunks = 8;
 static_assert(kChunks == kWorkChunks, "one work counter per chunk");
 
@@ -90,9 +92,21 @@ struct GeoArgs {
     char *roots;         // per wave: a bend-vertex table (rstride bytes, rcap vertices)
     int64_t rstride;
     int rcap;
+    char *gtab;          // big-candidate mode: per wave the target arrays of gcap targets (gstride bytes)
+    int64_t gstride;
+    int gcap;
 };
 
+// The target table of one source: per candidate target its index, face,
+// next target of the same face bucket, barycentrics, position with the
+// current pruning bound, best and other-direction distances and the best
+// tangent; a hash of faces to chains of targets; the bend-vertex state.
+// Either all in LDS (at most kMaxCand targets, Lds), or, for sources with
+// more candidates, the per-target arrays in a per-wavefront global area and
+// the rest in LDS (GTab): the helpers below are written once for both.
 struct Lds {
+    static constexpr bool kBig = false;
+    static constexpr int kBuckets = kHash;
     int32_t tj[kMaxCand], tface[kMaxCand], tnext[kMaxCand];
     double tb[kMaxCand][3];
     alignas(16) double cb[kMaxCand][4];  // target position and current pruning bound
@@ -102,14 +116,57 @@ struct Lds {
     BendLds B;
 };
 
-__device__ inline int hash_face(int f) { return (int)(((uint32_t)f * 2654435761u) >> 24) & (kHash - 1); }
+// Big-candidate mode: hash heads, the bend-vertex state and the sort buffer
+// of the candidate search in LDS.
+constexpr int kBigHash = 1024;
+constexpr int kBigSort = kBigCandMax;  // candidates are sorted in LDS
+struct LdsBig {
+    int32_t head[kBigHash];
+    int32_t ncand;
+    int32_t key[kBigSort];
+    BendLds B;
+};
+struct GTab {
+    static constexpr bool kBig = true;
+    static constexpr int kBuckets = kBigHash;
+    int32_t *tj, *tface, *tnext;
+    double (*tb)[3];
+    double (*cb)[4];
+    double *d1, *d2, *t1x, *t1y;
+    int32_t *head;
+    int32_t &ncand;
+    BendLds &B;
+};
+// Bytes of one wavefront's global target arrays for gcap targets.
+__host__ __device__ inline int64_t gtab_bytes(int gcap) { return ((int64_t)gcap * 100 + 255) / 256 * 256; }
+__device__ inline GTab gtab_of(char *base, int64_t stride, int slot, int gcap, LdsBig &LB) {
+    char *p = base + (int64_t)slot * stride;
+    double *dp = reinterpret_cast<double *>(p);  // the doubles first: 11 per target
+    double(*cb)[4] = reinterpret_cast<double(*)[4]>(dp);
+    double(*tb)[3] = reinterpret_cast<double(*)[3]>(dp + 4 * (int64_t)gcap);
+    double *d1 = dp + 7 * (int64_t)gcap;
+    int32_t *ip = reinterpret_cast<int32_t *>(dp + 11 * (int64_t)gcap);
+    return GTab{ip, ip + gcap, ip + 2 * (int64_t)gcap, tb, cb, d1, d1 + gcap, d1 + 2 * (int64_t)gcap,
+                d1 + 3 * (int64_t)gcap, LB.head, LB.ncand, LB.B};
+}
 
-__device__ inline int first_in_face(const Lds &L, int f) {
-    int s = L.head[hash_face(f)];
+// Multiplicative hash of a face index: the top bits of f times the golden
+// ratio in 32-bit fixed point (256 buckets: the top 8 bits).
+template <class TL>
+__device__ inline int hash_face(int f) {
+    constexpr int kShift = TL::kBuckets == 256 ? 24 : 22;
+    static_assert(TL::kBuckets == 256 || TL::kBuckets == 1024, "bucket counts");
+    return (int)(((uint32_t)f * 2654435761u) >> kShift) & (TL::kBuckets - 1);
+}
+
+template <class TL>
+__device__ inline int first_in_face(const TL &L, int f) {
+    int s = L.head[hash_face<TL>(f)];
     while (s >= 0 && L.tface[s] != f) s = L.tnext[s];
     return s;
 }
-__device__ inline int next_in_face(const Lds &L, int s, int f) {
+template <class TL>
+__device__ inline int next_in_face(const TL &L, int s, int f) {
     s = L.tnext[s];
     while (s >= 0 && L.tface[s] != f) s = L.tnext[s];
     return s;
@@ -129,8 +186,12 @@ struct Ctx {
 // the rest of the path.) Targets are tested four at a time, so that their
 // independent load and arithmetic chains overlap; the bound table is padded
 // to a multiple of four with entries that no path can reach.
-__device__ inline bool reaches_target(const Lds &L, const Ctx &C, const double P[3], const double u[3], double x0,
+template <class TL>
+__device__ inline bool reaches_target(const TL &L, const Ctx &C, const double P[3], const double u[3], double x0,
                                       double x1, double base) {
+    // with more targets than the LDS table holds, nearly every window within
+    // the cutoff can still improve one of them: only the cutoff prunes
+    if constexpr (TL::kBig) return base < C.cut_acc;
     for (int s0 = 0; s0 < C.nc4; s0 += 4) {
         bool hit = false;
 #pragma unroll
@@ -154,7 +215,8 @@ __device__ inline bool reaches_target(const Lds &L, const Ctx &C, const double P
 // distance among candidates whose direction differs (tie gap); `alt` is the
 // distance of another-direction path that comes with the candidate (through
 // a bend vertex with a second distance).
-__device__ inline void target_update(Lds &L, const Ctx &C, bool ok, int slot, double d, double tx, double ty,
+template <class TL>
+__device__ inline void target_update(TL &L, const Ctx &C, bool ok, int slot, double d, double tx, double ty,
                                      double alt) {
     // candidates no shorter than both distances (which only decrease) change nothing
     if (ok && d >= L.d1[slot] && d >= L.d2[slot] && alt >= L.d2[slot]) ok = false;
@@ -184,9 +246,9 @@ __device__ inline void target_update(Lds &L, const Ctx &C, bool ok, int slot, do
 // Both children of a window. F3: the face's vertices in 3D in the order
 // (A, B, C) = (tail, head, opposite) of the entry half-edge; U3: the unit
 // directions of the half-edges (A->B, B->C, C->A).
-template <typename R>
+template <typename R, class TL>
 __device__ inline void children(const He<R> &h, const Win<R> &w, double txc, bool full, const Ctx &C,
-                                const double F3[3][3], const double U3[3][3], const Lds &L, Win<R> &cl, bool &hl,
+                                const double F3[3][3], const double U3[3][3], const TL &L, Win<R> &cl, bool &hl,
                                 Win<R> &cr, bool &hr, int &pruned) {
     hl = false;
     hr = false;
@@ -229,8 +291,8 @@ struct SrcStats {
 // are compacted into a list and their fans flattened over the lanes, a chunk
 // of vertices at a time, so one launch round costs a few memory round trips,
 // not one per vertex.
-template <typename R>
-__device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, Lds &L, const BendTable &G, const Ctx &C,
+template <typename R, class TL>
+__device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, TL &L, const BendTable &G, const Ctx &C,
                              Stack<R> &S, SrcStats &st) {
     const int lane = lane_id();
     const DevMesh &M = sd.m;
@@ -311,8 +373,9 @@ __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, Lds &L, const
                 }
                 const PseudoRec pr = M.prec[e];
                 const double D = G.rD[e];
-                bool useful = false;
-                for (int s = 0; s < C.nc && !useful; ++s) {
+                // big-candidate mode: every vertex within the cutoff (as for windows)
+                bool useful = TL::kBig;
+                for (int s = 0; !TL::kBig && s < C.nc && !useful; ++s) {
                     const double bound = L.cb[s][3] - D;
                     const double q0 = L.cb[s][0] - pr.x, q1 = L.cb[s][1] - pr.y, q2 = L.cb[s][2] - pr.z;
                     useful = bound > 0.0 && q0 * q0 + q1 * q1 + q2 * q2 < bound * bound;
@@ -444,12 +507,104 @@ __device__ int find_candidates(const SurfDesc &sd, Lds &L, int src, int64_t c0) 
     return total;
 }
 
+// The Euclidean prefilter of one source in big-candidate mode: the 27 cells'
+// particle ranges are flattened over the lanes, the hits collected in LDS,
+// bitonic-sorted by particle index and written to the table and the row.
+// Returns the true count (more than cap is an overflow the caller reports).
+__device__ int find_candidates_big(const SurfDesc &sd, LdsBig &LB, GTab &T, int src, int64_t c0, int cap) {
+    const int lane = lane_id();
+    if (lane == 0) LB.ncand = 0;
+    const double xi = sd.xyz[3 * (int64_t)src], yi = sd.xyz[3 * (int64_t)src + 1], zi = sd.xyz[3 * (int64_t)src + 2];
+    const int lin = sd.cell_of[src];
+    const int cx = lin % sd.dims[0], cy = (lin / sd.dims[0]) % sd.dims[1], cz = lin / (sd.dims[0] * sd.dims[1]);
+    // lane l < 27: the particle range of neighbour cell l
+    int b = 0, e = 0;
+    if (lane < 27) {
+        const int x = cx + lane % 3 - 1, y = cy + (lane / 3) % 3 - 1, z = cz + lane / 9 - 1;
+        if (x >= 0 && x < sd.dims[0] && y >= 0 && y < sd.dims[1] && z >= 0 && z < sd.dims[2]) {
+            const int c = (z * sd.dims[1] + y) * sd.dims[0] + x;
+            b = sd.cell_start[c];
+            e = sd.cell_start[c + 1];
+        }
+    }
+    int inc = e - b;
+    for (int o = 1; o < kWave; o <<= 1) {
+        const int y = __shfl_up(inc, o);
+        if (lane >= o) inc += y;
+    }
+    const int total_in = __builtin_amdgcn_readlane(inc, 26);
+    const int excl = inc - (e - b);
+    // every cell's start in the flattened order and in the particle order, wave-uniform
+    int cs[27], cb0[27];
+#pragma unroll
+    for (int l = 0; l < 27; ++l) {
+        cs[l] = __builtin_amdgcn_readlane(excl, l);
+        cb0[l] = __builtin_amdgcn_readlane(b, l);
+    }
+    __syncthreads();
+    for (int q0 = 0; q0 < total_in; q0 += kWave) {
+        const int q = q0 + lane;
+        if (q >= total_in) continue;
+        // the cell holding flattened position q: the last one starting at or before q
+        int cell = 0;
+#pragma unroll
+        for (int l = 1; l < 27; ++l) cell = cs[l] <= q ? l : cell;
+        int base = cb0[0], st0 = cs[0];
+#pragma unroll
+        for (int l = 1; l < 27; ++l)
+            if (cell == l) {
+                base = cb0[l];
+                st0 = cs[l];
+            }
+        const int j = sd.order[base + (q - st0)];
+        if (j == src) continue;
+        const double ex = sd.xyz[3 * (int64_t)j] - xi, ey = sd.xyz[3 * (int64_t)j + 1] - yi,
+                     ez = sd.xyz[3 * (int64_t)j + 2] - zi;
+        if (ex * ex + ey * ey + ez * ez < sd.cut2) {
+            const int pos = atomicAdd(&LB.ncand, 1);
+            if (pos < kBigSort) LB.key[pos] = j;
+        }
+    }
+    __syncthreads();
+    const int total = LB.ncand;
+    const int m = min(total, min(cap, kBigSort));
+    int P = 1;
+    while (P < m) P <<= 1;
+    for (int s = m + lane; s < P; s += kWave) LB.key[s] = 0x7fffffff;
+    __syncthreads();
+    // bitonic sort of key[0, P) ascending
+    for (int k = 2; k <= P; k <<= 1) {
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int s = lane; s < P; s += kWave) {
+                const int t = s ^ jj;
+                if (t > s) {
+                    const int a0 = LB.key[s], a1 = LB.key[t];
+                    const bool up = (s & k) == 0;
+                    if ((a0 > a1) == up) {
+                        LB.key[s] = a1;
+                        LB.key[t] = a0;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int s = lane; s < m; s += kWave) {
+        const int j = LB.key[s];
+        T.tj[s] = j;
+        sd.cand[c0 + s] = j;
+    }
+    if (lane == 0) sd.cand_cnt[src] = total;
+    __syncthreads();
+    return total;
+}
+
 // Geodesics from one source to its candidate targets; writes the row and
 // returns whether any pair lies inside the guard band of the cutoff. Always
 // inlined: the FP32-mixed kernel holds both precisions' loops, and a call to
 // the FP64 one would make the FP32 loop spill registers around it.
-template <typename R>
-__device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &a, const SurfDesc &sd, Lds &L, unsigned char *stk, int stk_bytes, int src,
+template <typename R, class TL>
+__device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &a, const SurfDesc &sd, TL &L, unsigned char *stk, int stk_bytes, int src,
                            int64_t c0, int nc, bool guard_mode, int slot_id, SrcStats &st) {
     const int lane = lane_id();
     const long long t_start = clock64();
@@ -482,7 +637,7 @@ __device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &
     S.gsp = 0;
 
     // ---- LDS tables
-    for (int e = lane; e < kHash; e += kWave) L.head[e] = -1;
+    for (int e = lane; e < TL::kBuckets; e += kWave) L.head[e] = -1;
     if (lane == 0) {
         L.B.npend = 0;
         L.B.ntouched = 0;
@@ -501,7 +656,7 @@ __device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &
         L.d2[s] = INFINITY;
         L.t1x[s] = 0.0;
         L.t1y[s] = 0.0;
-        L.tnext[s] = atomicExch(&L.head[hash_face(f)], s);
+        L.tnext[s] = atomicExch(&L.head[hash_face<TL>(f)], s);
     }
     if (nc + lane < C.nc4) {
         L.cb[nc + lane][0] = L.cb[nc + lane][1] = L.cb[nc + lane][2] = 0.0;
@@ -831,10 +986,12 @@ __device__ __attribute__((always_inline)) inline int fused_move(const SurfDesc &
 // compiles to fewer registers; 2: as 1, and the source particle is then moved
 // (the fused update). Only mode 2 holds the update's code, which would
 // otherwise change the register allocation of every launch.
-template <bool kMixed, int kStk, int kMode>
+// kBig: the big-candidate instantiation (targets in a per-wavefront global
+// area, rows as wide as the surface's row capacity).
+template <bool kMixed, int kStk, int kMode, bool kBig>
 __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
     constexpr bool kOne = kMode >= 1, kFuse = kMode == 2;
-    __shared__ Lds L;
+    __shared__ typename std::conditional<kBig, LdsBig, Lds>::type L;
     __shared__ alignas(16) unsigned char stk[kStk];
     const int lane = lane_id();
     const int total = a.bi.begin[a.bi.nsurf];
@@ -887,22 +1044,34 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
         const int si = __builtin_amdgcn_readfirstlane(batch_surface(a.bi, idx));
         const SurfDesc &sd = a.sd[si];
         const int src = sd.order[idx - a.bi.begin[si]];
-        const int64_t c0 = (int64_t)src * kMaxCand;
-        const int nc = find_candidates(sd, L, src, c0);
-        if (nc > kMaxCand) {
-            if (lane == 0) ++c_limited;
-        } else if (nc > 0) {
-            st.overflow = false;
-            if (kMixed) {
-                // FP32 pass; a pair inside the guard band sends the source through FP64
-                if (run_source<float>(a, sd, L, stk, kStk, src, c0, nc, false, blockIdx.x, st)) {
-                    run_source<double>(a, sd, L, stk, kStk, src, c0, nc, true, blockIdx.x, st);
-                    ++st.guards;
+        // the propagation of one source over its target table
+        auto process = [&](auto &T, int64_t c0, int nc, int cap) {
+            if (nc > cap) {
+                if (lane == 0) ++c_limited;
+            } else if (nc > 0) {
+                st.overflow = false;
+                if (kMixed) {
+                    // FP32 pass; a pair inside the guard band sends the source through FP64
+                    if (run_source<float>(a, sd, T, stk, kStk, src, c0, nc, false, blockIdx.x, st)) {
+                        run_source<double>(a, sd, T, stk, kStk, src, c0, nc, true, blockIdx.x, st);
+                        ++st.guards;
+                    }
+                } else {
+                    run_source<double>(a, sd, T, stk, kStk, src, c0, nc, false, blockIdx.x, st);
                 }
-            } else {
-                run_source<double>(a, sd, L, stk, kStk, src, c0, nc, false, blockIdx.x, st);
+                if (st.overflow) ++c_limited;
             }
-            if (st.overflow) ++c_limited;
+        };
+        if constexpr (kBig) {
+            const int cap = min(sd.cap, min(a.gcap, kBigSort));
+            const int64_t c0 = (int64_t)src * sd.cap;
+            GTab T = gtab_of(a.gtab, a.gstride, blockIdx.x, a.gcap, L);
+            const int nc = find_candidates_big(sd, L, T, src, c0, cap);
+            process(T, c0, nc, cap);
+        } else {
+            const int64_t c0 = (int64_t)src * kMaxCand;
+            const int nc = find_candidates(sd, L, src, c0);
+            process(L, c0, nc, kMaxCand);
         }
         if (kOne) {
             // one source per workgroup (in mode 2 its particle is moved below)
@@ -940,32 +1109,35 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
     }
 }
 
-template <bool kMixed, int kStk, int kMode>
+template <bool kMixed, int kStk, int kMode, bool kBig>
 void launch_one(int nslots, size_t pad, const GeoArgs &a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (ev0 || ev1)
-        hipExtLaunchKernelGGL((k_geodesic<kMixed, kStk, kMode>), dim3(nslots), dim3(kWave), (uint32_t)pad, s, ev0, ev1,
-                              0, a);
-    else hipLaunchKernelGGL((k_geodesic<kMixed, kStk, kMode>), dim3(nslots), dim3(kWave), pad, s, a);
+        hipExtLaunchKernelGGL((k_geodesic<kMixed, kStk, kMode, kBig>), dim3(nslots), dim3(kWave), (uint32_t)pad, s, ev0,
+                              ev1, 0, a);
+    else hipLaunchKernelGGL((k_geodesic<kMixed, kStk, kMode, kBig>), dim3(nslots), dim3(kWave), pad, s, a);
 }
 template <bool kMixed, int kMode>
-void launch_stack(int kb, int nslots, size_t pad, const GeoArgs &a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-    if (kb <= 4) launch_one<kMixed, 4096, kMode>(nslots, pad, a, s, ev0, ev1);
-    else if (kb <= 8) launch_one<kMixed, 8192, kMode>(nslots, pad, a, s, ev0, ev1);
-    else launch_one<kMixed, 16384, kMode>(nslots, pad, a, s, ev0, ev1);
+void launch_stack(int kb, bool big, int nslots, size_t pad, const GeoArgs &a, hipStream_t s, hipEvent_t ev0,
+                  hipEvent_t ev1) {
+    if (big) launch_one<kMixed, kBigStk, kMode, true>(nslots, pad, a, s, ev0, ev1);
+    else if (kb <= 4) launch_one<kMixed, 4096, kMode, false>(nslots, pad, a, s, ev0, ev1);
+    else if (kb <= 8) launch_one<kMixed, 8192, kMode, false>(nslots, pad, a, s, ev0, ev1);
+    else launch_one<kMixed, 16384, kMode, false>(nslots, pad, a, s, ev0, ev1);
 }
 template <bool kMixed>
-void launch_variant(int mode, int kb, int nslots, size_t pad, const GeoArgs &a, hipStream_t s, hipEvent_t ev0,
-                    hipEvent_t ev1) {
-    if (mode == 2) launch_stack<kMixed, 2>(kb, nslots, pad, a, s, ev0, ev1);
-    else if (mode == 1) launch_stack<kMixed, 1>(kb, nslots, pad, a, s, ev0, ev1);
-    else launch_stack<kMixed, 0>(kb, nslots, pad, a, s, ev0, ev1);
+void launch_variant(int mode, int kb, bool big, int nslots, size_t pad, const GeoArgs &a, hipStream_t s,
+                    hipEvent_t ev0, hipEvent_t ev1) {
+    if (mode == 2) launch_stack<kMixed, 2>(kb, big, nslots, pad, a, s, ev0, ev1);
+    else if (mode == 1) launch_stack<kMixed, 1>(kb, big, nslots, pad, a, s, ev0, ev1);
+    else launch_stack<kMixed, 0>(kb, big, nslots, pad, a, s, ev0, ev1);
 }
 
 }  // namespace
 
 hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoParams &gp, const GeoShape &shape,
                            char *stack_mem, char *roots, int64_t rstride, int rcap, int32_t *work_ctr, Counters *ctr,
-                           bool fp32, bool fuse, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+                           bool fp32, bool fuse, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, char *gtab,
+                           int gcap) {
     GeoArgs a;
     a.sd = desc;
     a.bi = bi;
@@ -981,31 +1153,40 @@ hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoPa
     a.roots = roots;
     a.rstride = rstride;
     a.rcap = rcap;
+    const bool big = gcap > 0;
+    a.gtab = gtab;
+    a.gstride = big ? gtab_bytes(gcap) : 0;
+    a.gcap = gcap;
 
     if (shape.nslots < 1 || total < 1) return hipSuccess;
     if (fuse && total > shape.nslots) return hipErrorInvalidValue;  // the fused update needs a slot per source
+    if (big && (!gtab || gcap > kBigCandMax)) return hipErrorInvalidValue;
     const size_t pad = shape.pad_lds > 0 ? (size_t)shape.pad_lds : 0;
-    if (fp32) launch_variant<true>(mode, shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
-    else launch_variant<false>(mode, shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
+    if (fp32) launch_variant<true>(mode, shape.lds_stack_kb, big, shape.nslots, pad, a, s, ev0, ev1);
+    else launch_variant<false>(mode, shape.lds_stack_kb, big, shape.nslots, pad, a, s, ev0, ev1);
     return hipGetLastError();
 }
 
-int geodesic_blocks_per_cu(int lds_stack_kb, bool fp32) {
+int geodesic_blocks_per_cu(int lds_stack_kb, bool fp32, bool big) {
     int nb = 0;
     const void *f;
-    if (lds_stack_kb <= 4)
-        f = fp32 ? (const void *)&k_geodesic<true, 4096, 0> : (const void *)&k_geodesic<false, 4096, 0>;
+    if (big) f = fp32 ? (const void *)&k_geodesic<true, kBigStk, 0, true> : (const void *)&k_geodesic<false, kBigStk, 0, true>;
+    else if (lds_stack_kb <= 4)
+        f = fp32 ? (const void *)&k_geodesic<true, 4096, 0, false> : (const void *)&k_geodesic<false, 4096, 0, false>;
     else if (lds_stack_kb <= 8)
-        f = fp32 ? (const void *)&k_geodesic<true, 8192, 0> : (const void *)&k_geodesic<false, 8192, 0>;
-    else f = fp32 ? (const void *)&k_geodesic<true, 16384, 0> : (const void *)&k_geodesic<false, 16384, 0>;
+        f = fp32 ? (const void *)&k_geodesic<true, 8192, 0, false> : (const void *)&k_geodesic<false, 8192, 0, false>;
+    else f = fp32 ? (const void *)&k_geodesic<true, 16384, 0, false> : (const void *)&k_geodesic<false, 16384, 0, false>;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, f, kWave, 0) != hipSuccess) return 0;
     return nb;
 }
 
-size_t geodesic_lds_bytes(int lds_stack_kb, bool) {
+size_t geodesic_lds_bytes(int lds_stack_kb, bool, bool big) {
+    if (big) return sizeof(LdsBig) + (size_t)kBigStk;
     const int kb = lds_stack_kb <= 4 ? 4 : (lds_stack_kb <= 8 ? 8 : 16);
     return sizeof(Lds) + (size_t)kb * 1024;
 }
+
+int64_t geodesic_gtab_bytes(int gcap) { return gtab_bytes(gcap); }
 
 
 }  // namespace gsim

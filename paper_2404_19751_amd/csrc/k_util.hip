@@ -273,6 +273,31 @@ __global__ void k_forces_rows(int n, const int32_t *__restrict__ cnt, int cap, c
     if (nonfinite) wave_atomic_add(nonfinite, bad ? 1ull : 0ull);
 }
 
+// Euclidean candidates of every particle: the particles within the cutoff
+// in the 27 cells around it (cells no smaller than the cutoff).
+__global__ void k_count_candidates(int n, const double *__restrict__ xyz, const int32_t *__restrict__ cell_of,
+                                   const int32_t *__restrict__ cell_start, const int32_t *__restrict__ order,
+                                   int dx, int dy, int dz, double cut2, int32_t *__restrict__ cnt) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const double xi = xyz[3 * (int64_t)i], yi = xyz[3 * (int64_t)i + 1], zi = xyz[3 * (int64_t)i + 2];
+    const int lin = cell_of[i];
+    const int cx = lin % dx, cy = (lin / dx) % dy, cz = lin / (dx * dy);
+    int m = 0;
+    for (int z = max(cz - 1, 0); z <= min(cz + 1, dz - 1); ++z)
+        for (int y = max(cy - 1, 0); y <= min(cy + 1, dy - 1); ++y)
+            for (int x = max(cx - 1, 0); x <= min(cx + 1, dx - 1); ++x) {
+                const int c = (z * dy + y) * dx + x;
+                for (int q = cell_start[c]; q < cell_start[c + 1]; ++q) {
+                    const int j = order[q];
+                    const double ex = xyz[3 * (int64_t)j] - xi, ey = xyz[3 * (int64_t)j + 1] - yi,
+                                 ez = xyz[3 * (int64_t)j + 2] - zi;
+                    m += j != i && ex * ex + ey * ey + ez * ez < cut2;
+                }
+            }
+    cnt[i] = m;
+}
+
 // A particle state is usable when every face index is in range and every
 // barycentric triple lies in the face, sums to 1 and is not a vertex (the
 // conditions the host path checks too), and every velocity is finite.
@@ -543,6 +568,12 @@ hipError_t launch_forces_rows(int n, const int32_t *cnt, int cap_c, const double
                               hipStream_t s) {
     hipLaunchKernelGGL(k_forces_rows, dim3(nblocks(n)), dim3(kBlock), 0, s, n, cnt, cap_c, dist, tan, cutoff, kind, k,
                        sigma, F, Ei, npairs, pflags, nonfinite);
+    return hipGetLastError();
+}
+hipError_t launch_count_candidates(int n, const PrefilterBufs &b, double cut2, int32_t *cnt, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_count_candidates, dim3(nblocks(n)), dim3(kBlock), 0, s, n, b.xyz, b.cell_of, b.cell_start,
+                       b.order, b.dims[0], b.dims[1], b.dims[2], cut2, cnt);
     return hipGetLastError();
 }
 hipError_t launch_validate_state(int nf, int n, const int32_t *face, const double *bary, const double *vel,

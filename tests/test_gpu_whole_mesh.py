@@ -52,7 +52,7 @@ def test_whole_mesh_cutoff_matches_oracle(torus_case, prec):
         g = ctx.geodesic_pairs(mid, cut)
         cnt = ctx.counters()
         assert cnt["limited"] == 0
-        assert np.diff(o.off).max() > 128  # more neighbours than the cutoff kernel's rows hold
+        assert np.diff(o.off).max() > 128  # more neighbours than the cutoff kernel's LDS table holds
         if prec == "fp64":
             err = compare_pairs(g, o, W.mean_edge_length(m), label="torus_a3")
         else:
@@ -62,17 +62,36 @@ def test_whole_mesh_cutoff_matches_oracle(torus_case, prec):
         ctx.close()
 
 
-def test_cutoff_kernel_reports_the_limit(torus_case):
-    """The same case on the cutoff kernel exceeds its per-source candidate
-    rows: a limit error, not a partial result."""
-    from paper_2404_19751_amd import gsim
+def test_cutoff_kernel_takes_wide_patches(torus_case):
+    """The same case on the cutoff kernel, whose sources have more candidates
+    than its LDS table holds: the big-candidate instantiation matches the
+    oracle too."""
     m, f, b, cut, o, _ = torus_case
     ctx = _ctx("fp64", False)
     try:
         mid = ctx.mesh_upload(m.V, m.T)
         ctx.particles_set(mid, f, b)
+        g = ctx.geodesic_pairs(mid, cut)
+        assert ctx.counters()["limited"] == 0
+        err = compare_pairs(g, o, W.mean_edge_length(m), label="torus_a3 cutoff kernel")
+        log(f"[gpu-whole] torus a3 on the cutoff kernel: {len(o.dist)} pairs, err {err:.2e}")
+    finally:
+        ctx.close()
+
+
+def test_cutoff_kernel_reports_its_limit():
+    """More Euclidean candidates per source than the big-candidate kernel
+    takes (4096): a limit error naming the whole-mesh knob, not a partial
+    result."""
+    from paper_2404_19751_amd import gsim
+    m = W.icosphere(3)
+    f, b = W.random_particles(m.nf, 5000, 3)
+    ctx = _ctx("fp64", False)
+    try:
+        mid = ctx.mesh_upload(m.V, m.T)
+        ctx.particles_set(mid, f, b)
         with pytest.raises(gsim.GsimError) as e:
-            ctx.geodesic_pairs(mid, cut)
+            ctx.geodesic_pairs(mid, 3.0)
         assert e.value.status == gsim.E_LIMIT
         assert "whole_mesh" in str(e.value)
     finally:
