@@ -60,6 +60,9 @@ def lib():
         L.orc_pairs_export.argtypes = [P] * 9
         L.orc_pairs_counters.argtypes = [P, P]
         L.orc_pairs_free.argtypes = [P]
+        L.orc_geodesic_pairs_windows.argtypes = [P, C.c_int, P, P, C.c_double, C.c_int, P, C.c_int]
+        L.orc_geodesic_pairs_windows.restype = P
+        L.orc_pairs_window_counters.argtypes = [P, P]
         L.orc_walk.argtypes = [P, C.c_int, P, P, P, P, P, P]
         L.orc_walk.restype = C.c_int
         L.orc_philox4x32_10.argtypes = [P, P, P]
@@ -174,6 +177,45 @@ def geodesic_pairs(mesh: OracleMesh, face, bary, cutoff, sources=None, nthreads=
     return Pairs(off, nbr, dist, tan, flags, tie_off, tie_tan, tie_dist,
                  dict(windows=int(cnt[0]), pruned=int(cnt[1]), roots=int(cnt[2]), improvements=int(cnt[3]),
                       rejected=int(cnt[4])), float(tie_rel), float(cone_slack))
+
+
+def geodesic_pairs_windows(mesh: OracleMesh, face, bary, cutoff, sources=None, nthreads=0) -> Pairs:
+    """The pairs of ``geodesic_pairs`` by the exact window-propagation method
+    of Sec. 2.2 (MMP's continuous Dijkstra: windows on half-edges, processed
+    in distance order, trimmed to the pointwise minimum on every edge;
+    pseudo-source vertices launched once). An independent route to the same
+    distances, and the method's own work count: ``counters`` holds windows
+    inserted, propagated and trimmed, pseudo-source launches, faces entered,
+    insertions dropped and sources rejected. One direction per pair (no tie
+    sets; the tie flag is never set)."""
+    face = np.ascontiguousarray(face, np.int32)
+    bary = np.ascontiguousarray(bary, np.float64)
+    src = None if sources is None else np.ascontiguousarray(sources, np.int32)
+    nsrc = face.shape[0] if src is None else src.shape[0]
+    L = lib()
+    h = L.orc_geodesic_pairs_windows(mesh._h, face.shape[0], _p(face), _p(bary),
+                                     float(cutoff if math.isfinite(cutoff) else -1.0), nsrc,
+                                     None if src is None else _p(src), int(nthreads))
+    if not h:
+        raise ValueError("oracle rejected the particle state")
+    try:
+        P = L.orc_pairs_count(h)
+        off = np.empty(nsrc + 1, np.int64)
+        nbr = np.empty(P, np.int32)
+        dist = np.empty(P, np.float64)
+        tan = np.empty((P, 3), np.float64)
+        flags = np.empty(P, np.uint8)
+        tie_off = np.empty(P + 1, np.int64)
+        tie_tan = np.empty((P, 3), np.float64)
+        tie_dist = np.empty(P, np.float64)
+        L.orc_pairs_export(h, _p(off), _p(nbr), _p(dist), _p(tan), _p(flags), _p(tie_off), _p(tie_tan), _p(tie_dist))
+        cnt = np.empty(7, np.int64)
+        L.orc_pairs_window_counters(h, _p(cnt))
+    finally:
+        L.orc_pairs_free(h)
+    names = ("inserted", "propagated", "trimmed", "launches", "faces", "dropped", "rejected")
+    return Pairs(off, nbr, dist, tan, flags, tie_off, tie_tan, tie_dist,
+                 {k: int(v) for k, v in zip(names, cnt)}, 0.0, 0.0)
 
 
 def walk(mesh: OracleMesh, face, bary, disp, vel=None):

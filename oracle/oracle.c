@@ -10,6 +10,8 @@
  *   1. mesh: half-edges, corner angles, pseudo-source vertices (Sec. 2.2)
  *   2. geodesics by brute-force unfolding enumeration + Dijkstra over the
  *      bend vertices (Sec. 2.2 MMP paragraph; Sec. 3.1)
+ *   2b. geodesics by window propagation with trimming (Sec. 2.2, the MMP
+ *      continuous Dijkstra): a second exact route and the method's work count
  *   3. the shift walk (Sec. 3.2, steps (a)-(d), straightest rule at vertices)
  *   4. Philox4x32-10 (noise for the Brownian update of Sec. 2.1)
  */
@@ -231,6 +233,7 @@ struct orc_pairs {
     double *tie_tan, *tie_dist;
     int64_t count, tcount;
     int64_t counters[5];
+    int64_t wcounters[7]; /* window propagation (section 2b) */
 };
 
 typedef struct {
@@ -730,6 +733,585 @@ void orc_pairs_free(orc_pairs *p) {
     free(p->tie_dist);
     free(p);
 }
+
+/* ======================================================================
+ * 2b. Geodesics by window propagation with trimming (the exact method of
+ *     Sec. 2.2: Mitchell, Mount & Papadimitriou's continuous Dijkstra, in
+ *     the interval form of Surazhsky et al.)
+ *
+ * A second, independent route to the exact distances of section 2, and the
+ * method's own measure of work. A window lives on a half-edge h and stands
+ * for the straight rays that enter face(h) across the slice [b0, b1] of h
+ * from one image p of their root: the source, or a pseudo-source vertex at
+ * distance sg. Coordinates are h's edge frame: origin at h's tail A, x
+ * along A->B, y into face(h); the image lies on the other side (py < 0).
+ * Windows are processed in the order of their distance to their slice.
+ * Processing unfolds face(h)'s third vertex C, lowers the distances D(v) of
+ * the vertices the closed cone reaches, and continues the rays into at most
+ * two child windows on the far edges (Sec. 2.2: propagation across a face).
+ * A child is inserted on the twin of its edge after trimming against the
+ * windows already there: on the overlap of two slices each keeps the part
+ * where its distance is the smaller (the pointwise minimum), so a window
+ * may shrink, split or vanish. Every window is a family of real paths, so
+ * trimming never makes a distance too short, and it never cuts a shortest
+ * path: past a point reached by two shortest paths no path is shortest.
+ * A pseudo-source vertex is launched once, at its final distance: windows
+ * from it on the edge opposite it in each face around it, and its
+ * neighbours relaxed along the edges. A target's distance is the minimum
+ * over the source term (same face), the pseudo-source vertices of its face
+ * (D(v) + |v - x|) and the windows on its face's half-edges whose cone
+ * holds it.
+ * ====================================================================== */
+#define WMAXP 256 /* pieces one insertion may hold; beyond it a comparison is skipped (no trim: safe) */
+
+typedef struct {
+    int h, root, alive, done, gen, next;
+    double b0, b1;     /* slice of h, measured from h's tail */
+    double px, py, sg; /* image of the root in h's frame (py < 0), distance of the root */
+    double c, s;       /* source-frame direction of the frame's x axis (source-rooted windows) */
+} wwin;
+
+typedef struct {
+    const orc_mesh *m;
+    double U;                                /* prune bound */
+    wwin *w; int nw, cap;
+    int *hhead; int *htouch; int nht;        /* windows on each half-edge (linked), half-edges used */
+    double *hk; int *hid, *hgen; int hn, hcap; /* heap: key, window id or -1 - vertex, generation */
+    double *D, *Dt;                          /* vertex distance and its tangent (source frame) */
+    unsigned char *launched;
+    int *vtouch; int nvt;
+    unsigned char *fmark; int *ftouch; int nft;
+    int64_t cnt[7];
+} wctx;
+
+static void wheap_push(wctx *c, double k, int id, int gen) {
+    if (c->hn == c->hcap) {
+        c->hcap = c->hcap ? 2 * c->hcap : 1024;
+        c->hk = (double *)realloc(c->hk, sizeof(double) * c->hcap);
+        c->hid = (int *)realloc(c->hid, sizeof(int) * c->hcap);
+        c->hgen = (int *)realloc(c->hgen, sizeof(int) * c->hcap);
+    }
+    int i = c->hn++;
+    while (i > 0) {
+        int p = (i - 1) / 2;
+        if (c->hk[p] <= k) break;
+        c->hk[i] = c->hk[p]; c->hid[i] = c->hid[p]; c->hgen[i] = c->hgen[p];
+        i = p;
+    }
+    c->hk[i] = k; c->hid[i] = id; c->hgen[i] = gen;
+}
+
+static int wheap_pop(wctx *c, double *k, int *id, int *gen) {
+    if (c->hn == 0) return 0;
+    *k = c->hk[0]; *id = c->hid[0]; *gen = c->hgen[0];
+    c->hn--;
+    double lk = c->hk[c->hn]; int lid = c->hid[c->hn], lg = c->hgen[c->hn];
+    int i = 0;
+    for (;;) {
+        int ch = 2 * i + 1;
+        if (ch >= c->hn) break;
+        if (ch + 1 < c->hn && c->hk[ch + 1] < c->hk[ch]) ch++;
+        if (c->hk[ch] >= lk) break;
+        c->hk[i] = c->hk[ch]; c->hid[i] = c->hid[ch]; c->hgen[i] = c->hgen[ch];
+        i = ch;
+    }
+    if (c->hn > 0) { c->hk[i] = lk; c->hid[i] = lid; c->hgen[i] = lg; }
+    return 1;
+}
+
+/* length of the path through the point (x, 0) of the window's edge */
+static inline double wdist(const wwin *w, double x) { return w->sg + hypot(x - w->px, w->py); }
+
+/* the window's key: its distance to the nearest point of its slice */
+static double wkey(const wwin *w) {
+    double x = w->px < w->b0 ? w->b0 : (w->px > w->b1 ? w->b1 : w->px);
+    return wdist(w, x);
+}
+
+/* store a window, link it on its half-edge and queue it unless processed */
+static void wlink(wctx *c, const wwin *x) {
+    if (c->nw == c->cap) {
+        c->cap = c->cap ? 2 * c->cap : 4096;
+        c->w = (wwin *)realloc(c->w, sizeof(wwin) * c->cap);
+    }
+    int id = c->nw++;
+    c->w[id] = *x;
+    if (c->hhead[x->h] < 0) c->htouch[c->nht++] = x->h;
+    c->w[id].next = c->hhead[x->h];
+    c->hhead[x->h] = id;
+    if (!x->done) wheap_push(c, wkey(x), id, x->gen);
+}
+
+/* the points of (lo, hi) where two windows' distances can be equal. With
+ * equal root distances that is where the images' bisector meets the edge;
+ * otherwise the real roots of the quadratic left after squaring the
+ * equation twice. A cut that is no crossing (a root of the other sign
+ * branch, or the vertex of the quadratic taken when rounding makes a double
+ * root's discriminant negative) only splits a piece: each piece between
+ * cuts goes to the window shorter at its midpoint. */
+static int wcross(const wwin *a, const wwin *b, double lo, double hi, double *x) {
+    double dl = b->sg - a->sg;
+    double al = 2.0 * (b->px - a->px);
+    double be = a->px * a->px + a->py * a->py - b->px * b->px - b->py * b->py - dl * dl;
+    double r[2]; int nr = 0;
+    if (dl == 0.0) {
+        if (al != 0.0) r[nr++] = -be / al;
+    } else {
+        double A2 = al * al - 4.0 * dl * dl;
+        double B2 = 2.0 * al * be + 8.0 * dl * dl * b->px;
+        double C2 = be * be - 4.0 * dl * dl * (b->px * b->px + b->py * b->py);
+        double scale = fabs(A2) * (hi * hi + 1.0) + fabs(B2) * (fabs(hi) + 1.0) + fabs(C2);
+        if (!(scale > 0.0)) return 0;
+        if (fabs(A2) * (hi * hi + 1.0) <= 1e-13 * scale) {
+            if (B2 != 0.0) r[nr++] = -C2 / B2;
+        } else {
+            double disc = B2 * B2 - 4.0 * A2 * C2;
+            double sq = disc > 0.0 ? sqrt(disc) : 0.0;
+            double q = -0.5 * (B2 + (B2 >= 0.0 ? sq : -sq));
+            if (q != 0.0) {
+                r[nr++] = q / A2;
+                r[nr++] = C2 / q;
+            } else {
+                r[nr++] = 0.0;
+            }
+        }
+    }
+    int k = 0;
+    for (int i = 0; i < nr; i++)
+        if (r[i] > lo && r[i] < hi) x[k++] = r[i];
+    if (k == 2 && x[0] > x[1]) { double t = x[0]; x[0] = x[1]; x[1] = t; }
+    return k;
+}
+
+/* window o loses the ordered runs [r0, r1]: what is left stays as o (the
+ * first piece) and new windows (the others); an unprocessed window is
+ * queued again under its new key */
+static void wtrim(wctx *c, int o, const double *r0, const double *r1, int nr) {
+    wwin ow = c->w[o];
+    const double eps = SEG_MIN_REL * c->m->len[ow.h];
+    double k0[WMAXP + 2], k1[WMAXP + 2]; int nk = 0;
+    double cur = ow.b0;
+    for (int i = 0; i < nr; i++) {
+        if (r0[i] - cur > eps) { k0[nk] = cur; k1[nk++] = r0[i]; }
+        if (r1[i] > cur) cur = r1[i];
+    }
+    if (ow.b1 - cur > eps) { k0[nk] = cur; k1[nk++] = ow.b1; }
+    c->cnt[2]++;
+    if (nk == 0) { c->w[o].alive = 0; return; }
+    c->w[o].b0 = k0[0]; c->w[o].b1 = k1[0];
+    if (!ow.done) { c->w[o].gen++; wheap_push(c, wkey(&c->w[o]), o, c->w[o].gen); }
+    for (int i = 1; i < nk; i++) {
+        wwin y = ow;
+        y.b0 = k0[i]; y.b1 = k1[i]; y.gen = 0;
+        wlink(c, &y);
+    }
+}
+
+/* insert window x on its half-edge as the pointwise minimum with the
+ * windows already there */
+static void winsert(wctx *c, const wwin *x) {
+    const int h = x->h;
+    const double eps = SEG_MIN_REL * c->m->len[h];
+    double p0[WMAXP], p1[WMAXP]; int np = 1;
+    p0[0] = x->b0; p1[0] = x->b1;
+    for (int o = c->hhead[h]; o >= 0 && np > 0; o = c->w[o].next) {
+        if (!c->w[o].alive || 5 * np > WMAXP) continue;
+        const wwin ow = c->w[o];
+        double q0[WMAXP], q1[WMAXP]; int nq = 0;  /* what the new window keeps */
+        double r0[WMAXP], r1[WMAXP]; int nr = 0;  /* what the old window loses */
+        for (int q = 0; q < np; q++) {
+            double lo = p0[q] > ow.b0 ? p0[q] : ow.b0, hi = p1[q] < ow.b1 ? p1[q] : ow.b1;
+            if (hi - lo <= eps) { q0[nq] = p0[q]; q1[nq++] = p1[q]; continue; }
+            double cut[4]; int nc = 0;
+            cut[nc++] = lo;
+            nc += wcross(x, &ow, lo, hi, cut + nc);
+            cut[nc++] = hi;
+            if (lo > p0[q]) { q0[nq] = p0[q]; q1[nq++] = lo; }
+            for (int i = 0; i + 1 < nc; i++) {
+                double a = cut[i], b = cut[i + 1], mid = 0.5 * (a + b);
+                if (wdist(x, mid) < wdist(&ow, mid)) {
+                    if (nq > 0 && q1[nq - 1] >= a) q1[nq - 1] = b;
+                    else { q0[nq] = a; q1[nq++] = b; }
+                    if (nr > 0 && r1[nr - 1] >= a) r1[nr - 1] = b;
+                    else { r0[nr] = a; r1[nr++] = b; }
+                }
+            }
+            if (hi < p1[q]) {
+                if (nq > 0 && q1[nq - 1] >= hi) q1[nq - 1] = p1[q];
+                else { q0[nq] = hi; q1[nq++] = p1[q]; }
+            }
+        }
+        if (nr > 0) wtrim(c, o, r0, r1, nr);
+        np = 0;
+        for (int q = 0; q < nq; q++)
+            if (q1[q] - q0[q] > eps) { p0[np] = q0[q]; p1[np++] = q1[q]; }
+    }
+    if (np == 0) { c->cnt[5]++; return; }
+    for (int q = 0; q < np; q++) {
+        wwin y = *x;
+        y.b0 = p0[q]; y.b1 = p1[q]; y.alive = 1; y.done = 0; y.gen = 0;
+        if (!(wkey(&y) < c->U)) { c->cnt[5]++; continue; }
+        c->cnt[0]++;
+        wlink(c, &y);
+    }
+}
+
+/* the third vertex C of face(h) in h's frame, from the edge lengths */
+static void third_in_frame(const orc_mesh *m, int h, double *cx, double *cy) {
+    double L = m->len[h], lp = m->len[he_prev(h)], ln = m->len[he_next(h)];
+    *cx = (L * L + lp * lp - ln * ln) / (2.0 * L);
+    double y2 = lp * lp - *cx * *cx;
+    *cy = y2 > 0.0 ? sqrt(y2) : 0.0;
+}
+
+/* the source-frame unit direction of a window's ray (dx, dy) in its frame,
+ * or the tangent of its root vertex */
+static void wtangent(const wctx *c, const wwin *w, double dx, double dy, double *t) {
+    if (w->root >= 0) { t[0] = c->Dt[2 * w->root]; t[1] = c->Dt[2 * w->root + 1]; return; }
+    double l = hypot(dx, dy);
+    t[0] = t[1] = 0.0;
+    if (!(l > 0.0)) return;
+    dx /= l; dy /= l;
+    t[0] = w->c * dx - w->s * dy;
+    t[1] = w->s * dx + w->c * dy;
+}
+
+static void wvertex(wctx *c, int v, double d, const double *t) {
+    if (!(d < c->U) || !(d < c->D[v])) return;
+    if (!isfinite(c->D[v])) c->vtouch[c->nvt++] = v;
+    c->D[v] = d;
+    c->Dt[2 * v] = t[0]; c->Dt[2 * v + 1] = t[1];
+    if (c->m->pseudo[v] && !c->launched[v]) wheap_push(c, d, -1 - v, 0);
+}
+
+/* a child window on half-edge th from the rays of w through the part of its
+ * slice that reaches th's edge; (ox, oy) = th's tail and (ux, uy) = its unit
+ * direction, in w's frame; s0, s1 = the slice on th */
+static void wchild(wctx *c, const wwin *w, int th, double ox, double oy, double ux, double uy, double s0, double s1) {
+    const double Lt = c->m->len[th];
+    if (s0 < 0.0) s0 = 0.0;
+    if (s1 > Lt) s1 = Lt;
+    if (!(s1 - s0 > SEG_MIN_REL * Lt)) return;
+    double qx = w->px - ox, qy = w->py - oy;
+    wwin y = *w;
+    y.h = th; y.b0 = s0; y.b1 = s1;
+    y.px = ux * qx + uy * qy;
+    y.py = ux * qy - uy * qx;
+    if (!(y.py < 0.0)) return; /* rays grazing the edge's line enter no face */
+    y.c = w->c * ux - w->s * uy;
+    y.s = w->s * ux + w->c * uy;
+    y.alive = 1; y.done = 0; y.gen = 0;
+    winsert(c, &y);
+}
+
+/* parameter along the line O + s u where the ray from w's image through
+ * (x, 0) meets it */
+static double wray_hit(const wwin *w, double x, double ox, double oy, double ux, double uy) {
+    double dx = x - w->px, dy = -w->py;
+    double rx = w->px - ox, ry = w->py - oy;
+    return (rx * dy - ry * dx) / (ux * dy - uy * dx);
+}
+
+static void wprocess(wctx *c, int id) {
+    const orc_mesh *m = c->m;
+    wwin w = c->w[id];
+    c->w[id].done = 1;
+    c->cnt[1]++;
+    int h = w.h, f = h / 3;
+    if (!c->fmark[f]) { c->fmark[f] = 1; c->ftouch[c->nft++] = f; c->cnt[4]++; }
+    double L = m->len[h], cx, cy, t[2];
+    third_in_frame(m, h, &cx, &cy);
+    const double tol = CONE_EPS * L;
+    /* where the ray from the image through C crosses the edge */
+    double txc = w.px + (cx - w.px) * (-w.py) / (cy - w.py);
+    if (txc >= w.b0 - tol && txc <= w.b1 + tol) {
+        wtangent(c, &w, cx - w.px, cy - w.py, t);
+        wvertex(c, m->T[he_prev(h)], w.sg + hypot(cx - w.px, cy - w.py), t);
+    }
+    if (w.b0 <= tol) {
+        wtangent(c, &w, -w.px, -w.py, t);
+        wvertex(c, m->T[h], w.sg + hypot(w.px, w.py), t);
+    }
+    if (w.b1 >= L - tol) {
+        wtangent(c, &w, L - w.px, -w.py, t);
+        wvertex(c, m->T[he_next(h)], w.sg + hypot(L - w.px, w.py), t);
+    }
+    /* rays through [b0, min(b1, txc)] cross A->C: child on twin(prev(h)),
+     * whose frame has origin A and x towards C */
+    int tp = m->twin[he_prev(h)];
+    if (tp >= 0 && w.b0 < txc) {
+        double lp = m->len[he_prev(h)], ux = cx / lp, uy = cy / lp;
+        double s0 = wray_hit(&w, w.b0, 0.0, 0.0, ux, uy);
+        double s1 = w.b1 >= txc ? lp : wray_hit(&w, w.b1, 0.0, 0.0, ux, uy);
+        wchild(c, &w, tp, 0.0, 0.0, ux, uy, s0, s1);
+    }
+    /* rays through [max(b0, txc), b1] cross C->B: child on twin(next(h)),
+     * whose frame has origin C and x towards B */
+    int tn = m->twin[he_next(h)];
+    if (tn >= 0 && w.b1 > txc) {
+        double ln = m->len[he_next(h)], ux = (L - cx) / ln, uy = -cy / ln;
+        double s0 = w.b0 <= txc ? 0.0 : wray_hit(&w, w.b0, cx, cy, ux, uy);
+        double s1 = wray_hit(&w, w.b1, cx, cy, ux, uy);
+        wchild(c, &w, tn, cx, cy, ux, uy, s0, s1);
+    }
+}
+
+/* pseudo-source vertex v at its final distance: a window from v on the
+ * edge opposite it in every face around it, neighbours relaxed */
+static void wlaunch(wctx *c, int v) {
+    const orc_mesh *m = c->m;
+    c->launched[v] = 1;
+    c->cnt[3]++;
+    const double Dv = c->D[v], tv[2] = {c->Dt[2 * v], c->Dt[2 * v + 1]};
+    for (int a = m->fan_off[v]; a < m->fan_off[v + 1]; a++) {
+        int hv = m->fan[a], hn = he_next(hv), hp = he_prev(hv); /* v -> u1, u1 -> u2, u2 -> v */
+        wvertex(c, m->T[hn], Dv + m->len[hv], tv);
+        wvertex(c, m->T[hp], Dv + m->len[hp], tv);
+        int t = m->twin[hn];
+        if (t < 0) continue;
+        /* t runs u2 -> u1; v lies at distance len[hp] from u2 and len[hv] from u1 */
+        double L = m->len[t], a2 = m->len[hp], a1 = m->len[hv];
+        double px = (L * L + a2 * a2 - a1 * a1) / (2.0 * L), y2 = a2 * a2 - px * px;
+        wwin y;
+        memset(&y, 0, sizeof y);
+        y.h = t; y.root = v; y.alive = 1;
+        y.b0 = 0.0; y.b1 = L;
+        y.px = px; y.py = -(y2 > 0.0 ? sqrt(y2) : 0.0); y.sg = Dv;
+        y.c = 1.0; y.s = 0.0;
+        if (y.py < 0.0) winsert(c, &y);
+    }
+}
+
+/* a window from the source (the origin of the source frame) on half-edge th
+ * whose tail is O and head Q in that frame; 0 when the source lies on the
+ * edge's line (no window: the face across holds the source too) */
+static int wseed(wctx *c, int th, const double *O, const double *Q) {
+    if (th < 0) return 1;
+    double L = c->m->len[th], ux = (Q[0] - O[0]) / L, uy = (Q[1] - O[1]) / L;
+    wwin y;
+    memset(&y, 0, sizeof y);
+    y.h = th; y.root = -1; y.alive = 1;
+    y.b0 = 0.0; y.b1 = L;
+    y.px = -O[0] * ux - O[1] * uy;
+    y.py = -O[1] * ux + O[0] * uy;
+    y.c = ux; y.s = uy;
+    if (!(y.py < 0.0)) return 0;
+    winsert(c, &y);
+    return 1;
+}
+
+static void wsource_vertex(wctx *c, int v, const double *P) {
+    double l = len2(P), t[2] = {0.0, 0.0};
+    if (l > 0.0) { t[0] = P[0] / l; t[1] = P[1] / l; }
+    wvertex(c, v, l, t);
+}
+
+/* one source: seed, propagate, then the distance and tangent to every
+ * target (best[j] = INFINITY where none is found below the bound) */
+static int wsource(wctx *c, int src, const int *face, const double *bary, int n, double *best, double *tang) {
+    const orc_mesh *m = c->m;
+    int f = face[src];
+    const double *b = bary + 3 * src;
+    for (int j = 0; j < n; j++) best[j] = INFINITY;
+    if ((b[0] <= 0.0) + (b[1] <= 0.0) + (b[2] <= 0.0) >= 2) return -1; /* on a vertex */
+    double P[3][2];
+    P[0][0] = 0.0; P[0][1] = 0.0;
+    P[1][0] = m->len[3 * f]; P[1][1] = 0.0;
+    unfold_third(P[0], P[1], m->len[3 * f], m->len[3 * f + 2], m->len[3 * f + 1], P[2]);
+    double s[2] = {b[0] * P[0][0] + b[1] * P[1][0] + b[2] * P[2][0], b[0] * P[0][1] + b[1] * P[1][1] + b[2] * P[2][1]};
+    for (int k = 0; k < 3; k++) { P[k][0] -= s[0]; P[k][1] -= s[1]; }
+    /* faces holding the source, with their corners in the source frame */
+    int sf[4] = {f, -1, -1, -1}, nsf = 1;
+    double SP[4][3][2];
+    memcpy(SP[0], P, sizeof P);
+    for (int k = 0; k < 3; k++) wsource_vertex(c, m->T[3 * f + k], P[k]);
+    for (int k = 0; k < 3; k++) {
+        int h = 3 * f + k, t = m->twin[h];
+        const double *X = P[k], *Y = P[(k + 1) % 3];
+        if (b[(k + 2) % 3] > 0.0 && wseed(c, t, Y, X)) continue; /* the twin runs Y -> X */
+        if (t < 0) continue;
+        /* the source is on this edge (exactly, or up to rounding): the face
+         * across holds it too */
+        double Z[2];
+        unfold_third(Y, X, m->len[t], m->len[he_prev(t)], m->len[he_next(t)], Z);
+        sf[nsf] = t / 3;
+        int kk = t % 3; /* corner order of face t/3: T[t] = Y, next = X, prev = Z */
+        memcpy(SP[nsf][kk], Y, sizeof(double) * 2);
+        memcpy(SP[nsf][(kk + 1) % 3], X, sizeof(double) * 2);
+        memcpy(SP[nsf][(kk + 2) % 3], Z, sizeof(double) * 2);
+        nsf++;
+        wsource_vertex(c, m->T[he_prev(t)], Z);
+        wseed(c, m->twin[he_next(t)], Z, X); /* next(t) runs X -> Z */
+        wseed(c, m->twin[he_prev(t)], Y, Z); /* prev(t) runs Z -> Y */
+    }
+    /* continuous Dijkstra */
+    double k; int id, gen;
+    while (wheap_pop(c, &k, &id, &gen)) {
+        if (!(k < c->U)) break;
+        if (id < 0) {
+            int v = -1 - id;
+            if (c->launched[v] || k > c->D[v]) continue;
+            wlaunch(c, v);
+        } else {
+            const wwin *w = &c->w[id];
+            if (!w->alive || w->done || w->gen != gen) continue;
+            wprocess(c, id);
+        }
+    }
+    /* targets */
+    for (int j = 0; j < n; j++) {
+        if (j == src) continue;
+        int g = face[j];
+        const double *bj = bary + 3 * j;
+        double bd = INFINITY, bt[2] = {0.0, 0.0};
+        for (int z = 0; z < nsf; z++) {
+            if (sf[z] != g) continue;
+            double q[2] = {0.0, 0.0};
+            for (int a = 0; a < 3; a++) { q[0] += bj[a] * SP[z][a][0]; q[1] += bj[a] * SP[z][a][1]; }
+            double d = len2(q);
+            if (d < bd) { bd = d; bt[0] = d > 0.0 ? q[0] / d : 0.0; bt[1] = d > 0.0 ? q[1] / d : 0.0; }
+        }
+        double x3[3] = {0.0, 0.0, 0.0};
+        for (int a = 0; a < 3; a++)
+            for (int d = 0; d < 3; d++) x3[d] += bj[a] * m->V[3 * m->T[3 * g + a] + d];
+        for (int a = 0; a < 3; a++) {
+            int v = m->T[3 * g + a];
+            if (!m->pseudo[v] || !isfinite(c->D[v])) continue;
+            double e[3];
+            sub3(x3, m->V + 3 * v, e);
+            double d = c->D[v] + norm3(e);
+            if (d < bd) { bd = d; bt[0] = c->Dt[2 * v]; bt[1] = c->Dt[2 * v + 1]; }
+        }
+        for (int a = 0; a < 3; a++) {
+            int h = 3 * g + a;
+            if (c->hhead[h] < 0) continue;
+            double L = m->len[h], cx, cy;
+            third_in_frame(m, h, &cx, &cy);
+            /* the target in h's frame: corners A = (0, 0), B = (L, 0), C */
+            double xx = bj[(a + 1) % 3] * L + bj[(a + 2) % 3] * cx, xy = bj[(a + 2) % 3] * cy;
+            const double tol = CONE_EPS * L;
+            for (int o = c->hhead[h]; o >= 0; o = c->w[o].next) {
+                const wwin *w = &c->w[o];
+                if (!w->alive) continue;
+                double tx = w->px + (xx - w->px) * (-w->py) / (xy - w->py);
+                if (tx < w->b0 - tol || tx > w->b1 + tol) continue;
+                double d = w->sg + hypot(xx - w->px, xy - w->py);
+                if (d < bd) { bd = d; wtangent(c, w, xx - w->px, xy - w->py, bt); }
+            }
+        }
+        if (bd < c->U) { best[j] = bd; tang[2 * j] = bt[0]; tang[2 * j + 1] = bt[1]; }
+    }
+    return 0;
+}
+
+static void wreset(wctx *c) {
+    for (int i = 0; i < c->nht; i++) c->hhead[c->htouch[i]] = -1;
+    for (int i = 0; i < c->nvt; i++) { c->D[c->vtouch[i]] = INFINITY; c->launched[c->vtouch[i]] = 0; }
+    for (int i = 0; i < c->nft; i++) c->fmark[c->ftouch[i]] = 0;
+    c->nht = c->nvt = c->nft = 0;
+    c->nw = 0; c->hn = 0;
+}
+
+orc_pairs *orc_geodesic_pairs_windows(const orc_mesh *m, int n, const int *face, const double *bary, double cutoff,
+                                      int nsrc, const int *src, int nthreads) {
+    if (!m || n < 0 || (n > 0 && (!face || !bary))) return NULL;
+    for (int j = 0; j < n; j++)
+        if (face[j] < 0 || face[j] >= m->nf) return NULL;
+    int all = !(cutoff > 0.0) || !isfinite(cutoff);
+    if (!src) nsrc = n;
+    row_t *rows = (row_t *)calloc(nsrc > 0 ? nsrc : 1, sizeof(row_t));
+    orc_pairs *res = (orc_pairs *)calloc(1, sizeof(orc_pairs));
+    res->nsrc = nsrc;
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#else
+    (void)nthreads;
+#endif
+#pragma omp parallel
+    {
+        wctx c;
+        memset(&c, 0, sizeof c);
+        c.m = m;
+        c.hhead = (int *)malloc(sizeof(int) * 3 * m->nf);
+        c.htouch = (int *)malloc(sizeof(int) * 3 * m->nf);
+        for (int h = 0; h < 3 * m->nf; h++) c.hhead[h] = -1;
+        c.D = (double *)malloc(sizeof(double) * m->nv);
+        c.Dt = (double *)malloc(sizeof(double) * 2 * m->nv);
+        for (int v = 0; v < m->nv; v++) c.D[v] = INFINITY;
+        c.launched = (unsigned char *)calloc(m->nv, 1);
+        c.vtouch = (int *)malloc(sizeof(int) * m->nv);
+        c.fmark = (unsigned char *)calloc(m->nf, 1);
+        c.ftouch = (int *)malloc(sizeof(int) * m->nf);
+        double *best = (double *)malloc(sizeof(double) * (n > 0 ? n : 1));
+        double *tang = (double *)malloc(sizeof(double) * 2 * (n > 0 ? n : 1));
+        work_t gw;
+        memset(&gw, 0, sizeof gw);
+        double *gdist = all ? (double *)malloc(sizeof(double) * m->nv) : NULL;
+#pragma omp for schedule(dynamic, 1)
+        for (int si = 0; si < nsrc; si++) {
+            int i = src ? src[si] : si;
+            c.U = all ? graph_bound(m, face[i], bary + 3 * i, gdist, &gw) : cutoff;
+            row_t *rw = &rows[si];
+            if (wsource(&c, i, face, bary, n, best, tang) != 0) c.cnt[6]++;
+            int cnt = 0;
+            for (int j = 0; j < n; j++)
+                if (best[j] < c.U) cnt++;
+            rw->n = cnt;
+            rw->nbr = (int32_t *)malloc(sizeof(int32_t) * (cnt + 1));
+            rw->dist = (double *)malloc(sizeof(double) * (cnt + 1));
+            rw->tan = (double *)malloc(sizeof(double) * 3 * (cnt + 1));
+            rw->flags = (uint8_t *)malloc(cnt + 1);
+            const double *ex = m->ex + 3 * face[i], *ey = m->ey + 3 * face[i];
+            int q = 0;
+            for (int j = 0; j < n; j++) {
+                if (!(best[j] < c.U)) continue;
+                rw->nbr[q] = j; rw->dist[q] = best[j];
+                for (int d = 0; d < 3; d++) rw->tan[3 * q + d] = tang[2 * j] * ex[d] + tang[2 * j + 1] * ey[d];
+                rw->flags[q] = best[j] == 0.0 ? 2 : 0;
+                q++;
+            }
+            wreset(&c);
+        }
+#pragma omp critical
+        {
+            for (int z = 0; z < 7; z++) res->wcounters[z] += c.cnt[z];
+        }
+        free(c.w); free(c.hhead); free(c.htouch); free(c.hk); free(c.hid); free(c.hgen); free(c.D); free(c.Dt);
+        free(c.launched); free(c.vtouch); free(c.fmark); free(c.ftouch); free(best); free(tang);
+        free(gw.hk); free(gw.hv); free(gdist);
+    }
+    /* flatten: one direction per pair, no tie sets */
+    res->off = (int64_t *)malloc(sizeof(int64_t) * (nsrc + 1));
+    res->off[0] = 0;
+    int64_t tot = 0;
+    for (int s = 0; s < nsrc; s++) { tot += rows[s].n; res->off[s + 1] = tot; }
+    res->count = res->tcount = tot;
+    res->nbr = (int32_t *)malloc(sizeof(int32_t) * (tot + 1));
+    res->dist = (double *)malloc(sizeof(double) * (tot + 1));
+    res->tan = (double *)malloc(sizeof(double) * 3 * (tot + 1));
+    res->flags = (uint8_t *)malloc(tot + 1);
+    res->tie_off = (int64_t *)malloc(sizeof(int64_t) * (tot + 1));
+    res->tie_tan = (double *)malloc(sizeof(double) * 3 * (tot + 1));
+    res->tie_dist = (double *)malloc(sizeof(double) * (tot + 1));
+    res->tie_off[0] = 0;
+    int64_t p = 0;
+    for (int s = 0; s < nsrc; s++) {
+        row_t *rw = &rows[s];
+        for (int q = 0; q < rw->n; q++, p++) {
+            res->nbr[p] = rw->nbr[q]; res->dist[p] = rw->dist[q];
+            memcpy(res->tan + 3 * p, rw->tan + 3 * q, sizeof(double) * 3);
+            memcpy(res->tie_tan + 3 * p, rw->tan + 3 * q, sizeof(double) * 3);
+            res->tie_dist[p] = rw->dist[q];
+            res->flags[p] = rw->flags[q];
+            res->tie_off[p + 1] = p + 1;
+        }
+        free(rw->nbr); free(rw->dist); free(rw->tan); free(rw->flags);
+    }
+    free(rows);
+    return res;
+}
+
+void orc_pairs_window_counters(const orc_pairs *p, int64_t *c7) { memcpy(c7, p->wcounters, sizeof(int64_t) * 7); }
 
 /* ======================================================================
  * 3. The shift walk (Sec. 3.2): straight across faces; at an edge, move to

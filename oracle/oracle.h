@@ -17,6 +17,9 @@
  *    in planar unfoldings, bending only at saddle or boundary vertices; every
  *    such chain shorter than the cutoff is enumerated by brute force, with no
  *    trimming, and the shortest kept (Dijkstra over the bend vertices);
+ *  - the same distances by the window-propagation method itself (Sec. 2.2:
+ *    MMP's continuous Dijkstra with windows trimmed to the pointwise
+ *    minimum), with its counts of windows;
  *  - the per-particle straight walk across faces with parallel transport of
  *    the velocity (Sec. 3.2, the shift algorithm and its steps (a)-(d));
  *  - Philox4x32-10 (Salmon et al., SC'11) for Brownian noise (Sec. 2.1);
@@ -67,6 +70,22 @@ void orc_pairs_export(const orc_pairs *p, int64_t *off, int32_t *nbr, double *di
  * rejected (position on a vertex) */
 void orc_pairs_counters(const orc_pairs *p, int64_t *c5);
 void orc_pairs_free(orc_pairs *p);
+
+/* The same pairs by the exact window-propagation method of Sec. 2.2 (the
+ * continuous Dijkstra of Mitchell, Mount & Papadimitriou with windows
+ * trimmed to the pointwise minimum on every edge, pseudo-source vertices
+ * launched once): an independent route to the distances of
+ * orc_geodesic_pairs and the method's own count of work. One direction per
+ * pair (the first shortest found; no tie sets: tie_off[p] = p). Returns NULL
+ * on bad input. */
+orc_pairs *orc_geodesic_pairs_windows(const orc_mesh *m, int n, const int *face, const double *bary, double cutoff,
+                                      int nsrc, const int *src, int nthreads);
+/* counters of orc_geodesic_pairs_windows, summed over sources: [0] windows
+ * inserted, [1] windows propagated, [2] windows trimmed (shortened, split or
+ * removed), [3] pseudo-source launches, [4] faces entered (per source),
+ * [5] insertions dropped (dominated or beyond the bound), [6] sources
+ * rejected (on a vertex) */
+void orc_pairs_window_counters(const orc_pairs *p, int64_t *c7);
 
 /* Per-particle walk (shift). disp[n][3] (normal part removed inside), vel may
  * be NULL. face/bary/vel updated in place. stats[5]: crossings, vertex hits,
