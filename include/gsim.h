@@ -317,7 +317,10 @@ gsim_status gsim_step_batched(gsim_ctx *ctx, int32_t nmesh, const int32_t *mesh_
  *   "whole_mesh"    1: finite-cutoff passes also run on the whole-mesh kernel
  *                   below (windows pruned at the cutoff; no limit on candidates or
  *                   bend vertices per source; at most 46,340 particles per
- *                   surface, whose n x n pair rows take 37 bytes each). Without
+ *                   surface, whose n x n pair rows take 37 bytes each: 79 GB
+ *                   at that count, checked against the free device memory
+ *                   before each pass, as a pairs call's output is before it
+ *                   is written; GSIM_E_LIMIT names the bytes). Without
  *                   it, the cutoff kernel takes up to 4096 Euclidean candidates
  *                   per source: up to 128 in an LDS table, more with the targets
  *                   in global memory and rows sized from a count of the

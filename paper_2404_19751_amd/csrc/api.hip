@@ -11,7 +11,9 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
+#include <initializer_list>
 #include <map>
 #include <mutex>
 #include <new>
@@ -203,6 +205,28 @@ gsim_status fail(gsim_ctx *c, gsim_status s, const char *msg) noexcept {
             return fail(c, e_ == hipErrorOutOfMemory ? GSIM_E_OOM : GSIM_E_DEVICE,                \
                         std::string(#x " failed: ") + hipGetErrorString(e_));                      \
     } while (0)
+
+// Device memory that growing the buffers to the requested sizes takes
+// beyond what they hold now (ensure() frees a buffer before it allocates
+// 5/4 of the request), checked against what the device has free: an
+// oversized request becomes GSIM_E_LIMIT with the byte counts instead of a
+// failed allocation halfway through a pass.
+struct Grow {
+    const Buf *b;
+    size_t bytes;
+};
+gsim_status check_room(gsim_ctx *c, std::initializer_list<Grow> req, const std::string &what) {
+    double need = 0.0;
+    for (const Grow &g : req)
+        if (g.b->bytes < g.bytes) need += 1.25 * (double)g.bytes - (double)g.b->bytes;
+    size_t fr = 0, tot = 0;
+    if (need <= 0.0 || hipMemGetInfo(&fr, &tot) != hipSuccess) return GSIM_OK;
+    if (need <= 0.95 * (double)fr) return GSIM_OK;
+    char msg[256];
+    std::snprintf(msg, sizeof msg, " need %.3g GB more device memory; %.3g GB of %.3g GB are free", need * 1e-9,
+                  (double)fr * 1e-9, (double)tot * 1e-9);
+    return fail(c, GSIM_E_LIMIT, what + msg);
+}
 
 hipError_t ensure(Buf &b, size_t bytes) {
     if (b.bytes >= bytes && b.p) return hipSuccess;
@@ -463,6 +487,13 @@ gsim_status prepare_surface(gsim_ctx *c, const Member &mb, bool small, int src_b
         if (st != GSIM_OK) return st;
     }
     const size_t cap = all ? (size_t)n : (size_t)rowcap;
+    if (all) {
+        const size_t slots = (size_t)n * cap;
+        gsim_status st = check_room(c, {{&ms->cand, 4 * slots}, {&ms->cdist, 8 * slots}, {&ms->ctan, 24 * slots},
+                                        {&ms->cflags, slots}},
+                                    "the whole-mesh rows of " + std::to_string(n) + " particles (37 bytes a pair slot)");
+        if (st != GSIM_OK) return st;
+    }
     HIPCHK(c, ensure(ms->cell_of, sizeof(int32_t) * n));
     HIPCHK(c, ensure(ms->cell_start, sizeof(int32_t) * (ncell + 1)));
     HIPCHK(c, ensure(ms->cell_fill, sizeof(int32_t) * ncell));
@@ -649,7 +680,7 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
     B.nslots = std::min(std::min(total, c->cus * per_cu), c->max_slots);
     if (B.all) {
         // whole-mesh fronts are deep: fewer resident wavefronts rather than more memory
-        const double per_slot = 64.0 * c->stack_cap_all + 8.0 * B.vstride + (double)B.rstride;
+        const double per_slot = 64.0 * c->stack_cap_all + 8.0 * B.vstride + (double)B.rstride + 32.0 * B.tcap;
         const int64_t fit = (int64_t)(c->stack_budget / per_slot);
         B.nslots = (int)std::max<int64_t>(1, std::min<int64_t>(B.nslots, fit));
     }
@@ -805,6 +836,12 @@ gsim_status compact_pairs(gsim_ctx *c, MeshState *ms, double cutoff) {
     HIPCHK(c, hipMemcpyAsync(&total, P<int64_t>(ms->off) + n, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     ms->n_pairs = total;
+    {
+        const size_t t1 = (size_t)total + 1;
+        gsim_status cs = check_room(c, {{&ms->nbr, 4 * t1}, {&ms->dist, 8 * t1}, {&ms->tan, 24 * t1}, {&ms->flags, t1}},
+                                    "the " + std::to_string(total) + " pairs of this call (37 bytes each)");
+        if (cs != GSIM_OK) return cs;
+    }
     HIPCHK(c, ensure(ms->nbr, sizeof(int32_t) * (total + 1)));
     HIPCHK(c, ensure(ms->dist, sizeof(double) * (total + 1)));
     HIPCHK(c, ensure(ms->tan, sizeof(double) * 3 * (total + 1)));

@@ -202,8 +202,10 @@ struct SurfDesc {
 // memory, rows as wide as the largest count needs), up to kBigCandMax.
 constexpr int kCandCap = 128;
 constexpr int kBigCandMax = 4096;
-// Most particles on one surface in all-pairs mode: the n x n pair slots of
-// the row arrays (37 bytes each) stay within 32-bit indices.
+// Most particles on one surface in whole-mesh passes. The rows hold n x n
+// pair slots of 37 bytes (indices are 64-bit): about 79 GB at this count,
+// and a pairs call's compacted output up to as much again, which fits one
+// 288 GB device. Each pass also checks the memory actually free first.
 constexpr int kAllPairsMax = 46340;
 
 // FIRE state of one surface (device memory): time step, mixing factor,

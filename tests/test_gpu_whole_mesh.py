@@ -98,6 +98,37 @@ def test_cutoff_kernel_reports_its_limit():
         ctx.close()
 
 
+def test_whole_mesh_rows_checked_against_free_memory():
+    """46,000 particles need 78 GB of whole-mesh rows (37 bytes a pair
+    slot): with most of the device held by a torch allocation first, the
+    pass is refused with GSIM_E_LIMIT naming the bytes, before any row is
+    allocated; once the memory is back the same context runs a small pass."""
+    import torch
+    from paper_2404_19751_amd import gsim
+    m = W.icosphere(5)
+    n = 46000
+    f, b = W.random_particles(m.nf, n, 9)
+    free, total = torch.cuda.mem_get_info()
+    hold_bytes = max(0, free - 40 * 2**30)  # leave 40 GB: less than the rows need
+    log(f"[gpu-whole] holding {hold_bytes / 2**30:.0f} GiB of {total / 2**30:.0f} GiB")
+    hold = torch.empty(hold_bytes, dtype=torch.uint8, device="cuda")
+    ctx = _ctx("fp64", True)
+    try:
+        mid = ctx.mesh_upload(m.V, m.T)
+        ctx.particles_set(mid, f, b)
+        with pytest.raises(gsim.GsimError) as e:
+            ctx.geodesic_pairs(mid, 0.05)
+        assert e.value.status == gsim.E_LIMIT
+        assert "46000 particles" in str(e.value) and "GB" in str(e.value)
+        del hold
+        torch.cuda.empty_cache()
+        ctx.particles_set(mid, f[:500], b[:500])
+        g = ctx.geodesic_pairs(mid, 0.05)
+        assert len(g["nbr"]) > 0
+    finally:
+        ctx.close()
+
+
 def test_whole_mesh_agrees_with_cutoff_kernel():
     """Bumpy sphere, 1000 particles, cutoff 0.15: the whole-mesh kernel and
     the cutoff kernel are both exact, so neighbour sets are identical and
