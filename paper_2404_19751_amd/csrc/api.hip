@@ -102,6 +102,7 @@ struct gsim_ctx {
     int max_windows_all = 0;      // per-source window limit in all-pairs passes
     int cus = 256;
     bool whole_mesh = false;  // finite-cutoff passes on the whole-mesh kernel
+    int group_sources = 4;  // FP64 persistent passes: sources per wavefront, at most (1, 2 or 4)
     bool fuse_update = true;  // time steps move each particle inside the cutoff kernel
     // layout the bend-vertex tables were last emptied for
     void *roots_p = nullptr;
@@ -595,6 +596,7 @@ struct Batch {
     bool fused = false; // time steps move the particles inside the cutoff kernel
     bool big = false;   // some surface has more candidates per source than the LDS table holds
     int gcap = 0;       // its widest row (big-candidate target arrays per wavefront)
+    int group = 1;      // sources per wavefront (FP64, more sources than resident slots: 2 or 4)
     int nslots = 0;
     GeoShape shape{};
 };
@@ -661,6 +663,19 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
         B.vstride = std::max<int64_t>(B.vstride, B.mem[i].ms->dm.nv);
         B.rcap = std::max(B.rcap, B.mem[i].ms->dm.n_pseudo);
     }
+    // persistent grid: as many wavefronts as can be resident, at most one per source
+    const bool fp32 = c->prec == GSIM_FP32_MIXED;
+    const int per_cu = std::max(1, B.all ? geodesic_all_blocks_per_cu(c->lds_stack_kb, fp32)
+                                         : geodesic_blocks_per_cu(c->lds_stack_kb, fp32, B.big));
+    // several sources per wavefront (the largest group of at most
+    // group_sources that still gives every resident wavefront a full one):
+    // each of a group's sources has its own bend-vertex entries in the
+    // wavefront's table
+    B.group = 1;
+    if (!fp32 && !B.all && !B.big && !c->profile_sources)
+        for (int g = c->group_sources; g > 1 && B.group == 1; g /= 2)
+            if (total >= (int64_t)g * c->cus * per_cu) B.group = g;  // a full group for every resident wavefront
+    B.rcap *= B.group;
     B.rstride = bend_table_bytes(B.rcap);
     B.fire_blk.begin[ns] = nblk;
     if (B.any_fire) HIPCHK(c, ensure(c->partials, sizeof(double) * 3 * (size_t)std::max(nblk, 1)));
@@ -673,10 +688,6 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
         }
         B.desc[0].prof = P<long long>(c->prof);
     }
-    // persistent grid: as many wavefronts as can be resident, at most one per source
-    const bool fp32 = c->prec == GSIM_FP32_MIXED;
-    const int per_cu = std::max(1, B.all ? geodesic_all_blocks_per_cu(c->lds_stack_kb, fp32)
-                                         : geodesic_blocks_per_cu(c->lds_stack_kb, fp32, B.big));
     B.nslots = std::min(std::min(total, c->cus * per_cu), c->max_slots);
     if (B.all) {
         // whole-mesh fronts are deep: fewer resident wavefronts rather than more memory
@@ -797,7 +808,7 @@ gsim_status geodesic_pass(gsim_ctx *c, Batch &B, bool advance, bool commit_in = 
         HIPCHK(c, launch_geodesic(desc_dev(c), B.bi, gp, B.shape, P<char>(c->stack), P<char>(c->roots), B.rstride,
                                   B.rcap, P<int32_t>(c->work), P<Counters>(c->ctr), c->prec == GSIM_FP32_MIXED,
                                   advance && B.fused, s, st.a, st.b, B.big ? P<char>(c->gtab) : nullptr,
-                                  B.big ? B.gcap : 0));
+                                  B.big ? B.gcap : 0, B.group));
     }
     c->passes++;
     return GSIM_OK;
@@ -883,6 +894,7 @@ std::string graph_key(gsim_ctx *c, const Batch &B, int steps) {
     put(&B.small, sizeof(B.small));
     put(&B.fused, sizeof(B.fused));
     put(&B.big, sizeof(B.big));
+    put(&B.group, sizeof(B.group));
     put(&B.gcap, sizeof(B.gcap));
     put(&c->update_block, sizeof(int));
     put(&steps, sizeof(int));
@@ -1779,6 +1791,8 @@ gsim_status gsim_tune_set(gsim_ctx *c, const char *name, double value) {
         else if (k == "dom_rel" && value >= 0.0) c->gp.dom_rel = value;
         else if (k == "dom_rel32" && value >= 0.0) c->gp.dom_rel32 = value;
         else if (k == "whole_mesh" && (value == 0.0 || value == 1.0)) c->whole_mesh = value != 0.0;
+        else if (k == "group_sources" && (value == 1.0 || value == 2.0 || value == 4.0))
+            c->group_sources = (int)value;
         else if (k == "fuse_update" && (value == 0.0 || value == 1.0)) c->fuse_update = value != 0.0;
         else if (k == "time_geodesic_only" && (value == 0.0 || value == 1.0)) c->time_geodesic_only = value != 0.0;
         else return fail(c, GSIM_E_ARG, "unknown tuning knob or value out of range: " + k);

@@ -77,6 +77,12 @@ using namespace wnd;
 
 constexpr int kMaxCand = kCandCap;
 constexpr int kHash = 256;
+// Several sources per wavefront (kG of them, the grouped instantiations):
+// each takes 1/kG of the target table and of the hash buckets.
+template <int kG>
+constexpr int kGroupCand = kMaxCand / kG;
+template <int kG>
+constexpr int kGroupBuckets = kHash / kG;
 constexpr int kBigStk = 8192;  // LDS window stack of the big-candidate instantiation
 constexpr int kChunks = 8;
 static_assert(kChunks == kWorkChunks, "one work counter per chunk");
@@ -113,6 +119,11 @@ struct Lds {
     double d1[kMaxCand], d2[kMaxCand], t1x[kMaxCand], t1y[kMaxCand];
     int32_t head[kHash];
     int32_t ncand;
+    int32_t ncg[4];  // candidate counts of the searches of a group's sources
+    // the group being propagated (sources, rows, counts) and the sources that
+    // wait to run alone: in LDS rather than in registers the propagation needs
+    int32_t gsrc[4], gnc[4], galone[4];
+    int64_t gc0[4];
     BendLds B;
 };
 
@@ -151,17 +162,24 @@ __device__ inline GTab gtab_of(char *base, int64_t stride, int slot, int gcap, L
 }
 
 // Multiplicative hash of a face index: the top bits of f times the golden
-// ratio in 32-bit fixed point (256 buckets: the top 8 bits).
+// ratio in 32-bit fixed point (256 buckets: the top 8 bits). kB buckets per
+// source: the table's own count, or half of it for each source of a pair.
+template <int kB>
+__device__ inline int hash_bits(int f) {
+    static_assert(kB == 64 || kB == 128 || kB == 256 || kB == 1024, "bucket counts");
+    constexpr int kShift = kB == 64 ? 26 : (kB == 128 ? 25 : (kB == 256 ? 24 : 22));
+    return (int)(((uint32_t)f * 2654435761u) >> kShift) & (kB - 1);
+}
 template <class TL>
 __device__ inline int hash_face(int f) {
-    constexpr int kShift = TL::kBuckets == 256 ? 24 : 22;
-    static_assert(TL::kBuckets == 256 || TL::kBuckets == 1024, "bucket counts");
-    return (int)(((uint32_t)f * 2654435761u) >> kShift) & (TL::kBuckets - 1);
+    return hash_bits<TL::kBuckets>(f);
 }
 
-template <class TL>
-__device__ inline int first_in_face(const TL &L, int f) {
-    int s = L.head[hash_face<TL>(f)];
+// First target of face f in the table of the source whose buckets start at
+// hb (kB of them).
+template <class TL, int kB = TL::kBuckets>
+__device__ inline int first_in_face(const TL &L, int f, int hb = 0) {
+    int s = L.head[hb + hash_bits<kB>(f)];
     while (s >= 0 && L.tface[s] != f) s = L.tnext[s];
     return s;
 }
@@ -170,6 +188,25 @@ __device__ inline int next_in_face(const TL &L, int s, int f) {
     s = L.tnext[s];
     while (s >= 0 && L.tface[s] != f) s = L.tnext[s];
     return s;
+}
+
+// The wavefront's sources: one, or in the grouped instantiations (kG = 2 or
+// 4) up to kG of the same surface, sharing the lanes, the window stack and
+// the bend-vertex table. Source q of a group owns targets [q kGroupCand,
+// ...) and hash buckets [q kGroupBuckets, ...) of the table and bend-vertex
+// entries [q rcap1, (q + 1) rcap1); its source windows carry root -1 - q,
+// its bend-vertex windows the entry index, so every window knows its source.
+// A lone source of a grouped instantiation takes the whole table.
+template <int kG>
+__device__ inline int slot_of(int root, int rcap1) {
+    if constexpr (kG == 1) {
+        return 0;
+    } else {
+        int q = 0;
+#pragma unroll
+        for (int g = 1; g < kG; ++g) q += root >= g * rcap1;
+        return root >= 0 ? q : -1 - root;
+    }
 }
 
 // Per-source constants shared by the helpers.
@@ -188,11 +225,12 @@ struct Ctx {
 // to a multiple of four with entries that no path can reach.
 template <class TL>
 __device__ inline bool reaches_target(const TL &L, const Ctx &C, const double P[3], const double u[3], double x0,
-                                      double x1, double base) {
+                                      double x1, double base, int tb = 0, int nc4 = -1) {
     // with more targets than the LDS table holds, nearly every window within
     // the cutoff can still improve one of them: only the cutoff prunes
     if constexpr (TL::kBig) return base < C.cut_acc;
-    for (int s0 = 0; s0 < C.nc4; s0 += 4) {
+    const int te = tb + (nc4 < 0 ? C.nc4 : nc4);  // the source's targets: [tb, te)
+    for (int s0 = tb; s0 < te; s0 += 4) {
         bool hit = false;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -249,7 +287,7 @@ __device__ inline void target_update(TL &L, const Ctx &C, bool ok, int slot, dou
 template <typename R, class TL>
 __device__ inline void children(const He<R> &h, const Win<R> &w, double txc, bool full, const Ctx &C,
                                 const double F3[3][3], const double U3[3][3], const TL &L, Win<R> &cl, bool &hl,
-                                Win<R> &cr, bool &hr, int &pruned) {
+                                Win<R> &cr, bool &hr, int &pruned, int tb = 0, int nc4 = -1) {
     hl = false;
     hr = false;
     if (h.tp >= 0 && (full || (double)w.b0 < txc)) {
@@ -260,7 +298,7 @@ __device__ inline void children(const He<R> &h, const Win<R> &w, double txc, boo
             const double base = (double)w.sg + (double)seg_dist(cl.px, cl.py, cl.b0, cl.b1);
             // edge A -> C is the reverse of half-edge prev = (C -> A)
             const double u[3] = {-U3[2][0], -U3[2][1], -U3[2][2]};
-            if (reaches_target(L, C, F3[0], u, x0, x1, base)) hl = true;
+            if (reaches_target(L, C, F3[0], u, x0, x1, base, tb, nc4)) hl = true;
             else ++pruned;
         }
     }
@@ -272,7 +310,7 @@ __device__ inline void children(const He<R> &h, const Win<R> &w, double txc, boo
             const double base = (double)w.sg + (double)seg_dist(cr.px, cr.py, cr.b0, cr.b1);
             // edge C -> B is the reverse of half-edge next = (B -> C)
             const double u[3] = {-U3[1][0], -U3[1][1], -U3[1][2]};
-            if (reaches_target(L, C, F3[2], u, x0, x1, base)) hr = true;
+            if (reaches_target(L, C, F3[2], u, x0, x1, base, tb, nc4)) hr = true;
             else ++pruned;
         }
     }
@@ -290,10 +328,12 @@ struct SrcStats {
 // smallest such distance; the others stay pending. The selected vertices
 // are compacted into a list and their fans flattened over the lanes, a chunk
 // of vertices at a time, so one launch round costs a few memory round trips,
-// not one per vertex.
-template <typename R, class TL>
+// not one per vertex. In the pair instantiation an entry index e stands for
+// bend vertex e mod rcap1 of source e / rcap1 (its targets from q tspan on).
+template <typename R, class TL, int kG = 1>
 __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, TL &L, const BendTable &G, const Ctx &C,
-                             Stack<R> &S, SrcStats &st) {
+                             Stack<R> &S, SrcStats &st, int tspan = 0, const int *ncs = nullptr, int rcap1 = 0) {
+    constexpr int kB = kG == 1 ? TL::kBuckets : kGroupBuckets<kG>;
     const int lane = lane_id();
     const DevMesh &M = sd.m;
     const HeRec *__restrict__ he = M.he;
@@ -371,11 +411,13 @@ __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, TL &L, const 
                     e = G.sel[c0 + k];
                     L.B.sel[k] = e;
                 }
-                const PseudoRec pr = M.prec[e];
+                const int q = slot_of<kG>(e, rcap1);
+                const PseudoRec pr = M.prec[e - q * rcap1];
                 const double D = G.rD[e];
                 // big-candidate mode: every vertex within the cutoff (as for windows)
                 bool useful = TL::kBig;
-                for (int s = 0; !TL::kBig && s < C.nc && !useful; ++s) {
+                const int tb = q * tspan, te = tb + (kG == 1 ? C.nc : ncs[q]);
+                for (int s = tb; !TL::kBig && s < te && !useful; ++s) {
                     const double bound = L.cb[s][3] - D;
                     const double q0 = L.cb[s][0] - pr.x, q1 = L.cb[s][1] - pr.y, q2 = L.cb[s][2] - pr.z;
                     useful = bound > 0.0 && q0 * q0 + q1 * q1 + q2 * q2 < bound * bound;
@@ -410,8 +452,10 @@ __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, TL &L, const 
                 k = lo;
             }
             const int el = act ? L.B.sel[k] : 0;
+            const int q = slot_of<kG>(el, rcap1);  // the vertex's source
+            const int tb = q * tspan, hb = q * kB, eb = q * rcap1;
             PseudoRec pr{0.0, 0.0, 0.0, 0, 0, 0, 0};
-            if (act) pr = M.prec[el];
+            if (act) pr = M.prec[el - eb];
             const double D = act ? G.rD[el] : 0.0;
             const double vtx = act ? G.rtx[el] : 0.0, vty = act ? G.rty[el] : 0.0;
             const double D2 = act ? G.rD2[el] : INFINITY;  // the vertex's other-direction distance
@@ -436,11 +480,12 @@ __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, TL &L, const 
                 face_xyz(M, h / 3, h % 3, F3, U3);  // (v, u1, u2)
                 // the window's edge runs u2 -> u1: the reverse of half-edge next(h) = (u1 -> u2)
                 const double u[3] = {-U3[1][0], -U3[1][1], -U3[1][2]};
-                want = reaches_target(L, C, F3[2], u, 0.0, Rn.L, D + seg_dist(px, py, 0.0, Rn.L));
+                want = reaches_target(L, C, F3[2], u, 0.0, Rn.L, D + seg_dist(px, py, 0.0, Rn.L), tb,
+                                      kG == 1 ? C.nc4 : (ncs[q] + 3) & ~3);
             }
             // direct targets in face(h)
             const int g = h / 3;
-            int slot = act ? first_in_face(L, g) : -1;
+            int slot = act ? first_in_face<TL, kB>(L, g, hb) : -1;
             while (__ballot(slot >= 0)) {
                 const bool ok = slot >= 0;
                 double d = 0;
@@ -453,11 +498,11 @@ __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, TL &L, const 
             }
             // adjacent bend vertices along the two edges at v
             const int u1 = act ? Rh.head : 0;  // head of h
-            const int e1 = act && D + Rh.L < C.cut_acc ? M.pidx[u1] : -1;
-            bend_update(G, L.B, C.rc, e1 >= 0, e1, D + Rh.L, vtx, vty, D2 + Rh.L);
+            const int p1 = act && D + Rh.L < C.cut_acc ? M.pidx[u1] : -1;
+            bend_update(G, L.B, C.rc, p1 >= 0, eb + p1, D + Rh.L, vtx, vty, D2 + Rh.L);
             const int u2 = act ? Rh.opp_flags >> 1 : 0;
-            const int e2 = act && D + Rh.Lp < C.cut_acc ? M.pidx[u2] : -1;
-            bend_update(G, L.B, C.rc, e2 >= 0, e2, D + Rh.Lp, vtx, vty, D2 + Rh.Lp);
+            const int p2 = act && D + Rh.Lp < C.cut_acc ? M.pidx[u2] : -1;
+            bend_update(G, L.B, C.rc, p2 >= 0, eb + p2, D + Rh.Lp, vtx, vty, D2 + Rh.Lp);
             S.push(want, nw, st.overflow);
         }
         __syncthreads();  // the chunk arrays are rewritten by the next chunk
@@ -468,9 +513,13 @@ __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, TL &L, const 
 // scan the 27 cells around it, the hits are rank-sorted by particle index in
 // LDS and written out as the source's candidate row. Returns the true count
 // (more than kMaxCand is an overflow the caller reports).
-__device__ int find_candidates(const SurfDesc &sd, Lds &L, int src, int64_t c0) {
+__device__ int find_candidates(const SurfDesc &sd, Lds &L, int src, int64_t c0, int tb = 0, int cap = kMaxCand,
+                               int ci = -1) {
+    // tb, cap: the table region the targets go to (a source of a group: its
+    // share); ci: the count of a group's search q (ncg[q]), else ncand
     const int lane = lane_id();
-    if (lane == 0) L.ncand = 0;
+    int32_t &ncand = ci >= 0 ? L.ncg[ci] : L.ncand;
+    if (lane == 0) ncand = 0;
     __syncthreads();
     const double xi = sd.xyz[3 * (int64_t)src], yi = sd.xyz[3 * (int64_t)src + 1], zi = sd.xyz[3 * (int64_t)src + 2];
     const int lin = sd.cell_of[src];
@@ -486,23 +535,23 @@ __device__ int find_candidates(const SurfDesc &sd, Lds &L, int src, int64_t c0) 
                 const double ex = sd.xyz[3 * (int64_t)j] - xi, ey = sd.xyz[3 * (int64_t)j + 1] - yi,
                              ez = sd.xyz[3 * (int64_t)j + 2] - zi;
                 if (ex * ex + ey * ey + ez * ez < sd.cut2) {
-                    const int pos = atomicAdd(&L.ncand, 1);
-                    if (pos < kMaxCand) L.tnext[pos] = j;
+                    const int pos = atomicAdd(&ncand, 1);
+                    if (pos < cap) L.tnext[tb + pos] = j;
                 }
             }
         }
     }
     __syncthreads();
-    const int total = L.ncand;
-    const int m = min(total, kMaxCand);
+    const int total = ncand;
+    const int m = min(total, cap);
     for (int s = lane; s < m; s += kWave) {
-        const int j = L.tnext[s];
+        const int j = L.tnext[tb + s];
         int rank = 0;
-        for (int t = 0; t < m; ++t) rank += L.tnext[t] < j;
-        L.tj[rank] = j;
+        for (int t = 0; t < m; ++t) rank += L.tnext[tb + t] < j;
+        L.tj[tb + rank] = j;
     }
     __syncthreads();
-    for (int s = lane; s < m; s += kWave) sd.cand[c0 + s] = L.tj[s];
+    for (int s = lane; s < m; s += kWave) sd.cand[c0 + s] = L.tj[tb + s];
     if (lane == 0) sd.cand_cnt[src] = total;
     return total;
 }
@@ -599,18 +648,26 @@ __device__ int find_candidates_big(const SurfDesc &sd, LdsBig &LB, GTab &T, int 
     return total;
 }
 
-// Geodesics from one source to its candidate targets; writes the row and
-// returns whether any pair lies inside the guard band of the cutoff. Always
-// inlined: the FP32-mixed kernel holds both precisions' loops, and a call to
-// the FP64 one would make the FP32 loop spill registers around it.
-template <typename R, class TL>
-__device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &a, const SurfDesc &sd, TL &L, unsigned char *stk, int stk_bytes, int src,
-                           int64_t c0, int nc, bool guard_mode, int slot_id, SrcStats &st) {
+// Geodesics from the wavefront's sources to their candidate targets; writes
+// their rows and returns whether any pair lies inside the guard band of the
+// cutoff. Always inlined: the FP32-mixed kernel holds both precisions'
+// loops, and a call to the FP64 one would make the FP32 loop spill registers
+// around it.
+template <typename R, class TL, int kG = 1>
+__device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs &a, const SurfDesc &sd, TL &L,
+                                                                  unsigned char *stk, int stk_bytes, const int *srcs,
+                                                                  const int64_t *c0s, const int *ncs, int nsrc,
+                                                                  bool guard_mode, int slot_id, SrcStats &st) {
+    static_assert(kG == 1 || (!TL::kBig && std::is_same<R, double>::value), "groups: FP64 LDS tables only");
+    constexpr int kB = kG == 1 ? TL::kBuckets : kGroupBuckets<kG>;  // hash buckets per source
     const int lane = lane_id();
     const long long t_start = clock64();
     const unsigned long long launches0 = st.launches;
     long long iters = 0, t_launch = 0;
     const bool fp32 = sizeof(R) == 4;
+    // target ranges: a group's sources take 1/kG of the table each
+    const int tspan = kG == 1 || nsrc == 1 ? 0 : kGroupCand<kG>;
+    const int rcap1 = kG == 1 ? 0 : a.rcap / kG;  // bend-vertex entries per source of a group
     Ctx C;
     C.cutoff = sd.cutoff;
     // FP32 results may be off by rounding: everything within the guard band
@@ -623,8 +680,11 @@ __device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &
     C.tie_dir = fp32 ? a.gp.tie_dir32 : a.gp.tie_dir;
     C.root_keep = fp32 ? 1.0 - a.gp.root_rel32 : 1.0;
     C.rc = {C.root_keep, C.tie_dir, C.tie_rel};
-    C.nc = nc;
-    C.nc4 = (nc + 3) & ~3;
+    C.nc = ncs[0];
+    C.nc4 = (ncs[0] + 3) & ~3;
+    // source q's target count padded to four (read from ncs where a lane's
+    // source decides q: an array indexed per lane would live in scratch)
+    auto nc4_of = [&](int q) { return kG == 1 ? C.nc4 : (ncs[q] + 3) & ~3; };
     const HeRec *__restrict__ he = sd.m.he;
     const BendTable G = bend_table(a.roots, a.rstride, slot_id, a.rcap);
     Stack<R> S;
@@ -643,56 +703,63 @@ __device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &
         L.B.ntouched = 0;
     }
     __syncthreads();
-    for (int s = lane; s < nc; s += kWave) {
-        const int j = L.tj[s];
-        const int f = sd.face[j];
-        L.tface[s] = f;
-        for (int d = 0; d < 3; ++d) {
-            L.tb[s][d] = sd.bary[3 * (int64_t)j + d];
-            L.cb[s][d] = sd.xyz[3 * (int64_t)j + d];
+    for (int q = 0; q < nsrc; ++q) {
+        const int tb = q * tspan, nc = ncs[q];
+        for (int s = tb + lane; s < tb + nc; s += kWave) {
+            const int j = L.tj[s];
+            const int f = sd.face[j];
+            L.tface[s] = f;
+            for (int d = 0; d < 3; ++d) {
+                L.tb[s][d] = sd.bary[3 * (int64_t)j + d];
+                L.cb[s][d] = sd.xyz[3 * (int64_t)j + d];
+            }
+            L.cb[s][3] = C.cut_acc;
+            L.d1[s] = INFINITY;
+            L.d2[s] = INFINITY;
+            L.t1x[s] = 0.0;
+            L.t1y[s] = 0.0;
+            L.tnext[s] = atomicExch(&L.head[q * kB + hash_bits<kB>(f)], s);
         }
-        L.cb[s][3] = C.cut_acc;
-        L.d1[s] = INFINITY;
-        L.d2[s] = INFINITY;
-        L.t1x[s] = 0.0;
-        L.t1y[s] = 0.0;
-        L.tnext[s] = atomicExch(&L.head[hash_face<TL>(f)], s);
-    }
-    if (nc + lane < C.nc4) {
-        L.cb[nc + lane][0] = L.cb[nc + lane][1] = L.cb[nc + lane][2] = 0.0;
-        L.cb[nc + lane][3] = -INFINITY;  // padding: never reachable
+        if (nc + lane < nc4_of(q)) {
+            L.cb[tb + nc + lane][0] = L.cb[tb + nc + lane][1] = L.cb[tb + nc + lane][2] = 0.0;
+            L.cb[tb + nc + lane][3] = -INFINITY;  // padding: never reachable
+        }
     }
     __syncthreads();
 
     bool overflow = false;
     int pruned = 0;
 
-    // ---- seed from the source (root -1, sg = 0), in FP64
-    const int fs = sd.face[src];
-    const double sb[3] = {sd.bary[3 * (int64_t)src], sd.bary[3 * (int64_t)src + 1], sd.bary[3 * (int64_t)src + 2]};
-    const HeRec R0 = he[3 * fs];
-    const double P[3][2] = {{0.0, 0.0}, {R0.L, 0.0}, {R0.cx, R0.cy}};
-    const double sx = sb[1] * P[1][0] + sb[2] * P[2][0], sy = sb[1] * P[1][1] + sb[2] * P[2][1];
-    {
-        int slot = lane < 1 ? first_in_face(L, fs) : -1;
-        while (__ballot(slot >= 0)) {
-            bool ok = slot >= 0;
-            double d = 0, tx = 0, ty = 0;
-            if (ok) {
-                double qx = L.tb[slot][1] * P[1][0] + L.tb[slot][2] * P[2][0];
-                double qy = L.tb[slot][1] * P[1][1] + L.tb[slot][2] * P[2][1];
-                double dx = qx - sx, dy = qy - sy;
-                d = sqrt(dx * dx + dy * dy);
-                if (d > 0.0) {
-                    tx = dx / d;
-                    ty = dy / d;
+    // ---- seed from each source (root -1 - q, sg = 0), in FP64
+    for (int q = 0; q < nsrc; ++q) {
+        const int src = srcs[q];
+        const int hb = q * kB;
+        const int eb = q * rcap1;  // the source's bend-vertex entries
+        const int fs = sd.face[src];
+        const double sb[3] = {sd.bary[3 * (int64_t)src], sd.bary[3 * (int64_t)src + 1],
+                              sd.bary[3 * (int64_t)src + 2]};
+        const HeRec R0 = he[3 * fs];
+        const double P[3][2] = {{0.0, 0.0}, {R0.L, 0.0}, {R0.cx, R0.cy}};
+        const double sx = sb[1] * P[1][0] + sb[2] * P[2][0], sy = sb[1] * P[1][1] + sb[2] * P[2][1];
+        {
+            int slot = lane < 1 ? first_in_face<TL, kB>(L, fs, hb) : -1;
+            while (__ballot(slot >= 0)) {
+                bool ok = slot >= 0;
+                double d = 0, tx = 0, ty = 0;
+                if (ok) {
+                    double qx = L.tb[slot][1] * P[1][0] + L.tb[slot][2] * P[2][0];
+                    double qy = L.tb[slot][1] * P[1][1] + L.tb[slot][2] * P[2][1];
+                    double dx = qx - sx, dy = qy - sy;
+                    d = sqrt(dx * dx + dy * dy);
+                    if (d > 0.0) {
+                        tx = dx / d;
+                        ty = dy / d;
+                    }
                 }
+                target_update(L, C, ok, slot, d, tx, ty, INFINITY);
+                if (ok) slot = next_in_face(L, slot, fs);
             }
-            target_update(L, C, ok, slot, d, tx, ty, INFINITY);
-            if (ok) slot = next_in_face(L, slot, fs);
         }
-    }
-    {
         Win<R> w, wa, wb;
         bool want = false, wantA = false, wantB = false;
         bool rok = false;
@@ -707,7 +774,7 @@ __device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &
                 double dx = P[k][0] - sx, dy = P[k][1] - sy;
                 rd = sqrt(dx * dx + dy * dy);
                 rok = rd < C.cut_acc;
-                rv = pe;
+                rv = eb + pe;
                 rtx = rd > 0 ? dx / rd : 0.0;
                 rty = rd > 0 ? dy / rd : 0.0;
             }
@@ -721,7 +788,7 @@ __device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &
                 w.c = (R)(-ex);
                 w.s = (R)(-ey);
                 w.he = Rh.twin;
-                w.root = -1;
+                w.root = -1 - q;
                 if (sb[(k + 2) % 3] > 0.0) {
                     want = seg_dist(Rh.L - hx, -hy, 0.0, Rh.L) < C.cut_acc;
                 } else {
@@ -730,7 +797,7 @@ __device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &
                     w.py = R(0);
                     double F3[3][3], U3[3][3];
                     face_xyz(sd.m, Rh.twin / 3, Rh.twin % 3, F3, U3);
-                    children(Ht, w, 0.0, true, C, F3, U3, L, wa, wantA, wb, wantB, pruned);
+                    children(Ht, w, 0.0, true, C, F3, U3, L, wa, wantA, wb, wantB, pruned, q * tspan, nc4_of(q));
                 }
             }
         }
@@ -746,7 +813,7 @@ __device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &
             const double c = -ex, s = -ey;
             const double hx = sb[(k + 1) % 3] * Rh.L + sb[(k + 2) % 3] * Rh.cx;
             const double ptx = Rh.L - hx;
-            int slot = lane < 1 ? first_in_face(L, g) : -1;
+            int slot = lane < 1 ? first_in_face<TL, kB>(L, g, hb) : -1;
             while (__ballot(slot >= 0)) {
                 bool ok = slot >= 0;
                 double d = 0, tx = 0, ty = 0;
@@ -768,7 +835,7 @@ __device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &
             double dx = Rt.cx - ptx, dy = Rt.cy;
             double d = sqrt(dx * dx + dy * dy);
             const int pe = lane == 0 && (Rt.opp_flags & 1) && d < C.cut_acc ? sd.m.pidx[Rt.opp_flags >> 1] : -1;
-            bend_update(G, L.B, C.rc, pe >= 0, pe, d, (c * dx - s * dy) / d, (s * dx + c * dy) / d, INFINITY);
+            bend_update(G, L.B, C.rc, pe >= 0, eb + pe, d, (c * dx - s * dy) / d, (s * dx + c * dy) / d, INFINITY);
         }
         S.push(want, w, overflow);
         S.push(wantA, wa, overflow);
@@ -781,6 +848,7 @@ __device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &
     bool have = false;
     Win<R> w;
     unsigned long long nwin = 0;
+    const unsigned long long max_win = (unsigned long long)a.gp.max_windows * (unsigned long long)nsrc;
     for (;;) {
         ++iters;
         if (__ballot(overflow)) overflow = true;
@@ -791,7 +859,7 @@ __device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &
         // once nothing is left to propagate
         if (L.B.npend > 0 && (eager || !busy)) {
             const long long t0 = clock64();
-            launch_roots(a, sd, L, G, C, S, st);
+            launch_roots<R, TL, kG>(a, sd, L, G, C, S, st, tspan, ncs, rcap1);
             t_launch += clock64() - t0;
             if (!busy) busy = S.refill(have, w);
         }
@@ -800,7 +868,7 @@ __device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &
             continue;
         }
         nwin += (unsigned long long)__popcll(__ballot(have));
-        if (nwin > (unsigned long long)a.gp.max_windows) {
+        if (nwin > max_win) {
             overflow = true;
             break;
         }
@@ -813,6 +881,9 @@ __device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &
         double F3[3][3], U3[3][3];
         double wtx = 0.0, wty = 0.0, wD2 = INFINITY;  // the root's tangent and other-direction distance
         int f = -1, k = 0;
+        // the window's source: its targets, hash buckets and bend-vertex entries
+        const int q = have ? slot_of<kG>(w.root, rcap1) : 0;
+        const int tb = q * tspan, hb = q * kB, eb = q * rcap1;
         if (have) {
             // the records depend only on the entry half-edge and the root:
             // issue them together
@@ -840,10 +911,10 @@ __device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &
         }
         // the third vertex's bend-vertex number, loaded now so that the target
         // queries cover its latency
-        const int pe3 = have && H.pseudo ? sd.m.pidx[H.opp] : -1;
+        const int pv3 = have && H.pseudo ? sd.m.pidx[H.opp] : -1;
         // targets in face f
         {
-            int slot = have ? first_in_face(L, f) : -1;
+            int slot = have ? first_in_face<TL, kB>(L, f, hb) : -1;
             while (__ballot(slot >= 0)) {
                 bool ok = false;
                 double d = 0, tx = 0, ty = 0, alt = INFINITY;
@@ -873,6 +944,7 @@ __device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &
                 if (slot >= 0) slot = next_in_face(L, slot, f);
             }
         }
+        const int pe3 = pv3 >= 0 ? eb + pv3 : -1;
         // third vertex as a bend vertex: the candidate now, its table entry
         // loaded now and applied after the children (whose arithmetic covers
         // the load's latency)
@@ -908,7 +980,7 @@ __device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &
             alt3 = alt;
             if (ok) pE = bend_load(G, pe3);
         }
-        if (have) children(H, w, txc, false, C, F3, U3, L, cl, hl, cr, hr, pruned);
+        if (have) children(H, w, txc, false, C, F3, U3, L, cl, hl, cr, hr, pruned, tb, nc4_of(q));
         bend_update_loaded(G, L.B, C.rc, ok3, pe3, d3, tx3, ty3, alt3, pE);
         // keep one child in the lane, push the other
         S.push(hl && hr, cr, overflow);
@@ -919,50 +991,63 @@ __device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &
         }
     }
 
-    // ---- results (row of the candidate layout)
+    // ---- results (rows of the candidate layout)
     const long long t_res = clock64();
-    const int32_t *T = sd.m.T;
-    const double *p0 = sd.m.V + 3 * (int64_t)T[3 * fs], *p1 = sd.m.V + 3 * (int64_t)T[3 * fs + 1];
-    const double *nn = sd.m.fnrm + 3 * (int64_t)fs;
-    double ex3[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
-    double el = sqrt(ex3[0] * ex3[0] + ex3[1] * ex3[1] + ex3[2] * ex3[2]);
-    ex3[0] /= el;
-    ex3[1] /= el;
-    ex3[2] /= el;
-    double ey3[3] = {nn[1] * ex3[2] - nn[2] * ex3[1], nn[2] * ex3[0] - nn[0] * ex3[2], nn[0] * ex3[1] - nn[1] * ex3[0]};
     const bool ovf = __ballot(overflow) != 0;
     bool near_cut = false;
-    for (int s = lane; s < nc; s += kWave) {
-        const int64_t o = c0 + s;
-        double d = L.d1[s];
-        uint8_t fl = 0;
-        if (ovf) d = NAN;
-        if (L.d2[s] - d <= C.tie_rel * d) fl |= GSIM_PAIR_TIE_BIT;
-        if (d == 0.0) fl |= GSIM_PAIR_ZERO_BIT;
-        if (guard_mode) fl |= GSIM_PAIR_GUARD_BIT;
-        near_cut |= fabs(d - C.cutoff) <= a.gp.guard_rel * C.cutoff;
-        sd.cdist[o] = d;
-        sd.cflags[o] = fl;
-        for (int q = 0; q < 3; ++q) sd.ctan[3 * o + q] = L.t1x[s] * ex3[q] + L.t1y[s] * ey3[q];
+    for (int q = 0; q < nsrc; ++q) {
+        const int src = srcs[q], tb = q * tspan;
+        const int fs = sd.face[src];
+        const int32_t *T = sd.m.T;
+        const double *p0 = sd.m.V + 3 * (int64_t)T[3 * fs], *p1 = sd.m.V + 3 * (int64_t)T[3 * fs + 1];
+        const double *nn = sd.m.fnrm + 3 * (int64_t)fs;
+        double ex3[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
+        double el = sqrt(ex3[0] * ex3[0] + ex3[1] * ex3[1] + ex3[2] * ex3[2]);
+        ex3[0] /= el;
+        ex3[1] /= el;
+        ex3[2] /= el;
+        double ey3[3] = {nn[1] * ex3[2] - nn[2] * ex3[1], nn[2] * ex3[0] - nn[0] * ex3[2],
+                         nn[0] * ex3[1] - nn[1] * ex3[0]};
+        for (int s = lane; s < ncs[q]; s += kWave) {
+            const int64_t o = c0s[q] + s;
+            double d = L.d1[tb + s];
+            uint8_t fl = 0;
+            if (ovf) d = NAN;
+            if (L.d2[tb + s] - d <= C.tie_rel * d) fl |= GSIM_PAIR_TIE_BIT;
+            if (d == 0.0) fl |= GSIM_PAIR_ZERO_BIT;
+            if (guard_mode) fl |= GSIM_PAIR_GUARD_BIT;
+            near_cut |= fabs(d - C.cutoff) <= a.gp.guard_rel * C.cutoff;
+            sd.cdist[o] = d;
+            sd.cflags[o] = fl;
+            for (int c = 0; c < 3; ++c) sd.ctan[3 * o + c] = L.t1x[tb + s] * ex3[c] + L.t1y[tb + s] * ey3[c];
+        }
     }
     const bool any_near = __ballot(near_cut) != 0;
-    if (sd.prof && lane == 0) {
-        long long *q = sd.prof + 8 * (int64_t)src;
+    if (kG == 1 && sd.prof && lane == 0) {
+        long long *qp = sd.prof + 8 * (int64_t)srcs[0];
         const long long t_end = clock64();
-        q[0] += t_end - t_start;
-        q[1] += iters;
-        q[2] += (long long)nwin;
-        q[3] += (long long)(st.launches - launches0);
-        q[4] += t_loop - t_start;
-        q[5] += t_res - t_loop - t_launch;
-        q[6] += t_launch;
-        q[7] += t_end - t_res;
+        qp[0] += t_end - t_start;
+        qp[1] += iters;
+        qp[2] += (long long)nwin;
+        qp[3] += (long long)(st.launches - launches0);
+        qp[4] += t_loop - t_start;
+        qp[5] += t_res - t_loop - t_launch;
+        qp[6] += t_launch;
+        qp[7] += t_end - t_res;
     }
     st.windows += nwin;
     st.pruned += pruned;
     st.overflow |= ovf;
     bend_reset(G, L.B);
     return any_near;
+}
+
+// One source (the single-source instantiations).
+template <typename R, class TL>
+__device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &a, const SurfDesc &sd, TL &L,
+                                                                 unsigned char *stk, int stk_bytes, int src, int64_t c0,
+                                                                 int nc, bool guard_mode, int slot_id, SrcStats &st) {
+    return run_sources<R, TL, 1>(a, sd, L, stk, stk_bytes, &src, &c0, &nc, 1, guard_mode, slot_id, st);
 }
 
 // The fused update of one source particle (lane 0): force from its row,
@@ -988,9 +1073,14 @@ __device__ __attribute__((always_inline)) inline int fused_move(const SurfDesc &
 // otherwise change the register allocation of every launch.
 // kBig: the big-candidate instantiation (targets in a per-wavefront global
 // area, rows as wide as the surface's row capacity).
-template <bool kMixed, int kStk, int kMode, bool kBig>
+// kG = 2 or 4: the grouped instantiations (FP64, persistent grid, LDS
+// tables): a wavefront claims kG sources at a time and propagates together
+// those on the same surface with at most kGroupCand candidates each; a
+// source with more runs alone over the whole table.
+template <bool kMixed, int kStk, int kMode, bool kBig, int kG = 1>
 __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
     constexpr bool kOne = kMode >= 1, kFuse = kMode == 2;
+    static_assert(kG == 1 || (!kMixed && kMode == 0 && !kBig), "groups: FP64 persistent LDS-table launches");
     __shared__ typename std::conditional<kBig, LdsBig, Lds>::type L;
     __shared__ alignas(16) unsigned char stk[kStk];
     const int lane = lane_id();
@@ -1044,6 +1134,55 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
         const int si = __builtin_amdgcn_readfirstlane(batch_surface(a.bi, idx));
         const SurfDesc &sd = a.sd[si];
         const int src = sd.order[idx - a.bi.begin[si]];
+        if constexpr (kG > 1) {
+            // up to kG sources of the claimed range on this surface, each
+            // searched into its share of the table; those with no candidate
+            // drop out, those with more than a share wait and run alone
+            // over the whole table
+            constexpr int kCap = kGroupCand<kG>;
+            int nb = 0, na = 0;
+            int cur = src;
+            for (int g = 0; g < kG; ++g) {
+                if (g > 0) {
+                    if (left == 0 || __builtin_amdgcn_readfirstlane(batch_surface(a.bi, next)) != si) break;
+                    cur = sd.order[next - a.bi.begin[si]];
+                    ++next;
+                    --left;
+                }
+                const int64_t c = (int64_t)cur * kMaxCand;
+                const int n = find_candidates(sd, L, cur, c, nb * kCap, kCap, nb);
+                if (lane == 0) {
+                    if (n > kCap) {
+                        L.galone[na] = cur;
+                    } else if (n > 0) {
+                        L.gsrc[nb] = cur;
+                        L.gc0[nb] = c;
+                        L.gnc[nb] = n;
+                    }
+                }
+                na += n > kCap;
+                nb += n > 0 && n <= kCap;
+            }
+            __syncthreads();
+            if (nb > 0) {
+                st.overflow = false;
+                run_sources<double, Lds, kG>(a, sd, L, stk, kStk, L.gsrc, L.gc0, L.gnc, nb, false, blockIdx.x, st);
+                if (st.overflow) c_limited += (unsigned long long)nb;
+            }
+            for (int g = 0; g < na; ++g) {
+                const int s1 = L.galone[g];
+                const int64_t c = (int64_t)s1 * kMaxCand;
+                const int n = find_candidates(sd, L, s1, c);
+                if (n > kMaxCand) {
+                    if (lane == 0) ++c_limited;
+                } else {
+                    st.overflow = false;
+                    run_sources<double, Lds, kG>(a, sd, L, stk, kStk, &s1, &c, &n, 1, false, blockIdx.x, st);
+                    if (st.overflow) ++c_limited;
+                }
+            }
+            continue;
+        }
         // the propagation of one source over its target table
         auto process = [&](auto &T, int64_t c0, int nc, int cap) {
             if (nc > cap) {
@@ -1109,12 +1248,19 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
     }
 }
 
-template <bool kMixed, int kStk, int kMode, bool kBig>
+template <bool kMixed, int kStk, int kMode, bool kBig, int kG = 1>
 void launch_one(int nslots, size_t pad, const GeoArgs &a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (ev0 || ev1)
-        hipExtLaunchKernelGGL((k_geodesic<kMixed, kStk, kMode, kBig>), dim3(nslots), dim3(kWave), (uint32_t)pad, s, ev0,
-                              ev1, 0, a);
-    else hipLaunchKernelGGL((k_geodesic<kMixed, kStk, kMode, kBig>), dim3(nslots), dim3(kWave), pad, s, a);
+        hipExtLaunchKernelGGL((k_geodesic<kMixed, kStk, kMode, kBig, kG>), dim3(nslots), dim3(kWave), (uint32_t)pad, s,
+                              ev0, ev1, 0, a);
+    else hipLaunchKernelGGL((k_geodesic<kMixed, kStk, kMode, kBig, kG>), dim3(nslots), dim3(kWave), pad, s, a);
+}
+// the grouped instantiations: FP64, persistent grid, LDS tables
+template <int kG>
+void launch_groups(int kb, int nslots, size_t pad, const GeoArgs &a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    if (kb <= 4) launch_one<false, 4096, 0, false, kG>(nslots, pad, a, s, ev0, ev1);
+    else if (kb <= 8) launch_one<false, 8192, 0, false, kG>(nslots, pad, a, s, ev0, ev1);
+    else launch_one<false, 16384, 0, false, kG>(nslots, pad, a, s, ev0, ev1);
 }
 template <bool kMixed, int kMode>
 void launch_stack(int kb, bool big, int nslots, size_t pad, const GeoArgs &a, hipStream_t s, hipEvent_t ev0,
@@ -1137,7 +1283,7 @@ void launch_variant(int mode, int kb, bool big, int nslots, size_t pad, const Ge
 hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoParams &gp, const GeoShape &shape,
                            char *stack_mem, char *roots, int64_t rstride, int rcap, int32_t *work_ctr, Counters *ctr,
                            bool fp32, bool fuse, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, char *gtab,
-                           int gcap) {
+                           int gcap, int group) {
     GeoArgs a;
     a.sd = desc;
     a.bi = bi;
@@ -1162,6 +1308,16 @@ hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoPa
     if (fuse && total > shape.nslots) return hipErrorInvalidValue;  // the fused update needs a slot per source
     if (big && (!gtab || gcap > kBigCandMax)) return hipErrorInvalidValue;
     const size_t pad = shape.pad_lds > 0 ? (size_t)shape.pad_lds : 0;
+    if (group > 1) {
+        // several sources per wavefront: FP64, persistent grid, LDS tables,
+        // claims of a multiple of the group so that groups come from one
+        // claimed range
+        if ((group != 2 && group != 4) || fp32 || big || mode != 0 || rcap % group) return hipErrorInvalidValue;
+        a.grab = group * a.grab;
+        if (group == 2) launch_groups<2>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
+        else launch_groups<4>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
+        return hipGetLastError();
+    }
     if (fp32) launch_variant<true>(mode, shape.lds_stack_kb, big, shape.nslots, pad, a, s, ev0, ev1);
     else launch_variant<false>(mode, shape.lds_stack_kb, big, shape.nslots, pad, a, s, ev0, ev1);
     return hipGetLastError();
