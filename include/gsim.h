@@ -306,6 +306,15 @@ gsim_status gsim_step_batched(gsim_ctx *ctx, int32_t nmesh, const int32_t *mesh_
  *   "lds_stack_kb"  window-stack depth in LDS per wavefront: 4, 8 or 16 KiB (sets
  *                   how many wavefronts fit on a compute unit)
  *   "grab"          consecutive sources a wavefront claims at a time (1 .. 64)
+ *   "group_sources" 4 (default), 2 or 1: FP64 passes with a cutoff and more
+ *                   sources than resident wavefronts propagate up to this many
+ *                   neighbouring sources together in one wavefront (each with
+ *                   its share of the LDS target table; a source with more
+ *                   candidates than its share runs alone). The group shrinks
+ *                   until every resident wavefront gets a full one and the
+ *                   expected candidates of a source (twice the mean plus 8)
+ *                   fit a share. Results equal those of single sources to
+ *                   rounding (separately compiled multiply-adds)
  *   "update_block"  workgroup size of the separate update kernel: 64, 128 or 256
  *   "fuse_update"   1 (default): time steps with a cutoff and few enough particles
  *                   move each particle inside the geodesic launch; 0: always a

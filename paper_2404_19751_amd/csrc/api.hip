@@ -672,9 +672,19 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
     // each of a group's sources has its own bend-vertex entries in the
     // wavefront's table
     B.group = 1;
-    if (!fp32 && !B.all && !B.big && !c->profile_sources)
+    if (!fp32 && !B.all && !B.big && !c->profile_sources) {
+        // the expected Euclidean candidates of a source (uniform density):
+        // a group's sources share the table, so twice that plus 8 must fit a
+        // share, or too many sources would run alone
+        double mean = 0.0;
+        for (int i = 0; i < ns; ++i) {
+            const MeshState *ms = B.mem[i].ms;
+            const double cut = B.mem[i].cutoff;
+            mean = std::max(mean, ms->n * M_PI * cut * cut / std::max(surface_area(B.mem[i].ms), 1e-300));
+        }
         for (int g = c->group_sources; g > 1 && B.group == 1; g /= 2)
-            if (total >= (int64_t)g * c->cus * per_cu) B.group = g;  // a full group for every resident wavefront
+            if (total >= (int64_t)g * c->cus * per_cu && 2.0 * mean + 8.0 <= (double)(kCandCap / g)) B.group = g;
+    }
     B.rcap *= B.group;
     B.rstride = bend_table_bytes(B.rcap);
     B.fire_blk.begin[ns] = nblk;

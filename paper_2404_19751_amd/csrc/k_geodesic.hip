@@ -193,20 +193,29 @@ __device__ inline int next_in_face(const TL &L, int s, int f) {
 // The wavefront's sources: one, or in the grouped instantiations (kG = 2 or
 // 4) up to kG of the same surface, sharing the lanes, the window stack and
 // the bend-vertex table. Source q of a group owns targets [q kGroupCand,
-// ...) and hash buckets [q kGroupBuckets, ...) of the table and bend-vertex
-// entries [q rcap1, (q + 1) rcap1); its source windows carry root -1 - q,
-// its bend-vertex windows the entry index, so every window knows its source.
-// A lone source of a grouped instantiation takes the whole table.
+// ...) and hash buckets [q kGroupBuckets, ...) of the table, and entry
+// kG v + q of bend vertex v (a group's sources are neighbours and reach
+// mostly the same bend vertices: interleaved, their entries share cache
+// lines); its source windows carry root -1 - q, its bend-vertex windows the
+// entry index, so every window knows its source. A lone source of a grouped
+// instantiation takes the whole table.
 template <int kG>
-__device__ inline int slot_of(int root, int rcap1) {
+__device__ inline int slot_of(int root) {
+    static_assert(kG == 1 || kG == 2 || kG == 4, "group sizes");
     if constexpr (kG == 1) {
         return 0;
     } else {
-        int q = 0;
-#pragma unroll
-        for (int g = 1; g < kG; ++g) q += root >= g * rcap1;
-        return root >= 0 ? q : -1 - root;
+        return root >= 0 ? root & (kG - 1) : -1 - root;
     }
+}
+// bend-vertex entry of vertex number v (pidx) for source q, and back
+template <int kG>
+__device__ inline int bend_entry(int v, int q) {
+    return kG == 1 ? v : v * kG + q;
+}
+template <int kG>
+__device__ inline int bend_vertex(int e) {
+    return kG == 1 ? e : e / kG;
 }
 
 // Per-source constants shared by the helpers.
@@ -328,11 +337,11 @@ struct SrcStats {
 // smallest such distance; the others stay pending. The selected vertices
 // are compacted into a list and their fans flattened over the lanes, a chunk
 // of vertices at a time, so one launch round costs a few memory round trips,
-// not one per vertex. In the pair instantiation an entry index e stands for
-// bend vertex e mod rcap1 of source e / rcap1 (its targets from q tspan on).
+// not one per vertex. In the grouped instantiations entry e stands for bend
+// vertex e / kG of source e mod kG (its targets from q tspan on).
 template <typename R, class TL, int kG = 1>
 __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, TL &L, const BendTable &G, const Ctx &C,
-                             Stack<R> &S, SrcStats &st, int tspan = 0, const int *ncs = nullptr, int rcap1 = 0) {
+                             Stack<R> &S, SrcStats &st, int tspan = 0, const int *ncs = nullptr) {
     constexpr int kB = kG == 1 ? TL::kBuckets : kGroupBuckets<kG>;
     const int lane = lane_id();
     const DevMesh &M = sd.m;
@@ -411,8 +420,8 @@ __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, TL &L, const 
                     e = G.sel[c0 + k];
                     L.B.sel[k] = e;
                 }
-                const int q = slot_of<kG>(e, rcap1);
-                const PseudoRec pr = M.prec[e - q * rcap1];
+                const int q = slot_of<kG>(e);
+                const PseudoRec pr = M.prec[bend_vertex<kG>(e)];
                 const double D = G.rD[e];
                 // big-candidate mode: every vertex within the cutoff (as for windows)
                 bool useful = TL::kBig;
@@ -452,10 +461,10 @@ __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, TL &L, const 
                 k = lo;
             }
             const int el = act ? L.B.sel[k] : 0;
-            const int q = slot_of<kG>(el, rcap1);  // the vertex's source
-            const int tb = q * tspan, hb = q * kB, eb = q * rcap1;
+            const int q = slot_of<kG>(el);  // the vertex's source
+            const int tb = q * tspan, hb = q * kB;
             PseudoRec pr{0.0, 0.0, 0.0, 0, 0, 0, 0};
-            if (act) pr = M.prec[el - eb];
+            if (act) pr = M.prec[bend_vertex<kG>(el)];
             const double D = act ? G.rD[el] : 0.0;
             const double vtx = act ? G.rtx[el] : 0.0, vty = act ? G.rty[el] : 0.0;
             const double D2 = act ? G.rD2[el] : INFINITY;  // the vertex's other-direction distance
@@ -499,10 +508,10 @@ __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, TL &L, const 
             // adjacent bend vertices along the two edges at v
             const int u1 = act ? Rh.head : 0;  // head of h
             const int p1 = act && D + Rh.L < C.cut_acc ? M.pidx[u1] : -1;
-            bend_update(G, L.B, C.rc, p1 >= 0, eb + p1, D + Rh.L, vtx, vty, D2 + Rh.L);
+            bend_update(G, L.B, C.rc, p1 >= 0, bend_entry<kG>(p1, q), D + Rh.L, vtx, vty, D2 + Rh.L);
             const int u2 = act ? Rh.opp_flags >> 1 : 0;
             const int p2 = act && D + Rh.Lp < C.cut_acc ? M.pidx[u2] : -1;
-            bend_update(G, L.B, C.rc, p2 >= 0, eb + p2, D + Rh.Lp, vtx, vty, D2 + Rh.Lp);
+            bend_update(G, L.B, C.rc, p2 >= 0, bend_entry<kG>(p2, q), D + Rh.Lp, vtx, vty, D2 + Rh.Lp);
             S.push(want, nw, st.overflow);
         }
         __syncthreads();  // the chunk arrays are rewritten by the next chunk
@@ -667,7 +676,6 @@ __device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs 
     const bool fp32 = sizeof(R) == 4;
     // target ranges: a group's sources take 1/kG of the table each
     const int tspan = kG == 1 || nsrc == 1 ? 0 : kGroupCand<kG>;
-    const int rcap1 = kG == 1 ? 0 : a.rcap / kG;  // bend-vertex entries per source of a group
     Ctx C;
     C.cutoff = sd.cutoff;
     // FP32 results may be off by rounding: everything within the guard band
@@ -734,7 +742,6 @@ __device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs 
     for (int q = 0; q < nsrc; ++q) {
         const int src = srcs[q];
         const int hb = q * kB;
-        const int eb = q * rcap1;  // the source's bend-vertex entries
         const int fs = sd.face[src];
         const double sb[3] = {sd.bary[3 * (int64_t)src], sd.bary[3 * (int64_t)src + 1],
                               sd.bary[3 * (int64_t)src + 2]};
@@ -774,7 +781,7 @@ __device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs 
                 double dx = P[k][0] - sx, dy = P[k][1] - sy;
                 rd = sqrt(dx * dx + dy * dy);
                 rok = rd < C.cut_acc;
-                rv = eb + pe;
+                rv = bend_entry<kG>(pe, q);
                 rtx = rd > 0 ? dx / rd : 0.0;
                 rty = rd > 0 ? dy / rd : 0.0;
             }
@@ -835,7 +842,8 @@ __device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs 
             double dx = Rt.cx - ptx, dy = Rt.cy;
             double d = sqrt(dx * dx + dy * dy);
             const int pe = lane == 0 && (Rt.opp_flags & 1) && d < C.cut_acc ? sd.m.pidx[Rt.opp_flags >> 1] : -1;
-            bend_update(G, L.B, C.rc, pe >= 0, eb + pe, d, (c * dx - s * dy) / d, (s * dx + c * dy) / d, INFINITY);
+            bend_update(G, L.B, C.rc, pe >= 0, bend_entry<kG>(pe, q), d, (c * dx - s * dy) / d, (s * dx + c * dy) / d,
+                        INFINITY);
         }
         S.push(want, w, overflow);
         S.push(wantA, wa, overflow);
@@ -859,7 +867,7 @@ __device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs 
         // once nothing is left to propagate
         if (L.B.npend > 0 && (eager || !busy)) {
             const long long t0 = clock64();
-            launch_roots<R, TL, kG>(a, sd, L, G, C, S, st, tspan, ncs, rcap1);
+            launch_roots<R, TL, kG>(a, sd, L, G, C, S, st, tspan, ncs);
             t_launch += clock64() - t0;
             if (!busy) busy = S.refill(have, w);
         }
@@ -882,8 +890,8 @@ __device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs 
         double wtx = 0.0, wty = 0.0, wD2 = INFINITY;  // the root's tangent and other-direction distance
         int f = -1, k = 0;
         // the window's source: its targets, hash buckets and bend-vertex entries
-        const int q = have ? slot_of<kG>(w.root, rcap1) : 0;
-        const int tb = q * tspan, hb = q * kB, eb = q * rcap1;
+        const int q = have ? slot_of<kG>(w.root) : 0;
+        const int tb = q * tspan, hb = q * kB;
         if (have) {
             // the records depend only on the entry half-edge and the root:
             // issue them together
@@ -944,7 +952,7 @@ __device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs 
                 if (slot >= 0) slot = next_in_face(L, slot, f);
             }
         }
-        const int pe3 = pv3 >= 0 ? eb + pv3 : -1;
+        const int pe3 = pv3 >= 0 ? bend_entry<kG>(pv3, q) : -1;
         // third vertex as a bend vertex: the candidate now, its table entry
         // loaded now and applied after the children (whose arithmetic covers
         // the load's latency)
