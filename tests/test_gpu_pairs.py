@@ -76,3 +76,53 @@ def test_groups_equal_single_sources(name, group):
     log(f"[gpu-pairs] {name}: rows equal, distances and tangents within {worst:.1e}; after 3 steps {same} of "
         f"{total} particles on the same face, barycentrics within {bmax:.1e}; windows {c1['windows']} (one) / "
         f"{c2['windows']} ({group} per wavefront)")
+
+
+def _clustered_c4():
+    """The height field's particles plus a seeded cluster of 60 within 0.45
+    cutoff of particle 0: about 70 sources then have 33-72 candidates, more
+    than a group's share (32), while the mean stays near 7.5."""
+    w = W.workload("c4")
+    cut = w.potential["cutoff"]
+    x0 = w.bary[0] @ w.mesh.V[w.mesh.T[w.face[0]]]
+    cent = w.mesh.V[w.mesh.T].mean(1)
+    near = np.nonzero(np.linalg.norm(cent - x0, axis=1) < 0.45 * cut)[0]
+    rng = np.random.default_rng(5)
+    fc = near[rng.integers(0, len(near), 60)].astype(np.int32)
+    u1, u2 = rng.random(60), rng.random(60)
+    bc = np.stack([1 - np.sqrt(u1), np.sqrt(u1) * (1 - u2), np.sqrt(u1) * u2], 1)
+    return w, np.concatenate([w.face, fc]), np.concatenate([w.bary, bc]), cut
+
+
+def test_group_sources_with_too_many_candidates_run_alone(orc):
+    """Sources with more candidates than a group's share of the table run
+    alone over the whole table: the rows equal those of one source per
+    wavefront, and the crowded sources' rows match the oracle."""
+    from paper_2404_19751_amd import gsim
+    from tests.test_gpu_parity import compare_pairs
+    w, face, bary, cut = _clustered_c4()
+    out = {}
+    for group in (1, 4):
+        ctx = gsim.Context(0, "fp64")
+        try:
+            ctx.tune(group_sources=group)
+            mid = ctx.mesh_upload(w.mesh.V, w.mesh.T)
+            ctx.particles_set(mid, face, bary)
+            out[group] = ctx.geodesic_pairs(mid, cut)
+            assert ctx.counters()["limited"] == 0
+        finally:
+            ctx.close()
+    a, b = out[1], out[4]
+    assert np.array_equal(a["off"], b["off"]) and np.array_equal(a["nbr"], b["nbr"])
+    assert np.array_equal(a["flags"], b["flags"])
+    assert np.abs(a["dist"] - b["dist"]).max() <= 1e-13 * a["dist"].max()
+    crowded = np.nonzero(np.diff(b["off"]) > 32)[0]
+    assert len(crowded) >= 20
+    src = np.concatenate([crowded, np.arange(0, 20000, 997)]).astype(np.int32)
+    om = orc.OracleMesh(w.mesh.V, w.mesh.T)
+    o = orc.geodesic_pairs(om, face, bary, cut, sources=src)
+    sub = {k: np.concatenate([b[k][b["off"][i]:b["off"][i + 1]] for i in src]) for k in ("nbr", "dist", "tan", "flags")}
+    sub["off"] = np.concatenate([[0], np.cumsum([b["off"][i + 1] - b["off"][i] for i in src])])
+    err = compare_pairs(sub, o, w.mean_edge, label="clustered c4")
+    log(f"[gpu-pairs] clustered c4: {len(crowded)} sources with more than 32 candidates ran alone; "
+        f"{len(o.dist)} sampled pairs against the oracle, err {err:.2e}")
