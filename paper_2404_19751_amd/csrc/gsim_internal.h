@@ -283,7 +283,12 @@ hipError_t launch_voronoi_fill(const unsigned long long *bits, int n, int64_t wo
 // Bytes of one wavefront's bend-vertex table for rcap bend vertices (both
 // geodesic kernels): five doubles and four int32 each, rounded up to 256
 // bytes.
-__host__ __device__ inline int64_t bend_table_bytes(int rcap) { return ((int64_t)rcap * 56 + 255) / 256 * 256; }
+// bytes of one wavefront's bend-vertex table: rcap records of kBendRec bytes
+// and three int32 lists of rcap entries
+constexpr int kBendRec = 48;
+__host__ __device__ inline int64_t bend_table_bytes(int rcap) {
+    return ((int64_t)rcap * (kBendRec + 12) + 255) / 256 * 256;
+}
 // Set nslots bend-vertex tables (rstride bytes, rcap vertices each) to
 // empty: every distance infinite, nothing queued. The kernels leave them
 // empty again after each source.

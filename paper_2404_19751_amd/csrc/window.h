@@ -124,20 +124,30 @@ struct RootCfg {
 // are reset when the source is done (a fresh entry has rD = rL = rD2 =
 // infinity and queued = 0, so every source starts from an empty table
 // without a sweep over the mesh); sel receives the vertices of a launch.
+// An entry's fields form one 48-byte record (rD, rL, rtx, rty, rD2, queued),
+// so that reading or updating it touches one or two cache lines rather than
+// one per field; the three lists follow the records.
+template <typename T>
+struct RecField {
+    char *base;  // field address of entry 0
+    __device__ T &operator[](int64_t e) const { return *reinterpret_cast<T *>(base + e * kBendRec); }
+};
 struct BendTable {
-    double *rD, *rL, *rtx, *rty, *rD2;
-    int32_t *queued, *pend, *touched, *sel;
+    RecField<double> rD, rL, rtx, rty, rD2;
+    RecField<int32_t> queued;
+    int32_t *pend, *touched, *sel;
 };
 
 __device__ inline BendTable bend_table(char *base, int64_t stride, int slot, int rcap) {
     BendTable g;
-    g.rD = reinterpret_cast<double *>(base + (int64_t)slot * stride);
-    g.rL = g.rD + rcap;
-    g.rtx = g.rL + rcap;
-    g.rty = g.rtx + rcap;
-    g.rD2 = g.rty + rcap;
-    g.queued = reinterpret_cast<int32_t *>(g.rD2 + rcap);
-    g.pend = g.queued + rcap;
+    char *r = base + (int64_t)slot * stride;
+    g.rD = {r};
+    g.rL = {r + 8};
+    g.rtx = {r + 16};
+    g.rty = {r + 24};
+    g.rD2 = {r + 32};
+    g.queued = {r + 40};
+    g.pend = reinterpret_cast<int32_t *>(r + (int64_t)rcap * kBendRec);
     g.touched = g.pend + rcap;
     g.sel = g.touched + rcap;
     return g;
