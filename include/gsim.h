@@ -311,10 +311,12 @@ gsim_status gsim_step_batched(gsim_ctx *ctx, int32_t nmesh, const int32_t *mesh_
  *                   neighbouring sources together in one wavefront (each with
  *                   its share of the LDS target table; a source with more
  *                   candidates than its share runs alone). The group shrinks
- *                   until every resident wavefront gets a full one and the
+ *                   until every resident wavefront gets a full one, the
  *                   expected candidates of a source (twice the mean plus 8)
- *                   fit a share. Results equal those of single sources to
- *                   rounding (separately compiled multiply-adds)
+ *                   fit a share, and the resident wavefronts' bend-vertex
+ *                   tables (one 60-byte entry per bend vertex and source)
+ *                   fit the table budget. Results equal those of single
+ *                   sources to rounding (separately compiled multiply-adds)
  *   "update_block"  workgroup size of the separate update kernel: 64, 128 or 256
  *   "fuse_update"   1 (default): time steps with a cutoff and few enough particles
  *                   move each particle inside the geodesic launch; 0: always a

@@ -682,8 +682,14 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
             const double cut = B.mem[i].cutoff;
             mean = std::max(mean, ms->n * M_PI * cut * cut / std::max(surface_area(B.mem[i].ms), 1e-300));
         }
+        // and the resident wavefronts' bend-vertex tables (g entries per
+        // bend vertex each) must fit the table budget, or the group would
+        // cost resident wavefronts
+        const double slots = (double)std::min(c->cus * per_cu, c->max_slots);
         for (int g = c->group_sources; g > 1 && B.group == 1; g /= 2)
-            if (total >= (int64_t)g * c->cus * per_cu && 2.0 * mean + 8.0 <= (double)(kCandCap / g)) B.group = g;
+            if (total >= (int64_t)g * c->cus * per_cu && 2.0 * mean + 8.0 <= (double)(kCandCap / g) &&
+                slots * (double)bend_table_bytes(g * B.rcap) <= c->stack_budget)
+                B.group = g;
     }
     B.rcap *= B.group;
     B.rstride = bend_table_bytes(B.rcap);
