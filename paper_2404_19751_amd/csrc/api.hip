@@ -42,6 +42,7 @@ struct MeshState {
     double *bary = nullptr, *vel = nullptr, *xyz = nullptr;
     // prefilter
     Buf cell_of, cell_start, cell_fill, order, cand_cnt, cand, tmp64;
+    int64_t fill_zero = 0;  // leading cells of cell_fill known to hold zeros
     // candidate-layout results
     Buf cdist, ctan, cflags;
     // pairs
@@ -436,12 +437,9 @@ gsim_status row_capacity(gsim_ctx *c, MeshState *ms, double cutoff, int &cap) {
     pb.cap_c = kCandCap;
     for (int k = 0; k < 3; ++k) pb.dims[k] = dims[k];
     pb.cell = cell;
-    HIPCHK(c, launch_xyz(ms->dm, n, ms->face, ms->bary, ms->xyz, s));
-    HIPCHK(c, launch_prefilter_bin(ms->dm, n, pb, s));
-    HIPCHK(c, launch_scan_i32_to_i64(pb.cell_fill, P<int64_t>(ms->tmp64), (int)ncell, P<int64_t>(c->scan_scratch), s));
-    HIPCHK(c, launch_i64_to_i32(P<int64_t>(ms->tmp64), pb.cell_start, (int)ncell, s));
-    HIPCHK(c, launch_zero_i32(pb.cell_fill, ncell, s));
-    HIPCHK(c, launch_bin_scatter(n, pb, s));
+    HIPCHK(c, launch_cell_sort(ms->dm, n, ms->face, ms->bary, pb, P<int64_t>(c->scan_scratch), true, nullptr,
+                               nullptr, false, s));
+    ms->fill_zero = ncell;
     HIPCHK(c, launch_count_candidates(n, pb, cutoff * cutoff * (1.0 + 1e-12), P<int32_t>(ms->nbr_cnt), s));
     std::vector<int32_t> cnt(n);
     HIPCHK(c, hipMemcpyAsync(cnt.data(), ms->nbr_cnt.p, sizeof(int32_t) * n, hipMemcpyDeviceToHost, s));
@@ -497,7 +495,11 @@ gsim_status prepare_surface(gsim_ctx *c, const Member &mb, bool small, int src_b
     }
     HIPCHK(c, ensure(ms->cell_of, sizeof(int32_t) * n));
     HIPCHK(c, ensure(ms->cell_start, sizeof(int32_t) * (ncell + 1)));
-    HIPCHK(c, ensure(ms->cell_fill, sizeof(int32_t) * ncell));
+    {
+        const void *was = ms->cell_fill.p;
+        HIPCHK(c, ensure(ms->cell_fill, sizeof(int32_t) * ncell));
+        if (ms->cell_fill.p != was) ms->fill_zero = 0;  // a new allocation holds no known zeros
+    }
     HIPCHK(c, ensure(ms->order, sizeof(int32_t) * n));
     HIPCHK(c, ensure(ms->cand_cnt, sizeof(int32_t) * (n + 1)));
     HIPCHK(c, ensure(ms->cand, sizeof(int32_t) * (size_t)n * cap));
@@ -806,15 +808,11 @@ gsim_status geodesic_pass(gsim_ctx *c, Batch &B, bool advance, bool commit_in = 
             pb.cap_c = kCandCap;
             for (int k = 0; k < 3; ++k) pb.dims[k] = d.dims[k];
             pb.cell = d.cell;
-            HIPCHK(c, launch_pass_begin(desc_dev(c), 1, P<int32_t>(c->work), advance, s));
             if (commit_in) HIPCHK(c, launch_commit_batch(desc_dev(c), B.bi, s));
-            HIPCHK(c, launch_xyz(ms->dm, n, ms->face, ms->bary, ms->xyz, s));
-            HIPCHK(c, launch_prefilter_bin(ms->dm, n, pb, s));
-            HIPCHK(c, launch_scan_i32_to_i64(pb.cell_fill, P<int64_t>(ms->tmp64), ncell, P<int64_t>(c->scan_scratch),
-                                             s));
-            HIPCHK(c, launch_i64_to_i32(P<int64_t>(ms->tmp64), pb.cell_start, ncell, s));
-            HIPCHK(c, launch_zero_i32(pb.cell_fill, ncell, s));
-            HIPCHK(c, launch_bin_scatter(n, pb, s));
+            // starts the pass too (work counters, step counter)
+            HIPCHK(c, launch_cell_sort(ms->dm, n, ms->face, ms->bary, pb, P<int64_t>(c->scan_scratch),
+                                       ms->fill_zero < ncell, desc_dev(c), P<int32_t>(c->work), advance, s));
+            ms->fill_zero = std::max<int64_t>(ms->fill_zero, ncell);
         }
     }
     GeoParams gp = c->gp;
@@ -1404,13 +1402,9 @@ gsim_status gsim_voronoi_neighbours(gsim_ctx *c, int32_t id, int64_t *off, int32
         int32_t *err = P<int32_t>(c->wstats);
         {
             Stage st(c, "voronoi");
-            HIPCHK(c, launch_xyz(m, n, ms->face, ms->bary, ms->xyz, s));
-            HIPCHK(c, launch_prefilter_bin(m, n, pb, s));
-            HIPCHK(c, launch_scan_i32_to_i64(pb.cell_fill, P<int64_t>(ms->tmp64), (int)ncell,
-                                             P<int64_t>(c->scan_scratch), s));
-            HIPCHK(c, launch_i64_to_i32(P<int64_t>(ms->tmp64), pb.cell_start, (int)ncell, s));
-            HIPCHK(c, launch_zero_i32(pb.cell_fill, ncell, s));
-            HIPCHK(c, launch_bin_scatter(n, pb, s));
+            HIPCHK(c, launch_cell_sort(m, n, ms->face, ms->bary, pb, P<int64_t>(c->scan_scratch), true, nullptr,
+                                       nullptr, false, s));
+            ms->fill_zero = ncell;
             HIPCHK(c, launch_zero_u64(P<unsigned long long>(c->vbits), (int64_t)n * words, s));
             HIPCHK(c, launch_zero_i32(err, 2, s));
             HIPCHK(c, launch_voronoi_faces(m, n, ms->xyz, pb.cell_start, pb.order, dims, m.bbmin, cell,

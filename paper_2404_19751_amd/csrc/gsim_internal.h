@@ -151,7 +151,6 @@ hipError_t launch_xyz(const DevMesh &m, int n, const int32_t *face, const double
                       hipStream_t s);
 hipError_t launch_zero_i32(int32_t *p, int64_t n, hipStream_t s);
 hipError_t launch_zero_u64(unsigned long long *p, int64_t n, hipStream_t s);
-hipError_t launch_prefilter_bin(const DevMesh &m, int n, PrefilterBufs &b, hipStream_t s);
 hipError_t launch_scan_i32_to_i64(const int32_t *in, int64_t *out, int n, int64_t *scratch, hipStream_t s);
 
 // One surface of a batch (a single surface is a batch of one): everything
@@ -328,10 +327,18 @@ hipError_t launch_update_batch(const SurfDesc *desc, const BatchIdx &bi, int blo
                                hipStream_t s);
 // next state -> current state for every particle of the batch
 hipError_t launch_commit_batch(const SurfDesc *desc, const BatchIdx &bi, hipStream_t s);
+// Counting sort of n particles into the cells of b: positions, each
+// particle's cell, the cells' starts (cell_start[ncell] = n) and the
+// particles in cell order. b.cell_fill must hold zeros (clear writes them
+// first) and holds zeros again afterwards. With work, the first workgroup
+// also starts a geodesic pass of the one surface desc[0] (its work
+// counters; with advance, its step counter).
+hipError_t launch_cell_sort(const DevMesh &m, int n, const int32_t *face, const double *bary, PrefilterBufs &b,
+                            int64_t *scratch, bool clear, const SurfDesc *desc, int32_t *work, bool advance,
+                            hipStream_t s);
 // resident geodesic workgroups per compute unit for a stack size (0 on error)
 int geodesic_blocks_per_cu(int lds_stack_kb, bool fp32, bool big = false);
 
-hipError_t launch_bin_scatter(int n, PrefilterBufs &b, hipStream_t s);
 hipError_t launch_i64_to_i32(const int64_t *in, int32_t *out, int n, hipStream_t s);
 
 hipError_t launch_count_rows(int n, const int32_t *cnt, int cap_c, const double *dist, double cutoff, int32_t *out,

@@ -121,21 +121,69 @@ struct BB {
     double lo[3];
 };
 
-__global__ void k_bin_count(int n, PrefilterBufs b, BB bb) {
-    int j = blockIdx.x * blockDim.x + threadIdx.x;
+// The cell counting sort of one surface whose grid is too fine for one
+// workgroup's LDS, in four kernels: positions and cell counts (the first
+// workgroup also starts the geodesic pass), the block totals of the counts,
+// the cell starts (each block adds the totals of the blocks before it), and
+// the scatter. The counts start from zeros and the scatter takes each back
+// down to zero, so consecutive sorts need no clearing kernel between them.
+__global__ void k_cell_count(const double *__restrict__ V, const int32_t *__restrict__ T, int n,
+                             const int32_t *__restrict__ face, const double *__restrict__ bary, PrefilterBufs b,
+                             BB bb, const SurfDesc *__restrict__ desc, int32_t *__restrict__ work, int advance) {
+    if (work && blockIdx.x == 0) {
+        // start of a pass: the geodesic kernel's work counters, and (in a
+        // time step) the surface's step counter
+        if (threadIdx.x < kWorkChunks) work[threadIdx.x * kWorkStride] = 0;
+        if (advance && threadIdx.x == 0) *desc[0].step += 1;
+    }
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
+    const int f = face[j];
+    const double b0 = bary[3 * j], b1 = bary[3 * j + 1], b2 = bary[3 * j + 2];
+    const double *p0 = V + 3 * (int64_t)T[3 * f], *p1 = V + 3 * (int64_t)T[3 * f + 1],
+                 *p2 = V + 3 * (int64_t)T[3 * f + 2];
+    double x[3];
+    for (int d = 0; d < 3; ++d) {
+        x[d] = b0 * p0[d] + b1 * p1[d] + b2 * p2[d];
+        b.xyz[3 * j + d] = x[d];
+    }
     int c[3];
-    cell_coords(b.xyz + 3 * j, b, bb.lo, c);
-    int lin = (c[2] * b.dims[1] + c[1]) * b.dims[0] + c[0];
+    cell_coords(x, b, bb.lo, c);
+    const int lin = (c[2] * b.dims[1] + c[1]) * b.dims[0] + c[0];
     b.cell_of[j] = lin;
     atomicAdd(&b.cell_fill[lin], 1);
+}
+
+__device__ inline int64_t block_sum(int64_t v, int64_t *sh) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int w = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    int64_t t = 0;
+    for (int k = 0; k < nw; ++k) t += sh[k];
+    __syncthreads();
+    return t;
+}
+
+__global__ void k_scan_final_i32(const int32_t *__restrict__ in, int n, const int64_t *__restrict__ part,
+                                 int32_t *__restrict__ out) {
+    __shared__ int64_t sh[kScanBlock];
+    int64_t off = 0;
+    for (int k = threadIdx.x; k < (int)blockIdx.x; k += kScanBlock) off += part[k];
+    off = block_sum(off, sh);
+    const int i = blockIdx.x * kScanBlock + threadIdx.x;
+    const int64_t v = i < n ? in[i] : 0;
+    int64_t tot;
+    const int64_t ex = block_excl_scan(v, sh, &tot);
+    if (i < n) out[i] = (int32_t)(ex + off);
+    if (blockIdx.x == gridDim.x - 1 && threadIdx.x == 0) out[n] = (int32_t)(off + tot);
 }
 
 __global__ void k_bin_scatter(int n, PrefilterBufs b) {
     int j = blockIdx.x * blockDim.x + threadIdx.x;
     if (j >= n) return;
     int lin = b.cell_of[j];
-    int pos = b.cell_start[lin] + atomicAdd(&b.cell_fill[lin], 1);
+    int pos = b.cell_start[lin] + atomicSub(&b.cell_fill[lin], 1) - 1;
     b.order[pos] = j;
 }
 
@@ -513,15 +561,21 @@ hipError_t launch_scan_i32_to_i64(const int32_t *in, int64_t *out, int n, int64_
     return hipGetLastError();
 }
 
-hipError_t launch_prefilter_bin(const DevMesh &m, int n, PrefilterBufs &b, hipStream_t s) {
-    int ncell = b.dims[0] * b.dims[1] * b.dims[2];
+hipError_t launch_cell_sort(const DevMesh &m, int n, const int32_t *face, const double *bary, PrefilterBufs &b,
+                            int64_t *scratch, bool clear, const SurfDesc *desc, int32_t *work, bool advance,
+                            hipStream_t s) {
+    const int ncell = b.dims[0] * b.dims[1] * b.dims[2];
     BB bb;
     for (int d = 0; d < 3; ++d) bb.lo[d] = m.bbmin[d];
     hipError_t e;
-    if ((e = launch_zero_i32(b.cell_fill, ncell, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_bin_count, dim3(nblocks(n)), dim3(kBlock), 0, s, n, b, bb);
-    // cell_start = exclusive scan of cell_fill, computed through the int64 scan
-    // into cand_off's storage is not possible (sizes differ); use a dedicated pass
+    if (clear && (e = launch_zero_i32(b.cell_fill, ncell, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_cell_count, dim3(std::max(1, nblocks(n))), dim3(kBlock), 0, s, m.V, m.T, n, face, bary, b,
+                       bb, desc, work, advance ? 1 : 0);
+    const int nb = std::max(1, (ncell + kScanBlock - 1) / kScanBlock);
+    hipLaunchKernelGGL(k_scan_partials, dim3(nb), dim3(kScanBlock), 0, s, b.cell_fill, ncell, scratch);
+    hipLaunchKernelGGL(k_scan_final_i32, dim3(nb), dim3(kScanBlock), 0, s, b.cell_fill, ncell, scratch,
+                       b.cell_start);
+    if (n > 0) hipLaunchKernelGGL(k_bin_scatter, dim3(nblocks(n)), dim3(kBlock), 0, s, n, b);
     return hipGetLastError();
 }
 
@@ -539,10 +593,6 @@ hipError_t launch_pass_begin(const SurfDesc *desc, int nsurf, int32_t *work, boo
 hipError_t launch_fill_u64(unsigned long long *p, int64_t n, unsigned long long v, hipStream_t s) {
     if (n <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_fill_u64, dim3(nblocks(n)), dim3(kBlock), 0, s, p, n, v);
-    return hipGetLastError();
-}
-hipError_t launch_bin_scatter(int n, PrefilterBufs &b, hipStream_t s) {
-    hipLaunchKernelGGL(k_bin_scatter, dim3(nblocks(n)), dim3(kBlock), 0, s, n, b);
     return hipGetLastError();
 }
 hipError_t launch_i64_to_i32(const int64_t *in, int32_t *out, int n, hipStream_t s) {
