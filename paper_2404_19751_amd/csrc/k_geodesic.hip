@@ -522,12 +522,10 @@ __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, TL &L, const 
 // scan the 27 cells around it, the hits are rank-sorted by particle index in
 // LDS and written out as the source's candidate row. Returns the true count
 // (more than kMaxCand is an overflow the caller reports).
-__device__ int find_candidates(const SurfDesc &sd, Lds &L, int src, int64_t c0, int tb = 0, int cap = kMaxCand,
-                               int ci = -1) {
-    // tb, cap: the table region the targets go to (a source of a group: its
-    // share); ci: the count of a group's search q (ncg[q]), else ncand
+__device__ int find_candidates(const SurfDesc &sd, Lds &L, int src, int64_t c0) {
+    constexpr int tb = 0, cap = kMaxCand;
     const int lane = lane_id();
-    int32_t &ncand = ci >= 0 ? L.ncg[ci] : L.ncand;
+    int32_t &ncand = L.ncand;
     if (lane == 0) ncand = 0;
     __syncthreads();
     const double xi = sd.xyz[3 * (int64_t)src], yi = sd.xyz[3 * (int64_t)src + 1], zi = sd.xyz[3 * (int64_t)src + 2];
@@ -563,6 +561,103 @@ __device__ int find_candidates(const SurfDesc &sd, Lds &L, int src, int64_t c0, 
     for (int s = lane; s < m; s += kWave) sd.cand[c0 + s] = L.tj[tb + s];
     if (lane == 0) sd.cand_cnt[src] = total;
     return total;
+}
+
+// The Euclidean prefilter of a group's ng (at most kG) sources at once:
+// those at positions p0 .. p0 + ng - 1 of the surface's cell order. Lane
+// pairs (source, neighbour cell) scan the cells, two per lane, with their
+// loads interleaved; source q's hits go to region q of kGroupCand entries,
+// and are rank-sorted by particle index into the region of its place among
+// the sources with 1 .. kGroupCand candidates (the group, in order: gsrc,
+// gc0, gnc, nb of them), whose candidate rows are written. Sources with more
+// go to galone (na of them) and are searched again alone; every count goes
+// to cand_cnt. The same group and rows as searching the sources one by one.
+template <int kG>
+__device__ void find_candidates_group(const SurfDesc &sd, Lds &L, int p0, int ng, int &nb, int &na) {
+    constexpr int kCap = kGroupCand<kG>;
+    const int lane = lane_id();
+    if (lane < kG) L.ncg[lane] = 0;
+    __syncthreads();
+    int beg[2], len[2], own[2], qh[2];
+    double x[2], y[2], z[2];
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+        const int pr = lane + kWave * hh, q = pr / 27, l = pr - 27 * q;
+        beg[hh] = len[hh] = 0;
+        own[hh] = -1;
+        qh[hh] = q;
+        x[hh] = y[hh] = z[hh] = 0.0;
+        if (q < ng) {
+            const int src = sd.order[p0 + q];
+            own[hh] = src;
+            x[hh] = sd.xyz[3 * (int64_t)src];
+            y[hh] = sd.xyz[3 * (int64_t)src + 1];
+            z[hh] = sd.xyz[3 * (int64_t)src + 2];
+            const int lin = sd.cell_of[src];
+            const int cx = lin % sd.dims[0] + l % 3 - 1, cy = (lin / sd.dims[0]) % sd.dims[1] + (l / 3) % 3 - 1,
+                      cz = lin / (sd.dims[0] * sd.dims[1]) + l / 9 - 1;
+            if (cx >= 0 && cx < sd.dims[0] && cy >= 0 && cy < sd.dims[1] && cz >= 0 && cz < sd.dims[2]) {
+                const int c = (cz * sd.dims[1] + cy) * sd.dims[0] + cx;
+                beg[hh] = sd.cell_start[c];
+                len[hh] = sd.cell_start[c + 1] - beg[hh];
+            }
+        }
+    }
+    for (int it = 0; it < max(len[0], len[1]); ++it) {
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh) {
+            if (it < len[hh]) {
+                const int j = sd.order[beg[hh] + it];
+                if (j != own[hh]) {
+                    const double ex = sd.xyz[3 * (int64_t)j] - x[hh], ey = sd.xyz[3 * (int64_t)j + 1] - y[hh],
+                                 ez = sd.xyz[3 * (int64_t)j + 2] - z[hh];
+                    if (ex * ex + ey * ey + ez * ez < sd.cut2) {
+                        const int pos = atomicAdd(&L.ncg[qh[hh]], 1);
+                        if (pos < kCap) L.tnext[qh[hh] * kCap + pos] = j;
+                    }
+                }
+            }
+        }
+    }
+    __syncthreads();
+    // places: source q's index among the accepted ones (wave-uniform counts)
+    auto place_of = [&](int q) {
+        int pl = 0;
+        for (int t = 0; t < q; ++t) pl += L.ncg[t] > 0 && L.ncg[t] <= kCap;
+        return pl;
+    };
+    for (int k = lane; k < ng * kCap; k += kWave) {
+        const int q = k / kCap, s = k - q * kCap, m = L.ncg[q];
+        if (m <= kCap && s < m) {
+            const int j = L.tnext[q * kCap + s];
+            int rank = 0;
+            for (int t = 0; t < m; ++t) rank += L.tnext[q * kCap + t] < j;
+            L.tj[place_of(q) * kCap + rank] = j;
+        }
+    }
+    __syncthreads();
+    for (int k = lane; k < ng * kCap; k += kWave) {
+        const int q = k / kCap, s = k - q * kCap, m = L.ncg[q];
+        if (m <= kCap && s < m) sd.cand[(int64_t)sd.order[p0 + q] * kMaxCand + s] = L.tj[place_of(q) * kCap + s];
+    }
+    if (lane < ng) sd.cand_cnt[sd.order[p0 + lane]] = L.ncg[lane];
+    nb = na = 0;
+    for (int q = 0; q < ng; ++q) {
+        const int n = L.ncg[q];
+        const int src = sd.order[p0 + q];
+        if (n > kCap) {
+            if (lane == 0) L.galone[na] = src;
+            ++na;
+        } else if (n > 0) {
+            if (lane == 0) {
+                L.gsrc[nb] = src;
+                L.gc0[nb] = (int64_t)src * kMaxCand;
+                L.gnc[nb] = n;
+            }
+            ++nb;
+        }
+    }
+    __syncthreads();
 }
 
 // The Euclidean prefilter of one source in big-candidate mode: the 27 cells'
@@ -704,33 +799,52 @@ __device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs 
     S.lsp = 0;
     S.gsp = 0;
 
-    // ---- LDS tables
+    // ---- LDS tables. The sources' targets are flattened over the lanes
+    // (entry s of source q at table slot q tspan + s; e1..e3 end sources 0..2
+    // in the flattened order), so that a group's loads go out together.
     for (int e = lane; e < TL::kBuckets; e += kWave) L.head[e] = -1;
     if (lane == 0) {
         L.B.npend = 0;
         L.B.ntouched = 0;
     }
+    int e1 = ncs[0], e2 = e1, e3 = e1, ntot = e1;
+    if constexpr (kG > 1) {
+        e2 = e1 + (nsrc > 1 ? ncs[1] : 0);
+        e3 = e2 + (nsrc > 2 ? ncs[2] : 0);
+        ntot = e3 + (nsrc > 3 ? ncs[3] : 0);
+    }
+    // source and slot of flattened entry k
+    auto entry_of = [&](int k, int &q, int &s) {
+        q = kG == 1 ? 0 : (k >= e1) + (k >= e2) + (k >= e3);
+        s = k - (q == 0 ? 0 : q == 1 ? e1 : q == 2 ? e2 : e3);
+    };
     __syncthreads();
-    for (int q = 0; q < nsrc; ++q) {
-        const int tb = q * tspan, nc = ncs[q];
-        for (int s = tb + lane; s < tb + nc; s += kWave) {
-            const int j = L.tj[s];
-            const int f = sd.face[j];
-            L.tface[s] = f;
-            for (int d = 0; d < 3; ++d) {
-                L.tb[s][d] = sd.bary[3 * (int64_t)j + d];
-                L.cb[s][d] = sd.xyz[3 * (int64_t)j + d];
-            }
-            L.cb[s][3] = C.cut_acc;
-            L.d1[s] = INFINITY;
-            L.d2[s] = INFINITY;
-            L.t1x[s] = 0.0;
-            L.t1y[s] = 0.0;
-            L.tnext[s] = atomicExch(&L.head[q * kB + hash_bits<kB>(f)], s);
+    for (int k = lane; k < ntot; k += kWave) {
+        int q, s0;
+        entry_of(k, q, s0);
+        const int s = q * tspan + s0;
+        const int j = L.tj[s];
+        const int f = sd.face[j];
+        L.tface[s] = f;
+        for (int d = 0; d < 3; ++d) {
+            L.tb[s][d] = sd.bary[3 * (int64_t)j + d];
+            L.cb[s][d] = sd.xyz[3 * (int64_t)j + d];
         }
-        if (nc + lane < nc4_of(q)) {
-            L.cb[tb + nc + lane][0] = L.cb[tb + nc + lane][1] = L.cb[tb + nc + lane][2] = 0.0;
-            L.cb[tb + nc + lane][3] = -INFINITY;  // padding: never reachable
+        L.cb[s][3] = C.cut_acc;
+        L.d1[s] = INFINITY;
+        L.d2[s] = INFINITY;
+        L.t1x[s] = 0.0;
+        L.t1y[s] = 0.0;
+        L.tnext[s] = atomicExch(&L.head[q * kB + hash_bits<kB>(f)], s);
+    }
+    if (lane < 4 * nsrc) {
+        // padding of each source's bound table to a multiple of four: never reachable
+        const int q = kG == 1 ? 0 : lane >> 2, r = lane & 3;
+        const int nc = kG == 1 ? ncs[0] : ncs[q];
+        if (nc + r < ((nc + 3) & ~3)) {
+            const int s = q * tspan + nc + r;
+            L.cb[s][0] = L.cb[s][1] = L.cb[s][2] = 0.0;
+            L.cb[s][3] = -INFINITY;
         }
     }
     __syncthreads();
@@ -738,25 +852,48 @@ __device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs 
     bool overflow = false;
     int pruned = 0;
 
-    // ---- seed from each source (root -1 - q, sg = 0), in FP64
-    for (int q = 0; q < nsrc; ++q) {
-        const int src = srcs[q];
+    // ---- seed from each source (root -1 - q, sg = 0), in FP64: lane 3 q + k
+    // takes edge k of source q's face (the face frame: vertex 0 at the origin,
+    // vertex 1 on the x axis)
+    // (vertex i at (px(i), py(i)); per-lane indices are selects, not array
+    // indexing, which would put the frame in scratch memory)
+    struct SrcFrame {
+        int src, fs;
+        double b0, b1, b2, L, cx, cy, sx, sy;
+        __device__ double px(int i) const { return i == 0 ? 0.0 : i == 1 ? L : cx; }
+        __device__ double py(int i) const { return i == 2 ? cy : 0.0; }
+        __device__ double sb(int i) const { return i == 0 ? b0 : i == 1 ? b1 : b2; }
+    };
+    auto frame_of = [&](int q) {
+        SrcFrame F;
+        F.src = kG == 1 ? srcs[0] : srcs[q];
+        F.fs = sd.face[F.src];
+        F.b0 = sd.bary[3 * (int64_t)F.src];
+        F.b1 = sd.bary[3 * (int64_t)F.src + 1];
+        F.b2 = sd.bary[3 * (int64_t)F.src + 2];
+        const HeRec R0 = he[3 * F.fs];
+        F.L = R0.L;
+        F.cx = R0.cx;
+        F.cy = R0.cy;
+        F.sx = F.b1 * F.L + F.b2 * F.cx;
+        F.sy = F.b2 * F.cy;
+        return F;
+    };
+    {
+        const bool act = lane < 3 * nsrc;
+        const int q = kG == 1 || !act ? 0 : lane / 3, k = act ? lane - 3 * q : 0;
+        const SrcFrame F = frame_of(q);
         const int hb = q * kB;
-        const int fs = sd.face[src];
-        const double sb[3] = {sd.bary[3 * (int64_t)src], sd.bary[3 * (int64_t)src + 1],
-                              sd.bary[3 * (int64_t)src + 2]};
-        const HeRec R0 = he[3 * fs];
-        const double P[3][2] = {{0.0, 0.0}, {R0.L, 0.0}, {R0.cx, R0.cy}};
-        const double sx = sb[1] * P[1][0] + sb[2] * P[2][0], sy = sb[1] * P[1][1] + sb[2] * P[2][1];
+        // the targets in the source's own face (lane k = 0 of each source)
         {
-            int slot = lane < 1 ? first_in_face<TL, kB>(L, fs, hb) : -1;
+            int slot = act && k == 0 ? first_in_face<TL, kB>(L, F.fs, hb) : -1;
             while (__ballot(slot >= 0)) {
                 bool ok = slot >= 0;
                 double d = 0, tx = 0, ty = 0;
                 if (ok) {
-                    double qx = L.tb[slot][1] * P[1][0] + L.tb[slot][2] * P[2][0];
-                    double qy = L.tb[slot][1] * P[1][1] + L.tb[slot][2] * P[2][1];
-                    double dx = qx - sx, dy = qy - sy;
+                    double qx = L.tb[slot][1] * F.L + L.tb[slot][2] * F.cx;
+                    double qy = L.tb[slot][2] * F.cy;
+                    double dx = qx - F.sx, dy = qy - F.sy;
                     d = sqrt(dx * dx + dy * dy);
                     if (d > 0.0) {
                         tx = dx / d;
@@ -764,7 +901,7 @@ __device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs 
                     }
                 }
                 target_update(L, C, ok, slot, d, tx, ty, INFINITY);
-                if (ok) slot = next_in_face(L, slot, fs);
+                if (ok) slot = next_in_face(L, slot, F.fs);
             }
         }
         Win<R> w, wa, wb;
@@ -772,20 +909,21 @@ __device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs 
         bool rok = false;
         int rv = 0;
         double rd = 0, rtx = 0, rty = 0;
-        if (lane < 3) {
-            const int k = lane, h = 3 * fs + k;
+        if (act) {
+            const int h = 3 * F.fs + k;
             const HeRec Rh = he[h];
-            const double ex = (P[(k + 1) % 3][0] - P[k][0]) / Rh.L, ey = (P[(k + 1) % 3][1] - P[k][1]) / Rh.L;
+            const int k1 = k == 2 ? 0 : k + 1, k2 = k == 0 ? 2 : k - 1;  // (k + 1) % 3, (k + 2) % 3
+            const double ex = (F.px(k1) - F.px(k)) / Rh.L, ey = (F.py(k1) - F.py(k)) / Rh.L;
             const int pe = sd.m.pidx[sd.m.T[h]];
             if (pe >= 0) {
-                double dx = P[k][0] - sx, dy = P[k][1] - sy;
+                double dx = F.px(k) - F.sx, dy = F.py(k) - F.sy;
                 rd = sqrt(dx * dx + dy * dy);
                 rok = rd < C.cut_acc;
                 rv = bend_entry<kG>(pe, q);
                 rtx = rd > 0 ? dx / rd : 0.0;
                 rty = rd > 0 ? dy / rd : 0.0;
             }
-            const double hx = sb[(k + 1) % 3] * Rh.L + sb[(k + 2) % 3] * Rh.cx, hy = sb[(k + 2) % 3] * Rh.cy;
+            const double hx = F.sb(k1) * Rh.L + F.sb(k2) * Rh.cx, hy = F.sb(k2) * Rh.cy;
             if (Rh.twin >= 0) {
                 w.px = (R)(Rh.L - hx);
                 w.py = (R)(-hy);
@@ -796,7 +934,7 @@ __device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs 
                 w.s = (R)(-ey);
                 w.he = Rh.twin;
                 w.root = -1 - q;
-                if (sb[(k + 2) % 3] > 0.0) {
+                if (F.sb(k2) > 0.0) {
                     want = seg_dist(Rh.L - hx, -hy, 0.0, Rh.L) < C.cut_acc;
                 } else {
                     // source on this edge: the face across contains it as well
@@ -809,41 +947,48 @@ __device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs 
             }
         }
         bend_update(G, L.B, C.rc, rok, rv, rd, rtx, rty, INFINITY);
-        // on-edge sources: targets and third vertex of the face across
-        for (int k = 0; k < 3; ++k) {
-            bool on = sb[(k + 2) % 3] <= 0.0 && he[3 * fs + k].twin >= 0;
-            if (!on) continue;  // wave-uniform
-            const HeRec Rh = he[3 * fs + k];
-            const int t = Rh.twin, g = t / 3, m = t % 3;
-            const HeRec Rt = he[t];
-            const double ex = (P[(k + 1) % 3][0] - P[k][0]) / Rh.L, ey = (P[(k + 1) % 3][1] - P[k][1]) / Rh.L;
-            const double c = -ex, s = -ey;
-            const double hx = sb[(k + 1) % 3] * Rh.L + sb[(k + 2) % 3] * Rh.cx;
-            const double ptx = Rh.L - hx;
-            int slot = lane < 1 ? first_in_face<TL, kB>(L, g, hb) : -1;
-            while (__ballot(slot >= 0)) {
-                bool ok = slot >= 0;
-                double d = 0, tx = 0, ty = 0;
-                if (ok) {
-                    double qx = L.tb[slot][(m + 1) % 3] * Rt.L + L.tb[slot][(m + 2) % 3] * Rt.cx;
-                    double qy = L.tb[slot][(m + 2) % 3] * Rt.cy;
-                    double dx = qx - ptx, dy = qy;
-                    d = sqrt(dx * dx + dy * dy);
-                    if (d > 0) {
-                        dx /= d;
-                        dy /= d;
-                        tx = c * dx - s * dy;
-                        ty = s * dx + c * dy;
+        // on-edge sources: targets and third vertex of the face across (rare:
+        // one source at a time)
+        for (int qs = 0; qs < nsrc; ++qs) {
+            const SrcFrame E = frame_of(qs);
+            const int hbs = qs * kB;
+            for (int kk = 0; kk < 3; ++kk) {
+                const int kk1 = kk == 2 ? 0 : kk + 1, kk2 = kk == 0 ? 2 : kk - 1;
+                bool on = E.sb(kk2) <= 0.0 && he[3 * E.fs + kk].twin >= 0;
+                if (!on) continue;  // wave-uniform
+                const HeRec Rh = he[3 * E.fs + kk];
+                const int t = Rh.twin, g = t / 3, m = t % 3;
+                const HeRec Rt = he[t];
+                const double ex = (E.px(kk1) - E.px(kk)) / Rh.L, ey = (E.py(kk1) - E.py(kk)) / Rh.L;
+                const double c = -ex, sn = -ey;
+                const double hx = E.sb(kk1) * Rh.L + E.sb(kk2) * Rh.cx;
+                const double ptx = Rh.L - hx;
+                int slot = lane < 1 ? first_in_face<TL, kB>(L, g, hbs) : -1;
+                while (__ballot(slot >= 0)) {
+                    bool ok = slot >= 0;
+                    double d = 0, tx = 0, ty = 0;
+                    if (ok) {
+                        double qx = L.tb[slot][(m + 1) % 3] * Rt.L + L.tb[slot][(m + 2) % 3] * Rt.cx;
+                        double qy = L.tb[slot][(m + 2) % 3] * Rt.cy;
+                        double dx = qx - ptx, dy = qy;
+                        d = sqrt(dx * dx + dy * dy);
+                        if (d > 0) {
+                            dx /= d;
+                            dy /= d;
+                            tx = c * dx - sn * dy;
+                            ty = sn * dx + c * dy;
+                        }
                     }
+                    target_update(L, C, ok, slot, d, tx, ty, INFINITY);
+                    if (ok) slot = next_in_face(L, slot, g);
                 }
-                target_update(L, C, ok, slot, d, tx, ty, INFINITY);
-                if (ok) slot = next_in_face(L, slot, g);
+                double dx = Rt.cx - ptx, dy = Rt.cy;
+                double d = sqrt(dx * dx + dy * dy);
+                const int pe =
+                    lane == 0 && (Rt.opp_flags & 1) && d < C.cut_acc ? sd.m.pidx[Rt.opp_flags >> 1] : -1;
+                bend_update(G, L.B, C.rc, pe >= 0, bend_entry<kG>(pe, qs), d, (c * dx - sn * dy) / d,
+                            (sn * dx + c * dy) / d, INFINITY);
             }
-            double dx = Rt.cx - ptx, dy = Rt.cy;
-            double d = sqrt(dx * dx + dy * dy);
-            const int pe = lane == 0 && (Rt.opp_flags & 1) && d < C.cut_acc ? sd.m.pidx[Rt.opp_flags >> 1] : -1;
-            bend_update(G, L.B, C.rc, pe >= 0, bend_entry<kG>(pe, q), d, (c * dx - s * dy) / d, (s * dx + c * dy) / d,
-                        INFINITY);
         }
         S.push(want, w, overflow);
         S.push(wantA, wa, overflow);
@@ -1003,8 +1148,12 @@ __device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs 
     const long long t_res = clock64();
     const bool ovf = __ballot(overflow) != 0;
     bool near_cut = false;
-    for (int q = 0; q < nsrc; ++q) {
-        const int src = srcs[q], tb = q * tspan;
+    // flattened over the sources' entries like the table (each lane takes
+    // the 3D frame of its entry's source face)
+    for (int k = lane; k < ntot; k += kWave) {
+        int q, s;
+        entry_of(k, q, s);
+        const int src = kG == 1 ? srcs[0] : srcs[q], tb = q * tspan;
         const int fs = sd.face[src];
         const int32_t *T = sd.m.T;
         const double *p0 = sd.m.V + 3 * (int64_t)T[3 * fs], *p1 = sd.m.V + 3 * (int64_t)T[3 * fs + 1];
@@ -1016,19 +1165,17 @@ __device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs 
         ex3[2] /= el;
         double ey3[3] = {nn[1] * ex3[2] - nn[2] * ex3[1], nn[2] * ex3[0] - nn[0] * ex3[2],
                          nn[0] * ex3[1] - nn[1] * ex3[0]};
-        for (int s = lane; s < ncs[q]; s += kWave) {
-            const int64_t o = c0s[q] + s;
-            double d = L.d1[tb + s];
-            uint8_t fl = 0;
-            if (ovf) d = NAN;
-            if (L.d2[tb + s] - d <= C.tie_rel * d) fl |= GSIM_PAIR_TIE_BIT;
-            if (d == 0.0) fl |= GSIM_PAIR_ZERO_BIT;
-            if (guard_mode) fl |= GSIM_PAIR_GUARD_BIT;
-            near_cut |= fabs(d - C.cutoff) <= a.gp.guard_rel * C.cutoff;
-            sd.cdist[o] = d;
-            sd.cflags[o] = fl;
-            for (int c = 0; c < 3; ++c) sd.ctan[3 * o + c] = L.t1x[tb + s] * ex3[c] + L.t1y[tb + s] * ey3[c];
-        }
+        const int64_t o = (kG == 1 ? c0s[0] : c0s[q]) + s;
+        double d = L.d1[tb + s];
+        uint8_t fl = 0;
+        if (ovf) d = NAN;
+        if (L.d2[tb + s] - d <= C.tie_rel * d) fl |= GSIM_PAIR_TIE_BIT;
+        if (d == 0.0) fl |= GSIM_PAIR_ZERO_BIT;
+        if (guard_mode) fl |= GSIM_PAIR_GUARD_BIT;
+        near_cut |= fabs(d - C.cutoff) <= a.gp.guard_rel * C.cutoff;
+        sd.cdist[o] = d;
+        sd.cflags[o] = fl;
+        for (int c = 0; c < 3; ++c) sd.ctan[3 * o + c] = L.t1x[tb + s] * ex3[c] + L.t1y[tb + s] * ey3[c];
     }
     const bool any_near = __ballot(near_cut) != 0;
     if (kG == 1 && sd.prof && lane == 0) {
@@ -1147,31 +1294,12 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
             // searched into its share of the table; those with no candidate
             // drop out, those with more than a share wait and run alone
             // over the whole table
-            constexpr int kCap = kGroupCand<kG>;
-            int nb = 0, na = 0;
-            int cur = src;
-            for (int g = 0; g < kG; ++g) {
-                if (g > 0) {
-                    if (left == 0 || __builtin_amdgcn_readfirstlane(batch_surface(a.bi, next)) != si) break;
-                    cur = sd.order[next - a.bi.begin[si]];
-                    ++next;
-                    --left;
-                }
-                const int64_t c = (int64_t)cur * kMaxCand;
-                const int n = find_candidates(sd, L, cur, c, nb * kCap, kCap, nb);
-                if (lane == 0) {
-                    if (n > kCap) {
-                        L.galone[na] = cur;
-                    } else if (n > 0) {
-                        L.gsrc[nb] = cur;
-                        L.gc0[nb] = c;
-                        L.gnc[nb] = n;
-                    }
-                }
-                na += n > kCap;
-                nb += n > 0 && n <= kCap;
-            }
-            __syncthreads();
+            // the claimed sources that follow on the same surface
+            const int more = min(kG - 1, min(left, a.bi.begin[si + 1] - next));
+            next += more;
+            left -= more;
+            int nb, na;
+            find_candidates_group<kG>(sd, L, idx - a.bi.begin[si], 1 + more, nb, na);
             if (nb > 0) {
                 st.overflow = false;
                 run_sources<double, Lds, kG>(a, sd, L, stk, kStk, L.gsrc, L.gc0, L.gnc, nb, false, blockIdx.x, st);
