@@ -603,11 +603,17 @@ __device__ void find_candidates_group(const SurfDesc &sd, Lds &L, int p0, int ng
             }
         }
     }
+    // the next particle index of each pair is loaded one step ahead, so that
+    // a step waits for the positions only
+    int jn[2];
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) jn[hh] = len[hh] > 0 ? sd.order[beg[hh]] : -1;
     for (int it = 0; it < max(len[0], len[1]); ++it) {
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh) {
             if (it < len[hh]) {
-                const int j = sd.order[beg[hh] + it];
+                const int j = jn[hh];
+                if (it + 1 < len[hh]) jn[hh] = sd.order[beg[hh] + it + 1];
                 if (j != own[hh]) {
                     const double ex = sd.xyz[3 * (int64_t)j] - x[hh], ey = sd.xyz[3 * (int64_t)j + 1] - y[hh],
                                  ez = sd.xyz[3 * (int64_t)j + 2] - z[hh];
@@ -626,14 +632,21 @@ __device__ void find_candidates_group(const SurfDesc &sd, Lds &L, int p0, int ng
         for (int t = 0; t < q; ++t) pl += L.ncg[t] > 0 && L.ncg[t] <= kCap;
         return pl;
     };
-    for (int k = lane; k < ng * kCap; k += kWave) {
-        const int q = k / kCap, s = k - q * kCap, m = L.ncg[q];
-        if (m <= kCap && s < m) {
-            const int j = L.tnext[q * kCap + s];
-            int rank = 0;
-            for (int t = 0; t < m; ++t) rank += L.tnext[q * kCap + t] < j;
-            L.tj[place_of(q) * kCap + rank] = j;
+    // ranks within each source's hits, which sit in kCap consecutive lanes of
+    // a pass: compared through lane reads (absent entries hold INT_MAX)
+    static_assert(kCap == 32 || kCap == 64, "one or two sources per pass");
+    for (int base = 0; base < ng * kCap; base += kWave) {
+        const int k = base + lane, q = k / kCap, s = k - q * kCap;
+        const int m = q < ng ? L.ncg[q] : 0;
+        const bool mine = m <= kCap && s < m;
+        const int j = mine ? L.tnext[q * kCap + s] : INT_MAX;
+        int rank = 0;
+        for (int t = 0; t < kCap; ++t) {
+            int v = __builtin_amdgcn_readlane(j, t);
+            if (kCap == 32 && lane >= 32) v = __builtin_amdgcn_readlane(j, 32 + t);
+            rank += v < j;
         }
+        if (mine) L.tj[place_of(q) * kCap + rank] = j;
     }
     __syncthreads();
     for (int k = lane; k < ng * kCap; k += kWave) {
@@ -906,7 +919,7 @@ __device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs 
         }
         Win<R> w, wa, wb;
         bool want = false, wantA = false, wantB = false;
-        bool rok = false;
+        bool rok = false, on_edge = false;
         int rv = 0;
         double rd = 0, rtx = 0, rty = 0;
         if (act) {
@@ -937,6 +950,7 @@ __device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs 
                 if (F.sb(k2) > 0.0) {
                     want = seg_dist(Rh.L - hx, -hy, 0.0, Rh.L) < C.cut_acc;
                 } else {
+                    on_edge = true;
                     // source on this edge: the face across contains it as well
                     const He<R> Ht = load_he(sd.m, Rh.twin, R(0));
                     w.py = R(0);
@@ -948,8 +962,8 @@ __device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs 
         }
         bend_update(G, L.B, C.rc, rok, rv, rd, rtx, rty, INFINITY);
         // on-edge sources: targets and third vertex of the face across (rare:
-        // one source at a time)
-        for (int qs = 0; qs < nsrc; ++qs) {
+        // one source at a time, when a lane has found one)
+        for (int qs = 0; qs < nsrc && __ballot(on_edge) != 0; ++qs) {
             const SrcFrame E = frame_of(qs);
             const int hbs = qs * kB;
             for (int kk = 0; kk < 3; ++kk) {
