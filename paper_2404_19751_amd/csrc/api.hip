@@ -1088,7 +1088,7 @@ void gsim_destroy(gsim_ctx *c) {
             release(*b);
         for (void *p : {(void *)ms->face, (void *)ms->bary, (void *)ms->vel, (void *)ms->xyz})
             if (p) (void)hipFree(p);
-        for (void *p : {(void *)ms->dm.V, (void *)ms->dm.T, (void *)ms->dm.he, (void *)ms->dm.hef,
+        for (void *p : {(void *)ms->dm.V, (void *)ms->dm.T, (void *)ms->dm.he, (void *)ms->dm.twin, (void *)ms->dm.hef,
                         (void *)ms->dm.vflag, (void *)ms->dm.theta, (void *)ms->dm.fan_off, (void *)ms->dm.fan,
                         (void *)ms->dm.corner, (void *)ms->dm.fnrm, (void *)ms->dm.fpos,
                         (void *)ms->dm.pidx, (void *)ms->dm.pvert, (void *)ms->dm.prec})
@@ -1136,6 +1136,7 @@ gsim_status gsim_mesh_upload(gsim_ctx *c, int32_t nv, const double *xyz, int32_t
         HIPCHK(c, upload(d.V, H.V.data(), H.V.size(), s));
         HIPCHK(c, upload(d.T, H.T.data(), H.T.size(), s));
         HIPCHK(c, upload(d.he, H.he.data(), H.he.size(), s));
+        HIPCHK(c, upload(d.twin, H.twin.data(), H.twin.size(), s));
         HIPCHK(c, upload(d.hef, H.hef.data(), H.hef.size(), s));
         HIPCHK(c, upload(d.vflag, H.vflag.data(), H.vflag.size(), s));
         HIPCHK(c, upload(d.theta, H.theta.data(), H.theta.size(), s));

@@ -57,6 +57,7 @@ struct DevMesh {
     double *V = nullptr;        // [nv][3]
     int32_t *T = nullptr;       // [nf][3]
     HeRec *he = nullptr;        // [3nf]
+    int32_t *twin = nullptr;    // [3nf] twin of each half-edge (-1 on the boundary), 12 bytes a face
     HeRecF *hef = nullptr;      // [3nf]
     uint8_t *vflag = nullptr;   // [nv]
     double *theta = nullptr;    // [nv] corner-angle sum

@@ -75,6 +75,10 @@ __device__ inline void walk_one(const DevMesh &m, int &f, double b[3], d3 D, d3 
             const double *fp = m.fpos + 18 * (int64_t)f;
             d3 P[3] = {ld3(fp), ld3(fp + 3), ld3(fp + 6)};
             nf = ld3(m.fnrm + 3 * (int64_t)f);
+            // the faces across the three edges, loaded with the face so that
+            // a crossing waits for the next face's record only
+            const int32_t *tp = m.twin + 3 * (int64_t)f;
+            const int tw0 = tp[0], tw1 = tp[1], tw2 = tp[2];
             double twoA = sqrt(dot(cross(P[1] - P[0], P[2] - P[0]), cross(P[1] - P[0], P[2] - P[0])));
             double rate[3], s[3];
             int k1 = -1, k2 = -1;
@@ -167,10 +171,10 @@ __device__ inline void walk_one(const DevMesh &m, int &f, double b[3], d3 D, d3 
             for (int k = 0; k < 3; ++k) b[k] += s1 * rate[k];
             b[k1] = 0.0;
             rem -= s1;
-            const int h = 3 * f + (k1 + 1) % 3;
+            const int hk = (k1 + 1) % 3;
             d3 e = unit(P[(k1 + 2) % 3] - P[(k1 + 1) % 3]);
             d3 mo = cross(e, nf);  // in-plane normal of the edge, pointing out of f
-            const int tw = m.he[h].twin;
+            const int tw = hk == 0 ? tw0 : hk == 1 ? tw1 : tw2;
             if (tw < 0) {
                 ++bhit;
                 fl |= 8;
