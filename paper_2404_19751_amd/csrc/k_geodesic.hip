@@ -123,6 +123,7 @@ struct Lds {
     // the group being propagated (sources, rows, counts) and the sources that
     // wait to run alone: in LDS rather than in registers the propagation needs
     int32_t gsrc[4], gnc[4], galone[4];
+    int32_t gall[4];  // the sources a group's search covers
     int64_t gc0[4];
     BendLds B;
 };
@@ -590,6 +591,7 @@ __device__ void find_candidates_group(const SurfDesc &sd, Lds &L, int p0, int ng
         if (q < ng) {
             const int src = sd.order[p0 + q];
             own[hh] = src;
+            if (l == 0) L.gall[q] = src;
             x[hh] = sd.xyz[3 * (int64_t)src];
             y[hh] = sd.xyz[3 * (int64_t)src + 1];
             z[hh] = sd.xyz[3 * (int64_t)src + 2];
@@ -603,27 +605,37 @@ __device__ void find_candidates_group(const SurfDesc &sd, Lds &L, int p0, int ng
             }
         }
     }
-    // the next particle index of each pair is loaded one step ahead, so that
-    // a step waits for the positions only
-    int jn[2];
+    // four particles of each pair a step: their indices, then their
+    // positions, each as one round of loads
+    constexpr int kU = 4;
+    const double cut2 = sd.cut2;
+    for (int it = 0; it < max(len[0], len[1]); it += kU) {
+        int jj[2][kU];
 #pragma unroll
-    for (int hh = 0; hh < 2; ++hh) jn[hh] = len[hh] > 0 ? sd.order[beg[hh]] : -1;
-    for (int it = 0; it < max(len[0], len[1]); ++it) {
+        for (int hh = 0; hh < 2; ++hh)
 #pragma unroll
-        for (int hh = 0; hh < 2; ++hh) {
-            if (it < len[hh]) {
-                const int j = jn[hh];
-                if (it + 1 < len[hh]) jn[hh] = sd.order[beg[hh] + it + 1];
-                if (j != own[hh]) {
+            for (int u = 0; u < kU; ++u) jj[hh][u] = it + u < len[hh] ? sd.order[beg[hh] + it + u] : -1;
+        double dd[2][kU];
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+            for (int u = 0; u < kU; ++u) {
+                const int j = jj[hh][u];
+                dd[hh][u] = INFINITY;
+                if (j >= 0 && j != own[hh]) {
                     const double ex = sd.xyz[3 * (int64_t)j] - x[hh], ey = sd.xyz[3 * (int64_t)j + 1] - y[hh],
                                  ez = sd.xyz[3 * (int64_t)j + 2] - z[hh];
-                    if (ex * ex + ey * ey + ez * ez < sd.cut2) {
-                        const int pos = atomicAdd(&L.ncg[qh[hh]], 1);
-                        if (pos < kCap) L.tnext[qh[hh] * kCap + pos] = j;
-                    }
+                    dd[hh][u] = ex * ex + ey * ey + ez * ez;
                 }
             }
-        }
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+            for (int u = 0; u < kU; ++u)
+                if (dd[hh][u] < cut2) {
+                    const int pos = atomicAdd(&L.ncg[qh[hh]], 1);
+                    if (pos < kCap) L.tnext[qh[hh] * kCap + pos] = jj[hh][u];
+                }
     }
     __syncthreads();
     // places: source q's index among the accepted ones (wave-uniform counts)
@@ -651,13 +663,13 @@ __device__ void find_candidates_group(const SurfDesc &sd, Lds &L, int p0, int ng
     __syncthreads();
     for (int k = lane; k < ng * kCap; k += kWave) {
         const int q = k / kCap, s = k - q * kCap, m = L.ncg[q];
-        if (m <= kCap && s < m) sd.cand[(int64_t)sd.order[p0 + q] * kMaxCand + s] = L.tj[place_of(q) * kCap + s];
+        if (m <= kCap && s < m) sd.cand[(int64_t)L.gall[q] * kMaxCand + s] = L.tj[place_of(q) * kCap + s];
     }
-    if (lane < ng) sd.cand_cnt[sd.order[p0 + lane]] = L.ncg[lane];
+    if (lane < ng) sd.cand_cnt[L.gall[lane]] = L.ncg[lane];
     nb = na = 0;
     for (int q = 0; q < ng; ++q) {
         const int n = L.ncg[q];
-        const int src = sd.order[p0 + q];
+        const int src = L.gall[q];
         if (n > kCap) {
             if (lane == 0) L.galone[na] = src;
             ++na;
