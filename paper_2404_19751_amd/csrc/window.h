@@ -212,6 +212,46 @@ __device__ inline void bend_update_loaded(const BendTable &G, BendLds &L, const 
     if (!m) return;
     // list lengths, wave-uniform in registers
     int np = L.npend, nt = L.ntouched;
+    // The usual case: every lane holds a different entry, so each update is
+    // the lane's own, and they run at once (the lists are appended in lane
+    // order, as one lane at a time would). Otherwise one lane at a time,
+    // each result passed on to the lanes holding the same entry.
+    bool dup = false;
+    for (uint64_t r = m; r; r &= r - 1) {
+        const int l = __ffsll((unsigned long long)r) - 1;
+        dup |= ok && e == __builtin_amdgcn_readlane(e, l) && lane_id() != l;
+    }
+    if (!__ballot(dup)) {
+        int app = 0, fresh = 0;
+        if (ok) {
+            fresh = !(cD < INFINITY);
+            const bool differ = fabs(ax * ty - ay * tx) > rc.tie_dir || ax * tx + ay * ty < 0.0;
+            const bool tied = cD2 - cD <= rc.tie_rel * cD;
+            if (d < cD) {
+                if (differ) {
+                    cD2 = fmin(cD2, cD);
+                    cL = INFINITY;
+                }
+                cD = d;
+                ax = tx;
+                ay = ty;
+            } else if (differ) {
+                cD2 = fmin(cD2, d);
+            }
+            cD2 = fmin(cD2, alt);
+            if (!tied && cD2 - cD <= rc.tie_rel * cD) cL = INFINITY;
+            if (cD < cL * rc.keep && !qd) {
+                qd = 1;
+                app = 1;
+            }
+        }
+        const uint64_t ma = __ballot(app), mf = __ballot(fresh);
+        if (app) G.pend[np + __popcll(ma & lanemask_lt())] = e;
+        if (fresh) G.touched[nt + __popcll(mf & lanemask_lt())] = e;
+        np += __popcll(ma);
+        nt += __popcll(mf);
+        m = 0;
+    }
     while (m) {
         const int l = __ffsll((unsigned long long)m) - 1;
         int app = 0, fresh = 0;
