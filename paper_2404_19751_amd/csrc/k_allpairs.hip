@@ -187,6 +187,32 @@ __device__ inline void target_update(AllLds &L, double2 *td, double2 *tt, const 
         ay = t.y;
     }
     int reached = 0;  // targets found for the first time
+    // lanes on different targets (the usual case) update at once, else one
+    // lane at a time
+    bool dup = false;
+    for (uint64_t r = m; r; r &= r - 1) {
+        const int l = __ffsll((unsigned long long)r) - 1;
+        dup |= ok && j == __builtin_amdgcn_readlane(j, l) && lane_id() != l;
+    }
+    if (!__ballot(dup)) {
+        int first = 0;
+        if (ok) {
+            const bool found = c1 < INFINITY;
+            const bool differ = !found || fabs(ax * ty - ay * tx) > C.tie_dir || ax * tx + ay * ty < 0.0;
+            if (d < c1) {
+                if (differ) c2 = fmin(c2, c1);
+                c1 = d;
+                ax = tx;
+                ay = ty;
+                first = !found;
+            } else if (differ) {
+                c2 = fmin(c2, d);
+            }
+            c2 = fmin(c2, alt);
+        }
+        reached = __popcll(__ballot(first));
+        m = 0;
+    }
     while (m) {
         const int l = __ffsll((unsigned long long)m) - 1;
         int first = 0;

@@ -269,6 +269,31 @@ __device__ inline void target_update(TL &L, const Ctx &C, bool ok, int slot, dou
     // candidates no shorter than both distances (which only decrease) change nothing
     if (ok && d >= L.d1[slot] && d >= L.d2[slot] && alt >= L.d2[slot]) ok = false;
     uint64_t m = __ballot(ok);
+    if (!m) return;
+    // lanes on different targets (the usual case) update at once, else one
+    // lane at a time
+    bool dup = false;
+    for (uint64_t r = m; r; r &= r - 1) {
+        const int l = __ffsll((unsigned long long)r) - 1;
+        dup |= ok && slot == __builtin_amdgcn_readlane(slot, l) && lane_id() != l;
+    }
+    if (!__ballot(dup)) m = 0;
+    if (!m && ok) {
+        double c1 = L.d1[slot];
+        double ax = L.t1x[slot], ay = L.t1y[slot];
+        bool differ = !(c1 < INFINITY) || fabs(ax * ty - ay * tx) > C.tie_dir || ax * tx + ay * ty < 0.0;
+        if (d < c1) {
+            if (differ) L.d2[slot] = fmin(L.d2[slot], c1);
+            L.d1[slot] = d;
+            L.t1x[slot] = tx;
+            L.t1y[slot] = ty;
+            L.cb[slot][3] = fmin(C.cut_acc, d * (1.0 + C.tie_rel) + C.lb_slack);
+        } else if (differ) {
+            L.d2[slot] = fmin(L.d2[slot], d);
+        }
+        L.d2[slot] = fmin(L.d2[slot], alt);
+    }
+    lane_step_barrier();
     while (m) {
         int l = __ffsll((unsigned long long)m) - 1;
         if (lane_id() == l) {
