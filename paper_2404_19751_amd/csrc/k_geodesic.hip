@@ -849,6 +849,40 @@ __device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs 
     S.lsp = 0;
     S.gsp = 0;
 
+    // ---- the seeding's source frames and edge records, loaded before the
+    // table set-up so that their latency overlaps it. Lane 3 q + k takes edge
+    // k of source q's face (the face frame: vertex 0 at the origin, vertex 1
+    // on the x axis; vertex i at (px(i), py(i)); per-lane indices are
+    // selects, not array indexing, which would put the frame in scratch
+    // memory).
+    struct SrcFrame {
+        int src, fs;
+        double b0, b1, b2, L, cx, cy, sx, sy;
+        __device__ double px(int i) const { return i == 0 ? 0.0 : i == 1 ? L : cx; }
+        __device__ double py(int i) const { return i == 2 ? cy : 0.0; }
+        __device__ double sb(int i) const { return i == 0 ? b0 : i == 1 ? b1 : b2; }
+    };
+    auto frame_of = [&](int q) {
+        SrcFrame F;
+        F.src = kG == 1 ? srcs[0] : srcs[q];
+        F.fs = sd.face[F.src];
+        F.b0 = sd.bary[3 * (int64_t)F.src];
+        F.b1 = sd.bary[3 * (int64_t)F.src + 1];
+        F.b2 = sd.bary[3 * (int64_t)F.src + 2];
+        const HeRec R0 = he[3 * F.fs];
+        F.L = R0.L;
+        F.cx = R0.cx;
+        F.cy = R0.cy;
+        F.sx = F.b1 * F.L + F.b2 * F.cx;
+        F.sy = F.b2 * F.cy;
+        return F;
+    };
+    const bool seed_act = lane < 3 * nsrc;
+    const int seed_q = kG == 1 || !seed_act ? 0 : lane / 3, seed_k = seed_act ? lane - 3 * seed_q : 0;
+    const SrcFrame seed_F = frame_of(seed_q);
+    const HeRec seed_Rh = he[3 * seed_F.fs + seed_k];
+    const int seed_pe = seed_act ? sd.m.pidx[sd.m.T[3 * seed_F.fs + seed_k]] : -1;
+
     // ---- LDS tables. The sources' targets are flattened over the lanes
     // (entry s of source q at table slot q tspan + s; e1..e3 end sources 0..2
     // in the flattened order), so that a group's loads go out together.
@@ -903,37 +937,14 @@ __device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs 
     int pruned = 0;
 
     // ---- seed from each source (root -1 - q, sg = 0), in FP64: lane 3 q + k
-    // takes edge k of source q's face (the face frame: vertex 0 at the origin,
-    // vertex 1 on the x axis)
-    // (vertex i at (px(i), py(i)); per-lane indices are selects, not array
-    // indexing, which would put the frame in scratch memory)
-    struct SrcFrame {
-        int src, fs;
-        double b0, b1, b2, L, cx, cy, sx, sy;
-        __device__ double px(int i) const { return i == 0 ? 0.0 : i == 1 ? L : cx; }
-        __device__ double py(int i) const { return i == 2 ? cy : 0.0; }
-        __device__ double sb(int i) const { return i == 0 ? b0 : i == 1 ? b1 : b2; }
-    };
-    auto frame_of = [&](int q) {
-        SrcFrame F;
-        F.src = kG == 1 ? srcs[0] : srcs[q];
-        F.fs = sd.face[F.src];
-        F.b0 = sd.bary[3 * (int64_t)F.src];
-        F.b1 = sd.bary[3 * (int64_t)F.src + 1];
-        F.b2 = sd.bary[3 * (int64_t)F.src + 2];
-        const HeRec R0 = he[3 * F.fs];
-        F.L = R0.L;
-        F.cx = R0.cx;
-        F.cy = R0.cy;
-        F.sx = F.b1 * F.L + F.b2 * F.cx;
-        F.sy = F.b2 * F.cy;
-        return F;
-    };
+    // takes edge k of source q's face (its frame and records were loaded
+    // above)
     {
-        const bool act = lane < 3 * nsrc;
-        const int q = kG == 1 || !act ? 0 : lane / 3, k = act ? lane - 3 * q : 0;
-        const SrcFrame F = frame_of(q);
+        const bool act = seed_act;
+        const int q = seed_q, k = seed_k;
+        const SrcFrame &F = seed_F;
         const int hb = q * kB;
+        if (act && k == 0) L.B.sface[q] = F.fs;
         // the targets in the source's own face (lane k = 0 of each source)
         {
             int slot = act && k == 0 ? first_in_face<TL, kB>(L, F.fs, hb) : -1;
@@ -960,11 +971,10 @@ __device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs 
         int rv = 0;
         double rd = 0, rtx = 0, rty = 0;
         if (act) {
-            const int h = 3 * F.fs + k;
-            const HeRec Rh = he[h];
+            const HeRec &Rh = seed_Rh;
             const int k1 = k == 2 ? 0 : k + 1, k2 = k == 0 ? 2 : k - 1;  // (k + 1) % 3, (k + 2) % 3
             const double ex = (F.px(k1) - F.px(k)) / Rh.L, ey = (F.py(k1) - F.py(k)) / Rh.L;
-            const int pe = sd.m.pidx[sd.m.T[h]];
+            const int pe = seed_pe;
             if (pe >= 0) {
                 double dx = F.px(k) - F.sx, dy = F.py(k) - F.sy;
                 rd = sqrt(dx * dx + dy * dy);
@@ -1204,18 +1214,15 @@ __device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs 
     for (int k = lane; k < ntot; k += kWave) {
         int q, s;
         entry_of(k, q, s);
-        const int src = kG == 1 ? srcs[0] : srcs[q], tb = q * tspan;
-        const int fs = sd.face[src];
-        const int32_t *T = sd.m.T;
-        const double *p0 = sd.m.V + 3 * (int64_t)T[3 * fs], *p1 = sd.m.V + 3 * (int64_t)T[3 * fs + 1];
+        const int tb = q * tspan;
+        // the face frame: x along its first half-edge (the face record's unit
+        // direction), y = normal x x
+        const int fs = L.B.sface[q];
+        const double *ux = sd.m.fpos + 18 * (int64_t)fs + 9;
         const double *nn = sd.m.fnrm + 3 * (int64_t)fs;
-        double ex3[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
-        double el = sqrt(ex3[0] * ex3[0] + ex3[1] * ex3[1] + ex3[2] * ex3[2]);
-        ex3[0] /= el;
-        ex3[1] /= el;
-        ex3[2] /= el;
-        double ey3[3] = {nn[1] * ex3[2] - nn[2] * ex3[1], nn[2] * ex3[0] - nn[0] * ex3[2],
-                         nn[0] * ex3[1] - nn[1] * ex3[0]};
+        const double ex3[3] = {ux[0], ux[1], ux[2]};
+        const double ey3[3] = {nn[1] * ex3[2] - nn[2] * ex3[1], nn[2] * ex3[0] - nn[0] * ex3[2],
+                               nn[0] * ex3[1] - nn[1] * ex3[0]};
         const int64_t o = (kG == 1 ? c0s[0] : c0s[q]) + s;
         double d = L.d1[tb + s];
         uint8_t fl = 0;
