@@ -674,7 +674,7 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
     // each of a group's sources has its own bend-vertex entries in the
     // wavefront's table
     B.group = 1;
-    if (!fp32 && !B.all && !B.big && !c->profile_sources) {
+    if (!B.all && !B.big && !c->profile_sources) {
         // the expected Euclidean candidates of a source (uniform density):
         // a group's sources share the table, so twice that plus 8 must fit a
         // share, or too many sources would run alone

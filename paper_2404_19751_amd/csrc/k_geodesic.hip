@@ -808,11 +808,11 @@ __device__ int find_candidates_big(const SurfDesc &sd, LdsBig &LB, GTab &T, int 
 // loops, and a call to the FP64 one would make the FP32 loop spill registers
 // around it.
 template <typename R, class TL, int kG = 1>
-__device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs &a, const SurfDesc &sd, TL &L,
+__device__ __attribute__((always_inline)) inline unsigned run_sources(const GeoArgs &a, const SurfDesc &sd, TL &L,
                                                                   unsigned char *stk, int stk_bytes, const int *srcs,
                                                                   const int64_t *c0s, const int *ncs, int nsrc,
                                                                   bool guard_mode, int slot_id, SrcStats &st) {
-    static_assert(kG == 1 || (!TL::kBig && std::is_same<R, double>::value), "groups: FP64 LDS tables only");
+    static_assert(kG == 1 || !TL::kBig, "groups: LDS tables only");
     constexpr int kB = kG == 1 ? TL::kBuckets : kGroupBuckets<kG>;  // hash buckets per source
     const int lane = lane_id();
     const long long t_start = clock64();
@@ -1208,7 +1208,7 @@ __device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs 
     // ---- results (rows of the candidate layout)
     const long long t_res = clock64();
     const bool ovf = __ballot(overflow) != 0;
-    bool near_cut = false;
+    unsigned near_q = 0;  // bit q: a pair of source q lies inside the guard band
     // flattened over the sources' entries like the table (each lane takes
     // the 3D frame of its entry's source face)
     for (int k = lane; k < ntot; k += kWave) {
@@ -1230,12 +1230,12 @@ __device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs 
         if (L.d2[tb + s] - d <= C.tie_rel * d) fl |= GSIM_PAIR_TIE_BIT;
         if (d == 0.0) fl |= GSIM_PAIR_ZERO_BIT;
         if (guard_mode) fl |= GSIM_PAIR_GUARD_BIT;
-        near_cut |= fabs(d - C.cutoff) <= a.gp.guard_rel * C.cutoff;
+        if (fabs(d - C.cutoff) <= a.gp.guard_rel * C.cutoff) near_q |= 1u << q;
         sd.cdist[o] = d;
         sd.cflags[o] = fl;
         for (int c = 0; c < 3; ++c) sd.ctan[3 * o + c] = L.t1x[tb + s] * ex3[c] + L.t1y[tb + s] * ey3[c];
     }
-    const bool any_near = __ballot(near_cut) != 0;
+    for (int o = 32; o > 0; o >>= 1) near_q |= (unsigned)__shfl_xor((int)near_q, o);
     if (kG == 1 && sd.prof && lane == 0) {
         long long *qp = sd.prof + 8 * (int64_t)srcs[0];
         const long long t_end = clock64();
@@ -1252,12 +1252,12 @@ __device__ __attribute__((always_inline)) inline bool run_sources(const GeoArgs 
     st.pruned += pruned;
     st.overflow |= ovf;
     bend_reset(G, L.B);
-    return any_near;
+    return near_q;
 }
 
 // One source (the single-source instantiations).
 template <typename R, class TL>
-__device__ __attribute__((always_inline)) inline bool run_source(const GeoArgs &a, const SurfDesc &sd, TL &L,
+__device__ __attribute__((always_inline)) inline unsigned run_source(const GeoArgs &a, const SurfDesc &sd, TL &L,
                                                                  unsigned char *stk, int stk_bytes, int src, int64_t c0,
                                                                  int nc, bool guard_mode, int slot_id, SrcStats &st) {
     return run_sources<R, TL, 1>(a, sd, L, stk, stk_bytes, &src, &c0, &nc, 1, guard_mode, slot_id, st);
@@ -1293,7 +1293,7 @@ __device__ __attribute__((always_inline)) inline int fused_move(const SurfDesc &
 template <bool kMixed, int kStk, int kMode, bool kBig, int kG = 1>
 __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
     constexpr bool kOne = kMode >= 1, kFuse = kMode == 2;
-    static_assert(kG == 1 || (!kMixed && kMode == 0 && !kBig), "groups: FP64 persistent LDS-table launches");
+    static_assert(kG == 1 || (kMode == 0 && !kBig), "groups: persistent LDS-table launches");
     __shared__ typename std::conditional<kBig, LdsBig, Lds>::type L;
     __shared__ alignas(16) unsigned char stk[kStk];
     const int lane = lane_id();
@@ -1358,10 +1358,28 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
             left -= more;
             int nb, na;
             find_candidates_group<kG>(sd, L, idx - a.bi.begin[si], 1 + more, nb, na);
+            // FP32-mixed: the group in FP32, then each source with a pair
+            // inside the guard band of the cutoff again in FP64, alone
             if (nb > 0) {
                 st.overflow = false;
-                run_sources<double, Lds, kG>(a, sd, L, stk, kStk, L.gsrc, L.gc0, L.gnc, nb, false, blockIdx.x, st);
+                const unsigned nearm =
+                    kMixed ? run_sources<float, Lds, kG>(a, sd, L, stk, kStk, L.gsrc, L.gc0, L.gnc, nb, false,
+                                                         blockIdx.x, st)
+                           : run_sources<double, Lds, kG>(a, sd, L, stk, kStk, L.gsrc, L.gc0, L.gnc, nb, false,
+                                                          blockIdx.x, st);
                 if (st.overflow) c_limited += (unsigned long long)nb;
+                if constexpr (kMixed) {
+                    for (int q = 0; q < nb; ++q) {
+                        if (!((nearm >> q) & 1u)) continue;  // wave-uniform
+                        const int s1 = L.gsrc[q];
+                        const int64_t c = L.gc0[q];
+                        const int n = find_candidates(sd, L, s1, c);
+                        st.overflow = false;
+                        run_sources<double, Lds, kG>(a, sd, L, stk, kStk, &s1, &c, &n, 1, true, blockIdx.x, st);
+                        ++st.guards;
+                        if (st.overflow) ++c_limited;
+                    }
+                }
             }
             for (int g = 0; g < na; ++g) {
                 const int s1 = L.galone[g];
@@ -1371,7 +1389,14 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
                     if (lane == 0) ++c_limited;
                 } else {
                     st.overflow = false;
-                    run_sources<double, Lds, kG>(a, sd, L, stk, kStk, &s1, &c, &n, 1, false, blockIdx.x, st);
+                    if (kMixed) {
+                        if (run_sources<float, Lds, kG>(a, sd, L, stk, kStk, &s1, &c, &n, 1, false, blockIdx.x, st)) {
+                            run_sources<double, Lds, kG>(a, sd, L, stk, kStk, &s1, &c, &n, 1, true, blockIdx.x, st);
+                            ++st.guards;
+                        }
+                    } else {
+                        run_sources<double, Lds, kG>(a, sd, L, stk, kStk, &s1, &c, &n, 1, false, blockIdx.x, st);
+                    }
                     if (st.overflow) ++c_limited;
                 }
             }
@@ -1450,11 +1475,11 @@ void launch_one(int nslots, size_t pad, const GeoArgs &a, hipStream_t s, hipEven
     else hipLaunchKernelGGL((k_geodesic<kMixed, kStk, kMode, kBig, kG>), dim3(nslots), dim3(kWave), pad, s, a);
 }
 // the grouped instantiations: FP64, persistent grid, LDS tables
-template <int kG>
+template <bool kMixed, int kG>
 void launch_groups(int kb, int nslots, size_t pad, const GeoArgs &a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
-    if (kb <= 4) launch_one<false, 4096, 0, false, kG>(nslots, pad, a, s, ev0, ev1);
-    else if (kb <= 8) launch_one<false, 8192, 0, false, kG>(nslots, pad, a, s, ev0, ev1);
-    else launch_one<false, 16384, 0, false, kG>(nslots, pad, a, s, ev0, ev1);
+    if (kb <= 4) launch_one<kMixed, 4096, 0, false, kG>(nslots, pad, a, s, ev0, ev1);
+    else if (kb <= 8) launch_one<kMixed, 8192, 0, false, kG>(nslots, pad, a, s, ev0, ev1);
+    else launch_one<kMixed, 16384, 0, false, kG>(nslots, pad, a, s, ev0, ev1);
 }
 template <bool kMixed, int kMode>
 void launch_stack(int kb, bool big, int nslots, size_t pad, const GeoArgs &a, hipStream_t s, hipEvent_t ev0,
@@ -1506,10 +1531,15 @@ hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoPa
         // several sources per wavefront: FP64, persistent grid, LDS tables,
         // claims of a multiple of the group so that groups come from one
         // claimed range
-        if ((group != 2 && group != 4) || fp32 || big || mode != 0 || rcap % group) return hipErrorInvalidValue;
+        if ((group != 2 && group != 4) || big || mode != 0 || rcap % group) return hipErrorInvalidValue;
         a.grab = group * a.grab;
-        if (group == 2) launch_groups<2>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
-        else launch_groups<4>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
+        if (fp32) {
+            if (group == 2) launch_groups<true, 2>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
+            else launch_groups<true, 4>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
+        } else {
+            if (group == 2) launch_groups<false, 2>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
+            else launch_groups<false, 4>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
+        }
         return hipGetLastError();
     }
     if (fp32) launch_variant<true>(mode, shape.lds_stack_kb, big, shape.nslots, pad, a, s, ev0, ev1);

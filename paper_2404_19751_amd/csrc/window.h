@@ -24,13 +24,15 @@ struct Win {
 
 // stack records: 64 bytes (FP64) / 32 bytes (FP32). A window of a bend
 // vertex takes its tangent from the vertex, not from its own frame rotation
-// (c, s), so the FP32 record keeps the bend vertex in the slot of c instead.
+// (c, s), so the FP32 record keeps the bend vertex in the slot of c instead;
+// a source window has sg = 0, so the FP32 record keeps its root (-1 - the
+// source's place in a group) in the slot of sg.
 struct Rec64 {
     double v[7];
     int32_t he, root;
 };
 struct Rec32 {
-    float v[7];   // px, py, b0, b1, sg, then c, s (source windows) or the root's bits, 0
+    float v[7];   // px, py, b0, b1, then the root's bits, c, s (source windows) or sg, the root's bits, 0
     uint32_t hr;  // he | (1 << 31) for a window of a bend vertex
 };
 static_assert(sizeof(Rec64) == 64 && sizeof(Rec32) == 32, "stack record sizes");
@@ -57,18 +59,20 @@ __device__ inline void load_rec(const Rec64 &q, Win<double> &w) {
 }
 __device__ inline void store_rec(Rec32 &q, const Win<float> &w) {
     const bool rooted = w.root >= 0;
-    q.v[0] = w.px; q.v[1] = w.py; q.v[2] = w.b0; q.v[3] = w.b1; q.v[4] = w.sg;
+    q.v[0] = w.px; q.v[1] = w.py; q.v[2] = w.b0; q.v[3] = w.b1;
+    q.v[4] = rooted ? w.sg : __int_as_float(w.root);
     q.v[5] = rooted ? __int_as_float(w.root) : w.c;
     q.v[6] = rooted ? 0.0f : w.s;
     q.hr = (uint32_t)w.he | (rooted ? 0x80000000u : 0u);
 }
 __device__ inline void load_rec(const Rec32 &q, Win<float> &w) {
     const bool rooted = (q.hr >> 31) != 0;
-    w.px = q.v[0]; w.py = q.v[1]; w.b0 = q.v[2]; w.b1 = q.v[3]; w.sg = q.v[4];
+    w.px = q.v[0]; w.py = q.v[1]; w.b0 = q.v[2]; w.b1 = q.v[3];
+    w.sg = rooted ? q.v[4] : 0.0f;
     w.c = rooted ? 1.0f : q.v[5];
     w.s = rooted ? 0.0f : q.v[6];
     w.he = (int)(q.hr & 0x7fffffffu);
-    w.root = rooted ? __float_as_int(q.v[5]) : -1;
+    w.root = __float_as_int(rooted ? q.v[5] : q.v[4]);
 }
 
 // half-edge record in the working precision
