@@ -306,7 +306,7 @@ gsim_status gsim_step_batched(gsim_ctx *ctx, int32_t nmesh, const int32_t *mesh_
  *   "lds_stack_kb"  window-stack depth in LDS per wavefront: 4, 8 or 16 KiB (sets
  *                   how many wavefronts fit on a compute unit)
  *   "grab"          consecutive sources a wavefront claims at a time (1 .. 64)
- *   "group_sources" 4 (default), 2 or 1: FP64 passes with a cutoff and more
+ *   "group_sources" 4 (default), 2 or 1: passes with a cutoff and more
  *                   sources than resident wavefronts propagate up to this many
  *                   neighbouring sources together in one wavefront (each with
  *                   its share of the LDS target table; a source with more
@@ -316,7 +316,10 @@ gsim_status gsim_step_batched(gsim_ctx *ctx, int32_t nmesh, const int32_t *mesh_
  *                   fit a share, and the resident wavefronts' bend-vertex
  *                   tables (one 60-byte entry per bend vertex and source)
  *                   fit the table budget. Results equal those of single
- *                   sources to rounding (separately compiled multiply-adds)
+ *                   sources to rounding (separately compiled multiply-adds).
+ *                   In FP32-mixed mode a group propagates in FP32 and each
+ *                   of its sources with a pair in the guard band runs again
+ *                   alone in FP64
  *   "update_block"  workgroup size of the separate update kernel: 64, 128 or 256
  *   "fuse_update"   1 (default): time steps with a cutoff and few enough particles
  *                   move each particle inside the geodesic launch; 0: always a
