@@ -126,3 +126,37 @@ def test_group_sources_with_too_many_candidates_run_alone(orc):
     err = compare_pairs(sub, o, w.mean_edge, label="clustered c4")
     log(f"[gpu-pairs] clustered c4: {len(crowded)} sources with more than 32 candidates ran alone; "
         f"{len(o.dist)} sampled pairs against the oracle, err {err:.2e}")
+
+
+def test_fp32_groups_against_oracle(orc):
+    """FP32-mixed with four sources per wavefront on the clustered height
+    field: the group in FP32, sources with a pair in the guard band again
+    alone in FP64, crowded sources alone. Their rows and a sample of the rest
+    match the oracle to the FP32 tolerance (bit-exact neighbour sets)."""
+    from paper_2404_19751_amd import gsim
+    from tests.test_gpu_fp32 import compare32
+    from tests.util import oracle_band
+    w, face, bary, cut = _clustered_c4()
+    ctx = gsim.Context(0, "fp32")
+    try:
+        ctx.tune(group_sources=4)
+        mid = ctx.mesh_upload(w.mesh.V, w.mesh.T)
+        ctx.particles_set(mid, face, bary)
+        b = ctx.geodesic_pairs(mid, cut)
+        cnt = ctx.counters()
+        assert cnt["limited"] == 0
+    finally:
+        ctx.close()
+    crowded = np.nonzero(np.diff(b["off"]) > 32)[0]
+    assert len(crowded) >= 20
+    guard = np.nonzero(np.bitwise_and(b["flags"], 4))[0]
+    gsrc = np.unique(np.searchsorted(b["off"], guard, side="right") - 1)
+    src = np.unique(np.concatenate([crowded, gsrc[:40], np.arange(0, 20000, 997)])).astype(np.int32)
+    om = orc.OracleMesh(w.mesh.V, w.mesh.T)
+    o = orc.geodesic_pairs(om, face, bary, cut, sources=src, **oracle_band("fp32"))
+    sub = {k: np.concatenate([b[k][b["off"][i]:b["off"][i + 1]] for i in src]) for k in ("nbr", "dist", "tan", "flags")}
+    sub["off"] = np.concatenate([[0], np.cumsum([b["off"][i + 1] - b["off"][i] for i in src])])
+    d_err, t_err = compare32(sub, o, w.mean_edge, "clustered c4 fp32")
+    log(f"[gpu-pairs] clustered c4 fp32: {len(crowded)} crowded sources, {len(gsrc)} recomputed in FP64 "
+        f"({cnt['guard_sources']} guard runs); {len(src)} sources against the oracle, dist err {d_err:.2e}, "
+        f"tan err {t_err:.2e}")
