@@ -57,24 +57,21 @@ __device__ inline void row_force(int i, const int32_t *__restrict__ cnt, int cap
         F[2] += dU * t2;
         E += 0.5 * U;
     };
-    int s = 0;
-    // four entries' loads issued together, then summed in ascending order
-    for (; s + 4 <= m; s += 4) {
+    // eight entries' loads issued together (those past the row's end
+    // masked), then summed in ascending order
+    for (int s = 0; s < m; s += 8) {
         const int64_t p = (int64_t)i * cap + s;
-        double d[4], t[4][3];
+        double d[8], t[8][3];
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            d[q] = dist[p + q];
-            t[q][0] = tan[3 * (p + q)];
-            t[q][1] = tan[3 * (p + q) + 1];
-            t[q][2] = tan[3 * (p + q) + 2];
+        for (int q = 0; q < 8; ++q) {
+            const bool in = s + q < m;
+            d[q] = in ? dist[p + q] : INFINITY;
+            t[q][0] = in ? tan[3 * (p + q)] : 0.0;
+            t[q][1] = in ? tan[3 * (p + q) + 1] : 0.0;
+            t[q][2] = in ? tan[3 * (p + q) + 2] : 0.0;
         }
 #pragma unroll
-        for (int q = 0; q < 4; ++q) add(d[q], t[q][0], t[q][1], t[q][2]);
-    }
-    for (; s < m; ++s) {
-        const int64_t p = (int64_t)i * cap + s;
-        add(dist[p], tan[3 * p], tan[3 * p + 1], tan[3 * p + 2]);
+        for (int q = 0; q < 8; ++q) add(d[q], t[q][0], t[q][1], t[q][2]);
     }
 }
 
@@ -124,12 +121,10 @@ __device__ inline void displacement(const DevMesh &m, int f, int i, const double
     }
     double e1, e2;
     gaussian_pair(seed, step, i, e1, e2);
-    const double *p0 = m.V + 3 * (int64_t)m.T[3 * f], *p1 = m.V + 3 * (int64_t)m.T[3 * f + 1];
-    double ex[3] = {p1[0] - p0[0], p1[1] - p0[1], p1[2] - p0[2]};
-    const double l = sqrt(ex[0] * ex[0] + ex[1] * ex[1] + ex[2] * ex[2]);
-    ex[0] /= l;
-    ex[1] /= l;
-    ex[2] /= l;
+    // the unit direction of the first edge from the face record (one load
+    // after the face index, not the vertex indices and then the vertices)
+    const double *u0 = m.fpos + 18 * (int64_t)f + 9;
+    const double ex[3] = {u0[0], u0[1], u0[2]};
     const double *nn = m.fnrm + 3 * (int64_t)f;
     const double ey[3] = {nn[1] * ex[2] - nn[2] * ex[1], nn[2] * ex[0] - nn[0] * ex[2], nn[0] * ex[1] - nn[1] * ex[0]};
     const double amp = sqrt(2.0 * kT * lam * dt) / lam, a = dt / lam;
