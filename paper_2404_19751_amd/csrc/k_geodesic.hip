@@ -36,17 +36,18 @@
 //
 // Mapping to CDNA4: one wavefront per source (one workgroup per source when
 // there are no more sources than resident slots, else a persistent grid that
-// claims them; either way sources in spatial cell order from eight per-XCD
-// chunks so each XCD's L2 serves one region of the mesh); each lane holds one
-// live window in registers; a
-// lane with two children keeps one and pushes the other onto an LDS window
-// stack (ballot/popcount compaction; a per-wave global overflow area takes
-// what does not fit); idle lanes pop. The target table lives in LDS and its
-// updates are serialised across lanes by a ballot loop (no atomics,
-// deterministic in wave order); the bend-vertex table is a per-wavefront
-// table in global memory indexed by the mesh's bend-vertex number (any
-// number of bend vertices per source), emptied through its touched list. The
-// LDS stack depth is a template parameter: a shallower stack lowers the
+// claims them, up to four neighbouring sources per wavefront; either way
+// sources in spatial cell order from eight per-XCD chunks so each XCD's L2
+// serves one region of the mesh); each lane holds one live window in
+// registers; a lane with two children keeps one and pushes the other onto an
+// LDS window stack (ballot/popcount compaction; a per-wave global overflow
+// area takes what does not fit); idle lanes pop. The target table lives in
+// LDS; the bend-vertex table is a per-wavefront table in global memory
+// indexed by the mesh's bend-vertex number (any number of bend vertices per
+// source), emptied through its touched list. Lanes updating different
+// entries of either table do so at once, lanes on the same entry one at a
+// time by a ballot loop (no atomics, deterministic in wave order). The LDS
+// stack depth is a template parameter: a shallower stack lowers the
 // workgroup's LDS footprint and lets more wavefronts share a compute unit.
 //
 // Batches: the sources of several surfaces (each with its own mesh, cutoff
@@ -259,7 +260,7 @@ __device__ inline bool reaches_target(const TL &L, const Ctx &C, const double P[
     return false;
 }
 
-// Serialised target update: best distance, its tangent, and the best
+// Target update: best distance, its tangent, and the best
 // distance among candidates whose direction differs (tie gap); `alt` is the
 // distance of another-direction path that comes with the candidate (through
 // a bend vertex with a second distance).
@@ -1286,10 +1287,12 @@ __device__ __attribute__((always_inline)) inline int fused_move(const SurfDesc &
 // otherwise change the register allocation of every launch.
 // kBig: the big-candidate instantiation (targets in a per-wavefront global
 // area, rows as wide as the surface's row capacity).
-// kG = 2 or 4: the grouped instantiations (FP64, persistent grid, LDS
-// tables): a wavefront claims kG sources at a time and propagates together
-// those on the same surface with at most kGroupCand candidates each; a
-// source with more runs alone over the whole table.
+// kG = 2 or 4: the grouped instantiations (persistent grid, LDS tables): a
+// wavefront claims kG sources at a time and propagates together those on
+// the same surface with at most kGroupCand candidates each; a source with
+// more runs alone over the whole table. In FP32-mixed mode the group runs in
+// FP32 and each of its sources with a pair in the guard band again alone in
+// FP64.
 template <bool kMixed, int kStk, int kMode, bool kBig, int kG = 1>
 __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
     constexpr bool kOne = kMode >= 1, kFuse = kMode == 2;
@@ -1474,7 +1477,7 @@ void launch_one(int nslots, size_t pad, const GeoArgs &a, hipStream_t s, hipEven
                               ev0, ev1, 0, a);
     else hipLaunchKernelGGL((k_geodesic<kMixed, kStk, kMode, kBig, kG>), dim3(nslots), dim3(kWave), pad, s, a);
 }
-// the grouped instantiations: FP64, persistent grid, LDS tables
+// the grouped instantiations: persistent grid, LDS tables
 template <bool kMixed, int kG>
 void launch_groups(int kb, int nslots, size_t pad, const GeoArgs &a, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
     if (kb <= 4) launch_one<kMixed, 4096, 0, false, kG>(nslots, pad, a, s, ev0, ev1);
@@ -1528,9 +1531,9 @@ hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoPa
     if (big && (!gtab || gcap > kBigCandMax)) return hipErrorInvalidValue;
     const size_t pad = shape.pad_lds > 0 ? (size_t)shape.pad_lds : 0;
     if (group > 1) {
-        // several sources per wavefront: FP64, persistent grid, LDS tables,
-        // claims of a multiple of the group so that groups come from one
-        // claimed range
+        // several sources per wavefront: persistent grid, LDS tables, claims
+        // of a multiple of the group so that groups come from one claimed
+        // range
         if ((group != 2 && group != 4) || big || mode != 0 || rcap % group) return hipErrorInvalidValue;
         a.grab = group * a.grab;
         if (fp32) {
