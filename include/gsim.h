@@ -306,16 +306,17 @@ gsim_status gsim_step_batched(gsim_ctx *ctx, int32_t nmesh, const int32_t *mesh_
  *   "lds_stack_kb"  window-stack depth in LDS per wavefront: 4, 8 or 16 KiB (sets
  *                   how many wavefronts fit on a compute unit)
  *   "grab"          consecutive sources a wavefront claims at a time (1 .. 64)
- *   "group_sources" 4 (default), 2 or 1: passes with a cutoff and more
+ *   "group_sources" 4 (default), 8, 2 or 1: passes with a cutoff and more
  *                   sources than resident wavefronts propagate up to this many
  *                   neighbouring sources together in one wavefront (each with
  *                   its share of the LDS target table; a source with more
  *                   candidates than its share runs alone). The group shrinks
  *                   until every resident wavefront gets a full one, the
- *                   expected candidates of a source (twice the mean plus 8)
- *                   fit a share, and the resident wavefronts' bend-vertex
- *                   tables (one 60-byte entry per bend vertex and source)
- *                   fit the table budget. Results equal those of single
+ *                   expected candidates of a source (the mean plus three
+ *                   standard deviations of a Poisson count) fit a share,
+ *                   and the resident wavefronts' bend-vertex tables (one
+ *                   60-byte entry per bend vertex and source) fit the table
+ *                   budget (a third of the device's memory, at most 96 GB). Results equal those of single
  *                   sources to rounding (separately compiled multiply-adds).
  *                   In FP32-mixed mode a group propagates in FP32 and each
  *                   of its sources with a pair in the guard band runs again

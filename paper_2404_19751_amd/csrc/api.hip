@@ -100,6 +100,7 @@ struct gsim_ctx {
     int update_block = 128;
     int stack_cap_all = 1 << 18;  // window records per wavefront in all-pairs passes
     double stack_budget = 40e9;   // bytes of window stacks an all-pairs pass may hold
+    double table_budget = 96e9;   // bytes of the resident wavefronts' bend-vertex tables
     int max_windows_all = 0;      // per-source window limit in all-pairs passes
     int cus = 256;
     bool whole_mesh = false;  // finite-cutoff passes on the whole-mesh kernel
@@ -677,7 +678,8 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
     if (!B.all && !B.big && !c->profile_sources) {
         // the expected Euclidean candidates of a source (uniform density):
         // a group's sources share the table, so twice that plus 8 must fit a
-        // share, or too many sources would run alone
+        // share, or too many sources would run alone (three standard
+        // deviations of a Poisson count above the mean: a few in a thousand)
         double mean = 0.0;
         for (int i = 0; i < ns; ++i) {
             const MeshState *ms = B.mem[i].ms;
@@ -689,8 +691,8 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
         // cost resident wavefronts
         const double slots = (double)std::min(c->cus * per_cu, c->max_slots);
         for (int g = c->group_sources; g > 1 && B.group == 1; g /= 2)
-            if (total >= (int64_t)g * c->cus * per_cu && 2.0 * mean + 8.0 <= (double)(kCandCap / g) &&
-                slots * (double)bend_table_bytes(g * B.rcap) <= c->stack_budget)
+            if (total >= (int64_t)g * c->cus * per_cu && mean + 3.0 * std::sqrt(mean) <= (double)(kCandCap / g) &&
+                slots * (double)bend_table_bytes(g * B.rcap) <= c->table_budget)
                 B.group = g;
     }
     B.rcap *= B.group;
@@ -715,7 +717,7 @@ gsim_status prepare_batch(gsim_ctx *c, Batch &B) {
     }
     {
         // the bend-vertex tables of the resident wavefronts stay within a budget too
-        const int64_t fit = (int64_t)(c->stack_budget / (double)std::max<int64_t>(B.rstride, 1));
+        const int64_t fit = (int64_t)(c->table_budget / (double)std::max<int64_t>(B.rstride, 1));
         B.nslots = (int)std::max<int64_t>(1, std::min<int64_t>(B.nslots, fit));
     }
     // time steps move the particles inside the geodesic launch when there is
@@ -1036,8 +1038,11 @@ gsim_status gsim_create(int device, gsim_precision prec, void *hip_stream, gsim_
         c->lds_cu = lds;
     // whole-mesh window stacks: at most a quarter of the device's memory
     size_t mem_free = 0, mem_total = 0;
-    if (hipMemGetInfo(&mem_free, &mem_total) == hipSuccess && mem_total > 0)
+    if (hipMemGetInfo(&mem_free, &mem_total) == hipSuccess && mem_total > 0) {
         c->stack_budget = std::min(c->stack_budget, 0.25 * (double)mem_total);
+        // bend-vertex tables: at most a third of it
+        c->table_budget = std::min(c->table_budget, (double)mem_total / 3.0);
+    }
     c->gp.cutoff = 0.0;
     c->gp.launch_delta = 1e300;  // one bucket: every improved bend vertex once the stack drains
     c->gp.cone_tol = 1e-12;
@@ -1802,7 +1807,7 @@ gsim_status gsim_tune_set(gsim_ctx *c, const char *name, double value) {
         else if (k == "dom_rel" && value >= 0.0) c->gp.dom_rel = value;
         else if (k == "dom_rel32" && value >= 0.0) c->gp.dom_rel32 = value;
         else if (k == "whole_mesh" && (value == 0.0 || value == 1.0)) c->whole_mesh = value != 0.0;
-        else if (k == "group_sources" && (value == 1.0 || value == 2.0 || value == 4.0))
+        else if (k == "group_sources" && (value == 1.0 || value == 2.0 || value == 4.0 || value == 8.0))
             c->group_sources = (int)value;
         else if (k == "fuse_update" && (value == 0.0 || value == 1.0)) c->fuse_update = value != 0.0;
         else if (k == "time_geodesic_only" && (value == 0.0 || value == 1.0)) c->time_geodesic_only = value != 0.0;

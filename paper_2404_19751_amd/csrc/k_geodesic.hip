@@ -80,6 +80,7 @@ constexpr int kMaxCand = kCandCap;
 constexpr int kHash = 256;
 // Several sources per wavefront (kG of them, the grouped instantiations):
 // each takes 1/kG of the target table and of the hash buckets.
+constexpr int kMaxGroup = 8;
 template <int kG>
 constexpr int kGroupCand = kMaxCand / kG;
 template <int kG>
@@ -120,12 +121,12 @@ struct Lds {
     double d1[kMaxCand], d2[kMaxCand], t1x[kMaxCand], t1y[kMaxCand];
     int32_t head[kHash];
     int32_t ncand;
-    int32_t ncg[4];  // candidate counts of the searches of a group's sources
+    int32_t ncg[kMaxGroup];  // candidate counts of the searches of a group's sources
     // the group being propagated (sources, rows, counts) and the sources that
     // wait to run alone: in LDS rather than in registers the propagation needs
-    int32_t gsrc[4], gnc[4], galone[4];
-    int32_t gall[4];  // the sources a group's search covers
-    int64_t gc0[4];
+    int32_t gsrc[kMaxGroup], gnc[kMaxGroup], galone[kMaxGroup];
+    int32_t gall[kMaxGroup];  // the sources a group's search covers
+    int64_t gc0[kMaxGroup];
     BendLds B;
 };
 
@@ -168,8 +169,8 @@ __device__ inline GTab gtab_of(char *base, int64_t stride, int slot, int gcap, L
 // source: the table's own count, or half of it for each source of a pair.
 template <int kB>
 __device__ inline int hash_bits(int f) {
-    static_assert(kB == 64 || kB == 128 || kB == 256 || kB == 1024, "bucket counts");
-    constexpr int kShift = kB == 64 ? 26 : (kB == 128 ? 25 : (kB == 256 ? 24 : 22));
+    static_assert(kB == 32 || kB == 64 || kB == 128 || kB == 256 || kB == 1024, "bucket counts");
+    constexpr int kShift = kB == 32 ? 27 : (kB == 64 ? 26 : (kB == 128 ? 25 : (kB == 256 ? 24 : 22)));
     return (int)(((uint32_t)f * 2654435761u) >> kShift) & (kB - 1);
 }
 template <class TL>
@@ -203,7 +204,7 @@ __device__ inline int next_in_face(const TL &L, int s, int f) {
 // instantiation takes the whole table.
 template <int kG>
 __device__ inline int slot_of(int root) {
-    static_assert(kG == 1 || kG == 2 || kG == 4, "group sizes");
+    static_assert(kG == 1 || kG == 2 || kG == 4 || kG == 8, "group sizes");
     if constexpr (kG == 1) {
         return 0;
     } else {
@@ -605,10 +606,11 @@ __device__ void find_candidates_group(const SurfDesc &sd, Lds &L, int p0, int ng
     const int lane = lane_id();
     if (lane < kG) L.ncg[lane] = 0;
     __syncthreads();
-    int beg[2], len[2], own[2], qh[2];
-    double x[2], y[2], z[2];
+    constexpr int kPairs = (27 * kG + kWave - 1) / kWave;  // (source, cell) pairs per lane
+    int beg[kPairs], len[kPairs], own[kPairs], qh[kPairs];
+    double x[kPairs], y[kPairs], z[kPairs];
 #pragma unroll
-    for (int hh = 0; hh < 2; ++hh) {
+    for (int hh = 0; hh < kPairs; ++hh) {
         const int pr = lane + kWave * hh, q = pr / 27, l = pr - 27 * q;
         beg[hh] = len[hh] = 0;
         own[hh] = -1;
@@ -635,15 +637,18 @@ __device__ void find_candidates_group(const SurfDesc &sd, Lds &L, int p0, int ng
     // positions, each as one round of loads
     constexpr int kU = 4;
     const double cut2 = sd.cut2;
-    for (int it = 0; it < max(len[0], len[1]); it += kU) {
-        int jj[2][kU];
+    int maxlen = 0;
 #pragma unroll
-        for (int hh = 0; hh < 2; ++hh)
+    for (int hh = 0; hh < kPairs; ++hh) maxlen = max(maxlen, len[hh]);
+    for (int it = 0; it < maxlen; it += kU) {
+        int jj[kPairs][kU];
+#pragma unroll
+        for (int hh = 0; hh < kPairs; ++hh)
 #pragma unroll
             for (int u = 0; u < kU; ++u) jj[hh][u] = it + u < len[hh] ? sd.order[beg[hh] + it + u] : -1;
-        double dd[2][kU];
+        double dd[kPairs][kU];
 #pragma unroll
-        for (int hh = 0; hh < 2; ++hh)
+        for (int hh = 0; hh < kPairs; ++hh)
 #pragma unroll
             for (int u = 0; u < kU; ++u) {
                 const int j = jj[hh][u];
@@ -655,7 +660,7 @@ __device__ void find_candidates_group(const SurfDesc &sd, Lds &L, int p0, int ng
                 }
             }
 #pragma unroll
-        for (int hh = 0; hh < 2; ++hh)
+        for (int hh = 0; hh < kPairs; ++hh)
 #pragma unroll
             for (int u = 0; u < kU; ++u)
                 if (dd[hh][u] < cut2) {
@@ -672,7 +677,7 @@ __device__ void find_candidates_group(const SurfDesc &sd, Lds &L, int p0, int ng
     };
     // ranks within each source's hits, which sit in kCap consecutive lanes of
     // a pass: compared through lane reads (absent entries hold INT_MAX)
-    static_assert(kCap == 32 || kCap == 64, "one or two sources per pass");
+    static_assert(kCap == 16 || kCap == 32 || kCap == 64, "one, two or four sources per pass");
     for (int base = 0; base < ng * kCap; base += kWave) {
         const int k = base + lane, q = k / kCap, s = k - q * kCap;
         const int m = q < ng ? L.ncg[q] : 0;
@@ -681,7 +686,9 @@ __device__ void find_candidates_group(const SurfDesc &sd, Lds &L, int p0, int ng
         int rank = 0;
         for (int t = 0; t < kCap; ++t) {
             int v = __builtin_amdgcn_readlane(j, t);
-            if (kCap == 32 && lane >= 32) v = __builtin_amdgcn_readlane(j, 32 + t);
+#pragma unroll
+            for (int b = 1; b < kWave / kCap; ++b)
+                if (lane >= b * kCap) v = __builtin_amdgcn_readlane(j, b * kCap + t);
             rank += v < j;
         }
         if (mine) L.tj[place_of(q) * kCap + rank] = j;
@@ -892,16 +899,27 @@ __device__ __attribute__((always_inline)) inline unsigned run_sources(const GeoA
         L.B.npend = 0;
         L.B.ntouched = 0;
     }
-    int e1 = ncs[0], e2 = e1, e3 = e1, ntot = e1;
-    if constexpr (kG > 1) {
-        e2 = e1 + (nsrc > 1 ? ncs[1] : 0);
-        e3 = e2 + (nsrc > 2 ? ncs[2] : 0);
-        ntot = e3 + (nsrc > 3 ? ncs[3] : 0);
+    constexpr int kQ = kG == 1 ? 1 : kG;
+    int en[kQ];  // source q's entries end at en[q] in the flattened order
+    {
+        int acc = 0;
+#pragma unroll
+        for (int t = 0; t < kQ; ++t) {
+            if (t < nsrc) acc += ncs[t];
+            en[t] = acc;
+        }
     }
+    const int ntot = en[kQ - 1];
     // source and slot of flattened entry k
     auto entry_of = [&](int k, int &q, int &s) {
-        q = kG == 1 ? 0 : (k >= e1) + (k >= e2) + (k >= e3);
-        s = k - (q == 0 ? 0 : q == 1 ? e1 : q == 2 ? e2 : e3);
+        q = 0;
+        s = k;
+#pragma unroll
+        for (int t = 0; t + 1 < kQ; ++t)
+            if (k >= en[t]) {
+                q = t + 1;
+                s = k - en[t];
+            }
     };
     __syncthreads();
     for (int k = lane; k < ntot; k += kWave) {
@@ -1534,14 +1552,16 @@ hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoPa
         // several sources per wavefront: persistent grid, LDS tables, claims
         // of a multiple of the group so that groups come from one claimed
         // range
-        if ((group != 2 && group != 4) || big || mode != 0 || rcap % group) return hipErrorInvalidValue;
+        if ((group != 2 && group != 4 && group != 8) || big || mode != 0 || rcap % group) return hipErrorInvalidValue;
         a.grab = group * a.grab;
         if (fp32) {
             if (group == 2) launch_groups<true, 2>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
-            else launch_groups<true, 4>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
+            else if (group == 4) launch_groups<true, 4>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
+            else launch_groups<true, 8>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
         } else {
             if (group == 2) launch_groups<false, 2>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
-            else launch_groups<false, 4>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
+            else if (group == 4) launch_groups<false, 4>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
+            else launch_groups<false, 8>(shape.lds_stack_kb, shape.nslots, pad, a, s, ev0, ev1);
         }
         return hipGetLastError();
     }

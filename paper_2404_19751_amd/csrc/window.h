@@ -160,7 +160,7 @@ __device__ inline BendTable bend_table(char *base, int64_t stride, int slot, int
 // Wave-uniform state of the table and the LDS of one launch chunk.
 struct BendLds {
     int32_t npend, ntouched;
-    int32_t sface[4];  // the faces of the wavefront's sources (cutoff kernel)
+    int32_t sface[8];  // the faces of the wavefront's sources (cutoff kernel)
     int32_t sel[kLaunchChunk];       // bend vertices of the chunk
     int32_t pref[kLaunchChunk + 1];  // prefix sums of their fan sizes
 };

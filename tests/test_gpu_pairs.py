@@ -1,5 +1,5 @@
-"""Two or four sources per wavefront (the grouped instantiations of the
-cutoff kernel: FP64 passes with more sources than resident wavefronts)
+"""Two, four or eight sources per wavefront (the grouped instantiations of
+the cutoff kernel: passes with more sources than resident wavefronts)
 against one source per wavefront, on the height field (20,000 sources) and the 16 batched
 surfaces of C3: the same neighbour rows and flags, distances and tangents
 equal to rounding (the two instantiations are compiled separately, so their
@@ -47,7 +47,7 @@ def _pairs_and_steps(ws, group, steps):
         ctx.close()
 
 
-@pytest.mark.parametrize("group", [2, 4])
+@pytest.mark.parametrize("group", [2, 4, 8])
 @pytest.mark.parametrize("name", ["c4", "c3"])
 def test_groups_equal_single_sources(name, group):
     ws = W.workload(name)
