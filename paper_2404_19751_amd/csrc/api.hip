@@ -816,6 +816,9 @@ gsim_status geodesic_pass(gsim_ctx *c, Batch &B, bool advance, bool commit_in = 
                                        ms->fill_zero < ncell, desc_dev(c), P<int32_t>(c->work), advance, s));
             ms->fill_zero = std::max<int64_t>(ms->fill_zero, ncell);
         }
+        // several sources per wavefront: their candidate searches run ahead
+        // of the pass, at the occupancy of a small kernel
+        if (B.group > 1) HIPCHK(c, launch_candidates(desc_dev(c), B.bi, B.group, s));
     }
     GeoParams gp = c->gp;
     if (!(gp.launch_delta > 0.0)) gp.launch_delta = 0.5 * B.mem[0].ms->dm.mean_edge;
@@ -824,7 +827,7 @@ gsim_status geodesic_pass(gsim_ctx *c, Batch &B, bool advance, bool commit_in = 
         HIPCHK(c, launch_geodesic(desc_dev(c), B.bi, gp, B.shape, P<char>(c->stack), P<char>(c->roots), B.rstride,
                                   B.rcap, P<int32_t>(c->work), P<Counters>(c->ctr), c->prec == GSIM_FP32_MIXED,
                                   advance && B.fused, s, st.a, st.b, B.big ? P<char>(c->gtab) : nullptr,
-                                  B.big ? B.gcap : 0, B.group));
+                                  B.big ? B.gcap : 0, B.group, B.group > 1));
     }
     c->passes++;
     return GSIM_OK;

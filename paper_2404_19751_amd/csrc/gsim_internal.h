@@ -250,14 +250,17 @@ struct GeoShape {
 // gcap > 0 selects the big-candidate instantiation: every surface's rows are
 // sd.cap wide (at most kBigCandMax) and each resident wavefront keeps its
 // source's target arrays for up to gcap targets in gtab
-// (geodesic_gtab_bytes(gcap) bytes per wavefront). group = 2 or 4: in FP64
-// with more sources than slots, that many sources per wavefront (the
-// bend-vertex tables then hold rcap = group times the bend vertices of a
-// surface).
+// (geodesic_gtab_bytes(gcap) bytes per wavefront). group = 2, 4 or 8: with
+// more sources than slots, that many sources per wavefront (the bend-vertex
+// tables then hold rcap = group times the bend vertices of a surface).
 hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoParams &gp, const GeoShape &shape,
                            char *stack_mem, char *roots, int64_t rstride, int rcap, int32_t *work_ctr, Counters *ctr,
                            bool fp32, bool fuse, hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr,
-                           char *gtab = nullptr, int gcap = 0, int group = 1);
+                           char *gtab = nullptr, int gcap = 0, int group = 1, bool pre_cand = false);
+// The Euclidean candidate rows and counts of every source of the batch,
+// group sources at a time (2, 4 or 8), ahead of a grouped geodesic pass
+// (launched with pre_cand), which then reads them instead of searching.
+hipError_t launch_candidates(const SurfDesc *desc, const BatchIdx &bi, int group, hipStream_t s);
 int64_t geodesic_gtab_bytes(int gcap);
 // All-pairs geodesics (no cutoff) for every source of the batch: every other
 // particle of the surface is a target. vdist: per resident wavefront a table

@@ -103,6 +103,7 @@ struct GeoArgs {
     char *gtab;          // big-candidate mode: per wave the target arrays of gcap targets (gstride bytes)
     int64_t gstride;
     int gcap;
+    int pre_cand;        // the candidate rows and counts were written ahead of the pass (k_candidates)
 };
 
 // The target table of one source: per candidate target its index, face,
@@ -546,11 +547,47 @@ __device__ void launch_roots(const GeoArgs &a, const SurfDesc &sd, TL &L, const 
     }
 }
 
+// The group lists from a group search's counts (L.ncg, L.gall): sources
+// with 1 .. kGroupCand candidates in order (gsrc, gc0, gnc; nb of them) and
+// those with more (galone; na).
+template <int kG, class LT>
+__device__ void group_lists(LT &L, int ng, int &nb, int &na) {
+    constexpr int kCap = kGroupCand<kG>;
+    const int lane = lane_id();
+    nb = na = 0;
+    for (int q = 0; q < ng; ++q) {
+        const int n = L.ncg[q];
+        const int src = L.gall[q];
+        if (n > kCap) {
+            if (lane == 0) L.galone[na] = src;
+            ++na;
+        } else if (n > 0) {
+            if (lane == 0) {
+                L.gsrc[nb] = src;
+                L.gc0[nb] = (int64_t)src * kMaxCand;
+                L.gnc[nb] = n;
+            }
+            ++nb;
+        }
+    }
+    __syncthreads();
+}
+
+// The LDS of the candidate-search kernel: the search's scratch and group
+// lists only.
+struct CandLds {
+    int32_t tj[kMaxCand], tnext[kMaxCand];
+    int32_t ncand;
+    int32_t ncg[kMaxGroup], gsrc[kMaxGroup], gnc[kMaxGroup], galone[kMaxGroup], gall[kMaxGroup];
+    int64_t gc0[kMaxGroup];
+};
+
 // Euclidean prefilter of one source (the lower bound of Sec. 3.1): lanes 0-26
 // scan the 27 cells around it, the hits are rank-sorted by particle index in
 // LDS and written out as the source's candidate row. Returns the true count
 // (more than kMaxCand is an overflow the caller reports).
-__device__ int find_candidates(const SurfDesc &sd, Lds &L, int src, int64_t c0) {
+template <class LT>
+__device__ int find_candidates(const SurfDesc &sd, LT &L, int src, int64_t c0) {
     constexpr int tb = 0, cap = kMaxCand;
     const int lane = lane_id();
     int32_t &ncand = L.ncand;
@@ -600,8 +637,8 @@ __device__ int find_candidates(const SurfDesc &sd, Lds &L, int src, int64_t c0) 
 // gc0, gnc, nb of them), whose candidate rows are written. Sources with more
 // go to galone (na of them) and are searched again alone; every count goes
 // to cand_cnt. The same group and rows as searching the sources one by one.
-template <int kG>
-__device__ void find_candidates_group(const SurfDesc &sd, Lds &L, int p0, int ng, int &nb, int &na) {
+template <int kG, class LT>
+__device__ void find_candidates_group(const SurfDesc &sd, LT &L, int p0, int ng, int &nb, int &na) {
     constexpr int kCap = kGroupCand<kG>;
     const int lane = lane_id();
     if (lane < kG) L.ncg[lane] = 0;
@@ -699,23 +736,65 @@ __device__ void find_candidates_group(const SurfDesc &sd, Lds &L, int p0, int ng
         if (m <= kCap && s < m) sd.cand[(int64_t)L.gall[q] * kMaxCand + s] = L.tj[place_of(q) * kCap + s];
     }
     if (lane < ng) sd.cand_cnt[L.gall[lane]] = L.ncg[lane];
-    nb = na = 0;
-    for (int q = 0; q < ng; ++q) {
-        const int n = L.ncg[q];
-        const int src = L.gall[q];
-        if (n > kCap) {
-            if (lane == 0) L.galone[na] = src;
-            ++na;
-        } else if (n > 0) {
-            if (lane == 0) {
-                L.gsrc[nb] = src;
-                L.gc0[nb] = (int64_t)src * kMaxCand;
-                L.gnc[nb] = n;
-            }
-            ++nb;
-        }
+    group_lists<kG>(L, ng, nb, na);
+}
+
+// A group's sources from their candidate rows written ahead of the pass
+// (k_candidates): counts, the rows of those with 1 .. kGroupCand candidates
+// into their places' regions of the table, and the group lists.
+template <int kG>
+__device__ void take_candidates(const SurfDesc &sd, Lds &L, int p0, int ng, int &nb, int &na) {
+    constexpr int kCap = kGroupCand<kG>;
+    const int lane = lane_id();
+    if (lane < ng) {
+        const int src = sd.order[p0 + lane];
+        L.gall[lane] = src;
+        L.ncg[lane] = sd.cand_cnt[src];
     }
     __syncthreads();
+    for (int k = lane; k < ng * kCap; k += kWave) {
+        const int q = k / kCap, s = k - q * kCap, m = L.ncg[q];
+        if (m <= kCap && s < m) {
+            int pl = 0;
+            for (int t = 0; t < q; ++t) pl += L.ncg[t] > 0 && L.ncg[t] <= kCap;
+            L.tj[pl * kCap + s] = sd.cand[(int64_t)L.gall[q] * kMaxCand + s];
+        }
+    }
+    group_lists<kG>(L, ng, nb, na);
+}
+
+// One source's candidate row written ahead of the pass into the table
+// (as find_candidates leaves it); returns its count.
+__device__ int take_row(const SurfDesc &sd, Lds &L, int src, int64_t c0) {
+    const int n = sd.cand_cnt[src];
+    for (int s = lane_id(); s < min(n, kMaxCand); s += kWave) L.tj[s] = sd.cand[c0 + s];
+    __syncthreads();
+    return n;
+}
+
+// The Euclidean prefilter of every source ahead of a grouped pass: kG
+// consecutive sources of the cell order per wavefront (on one surface at a
+// time), the same rows and counts as the search inside the pass, at the
+// occupancy of a kernel with small LDS and register needs rather than that
+// of the propagation.
+template <int kG>
+__global__ __launch_bounds__(kWave) void k_candidates(const SurfDesc *__restrict__ desc, BatchIdx bi) {
+    __shared__ CandLds L;
+    const int total = bi.begin[bi.nsurf];
+    int pos = (int)blockIdx.x * kG;
+    const int end = min(pos + kG, total);
+    while (pos < end) {
+        const int si = __builtin_amdgcn_readfirstlane(batch_surface(bi, pos));
+        const SurfDesc &sd = desc[si];
+        const int ng = min(end, bi.begin[si + 1]) - pos;
+        int nb, na;
+        find_candidates_group<kG>(sd, L, pos - bi.begin[si], ng, nb, na);
+        for (int g = 0; g < na; ++g) {
+            const int s1 = L.galone[g];
+            find_candidates(sd, L, s1, (int64_t)s1 * kMaxCand);
+        }
+        pos += ng;
+    }
 }
 
 // The Euclidean prefilter of one source in big-candidate mode: the 27 cells'
@@ -1378,7 +1457,8 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
             next += more;
             left -= more;
             int nb, na;
-            find_candidates_group<kG>(sd, L, idx - a.bi.begin[si], 1 + more, nb, na);
+            if (a.pre_cand) take_candidates<kG>(sd, L, idx - a.bi.begin[si], 1 + more, nb, na);
+            else find_candidates_group<kG>(sd, L, idx - a.bi.begin[si], 1 + more, nb, na);
             // FP32-mixed: the group in FP32, then each source with a pair
             // inside the guard band of the cutoff again in FP64, alone
             if (nb > 0) {
@@ -1394,7 +1474,7 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
                         if (!((nearm >> q) & 1u)) continue;  // wave-uniform
                         const int s1 = L.gsrc[q];
                         const int64_t c = L.gc0[q];
-                        const int n = find_candidates(sd, L, s1, c);
+                        const int n = a.pre_cand ? take_row(sd, L, s1, c) : find_candidates(sd, L, s1, c);
                         st.overflow = false;
                         run_sources<double, Lds, kG>(a, sd, L, stk, kStk, &s1, &c, &n, 1, true, blockIdx.x, st);
                         ++st.guards;
@@ -1405,7 +1485,7 @@ __global__ __launch_bounds__(kWave, 2) void k_geodesic(GeoArgs a) {
             for (int g = 0; g < na; ++g) {
                 const int s1 = L.galone[g];
                 const int64_t c = (int64_t)s1 * kMaxCand;
-                const int n = find_candidates(sd, L, s1, c);
+                const int n = a.pre_cand ? take_row(sd, L, s1, c) : find_candidates(sd, L, s1, c);
                 if (n > kMaxCand) {
                     if (lane == 0) ++c_limited;
                 } else {
@@ -1523,7 +1603,7 @@ void launch_variant(int mode, int kb, bool big, int nslots, size_t pad, const Ge
 hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoParams &gp, const GeoShape &shape,
                            char *stack_mem, char *roots, int64_t rstride, int rcap, int32_t *work_ctr, Counters *ctr,
                            bool fp32, bool fuse, hipStream_t s, hipEvent_t ev0, hipEvent_t ev1, char *gtab,
-                           int gcap, int group) {
+                           int gcap, int group, bool pre_cand) {
     GeoArgs a;
     a.sd = desc;
     a.bi = bi;
@@ -1543,6 +1623,7 @@ hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoPa
     a.gtab = gtab;
     a.gstride = big ? gtab_bytes(gcap) : 0;
     a.gcap = gcap;
+    a.pre_cand = pre_cand && group > 1 ? 1 : 0;
 
     if (shape.nslots < 1 || total < 1) return hipSuccess;
     if (fuse && total > shape.nslots) return hipErrorInvalidValue;  // the fused update needs a slot per source
@@ -1567,6 +1648,17 @@ hipError_t launch_geodesic(const SurfDesc *desc, const BatchIdx &bi, const GeoPa
     }
     if (fp32) launch_variant<true>(mode, shape.lds_stack_kb, big, shape.nslots, pad, a, s, ev0, ev1);
     else launch_variant<false>(mode, shape.lds_stack_kb, big, shape.nslots, pad, a, s, ev0, ev1);
+    return hipGetLastError();
+}
+
+hipError_t launch_candidates(const SurfDesc *desc, const BatchIdx &bi, int group, hipStream_t s) {
+    const int total = bi.begin[bi.nsurf];
+    if (total <= 0) return hipSuccess;
+    const int nb = (total + group - 1) / group;
+    if (group == 2) hipLaunchKernelGGL(k_candidates<2>, dim3(nb), dim3(kWave), 0, s, desc, bi);
+    else if (group == 4) hipLaunchKernelGGL(k_candidates<4>, dim3(nb), dim3(kWave), 0, s, desc, bi);
+    else if (group == 8) hipLaunchKernelGGL(k_candidates<8>, dim3(nb), dim3(kWave), 0, s, desc, bi);
+    else return hipErrorInvalidValue;
     return hipGetLastError();
 }
 
