@@ -64,12 +64,13 @@ __device__ inline void walk_one(const DevMesh &m, int &f, double b[3], d3 D, d3 
         d3 u = (1.0 / rem) * D;
         int excl = -1;   // slot whose edge was just crossed/reflected: not an exit
         int onlyk = -1;  // sitting on the vertex of this slot: only its opposite edge is an exit
+        // an edge crossing leaves the direction (and velocity) as components
+        // along the crossed edge te and across it; they are turned into the
+        // new face's plane once its record, normal included, has arrived
+        bool turn = false;
+        d3 te = {0.0, 0.0, 0.0};
+        double tue = 0.0, tum = 0.0, tve = 0.0, tvm = 0.0;
         for (int it = 0;; ++it) {
-            if (it >= kWalkCap) {
-                cap = 1;
-                fl |= 4;
-                break;
-            }
             // the face's vertices in slot order (one record: no dependent
             // load through the vertex indices)
             const double *fp = m.fpos + 18 * (int64_t)f;
@@ -79,12 +80,25 @@ __device__ inline void walk_one(const DevMesh &m, int &f, double b[3], d3 D, d3 
             // a crossing waits for the next face's record only
             const int32_t *tp = m.twin + 3 * (int64_t)f;
             const int tw0 = tp[0], tw1 = tp[1], tw2 = tp[2];
+            if (turn) {
+                const d3 mi = cross(te, nf);  // pointing into this face, away from the crossed edge
+                u = tue * te + tum * mi;
+                if (hv) v = tve * te + tvm * mi;
+                turn = false;
+            }
+            if (it >= kWalkCap) {
+                cap = 1;
+                fl |= 4;
+                break;
+            }
             double twoA = sqrt(dot(cross(P[1] - P[0], P[2] - P[0]), cross(P[1] - P[0], P[2] - P[0])));
+            // the edge opposite each slot, from its next to its previous vertex
+            const d3 E0 = P[2] - P[1], E1 = P[0] - P[2], E2 = P[1] - P[0];
             double rate[3], s[3];
             int k1 = -1, k2 = -1;
             for (int k = 0; k < 3; ++k) {
                 // gradient of b_k: in-plane normal of the opposite edge, pointing to vertex k
-                d3 g = cross(nf, P[(k + 2) % 3] - P[(k + 1) % 3]);
+                d3 g = cross(nf, k == 0 ? E0 : k == 1 ? E1 : E2);
                 rate[k] = dot(u, g) / twoA;
                 bool allowed = (onlyk < 0 || k == onlyk) && k != excl;
                 s[k] = (allowed && rate[k] < 0.0) ? fmax(-b[k] / rate[k], 0.0) : INFINITY;
@@ -172,7 +186,7 @@ __device__ inline void walk_one(const DevMesh &m, int &f, double b[3], d3 D, d3 
             b[k1] = 0.0;
             rem -= s1;
             const int hk = (k1 + 1) % 3;
-            d3 e = unit(P[(k1 + 2) % 3] - P[(k1 + 1) % 3]);
+            d3 e = unit(k1 == 0 ? E0 : k1 == 1 ? E1 : E2);
             d3 mo = cross(e, nf);  // in-plane normal of the edge, pointing out of f
             const int tw = hk == 0 ? tw0 : hk == 1 ? tw1 : tw2;
             if (tw < 0) {
@@ -190,13 +204,14 @@ __device__ inline void walk_one(const DevMesh &m, int &f, double b[3], d3 D, d3 
             nb[q] = b[(k1 + 2) % 3];
             nb[(q + 1) % 3] = b[(k1 + 1) % 3];
             nb[(q + 2) % 3] = 0.0;
-            d3 mi = cross(e, ld3(m.fnrm + 3 * (int64_t)g));  // pointing into the new face
-            double ue = dot(u, e), um = dot(u, mo);
-            u = ue * e + um * mi;
+            te = e;
+            tue = dot(u, e);
+            tum = dot(u, mo);
             if (hv) {
-                double ve = dot(v, e), vm = dot(v, mo);
-                v = ve * e + vm * mi;
+                tve = dot(v, e);
+                tvm = dot(v, mo);
             }
+            turn = true;
             f = g;
             b[0] = nb[0];
             b[1] = nb[1];
