@@ -321,7 +321,8 @@ gsim_status gsim_step_batched(gsim_ctx *ctx, int32_t nmesh, const int32_t *mesh_
  *                   In FP32-mixed mode a group propagates in FP32 and each
  *                   of its sources with a pair in the guard band runs again
  *                   alone in FP64
- *   "update_block"  workgroup size of the separate update kernel: 64, 128 or 256
+ *   "update_block"  workgroup size of the separate update kernel: 64 (default),
+ *                   128 or 256
  *   "fuse_update"   1 (default): time steps with a cutoff and few enough particles
  *                   move each particle inside the geodesic launch; 0: always a
  *                   separate update launch per step

@@ -97,7 +97,9 @@ struct gsim_ctx {
     int max_slots = 65536;
     int lds_stack_kb = 4;
     int grab = 1;
-    int update_block = 128;
+    // the update's wavefronts spread over more compute units (20,000 particles
+    // on the height field: 40.4 against 41.7 us with 128, 44.6 with 256)
+    int update_block = 64;
     int stack_cap_all = 1 << 18;  // window records per wavefront in all-pairs passes
     double stack_budget = 40e9;   // bytes of window stacks an all-pairs pass may hold
     double table_budget = 96e9;   // bytes of the resident wavefronts' bend-vertex tables
